@@ -1,0 +1,149 @@
+"""Named workloads: the five benchmark configurations and small test cases.
+
+Each workload is a plain dict:
+
+    instances       list[Instance]      (one, or 32 for the ragged batch)
+    precision       "fp64" | "mixed"
+    refresh_every   proposals between full double-precision recomputations
+                    of the inverse (0 = only after parameter updates)
+    sweeps          sweeps per SR iteration (1 sweep = N_e proposals/walker)
+    warmup          sweeps before the first sample
+    sample_every    sweeps between samples (one sample per walker each time)
+    sr_iters        SR iterations
+    dtau, eps_rel, eps_abs   SR step and diagonal regularisation
+    solver          "chol" | "cg"
+    sampler_seed    Philox key for the Metropolis chain
+
+The physical content follows the benchmark descriptions; where a description
+leaves a value open the value chosen here is stated next to it.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .instance import (Instance, f_map_full, f_map_sublattice, make_instance,
+                       ring8_orbitals, v_map_distance, v_map_nn)
+from .lattice import chain, square
+
+INPUT_SEED = 11418
+
+
+def _c1(n_walkers: int = 64) -> list[Instance]:
+    lat = chain(8)
+    phi = ring8_orbitals()
+    return [make_instance("ring8_U4", lat, 4, 4, 4.0, f_map_full(lat), v_map_nn(lat),
+                          g0=-0.5, v_nn=0.1, f0=phi @ phi.T, f_noise=0.01,
+                          n_walkers=n_walkers, seed=INPUT_SEED)]
+
+
+def _c2(n_walkers: int = 1024) -> list[Instance]:
+    lat = square(8)
+    return [make_instance("sq8_U4", lat, 32, 32, 4.0, f_map_sublattice(lat, 2, 2),
+                          v_map_distance(lat), g0=-0.5, v_nn=0.1,
+                          n_walkers=n_walkers, seed=INPUT_SEED)]
+
+
+def _c3(n_walkers: int = 4096) -> list[Instance]:
+    lat = square(10)
+    return [make_instance("sq10_U8", lat, 50, 50, 8.0, f_map_full(lat), v_map_nn(lat),
+                          g0=-1.0, v_nn=0.1, n_walkers=n_walkers, seed=INPUT_SEED)]
+
+
+def _c4(n_walkers: int = 256, n_inst: int = 32) -> list[Instance]:
+    rng = np.random.default_rng(INPUT_SEED)
+    out = []
+    for k in range(n_inst):
+        L = int(rng.integers(4, 13))
+        U = float(rng.uniform(2.0, 10.0))
+        fill = float(rng.uniform(0.8, 1.0))
+        lat = square(L)
+        ne = 2 * int(round(fill * lat.n_sites / 2))
+        fmap = f_map_sublattice(lat, 2, 2) if L % 2 == 0 else f_map_sublattice(lat, 1, 1)
+        out.append(make_instance(f"batch{k:02d}_L{L}_U{U:.2f}", lat, ne // 2, ne // 2, U,
+                                 fmap, v_map_nn(lat), g0=-U / 8, v_nn=0.1,
+                                 n_walkers=n_walkers, seed=INPUT_SEED + 1 + k))
+    return out
+
+
+def _c5(n_walkers: int = 8192, n_hidden: int = 512) -> list[Instance]:
+    lat = square(16)
+    return [make_instance("sq16_U8_rbm", lat, 112, 112, 8.0, f_map_sublattice(lat, 2, 2),
+                          v_map_nn(lat), g0=-1.0, v_nn=0.1, n_hidden=n_hidden,
+                          rbm_sigma=0.01, n_walkers=n_walkers, seed=INPUT_SEED)]
+
+
+def _wl(instances, **kw) -> dict:
+    d = dict(instances=instances, precision="fp64", refresh_every=0, sweeps=10,
+             warmup=100, sample_every=1, sr_iters=10, dtau=0.02, eps_rel=1e-3,
+             eps_abs=1e-6, solver="chol", sampler_seed=1711 * 1000)
+    d.update(kw)
+    return d
+
+
+def workload(name: str, **overrides) -> dict:
+    """Build a named workload; keyword overrides replace defaults (e.g. n_walkers)."""
+    nw = overrides.pop("n_walkers", None)
+    kw_inst = {} if nw is None else {"n_walkers": nw}
+    if name == "c1_ring8_fp64":
+        d = _wl(_c1(**kw_inst), sweeps=1000, warmup=100, sample_every=1, sr_iters=0,
+                sampler_seed=1711 * 1000 + 1)
+    elif name == "c2_sq8_fp64":
+        d = _wl(_c2(**kw_inst), sweeps=200, warmup=100, sample_every=1, sr_iters=10,
+                refresh_every=4 * 64, sampler_seed=1711 * 1000 + 2)
+    elif name == "c3_sq10_mixed":
+        d = _wl(_c3(**kw_inst), precision="mixed", refresh_every=32, sweeps=10,
+                warmup=100, sample_every=10, sr_iters=10, sampler_seed=1711 * 1000 + 3)
+    elif name == "c4_batch32_mixed":
+        d = _wl(_c4(**kw_inst), precision="mixed", refresh_every=32, sweeps=10,
+                warmup=100, sample_every=1, sr_iters=10, sampler_seed=1711 * 1000 + 4)
+    elif name == "c5_sq16_rbm_mixed":
+        d = _wl(_c5(**kw_inst), precision="mixed", refresh_every=0, sweeps=10,
+                warmup=100, sample_every=10, sr_iters=10, dtau=0.01, solver="cg",
+                sampler_seed=1711 * 1000 + 5)
+    elif name == "ring4":
+        lat = chain(4)
+        d = _wl([make_instance("ring4_U4", lat, 2, 2, 4.0, f_map_full(lat), v_map_nn(lat),
+                               f_noise=0.05, n_walkers=nw or 16, seed=INPUT_SEED)],
+                sweeps=200, warmup=20, sr_iters=0)
+    elif name == "ring6":
+        lat = chain(6)
+        d = _wl([make_instance("ring6_U4", lat, 3, 3, 4.0, f_map_full(lat), v_map_nn(lat),
+                               f_noise=0.05, n_walkers=nw or 16, seed=INPUT_SEED)],
+                sweeps=200, warmup=20, sr_iters=0)
+    elif name == "sq4_sub2":
+        lat = square(4)
+        d = _wl([make_instance("sq4_U4", lat, 7, 7, 4.0, f_map_sublattice(lat, 2, 2),
+                               v_map_distance(lat), f_noise=0.05, n_walkers=nw or 64,
+                               seed=INPUT_SEED)], sweeps=20, warmup=10, sr_iters=2)
+    elif name == "ring6_rbm":
+        lat = chain(6)
+        d = _wl([make_instance("ring6_rbm", lat, 3, 3, 4.0, f_map_full(lat), v_map_nn(lat),
+                               f_noise=0.05, n_hidden=12, rbm_sigma=0.1,
+                               n_walkers=nw or 16, seed=INPUT_SEED)],
+                sweeps=100, warmup=20, sr_iters=0)
+    else:
+        raise KeyError(name)
+    d["name"] = name
+    d.update(overrides)
+    return d
+
+
+WORKLOADS = ("c1_ring8_fp64", "c2_sq8_fp64", "c3_sq10_mixed", "c4_batch32_mixed",
+             "c5_sq16_rbm_mixed", "ring4", "ring6", "sq4_sub2", "ring6_rbm")
+
+
+def random_configs(inst: Instance, n: int, seed: int) -> np.ndarray:
+    """n uniformly drawn electron configurations, shape [n, N_e] int32.
+
+    Electron a < n_up sits at spin-orbital I = site (up); a >= n_up at
+    I = site + Ns (down).  Within a spin, sites are in ascending order.
+    """
+    rng = np.random.default_rng(seed)
+    ns = inst.n_sites
+    out = np.empty((n, inst.n_elec), dtype=np.int32)
+    for w in range(n):
+        up = np.sort(rng.choice(ns, inst.n_up, replace=False))
+        dn = np.sort(rng.choice(ns, inst.n_dn, replace=False))
+        out[w, :inst.n_up] = up
+        out[w, inst.n_up:] = dn + ns
+    return out
