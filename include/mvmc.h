@@ -1,0 +1,232 @@
+/*
+ * mvmc.h -- C ABI of libmvmc, the MI355X (gfx950) many-variable variational
+ * Monte Carlo hot path: batched Metropolis sampling of a Pfaffian x Jastrow x
+ * Gutzwiller (optionally x RBM) wave function, local energies and
+ * log-derivatives, and the stochastic-reconfiguration (SR) update.
+ *
+ * The operations follow arXiv:1711.11418 ("mVMC -- open-source software for
+ * many-variable variational Monte Carlo method"):
+ *   wave function   psi = P_G P_J phi_AP-Pf      section 3.2 (Eqs. Pf, AP-Pf,
+ *                                                 Gutzwiller/Jastrow factors)
+ *   <x|phi_Pf>      proportional to Pf(X), X_IJ = F_IJ - F_JI   section 3.2.1
+ *   sampling        Metropolis over rho(x) = |<x|psi>|^2, hopping update
+ *                   and Sherman-Morrison-type fast update   section 3.1
+ *   estimators      Eq. MC (local energy); O_k = d ln<x|psi>/d alpha_k with
+ *                   Eq. DiffPf for the pair amplitudes      section 3.3.1
+ *   SR              Delta alpha = -dtau S^-1 g (Eq. SR_equation_system),
+ *                   Cholesky or the CG method of Algorithm 1   sections 3.3.1-3.3.2
+ * plus an RBM factor exp(sum_v a_v s_v) prod_h 2 cosh(b_h + sum_v W_hv s_v),
+ * s_v = 2 n_v - 1 over the 2 Ns spin-orbitals (not in the paper).
+ *
+ * Conventions for every function:
+ *   - Returns an mvmc_status; MVMC_OK == 0.  Nothing throws across the ABI.
+ *   - Arguments are checked before anything is enqueued; on an argument error
+ *     the context is unchanged.  mvmc_last_error() describes the last failure.
+ *   - Pointers named d_* are device pointers, h_* host pointers.  The caller
+ *     owns every buffer it passes, including the workspace; the library owns
+ *     only the host-side context and never allocates device memory.
+ *   - All device work is enqueued on the stream given to init, in order.
+ *     Calls that fill h_* outputs synchronise that stream before returning.
+ *   - Spin-orbital index I = i + Ns*sigma (sigma = 0 up, 1 down); electron
+ *     a < n_up is up, a >= n_up is down (section 3.2.1).
+ */
+#ifndef MVMC_H
+#define MVMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mvmc_ctx mvmc_ctx;
+
+typedef enum {
+  MVMC_OK = 0,
+  MVMC_E_ARG = 1,        /* bad pointer, value or index map */
+  MVMC_E_SHAPE = 2,      /* inconsistent sizes (odd N_e, n_up != n_dn, ...) */
+  MVMC_E_WORKSPACE = 3,  /* workspace too small or misaligned */
+  MVMC_E_HIP = 4,        /* a HIP runtime call or kernel launch failed */
+  MVMC_E_SINGULAR = 5,   /* X (or the regularised S) could not be factorised */
+  MVMC_E_NONFINITE = 6,  /* NaN/Inf parameter or result */
+  MVMC_E_STATE = 7       /* call out of order (e.g. sr_update before build_sr) */
+} mvmc_status;
+
+typedef enum { MVMC_FP64 = 0, MVMC_MIXED = 1 } mvmc_precision;
+typedef enum { MVMC_SOLVE_CHOL = 0, MVMC_SOLVE_CG = 1 } mvmc_solver;
+
+/*
+ * One lattice instance (host pointers, copied at init).  Hamiltonian
+ * H = -sum_bonds,sigma t (c+_i c_j + h.c.) + sum_i U_i n_iup n_idn
+ * (section 2.3, Eq. GHam with H_U).  Index maps name the parameter slot of
+ * each pair amplitude f_ij, Gutzwiller g_i and Jastrow v_ij (the Orbital,
+ * Gutzwiller and Jastrow keyword files of Table 1), -1 = held at zero.
+ * Instance parameter vector: [f (n_f) | g (n_g) | v (n_v) | RBM a (2Ns) |
+ * RBM b (M) | RBM W (M x 2Ns row-major)], the RBM blocks only when M > 0.
+ */
+typedef struct {
+  int32_t n_sites;            /* Ns, 3..1024 */
+  int32_t n_up, n_dn;         /* n_up == n_dn >= 1 (anti-parallel pairing, Eq. AP-Pf) */
+  int32_t n_bonds;            /* unordered nearest-neighbour bonds */
+  const int32_t *bond_i;      /* [n_bonds] */
+  const int32_t *bond_j;      /* [n_bonds] */
+  const double *bond_t;       /* [n_bonds] hopping amplitude t_ij */
+  const double *U;            /* [Ns] on-site interaction */
+  int32_t n_f;                /* pair-amplitude slots */
+  const int32_t *f_idx;       /* [Ns*Ns] row-major, f_ij slot or -1 */
+  int32_t n_g;
+  const int32_t *g_idx;       /* [Ns] */
+  int32_t n_v;
+  const int32_t *v_idx;       /* [Ns*Ns] symmetric, diagonal -1 */
+  int32_t n_hidden;           /* RBM hidden units M; 0 = no RBM factor */
+  int32_t n_walkers;          /* independent Markov chains for this instance */
+} mvmc_instance_desc;
+
+typedef struct {
+  int32_t precision;          /* MVMC_FP64: double sweeps and S.  MVMC_MIXED: single-
+                                 precision sweeps/O, split-bf16 S with FP32 accumulation;
+                                 inverse refresh and SR solve stay double */
+  int32_t refresh_every;      /* proposals between full double recomputations of X^-1
+                                 (0 = only at init, set_state and parameter updates) */
+  uint64_t seed;              /* Philox4x32-10 key (proposal stream and initial draw) */
+  int32_t n_instances;
+  const mvmc_instance_desc *inst;
+  int32_t n_slots;            /* sample slots per SR step: rows of O per walker */
+  int32_t solver;             /* MVMC_SOLVE_CHOL reserves the double factor; CG does not */
+  int32_t build_s;            /* 1 = explicit S is built (reserves its scratch); 0 = CG only */
+  int32_t sweep_threads;      /* 0 = automatic, else 64, 128 or 256 threads per walker */
+} mvmc_config;
+
+/* Sizes of the caller-owned buffers for a configuration. */
+typedef struct {
+  int64_t n_walkers;          /* total walkers */
+  int64_t n_params;           /* total parameters (length of params, g, dparams) */
+  int64_t eloc_elems;         /* doubles in the local-energy buffer */
+  int64_t O_elems;            /* elements of O (double for FP64, float for MIXED) */
+  int64_t S_elems;            /* elements of S (same type as O); 0 when build_s == 0 */
+  int64_t Y_elems;            /* doubles returned by mvmc_get_inverse */
+  int64_t workspace_bytes;    /* device workspace, 256-byte aligned */
+  int32_t O_elem_bytes;       /* 8 (FP64) or 4 (MIXED) */
+  int32_t pad;
+} mvmc_sizes;
+
+/* Where instance k lives inside the caller buffers (element offsets). */
+typedef struct {
+  int64_t walker_off, n_walkers;   /* global walker ids [walker_off, walker_off+n_walkers) */
+  int64_t param_off, n_params;     /* block of params / g / dparams */
+  int64_t eloc_off;                /* eloc[eloc_off + slot*n_walkers + w] */
+  int64_t O_off, O_ld;             /* O row (slot*n_walkers + w) at O_off + row*O_ld */
+  int64_t S_off;                   /* S block [n_params][n_params] at S_off (full square) */
+  int64_t Y_off;                   /* get_inverse: walker w at Y_off + w*n_elec^2, row-major */
+  int64_t pos_off;                 /* get/set_state: walker w at pos_off + w*n_elec */
+  int32_t n_elec, n_sites;
+} mvmc_instance_layout;
+
+/* Sizes for cfg; touches no device.  Errors: MVMC_E_ARG / MVMC_E_SHAPE. */
+int mvmc_query_sizes(const mvmc_config *cfg, mvmc_sizes *out);
+
+/* Layout of instance k for cfg; touches no device. */
+int mvmc_query_layout(const mvmc_config *cfg, int32_t k, mvmc_instance_layout *out);
+
+/*
+ * Create a context: copies the descriptors, lays out the workspace, expands
+ * d_params (device, double, n_params) into the skew table A = F - F^T, v_ij,
+ * g_i and the RBM weights, draws a uniform initial configuration per walker
+ * (redrawn while X is singular) and computes X^-1 in double.
+ * d_workspace: device memory of at least workspace_bytes, 256-byte aligned,
+ * owned by the caller and untouched by anything else until mvmc_destroy.
+ * hip_stream: hipStream_t (NULL = default stream).
+ * Errors: MVMC_E_ARG, MVMC_E_SHAPE, MVMC_E_WORKSPACE, MVMC_E_HIP,
+ * MVMC_E_SINGULAR (no invertible initial configuration in 100 draws).
+ */
+int mvmc_init_wavefunction(mvmc_ctx **out, const mvmc_config *cfg, void *d_workspace,
+                           size_t ws_bytes, const double *d_params, void *hip_stream);
+
+/*
+ * n_sweeps sweeps of every walker; one sweep is N_e hopping proposals
+ * (section 3.1.2), each accepted with probability min(1, R^2), R = psi(x')/psi(x)
+ * from a row of X^-1 and the correlator ratios, followed on acceptance by the
+ * rank-2 update of X^-1.  h_accepted (may be NULL): [n_instances] accepted
+ * proposals in this call.
+ */
+int mvmc_sample_sweeps(mvmc_ctx *ctx, int32_t n_sweeps, int64_t *h_accepted);
+
+/*
+ * Local energy E_loc(x) (Eq. MC, H of section 2.3) and the row of
+ * O_k = d ln<x|psi>/d alpha_k (section 3.3.1) of every walker's current
+ * configuration into sample slot `slot` (0 <= slot < n_slots):
+ * d_eloc[eloc_off + slot*W + w] and O row slot*W + w (layout above); columns
+ * n_params..O_ld-1 are written as zero.
+ */
+int mvmc_measure_energy_and_O(mvmc_ctx *ctx, int32_t slot, double *d_eloc, void *d_O);
+
+/*
+ * SR quantities over the first n_slots_used slots (section 3.3.1):
+ * E_bar, var(E); o_k; O is centred in place (O <- O - o); d_g = O~^T(E-E_bar)/N
+ * (double, n_params); d_S (may be NULL) = O~^T O~ / N, both triangles of each
+ * instance block.  h_E, h_Evar (may be NULL): [n_instances].
+ */
+int mvmc_build_sr(mvmc_ctx *ctx, int32_t n_slots_used, const double *d_eloc, void *d_O, void *d_S,
+                  double *d_g, double *h_E, double *h_Evar);
+
+/*
+ * Solve S_reg x = g with S_reg = S + diag(eps_rel S_kk + eps_abs) (parameters
+ * with S_kk < 1e-12 frozen) by Cholesky (needs d_S from build_sr) or by CG
+ * (Algorithm 1, matrix-free over the centred d_O, stop when
+ * |r|^2 < cg_tol^2 |g|^2 or after cg_maxit iterations); then
+ * d_params += d_dparams = -dtau x (Eq. SR_equation_system), re-expands the
+ * tables and recomputes every walker's X^-1 in double.
+ * h_cg_iters (may be NULL): [n_instances].  d_dparams may be NULL.
+ * Errors: MVMC_E_STATE (build_sr not called), MVMC_E_SINGULAR (Cholesky failed
+ * or a walker's X became singular), MVMC_E_NONFINITE.
+ */
+int mvmc_sr_update(mvmc_ctx *ctx, const void *d_S, const void *d_O, const double *d_g, double dtau,
+                   double eps_rel, double eps_abs, int32_t solver, double cg_tol, int32_t cg_maxit,
+                   double *d_params, double *d_dparams, int32_t *h_cg_iters);
+
+/* Replace the parameters (device, double) and recompute every walker. */
+int mvmc_set_params(mvmc_ctx *ctx, const double *d_params);
+
+/* Walker configurations (spin-orbital of each electron; walker w of instance k
+ * at pos_off + w*n_elec) and the Philox proposal counters [n_walkers]. */
+int mvmc_get_state(mvmc_ctx *ctx, int32_t *d_pos, uint64_t *d_counter);
+
+/* Load configurations and counters (counters equal within an instance),
+ * rebuild the empty-site lists in ascending order and recompute X^-1. */
+int mvmc_set_state(mvmc_ctx *ctx, const int32_t *d_pos, const uint64_t *d_counter);
+
+/* Every walker's current X^-1 as double (Y_elems, layout above). */
+int mvmc_get_inverse(mvmc_ctx *ctx, double *d_Y);
+
+/* log|Pf(X)| and sign of every walker from the last full recomputation. */
+int mvmc_get_pfaffian(mvmc_ctx *ctx, double *d_logabs, double *d_sign);
+
+/* Full double recomputation of every walker now. */
+int mvmc_refresh(mvmc_ctx *ctx);
+
+/*
+ * Record every proposal into d_trace (32-byte records
+ * {int64 n; int32 walker; int32 a; int32 i_new; int32 accepted; double ratio}),
+ * record for proposal n of walker w at w*capacity + (n - n_at_enable).
+ * d_trace NULL or capacity 0 disables.
+ */
+int mvmc_trace_enable(mvmc_ctx *ctx, void *d_trace, int64_t per_walker_capacity);
+
+/*
+ * Kernel timing with HIP events on the context's stream.  enable = 1 starts
+ * (and clears) collection, 0 stops; when h_ms/h_calls are not NULL the
+ * totals so far are returned for categories
+ * [0 sweep, 1 refresh, 2 measure, 3 SR statistics, 4 S build, 5 SR solve].
+ */
+int mvmc_timing(mvmc_ctx *ctx, int32_t enable, double *h_ms, int64_t *h_calls);
+
+int mvmc_destroy(mvmc_ctx *ctx);
+const char *mvmc_last_error(const mvmc_ctx *ctx);
+const char *mvmc_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MVMC_H */

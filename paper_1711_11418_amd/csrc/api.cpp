@@ -1,0 +1,1127 @@
+// Host runtime of libmvmc: argument checks, workspace planning, walker
+// buckets, and the call sequence behind each entry point of include/mvmc.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mvmc.h"
+#include "launch.h"
+#include "sr.h"
+
+using namespace mvmc;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr size_t kLdsLimit = 152 * 1024;   // per-workgroup LDS budget used for residency
+constexpr int kMaxSites = 1024;
+constexpr int kMaxElec = 2048;
+constexpr int kTimingCats = 6;
+
+inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
+
+// ------------------------------------------------------------- planning
+struct Pool {
+  size_t off = 0, bytes = 0;
+};
+
+struct Plan {
+  std::vector<InstDev> inst;
+  std::vector<SrInst> sr;
+  // pools (byte offsets into the workspace)
+  Pool inst_p, srinst_p, walker_inst, lists, A64, A32, V, fidx, vidx, G, U, gidx, nbr_ptr,
+      nbr_site, nbr_t, fm_ptr, fm, gm_ptr, gm, vm_ptr, vm, rbm64, rbm32, Y, Y64, pos, empty, h,
+      theta, cnt, target, needs_refresh, accepted, logpf, sgnpf, minpiv, status, trace_base,
+      obar, sdiag, x, r, p, w, t, shift, mask, scal, colpart, syrkpart, chol, split;
+  size_t total = 0;
+  int64_t W = 0, np = 0, eloc = 0, O_elems = 0, S_elems = 0, Y_elems = 0;
+  int max_ne = 0, max_ns = 0, max_M = 0, max_ksplit = 1;
+  int64_t max_np = 0, max_ld = 0, max_rows = 0;
+  bool need_Y64 = false;
+  size_t tsize = 8;
+};
+
+struct HostInst {
+  std::vector<int32_t> f_idx, v_idx, g_idx;
+  std::vector<int32_t> nbr_ptr, nbr_site;
+  std::vector<double> nbr_t, U;
+  std::vector<int32_t> fm_ptr, fm, gm_ptr, gm, vm_ptr, vm;
+};
+
+struct Err {
+  int code = MVMC_OK;
+  std::string msg;
+};
+
+Err fail(int code, const char* fmt, ...) {
+  Err e;
+  e.code = code;
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  e.msg = buf;
+  return e;
+}
+
+int sweep_threads_for(const mvmc_config& c, int ne) {
+  if (c.sweep_threads) return c.sweep_threads;
+  return ne <= 48 ? 64 : (ne <= 96 ? 128 : 256);
+}
+
+Err validate(const mvmc_config* c) {
+  if (!c) return fail(MVMC_E_ARG, "config is NULL");
+  if (c->precision != MVMC_FP64 && c->precision != MVMC_MIXED)
+    return fail(MVMC_E_ARG, "precision must be MVMC_FP64 or MVMC_MIXED");
+  if (c->refresh_every < 0) return fail(MVMC_E_ARG, "refresh_every < 0");
+  if (c->n_instances < 1 || !c->inst) return fail(MVMC_E_ARG, "need at least one instance");
+  if (c->n_slots < 1) return fail(MVMC_E_ARG, "n_slots must be >= 1");
+  if (c->solver != MVMC_SOLVE_CHOL && c->solver != MVMC_SOLVE_CG)
+    return fail(MVMC_E_ARG, "solver must be MVMC_SOLVE_CHOL or MVMC_SOLVE_CG");
+  if (c->solver == MVMC_SOLVE_CHOL && !c->build_s)
+    return fail(MVMC_E_ARG, "the Cholesky solver needs build_s = 1");
+  if (c->sweep_threads && c->sweep_threads != 64 && c->sweep_threads != 128 &&
+      c->sweep_threads != 256)
+    return fail(MVMC_E_ARG, "sweep_threads must be 0, 64, 128 or 256");
+  for (int k = 0; k < c->n_instances; ++k) {
+    const mvmc_instance_desc& d = c->inst[k];
+    const int ns = d.n_sites;
+    if (ns < 3 || ns > kMaxSites) return fail(MVMC_E_SHAPE, "instance %d: n_sites %d outside [3, %d]", k, ns, kMaxSites);
+    if (d.n_up < 1 || d.n_dn < 1 || d.n_up > ns || d.n_dn > ns)
+      return fail(MVMC_E_SHAPE, "instance %d: electron counts out of range", k);
+    if (d.n_up != d.n_dn)
+      return fail(MVMC_E_SHAPE, "instance %d: anti-parallel pairing needs n_up == n_dn", k);
+    if (d.n_up + d.n_dn > kMaxElec) return fail(MVMC_E_SHAPE, "instance %d: too many electrons", k);
+    if (d.n_walkers < 1) return fail(MVMC_E_SHAPE, "instance %d: n_walkers < 1", k);
+    if (d.n_bonds < 0 || (d.n_bonds > 0 && (!d.bond_i || !d.bond_j || !d.bond_t)))
+      return fail(MVMC_E_ARG, "instance %d: bond arrays missing", k);
+    for (int b = 0; b < d.n_bonds; ++b) {
+      if (d.bond_i[b] < 0 || d.bond_i[b] >= ns || d.bond_j[b] < 0 || d.bond_j[b] >= ns ||
+          d.bond_i[b] == d.bond_j[b])
+        return fail(MVMC_E_ARG, "instance %d: bond %d out of range", k, b);
+      if (!std::isfinite(d.bond_t[b])) return fail(MVMC_E_NONFINITE, "instance %d: bond_t not finite", k);
+    }
+    if (!d.U || !d.f_idx || !d.g_idx || !d.v_idx) return fail(MVMC_E_ARG, "instance %d: map missing", k);
+    for (int i = 0; i < ns; ++i)
+      if (!std::isfinite(d.U[i])) return fail(MVMC_E_NONFINITE, "instance %d: U not finite", k);
+    if (d.n_f < 0 || d.n_g < 0 || d.n_v < 0 || d.n_hidden < 0)
+      return fail(MVMC_E_ARG, "instance %d: negative parameter count", k);
+    for (int e = 0; e < ns * ns; ++e) {
+      if (d.f_idx[e] < -1 || d.f_idx[e] >= d.n_f) return fail(MVMC_E_ARG, "instance %d: f_idx[%d] out of range", k, e);
+      if (d.v_idx[e] < -1 || d.v_idx[e] >= d.n_v) return fail(MVMC_E_ARG, "instance %d: v_idx[%d] out of range", k, e);
+      const int i = e / ns, j = e % ns;
+      if (d.v_idx[e] != d.v_idx[j * ns + i]) return fail(MVMC_E_ARG, "instance %d: v_idx not symmetric", k);
+      if (i == j && d.v_idx[e] != -1) return fail(MVMC_E_ARG, "instance %d: v_idx diagonal must be -1", k);
+    }
+    for (int i = 0; i < ns; ++i)
+      if (d.g_idx[i] < -1 || d.g_idx[i] >= d.n_g) return fail(MVMC_E_ARG, "instance %d: g_idx out of range", k);
+  }
+  return Err{};
+}
+
+int64_t nparams_of(const mvmc_instance_desc& d) {
+  const int64_t n2 = 2 * (int64_t)d.n_sites;
+  const int64_t rbm = d.n_hidden ? n2 + d.n_hidden + (int64_t)d.n_hidden * n2 : 0;
+  return (int64_t)d.n_f + d.n_g + d.n_v + rbm;
+}
+
+int64_t f_members(const mvmc_instance_desc& d) {
+  int64_t m = 0;
+  for (int e = 0; e < d.n_sites * d.n_sites; ++e) m += d.f_idx[e] >= 0;
+  return m;
+}
+int64_t v_members(const mvmc_instance_desc& d) {
+  int64_t m = 0;
+  const int ns = d.n_sites;
+  for (int i = 0; i < ns; ++i)
+    for (int j = i + 1; j < ns; ++j) m += d.v_idx[i * ns + j] >= 0;
+  return m;
+}
+
+Plan make_plan(const mvmc_config& c) {
+  Plan P;
+  P.tsize = c.precision == MVMC_FP64 ? 8 : 4;
+  const int n = c.n_instances;
+  P.inst.resize(n);
+  P.sr.resize(n);
+  int64_t off_A = 0, off_V = 0, off_site = 0, off_nptr = 0, off_nbr = 0, off_fm_ptr = 0,
+          off_fm = 0, off_gm_ptr = 0, off_gm = 0, off_vm_ptr = 0, off_vm = 0, off_rbm = 0,
+          off_Y = 0, off_pos = 0, off_empty = 0, off_h = 0, off_theta = 0, off_chol = 0,
+          off_split = 0, off_colpart = 0, off_syrkpart = 0, off_O = 0, off_S = 0;
+  for (int k = 0; k < n; ++k) {
+    const mvmc_instance_desc& d = c.inst[k];
+    InstDev& I = P.inst[k];
+    std::memset(&I, 0, sizeof I);
+    I.ns = d.n_sites;
+    I.nup = d.n_up;
+    I.ndn = d.n_dn;
+    I.ne = d.n_up + d.n_dn;
+    I.nf = d.n_f;
+    I.ng = d.n_g;
+    I.nv = d.n_v;
+    I.M = d.n_hidden;
+    I.W = d.n_walkers;
+    I.np = (int32_t)nparams_of(d);
+    I.ldO = (int32_t)((I.np + 63) / 64 * 64);
+    std::vector<int> deg(I.ns, 0);
+    for (int b = 0; b < d.n_bonds; ++b) {
+      ++deg[d.bond_i[b]];
+      ++deg[d.bond_j[b]];
+    }
+    I.deg_max = 0;
+    for (int x : deg) I.deg_max = std::max(I.deg_max, x);
+    const int nt = sweep_threads_for(c, I.ne);
+    I.sweep_lds = sweep_lds_bytes(I.ne, I.ns, I.M, true, P.tsize, nt) <= kLdsLimit;
+    I.refresh_lds = refresh_lds_bytes(I.ne, I.ns, true) <= kLdsLimit;
+    if (!I.refresh_lds) P.need_Y64 = true;
+    I.walker_off = P.W;
+    I.param_off = P.np;
+    I.rows = (int64_t)c.n_slots * I.W;
+    I.eloc_off = P.eloc;
+    I.O_off = off_O;
+    I.S_off = off_S;
+    const int64_t n2 = 2 * (int64_t)I.ns;
+    I.A_off = off_A;
+    off_A += n2 * n2;
+    I.V_off = off_V;
+    off_V += (int64_t)I.ns * I.ns;
+    I.site_off = off_site;
+    off_site += I.ns;
+    I.nptr_off = off_nptr;
+    off_nptr += I.ns + 1;
+    I.nbr_off = off_nbr;
+    off_nbr += 2 * (int64_t)d.n_bonds;
+    I.fm_ptr_off = off_fm_ptr;
+    off_fm_ptr += I.nf + 1;
+    I.fm_off = off_fm;
+    off_fm += f_members(d);
+    I.gm_ptr_off = off_gm_ptr;
+    off_gm_ptr += I.ng + 1;
+    I.gm_off = off_gm;
+    off_gm += I.ns;
+    I.vm_ptr_off = off_vm_ptr;
+    off_vm_ptr += I.nv + 1;
+    I.vm_off = off_vm;
+    off_vm += v_members(d);
+    I.rbm_a_off = off_rbm;
+    I.rbm_b_off = off_rbm + (I.M ? n2 : 0);
+    I.rbm_W_off = I.rbm_b_off + I.M;
+    off_rbm += I.M ? n2 + I.M + I.M * n2 : 0;
+    I.Y_off = off_Y;
+    off_Y += (int64_t)I.W * I.ne * I.ne;
+    I.pos_off = off_pos;
+    off_pos += (int64_t)I.W * I.ne;
+    I.empty_off = off_empty;
+    off_empty += (int64_t)I.W * n2;
+    I.h_off = off_h;
+    off_h += (int64_t)I.W * I.ns;
+    I.theta_off = off_theta;
+    off_theta += (int64_t)I.W * I.M;
+    I.chol_off = off_chol;
+    if (c.build_s && c.solver == MVMC_SOLVE_CHOL) off_chol += (int64_t)I.np * I.np;
+    I.split_off = off_split;
+    if (c.build_s && c.precision == MVMC_MIXED) off_split += 2 * I.rows * I.ldO;
+
+    SrInst& S = P.sr[k];
+    std::memset(&S, 0, sizeof S);
+    S.np = I.np;
+    S.ldO = I.ldO;
+    S.rows = I.rows;
+    S.O_off = I.O_off;
+    S.S_off = I.S_off;
+    S.eloc_off = I.eloc_off;
+    S.param_off = I.param_off;
+    S.chol_off = I.chol_off;
+    S.split_off = I.split_off;
+    S.colpart_off = off_colpart;
+    off_colpart += 3 * ((I.rows + kRowChunk - 1) / kRowChunk) * I.ldO;
+    const int64_t ntile = (I.np + 63) / 64;
+    const int64_t tiles = ntile * (ntile + 1) / 2;
+    int64_t ks = std::max<int64_t>(1, 1024 / std::max<int64_t>(tiles, 1));
+    ks = std::min<int64_t>(ks, std::max<int64_t>(1, I.rows / 256));
+    while (ks > 1 && ks * tiles * 4096 * 8 > ((int64_t)256 << 20)) ks /= 2;
+    S.ksplit = (int32_t)ks;
+    S.syrkpart_off = off_syrkpart;
+    if (c.build_s) off_syrkpart += ks * tiles * 4096;
+
+    off_O += I.rows * I.ldO;
+    if (c.build_s) off_S += (int64_t)I.np * I.np;
+    P.W += I.W;
+    P.np += I.np;
+    P.eloc += I.rows;
+    P.Y_elems += (int64_t)I.W * I.ne * I.ne;
+    P.max_ne = std::max(P.max_ne, I.ne);
+    P.max_ns = std::max(P.max_ns, I.ns);
+    P.max_M = std::max(P.max_M, I.M);
+    P.max_np = std::max<int64_t>(P.max_np, I.np);
+    P.max_ld = std::max<int64_t>(P.max_ld, I.ldO);
+    P.max_rows = std::max<int64_t>(P.max_rows, I.rows);
+    P.max_ksplit = std::max<int>(P.max_ksplit, S.ksplit);
+  }
+  P.O_elems = off_O;
+  P.S_elems = c.build_s ? off_S : 0;
+
+  size_t cur = 0;
+  auto take = [&](Pool& p, size_t bytes) {
+    p.off = cur;
+    p.bytes = bytes;
+    cur = align_up(cur + std::max<size_t>(bytes, 1));
+  };
+  const size_t W = (size_t)P.W;
+  take(P.inst_p, sizeof(InstDev) * n);
+  take(P.srinst_p, sizeof(SrInst) * n);
+  take(P.walker_inst, 4 * W);
+  take(P.lists, 4 * W * 4);
+  take(P.A64, 8 * (size_t)off_A);
+  take(P.A32, 4 * (size_t)off_A);
+  take(P.V, 8 * (size_t)off_V);
+  take(P.fidx, 4 * (size_t)off_V);
+  take(P.vidx, 4 * (size_t)off_V);
+  take(P.G, 8 * (size_t)off_site);
+  take(P.U, 8 * (size_t)off_site);
+  take(P.gidx, 4 * (size_t)off_site);
+  take(P.nbr_ptr, 4 * (size_t)off_nptr);
+  take(P.nbr_site, 4 * (size_t)off_nbr);
+  take(P.nbr_t, 8 * (size_t)off_nbr);
+  take(P.fm_ptr, 4 * (size_t)off_fm_ptr);
+  take(P.fm, 4 * (size_t)off_fm);
+  take(P.gm_ptr, 4 * (size_t)off_gm_ptr);
+  take(P.gm, 4 * (size_t)off_gm);
+  take(P.vm_ptr, 4 * (size_t)off_vm_ptr);
+  take(P.vm, 4 * (size_t)off_vm);
+  take(P.rbm64, 8 * (size_t)off_rbm);
+  take(P.rbm32, 4 * (size_t)off_rbm);
+  take(P.Y, P.tsize * (size_t)off_Y);
+  take(P.Y64, P.need_Y64 ? 8 * (size_t)off_Y : 0);
+  take(P.pos, 4 * (size_t)off_pos);
+  take(P.empty, 4 * (size_t)off_empty);
+  take(P.h, 8 * (size_t)off_h);
+  take(P.theta, 8 * (size_t)off_theta);
+  take(P.cnt, 8 * W);
+  take(P.target, 8 * W);
+  take(P.needs_refresh, 4 * W);
+  take(P.accepted, 8 * W);
+  take(P.logpf, 8 * W);
+  take(P.sgnpf, 8 * W);
+  take(P.minpiv, 8 * W);
+  take(P.status, 4 * W);
+  take(P.trace_base, 8 * W);
+  const size_t NP = (size_t)P.np;
+  take(P.obar, 8 * NP);
+  take(P.sdiag, 8 * NP);
+  take(P.x, 8 * NP);
+  take(P.r, 8 * NP);
+  take(P.p, 8 * NP);
+  take(P.w, 8 * NP);
+  take(P.shift, 8 * NP);
+  take(P.mask, 8 * NP);
+  take(P.t, 8 * (size_t)P.eloc);
+  take(P.scal, 8 * (size_t)kScal * n);
+  take(P.colpart, 8 * (size_t)off_colpart);
+  take(P.syrkpart, 8 * (size_t)off_syrkpart);
+  take(P.chol, 8 * (size_t)off_chol);
+  take(P.split, 2 * (size_t)off_split);
+  P.total = cur;
+  return P;
+}
+
+HostInst host_tables(const mvmc_instance_desc& d) {
+  HostInst H;
+  const int ns = d.n_sites;
+  H.f_idx.assign(d.f_idx, d.f_idx + ns * ns);
+  H.v_idx.assign(d.v_idx, d.v_idx + ns * ns);
+  H.g_idx.assign(d.g_idx, d.g_idx + ns);
+  H.U.assign(d.U, d.U + ns);
+  std::vector<std::vector<std::pair<int, double>>> nb(ns);
+  for (int b = 0; b < d.n_bonds; ++b) {
+    nb[d.bond_i[b]].push_back({d.bond_j[b], d.bond_t[b]});
+    nb[d.bond_j[b]].push_back({d.bond_i[b], d.bond_t[b]});
+  }
+  H.nbr_ptr.push_back(0);
+  for (int s = 0; s < ns; ++s) {
+    for (auto& e : nb[s]) {
+      H.nbr_site.push_back(e.first);
+      H.nbr_t.push_back(e.second);
+    }
+    H.nbr_ptr.push_back((int32_t)H.nbr_site.size());
+  }
+  std::vector<std::vector<int32_t>> fl(d.n_f), gl(d.n_g), vl(d.n_v);
+  for (int i = 0; i < ns; ++i)
+    for (int j = 0; j < ns; ++j)
+      if (d.f_idx[i * ns + j] >= 0) fl[d.f_idx[i * ns + j]].push_back(i * ns + j);
+  for (int i = 0; i < ns; ++i)
+    if (d.g_idx[i] >= 0) gl[d.g_idx[i]].push_back(i);
+  for (int i = 0; i < ns; ++i)
+    for (int j = i + 1; j < ns; ++j)
+      if (d.v_idx[i * ns + j] >= 0) vl[d.v_idx[i * ns + j]].push_back(i * ns + j);
+  auto csr = [](const std::vector<std::vector<int32_t>>& L, std::vector<int32_t>& ptr,
+                std::vector<int32_t>& idx) {
+    ptr.push_back(0);
+    for (auto& l : L) {
+      idx.insert(idx.end(), l.begin(), l.end());
+      ptr.push_back((int32_t)idx.size());
+    }
+  };
+  csr(fl, H.fm_ptr, H.fm);
+  csr(gl, H.gm_ptr, H.gm);
+  csr(vl, H.vm_ptr, H.vm);
+  return H;
+}
+
+struct Bucket {
+  size_t list_off;   // byte offset of its walker list inside the list pool
+  int n = 0, max_ne = 0, max_ns = 0, max_M = 0, nthreads = 256;
+  bool lds = true;
+};
+
+}  // namespace
+
+// ------------------------------------------------------------------ context
+struct mvmc_ctx {
+  mvmc_config cfg{};
+  std::vector<mvmc_instance_desc> desc;
+  Plan plan;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  Pools P{};
+  SrArgs SA{};
+  int32_t* d_all = nullptr;       // every walker, instance order
+  int32_t* d_scratch = nullptr;   // redraw list
+  std::vector<Bucket> sweep_b, refresh_b;
+  std::vector<uint64_t> cnt_host;   // per-instance proposal counter mirror
+  TraceRec* trace = nullptr;
+  int64_t trace_cap = 0;
+  bool sr_ready = false;
+  std::string err;
+  SrInst* h_sr = nullptr;           // pinned staging of the SR table
+  // timing
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+  size_t ev_used = 0;
+  std::vector<int> ev_cat;
+  double t_ms[kTimingCats] = {};
+  int64_t t_calls[kTimingCats] = {};
+};
+
+namespace {
+
+int set_err(mvmc_ctx* c, const Err& e) {
+  if (c) c->err = e.msg;
+  return e.code;
+}
+
+#define HIPCHK(ctx, expr)                                                                  \
+  do {                                                                                     \
+    hipError_t _e = (expr);                                                                \
+    if (_e != hipSuccess) {                                                                \
+      return set_err(ctx, fail(MVMC_E_HIP, "%s failed: %s", #expr, hipGetErrorString(_e))); \
+    }                                                                                      \
+  } while (0)
+
+#define LAUNCHCHK(ctx)                                                                         \
+  do {                                                                                         \
+    hipError_t _e = hipGetLastError();                                                         \
+    if (_e != hipSuccess) return set_err(ctx, fail(MVMC_E_HIP, "kernel launch: %s", hipGetErrorString(_e))); \
+  } while (0)
+
+template <typename T>
+T* at(char* base, const Pool& p) {
+  return reinterpret_cast<T*>(base + p.off);
+}
+
+// timing helpers: events bracket a group of launches of one category
+int tic(mvmc_ctx* c, int cat) {
+  if (!c->timing) return -1;
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return -1;
+    c->ev_pool.push_back({a, b});
+    c->ev_cat.push_back(cat);
+  }
+  const int id = (int)c->ev_used++;
+  c->ev_cat[id] = cat;
+  (void)hipEventRecord(c->ev_pool[id].first, c->stream);
+  return id;
+}
+void toc(mvmc_ctx* c, int id) {
+  if (id >= 0) (void)hipEventRecord(c->ev_pool[id].second, c->stream);
+}
+void harvest(mvmc_ctx* c) {
+  if (!c->ev_used) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (size_t i = 0; i < c->ev_used; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev_pool[i].first, c->ev_pool[i].second) == hipSuccess) {
+      c->t_ms[c->ev_cat[i]] += ms;
+      c->t_calls[c->ev_cat[i]] += 1;
+    }
+  }
+  c->ev_used = 0;
+}
+
+void build_buckets(mvmc_ctx* c) {
+  const Plan& P = c->plan;
+  const int n = c->cfg.n_instances;
+  // key: (lds flag, LDS size class or 0, threads)
+  std::map<std::tuple<int, size_t, int>, std::vector<int>> sweep_groups, refresh_groups;
+  for (int k = 0; k < n; ++k) {
+    const InstDev& I = P.inst[k];
+    const int nt = sweep_threads_for(c->cfg, I.ne);
+    size_t sb = sweep_lds_bytes(I.ne, I.ns, I.M, I.sweep_lds, P.tsize, nt);
+    size_t cls = 4096;
+    while (cls < sb) cls <<= 1;
+    sweep_groups[{I.sweep_lds, cls, nt}].push_back(k);
+    size_t rb = refresh_lds_bytes(I.ne, I.ns, I.refresh_lds);
+    size_t rcls = 4096;
+    while (rcls < rb) rcls <<= 1;
+    refresh_groups[{I.refresh_lds, rcls, 256}].push_back(k);
+  }
+  std::vector<int32_t> lists;
+  auto emit = [&](const std::map<std::tuple<int, size_t, int>, std::vector<int>>& groups,
+                  std::vector<Bucket>& out) {
+    for (auto& g : groups) {
+      Bucket b;
+      b.lds = std::get<0>(g.first);
+      b.nthreads = std::get<2>(g.first);
+      b.list_off = lists.size() * 4;
+      std::vector<int> ks = g.second;
+      // longest walkers first (cost ~ N_e^2)
+      std::stable_sort(ks.begin(), ks.end(), [&](int a, int bb) {
+        return P.inst[a].ne > P.inst[bb].ne;
+      });
+      for (int k : ks) {
+        const InstDev& I = P.inst[k];
+        for (int w = 0; w < I.W; ++w) lists.push_back((int32_t)(I.walker_off + w));
+        b.max_ne = std::max(b.max_ne, I.ne);
+        b.max_ns = std::max(b.max_ns, I.ns);
+        b.max_M = std::max(b.max_M, I.M);
+      }
+      b.n = (int)(lists.size() - b.list_off / 4);
+      out.push_back(b);
+    }
+  };
+  emit(sweep_groups, c->sweep_b);
+  emit(refresh_groups, c->refresh_b);
+  // list pool: [sweep lists | refresh lists | all walkers | scratch]
+  const size_t W = (size_t)P.W;
+  std::vector<int32_t> all(W);
+  for (size_t w = 0; w < W; ++w) all[w] = (int32_t)w;
+  char* base = c->ws + P.lists.off;
+  (void)hipMemcpy(base, lists.data(), lists.size() * 4, hipMemcpyHostToDevice);
+  c->d_all = reinterpret_cast<int32_t*>(base + 2 * W * 4);
+  c->d_scratch = reinterpret_cast<int32_t*>(base + 3 * W * 4);
+  (void)hipMemcpy(c->d_all, all.data(), W * 4, hipMemcpyHostToDevice);
+}
+
+template <typename T>
+int refresh_all(mvmc_ctx* c, double sing_tol) {
+  const int id = tic(c, 1);
+  for (auto& b : c->refresh_b)
+    launch_refresh<T>(c->P, reinterpret_cast<int32_t*>(c->ws + c->plan.lists.off + b.list_off),
+                      b.n, b.max_ne, b.max_ns, b.lds, sing_tol, c->stream);
+  toc(c, id);
+  LAUNCHCHK(c);
+  return MVMC_OK;
+}
+
+int refresh_any(mvmc_ctx* c, double sing_tol) {
+  return c->cfg.precision == MVMC_FP64 ? refresh_all<double>(c, sing_tol)
+                                       : refresh_all<float>(c, sing_tol);
+}
+
+// Read walker status; returns the first singular walker or -1.
+int first_singular(mvmc_ctx* c, std::vector<int32_t>& st) {
+  st.resize(c->plan.W);
+  if (hipMemcpyAsync(st.data(), c->P.status, 4 * st.size(), hipMemcpyDeviceToHost, c->stream) !=
+      hipSuccess)
+    return -2;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return -2;
+  for (size_t w = 0; w < st.size(); ++w)
+    if (st[w]) return (int)w;
+  return -1;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- entry points
+extern "C" {
+
+const char* mvmc_status_string(int s) {
+  switch (s) {
+    case MVMC_OK: return "ok";
+    case MVMC_E_ARG: return "invalid argument";
+    case MVMC_E_SHAPE: return "inconsistent shape";
+    case MVMC_E_WORKSPACE: return "workspace too small or misaligned";
+    case MVMC_E_HIP: return "HIP runtime error";
+    case MVMC_E_SINGULAR: return "singular matrix";
+    case MVMC_E_NONFINITE: return "non-finite value";
+    case MVMC_E_STATE: return "call out of order";
+    default: return "unknown status";
+  }
+}
+
+const char* mvmc_last_error(const mvmc_ctx* c) { return c ? c->err.c_str() : "no context"; }
+
+int mvmc_query_sizes(const mvmc_config* cfg, mvmc_sizes* out) {
+  Err e = validate(cfg);
+  if (e.code) return e.code;
+  if (!out) return MVMC_E_ARG;
+  Plan P = make_plan(*cfg);
+  out->n_walkers = P.W;
+  out->n_params = P.np;
+  out->eloc_elems = P.eloc;
+  out->O_elems = P.O_elems;
+  out->S_elems = P.S_elems;
+  out->Y_elems = P.Y_elems;
+  out->workspace_bytes = (int64_t)P.total;
+  out->O_elem_bytes = (int32_t)P.tsize;
+  out->pad = 0;
+  return MVMC_OK;
+}
+
+int mvmc_query_layout(const mvmc_config* cfg, int32_t k, mvmc_instance_layout* out) {
+  Err e = validate(cfg);
+  if (e.code) return e.code;
+  if (!out || k < 0 || k >= cfg->n_instances) return MVMC_E_ARG;
+  Plan P = make_plan(*cfg);
+  const InstDev& I = P.inst[k];
+  out->walker_off = I.walker_off;
+  out->n_walkers = I.W;
+  out->param_off = I.param_off;
+  out->n_params = I.np;
+  out->eloc_off = I.eloc_off;
+  out->O_off = I.O_off;
+  out->O_ld = I.ldO;
+  out->S_off = I.S_off;
+  out->Y_off = I.Y_off;
+  out->pos_off = I.pos_off;
+  out->n_elec = I.ne;
+  out->n_sites = I.ns;
+  return MVMC_OK;
+}
+
+int mvmc_init_wavefunction(mvmc_ctx** out, const mvmc_config* cfg, void* d_ws, size_t ws_bytes,
+                           const double* d_params, void* hip_stream) {
+  if (!out) return MVMC_E_ARG;
+  *out = nullptr;
+  Err e = validate(cfg);
+  if (e.code) return e.code;
+  if (!d_ws || !d_params) return MVMC_E_ARG;
+  if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) return MVMC_E_WORKSPACE;
+  mvmc_ctx* c = new (std::nothrow) mvmc_ctx;
+  if (!c) return MVMC_E_ARG;
+  c->cfg = *cfg;
+  c->desc.assign(cfg->inst, cfg->inst + cfg->n_instances);
+  c->cfg.inst = c->desc.data();
+  c->plan = make_plan(c->cfg);
+  if (ws_bytes < c->plan.total) {
+    delete c;
+    return MVMC_E_WORKSPACE;
+  }
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  c->ws = reinterpret_cast<char*>(d_ws);
+  const Plan& P = c->plan;
+  char* b = c->ws;
+  Pools& Q = c->P;
+  Q.inst = at<InstDev>(b, P.inst_p);
+  Q.walker_inst = at<int32_t>(b, P.walker_inst);
+  Q.A64 = at<double>(b, P.A64);
+  Q.A32 = at<float>(b, P.A32);
+  Q.V = at<double>(b, P.V);
+  Q.G = at<double>(b, P.G);
+  Q.U = at<double>(b, P.U);
+  Q.nbr_ptr = at<int32_t>(b, P.nbr_ptr);
+  Q.nbr_site = at<int32_t>(b, P.nbr_site);
+  Q.nbr_t = at<double>(b, P.nbr_t);
+  Q.fidx = at<int32_t>(b, P.fidx);
+  Q.vidx = at<int32_t>(b, P.vidx);
+  Q.gidx = at<int32_t>(b, P.gidx);
+  Q.fm_ptr = at<int32_t>(b, P.fm_ptr);
+  Q.fm = at<int32_t>(b, P.fm);
+  Q.gm_ptr = at<int32_t>(b, P.gm_ptr);
+  Q.gm = at<int32_t>(b, P.gm);
+  Q.vm_ptr = at<int32_t>(b, P.vm_ptr);
+  Q.vm = at<int32_t>(b, P.vm);
+  Q.rbm64 = at<double>(b, P.rbm64);
+  Q.rbm32 = at<float>(b, P.rbm32);
+  Q.Y = b + P.Y.off;
+  Q.Y64 = P.need_Y64 ? at<double>(b, P.Y64) : nullptr;
+  Q.pos = at<int32_t>(b, P.pos);
+  Q.empty = at<int32_t>(b, P.empty);
+  Q.h = at<double>(b, P.h);
+  Q.theta = at<double>(b, P.theta);
+  Q.cnt = at<uint64_t>(b, P.cnt);
+  Q.accepted = at<int64_t>(b, P.accepted);
+  Q.logpf = at<double>(b, P.logpf);
+  Q.sgnpf = at<double>(b, P.sgnpf);
+  Q.minpiv = at<double>(b, P.minpiv);
+  Q.status = at<int32_t>(b, P.status);
+  SrArgs& S = c->SA;
+  S.inst = at<SrInst>(b, P.srinst_p);
+  S.obar = at<double>(b, P.obar);
+  S.sdiag = at<double>(b, P.sdiag);
+  S.scal = at<double>(b, P.scal);
+  S.colpart = at<double>(b, P.colpart);
+  S.syrkpart = at<double>(b, P.syrkpart);
+  S.chol = at<double>(b, P.chol);
+  S.x = at<double>(b, P.x);
+  S.r = at<double>(b, P.r);
+  S.p = at<double>(b, P.p);
+  S.w = at<double>(b, P.w);
+  S.t = at<double>(b, P.t);
+  S.shift = at<double>(b, P.shift);
+  S.mask = at<double>(b, P.mask);
+
+  // static tables
+  std::vector<int32_t> winst(P.W);
+  std::vector<int32_t> fidx, vidx, gidx, nptr, nsite, fmp, fm, gmp, gm, vmp, vm;
+  std::vector<double> U, nt;
+  for (int k = 0; k < cfg->n_instances; ++k) {
+    HostInst H = host_tables(c->desc[k]);
+    const InstDev& I = P.inst[k];
+    for (int w = 0; w < I.W; ++w) winst[I.walker_off + w] = k;
+    fidx.insert(fidx.end(), H.f_idx.begin(), H.f_idx.end());
+    vidx.insert(vidx.end(), H.v_idx.begin(), H.v_idx.end());
+    gidx.insert(gidx.end(), H.g_idx.begin(), H.g_idx.end());
+    U.insert(U.end(), H.U.begin(), H.U.end());
+    nptr.insert(nptr.end(), H.nbr_ptr.begin(), H.nbr_ptr.end());
+    nsite.insert(nsite.end(), H.nbr_site.begin(), H.nbr_site.end());
+    nt.insert(nt.end(), H.nbr_t.begin(), H.nbr_t.end());
+    fmp.insert(fmp.end(), H.fm_ptr.begin(), H.fm_ptr.end());
+    fm.insert(fm.end(), H.fm.begin(), H.fm.end());
+    gmp.insert(gmp.end(), H.gm_ptr.begin(), H.gm_ptr.end());
+    gm.insert(gm.end(), H.gm.begin(), H.gm.end());
+    vmp.insert(vmp.end(), H.vm_ptr.begin(), H.vm_ptr.end());
+    vm.insert(vm.end(), H.vm.begin(), H.vm.end());
+  }
+  auto up = [&](const Pool& p, const void* src, size_t bytes) -> hipError_t {
+    if (!bytes) return hipSuccess;
+    return hipMemcpy(b + p.off, src, bytes, hipMemcpyHostToDevice);
+  };
+  hipError_t he = hipSuccess;
+  auto chk = [&](hipError_t x) {
+    if (x != hipSuccess && he == hipSuccess) he = x;
+  };
+  chk(up(P.inst_p, P.inst.data(), sizeof(InstDev) * P.inst.size()));
+  chk(up(P.srinst_p, P.sr.data(), sizeof(SrInst) * P.sr.size()));
+  chk(up(P.walker_inst, winst.data(), 4 * winst.size()));
+  chk(up(P.fidx, fidx.data(), 4 * fidx.size()));
+  chk(up(P.vidx, vidx.data(), 4 * vidx.size()));
+  chk(up(P.gidx, gidx.data(), 4 * gidx.size()));
+  chk(up(P.U, U.data(), 8 * U.size()));
+  chk(up(P.nbr_ptr, nptr.data(), 4 * nptr.size()));
+  chk(up(P.nbr_site, nsite.data(), 4 * nsite.size()));
+  chk(up(P.nbr_t, nt.data(), 8 * nt.size()));
+  chk(up(P.fm_ptr, fmp.data(), 4 * fmp.size()));
+  chk(up(P.fm, fm.data(), 4 * fm.size()));
+  chk(up(P.gm_ptr, gmp.data(), 4 * gmp.size()));
+  chk(up(P.gm, gm.data(), 4 * gm.size()));
+  chk(up(P.vm_ptr, vmp.data(), 4 * vmp.size()));
+  chk(up(P.vm, vm.data(), 4 * vm.size()));
+  chk(hipMemset(Q.cnt, 0, 8 * P.W));
+  chk(hipMemset(Q.accepted, 0, 8 * P.W));
+  chk(hipMemset(b + P.needs_refresh.off, 0, 4 * P.W));
+  chk(hipMemset(Q.theta, 0, 8 * std::max<size_t>(P.theta.bytes / 8, 1)));
+  chk(hipMemset(S.scal, 0, P.scal.bytes));
+  chk(hipHostMalloc((void**)&c->h_sr, sizeof(SrInst) * P.sr.size(), hipHostMallocDefault));
+  if (he != hipSuccess) {
+    c->err = std::string("init upload: ") + hipGetErrorString(he);
+    mvmc_destroy(c);
+    return MVMC_E_HIP;
+  }
+  std::memcpy(c->h_sr, P.sr.data(), sizeof(SrInst) * P.sr.size());
+  build_buckets(c);
+  c->cnt_host.assign(cfg->n_instances, 0);
+
+  // parameters -> tables
+  launch_expand(Q, P.inst.data(), cfg->n_instances, d_params, c->stream);
+  // initial configurations: uniform draws, redrawn while X is singular
+  std::vector<int32_t> st;
+  std::vector<int32_t> redo(P.W);
+  for (int64_t w = 0; w < P.W; ++w) redo[w] = (int32_t)w;
+  int attempt = 0;
+  for (; attempt < 100 && !redo.empty(); ++attempt) {
+    if (hipMemcpy(c->d_scratch, redo.data(), 4 * redo.size(), hipMemcpyHostToDevice) != hipSuccess)
+      break;
+    launch_draw_configs(Q, c->d_scratch, (int)redo.size(), cfg->seed, (uint32_t)attempt, c->stream);
+    launch_build_empty(Q, c->d_scratch, (int)redo.size(), P.max_ns, c->stream);
+    int rc = refresh_any(c, 1e-8);
+    if (rc) {
+      mvmc_destroy(c);
+      return rc;
+    }
+    if (first_singular(c, st) == -2) break;
+    redo.clear();
+    for (int64_t w = 0; w < P.W; ++w)
+      if (st[w]) redo.push_back((int32_t)w);
+  }
+  if (hipGetLastError() != hipSuccess || !redo.empty()) {
+    const int code = redo.empty() ? MVMC_E_HIP : MVMC_E_SINGULAR;
+    fprintf(stderr, "mvmc_init_wavefunction: %s (%zu walkers without an invertible start)\n",
+            mvmc_status_string(code), redo.size());
+    mvmc_destroy(c);
+    return code;
+  }
+  *out = c;
+  return MVMC_OK;
+}
+
+int mvmc_destroy(mvmc_ctx* c) {
+  if (!c) return MVMC_OK;
+  for (auto& e : c->ev_pool) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  if (c->h_sr) (void)hipHostFree(c->h_sr);
+  delete c;
+  return MVMC_OK;
+}
+
+int mvmc_set_params(mvmc_ctx* c, const double* d_params) {
+  if (!c || !d_params) return MVMC_E_ARG;
+  launch_expand(c->P, c->plan.inst.data(), c->cfg.n_instances, d_params, c->stream);
+  LAUNCHCHK(c);
+  return refresh_any(c, 0.0);
+}
+
+int mvmc_refresh(mvmc_ctx* c) {
+  if (!c) return MVMC_E_ARG;
+  return refresh_any(c, 0.0);
+}
+
+int mvmc_sample_sweeps(mvmc_ctx* c, int32_t n_sweeps, int64_t* h_accepted) {
+  if (!c || n_sweeps < 0) return set_err(c, fail(MVMC_E_ARG, "n_sweeps must be >= 0"));
+  const Plan& P = c->plan;
+  const int R = c->cfg.refresh_every;
+  HIPCHK(c, hipMemsetAsync(c->P.accepted, 0, 8 * P.W, c->stream));
+  if (n_sweeps == 0) {
+    if (h_accepted)
+      for (int k = 0; k < c->cfg.n_instances; ++k) h_accepted[k] = 0;
+    return MVMC_OK;
+  }
+  // proposals per walker this call and the number of refresh-aligned rounds
+  int rounds = 1;
+  std::vector<uint64_t> target(c->cfg.n_instances);
+  for (int k = 0; k < c->cfg.n_instances; ++k) {
+    const uint64_t tot = (uint64_t)n_sweeps * P.inst[k].ne;
+    target[k] = c->cfg.n_instances ? tot : 0;
+    if (R > 0) {
+      const uint64_t ph = c->cnt_host[k] % (uint64_t)R;
+      uint64_t rem = tot, r = 0, first = (uint64_t)R - ph;
+      if (rem <= first) r = 1;
+      else r = 1 + (rem - first + R - 1) / R;
+      rounds = std::max<int>(rounds, (int)r);
+    }
+  }
+  const int64_t cap = R > 0 ? R : (int64_t)1 << 62;
+  uint64_t* tgt = reinterpret_cast<uint64_t*>(c->ws + P.target.off);
+  int32_t* nr = reinterpret_cast<int32_t*>(c->ws + P.needs_refresh.off);
+  {
+    // target[w] = cnt[w] + n_sweeps * N_e(instance of w), computed on the host mirror
+    std::vector<uint64_t> t(P.W);
+    for (int k = 0; k < c->cfg.n_instances; ++k) {
+      const InstDev& I = P.inst[k];
+      for (int w = 0; w < I.W; ++w) t[I.walker_off + w] = c->cnt_host[k] + target[k];
+    }
+    HIPCHK(c, hipMemcpy(tgt, t.data(), 8 * P.W, hipMemcpyHostToDevice));
+  }
+  const uint64_t* tb = reinterpret_cast<uint64_t*>(c->ws + P.trace_base.off);
+  for (int r = 0; r < rounds; ++r) {
+    const int id = tic(c, 0);
+    for (auto& b : c->sweep_b) {
+      const int32_t* lst = reinterpret_cast<int32_t*>(c->ws + P.lists.off + b.list_off);
+      if (c->cfg.precision == MVMC_FP64)
+        launch_sweep<double>(c->P, lst, b.n, (int)std::min<int64_t>(cap, INT32_MAX), c->cfg.seed,
+                             b.max_ne, b.max_ns, b.max_M, b.lds, b.nthreads, c->trace,
+                             c->trace_cap, tb, tgt, nr, R, c->stream);
+      else
+        launch_sweep<float>(c->P, lst, b.n, (int)std::min<int64_t>(cap, INT32_MAX), c->cfg.seed,
+                            b.max_ne, b.max_ns, b.max_M, b.lds, b.nthreads, c->trace,
+                            c->trace_cap, tb, tgt, nr, R, c->stream);
+    }
+    toc(c, id);
+    LAUNCHCHK(c);
+    if (R > 0) {
+      const int id2 = tic(c, 1);
+      for (auto& b : c->refresh_b) {
+        const int32_t* lst = reinterpret_cast<int32_t*>(c->ws + P.lists.off + b.list_off);
+        if (c->cfg.precision == MVMC_FP64)
+          launch_refresh_if<double>(c->P, lst, b.n, b.max_ne, b.max_ns, b.lds, nr, c->stream);
+        else
+          launch_refresh_if<float>(c->P, lst, b.n, b.max_ne, b.max_ns, b.lds, nr, c->stream);
+      }
+      toc(c, id2);
+      LAUNCHCHK(c);
+    }
+  }
+  for (int k = 0; k < c->cfg.n_instances; ++k) c->cnt_host[k] += target[k];
+  if (h_accepted) {
+    std::vector<int64_t> acc(P.W);
+    HIPCHK(c, hipMemcpyAsync(acc.data(), c->P.accepted, 8 * P.W, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < c->cfg.n_instances; ++k) {
+      const InstDev& I = P.inst[k];
+      int64_t s = 0;
+      for (int w = 0; w < I.W; ++w) s += acc[I.walker_off + w];
+      h_accepted[k] = s;
+    }
+  }
+  return MVMC_OK;
+}
+
+int mvmc_measure_energy_and_O(mvmc_ctx* c, int32_t slot, double* d_eloc, void* d_O) {
+  if (!c || !d_eloc || !d_O) return set_err(c, fail(MVMC_E_ARG, "NULL buffer"));
+  if (slot < 0 || slot >= c->cfg.n_slots)
+    return set_err(c, fail(MVMC_E_ARG, "slot %d outside [0, %d)", slot, c->cfg.n_slots));
+  const Plan& P = c->plan;
+  const int id = tic(c, 2);
+  if (c->cfg.precision == MVMC_FP64)
+    launch_measure<double>(c->P, c->d_all, (int)P.W, slot, d_eloc, (double*)d_O, P.max_ne,
+                           P.max_ns, P.max_M, c->stream);
+  else
+    launch_measure<float>(c->P, c->d_all, (int)P.W, slot, d_eloc, (float*)d_O, P.max_ne, P.max_ns,
+                          P.max_M, c->stream);
+  toc(c, id);
+  LAUNCHCHK(c);
+  return MVMC_OK;
+}
+
+int mvmc_build_sr(mvmc_ctx* c, int32_t n_used, const double* d_eloc, void* d_O, void* d_S,
+                  double* d_g, double* h_E, double* h_Evar) {
+  if (!c || !d_eloc || !d_O || !d_g) return set_err(c, fail(MVMC_E_ARG, "NULL buffer"));
+  if (n_used < 1 || n_used > c->cfg.n_slots)
+    return set_err(c, fail(MVMC_E_ARG, "n_slots_used %d outside [1, %d]", n_used, c->cfg.n_slots));
+  if (d_S && !c->cfg.build_s) return set_err(c, fail(MVMC_E_STATE, "context built with build_s = 0"));
+  const Plan& P = c->plan;
+  const int n = c->cfg.n_instances;
+  HIPCHK(c, hipStreamSynchronize(c->stream));   // staging buffer may still be in flight
+  int64_t max_rows = 0;
+  for (int k = 0; k < n; ++k) {
+    c->h_sr[k].rows = (int64_t)n_used * P.inst[k].W;
+    max_rows = std::max(max_rows, c->h_sr[k].rows);
+  }
+  HIPCHK(c, hipMemcpyAsync((void*)c->SA.inst, c->h_sr, sizeof(SrInst) * n, hipMemcpyHostToDevice,
+                           c->stream));
+  c->SA.eloc = d_eloc;
+  const bool mixed = c->cfg.precision == MVMC_MIXED;
+  uint16_t* split = (mixed && d_S) ? reinterpret_cast<uint16_t*>(c->ws + P.split.off) : nullptr;
+  int id = tic(c, 3);
+  sr_estats(c->SA, n, c->stream);
+  if (mixed)
+    sr_colstats<float>(c->SA, (float*)d_O, split, d_g, n, P.max_ld, max_rows, c->stream);
+  else
+    sr_colstats<double>(c->SA, (double*)d_O, nullptr, d_g, n, P.max_ld, max_rows, c->stream);
+  toc(c, id);
+  LAUNCHCHK(c);
+  if (d_S) {
+    id = tic(c, 4);
+    if (mixed)
+      sr_syrk_bf16x3(c->SA, split, (float*)d_S, n, P.max_np, P.max_ksplit, c->stream);
+    else
+      sr_syrk_vec<double, double>(c->SA, (const double*)d_O, (double*)d_S, n, P.max_np,
+                                  P.max_ksplit, c->stream);
+    toc(c, id);
+    LAUNCHCHK(c);
+  }
+  c->sr_ready = true;
+  if (h_E || h_Evar) {
+    std::vector<double> sc((size_t)kScal * n);
+    HIPCHK(c, hipMemcpyAsync(sc.data(), c->SA.scal, 8 * sc.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < n; ++k) {
+      if (h_E) h_E[k] = sc[k * kScal + kEbar];
+      if (h_Evar) h_Evar[k] = sc[k * kScal + kEvar];
+    }
+  }
+  return MVMC_OK;
+}
+
+int mvmc_sr_update(mvmc_ctx* c, const void* d_S, const void* d_O, const double* d_g, double dtau,
+                   double eps_rel, double eps_abs, int32_t solver, double cg_tol, int32_t cg_maxit,
+                   double* d_params, double* d_dparams, int32_t* h_cg_iters) {
+  if (!c || !d_g || !d_params) return set_err(c, fail(MVMC_E_ARG, "NULL buffer"));
+  if (!c->sr_ready) return set_err(c, fail(MVMC_E_STATE, "mvmc_build_sr must run first"));
+  if (!std::isfinite(dtau) || !std::isfinite(eps_rel) || !std::isfinite(eps_abs) || eps_rel < 0 ||
+      eps_abs < 0)
+    return set_err(c, fail(MVMC_E_ARG, "dtau/eps must be finite and eps >= 0"));
+  const Plan& P = c->plan;
+  const int n = c->cfg.n_instances;
+  const bool mixed = c->cfg.precision == MVMC_MIXED;
+  const double freeze = 1e-12;
+  std::vector<double> sc((size_t)kScal * n);
+  if (solver == MVMC_SOLVE_CHOL) {
+    if (!d_S || c->cfg.solver != MVMC_SOLVE_CHOL)
+      return set_err(c, fail(MVMC_E_STATE, "Cholesky needs d_S and a context built for it"));
+    for (int k = 0; k < n; ++k) {
+      HIPCHK(c, hipMemsetAsync(c->SA.scal + k * kScal + kFlag, 0, 8, c->stream));
+    }
+    const int id = tic(c, 5);
+    if (mixed)
+      sr_cholesky_solve<float>(c->SA, (const float*)d_S, d_g, eps_rel, eps_abs, freeze, n, P.max_np,
+                               c->stream);
+    else
+      sr_cholesky_solve<double>(c->SA, (const double*)d_S, d_g, eps_rel, eps_abs, freeze, n,
+                                P.max_np, c->stream);
+    toc(c, id);
+    LAUNCHCHK(c);
+    HIPCHK(c, hipMemcpyAsync(sc.data(), c->SA.scal, 8 * sc.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < n; ++k)
+      if (sc[k * kScal + kFlag] != 0.0)
+        return set_err(c, fail(MVMC_E_SINGULAR, "instance %d: S_reg not positive definite", k));
+    if (h_cg_iters)
+      for (int k = 0; k < n; ++k) h_cg_iters[k] = 0;
+  } else if (solver == MVMC_SOLVE_CG) {
+    if (!d_O) return set_err(c, fail(MVMC_E_ARG, "CG needs the centred O"));
+    if (cg_maxit < 1 || !(cg_tol > 0)) return set_err(c, fail(MVMC_E_ARG, "cg_maxit >= 1 and cg_tol > 0"));
+    const int id = tic(c, 5);
+    if (mixed)
+      sr_cg_begin<float>(c->SA, d_g, eps_rel, eps_abs, freeze, cg_tol, n, P.max_np, c->stream);
+    else
+      sr_cg_begin<double>(c->SA, d_g, eps_rel, eps_abs, freeze, cg_tol, n, P.max_np, c->stream);
+    int64_t max_rows = 0;
+    for (int k = 0; k < n; ++k) max_rows = std::max(max_rows, c->h_sr[k].rows);
+    for (int it = 1; it <= cg_maxit; ++it) {
+      if (mixed)
+        sr_cg_iter<float>(c->SA, (const float*)d_O, it, n, P.max_np, max_rows, c->stream);
+      else
+        sr_cg_iter<double>(c->SA, (const double*)d_O, it, n, P.max_np, max_rows, c->stream);
+      if (it % 16 == 0 || it == cg_maxit) {
+        LAUNCHCHK(c);
+        HIPCHK(c, hipMemcpyAsync(sc.data(), c->SA.scal, 8 * sc.size(), hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        bool all = true;
+        for (int k = 0; k < n; ++k) all = all && sc[k * kScal + kDone] != 0.0;
+        if (all) break;
+      }
+    }
+    toc(c, id);
+    HIPCHK(c, hipMemcpyAsync(sc.data(), c->SA.scal, 8 * sc.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (h_cg_iters)
+      for (int k = 0; k < n; ++k) h_cg_iters[k] = (int32_t)sc[k * kScal + kIters];
+  } else {
+    return set_err(c, fail(MVMC_E_ARG, "unknown solver %d", solver));
+  }
+  sr_apply(c->SA, dtau, d_params, d_dparams, n, P.max_np, c->stream);
+  LAUNCHCHK(c);
+  launch_expand(c->P, P.inst.data(), n, d_params, c->stream);
+  LAUNCHCHK(c);
+  int rc = refresh_any(c, 0.0);
+  if (rc) return rc;
+  std::vector<int32_t> st;
+  const int bad = first_singular(c, st);
+  if (bad == -2) return set_err(c, fail(MVMC_E_HIP, "status read failed"));
+  if (bad >= 0) return set_err(c, fail(MVMC_E_SINGULAR, "walker %d: X singular after update", bad));
+  return MVMC_OK;
+}
+
+int mvmc_get_state(mvmc_ctx* c, int32_t* d_pos, uint64_t* d_counter) {
+  if (!c) return MVMC_E_ARG;
+  const Plan& P = c->plan;
+  if (d_pos)
+    HIPCHK(c, hipMemcpyAsync(d_pos, c->P.pos, P.pos.bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (d_counter)
+    HIPCHK(c, hipMemcpyAsync(d_counter, c->P.cnt, 8 * P.W, hipMemcpyDeviceToDevice, c->stream));
+  return MVMC_OK;
+}
+
+int mvmc_set_state(mvmc_ctx* c, const int32_t* d_pos, const uint64_t* d_counter) {
+  if (!c || !d_pos || !d_counter) return set_err(c, fail(MVMC_E_ARG, "NULL buffer"));
+  const Plan& P = c->plan;
+  // validate on the host before touching the walker state
+  std::vector<int32_t> pos(P.pos.bytes / 4);
+  std::vector<uint64_t> cnt(P.W);
+  HIPCHK(c, hipMemcpyAsync(pos.data(), d_pos, P.pos.bytes, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(cnt.data(), d_counter, 8 * P.W, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < c->cfg.n_instances; ++k) {
+    const InstDev& I = P.inst[k];
+    for (int w = 0; w < I.W; ++w) {
+      if (cnt[I.walker_off + w] != cnt[I.walker_off])
+        return set_err(c, fail(MVMC_E_ARG, "instance %d: counters must be equal", k));
+      std::vector<char> occ(2 * I.ns, 0);
+      const int32_t* p = pos.data() + I.pos_off + (int64_t)w * I.ne;
+      for (int a = 0; a < I.ne; ++a) {
+        const int lo = a < I.nup ? 0 : I.ns, hi = lo + I.ns;
+        if (p[a] < lo || p[a] >= hi || occ[p[a]])
+          return set_err(c, fail(MVMC_E_ARG, "instance %d walker %d: bad configuration", k, w));
+        occ[p[a]] = 1;
+      }
+    }
+  }
+  HIPCHK(c, hipMemcpyAsync(c->P.pos, d_pos, P.pos.bytes, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->P.cnt, d_counter, 8 * P.W, hipMemcpyDeviceToDevice, c->stream));
+  launch_build_empty(c->P, c->d_all, (int)P.W, P.max_ns, c->stream);
+  LAUNCHCHK(c);
+  for (int k = 0; k < c->cfg.n_instances; ++k) c->cnt_host[k] = cnt[P.inst[k].walker_off];
+  int rc = refresh_any(c, 0.0);
+  if (rc) return rc;
+  std::vector<int32_t> st;
+  const int bad = first_singular(c, st);
+  if (bad >= 0) return set_err(c, fail(MVMC_E_SINGULAR, "walker %d: X singular", bad));
+  return MVMC_OK;
+}
+
+int mvmc_get_inverse(mvmc_ctx* c, double* d_Y) {
+  if (!c || !d_Y) return MVMC_E_ARG;
+  const Plan& P = c->plan;
+  if (c->cfg.precision == MVMC_FP64) {
+    HIPCHK(c, hipMemcpyAsync(d_Y, c->P.Y, 8 * P.Y_elems, hipMemcpyDeviceToDevice, c->stream));
+  } else {
+    launch_widen(reinterpret_cast<const float*>(c->P.Y), d_Y, P.Y_elems, c->stream);
+    LAUNCHCHK(c);
+  }
+  return MVMC_OK;
+}
+
+int mvmc_get_pfaffian(mvmc_ctx* c, double* d_logabs, double* d_sign) {
+  if (!c) return MVMC_E_ARG;
+  if (d_logabs)
+    HIPCHK(c, hipMemcpyAsync(d_logabs, c->P.logpf, 8 * c->plan.W, hipMemcpyDeviceToDevice, c->stream));
+  if (d_sign)
+    HIPCHK(c, hipMemcpyAsync(d_sign, c->P.sgnpf, 8 * c->plan.W, hipMemcpyDeviceToDevice, c->stream));
+  return MVMC_OK;
+}
+
+int mvmc_trace_enable(mvmc_ctx* c, void* d_trace, int64_t cap) {
+  if (!c || cap < 0) return MVMC_E_ARG;
+  if (!d_trace || cap == 0) {
+    c->trace = nullptr;
+    c->trace_cap = 0;
+    return MVMC_OK;
+  }
+  HIPCHK(c, hipMemcpyAsync(c->ws + c->plan.trace_base.off, c->P.cnt, 8 * c->plan.W,
+                           hipMemcpyDeviceToDevice, c->stream));
+  c->trace = reinterpret_cast<TraceRec*>(d_trace);
+  c->trace_cap = cap;
+  return MVMC_OK;
+}
+
+int mvmc_timing(mvmc_ctx* c, int32_t enable, double* h_ms, int64_t* h_calls) {
+  if (!c) return MVMC_E_ARG;
+  harvest(c);
+  if (h_ms)
+    for (int i = 0; i < kTimingCats; ++i) h_ms[i] = c->t_ms[i];
+  if (h_calls)
+    for (int i = 0; i < kTimingCats; ++i) h_calls[i] = c->t_calls[i];
+  if (enable && !c->timing)
+    for (int i = 0; i < kTimingCats; ++i) {
+      c->t_ms[i] = 0.0;
+      c->t_calls[i] = 0;
+    }
+  c->timing = enable != 0;
+  return MVMC_OK;
+}
+
+}  // extern "C"

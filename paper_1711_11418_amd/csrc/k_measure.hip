@@ -1,0 +1,173 @@
+// Local energy and log-derivatives for one sample slot, one workgroup per walker.
+//
+// E_loc(x) = sum_x' <x|H|x'> psi(x')/psi(x)  (section 3.1.1, Eq. MC) for
+// H = H_T + H_U (section 2.3): the diagonal sum_i U_i n_iup n_idn plus, for
+// every electron a and every neighbour j of its site with (j, sigma_a) empty,
+// -t * R(a -> j), R read from the current inverse exactly as in the sweep
+// (the moved electron keeps its row, which carries the fermion sign).
+//
+// O_k = d ln<x|psi>/d alpha_k (section 3.3.1):
+//   f slot k : -sum over members (i, j) of Y[a(i,up)][b(j,dn)]  (Eq. DiffPf,
+//              appendix C: dPf/dF_AB = -Pf (X^-1)_AB)
+//   g slot k : sum over member sites of n_iup n_idn
+//   v slot k : sum over member pairs i < j of (n_i - 1)(n_j - 1)
+//   RBM      : sigma_v, tanh theta_h, tanh theta_h sigma_v
+// Rows are written in the parameter-vector order; padding columns are zeroed.
+#include "launch.h"
+
+namespace mvmc {
+
+namespace {
+constexpr int kMeasureThreads = 256;
+template <typename T> __device__ __forceinline__ const T* table_of(const Pools& P, int64_t off);
+template <> __device__ __forceinline__ const double* table_of<double>(const Pools& P, int64_t off) {
+  return P.A64 + off;
+}
+template <> __device__ __forceinline__ const float* table_of<float>(const Pools& P, int64_t off) {
+  return P.A32 + off;
+}
+}  // namespace
+
+template <typename T>
+__global__ __launch_bounds__(kMeasureThreads) void k_measure(Pools P,
+                                                             const int32_t* __restrict__ wlist,
+                                                             int slot, double* __restrict__ eloc,
+                                                             T* __restrict__ O) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int gw = wlist[blockIdx.x];
+  const InstDev& I = P.inst[P.walker_inst[gw]];
+  const int ne = I.ne, ns = I.ns, n2 = 2 * ns, M = I.M;
+  const int64_t lw = gw - I.walker_off;
+  const int tid = threadIdx.x;
+
+  double* red = (double*)smem;                  // 16
+  double* hs = red + 16;                        // ns
+  double* ths = hs + ns;                        // M
+  int32_t* pos_s = (int32_t*)(ths + M);         // ne
+  int32_t* eidx = pos_s + ne;                   // 2ns
+
+  const int32_t* posg = P.pos + I.pos_off + lw * ne;
+  for (int v = tid; v < n2; v += blockDim.x) eidx[v] = -1;
+  for (int l = tid; l < ns; l += blockDim.x) hs[l] = P.h[I.h_off + lw * ns + l];
+  for (int hh = tid; hh < M; hh += blockDim.x) ths[hh] = P.theta[I.theta_off + lw * M + hh];
+  __syncthreads();
+  for (int b = tid; b < ne; b += blockDim.x) {
+    pos_s[b] = posg[b];
+    eidx[posg[b]] = b;
+  }
+  __syncthreads();
+
+  const T* Y = (const T*)P.Y + I.Y_off + lw * ne * ne;
+  const T* A = table_of<T>(P, I.A_off);
+  const double* V = P.V + I.V_off;
+  const double* G = P.G + I.site_off;
+  const double* Uv = P.U + I.site_off;
+  const int32_t* nptr = P.nbr_ptr + I.nptr_off;
+  const int32_t* nsite = P.nbr_site + I.nbr_off;
+  const double* nt = P.nbr_t + I.nbr_off;
+  const double* ra = P.rbm64 + I.rbm_a_off;
+  const double* rW = P.rbm64 + I.rbm_W_off;
+
+  double e = 0.0;
+  for (int i = tid; i < ns; i += blockDim.x)
+    if (eidx[i] >= 0 && eidx[i + ns] >= 0) e += Uv[i];
+  const int deg = I.deg_max;
+  for (int t = tid; t < ne * deg; t += blockDim.x) {
+    const int a = t / deg, qn = t % deg;
+    const int Iold = pos_s[a];
+    const int sigma = Iold >= ns ? 1 : 0;
+    const int site_old = Iold - sigma * ns;
+    const int s0 = nptr[site_old] + qn;
+    if (s0 >= nptr[site_old + 1]) continue;
+    const int site_new = nsite[s0];
+    const int Inew = site_new + sigma * ns;
+    if (eidx[Inew] >= 0) continue;
+    const T* Arow = A + (int64_t)Inew * n2;
+    const T* Ya = Y + a * ne;
+    double s = 0.0;
+    for (int b = 0; b < ne; ++b)
+      if (b != a) s += (double)Arow[pos_s[b]] * (double)Ya[b];
+    const double r_pf = -s;
+    const int opp = (1 - sigma) * ns;
+    double logc = G[site_new] * (eidx[site_new + opp] >= 0 ? 1.0 : 0.0) -
+                  G[site_old] * (eidx[site_old + opp] >= 0 ? 1.0 : 0.0) + hs[site_new] -
+                  hs[site_old] - V[(int64_t)site_old * ns + site_new];
+    if (M) {
+      logc += 2.0 * (ra[Inew] - ra[Iold]);
+      for (int hh = 0; hh < M; ++hh) {
+        const double th = ths[hh];
+        const double d = 2.0 * (rW[(int64_t)hh * n2 + Inew] - rW[(int64_t)hh * n2 + Iold]);
+        logc += log2cosh(th + d) - log2cosh(th);
+      }
+    }
+    e += -nt[s0] * r_pf * exp(logc);
+  }
+  e = block_sum(e, red);
+  for (int hh = tid; hh < M; hh += blockDim.x) ths[hh] = tanh(ths[hh]);
+  __syncthreads();
+  const int64_t row = (int64_t)slot * I.W + lw;
+  if (tid == 0) eloc[I.eloc_off + row] = e;
+
+  T* Orow = O + I.O_off + row * I.ldO;
+  const int32_t* fptr = P.fm_ptr + I.fm_ptr_off;
+  const int32_t* fm = P.fm + I.fm_off;
+  for (int k = tid; k < I.nf; k += blockDim.x) {
+    double s = 0.0;
+    for (int m = fptr[k]; m < fptr[k + 1]; ++m) {
+      const int pk = fm[m];
+      const int ea = eidx[pk / ns], eb = eidx[pk % ns + ns];
+      if (ea >= 0 && eb >= 0) s -= (double)Y[ea * ne + eb];
+    }
+    Orow[k] = (T)s;
+  }
+  const int32_t* gptr = P.gm_ptr + I.gm_ptr_off;
+  const int32_t* gm = P.gm + I.gm_off;
+  for (int k = tid; k < I.ng; k += blockDim.x) {
+    double s = 0.0;
+    for (int m = gptr[k]; m < gptr[k + 1]; ++m) {
+      const int i = gm[m];
+      if (eidx[i] >= 0 && eidx[i + ns] >= 0) s += 1.0;
+    }
+    Orow[I.nf + k] = (T)s;
+  }
+  const int32_t* vptr = P.vm_ptr + I.vm_ptr_off;
+  const int32_t* vm = P.vm + I.vm_off;
+  for (int k = tid; k < I.nv; k += blockDim.x) {
+    double s = 0.0;
+    for (int m = vptr[k]; m < vptr[k + 1]; ++m) {
+      const int pk = vm[m];
+      const int i = pk / ns, j = pk % ns;
+      const int mi = (eidx[i] >= 0) + (eidx[i + ns] >= 0) - 1;
+      const int mj = (eidx[j] >= 0) + (eidx[j + ns] >= 0) - 1;
+      s += (double)(mi * mj);
+    }
+    Orow[I.nf + I.ng + k] = (T)s;
+  }
+  if (M) {
+    T* Oa = Orow + I.nf + I.ng + I.nv;
+    T* Ob = Oa + n2;
+    T* OW = Ob + M;
+    for (int v = tid; v < n2; v += blockDim.x) Oa[v] = (T)(eidx[v] >= 0 ? 1.0 : -1.0);
+    for (int hh = tid; hh < M; hh += blockDim.x) Ob[hh] = (T)ths[hh];
+    for (int64_t idx = tid; idx < (int64_t)M * n2; idx += blockDim.x) {
+      const int hh = (int)(idx / n2), v = (int)(idx % n2);
+      OW[idx] = (T)(eidx[v] >= 0 ? ths[hh] : -ths[hh]);
+    }
+  }
+  for (int k = I.np + tid; k < I.ldO; k += blockDim.x) Orow[k] = T(0);
+}
+
+template <typename T>
+void launch_measure(const Pools& P, const int32_t* wlist, int n, int slot, double* eloc, T* O,
+                    int max_ne, int max_ns, int max_M, hipStream_t s) {
+  if (n <= 0) return;
+  const size_t sh = (16 + max_ns + max_M) * sizeof(double) + (max_ne + 2 * max_ns) * sizeof(int32_t);
+  hipLaunchKernelGGL(k_measure<T>, dim3(n), dim3(kMeasureThreads), sh, s, P, wlist, slot, eloc, O);
+}
+
+template void launch_measure<double>(const Pools&, const int32_t*, int, int, double*, double*, int,
+                                     int, int, hipStream_t);
+template void launch_measure<float>(const Pools&, const int32_t*, int, int, double*, float*, int,
+                                    int, int, hipStream_t);
+
+}  // namespace mvmc

@@ -1,0 +1,618 @@
+// Stochastic reconfiguration on the GPU (section 3.3.1, Eq. SR_equation_system;
+// section 3.3.2, Algorithm 1).
+//
+//   E_bar = (1/N) sum E_mu,  o_k = (1/N) sum O_mu,k,  O~ = O - o   (centred in place)
+//   S = (1/N) O~^T O~,       g = (1/N) O~^T (E - E_bar)
+//   S_reg = S + diag(eps_rel S_kk + eps_abs); parameters with S_kk < freeze
+//   are frozen (row/column of S_reg replaced by the identity, g_k = 0)
+//   Delta alpha = -dtau S_reg^-1 g   by blocked Cholesky or by CG with the
+//   matrix-free product S_reg v = (1/N) O~^T (O~ v) + shift v.
+//
+// All reductions run in a fixed order (row chunks summed by a second pass),
+// so results are bitwise reproducible.  Every kernel is batched over
+// instances (the last grid dimension) so ragged batches share launches.
+#include <float.h>
+
+#include "sr.h"
+
+namespace mvmc {
+
+// ------------------------------------------------------------ statistics
+__global__ void k_estats(SrArgs A) {
+  const SrInst& I = A.inst[blockIdx.x];
+  __shared__ double red[16];
+  const double* e = A.eloc + I.eloc_off;
+  const int64_t N = I.rows;
+  double s = 0.0;
+  for (int64_t m = threadIdx.x; m < N; m += blockDim.x) s += e[m];
+  s = block_sum(s, red);
+  const double mean = s / (double)N;
+  double v = 0.0;
+  for (int64_t m = threadIdx.x; m < N; m += blockDim.x) {
+    const double d = e[m] - mean;
+    v += d * d;
+  }
+  v = block_sum(v, red);
+  if (threadIdx.x == 0) {
+    A.scal[blockIdx.x * kScal + kEbar] = mean;
+    A.scal[blockIdx.x * kScal + kEvar] = v / (double)N;
+  }
+}
+
+// mode 0: partial column sums of O.  mode 1: centre O in place and form
+// partial sums of O~^2 and O~ (E - E_bar); optionally write the bf16 split.
+template <typename T>
+__global__ void k_colpass(SrArgs A, T* __restrict__ O, int mode, uint16_t* __restrict__ split) {
+  const SrInst& I = A.inst[blockIdx.z];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.y * kRowChunk;
+  if (r0 >= I.rows) return;
+  const int64_t r1 = r0 + kRowChunk < I.rows ? r0 + kRowChunk : I.rows;
+  if (k >= I.ldO) return;
+  T* Ob = O + I.O_off;
+  double* part = A.colpart + I.colpart_off;
+  const int64_t ld = I.ldO;
+  if (mode == 0) {
+    double s = 0.0;
+    for (int64_t m = r0; m < r1; ++m) s += (double)Ob[m * ld + k];
+    part[(blockIdx.y * 3 + 0) * ld + k] = s;
+  } else {
+    const double ob = A.obar[I.param_off + k];
+    const double eb = A.scal[blockIdx.z * kScal + kEbar];
+    const double* e = A.eloc + I.eloc_off;
+    uint16_t* hi = split ? split + I.split_off : nullptr;
+    uint16_t* lo = split ? split + I.split_off + I.rows * ld : nullptr;
+    double s2 = 0.0, sg = 0.0;
+    for (int64_t m = r0; m < r1; ++m) {
+      const T c = (T)((double)Ob[m * ld + k] - ob);
+      Ob[m * ld + k] = c;
+      const double cd = (double)c;
+      s2 += cd * cd;
+      sg += cd * (e[m] - eb);
+      if (hi) {
+        const uint16_t h = f32_to_bf16((float)c);
+        hi[m * ld + k] = h;
+        lo[m * ld + k] = f32_to_bf16((float)c - bf16_to_f32(h));
+      }
+    }
+    part[(blockIdx.y * 3 + 1) * ld + k] = s2;
+    part[(blockIdx.y * 3 + 2) * ld + k] = sg;
+  }
+}
+
+// Fixed-order sum of the row-chunk partials.
+__global__ void k_colfinish(SrArgs A, int mode, double* __restrict__ g) {
+  const SrInst& I = A.inst[blockIdx.y];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= I.ldO) return;
+  const double* part = A.colpart + I.colpart_off;
+  const int64_t ld = I.ldO;
+  const int nch = (int)ceil_div<int64_t>(I.rows, kRowChunk);
+  const double invN = 1.0 / (double)I.rows;
+  if (mode == 0) {
+    double s = 0.0;
+    for (int c = 0; c < nch; ++c) s += part[(c * 3 + 0) * ld + k];
+    if (k < I.np) A.obar[I.param_off + k] = s * invN;
+  } else {
+    double s2 = 0.0, sg = 0.0;
+    for (int c = 0; c < nch; ++c) {
+      s2 += part[(c * 3 + 1) * ld + k];
+      sg += part[(c * 3 + 2) * ld + k];
+    }
+    if (k < I.np) {
+      A.sdiag[I.param_off + k] = s2 * invN;
+      g[I.param_off + k] = sg * invN;
+    }
+  }
+}
+
+// ------------------------------------------------------ FP64 SYRK (vector)
+// 64x64 upper-triangle tiles of S = O~^T O~ / N, split over row chunks.
+constexpr int kTile = 64, kKc = 32;
+
+__device__ __forceinline__ void tile_of(int t, int nt, int& ti, int& tj) {
+  int row = 0, start = 0;
+  while (t >= start + (nt - row)) {
+    start += nt - row;
+    ++row;
+  }
+  ti = row;
+  tj = row + (t - start);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_syrk_vec(SrArgs A, const T* __restrict__ O) {
+  const SrInst& I = A.inst[blockIdx.z];
+  const int nt = (int)ceil_div<int64_t>(I.np, kTile);
+  const int ntiles = nt * (nt + 1) / 2;
+  if ((int)blockIdx.x >= ntiles || (int)blockIdx.y >= I.ksplit) return;
+  int ti, tj;
+  tile_of(blockIdx.x, nt, ti, tj);
+  const int64_t chunk = ceil_div<int64_t>(ceil_div<int64_t>(I.rows, I.ksplit), kKc) * kKc;
+  const int64_t r0 = (int64_t)blockIdx.y * chunk;
+  const int64_t r1 = r0 + chunk < I.rows ? r0 + chunk : I.rows;
+  __shared__ double As[kKc][kTile + 1];
+  __shared__ double Bs[kKc][kTile + 1];
+  const T* Ob = O + I.O_off;
+  const int64_t ld = I.ldO;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double acc[4][4] = {};
+  const int c_a = ti * kTile, c_b = tj * kTile;
+  for (int64_t m0 = r0; m0 < r1; m0 += kKc) {
+    for (int e = threadIdx.x; e < kKc * kTile; e += 256) {
+      const int kk = e / kTile, c = e % kTile;
+      const int64_t m = m0 + kk;
+      const bool okm = m < r1;
+      As[kk][c] = (okm && c_a + c < I.np) ? (double)Ob[m * ld + c_a + c] : 0.0;
+      Bs[kk][c] = (okm && c_b + c < I.np) ? (double)Ob[m * ld + c_b + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < kKc; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+    }
+    __syncthreads();
+  }
+  double* part = A.syrkpart + I.syrkpart_off + ((int64_t)blockIdx.y * ntiles + blockIdx.x) * kTile * kTile;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) part[(ty * 4 + i) * kTile + tx * 4 + j] = acc[i][j];
+}
+
+// Sum the split-K partials in order, scale by 1/N, write both triangles.
+template <typename TS>
+__global__ void k_syrk_reduce(SrArgs A, TS* __restrict__ S) {
+  const SrInst& I = A.inst[blockIdx.y];
+  const int nt = (int)ceil_div<int64_t>(I.np, kTile);
+  const int ntiles = nt * (nt + 1) / 2;
+  if ((int)blockIdx.x >= ntiles) return;
+  int ti, tj;
+  tile_of(blockIdx.x, nt, ti, tj);
+  const double* part = A.syrkpart + I.syrkpart_off;
+  const double invN = 1.0 / (double)I.rows;
+  TS* Sb = S + I.S_off;
+  for (int e = threadIdx.x; e < kTile * kTile; e += blockDim.x) {
+    const int i = e / kTile, j = e % kTile;
+    const int64_t r = (int64_t)ti * kTile + i, c = (int64_t)tj * kTile + j;
+    if (r >= I.np || c >= I.np) continue;
+    double s = 0.0;
+    for (int ks = 0; ks < I.ksplit; ++ks) s += part[((int64_t)ks * ntiles + blockIdx.x) * kTile * kTile + e];
+    s *= invN;
+    Sb[r * I.np + c] = (TS)s;
+    Sb[c * I.np + r] = (TS)s;
+  }
+}
+
+// ------------------------------------------------------------ SR solve
+// Regularised matrix into the FP64 factor pool (lower triangle and diagonal)
+// and the masked right-hand side into x.
+template <typename TS>
+__global__ void k_chol_prep(SrArgs A, const TS* __restrict__ S, const double* __restrict__ g,
+                            double eps_rel, double eps_abs, double freeze) {
+  const SrInst& I = A.inst[blockIdx.y];
+  const int64_t r = blockIdx.x;
+  if (r >= I.np) return;
+  const double* d = A.sdiag + I.param_off;
+  const bool kr = d[r] >= freeze;
+  double* F = A.chol + I.chol_off + r * I.np;
+  const TS* Sr = S + I.S_off + r * I.np;
+  for (int64_t c = threadIdx.x; c <= r; c += blockDim.x) {
+    const bool kc = d[c] >= freeze;
+    double v = (kr && kc) ? (double)Sr[c] : 0.0;
+    if (c == r) v += kr ? eps_rel * d[r] + eps_abs : 1.0;
+    F[c] = v;
+  }
+  if (threadIdx.x == 0) A.x[I.param_off + r] = kr ? g[I.param_off + r] : 0.0;
+}
+
+constexpr int kNb = 64;
+
+__global__ __launch_bounds__(256) void k_potrf_diag(SrArgs A, int kb) {
+  const SrInst& I = A.inst[blockIdx.x];
+  const int nblk = (int)ceil_div<int64_t>(I.np, kNb);
+  if (kb >= nblk) return;
+  const int64_t o = (int64_t)kb * kNb;
+  const int nb = (int)(I.np - o < kNb ? I.np - o : kNb);
+  __shared__ double L[kNb][kNb + 1];
+  double* F = A.chol + I.chol_off;
+  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+    const int i = e / nb, j = e % nb;
+    L[i][j] = j <= i ? F[(o + i) * I.np + o + j] : 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    if (threadIdx.x == 0) {
+      const double dj = L[j][j];
+      if (!(dj > 0.0)) A.scal[blockIdx.x * kScal + kFlag] = 1.0;
+      L[j][j] = sqrt(dj > 0.0 ? dj : DBL_MIN);
+    }
+    __syncthreads();
+    const double ljj = L[j][j];
+    for (int i = j + 1 + threadIdx.x; i < nb; i += blockDim.x) L[i][j] /= ljj;
+    __syncthreads();
+    const int rem = nb - j - 1;
+    for (int e = threadIdx.x; e < rem * rem; e += blockDim.x) {
+      const int i = j + 1 + e / rem, k = j + 1 + e % rem;
+      if (k <= i) L[i][k] -= L[i][j] * L[k][j];
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+    const int i = e / nb, j = e % nb;
+    if (j <= i) F[(o + i) * I.np + o + j] = L[i][j];
+  }
+}
+
+// Panel below the diagonal block: rows r solve  L[r][blk] L_kk^T = F[r][blk].
+__global__ __launch_bounds__(64) void k_trsm_panel(SrArgs A, int kb) {
+  const SrInst& I = A.inst[blockIdx.y];
+  const int nblk = (int)ceil_div<int64_t>(I.np, kNb);
+  const int ib = kb + 1 + blockIdx.x;
+  if (kb >= nblk || ib >= nblk) return;
+  const int64_t o = (int64_t)kb * kNb, ro = (int64_t)ib * kNb;
+  const int nb = (int)(I.np - o < kNb ? I.np - o : kNb);
+  const int nr = (int)(I.np - ro < kNb ? I.np - ro : kNb);
+  __shared__ double L[kNb][kNb + 1];
+  __shared__ double Pn[kNb][kNb + 1];
+  double* F = A.chol + I.chol_off;
+  for (int e = threadIdx.x; e < kNb * kNb; e += blockDim.x) {
+    const int i = e / kNb, j = e % kNb;
+    L[i][j] = (i < nb && j <= i) ? F[(o + i) * I.np + o + j] : 0.0;
+    Pn[i][j] = (i < nr && j < nb) ? F[(ro + i) * I.np + o + j] : 0.0;
+  }
+  __syncthreads();
+  const int r = threadIdx.x;
+  if (r < nr) {
+    for (int j = 0; j < nb; ++j) {
+      double s = Pn[r][j];
+      for (int m = 0; m < j; ++m) s -= Pn[r][m] * L[j][m];
+      Pn[r][j] = s / L[j][j];
+    }
+    for (int j = 0; j < nb; ++j) F[(ro + r) * I.np + o + j] = Pn[r][j];
+  }
+}
+
+// Trailing update of the lower triangle: F[ib][jb] -= L[ib][kb] L[jb][kb]^T.
+__global__ __launch_bounds__(256) void k_chol_update(SrArgs A, int kb) {
+  const SrInst& I = A.inst[blockIdx.y];
+  const int nblk = (int)ceil_div<int64_t>(I.np, kNb);
+  const int R = nblk - kb - 1;
+  if (R <= 0 || (int)blockIdx.x >= R * (R + 1) / 2) return;
+  // linear index -> (ib', jb') with ib' >= jb'
+  int ibp = 0, start = 0;
+  while ((int)blockIdx.x >= start + ibp + 1) {
+    start += ibp + 1;
+    ++ibp;
+  }
+  const int jbp = blockIdx.x - start;
+  const int ib = kb + 1 + ibp, jb = kb + 1 + jbp;
+  const int64_t o = (int64_t)kb * kNb, ro = (int64_t)ib * kNb, co = (int64_t)jb * kNb;
+  const int nk = (int)(I.np - o < kNb ? I.np - o : kNb);
+  const int nr = (int)(I.np - ro < kNb ? I.np - ro : kNb);
+  const int nc = (int)(I.np - co < kNb ? I.np - co : kNb);
+  __shared__ double Ls[kNb][kNb + 1];
+  __shared__ double Ms[kNb][kNb + 1];
+  double* F = A.chol + I.chol_off;
+  for (int e = threadIdx.x; e < kNb * kNb; e += blockDim.x) {
+    const int i = e / kNb, k = e % kNb;
+    Ls[i][k] = (i < nr && k < nk) ? F[(ro + i) * I.np + o + k] : 0.0;
+    Ms[i][k] = (i < nc && k < nk) ? F[(co + i) * I.np + o + k] : 0.0;
+  }
+  __syncthreads();
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double acc[4][4] = {};
+  for (int k = 0; k < nk; ++k) {
+    double a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = Ls[ty * 4 + i][k];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[j] = Ms[tx * 4 + j][k];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = ty * 4 + i, c = tx * 4 + j;
+      if (r < nr && c < nc && (ib != jb || c <= r)) F[(ro + r) * I.np + co + c] -= acc[i][j];
+    }
+}
+
+// Forward substitution L y = b on diagonal block kb (in place in x).
+__global__ __launch_bounds__(64) void k_trsv_diag(SrArgs A, int kb, int transpose) {
+  const SrInst& I = A.inst[blockIdx.x];
+  const int nblk = (int)ceil_div<int64_t>(I.np, kNb);
+  if (kb >= nblk) return;
+  const int64_t o = (int64_t)kb * kNb;
+  const int nb = (int)(I.np - o < kNb ? I.np - o : kNb);
+  __shared__ double L[kNb][kNb + 1];
+  __shared__ double y[kNb];
+  const double* F = A.chol + I.chol_off;
+  double* x = A.x + I.param_off + o;
+  for (int e = threadIdx.x; e < kNb * kNb; e += blockDim.x) {
+    const int i = e / kNb, j = e % kNb;
+    L[i][j] = (i < nb && j <= i) ? F[(o + i) * I.np + o + j] : 0.0;
+  }
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) y[i] = x[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (!transpose) {
+      for (int i = 0; i < nb; ++i) {
+        double s = y[i];
+        for (int m = 0; m < i; ++m) s -= L[i][m] * y[m];
+        y[i] = s / L[i][i];
+      }
+    } else {
+      for (int i = nb - 1; i >= 0; --i) {
+        double s = y[i];
+        for (int m = i + 1; m < nb; ++m) s -= L[m][i] * y[m];
+        y[i] = s / L[i][i];
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) x[i] = y[i];
+}
+
+// Off-diagonal updates of the right-hand side after block kb is solved.
+// forward:  x[r] -= sum_{c in kb} L[r][c] x[c]   for r in later blocks
+// backward: x[c] -= sum_{r in kb} L[r][c] x[r]   for c in earlier blocks
+__global__ __launch_bounds__(64) void k_trsv_update(SrArgs A, int kb, int transpose) {
+  const SrInst& I = A.inst[blockIdx.y];
+  const int nblk = (int)ceil_div<int64_t>(I.np, kNb);
+  if (kb >= nblk) return;
+  const int ob = transpose ? (int)blockIdx.x : kb + 1 + (int)blockIdx.x;
+  if (transpose ? ob >= kb : ob >= nblk) return;
+  const int64_t o = (int64_t)kb * kNb, bo = (int64_t)ob * kNb;
+  const int nb = (int)(I.np - o < kNb ? I.np - o : kNb);
+  const int nr = (int)(I.np - bo < kNb ? I.np - bo : kNb);
+  const double* F = A.chol + I.chol_off;
+  double* x = A.x + I.param_off;
+  __shared__ double xs[kNb];
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) xs[i] = x[o + i];
+  __syncthreads();
+  const int r = threadIdx.x;
+  if (r < nr) {
+    double s = 0.0;
+    if (!transpose)
+      for (int c = 0; c < nb; ++c) s += F[(bo + r) * I.np + o + c] * xs[c];
+    else
+      for (int c = 0; c < nb; ++c) s += F[(o + c) * I.np + bo + r] * xs[c];
+    x[bo + r] -= s;
+  }
+}
+
+// ------------------------------------------------------------------- CG
+// Algorithm 1 with A = S_reg applied matrix-free.
+__global__ void k_cg_init(SrArgs A, const double* __restrict__ g, double eps_rel, double eps_abs,
+                          double freeze) {
+  const SrInst& I = A.inst[blockIdx.y];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= I.np) return;
+  const int64_t o = I.param_off + k;
+  const double d = A.sdiag[o];
+  const bool keep = d >= freeze;
+  const double b = keep ? g[o] : 0.0;
+  A.x[o] = 0.0;
+  A.r[o] = b;
+  A.p[o] = b;
+  A.shift[o] = keep ? eps_rel * d + eps_abs : 1.0;
+  A.mask[o] = keep ? 1.0 : 0.0;
+}
+
+// out = a . b per instance (one block per instance, fixed order)
+__global__ void k_dot(SrArgs A, const double* __restrict__ a, const double* __restrict__ b,
+                      int slot, int check_done) {
+  const SrInst& I = A.inst[blockIdx.x];
+  if (check_done && A.scal[blockIdx.x * kScal + kDone] != 0.0) return;
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int64_t k = threadIdx.x; k < I.np; k += blockDim.x) s += a[I.param_off + k] * b[I.param_off + k];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) A.scal[blockIdx.x * kScal + slot] = s;
+}
+
+// t = O~ (mask o p): one wave per sample row.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemv_rows(SrArgs A, const T* __restrict__ O) {
+  const SrInst& I = A.inst[blockIdx.y];
+  if (A.scal[blockIdx.y * kScal + kDone] != 0.0) return;
+  const int64_t m = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (m >= I.rows) return;
+  const int lane = threadIdx.x & 63;
+  const T* row = O + I.O_off + m * I.ldO;
+  const double* p = A.p + I.param_off;
+  const double* mk = A.mask + I.param_off;
+  double s = 0.0;
+  for (int64_t k = lane; k < I.np; k += 64) s += (double)row[k] * (p[k] * mk[k]);
+  s = wave_sum(s);
+  if (lane == 0) A.t[I.eloc_off + m] = s;
+}
+
+// w = mask o (O~^T t) / N + shift o p: threads over columns.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemv_cols(SrArgs A, const T* __restrict__ O) {
+  const SrInst& I = A.inst[blockIdx.y];
+  if (A.scal[blockIdx.y * kScal + kDone] != 0.0) return;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= I.np) return;
+  const T* col = O + I.O_off + k;
+  const double* t = A.t + I.eloc_off;
+  double s = 0.0;
+  for (int64_t m = 0; m < I.rows; ++m) s += (double)col[m * I.ldO] * t[m];
+  const int64_t o = I.param_off + k;
+  A.w[o] = A.mask[o] * s / (double)I.rows + A.shift[o] * A.p[o];
+}
+
+// alpha = rho / (p . w);  x += alpha p;  r -= alpha w
+__global__ void k_cg_xr(SrArgs A) {
+  const SrInst& I = A.inst[blockIdx.y];
+  const double* sc = A.scal + blockIdx.y * kScal;
+  if (sc[kDone] != 0.0) return;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= I.np) return;
+  const double alpha = sc[kRho] / sc[kPw];
+  const int64_t o = I.param_off + k;
+  A.x[o] += alpha * A.p[o];
+  A.r[o] -= alpha * A.w[o];
+}
+
+// Convergence test (rho' < eps^2 |b|^2) and beta; one thread per instance.
+__global__ void k_cg_check(SrArgs A, int iter) {
+  double* sc = A.scal + blockIdx.x * kScal;
+  if (sc[kDone] != 0.0) return;
+  const double rn = sc[kRhoNew];
+  sc[kIters] = (double)iter;
+  if (rn < sc[kThresh]) {
+    sc[kDone] = 1.0;
+    return;
+  }
+  sc[kBeta] = rn / sc[kRho];
+  sc[kRho] = rn;
+}
+
+__global__ void k_cg_p(SrArgs A) {
+  const SrInst& I = A.inst[blockIdx.y];
+  const double* sc = A.scal + blockIdx.y * kScal;
+  if (sc[kDone] != 0.0) return;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= I.np) return;
+  const int64_t o = I.param_off + k;
+  A.p[o] = A.r[o] + sc[kBeta] * A.p[o];
+}
+
+__global__ void k_cg_setup(SrArgs A, double eps) {
+  double* sc = A.scal + blockIdx.x * kScal;
+  // rho = |r|^2 = |b|^2 is in kRho (k_dot into kRho)
+  sc[kThresh] = eps * eps * sc[kRho];
+  sc[kDone] = 0.0;
+  sc[kIters] = 0.0;
+}
+
+// alpha <- alpha - dtau x   (frozen parameters have x = 0)
+__global__ void k_apply_update(SrArgs A, double dtau, double* __restrict__ params,
+                               double* __restrict__ dparams) {
+  const SrInst& I = A.inst[blockIdx.y];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= I.np) return;
+  const int64_t o = I.param_off + k;
+  const double d = -dtau * A.x[o];
+  if (dparams) dparams[o] = d;
+  params[o] += d;
+}
+
+// --------------------------------------------------------------- launchers
+void sr_estats(const SrArgs& A, int n_inst, hipStream_t s) {
+  hipLaunchKernelGGL(k_estats, dim3(n_inst), dim3(256), 0, s, A);
+}
+
+template <typename T>
+void sr_colstats(const SrArgs& A, T* O, uint16_t* split, double* g, int n_inst, int64_t max_ld,
+                 int64_t max_rows, hipStream_t s) {
+  const int cb = (int)ceil_div<int64_t>(max_ld, 256);
+  const int ch = (int)ceil_div<int64_t>(max_rows, kRowChunk);
+  hipLaunchKernelGGL(k_colpass<T>, dim3(cb, ch, n_inst), dim3(256), 0, s, A, O, 0, split);
+  hipLaunchKernelGGL(k_colfinish, dim3(cb, n_inst), dim3(256), 0, s, A, 0, g);
+  hipLaunchKernelGGL(k_colpass<T>, dim3(cb, ch, n_inst), dim3(256), 0, s, A, O, 1, split);
+  hipLaunchKernelGGL(k_colfinish, dim3(cb, n_inst), dim3(256), 0, s, A, 1, g);
+}
+
+template <typename T, typename TS>
+void sr_syrk_vec(const SrArgs& A, const T* O, TS* S, int n_inst, int64_t max_np, int max_ksplit,
+                 hipStream_t s) {
+  const int nt = (int)ceil_div<int64_t>(max_np, kTile);
+  const int ntiles = nt * (nt + 1) / 2;
+  hipLaunchKernelGGL(k_syrk_vec<T>, dim3(ntiles, max_ksplit, n_inst), dim3(256), 0, s, A, O);
+  hipLaunchKernelGGL(k_syrk_reduce<TS>, dim3(ntiles, n_inst), dim3(256), 0, s, A, S);
+}
+
+template <typename TS>
+void sr_cholesky_solve(const SrArgs& A, const TS* S, const double* g, double eps_rel, double eps_abs,
+                       double freeze, int n_inst, int64_t max_np, hipStream_t s) {
+  hipLaunchKernelGGL(k_chol_prep<TS>, dim3(max_np, n_inst), dim3(256), 0, s, A, S, g, eps_rel,
+                     eps_abs, freeze);
+  const int nblk = (int)ceil_div<int64_t>(max_np, kNb);
+  for (int kb = 0; kb < nblk; ++kb) {
+    hipLaunchKernelGGL(k_potrf_diag, dim3(n_inst), dim3(256), 0, s, A, kb);
+    const int R = nblk - kb - 1;
+    if (R > 0) {
+      hipLaunchKernelGGL(k_trsm_panel, dim3(R, n_inst), dim3(64), 0, s, A, kb);
+      hipLaunchKernelGGL(k_chol_update, dim3(R * (R + 1) / 2, n_inst), dim3(256), 0, s, A, kb);
+    }
+  }
+  for (int kb = 0; kb < nblk; ++kb) {
+    hipLaunchKernelGGL(k_trsv_diag, dim3(n_inst), dim3(64), 0, s, A, kb, 0);
+    if (nblk - kb - 1 > 0)
+      hipLaunchKernelGGL(k_trsv_update, dim3(nblk - kb - 1, n_inst), dim3(64), 0, s, A, kb, 0);
+  }
+  for (int kb = nblk - 1; kb >= 0; --kb) {
+    hipLaunchKernelGGL(k_trsv_diag, dim3(n_inst), dim3(64), 0, s, A, kb, 1);
+    if (kb > 0) hipLaunchKernelGGL(k_trsv_update, dim3(kb, n_inst), dim3(64), 0, s, A, kb, 1);
+  }
+}
+
+template <typename T>
+void sr_cg_begin(const SrArgs& A, const double* g, double eps_rel, double eps_abs, double freeze,
+                 double eps, int n_inst, int64_t max_np, hipStream_t s) {
+  const int cb = (int)ceil_div<int64_t>(max_np, 256);
+  hipLaunchKernelGGL(k_cg_init, dim3(cb, n_inst), dim3(256), 0, s, A, g, eps_rel, eps_abs, freeze);
+  hipLaunchKernelGGL(k_dot, dim3(n_inst), dim3(256), 0, s, A, (const double*)A.r, (const double*)A.r,
+                     kRho, 0);
+  hipLaunchKernelGGL(k_cg_setup, dim3(n_inst), dim3(1), 0, s, A, eps);
+}
+
+template <typename T>
+void sr_cg_iter(const SrArgs& A, const T* O, int iter, int n_inst, int64_t max_np, int64_t max_rows,
+                hipStream_t s) {
+  const int cb = (int)ceil_div<int64_t>(max_np, 256);
+  hipLaunchKernelGGL(k_gemv_rows<T>, dim3((unsigned)ceil_div<int64_t>(max_rows, 4), n_inst),
+                     dim3(256), 0, s, A, O);
+  hipLaunchKernelGGL(k_gemv_cols<T>, dim3(cb, n_inst), dim3(256), 0, s, A, O);
+  hipLaunchKernelGGL(k_dot, dim3(n_inst), dim3(256), 0, s, A, (const double*)A.p, (const double*)A.w,
+                     kPw, 1);
+  hipLaunchKernelGGL(k_cg_xr, dim3(cb, n_inst), dim3(256), 0, s, A);
+  hipLaunchKernelGGL(k_dot, dim3(n_inst), dim3(256), 0, s, A, (const double*)A.r, (const double*)A.r,
+                     kRhoNew, 1);
+  hipLaunchKernelGGL(k_cg_check, dim3(n_inst), dim3(1), 0, s, A, iter);
+  hipLaunchKernelGGL(k_cg_p, dim3(cb, n_inst), dim3(256), 0, s, A);
+}
+
+void sr_apply(const SrArgs& A, double dtau, double* params, double* dparams, int n_inst,
+              int64_t max_np, hipStream_t s) {
+  const int cb = (int)ceil_div<int64_t>(max_np, 256);
+  hipLaunchKernelGGL(k_apply_update, dim3(cb, n_inst), dim3(256), 0, s, A, dtau, params, dparams);
+}
+
+template void sr_colstats<double>(const SrArgs&, double*, uint16_t*, double*, int, int64_t, int64_t,
+                                  hipStream_t);
+template void sr_colstats<float>(const SrArgs&, float*, uint16_t*, double*, int, int64_t, int64_t,
+                                 hipStream_t);
+template void sr_syrk_vec<double, double>(const SrArgs&, const double*, double*, int, int64_t, int,
+                                          hipStream_t);
+template void sr_syrk_vec<float, float>(const SrArgs&, const float*, float*, int, int64_t, int,
+                                        hipStream_t);
+template void sr_cholesky_solve<double>(const SrArgs&, const double*, const double*, double, double,
+                                        double, int, int64_t, hipStream_t);
+template void sr_cholesky_solve<float>(const SrArgs&, const float*, const double*, double, double,
+                                       double, int, int64_t, hipStream_t);
+template void sr_cg_begin<double>(const SrArgs&, const double*, double, double, double, double, int,
+                                  int64_t, hipStream_t);
+template void sr_cg_begin<float>(const SrArgs&, const double*, double, double, double, double, int,
+                                 int64_t, hipStream_t);
+template void sr_cg_iter<double>(const SrArgs&, const double*, int, int, int64_t, int64_t,
+                                 hipStream_t);
+template void sr_cg_iter<float>(const SrArgs&, const float*, int, int, int64_t, int64_t, hipStream_t);
+
+}  // namespace mvmc

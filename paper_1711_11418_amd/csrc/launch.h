@@ -1,0 +1,44 @@
+// Host-side launchers for the kernels, one group per .hip file.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace mvmc {
+
+// k_state.hip
+void launch_expand(const Pools& P, const InstDev* inst_host, int n_inst, const double* params,
+                   hipStream_t s);
+void launch_draw_configs(const Pools& P, const int32_t* wlist, int n, uint64_t seed,
+                         uint32_t attempt, hipStream_t s);
+void launch_build_empty(const Pools& P, const int32_t* wlist, int n, int max_ns, hipStream_t s);
+
+// k_refresh.hip: full double-precision X^-1, log|Pf|, sign, Jastrow field and
+// RBM angles for the walkers in wlist.  T is the walker-matrix type.
+template <typename T>
+void launch_refresh(const Pools& P, const int32_t* wlist, int n, int max_ne, int max_ns,
+                    bool lds, double sing_tol, hipStream_t s);
+size_t refresh_lds_bytes(int ne, int ns, bool lds);
+// Same, only for walkers whose flag is set; clears the flag.
+template <typename T>
+void launch_refresh_if(const Pools& P, const int32_t* wlist, int n, int max_ne, int max_ns,
+                       bool lds, int32_t* flags, hipStream_t s);
+// double copy of a float array
+void launch_widen(const float* src, double* dst, int64_t n, hipStream_t s);
+
+// k_sweep.hip: n_prop Metropolis proposals per walker.
+template <typename T>
+void launch_sweep(const Pools& P, const int32_t* wlist, int n, int cap, uint64_t seed,
+                  int max_ne, int max_ns, int max_M, bool lds, int nthreads,
+                  TraceRec* trace, int64_t trace_cap, const uint64_t* trace_base,
+                  const uint64_t* target, int32_t* needs_refresh, int R, hipStream_t s);
+size_t sweep_lds_bytes(int ne, int ns, int M, bool lds, size_t tsize, int nthreads);
+
+// k_measure.hip: local energy and O_k rows for sample slot `slot`.
+template <typename T>
+void launch_measure(const Pools& P, const int32_t* wlist, int n, int slot, double* eloc, T* O,
+                    int max_ne, int max_ns, int max_M, hipStream_t s);
+
+}  // namespace mvmc

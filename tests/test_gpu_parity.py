@@ -1,0 +1,208 @@
+"""GPU parity: libmvmc (HIP, through the C ABI) against the CPU oracle.
+
+Each case prints its name, shapes and seeds before touching the GPU.
+"""
+import numpy as np
+import pytest
+
+from mvmc_inputs import workload
+from oracle import sr as osr
+from oracle import wavefunction as wf
+from oracle.pfaffian import pfaffian_log
+
+from gpu_common import (compare_trace, good_configs, log, oracle_measure, oracle_trajectories,
+                        square_case)
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+SEED = 0x5EED1711
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    from paper_1711_11418_amd import binding
+    binding.load()
+
+
+def _ctx(insts, params, **kw):
+    from paper_1711_11418_amd import MVMC
+    return MVMC(insts, params, **kw)
+
+
+def _case(name):
+    if name == "sq10_full":
+        return square_case(10, 50, 4, full_f=True)
+    if name == "sq12_sub":
+        return square_case(12, 72, 2, full_f=False)
+    if name == "sq6_rbm":
+        return square_case(6, 16, 4, full_f=False, n_hidden=24)
+    inst = workload(name)["instances"][0]
+    inst.n_walkers = 8
+    return inst
+
+
+# ------------------------------------------------------------------ refresh
+@pytest.mark.parametrize("name", ["ring6", "c1_ring8_fp64", "sq4_sub2", "ring6_rbm", "sq10_full",
+                                  "sq12_sub"])
+def test_refresh_inverse_and_pfaffian(name):
+    inst = _case(name)
+    pos0 = good_configs(inst, inst.params0, inst.n_walkers, 3)
+    log(f"[refresh] {name}: Ns={inst.n_sites} Ne={inst.n_elec} W={inst.n_walkers}")
+    ctx = _ctx([inst], inst.params0)
+    ctx.set_state(pos0.ravel(), np.zeros(inst.n_walkers, dtype=np.int64))
+    Y = ctx.Y_of(ctx.get_inverse(), 0).cpu().numpy()
+    la, sg = (t.cpu().numpy() for t in ctx.get_pfaffian())
+    A = wf.skew_table(wf.expand(inst, inst.params0))
+    for w in range(inst.n_walkers):
+        X = A[np.ix_(pos0[w], pos0[w])]
+        Yr = np.linalg.inv(X)
+        assert np.max(np.abs(Y[w] - Yr)) <= 1e-10 * np.max(np.abs(Yr))
+        s, l = pfaffian_log(X)
+        assert sg[w] == s
+        assert la[w] == pytest.approx(l, abs=1e-10 * max(1.0, abs(l)))
+    ctx.close()
+
+
+# ------------------------------------------------------- trajectory replay
+@pytest.mark.parametrize("name,sweeps,refresh", [
+    ("ring6", 20, 0), ("c1_ring8_fp64", 20, 7), ("sq4_sub2", 10, 0), ("ring6_rbm", 20, 5),
+    ("sq10_full", 2, 0), ("sq6_rbm", 4, 16), ("sq12_sub", 1, 50),
+])
+def test_trajectory_replay_fp64(name, sweeps, refresh):
+    inst = _case(name)
+    pos0 = good_configs(inst, inst.params0, inst.n_walkers, 7)
+    n_prop = sweeps * inst.n_elec
+    log(f"[replay] {name}: Ne={inst.n_elec} W={inst.n_walkers} proposals={n_prop} "
+        f"refresh_every={refresh} seed={SEED}")
+    ctx = _ctx([inst], inst.params0, seed=SEED, refresh_every=refresh)
+    ctx.set_state(pos0.ravel(), np.zeros(inst.n_walkers, dtype=np.int64))
+    ctx.enable_trace(n_prop)
+    acc = ctx.sample(sweeps)
+    rec = ctx.trace_records()
+    walkers, m = oracle_trajectories(inst, inst.params0, pos0, 0, n_prop, SEED)
+    st = compare_trace(rec, walkers, n_prop, SEED, rtol=1e-10)
+    log(f"  compared {st['compared']} ratios, worst rel err {st['worst_rel']:.2e}, accepted {acc}")
+    assert acc[0] == sum(int(t[4]) for wk in walkers for t in wk.trace)
+    pos, cnt = ctx.get_state()
+    pos = ctx.pos_of(pos, 0).cpu().numpy()
+    assert np.array_equal(pos, np.array([wk.pos for wk in walkers]))
+    assert np.all(cnt.cpu().numpy() == n_prop)
+    # the rank-2 updated inverse equals the inverse of the final X
+    Y = ctx.Y_of(ctx.get_inverse(), 0).cpu().numpy()
+    A = wf.skew_table(m)
+    for w in range(inst.n_walkers):
+        Yr = np.linalg.inv(A[np.ix_(pos[w], pos[w])])
+        assert np.max(np.abs(Y[w] - Yr)) <= 1e-9 * np.max(np.abs(Yr)), w
+    # local energy and O_k at the final configuration
+    ctx.measure(0)
+    el = ctx.eloc_of(0, 1).cpu().numpy()
+    O = ctx.O_of(0, 1).cpu().numpy()
+    for w in range(inst.n_walkers):
+        e_ref, o_ref = oracle_measure(inst, m, pos[w])
+        assert el[w] == pytest.approx(e_ref, rel=1e-10, abs=1e-10)
+        assert np.allclose(O[w], o_ref, rtol=1e-9, atol=1e-10)
+    ctx.close()
+
+
+# --------------------------------------------------------------------- SR
+@pytest.mark.parametrize("solver", ["chol", "cg"])
+def test_sr_matrices_and_update(solver):
+    inst = workload("sq4_sub2")["instances"][0]
+    inst.n_walkers = 64
+    slots = 6
+    log(f"[sr] sq4_sub2 W=64 slots={slots} solver={solver}")
+    ctx = _ctx([inst], inst.params0, seed=SEED, n_slots=slots, solver=solver, build_s=True)
+    ctx.sample(5)
+    for s in range(slots):
+        ctx.sample(1)
+        ctx.measure(s)
+    O = ctx.O_of(0, slots).cpu().numpy().copy()
+    E = ctx.eloc_of(0, slots).cpu().numpy().copy()
+    Eb, Ev = ctx.build_sr(slots)
+    ref = osr.sr_stats(O, E)
+    assert Eb[0] == pytest.approx(ref["E"], rel=1e-13)
+    assert Ev[0] == pytest.approx(ref["E_var"], rel=1e-10)
+    S = ctx.S_of(0).cpu().numpy()
+    assert np.max(np.abs(S - ref["S"])) <= 1e-12 * np.max(np.abs(ref["S"]))
+    g = ctx.params_of(0, ctx.g).cpu().numpy()
+    assert np.max(np.abs(g - ref["g"])) <= 1e-12 * max(np.max(np.abs(ref["g"])), 1e-300) + 1e-15
+    Oc = ctx.O_of(0, slots).cpu().numpy()
+    assert np.allclose(Oc, ref["Oc"], rtol=0, atol=1e-13 * max(1.0, np.max(np.abs(O))))
+    p0 = ctx.params.cpu().numpy().copy()
+    it = ctx.sr_update(dtau=0.05, eps_rel=1e-3, eps_abs=1e-6, solver=solver, cg_tol=1e-12,
+                       cg_maxit=2000)
+    want = osr.sr_update(O, E, 0.05, 1e-3, 1e-6, solver=solver, cg_eps=1e-12)
+    d = ctx.dparams.cpu().numpy()
+    log(f"  cg iterations gpu={it[0]} oracle={want['cg_iters']}")
+    assert np.allclose(d, want["dalpha"], rtol=1e-8, atol=1e-11 * np.max(np.abs(want["dalpha"])))
+    assert np.allclose(ctx.params.cpu().numpy(), p0 + d, rtol=0, atol=1e-15)
+    ctx.close()
+
+
+# ------------------------------------------------------------ mixed precision
+@pytest.mark.parametrize("name,sweeps", [("sq4_sub2", 10), ("sq10_full", 2)])
+def test_mixed_precision_ratios(name, sweeps):
+    inst = _case(name)
+    pos0 = good_configs(inst, inst.params0, inst.n_walkers, 9, cond_max=1e4)
+    n_prop = sweeps * inst.n_elec
+    log(f"[mixed] {name}: Ne={inst.n_elec} W={inst.n_walkers} proposals={n_prop} refresh 32")
+    ctx = _ctx([inst], inst.params0, seed=SEED, precision="mixed", refresh_every=32)
+    ctx.set_state(pos0.ravel(), np.zeros(inst.n_walkers, dtype=np.int64))
+    ctx.enable_trace(n_prop)
+    ctx.sample(sweeps)
+    rec = ctx.trace_records()
+    walkers, _ = oracle_trajectories(inst, inst.params0, pos0, 0, n_prop, SEED)
+    st = compare_trace(rec, walkers, n_prop, SEED, rtol=2e-4, mixed=True)
+    log(f"  mixed: compared {st['compared']}, worst rel err {st['worst_rel']:.2e}, "
+        f"diverged chains {st['diverged']}")
+    assert st["compared"] > 0.8 * n_prop * inst.n_walkers
+    ctx.close()
+
+
+def test_mixed_split_bf16_overlap():
+    inst = workload("sq4_sub2")["instances"][0]
+    inst.n_walkers = 256
+    slots = 2
+    log("[mixed-S] sq4_sub2 W=256 slots=2")
+    ctx = _ctx([inst], inst.params0, seed=SEED, precision="mixed", refresh_every=32,
+               n_slots=slots)
+    ctx.sample(5)
+    for s in range(slots):
+        ctx.sample(1)
+        ctx.measure(s)
+    ctx.build_sr(slots)
+    Oc = ctx.O_of(0, slots).cpu().numpy().astype(np.float64)
+    S_ref = Oc.T @ Oc / Oc.shape[0]
+    S = ctx.S_of(0).cpu().numpy().astype(np.float64)
+    err = np.max(np.abs(S - S_ref)) / np.max(np.abs(S_ref))
+    log(f"  split-bf16 S max rel error {err:.2e}")
+    assert err < 2e-5
+    ctx.close()
+
+
+# ----------------------------------------------------------- ragged batch
+def test_batched_instances_replay():
+    insts = [workload(n)["instances"][0] for n in ("ring6", "sq4_sub2", "c1_ring8_fp64")]
+    insts.append(square_case(6, 15, 3, full_f=False))
+    for i in insts[:3]:
+        i.n_walkers = 5
+    params = np.concatenate([i.params0 for i in insts])
+    pos0 = [good_configs(i, i.params0, i.n_walkers, 11) for i in insts]
+    log("[batch] " + ", ".join(f"Ne={i.n_elec}xW={i.n_walkers}" for i in insts))
+    ctx = _ctx(insts, params, seed=SEED, refresh_every=9)
+    ctx.set_state(np.concatenate([p.ravel() for p in pos0]),
+                  np.zeros(sum(i.n_walkers for i in insts), dtype=np.int64))
+    sweeps = 3
+    ctx.enable_trace(sweeps * max(i.n_elec for i in insts))
+    ctx.sample(sweeps)
+    rec = ctx.trace_records()
+    for k, inst in enumerate(insts):
+        lay = ctx.layouts[k]
+        n_prop = sweeps * inst.n_elec
+        walkers, _ = oracle_trajectories(inst, inst.params0, pos0[k], lay.walker_off, n_prop, SEED)
+        sub = rec[lay.walker_off:lay.walker_off + inst.n_walkers]
+        compare_trace(sub, walkers, n_prop, SEED, rtol=1e-10)
+    ctx.close()
