@@ -1,0 +1,243 @@
+"""Benchmark of the many-variable VMC hot path on one MI355X.
+
+A step is one SR iteration of the 8x8 periodic Hubbard model (U = 4,
+N_e = 64, 2x2-sublattice pair amplitudes + distance Jastrow + Gutzwiller,
+N_p = 271): 1024 walkers x 200 sweeps (64 proposals each) with the local
+energy and O_k measured after every sweep, then the SR statistics, the S
+build, the Cholesky solve, the parameter update and the full refresh of
+every walker.  Inputs are seeded and synthetic and resident in HBM before
+timing starts.
+
+Printed: one JSON line with the walker hop-update rate (proposals/s) over
+whole steps, the S-build rate, the roofline of the sweep kernel, the
+mixed-precision run of the same workload, the split-bf16 S build at the
+4096 x 10^4 shape, and the CPU oracle timed on the host.
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu] [--skip-legs]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+BF16_PEAK_TFLOPS = 2500.0
+METRIC = "walker hop-updates/s + SR S-build TFLOP/s, batched/mixed vs plain FP64"
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", sweep_threads=0):
+    import numpy as np
+    import torch
+
+    from paper_1711_11418_amd import MVMC
+
+    inst = wl["instances"][0]
+    sweeps = wl["sweeps"]
+    ctx = MVMC([inst], inst.params0, precision=precision, refresh_every=refresh_every,
+               seed=wl["sampler_seed"], n_slots=sweeps, solver=solver, build_s=True,
+               sweep_threads=sweep_threads)
+    ctx.sample(wl["warmup"])
+    torch.cuda.synchronize()
+
+    def step(profile=False):
+        acc = 0
+        for s in range(sweeps):
+            if profile:
+                acc += int(ctx.sample(1)[0])
+            else:
+                ctx.sample_async(1)
+            ctx.measure(s)
+        E, V = ctx.build_sr(sweeps)
+        ctx.sr_update(dtau=wl["dtau"], eps_rel=wl["eps_rel"], eps_abs=wl["eps_abs"], solver=solver)
+        return acc, float(E[0])
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    energies = []
+    for _ in range(steps):
+        energies.append(step()[1])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # one more step with HIP events around every kernel group, for the roofline
+    ctx.sample(0)          # read and clear the accepted counters
+    ctx.timing(True)
+    accepted, _ = step(profile=True)
+    ms, calls = ctx.timing(False)
+    ctx.close()
+    W, ne, npar = inst.n_walkers, inst.n_elec, inst.n_params
+    proposals = steps * sweeps * W * ne
+    return {
+        "seconds": dt, "proposals": proposals, "rate": proposals / dt,
+        "ms_per_step": 1e3 * dt / steps, "energies": energies,
+        "accept_ratio": accepted / (sweeps * W * ne), "kernel_ms": ms.tolist(),
+        "kernel_calls": calls.tolist(), "W": W, "ne": ne, "np": npar, "sweeps": sweeps,
+        "N": sweeps * W,
+    }
+
+
+def sweep_roofline(r, wsize):
+    """Algorithmic bytes of the sweep per launch over its measured duration."""
+    W, ne = r["W"], r["ne"]
+    avg_ms = r["kernel_ms"][0] / max(r["kernel_calls"][0], 1)
+    props = W * ne                          # one sweep per launch in this workload
+    acc = r["accept_ratio"] * props
+    bytes_ = props * ne * wsize + acc * 2 * ne * ne * wsize
+    flops = props * 2 * ne + acc * 6 * ne * ne
+    return avg_ms, bytes_, flops
+
+
+def s_build_leg():
+    """Split-bf16 S build at the 4096-sample x 10^4-parameter shape."""
+    import numpy as np
+    import torch
+
+    from mvmc_inputs import workload
+    from paper_1711_11418_amd import MVMC
+
+    wl = workload("c3_sq10_mixed")
+    inst = wl["instances"][0]
+    ctx = MVMC([inst], inst.params0, precision="mixed", refresh_every=32,
+               seed=wl["sampler_seed"], n_slots=1, solver="cg", build_s=True)
+    ctx.sample(2)
+    ctx.measure(0)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    reps = 3
+    for _ in range(reps):
+        ctx.build_sr(1)
+    ms, calls = ctx.timing(False)
+    ctx.close()
+    N, npar = inst.n_walkers, inst.n_params
+    flops = N * npar * (npar + 1)
+    avg = ms[4] / max(calls[4], 1)
+    return {"shape": [N, npar], "ms": avg, "tflops": flops / (avg * 1e-3) / 1e12,
+            "algorithmic_flops": flops}
+
+
+def _oracle_worker(args):
+    import numpy as np
+    os.environ["OMP_NUM_THREADS"] = "1"
+    from mvmc_inputs import random_configs, workload
+    from oracle import sampler
+    from oracle import wavefunction as wf
+    wid, n_prop, budget = args
+    inst = workload("c2_sq8_fp64", n_walkers=4)["instances"][0]
+    m = wf.expand(inst, inst.params0)
+    A = wf.skew_table(m)
+    done = 0
+    t0 = time.perf_counter()
+    for pos in random_configs(inst, 64, 100 + wid):
+        if wf.log_psi(m, pos, A)[0] == 0.0:
+            continue
+        wk = sampler.make_walker(m, pos, gid=wid)
+        for _ in range(n_prop):
+            sampler.step(m, wk, 1711, A)
+            done += 1
+            if time.perf_counter() - t0 > budget:
+                return done, time.perf_counter() - t0
+    return done, time.perf_counter() - t0
+
+
+def cpu_baseline(budget_s=12.0):
+    """The oracle (full-recompute Metropolis, Parlett-Reid per proposal) on
+    the host cores, one process per core, on a time-bounded sample of the
+    8x8 workload; plus numpy O^T O at 4096 x 2000 in double."""
+    import multiprocessing as mp
+
+    import numpy as np
+    cores = min(os.cpu_count() or 1, 16)
+    with mp.get_context("spawn").Pool(cores) as pool:
+        res = pool.map(_oracle_worker, [(w, 10 ** 9, budget_s) for w in range(cores)])
+    props = sum(r[0] for r in res)
+    wall = max(r[1] for r in res)
+    rng = np.random.default_rng(0)
+    O = rng.standard_normal((4096, 2000))
+    t0 = time.perf_counter()
+    S = O.T @ O / 4096
+    ts = time.perf_counter() - t0
+    return {"value": props / wall, "unit": "hop-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{props} full-recompute proposals on the 8x8 U=4 workload, "
+                      f"{cores} processes x {budget_s:.0f} s",
+            "s_build_gflops_numpy_fp64": 4096 * 2000 * 2001 / ts / 1e9}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--skip-legs", action="store_true")
+    ap.add_argument("--sweep-threads", type=int, default=0,
+                    help="0: register-resident sweep where it fits; 64/128/256: LDS sweep")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the walkers of this workload fit one MI355X; "
+              "multi-GPU sharding is described in DESIGN.md and not run.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    from mvmc_inputs import workload
+
+    wl = workload("c2_sq8_fp64")
+    log(f"[bench] c2_sq8_fp64 fp64: W=1024 sweeps/step={wl['sweeps']} steps={a.steps} "
+        f"warmup={a.warmup}")
+    r = run_sr_workload(wl, "fp64", a.steps, a.warmup, wl["refresh_every"],
+                        sweep_threads=a.sweep_threads)
+    avg_ms, bytes_, flops = sweep_roofline(r, 8)
+    achieved = bytes_ / (avg_ms * 1e-3) / 1e9
+    s_ms = r["kernel_ms"][4] / max(r["kernel_calls"][4], 1)
+    s_flops = r["N"] * r["np"] * (r["np"] + 1)
+    out = {
+        "metric": METRIC, "value": r["rate"], "unit": "hop-updates/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "c2_sq8_fp64: 8x8 Hubbard U=4, Ne=64, Np=271, 1024 walkers x "
+                               "200 sweeps + SR (Cholesky) per step",
+                   "walkers": r["W"], "n_elec": r["ne"], "n_params": r["np"],
+                   "sweeps_per_step": r["sweeps"], "samples_per_step": r["N"]},
+        "accepted_per_s": r["rate"] * r["accept_ratio"],
+        "accept_ratio": r["accept_ratio"],
+        "s_build": {"tflops": s_flops / (s_ms * 1e-3) / 1e12, "ms": s_ms, "dtype": "f64",
+                    "shape": [r["N"], r["np"]]},
+        "roofline": {"kernel": "k_sweep<double>", "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "avg_launch_ms": avg_ms,
+                     "alg_bytes_per_launch": bytes_, "alg_flops_per_launch": flops,
+                     "fp64_tflops": flops / (avg_ms * 1e-3) / 1e12},
+        "kernel_ms_per_step": dict(zip(["sweep", "refresh", "measure", "sr_stats", "s_build",
+                                        "sr_solve"], r["kernel_ms"])),
+        "energy_per_site": [e / 64 for e in r["energies"]],
+    }
+    if not a.skip_legs:
+        log("[bench] mixed-precision leg (same workload, fp32 sweeps, refresh every 32)")
+        m = run_sr_workload(wl, "mixed", max(1, a.steps - 1), 1, 32,
+                            sweep_threads=a.sweep_threads)
+        out["mixed"] = {"value": m["rate"], "ms_per_step": m["ms_per_step"],
+                        "speedup_vs_fp64": m["rate"] / r["rate"],
+                        "energy_per_site": [e / 64 for e in m["energies"]],
+                        "kernel_ms_per_step": m["kernel_ms"]}
+        log("[bench] split-bf16 S build at 4096 x 10^4")
+        out["s_build_bf16x3_c3"] = s_build_leg()
+    if not a.no_cpu:
+        log("[bench] CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

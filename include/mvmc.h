@@ -148,7 +148,8 @@ int mvmc_init_wavefunction(mvmc_ctx **out, const mvmc_config *cfg, void *d_works
  * (section 3.1.2), each accepted with probability min(1, R^2), R = psi(x')/psi(x)
  * from a row of X^-1 and the correlator ratios, followed on acceptance by the
  * rank-2 update of X^-1.  h_accepted (may be NULL): [n_instances] accepted
- * proposals in this call.
+ * proposals since the last call that returned them (the counters are then
+ * cleared; with NULL they keep accumulating).
  */
 int mvmc_sample_sweeps(mvmc_ctx *ctx, int32_t n_sweeps, int64_t *h_accepted);
 

@@ -228,6 +228,8 @@ class MVMC:
 
     # ----------------------------------------------------------- hot path
     def sample(self, n_sweeps: int) -> np.ndarray:
+        """n_sweeps sweeps; returns the accepted proposals per instance since
+        the last call that returned them (and clears the counters)."""
         acc = np.zeros(self.n_inst, dtype=np.int64)
         self._check(self.lib.mvmc_sample_sweeps(self.ctx, int(n_sweeps),
                                                 acc.ctypes.data_as(C.c_void_p)))

@@ -25,6 +25,7 @@ constexpr size_t kLdsLimit = 152 * 1024;   // per-workgroup LDS budget used for 
 constexpr int kMaxSites = 1024;
 constexpr int kMaxElec = 2048;
 constexpr int kTimingCats = 6;
+constexpr int kRegWpb = 4;   // walkers per workgroup of the register sweep
 
 inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
 
@@ -36,9 +37,11 @@ struct Pool {
 struct Plan {
   std::vector<InstDev> inst;
   std::vector<SrInst> sr;
+  std::vector<int> reg_class;     // register-sweep tier per instance (0 = LDS/HBM kernel)
   // pools (byte offsets into the workspace)
   Pool inst_p, srinst_p, walker_inst, lists, A64, A32, V, fidx, vidx, G, U, gidx, nbr_ptr,
-      nbr_site, nbr_t, fm_ptr, fm, gm_ptr, gm, vm_ptr, vm, rbm64, rbm32, Y, Y64, pos, empty, h,
+      nbr_site, nbr_t, fm_ptr, fm, gm_ptr, gm, vm_ptr, vm, rbm64, rbm32, rbmT64, rbmT32, Y, Y64,
+      pos, empty, h,
       theta, cnt, target, needs_refresh, accepted, logpf, sgnpf, minpiv, status, trace_base,
       obar, sdiag, x, r, p, w, t, shift, mask, scal, colpart, syrkpart, chol, split;
   size_t total = 0;
@@ -153,6 +156,7 @@ Plan make_plan(const mvmc_config& c) {
   const int n = c.n_instances;
   P.inst.resize(n);
   P.sr.resize(n);
+  P.reg_class.assign(n, 0);
   int64_t off_A = 0, off_V = 0, off_site = 0, off_nptr = 0, off_nbr = 0, off_fm_ptr = 0,
           off_fm = 0, off_gm_ptr = 0, off_gm = 0, off_vm_ptr = 0, off_vm = 0, off_rbm = 0,
           off_Y = 0, off_pos = 0, off_empty = 0, off_h = 0, off_theta = 0, off_chol = 0,
@@ -181,6 +185,11 @@ Plan make_plan(const mvmc_config& c) {
     for (int x : deg) I.deg_max = std::max(I.deg_max, x);
     const int nt = sweep_threads_for(c, I.ne);
     I.sweep_lds = sweep_lds_bytes(I.ne, I.ns, I.M, true, P.tsize, nt) <= kLdsLimit;
+    if (c.sweep_threads == 0) {
+      const int rc = sweep_reg_class(I.ne, P.tsize);
+      if (rc && sweep_reg_lds_bytes(rc, I.ns, I.M, P.tsize, kRegWpb) <= kLdsLimit)
+        P.reg_class[k] = rc;
+    }
     I.refresh_lds = refresh_lds_bytes(I.ne, I.ns, true) <= kLdsLimit;
     if (!I.refresh_lds) P.need_Y64 = true;
     I.walker_off = P.W;
@@ -280,7 +289,7 @@ Plan make_plan(const mvmc_config& c) {
   take(P.inst_p, sizeof(InstDev) * n);
   take(P.srinst_p, sizeof(SrInst) * n);
   take(P.walker_inst, 4 * W);
-  take(P.lists, 4 * W * 4);
+  take(P.lists, 4 * (4 * W + (size_t)kRegWpb * n));
   take(P.A64, 8 * (size_t)off_A);
   take(P.A32, 4 * (size_t)off_A);
   take(P.V, 8 * (size_t)off_V);
@@ -300,6 +309,8 @@ Plan make_plan(const mvmc_config& c) {
   take(P.vm, 4 * (size_t)off_vm);
   take(P.rbm64, 8 * (size_t)off_rbm);
   take(P.rbm32, 4 * (size_t)off_rbm);
+  take(P.rbmT64, 8 * (size_t)off_rbm);
+  take(P.rbmT32, 4 * (size_t)off_rbm);
   take(P.Y, P.tsize * (size_t)off_Y);
   take(P.Y64, P.need_Y64 ? 8 * (size_t)off_Y : 0);
   take(P.pos, 4 * (size_t)off_pos);
@@ -381,6 +392,7 @@ struct Bucket {
   size_t list_off;   // byte offset of its walker list inside the list pool
   int n = 0, max_ne = 0, max_ns = 0, max_M = 0, nthreads = 256;
   bool lds = true;
+  int reg = 0;       // register-sweep tier (n = number of walker groups) or 0
 };
 
 }  // namespace
@@ -473,19 +485,42 @@ void build_buckets(mvmc_ctx* c) {
   const int n = c->cfg.n_instances;
   // key: (lds flag, LDS size class or 0, threads)
   std::map<std::tuple<int, size_t, int>, std::vector<int>> sweep_groups, refresh_groups;
+  std::map<int, std::vector<int>> reg_groups;
   for (int k = 0; k < n; ++k) {
     const InstDev& I = P.inst[k];
+    size_t rb = refresh_lds_bytes(I.ne, I.ns, I.refresh_lds);
+    size_t rcls = 4096;
+    while (rcls < rb) rcls <<= 1;
+    refresh_groups[{I.refresh_lds, rcls, 256}].push_back(k);
+    if (P.reg_class[k]) {
+      reg_groups[P.reg_class[k]].push_back(k);
+      continue;
+    }
     const int nt = sweep_threads_for(c->cfg, I.ne);
     size_t sb = sweep_lds_bytes(I.ne, I.ns, I.M, I.sweep_lds, P.tsize, nt);
     size_t cls = 4096;
     while (cls < sb) cls <<= 1;
     sweep_groups[{I.sweep_lds, cls, nt}].push_back(k);
-    size_t rb = refresh_lds_bytes(I.ne, I.ns, I.refresh_lds);
-    size_t rcls = 4096;
-    while (rcls < rb) rcls <<= 1;
-    refresh_groups[{I.refresh_lds, rcls, 256}].push_back(k);
   }
   std::vector<int32_t> lists;
+  // register tiers: each instance's walkers in groups of kRegWpb, padded with -1
+  for (auto& g : reg_groups) {
+    Bucket b;
+    b.reg = g.first;
+    b.list_off = lists.size() * 4;
+    std::vector<int> ks = g.second;
+    std::stable_sort(ks.begin(), ks.end(), [&](int x, int y) { return P.inst[x].ne > P.inst[y].ne; });
+    for (int k : ks) {
+      const InstDev& I = P.inst[k];
+      for (int w = 0; w < I.W; ++w) lists.push_back((int32_t)(I.walker_off + w));
+      while ((lists.size() - b.list_off / 4) % kRegWpb) lists.push_back(-1);
+      b.max_ne = std::max(b.max_ne, I.ne);
+      b.max_ns = std::max(b.max_ns, I.ns);
+      b.max_M = std::max(b.max_M, I.M);
+    }
+    b.n = (int)((lists.size() - b.list_off / 4) / kRegWpb);
+    c->sweep_b.push_back(b);
+  }
   auto emit = [&](const std::map<std::tuple<int, size_t, int>, std::vector<int>>& groups,
                   std::vector<Bucket>& out) {
     for (auto& g : groups) {
@@ -511,14 +546,14 @@ void build_buckets(mvmc_ctx* c) {
   };
   emit(sweep_groups, c->sweep_b);
   emit(refresh_groups, c->refresh_b);
-  // list pool: [sweep lists | refresh lists | all walkers | scratch]
+  // list pool: [sweep lists (padded) | refresh lists | all walkers | scratch]
   const size_t W = (size_t)P.W;
   std::vector<int32_t> all(W);
   for (size_t w = 0; w < W; ++w) all[w] = (int32_t)w;
   char* base = c->ws + P.lists.off;
   (void)hipMemcpy(base, lists.data(), lists.size() * 4, hipMemcpyHostToDevice);
-  c->d_all = reinterpret_cast<int32_t*>(base + 2 * W * 4);
-  c->d_scratch = reinterpret_cast<int32_t*>(base + 3 * W * 4);
+  c->d_all = reinterpret_cast<int32_t*>(base + lists.size() * 4);
+  c->d_scratch = c->d_all + W;
   (void)hipMemcpy(c->d_all, all.data(), W * 4, hipMemcpyHostToDevice);
 }
 
@@ -653,6 +688,8 @@ int mvmc_init_wavefunction(mvmc_ctx** out, const mvmc_config* cfg, void* d_ws, s
   Q.vm = at<int32_t>(b, P.vm);
   Q.rbm64 = at<double>(b, P.rbm64);
   Q.rbm32 = at<float>(b, P.rbm32);
+  Q.rbmT64 = at<double>(b, P.rbmT64);
+  Q.rbmT32 = at<float>(b, P.rbmT32);
   Q.Y = b + P.Y.off;
   Q.Y64 = P.need_Y64 ? at<double>(b, P.Y64) : nullptr;
   Q.pos = at<int32_t>(b, P.pos);
@@ -802,19 +839,17 @@ int mvmc_sample_sweeps(mvmc_ctx* c, int32_t n_sweeps, int64_t* h_accepted) {
   if (!c || n_sweeps < 0) return set_err(c, fail(MVMC_E_ARG, "n_sweeps must be >= 0"));
   const Plan& P = c->plan;
   const int R = c->cfg.refresh_every;
-  HIPCHK(c, hipMemsetAsync(c->P.accepted, 0, 8 * P.W, c->stream));
-  if (n_sweeps == 0) {
-    if (h_accepted)
-      for (int k = 0; k < c->cfg.n_instances; ++k) h_accepted[k] = 0;
-    return MVMC_OK;
-  }
   // proposals per walker this call and the number of refresh-aligned rounds
+  // register-tier walkers refresh inside the sweep kernel; LDS-tier walkers
+  // stop at every multiple of refresh_every and are refreshed between launches
   int rounds = 1;
+  bool lds_refresh = false;
   std::vector<uint64_t> target(c->cfg.n_instances);
   for (int k = 0; k < c->cfg.n_instances; ++k) {
     const uint64_t tot = (uint64_t)n_sweeps * P.inst[k].ne;
-    target[k] = c->cfg.n_instances ? tot : 0;
-    if (R > 0) {
+    target[k] = tot;
+    if (R > 0 && !P.reg_class[k]) {
+      lds_refresh = true;
       const uint64_t ph = c->cnt_host[k] % (uint64_t)R;
       uint64_t rem = tot, r = 0, first = (uint64_t)R - ph;
       if (rem <= first) r = 1;
@@ -839,6 +874,20 @@ int mvmc_sample_sweeps(mvmc_ctx* c, int32_t n_sweeps, int64_t* h_accepted) {
     const int id = tic(c, 0);
     for (auto& b : c->sweep_b) {
       const int32_t* lst = reinterpret_cast<int32_t*>(c->ws + P.lists.off + b.list_off);
+      if (b.reg) {
+        if (r > 0) continue;   // finished its whole target in the first round
+        const int cp = INT32_MAX;
+        const bool ok =
+            c->cfg.precision == MVMC_FP64
+                ? launch_sweep_reg<double>(c->P, lst, b.n, b.reg, b.max_ns, b.max_M, cp,
+                                           c->cfg.seed, c->trace, c->trace_cap, tb, tgt, nr, R,
+                                           1, c->stream)
+                : launch_sweep_reg<float>(c->P, lst, b.n, b.reg, b.max_ns, b.max_M, cp,
+                                          c->cfg.seed, c->trace, c->trace_cap, tb, tgt, nr, R,
+                                          1, c->stream);
+        if (!ok) return set_err(c, fail(MVMC_E_ARG, "no register sweep tier %d", b.reg));
+        continue;
+      }
       if (c->cfg.precision == MVMC_FP64)
         launch_sweep<double>(c->P, lst, b.n, (int)std::min<int64_t>(cap, INT32_MAX), c->cfg.seed,
                              b.max_ne, b.max_ns, b.max_M, b.lds, b.nthreads, c->trace,
@@ -850,7 +899,7 @@ int mvmc_sample_sweeps(mvmc_ctx* c, int32_t n_sweeps, int64_t* h_accepted) {
     }
     toc(c, id);
     LAUNCHCHK(c);
-    if (R > 0) {
+    if (lds_refresh) {
       const int id2 = tic(c, 1);
       for (auto& b : c->refresh_b) {
         const int32_t* lst = reinterpret_cast<int32_t*>(c->ws + P.lists.off + b.list_off);
@@ -874,6 +923,7 @@ int mvmc_sample_sweeps(mvmc_ctx* c, int32_t n_sweeps, int64_t* h_accepted) {
       for (int w = 0; w < I.W; ++w) s += acc[I.walker_off + w];
       h_accepted[k] = s;
     }
+    HIPCHK(c, hipMemsetAsync(c->P.accepted, 0, 8 * P.W, c->stream));
   }
   return MVMC_OK;
 }

@@ -64,6 +64,8 @@ struct Pools {
   int32_t* vm;
   double* rbm64;                   // a, b, W in double
   float* rbm32;                    // same, single precision
+  double* rbmT64;                  // a, b, W^T ([2Ns][M]) in double
+  float* rbmT32;                   // same, single precision
   void* Y;                         // double or float walker matrices
   double* Y64;                     // double scratch for refreshes that do not fit LDS
   int32_t* pos;

@@ -28,7 +28,14 @@ template <> __device__ __forceinline__ const float* table_of<float>(const Pools&
 }
 }  // namespace
 
-template <typename T>
+// LDS carve-up: [red 16 | hs ns | ths M] doubles, [Y ne*ne | f ns*(ns+1)] T, ints.
+__host__ __device__ inline size_t mal16(size_t x) { return (x + 15) & ~(size_t)15; }
+__host__ __device__ inline size_t measure_lds(int ne, int ns, int M, size_t ts, bool ylds, bool flds) {
+  return mal16((16 + (size_t)ns + M) * sizeof(double)) + (ylds ? mal16((size_t)ne * (ne + 1) * ts) : 0) +
+         (flds ? mal16((size_t)ns * (ns + 1) * ts) : 0) + (size_t)(ne + 2 * ns) * sizeof(int32_t);
+}
+
+template <typename T, bool YLDS, bool FLDS>
 __global__ __launch_bounds__(kMeasureThreads) void k_measure(Pools P,
                                                              const int32_t* __restrict__ wlist,
                                                              int slot, double* __restrict__ eloc,
@@ -36,20 +43,37 @@ __global__ __launch_bounds__(kMeasureThreads) void k_measure(Pools P,
   extern __shared__ __align__(16) unsigned char smem[];
   const int gw = wlist[blockIdx.x];
   const InstDev& I = P.inst[P.walker_inst[gw]];
-  const int ne = I.ne, ns = I.ns, n2 = 2 * ns, M = I.M;
+  const int ne = I.ne, ns = I.ns, n2 = 2 * ns, M = I.M, nup = I.nup;
   const int64_t lw = gw - I.walker_off;
   const int tid = threadIdx.x;
+  const int ldf = ns + 1;
 
-  double* red = (double*)smem;                  // 16
+  unsigned char* q = smem;
+  double* red = (double*)q;                     // 16
   double* hs = red + 16;                        // ns
   double* ths = hs + ns;                        // M
-  int32_t* pos_s = (int32_t*)(ths + M);         // ne
+  q += mal16((16 + (size_t)ns + M) * sizeof(double));
+  const T* Yglob = (const T*)P.Y + I.Y_off + lw * ne * ne;
+  T* Ys = (T*)q;
+  if (YLDS) q += mal16((size_t)ne * (ne + 1) * sizeof(T));
+  const int ldy = YLDS ? ne + 1 : ne;   // padded rows avoid LDS bank conflicts
+  T* fs = (T*)q;
+  if (FLDS) q += mal16((size_t)ns * ldf * sizeof(T));
+  int32_t* pos_s = (int32_t*)q;                 // ne
   int32_t* eidx = pos_s + ne;                   // 2ns
 
   const int32_t* posg = P.pos + I.pos_off + lw * ne;
+  const T* A = table_of<T>(P, I.A_off);
   for (int v = tid; v < n2; v += blockDim.x) eidx[v] = -1;
   for (int l = tid; l < ns; l += blockDim.x) hs[l] = P.h[I.h_off + lw * ns + l];
   for (int hh = tid; hh < M; hh += blockDim.x) ths[hh] = P.theta[I.theta_off + lw * M + hh];
+  if (YLDS)
+    for (int e = tid; e < ne * ne; e += blockDim.x) Ys[(e / ne) * ldy + e % ne] = Yglob[e];
+  if (FLDS)
+    for (int e = tid; e < ns * ns; e += blockDim.x) {
+      const int i = e / ns, j = e - (e / ns) * ns;
+      fs[i * ldf + j] = A[(int64_t)i * n2 + ns + j];
+    }
   __syncthreads();
   for (int b = tid; b < ne; b += blockDim.x) {
     pos_s[b] = posg[b];
@@ -57,8 +81,9 @@ __global__ __launch_bounds__(kMeasureThreads) void k_measure(Pools P,
   }
   __syncthreads();
 
-  const T* Y = (const T*)P.Y + I.Y_off + lw * ne * ne;
-  const T* A = table_of<T>(P, I.A_off);
+  const T* Y = YLDS ? (const T*)Ys : Yglob;
+  // pair amplitude f(i, j) = A[i][Ns + j]
+  auto fval = [&](int i, int j) -> T { return FLDS ? fs[i * ldf + j] : A[(int64_t)i * n2 + ns + j]; };
   const double* V = P.V + I.V_off;
   const double* G = P.G + I.site_off;
   const double* Uv = P.U + I.site_off;
@@ -73,7 +98,7 @@ __global__ __launch_bounds__(kMeasureThreads) void k_measure(Pools P,
     if (eidx[i] >= 0 && eidx[i + ns] >= 0) e += Uv[i];
   const int deg = I.deg_max;
   for (int t = tid; t < ne * deg; t += blockDim.x) {
-    const int a = t / deg, qn = t % deg;
+    const int a = t / deg, qn = t - (t / deg) * deg;
     const int Iold = pos_s[a];
     const int sigma = Iold >= ns ? 1 : 0;
     const int site_old = Iold - sigma * ns;
@@ -82,11 +107,16 @@ __global__ __launch_bounds__(kMeasureThreads) void k_measure(Pools P,
     const int site_new = nsite[s0];
     const int Inew = site_new + sigma * ns;
     if (eidx[Inew] >= 0) continue;
-    const T* Arow = A + (int64_t)Inew * n2;
-    const T* Ya = Y + a * ne;
+    // new row a of X is non-zero only on the opposite-spin electrons (Eq. AP-Pf)
+    const T* Ya = Y + a * ldy;
     double s = 0.0;
-    for (int b = 0; b < ne; ++b)
-      if (b != a) s += (double)Arow[pos_s[b]] * (double)Ya[b];
+    if (sigma == 0) {
+#pragma unroll 4
+      for (int b = nup; b < ne; ++b) s += (double)Ya[b] * (double)fval(site_new, pos_s[b] - ns);
+    } else {
+#pragma unroll 4
+      for (int b = 0; b < nup; ++b) s -= (double)Ya[b] * (double)fval(pos_s[b], site_new);
+    }
     const double r_pf = -s;
     const int opp = (1 - sigma) * ns;
     double logc = G[site_new] * (eidx[site_new + opp] >= 0 ? 1.0 : 0.0) -
@@ -116,7 +146,7 @@ __global__ __launch_bounds__(kMeasureThreads) void k_measure(Pools P,
     for (int m = fptr[k]; m < fptr[k + 1]; ++m) {
       const int pk = fm[m];
       const int ea = eidx[pk / ns], eb = eidx[pk % ns + ns];
-      if (ea >= 0 && eb >= 0) s -= (double)Y[ea * ne + eb];
+      if (ea >= 0 && eb >= 0) s -= (double)Y[ea * ldy + eb];
     }
     Orow[k] = (T)s;
   }
@@ -161,8 +191,23 @@ template <typename T>
 void launch_measure(const Pools& P, const int32_t* wlist, int n, int slot, double* eloc, T* O,
                     int max_ne, int max_ns, int max_M, hipStream_t s) {
   if (n <= 0) return;
-  const size_t sh = (16 + max_ns + max_M) * sizeof(double) + (max_ne + 2 * max_ns) * sizeof(int32_t);
-  hipLaunchKernelGGL(k_measure<T>, dim3(n), dim3(kMeasureThreads), sh, s, P, wlist, slot, eloc, O);
+  const size_t budget = 96 * 1024;
+  const bool ylds = measure_lds(max_ne, max_ns, max_M, sizeof(T), true, false) <= budget;
+  const bool flds = measure_lds(max_ne, max_ns, max_M, sizeof(T), ylds, true) <= budget;
+  const size_t sh = measure_lds(max_ne, max_ns, max_M, sizeof(T), ylds, flds);
+#define MVMC_MEAS(YL, FL)                                                                       \
+  do {                                                                                          \
+    if (sh > 65536)                                                                             \
+      (void)hipFuncSetAttribute((const void*)&k_measure<T, YL, FL>,                             \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);           \
+    hipLaunchKernelGGL((k_measure<T, YL, FL>), dim3(n), dim3(kMeasureThreads), sh, s, P, wlist, \
+                       slot, eloc, O);                                                          \
+  } while (0)
+  if (ylds && flds) MVMC_MEAS(true, true);
+  else if (ylds) MVMC_MEAS(true, false);
+  else if (flds) MVMC_MEAS(false, true);
+  else MVMC_MEAS(false, false);
+#undef MVMC_MEAS
 }
 
 template void launch_measure<double>(const Pools&, const int32_t*, int, int, double*, double*, int,

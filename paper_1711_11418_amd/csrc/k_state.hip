@@ -44,9 +44,18 @@ __global__ void k_expand(Pools P, const double* __restrict__ params) {
   if (I.M) {
     const int64_t nr = (int64_t)n2 + I.M + (int64_t)I.M * n2;
     const double* pr = p + I.nf + I.ng + I.nv;
+    const int64_t nab = (int64_t)n2 + I.M;
     for (int64_t e = t0; e < nr; e += stride) {
       P.rbm64[I.rbm_a_off + e] = pr[e];
       P.rbm32[I.rbm_a_off + e] = (float)pr[e];
+      // transposed copy: W^T[v][h] = W[h][v]
+      int64_t et = e;
+      if (e >= nab) {
+        const int64_t w = e - nab, hh = w / n2, v = w - hh * n2;
+        et = nab + v * I.M + hh;
+      }
+      P.rbmT64[I.rbm_a_off + et] = pr[e];
+      P.rbmT32[I.rbm_a_off + et] = (float)pr[e];
     }
   }
 }

@@ -1,0 +1,602 @@
+// Register-resident Metropolis sweep: one wavefront per walker, X^-1 held in
+// VGPRs for the whole launch, WPB walkers of one instance per workgroup
+// sharing the pair-amplitude table f in LDS.
+//
+// Lane l owns the columns c = l + 64k (k < KC) of Y = X^-1 and keeps
+// y[k][i] = Y[i][c] for every row i.  Per proposal (same arithmetic as the
+// LDS kernel; hopping update of section 3.1.2 with the fast-update ratio):
+//   row a of Y      y[k][a], a uniform index (branch tree over a)
+//   x'_c            the anti-parallel pair amplitude between the new
+//                   spin-orbital I' and electron c: f(site', site_c) when an
+//                   up electron moves and c is down, -f(site_c, site') when a
+//                   down electron moves and c is up, else 0 (Eq. AP-Pf with
+//                   X_IJ = F_IJ - F_JI)
+//   r_Pf            -sum_c Y[a][c] x'_c   (DPP wave reduction)
+//   correlators     scalar loads (Gutzwiller, Jastrow field in LDS, RBM)
+// On acceptance, with p = -Y[a,:], q = -Y^T x' + e_a (column sums over the
+// registers with x' broadcast from LDS):
+//   y[k][i] += p_i (q_c / r_Pf) - q_i (p_c / r_Pf)
+// Every per-proposal quantity that is the same for the whole walker lives in
+// scalar registers (Philox runs on the scalar unit), so the proposal loop has
+// no workgroup barrier.
+#include "launch.h"
+
+namespace mvmc {
+
+namespace {
+
+__host__ __device__ inline size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+// LDS: [f table ns x (ns+1) | WPB x per-walker block]
+__host__ __device__ inline size_t reg_table_bytes(int ns, size_t ts) {
+  return a16((size_t)ns * (ns + 1) * ts);
+}
+__host__ __device__ inline size_t reg_walker_bytes(int ne_max, int ns, int M, size_t ts) {
+  return a16(3 * (size_t)ne_max * ts) + a16(2 * (size_t)ne_max * sizeof(double)) +
+         a16((size_t)ns * sizeof(double)) + a16((size_t)M * ts) +
+         a16((size_t)(4 * ns + 2 * ne_max) * sizeof(int32_t));
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes: butterflies inside each row of 16 (quad_perm,
+// half-row and row mirrors), then the row sums are carried up by the row
+// broadcasts; lane 63 ends with the total, which is read back as a scalar.
+__device__ __forceinline__ double wave_total(double v) {
+  v += dpp_d<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+  v += dpp_d<0x141, 0xF>(v);   // row_half_mirror
+  v += dpp_d<0x140, 0xF>(v);   // row_mirror
+  v += dpp_d<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_d<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
+// y[a] for a uniform runtime index a, as a branch tree over compile-time
+// indices.  The empty volatile asm in each leaf keeps the compiler from
+// folding the tree back into one dynamically indexed access, which would
+// move the whole register array to scratch memory.
+template <typename T, int N, int LO, int HI>
+__device__ __forceinline__ T pick(const T (&y)[N], int a) {
+  if constexpr (HI - LO == 1) {
+    asm volatile("" ::: );
+    return y[LO];
+  } else {
+    constexpr int MID = (LO + HI) / 2;
+    if (a < MID) return pick<T, N, LO, MID>(y, a);
+    return pick<T, N, MID, HI>(y, a);
+  }
+}
+
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_keep(double v) {
+  // lanes outside the row mask keep their own value
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, ROWMASK,
+                                             0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), CTRL, ROWMASK,
+                                             0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, dpp_keep<0xB1, 0xF>(v));
+  v = fmax(v, dpp_keep<0x4E, 0xF>(v));
+  v = fmax(v, dpp_keep<0x141, 0xF>(v));
+  v = fmax(v, dpp_keep<0x140, 0xF>(v));
+  v = fmax(v, dpp_keep<0x142, 0xA>(v));
+  v = fmax(v, dpp_keep<0x143, 0xC>(v));
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ int dpp_keep_i(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, ROWMASK, 0xF, false);
+}
+__device__ __forceinline__ int wave_min_i(int v) {
+  v = min(v, dpp_keep_i<0xB1, 0xF>(v));
+  v = min(v, dpp_keep_i<0x4E, 0xF>(v));
+  v = min(v, dpp_keep_i<0x141, 0xF>(v));
+  v = min(v, dpp_keep_i<0x140, 0xF>(v));
+  v = min(v, dpp_keep_i<0x142, 0xA>(v));
+  v = min(v, dpp_keep_i<0x143, 0xC>(v));
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
+template <typename T> __device__ __forceinline__ const T* table_ptr(const Pools& P, int64_t off);
+template <> __device__ __forceinline__ const double* table_ptr<double>(const Pools& P, int64_t off) {
+  return P.A64 + off;
+}
+template <> __device__ __forceinline__ const float* table_ptr<float>(const Pools& P, int64_t off) {
+  return P.A32 + off;
+}
+template <typename T> __device__ __forceinline__ const T* rbmT_ptr(const Pools& P);
+template <> __device__ __forceinline__ const double* rbmT_ptr<double>(const Pools& P) { return P.rbmT64; }
+template <> __device__ __forceinline__ const float* rbmT_ptr<float>(const Pools& P) { return P.rbmT32; }
+
+__device__ __forceinline__ int sgpr(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+}  // namespace
+
+size_t sweep_reg_lds_bytes(int ne_max, int ns, int M, size_t tsize, int wpb) {
+  return reg_table_bytes(ns, tsize) + (size_t)wpb * reg_walker_bytes(ne_max, ns, M, tsize);
+}
+
+constexpr int kChunk = 8;   // rows per group of broadcast loads in the update
+
+// Double-precision recomputation of X^-1 for the walker of this wavefront,
+// in registers (lane c keeps column c).  Same in-place skew Gauss-Jordan as
+// the refresh kernel: pivot block K = {i, j}, x = M[i][j], and
+//   M_Kc <- P^-1 M_Kc,  M_rK <- -M_rK P^-1,  M_rc <- M_rc - M_rK P^-1 M_Kc.
+// Every intermediate M is skew-symmetric, so column j of M is minus row j:
+// each lane reads rows i and j from its own registers (uniform index), and
+// the update of lane c's column is
+//   m[r] <- g_c m[r] + a_c M[j][r] + b_c M[i][r]
+// with (g, a, b) = (1, M[i][c]/x, -M[j][c]/x) off the pivot columns,
+// (0, 1/x, 0) for c = i and (0, 0, -1/x) for c = j; rows i and j are then
+// set to P^-1 applied to the old rows.  Pf(X) = sgn(pi) prod_k x_k.
+template <int NE_MAX, int KC>
+__device__ __forceinline__ int reg_refresh(double (&m)[KC][NE_MAX], const int (&posr)[KC],
+                                           const double* __restrict__ f, int ldf, bool f_in_lds,  // f(i,j) at f[i*ldf+j] in LDS or f[i*n2+j] in HBM
+                                           int n2, int ns, int ne, int lane, int32_t* posl,
+                                           double* sri, double* srj, int32_t* ord,
+                                           double& logabs, double& sgn) {
+#pragma unroll
+  for (int k = 0; k < KC; ++k)
+    if (lane + 64 * k < NE_MAX) posl[lane + 64 * k] = posr[k];
+  wave_sync();
+  // X[r][c]: anti-parallel pairing, f(i, j) = A[i][Ns + j]
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const int c = lane + 64 * k, pc = posr[k];
+#pragma unroll
+    for (int r = 0; r < NE_MAX; ++r) {
+      double v = 0.0;
+      if (r < ne && c < ne) {
+        const int pr = posl[r];
+        if (pr < ns && pc >= ns)
+          v = f_in_lds ? f[pr * ldf + (pc - ns)] : f[(int64_t)pr * n2 + (pc - ns)];
+        else if (pr >= ns && pc < ns)
+          v = f_in_lds ? -f[pc * ldf + (pr - ns)] : -f[(int64_t)pc * n2 + (pr - ns)];
+      }
+      m[k][r] = v;
+    }
+  }
+  uint64_t done0 = 0, done1 = 0;   // pivoted indices (NE_MAX <= 128)
+  logabs = 0.0;
+  sgn = 1.0;
+  for (int step = 0; step < ne / 2; ++step) {
+    const int i = done0 != ~0ull ? __builtin_ctzll(~done0) : 64 + __builtin_ctzll(~done1);
+    double ri[KC], rj[KC];
+    double best = -1.0;
+    int bc = 1 << 30;
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      ri[k] = pick<double, NE_MAX, 0, NE_MAX>(m[k], i);
+      const int c = lane + 64 * k;
+      const bool piv = c < 64 ? ((done0 >> c) & 1) : ((done1 >> (c - 64)) & 1);
+      const double v = (c < ne && !piv && c != i) ? fabs(ri[k]) : -1.0;
+      if (v > best) {
+        best = v;
+        bc = c;
+      }
+    }
+    const double vmax = wave_max(best);
+    const int j = wave_min_i(best == vmax ? bc : (1 << 30));
+    if (!(vmax > 0.0) || j >= ne) return 1;   // singular
+    const int kj = j >> 6;
+    double xij = 0.0;
+#pragma unroll
+    for (int k = 0; k < KC; ++k)
+      if (k == kj) xij = ri[k];
+    const int xlo = __builtin_amdgcn_readlane(__double2loint(xij), j & 63);
+    const int xhi = __builtin_amdgcn_readlane(__double2hiint(xij), j & 63);
+    const double x = __hiloint2double(xhi, xlo);
+    logabs += log(fabs(x));
+    if (x < 0.0) sgn = -sgn;
+    if (lane == 0) {
+      ord[2 * step] = i;
+      ord[2 * step + 1] = j;
+    }
+    if (i < 64) done0 |= 1ull << i; else done1 |= 1ull << (i - 64);
+    if (j < 64) done0 |= 1ull << j; else done1 |= 1ull << (j - 64);
+    const double ix = 1.0 / x;
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      rj[k] = pick<double, NE_MAX, 0, NE_MAX>(m[k], j);
+      const int c = lane + 64 * k;
+      if (c < NE_MAX) {
+        sri[c] = ri[k];
+        srj[c] = rj[k];
+      }
+    }
+    wave_sync();
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const int c = lane + 64 * k;
+      const bool isI = c == i, isJ = c == j;
+      const double g = (isI || isJ) ? 0.0 : 1.0;
+      const double a = isI ? ix : (isJ ? 0.0 : ri[k] * ix);
+      const double b = isJ ? -ix : (isI ? 0.0 : -rj[k] * ix);
+      // rows i and j become P^-1 applied to the old rows
+      const double vi = isI ? 0.0 : (isJ ? -ix : -rj[k] * ix);
+      const double vj = isI ? ix : (isJ ? 0.0 : ri[k] * ix);
+#pragma unroll
+      for (int r0 = 0; r0 < NE_MAX; r0 += kChunk) {
+#pragma unroll
+        for (int r = r0; r < r0 + kChunk && r < NE_MAX; ++r) {
+          double nv = g * m[k][r] + a * srj[r] + b * sri[r];
+          nv = (r == i) ? vi : nv;
+          nv = (r == j) ? vj : nv;
+          m[k][r] = nv;
+        }
+        asm volatile("" ::: "memory");
+      }
+    }
+    wave_sync();
+  }
+  // sign of the pivot permutation (scalar cycle walk)
+  uint64_t vis0 = 0, vis1 = 0;
+  int parity = 0;
+  for (int b = 0; b < ne; ++b) {
+    const bool seen = b < 64 ? ((vis0 >> b) & 1) : ((vis1 >> (b - 64)) & 1);
+    if (seen) continue;
+    int c = b, len = 0;
+    while (true) {
+      const bool sc = c < 64 ? ((vis0 >> c) & 1) : ((vis1 >> (c - 64)) & 1);
+      if (sc) break;
+      if (c < 64) vis0 |= 1ull << c; else vis1 |= 1ull << (c - 64);
+      c = __builtin_amdgcn_readfirstlane(ord[c]);
+      ++len;
+    }
+    parity += len - 1;
+  }
+  if (parity & 1) sgn = -sgn;
+  return 0;
+}
+
+template <typename T, int NE_MAX, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* __restrict__ wlist,
+                                                        int cap, uint64_t seed, TraceRec* trace,
+                                                        int64_t trace_cap,
+                                                        const uint64_t* __restrict__ trace_base,
+                                                        const uint64_t* __restrict__ target,
+                                                        int32_t* __restrict__ needs_refresh, int R,
+                                                        int kref) {
+  constexpr int KC = (NE_MAX + 63) / 64;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int lane = threadIdx.x & 63;
+  const int wv = sgpr(threadIdx.x >> 6);
+  const int g0 = wlist[blockIdx.x * WPB];
+  const InstDev& I = P.inst[P.walker_inst[g0]];
+  const int ns = I.ns, ne = I.ne, n2 = 2 * ns, M = I.M, nup = I.nup;
+  const int ldf = ns + 1;
+
+  // shared pair-amplitude table f[i][j] = A[i][Ns + j]
+  T* fs = (T*)smem;
+  {
+    const T* A = table_ptr<T>(P, I.A_off);
+    for (int e = threadIdx.x; e < ns * ns; e += 64 * WPB) {
+      const int i = e / ns, j = e - (e / ns) * ns;
+      fs[i * ldf + j] = A[(int64_t)i * n2 + ns + j];
+    }
+  }
+  __syncthreads();   // the only workgroup barrier
+
+  const int gw = sgpr(wlist[blockIdx.x * WPB + wv]);
+  if (gw < 0) return;
+  const uint64_t n0 = P.cnt[gw];
+  const uint64_t tg = target[gw];
+  uint64_t todo = tg > n0 ? tg - n0 : 0;
+  if (todo > (uint64_t)cap) todo = (uint64_t)cap;
+  if (R > 0 && !kref) {
+    const uint64_t left = (uint64_t)R - n0 % (uint64_t)R;
+    if (todo > left) todo = left;
+  }
+  if (todo == 0) return;
+  const int n_prop = (int)todo;
+  const int64_t lw = gw - I.walker_off;
+
+  unsigned char* q = smem + reg_table_bytes(ns, sizeof(T)) +
+                     (size_t)wv * reg_walker_bytes(NE_MAX, ns, M, sizeof(T));
+  T* xn = (T*)q;
+  T* pv = xn + NE_MAX;
+  T* qv = pv + NE_MAX;
+  q += a16(3 * (size_t)NE_MAX * sizeof(T));
+  double* sri = (double*)q;          // refresh scratch: rows i and j of M
+  double* srj = sri + NE_MAX;
+  q += a16(2 * (size_t)NE_MAX * sizeof(double));
+  double* hs = (double*)q;
+  q += a16((size_t)ns * sizeof(double));
+  T* ths = (T*)q;
+  q += a16((size_t)M * sizeof(T));
+  int32_t* eidx = (int32_t*)q;      // 2ns
+  int32_t* emp = eidx + n2;         // 2ns
+  int32_t* posl = emp + n2;         // NE_MAX: configuration broadcast for the refresh
+  int32_t* ord = posl + NE_MAX;     // NE_MAX: pivot order of the refresh
+
+  int32_t* posg = P.pos + I.pos_off + lw * ne;
+  int32_t* empg = P.empty + I.empty_off + lw * n2;
+  double* hg = P.h + I.h_off + lw * ns;
+  double* thg = P.theta + I.theta_off + lw * M;
+  T* Yg = (T*)P.Y + I.Y_off + lw * ne * ne;
+
+  for (int v = lane; v < n2; v += 64) {
+    eidx[v] = -1;
+    emp[v] = empg[v];
+  }
+  for (int l = lane; l < ns; l += 64) hs[l] = hg[l];
+  for (int hh = lane; hh < M; hh += 64) ths[hh] = (T)thg[hh];
+  for (int c = lane; c < 3 * NE_MAX; c += 64) xn[c] = T(0);
+  int posr[KC];
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const int c = lane + 64 * k;
+    posr[k] = c < ne ? posg[c] : -1;
+  }
+  wave_sync();
+#pragma unroll
+  for (int k = 0; k < KC; ++k)
+    if (posr[k] >= 0) eidx[posr[k]] = lane + 64 * k;
+
+  T y[KC][NE_MAX];
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const int c = lane + 64 * k;
+#pragma unroll
+    for (int i = 0; i < NE_MAX; ++i) y[k][i] = (c < ne && i < ne) ? Yg[(int64_t)i * ne + c] : T(0);
+  }
+  wave_sync();
+
+  const double* V = P.V + I.V_off;
+  const double* G = P.G + I.site_off;
+  const T* raT = rbmT_ptr<T>(P) + I.rbm_a_off;                 // a (2Ns)
+  const T* WT = rbmT_ptr<T>(P) + I.rbm_W_off;                  // W^T [2Ns][M]
+  const uint64_t tb = trace ? trace_base[gw] : 0;
+  int64_t acc = 0;
+  int singular = 0;
+  double last_logpf = 0.0, last_sgn = 0.0;
+  bool refreshed = false;
+  const double* f64 = sizeof(T) == 8 ? (const double*)fs : P.A64 + I.A_off + ns;
+  const bool f64_lds = sizeof(T) == 8;
+  const double* rbT64 = P.rbmT64;
+
+  for (int it = 0; it < n_prop; ++it) {
+    const uint64_t n = n0 + (uint64_t)it;
+    do {
+    const uint4 r = draw(seed, n, (uint32_t)gw, 0u);
+    const int a = sgpr(scaled(r.x, ne));
+    const int sigma = a >= nup ? 1 : 0;
+    const int nemp = ns - (sigma ? I.ndn : nup);
+    if (nemp == 0) {
+      if (trace && lane == 0 && n - tb < (uint64_t)trace_cap) {
+        TraceRec rec;
+        rec.n = (int64_t)n; rec.walker = gw; rec.a = a; rec.i_new = -1; rec.accepted = 0;
+        rec.ratio = 0.0;
+        trace[(int64_t)gw * trace_cap + (int64_t)(n - tb)] = rec;
+      }
+      break;
+    }
+    const int kk_emp = sgpr(scaled(r.y, nemp));
+    const int site_new = sgpr(emp[sigma * ns + kk_emp]);
+    const int Inew = site_new + sigma * ns;
+    const int ka = a >> 6, la = a & 63;
+    int pa = posr[0];
+#pragma unroll
+    for (int k = 1; k < KC; ++k)
+      if (ka == k) pa = posr[k];
+    const int Iold = sgpr(__builtin_amdgcn_readlane(pa, la));
+    const int site_old = Iold - sigma * ns;
+
+    // correlator terms: scalar loads issued before the vector work
+    const int opp = (1 - sigma) * ns;
+    const double gnew = G[site_new], gold = G[site_old];
+    const double vio = V[(int64_t)site_old * ns + site_new];
+
+    T ya[KC], xc[KC];
+    double part = 0.0;
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      ya[k] = pick<T, NE_MAX, 0, NE_MAX>(y[k], a);
+      const int c = lane + 64 * k;
+      const int pb = posr[k];
+      T xb = T(0);
+      if (c < ne && c != a) {
+        if (sigma == 0) {
+          if (pb >= ns) xb = fs[site_new * ldf + (pb - ns)];
+        } else {
+          if (pb < ns) xb = -fs[pb * ldf + site_new];
+        }
+      }
+      xc[k] = xb;
+      if (c < NE_MAX) xn[c] = xb;
+      part += (double)(ya[k] * xb);
+    }
+    double rbm = 0.0;
+    if (M) {
+      for (int hh = lane; hh < M; hh += 64) {
+        const T d = T(2) * (WT[(int64_t)Inew * M + hh] - WT[(int64_t)Iold * M + hh]);
+        const T th = ths[hh];
+        rbm += (double)(log2cosh(th + d) - log2cosh(th));
+      }
+      rbm = wave_total(rbm);
+    }
+    const double r_pf = -wave_total(part);
+    double logc = gnew * (eidx[site_new + opp] >= 0 ? 1.0 : 0.0) -
+                  gold * (eidx[site_old + opp] >= 0 ? 1.0 : 0.0) + hs[site_new] - hs[site_old] -
+                  vio;
+    if (M) logc += 2.0 * ((double)raT[Inew] - (double)raT[Iold]) + rbm;
+    const double Rt = r_pf * exp(logc);
+    const double u = uniform53(r.z, r.w);
+    const int accept = sgpr(u < Rt * Rt ? 1 : 0);
+    if (trace && lane == 0 && n - tb < (uint64_t)trace_cap) {
+      TraceRec rec;
+      rec.n = (int64_t)n; rec.walker = gw; rec.a = a; rec.i_new = Inew; rec.accepted = accept;
+      rec.ratio = Rt;
+      trace[(int64_t)gw * trace_cap + (int64_t)(n - tb)] = rec;
+    }
+    if (!accept) break;
+    ++acc;
+    wave_sync();   // x' of every lane visible
+
+    // q_c = -sum_j Y[j][c] x'_j + delta_{c,a};  p_c = -Y[a][c]
+    T pc[KC], qc[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      T s = T(0);
+#pragma unroll
+      for (int j0 = 0; j0 < NE_MAX; j0 += kChunk) {
+#pragma unroll
+        for (int j = j0; j < j0 + kChunk && j < NE_MAX; ++j) s += y[k][j] * xn[j];
+        asm volatile("" ::: "memory");   // bound the number of broadcast loads in flight
+      }
+      const int c = lane + 64 * k;
+      qc[k] = (c == a ? T(1) : T(0)) - s;
+      pc[k] = -ya[k];
+      if (c < NE_MAX) {
+        pv[c] = pc[k];
+        qv[c] = qc[k];
+      }
+    }
+    wave_sync();
+    const T ir = T(1.0 / r_pf);
+#pragma unroll
+    for (int i0 = 0; i0 < NE_MAX; i0 += kChunk) {
+#pragma unroll
+      for (int k = 0; k < KC; ++k) {
+        const T qs = qc[k] * ir, ps = pc[k] * ir;
+#pragma unroll
+        for (int i = i0; i < i0 + kChunk && i < NE_MAX; ++i) y[k][i] += pv[i] * qs - qv[i] * ps;
+      }
+      asm volatile("" ::: "memory");
+    }
+    for (int l = lane; l < ns; l += 64)
+      hs[l] += V[(int64_t)site_new * ns + l] - V[(int64_t)site_old * ns + l];
+    for (int hh = lane; hh < M; hh += 64)
+      ths[hh] += T(2) * (WT[(int64_t)Inew * M + hh] - WT[(int64_t)Iold * M + hh]);
+#pragma unroll
+    for (int k = 0; k < KC; ++k)
+      if (ka == k && lane == la) posr[k] = Inew;
+    if (lane == 0) {
+      eidx[Iold] = -1;
+      eidx[Inew] = a;
+      emp[sigma * ns + kk_emp] = site_old;
+    }
+    wave_sync();
+    } while (false);
+
+    // periodic double-precision recomputation, inside the launch
+    if (kref && R > 0 && (n + 1) % (uint64_t)R == 0) {
+      double lp, sg;
+      if constexpr (sizeof(T) == 8) {
+        singular = reg_refresh<NE_MAX, KC>(y, posr, f64, ldf, f64_lds, n2, ns, ne, lane, posl,
+                                           sri, srj, ord, lp, sg);
+      } else {
+        double m[KC][NE_MAX];
+        singular = reg_refresh<NE_MAX, KC>(m, posr, f64, ldf, f64_lds, n2, ns, ne, lane, posl,
+                                           sri, srj, ord, lp, sg);
+#pragma unroll
+        for (int k = 0; k < KC; ++k)
+#pragma unroll
+          for (int r = 0; r < NE_MAX; ++r) y[k][r] = (T)m[k][r];
+      }
+      last_logpf = lp;
+      last_sgn = sg;
+      refreshed = true;
+      // Jastrow field and RBM angles from scratch
+      for (int l = lane; l < ns; l += 64) {
+        double sum = 0.0;
+        for (int mm = 0; mm < ns; ++mm)
+          sum += V[(int64_t)l * ns + mm] *
+                 (double)((eidx[mm] >= 0 ? 1 : 0) + (eidx[mm + ns] >= 0 ? 1 : 0) - 1);
+        hs[l] = sum;
+      }
+      for (int hh = lane; hh < M; hh += 64) {
+        double th = rbT64[I.rbm_b_off + hh];
+        for (int v = 0; v < n2; ++v)
+          th += rbT64[I.rbm_W_off + (int64_t)v * M + hh] * (eidx[v] >= 0 ? 1.0 : -1.0);
+        ths[hh] = (T)th;
+      }
+      wave_sync();
+      if (singular) break;
+    }
+  }
+
+  // write the walker back
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const int c = lane + 64 * k;
+    if (c < ne) {
+      posg[c] = posr[k];
+#pragma unroll
+      for (int i = 0; i < NE_MAX; ++i)
+        if (i < ne) Yg[(int64_t)i * ne + c] = y[k][i];
+    }
+  }
+  for (int v = lane; v < n2; v += 64) empg[v] = emp[v];
+  for (int l = lane; l < ns; l += 64) hg[l] = hs[l];
+  for (int hh = lane; hh < M; hh += 64) thg[hh] = (double)ths[hh];
+  if (lane == 0) {
+    const uint64_t n1 = n0 + (uint64_t)n_prop;
+    P.cnt[gw] = n1;
+    P.accepted[gw] += acc;
+    if (R > 0 && !kref && n1 % (uint64_t)R == 0) needs_refresh[gw] = 1;
+    if (refreshed) {
+      P.logpf[gw] = singular ? -INFINITY : last_logpf;
+      P.sgnpf[gw] = singular ? 0.0 : last_sgn;
+      P.status[gw] = singular;
+    }
+  }
+}
+
+template <typename T>
+bool launch_sweep_reg(const Pools& P, const int32_t* wlist, int n_groups, int ne_max, int max_ns,
+                      int max_M, int cap, uint64_t seed, TraceRec* trace, int64_t trace_cap,
+                      const uint64_t* trace_base, const uint64_t* target, int32_t* needs_refresh,
+                      int R, int kref, hipStream_t s) {
+  constexpr int WPB = 4;
+  if (n_groups <= 0 || cap <= 0) return true;
+  const size_t sh = sweep_reg_lds_bytes(ne_max, max_ns, max_M, sizeof(T), WPB);
+#define MVMC_REG(NEM)                                                                            \
+  do {                                                                                           \
+    if (sh > 65536)                                                                              \
+      (void)hipFuncSetAttribute((const void*)&k_sweep_reg<T, NEM, WPB>,                          \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);            \
+    hipLaunchKernelGGL((k_sweep_reg<T, NEM, WPB>), dim3(n_groups), dim3(64 * WPB), sh, s, P,     \
+                       wlist, cap, seed, trace, trace_cap, trace_base, target, needs_refresh, R, \
+                       kref);                                                                    \
+    return true;                                                                                 \
+  } while (0)
+  if (ne_max == 32) MVMC_REG(32);
+  if (ne_max == 64) MVMC_REG(64);
+#undef MVMC_REG
+  return false;
+}
+
+int sweep_reg_class(int ne, size_t tsize) {
+  (void)tsize;
+  if (ne <= 32) return 32;
+  if (ne <= 64) return 64;
+  return 0;
+}
+
+template bool launch_sweep_reg<double>(const Pools&, const int32_t*, int, int, int, int, int,
+                                       uint64_t, TraceRec*, int64_t, const uint64_t*,
+                                       const uint64_t*, int32_t*, int, int, hipStream_t);
+template bool launch_sweep_reg<float>(const Pools&, const int32_t*, int, int, int, int, int,
+                                      uint64_t, TraceRec*, int64_t, const uint64_t*,
+                                      const uint64_t*, int32_t*, int, int, hipStream_t);
+
+}  // namespace mvmc

@@ -60,17 +60,21 @@ def oracle_trajectories(inst, params, pos0: np.ndarray, gid0: int, n_prop: int, 
 
 
 def compare_trace(rec: np.ndarray, walkers, n_prop: int, seed: int, rtol: float = 1e-10,
-                  mixed: bool = False) -> dict:
+                  mixed: bool = False, floor: float = 1e-6) -> dict:
     """Compare GPU trace records with oracle traces.
 
-    FP64: every decision must match and ratios agree to rtol (relative to
-    max(|R|, 1e-6)).  Mixed: ratios agree to rtol; a differing decision is
-    allowed only when u lies within rtol of R^2, after which that chain is
-    no longer compared.
+    Ratio error is |R_gpu - R| / max(|R|, floor).  FP64: every decision
+    must match and the error stay below rtol.  Mixed (single-precision
+    inverse): the error stays below rtol with floor ~ 1e-2, because the dot
+    product of row a of X^-1 with the new row of X cancels for small R and
+    its single-precision error is absolute; a differing decision is allowed
+    only when u lies within the ratio error of R^2, after which that chain
+    is no longer compared.
     """
     n_cmp = 0
     worst = 0.0
     diverged = 0
+    errors = []
     for w, wk in enumerate(walkers):
         for k in range(n_prop):
             n, a, inew, R, acc = wk.trace[k]
@@ -79,8 +83,9 @@ def compare_trace(rec: np.ndarray, walkers, n_prop: int, seed: int, rtol: float 
             assert int(g["a"]) == a and int(g["i_new"]) == inew, (w, k, g, wk.trace[k])
             if inew < 0:
                 continue
-            err = abs(float(g["ratio"]) - R) / max(abs(R), 1e-6)
+            err = abs(float(g["ratio"]) - R) / max(abs(R), floor)
             worst = max(worst, err)
+            errors.append(err)
             assert err <= rtol, (w, k, float(g["ratio"]), R, err)
             n_cmp += 1
             if bool(g["accepted"]) != acc:
@@ -88,10 +93,11 @@ def compare_trace(rec: np.ndarray, walkers, n_prop: int, seed: int, rtol: float 
                     raise AssertionError(f"walker {w} proposal {k}: decision differs")
                 r = proposal_draw(seed, wk.gid, n)
                 u = uniform53(r[2], r[3])
-                assert abs(u - R * R) <= 4 * rtol * max(R * R, 1e-12), (w, k, u, R)
+                dR = abs(float(g["ratio"]) - R)
+                assert abs(u - R * R) <= 2.5 * dR * (abs(R) + dR) + 1e-15, (w, k, u, R)
                 diverged += 1
                 break
-    return {"compared": n_cmp, "worst_rel": worst, "diverged": diverged}
+    return {"compared": n_cmp, "worst_rel": worst, "diverged": diverged, "errors": errors}
 
 
 def oracle_measure(inst, m, pos):

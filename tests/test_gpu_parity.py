@@ -39,6 +39,8 @@ def _case(name):
         return square_case(12, 72, 2, full_f=False)
     if name == "sq6_rbm":
         return square_case(6, 16, 4, full_f=False, n_hidden=24)
+    if name == "sq8_half":
+        return square_case(8, 32, 6, full_f=False)
     inst = workload(name)["instances"][0]
     inst.n_walkers = 8
     return inst
@@ -67,17 +69,21 @@ def test_refresh_inverse_and_pfaffian(name):
 
 
 # ------------------------------------------------------- trajectory replay
-@pytest.mark.parametrize("name,sweeps,refresh", [
-    ("ring6", 20, 0), ("c1_ring8_fp64", 20, 7), ("sq4_sub2", 10, 0), ("ring6_rbm", 20, 5),
-    ("sq10_full", 2, 0), ("sq6_rbm", 4, 16), ("sq12_sub", 1, 50),
+# threads = 0 selects the register-resident sweep where N_e fits it (N_e <= 64);
+# 64/128/256 force the LDS-resident sweep with that many threads per walker.
+@pytest.mark.parametrize("name,sweeps,refresh,threads", [
+    ("ring6", 20, 0, 0), ("c1_ring8_fp64", 20, 7, 0), ("sq4_sub2", 10, 0, 0),
+    ("ring6_rbm", 20, 5, 0), ("sq8_half", 3, 0, 0), ("sq8_half", 3, 64, 0),
+    ("sq4_sub2", 10, 0, 64), ("sq8_half", 3, 0, 128), ("ring6_rbm", 20, 5, 256),
+    ("sq10_full", 2, 0, 0), ("sq6_rbm", 4, 16, 0), ("sq12_sub", 1, 50, 0),
 ])
-def test_trajectory_replay_fp64(name, sweeps, refresh):
+def test_trajectory_replay_fp64(name, sweeps, refresh, threads):
     inst = _case(name)
     pos0 = good_configs(inst, inst.params0, inst.n_walkers, 7)
     n_prop = sweeps * inst.n_elec
     log(f"[replay] {name}: Ne={inst.n_elec} W={inst.n_walkers} proposals={n_prop} "
-        f"refresh_every={refresh} seed={SEED}")
-    ctx = _ctx([inst], inst.params0, seed=SEED, refresh_every=refresh)
+        f"refresh_every={refresh} sweep_threads={threads} seed={SEED}")
+    ctx = _ctx([inst], inst.params0, seed=SEED, refresh_every=refresh, sweep_threads=threads)
     ctx.set_state(pos0.ravel(), np.zeros(inst.n_walkers, dtype=np.int64))
     ctx.enable_trace(n_prop)
     acc = ctx.sample(sweeps)
@@ -134,9 +140,14 @@ def test_sr_matrices_and_update(solver):
     p0 = ctx.params.cpu().numpy().copy()
     it = ctx.sr_update(dtau=0.05, eps_rel=1e-3, eps_abs=1e-6, solver=solver, cg_tol=1e-12,
                        cg_maxit=2000)
-    want = osr.sr_update(O, E, 0.05, 1e-3, 1e-6, solver=solver, cg_eps=1e-12)
+    want = osr.sr_update(O, E, 0.05, 1e-3, 1e-6, solver=solver, cg_eps=1e-12, cg_kmax=2000)
     d = ctx.dparams.cpu().numpy()
     log(f"  cg iterations gpu={it[0]} oracle={want['cg_iters']}")
+    if solver == "cg":
+        assert abs(int(it[0]) - want["cg_iters"]) <= max(3, want["cg_iters"] // 10)
+        # the solution satisfies the regularised system to the CG tolerance
+        res = want["S_reg"] @ (-d / 0.05) - want["g_reg"]
+        assert np.linalg.norm(res) <= 1e-10 * np.linalg.norm(want["g_reg"])
     assert np.allclose(d, want["dalpha"], rtol=1e-8, atol=1e-11 * np.max(np.abs(want["dalpha"])))
     assert np.allclose(ctx.params.cpu().numpy(), p0 + d, rtol=0, atol=1e-15)
     ctx.close()
@@ -155,10 +166,12 @@ def test_mixed_precision_ratios(name, sweeps):
     ctx.sample(sweeps)
     rec = ctx.trace_records()
     walkers, _ = oracle_trajectories(inst, inst.params0, pos0, 0, n_prop, SEED)
-    st = compare_trace(rec, walkers, n_prop, SEED, rtol=2e-4, mixed=True)
-    log(f"  mixed: compared {st['compared']}, worst rel err {st['worst_rel']:.2e}, "
-        f"diverged chains {st['diverged']}")
-    assert st["compared"] > 0.8 * n_prop * inst.n_walkers
+    st = compare_trace(rec, walkers, n_prop, SEED, rtol=2e-3, mixed=True, floor=1e-2)
+    errs = np.array(st["errors"])
+    log(f"  mixed: compared {st['compared']}, rel err median {np.median(errs):.2e} "
+        f"p99 {np.percentile(errs, 99):.2e} max {errs.max():.2e}, diverged chains {st['diverged']}")
+    assert st["compared"] > 0.5 * n_prop * inst.n_walkers
+    assert np.median(errs) < 2e-5
     ctx.close()
 
 
