@@ -123,8 +123,13 @@ def s_build_leg():
     N, npar = inst.n_walkers, inst.n_params
     flops = N * npar * (npar + 1)
     avg = ms[4] / max(calls[4], 1)
+    # the kernel runs 64x64 upper-triangle tiles, three bf16 MFMA passes each
+    nt = -(-npar // 64)
+    issued = 3 * 2 * (-(-N // 16) * 16) * 64 * 64 * nt * (nt + 1) // 2
     return {"shape": [N, npar], "ms": avg, "tflops": flops / (avg * 1e-3) / 1e12,
-            "algorithmic_flops": flops}
+            "algorithmic_flops": flops, "issued_mfma_tflops": issued / (avg * 1e-3) / 1e12,
+            "issued_frac_of_bf16_peak": issued / (avg * 1e-3) / 1e12 / BF16_PEAK_TFLOPS,
+            "note": "time of the S kernels only (centring and split excluded)"}
 
 
 def _oracle_worker(args):

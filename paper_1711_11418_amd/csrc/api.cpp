@@ -238,7 +238,8 @@ Plan make_plan(const mvmc_config& c) {
     I.chol_off = off_chol;
     if (c.build_s && c.solver == MVMC_SOLVE_CHOL) off_chol += (int64_t)I.np * I.np;
     I.split_off = off_split;
-    if (c.build_s && c.precision == MVMC_MIXED) off_split += 2 * I.rows * I.ldO;
+    const int64_t rows16 = (I.rows + 15) / 16 * 16;
+    if (c.build_s && c.precision == MVMC_MIXED) off_split += 2 * rows16 * I.ldO;
 
     SrInst& S = P.sr[k];
     std::memset(&S, 0, sizeof S);
@@ -251,6 +252,7 @@ Plan make_plan(const mvmc_config& c) {
     S.param_off = I.param_off;
     S.chol_off = I.chol_off;
     S.split_off = I.split_off;
+    S.split_rows = rows16;
     S.colpart_off = off_colpart;
     off_colpart += 3 * ((I.rows + kRowChunk - 1) / kRowChunk) * I.ldO;
     const int64_t ntile = (I.np + 63) / 64;
@@ -875,7 +877,7 @@ int mvmc_sample_sweeps(mvmc_ctx* c, int32_t n_sweeps, int64_t* h_accepted) {
     for (auto& b : c->sweep_b) {
       const int32_t* lst = reinterpret_cast<int32_t*>(c->ws + P.lists.off + b.list_off);
       if (b.reg) {
-        if (r > 0) continue;   // finished its whole target in the first round
+        if (r > 0) continue;   // refreshes inside the kernel; done in the first round
         const int cp = INT32_MAX;
         const bool ok =
             c->cfg.precision == MVMC_FP64

@@ -114,6 +114,16 @@ __device__ __forceinline__ uint4 draw(uint64_t seed, uint64_t n, uint32_t walker
                        (uint32_t)seed, (uint32_t)(seed >> 32));
 }
 
+// Same draw with the key words passed through an opaque scalar move, so a
+// caller inside a long loop recomputes the ten round keys instead of keeping
+// all of them live in scalar registers.
+__device__ __forceinline__ uint4 draw_lean(uint64_t seed, uint64_t n, uint32_t walker,
+                                           uint32_t tag) {
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  asm volatile("" : "+s"(k0), "+s"(k1));
+  return philox4x32_10(make_uint4((uint32_t)n, (uint32_t)(n >> 32), walker, tag), k0, k1);
+}
+
 // Multiply-shift map of a 32-bit word onto {0..n-1}.
 __device__ __forceinline__ int scaled(uint32_t r, int n) {
   return (int)(((uint64_t)r * (uint64_t)n) >> 32);

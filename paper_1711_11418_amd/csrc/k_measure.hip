@@ -19,6 +19,34 @@ namespace mvmc {
 
 namespace {
 constexpr int kMeasureThreads = 256;
+// Sum over the members of each parameter slot: a group of G lanes per slot,
+// lanes stride over the members, fixed-order shuffle reduction inside the
+// group (deterministic).  G is picked from the mean members per slot.
+template <int G, typename T, typename F>
+__device__ __forceinline__ void slot_sums(int nslot, const int32_t* __restrict__ ptr,
+                                          const int32_t* __restrict__ mem, F val,
+                                          T* __restrict__ out) {
+  const int lane_in = threadIdx.x & (G - 1);
+  const int grp = threadIdx.x / G, ngrp = blockDim.x / G;
+  for (int k = grp; k < nslot; k += ngrp) {
+    double s = 0.0;
+    for (int m = ptr[k] + lane_in; m < ptr[k + 1]; m += G) s += val(mem[m]);
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane_in == 0) out[k] = (T)s;
+  }
+}
+
+template <typename T, typename F>
+__device__ __forceinline__ void slot_sums_any(int nslot, int nmem, const int32_t* ptr,
+                                              const int32_t* mem, F val, T* out) {
+  const int avg = nslot > 0 ? (nmem + nslot - 1) / nslot : 0;
+  if (avg <= 2) slot_sums<1>(nslot, ptr, mem, val, out);
+  else if (avg <= 8) slot_sums<4>(nslot, ptr, mem, val, out);
+  else if (avg <= 32) slot_sums<16>(nslot, ptr, mem, val, out);
+  else slot_sums<64>(nslot, ptr, mem, val, out);
+}
+
 template <typename T> __device__ __forceinline__ const T* table_of(const Pools& P, int64_t off);
 template <> __device__ __forceinline__ const double* table_of<double>(const Pools& P, int64_t off) {
   return P.A64 + off;
@@ -140,39 +168,25 @@ __global__ __launch_bounds__(kMeasureThreads) void k_measure(Pools P,
 
   T* Orow = O + I.O_off + row * I.ldO;
   const int32_t* fptr = P.fm_ptr + I.fm_ptr_off;
-  const int32_t* fm = P.fm + I.fm_off;
-  for (int k = tid; k < I.nf; k += blockDim.x) {
-    double s = 0.0;
-    for (int m = fptr[k]; m < fptr[k + 1]; ++m) {
-      const int pk = fm[m];
-      const int ea = eidx[pk / ns], eb = eidx[pk % ns + ns];
-      if (ea >= 0 && eb >= 0) s -= (double)Y[ea * ldy + eb];
-    }
-    Orow[k] = (T)s;
-  }
+  slot_sums_any(I.nf, fptr[I.nf], fptr, P.fm + I.fm_off,
+                [&](int pk) -> double {
+                  const int ea = eidx[pk / ns], eb = eidx[pk % ns + ns];
+                  return (ea >= 0 && eb >= 0) ? -(double)Y[ea * ldy + eb] : 0.0;
+                },
+                Orow);
   const int32_t* gptr = P.gm_ptr + I.gm_ptr_off;
-  const int32_t* gm = P.gm + I.gm_off;
-  for (int k = tid; k < I.ng; k += blockDim.x) {
-    double s = 0.0;
-    for (int m = gptr[k]; m < gptr[k + 1]; ++m) {
-      const int i = gm[m];
-      if (eidx[i] >= 0 && eidx[i + ns] >= 0) s += 1.0;
-    }
-    Orow[I.nf + k] = (T)s;
-  }
+  slot_sums_any(I.ng, gptr[I.ng], gptr, P.gm + I.gm_off,
+                [&](int i) -> double { return (eidx[i] >= 0 && eidx[i + ns] >= 0) ? 1.0 : 0.0; },
+                Orow + I.nf);
   const int32_t* vptr = P.vm_ptr + I.vm_ptr_off;
-  const int32_t* vm = P.vm + I.vm_off;
-  for (int k = tid; k < I.nv; k += blockDim.x) {
-    double s = 0.0;
-    for (int m = vptr[k]; m < vptr[k + 1]; ++m) {
-      const int pk = vm[m];
-      const int i = pk / ns, j = pk % ns;
-      const int mi = (eidx[i] >= 0) + (eidx[i + ns] >= 0) - 1;
-      const int mj = (eidx[j] >= 0) + (eidx[j + ns] >= 0) - 1;
-      s += (double)(mi * mj);
-    }
-    Orow[I.nf + I.ng + k] = (T)s;
-  }
+  slot_sums_any(I.nv, vptr[I.nv], vptr, P.vm + I.vm_off,
+                [&](int pk) -> double {
+                  const int i = pk / ns, j = pk % ns;
+                  const int mi = (eidx[i] >= 0) + (eidx[i + ns] >= 0) - 1;
+                  const int mj = (eidx[j] >= 0) + (eidx[j + ns] >= 0) - 1;
+                  return (double)(mi * mj);
+                },
+                Orow + I.nf + I.ng);
   if (M) {
     T* Oa = Orow + I.nf + I.ng + I.nv;
     T* Ob = Oa + n2;

@@ -61,7 +61,7 @@ __global__ void k_colpass(SrArgs A, T* __restrict__ O, int mode, uint16_t* __res
     const double eb = A.scal[blockIdx.z * kScal + kEbar];
     const double* e = A.eloc + I.eloc_off;
     uint16_t* hi = split ? split + I.split_off : nullptr;
-    uint16_t* lo = split ? split + I.split_off + I.rows * ld : nullptr;
+    uint16_t* lo = split ? split + I.split_off + I.split_rows * ld : nullptr;
     double s2 = 0.0, sg = 0.0;
     for (int64_t m = r0; m < r1; ++m) {
       const T c = (T)((double)Ob[m * ld + k] - ob);
@@ -71,8 +71,9 @@ __global__ void k_colpass(SrArgs A, T* __restrict__ O, int mode, uint16_t* __res
       sg += cd * (e[m] - eb);
       if (hi) {
         const uint16_t h = f32_to_bf16((float)c);
-        hi[m * ld + k] = h;
-        lo[m * ld + k] = f32_to_bf16((float)c - bf16_to_f32(h));
+        const int64_t si = split_index(m, k, ld);
+        hi[si] = h;
+        lo[si] = f32_to_bf16((float)c - bf16_to_f32(h));
       }
     }
     part[(blockIdx.y * 3 + 1) * ld + k] = s2;

@@ -127,6 +127,12 @@ template <> __device__ __forceinline__ const double* rbmT_ptr<double>(const Pool
 template <> __device__ __forceinline__ const float* rbmT_ptr<float>(const Pools& P) { return P.rbmT32; }
 
 __device__ __forceinline__ int sgpr(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// Uniform value the optimiser may not look through (keeps branch-tree tests
+// as 32-bit scalar compares).
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
 
 }  // namespace
 
@@ -135,6 +141,13 @@ size_t sweep_reg_lds_bytes(int ne_max, int ns, int M, size_t tsize, int wpb) {
 }
 
 constexpr int kChunk = 8;   // rows per group of broadcast loads in the update
+
+// With the in-register refresh on, register-tier walkers recompute X^-1 in
+// double inside the launch at every multiple of refresh_every instead of
+// stopping for the refresh kernel.
+#ifndef MVMC_SWEEP_INKERNEL_REFRESH
+#define MVMC_SWEEP_INKERNEL_REFRESH 1
+#endif
 
 // Double-precision recomputation of X^-1 for the walker of this wavefront,
 // in registers (lane c keeps column c).  Same in-place skew Gauss-Jordan as
@@ -353,10 +366,13 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
 
   T y[KC][NE_MAX];
 #pragma unroll
-  for (int k = 0; k < KC; ++k) {
-    const int c = lane + 64 * k;
+  for (int i = 0; i < NE_MAX; ++i) {
+    const T* row = Yg + (size_t)(i < ne ? i : 0) * ne;   // uniform row pointer
 #pragma unroll
-    for (int i = 0; i < NE_MAX; ++i) y[k][i] = (c < ne && i < ne) ? Yg[(int64_t)i * ne + c] : T(0);
+    for (int k = 0; k < KC; ++k) {
+      const int c = lane + 64 * k;
+      y[k][i] = (c < ne && i < ne) ? row[c] : T(0);
+    }
   }
   wave_sync();
 
@@ -373,11 +389,12 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
   const bool f64_lds = sizeof(T) == 8;
   const double* rbT64 = P.rbmT64;
 
+  int to_refresh = R > 0 ? R - (int)(n0 % (uint64_t)R) : 0;   // proposals until the next refresh
   for (int it = 0; it < n_prop; ++it) {
     const uint64_t n = n0 + (uint64_t)it;
     do {
-    const uint4 r = draw(seed, n, (uint32_t)gw, 0u);
-    const int a = sgpr(scaled(r.x, ne));
+    const uint4 r = draw_lean(seed, n, (uint32_t)gw, 0u);
+    const int a = opaque(sgpr(scaled(r.x, ne)));
     const int sigma = a >= nup ? 1 : 0;
     const int nemp = ns - (sigma ? I.ndn : nup);
     if (nemp == 0) {
@@ -498,7 +515,9 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
     } while (false);
 
     // periodic double-precision recomputation, inside the launch
-    if (kref && R > 0 && (n + 1) % (uint64_t)R == 0) {
+#if MVMC_SWEEP_INKERNEL_REFRESH
+    if (R > 0 && --to_refresh == 0) to_refresh = R;
+    if (kref && R > 0 && to_refresh == R) {
       double lp, sg;
       if constexpr (sizeof(T) == 8) {
         singular = reg_refresh<NE_MAX, KC>(y, posr, f64, ldf, f64_lds, n2, ns, ne, lane, posl,
@@ -532,17 +551,24 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
       wave_sync();
       if (singular) break;
     }
+#endif
   }
 
   // write the walker back
 #pragma unroll
   for (int k = 0; k < KC; ++k) {
     const int c = lane + 64 * k;
-    if (c < ne) {
-      posg[c] = posr[k];
+    if (c < ne) posg[c] = posr[k];
+  }
 #pragma unroll
-      for (int i = 0; i < NE_MAX; ++i)
-        if (i < ne) Yg[(int64_t)i * ne + c] = y[k][i];
+  for (int i = 0; i < NE_MAX; ++i) {
+    if (i < ne) {
+      T* row = Yg + (size_t)i * ne;
+#pragma unroll
+      for (int k = 0; k < KC; ++k) {
+        const int c = lane + 64 * k;
+        if (c < ne) row[c] = y[k][i];
+      }
     }
   }
   for (int v = lane; v < n2; v += 64) empg[v] = emp[v];

@@ -1,14 +1,21 @@
-// Split-bf16 S build for the mixed-precision path.
+// Split-bf16 S build on the matrix cores (gfx950 v_mfma_f32_32x32x16_bf16).
 //
 // The centred single-precision O~ is stored as hi = bf16(O~) and
-// lo = bf16(O~ - hi); S = O~^T O~ / N is accumulated in FP32 as
-// hi^T hi + hi^T lo + lo^T hi (the lo^T lo term is below FP32 resolution).
+// lo = bf16(O~ - hi) in a k-blocked layout (split_index in sr.h); S = O~^T O~ / N
+// is accumulated in FP32 as hi^T hi + hi^T lo + lo^T hi (the lo^T lo term is
+// below single-precision resolution).  One wavefront computes a 64 x 64 tile
+// of the upper triangle as 2 x 2 blocks of 32 x 32 MFMA accumulators; the
+// contraction runs over the samples, 16 per MFMA.
 #include "sr.h"
 
 namespace mvmc {
 
 namespace {
-constexpr int kT = 64, kK = 32;
+constexpr int kT = 64;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ void tile_index(int t, int nt, int& ti, int& tj) {
   int row = 0, start = 0;
@@ -19,79 +26,116 @@ __device__ __forceinline__ void tile_index(int t, int nt, int& ti, int& tj) {
   ti = row;
   tj = row + (t - start);
 }
+
+// Eight consecutive samples of one parameter (zero beyond the used rows).
+__device__ __forceinline__ bf16x8 load8(const uint16_t* __restrict__ base, int64_t kg, int64_t p,
+                                        int64_t ld, bool ok, int valid) {
+  u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (ok) {
+    v = *reinterpret_cast<const u16x8*>(base + (kg * ld + p) * 8);
+    if (valid < 8) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        if (e >= valid) v[e] = 0;
+    }
+  }
+  return __builtin_bit_cast(bf16x8, v);
+}
 }  // namespace
 
-__global__ __launch_bounds__(256) void k_syrk_split_vec(SrArgs A, const uint16_t* __restrict__ split) {
+__global__ __launch_bounds__(64) void k_syrk_mfma(SrArgs A, const uint16_t* __restrict__ split,
+                                                  float* __restrict__ S) {
   const SrInst& I = A.inst[blockIdx.z];
   const int nt = (int)ceil_div<int64_t>(I.np, kT);
   const int ntiles = nt * (nt + 1) / 2;
   if ((int)blockIdx.x >= ntiles || (int)blockIdx.y >= I.ksplit) return;
   int ti, tj;
   tile_index(blockIdx.x, nt, ti, tj);
-  const int64_t chunk = ceil_div<int64_t>(ceil_div<int64_t>(I.rows, I.ksplit), kK) * kK;
-  const int64_t r0 = (int64_t)blockIdx.y * chunk;
-  const int64_t r1 = r0 + chunk < I.rows ? r0 + chunk : I.rows;
-  __shared__ float Ah[kK][kT + 1], Al[kK][kT + 1], Bh[kK][kT + 1], Bl[kK][kT + 1];
-  const int64_t ld = I.ldO;
+  const int64_t ld = I.ldO, np = I.np, rows = I.rows;
+  const int64_t chunk = ceil_div<int64_t>(ceil_div<int64_t>(rows, I.ksplit), 16) * 16;
+  const int64_t k0 = (int64_t)blockIdx.y * chunk;
+  const int64_t k1 = k0 + chunk < rows ? k0 + chunk : rows;
   const uint16_t* hi = split + I.split_off;
-  const uint16_t* lo = hi + I.rows * ld;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  float acc[4][4] = {};
-  const int ca = ti * kT, cb = tj * kT;
-  for (int64_t m0 = r0; m0 < r1; m0 += kK) {
-    for (int e = threadIdx.x; e < kK * kT; e += 256) {
-      const int kk = e / kT, c = e % kT;
-      const int64_t m = m0 + kk;
-      const bool ok = m < r1;
-      const bool oa = ok && ca + c < I.np, ob = ok && cb + c < I.np;
-      Ah[kk][c] = oa ? bf16_to_f32(hi[m * ld + ca + c]) : 0.f;
-      Al[kk][c] = oa ? bf16_to_f32(lo[m * ld + ca + c]) : 0.f;
-      Bh[kk][c] = ob ? bf16_to_f32(hi[m * ld + cb + c]) : 0.f;
-      Bl[kk][c] = ob ? bf16_to_f32(lo[m * ld + cb + c]) : 0.f;
-    }
-    __syncthreads();
-    for (int kk = 0; kk < kK; ++kk) {
-      float ah[4], al[4], bh[4], bl[4];
+  const uint16_t* lo = hi + I.split_rows * ld;
+  const int lane = threadIdx.x, m = lane & 31, kh = lane >> 5;
+  const int64_t p0 = (int64_t)ti * kT, q0 = (int64_t)tj * kT;
+  f32x16 acc[2][2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        ah[i] = Ah[kk][ty * 4 + i];
-        al[i] = Al[kk][ty * 4 + i];
-        bh[i] = Bh[kk][tx * 4 + i];
-        bl[i] = Bl[kk][tx * 4 + i];
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  for (int64_t k = k0; k < k1; k += 16) {
+    const int64_t kg = (k >> 3) + kh;                 // this lane's group of 8 samples
+    const int64_t left = rows - kg * 8;
+    const int valid = left >= 8 ? 8 : (left > 0 ? (int)left : 0);
+    bf16x8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int64_t p = p0 + 32 * i + m, q = q0 + 32 * i + m;
+      ah[i] = load8(hi, kg, p, ld, p < np && valid > 0, valid);
+      al[i] = load8(lo, kg, p, ld, p < np && valid > 0, valid);
+      bh[i] = load8(hi, kg, q, ld, q < np && valid > 0, valid);
+      bl[i] = load8(lo, kg, q, ld, q < np && valid > 0, valid);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
       }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += ah[i] * bh[j] + (ah[i] * bl[j] + al[i] * bh[j]);
-    }
-    __syncthreads();
   }
+  // accumulator r of lane l holds D[row][col], col = l % 32,
+  // row = 8 (r / 4) + 4 (l / 32) + r % 4
+  const bool direct = I.ksplit == 1;
+  const float invN = (float)(1.0 / (double)rows);
   double* part = A.syrkpart + I.syrkpart_off + ((int64_t)blockIdx.y * ntiles + blockIdx.x) * kT * kT;
+  float* Sb = S + I.S_off;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) part[(ty * 4 + i) * kT + tx * 4 + j] = (double)acc[i][j];
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int lr = 32 * i + 8 * (r >> 2) + 4 * kh + (r & 3);
+        const int lc = 32 * j + m;
+        const float v = acc[i][j][r];
+        if (direct) {
+          const int64_t row = p0 + lr, col = q0 + lc;
+          if (row < np && col < np && (ti != tj || row <= col)) {
+            Sb[row * np + col] = v * invN;
+            Sb[col * np + row] = v * invN;
+          }
+        } else {
+          part[lr * kT + lc] = (double)v;
+        }
+      }
 }
 
 __global__ void k_syrk_split_reduce(SrArgs A, float* __restrict__ S) {
   const SrInst& I = A.inst[blockIdx.y];
+  if (I.ksplit == 1) return;   // written directly by the tile kernel
   const int nt = (int)ceil_div<int64_t>(I.np, kT);
   const int ntiles = nt * (nt + 1) / 2;
   if ((int)blockIdx.x >= ntiles) return;
   int ti, tj;
   tile_index(blockIdx.x, nt, ti, tj);
   const double* part = A.syrkpart + I.syrkpart_off;
-  const float invN = (float)(1.0 / (double)I.rows);
+  const double invN = 1.0 / (double)I.rows;
   float* Sb = S + I.S_off;
   for (int e = threadIdx.x; e < kT * kT; e += blockDim.x) {
     const int i = e / kT, j = e % kT;
     const int64_t r = (int64_t)ti * kT + i, c = (int64_t)tj * kT + j;
-    if (r >= I.np || c >= I.np) continue;
-    float s = 0.f;
-    for (int ks = 0; ks < I.ksplit; ++ks) s += (float)part[((int64_t)ks * ntiles + blockIdx.x) * kT * kT + e];
-    s *= invN;
-    Sb[r * I.np + c] = s;
-    Sb[c * I.np + r] = s;
+    if (r >= I.np || c >= I.np || (ti == tj && r > c)) continue;
+    double s = 0.0;
+    for (int ks = 0; ks < I.ksplit; ++ks) s += part[((int64_t)ks * ntiles + blockIdx.x) * kT * kT + e];
+    const float v = (float)(s * invN);
+    Sb[r * I.np + c] = v;
+    Sb[c * I.np + r] = v;
   }
 }
 
@@ -99,7 +143,7 @@ void sr_syrk_bf16x3(const SrArgs& A, const uint16_t* split, float* S, int n_inst
                     int max_ksplit, hipStream_t s) {
   const int nt = (int)ceil_div<int64_t>(max_np, kT);
   const int ntiles = nt * (nt + 1) / 2;
-  hipLaunchKernelGGL(k_syrk_split_vec, dim3(ntiles, max_ksplit, n_inst), dim3(256), 0, s, A, split);
+  hipLaunchKernelGGL(k_syrk_mfma, dim3(ntiles, max_ksplit, n_inst), dim3(64), 0, s, A, split, S);
   hipLaunchKernelGGL(k_syrk_split_reduce, dim3(ntiles, n_inst), dim3(256), 0, s, A, S);
 }
 

@@ -17,8 +17,16 @@ struct SrInst {
   int64_t np, ldO, rows;          // parameters, O stride, samples used in this SR step
   int64_t O_off, S_off, eloc_off, param_off;
   int64_t colpart_off, syrkpart_off, chol_off, split_off;
+  int64_t split_rows;             // rows allocated per bf16 array (multiple of 16)
   int32_t ksplit, pad;
 };
+
+// bf16 split layout: element (sample m, parameter k) of the hi (or lo) array
+// at ((m / 8) * ldO + k) * 8 + m % 8, so the eight samples of one k-group of a
+// parameter are one 16-byte vector (an MFMA operand).
+__host__ __device__ inline int64_t split_index(int64_t m, int64_t k, int64_t ld) {
+  return ((m >> 3) * ld + k) * 8 + (m & 7);
+}
 
 struct SrArgs {
   const SrInst* inst;
