@@ -36,7 +36,11 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", sweep_threads=0):
+def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", sweep_threads=0,
+                    use_graph=True):
+    """Time whole SR steps.  With use_graph the sampling part of a step (the
+    sweeps and the measurement after each of them) is captured once into a
+    HIP graph and replayed; the SR build and update run eagerly."""
     import numpy as np
     import torch
 
@@ -44,39 +48,56 @@ def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", 
 
     inst = wl["instances"][0]
     sweeps = wl["sweeps"]
-    ctx = MVMC([inst], inst.params0, precision=precision, refresh_every=refresh_every,
-               seed=wl["sampler_seed"], n_slots=sweeps, solver=solver, build_s=True,
-               sweep_threads=sweep_threads)
-    ctx.sample(wl["warmup"])
-    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        ctx = MVMC([inst], inst.params0, precision=precision, refresh_every=refresh_every,
+                   seed=wl["sampler_seed"], n_slots=sweeps, solver=solver, build_s=True,
+                   sweep_threads=sweep_threads, stream=side)
+        ctx.sample(wl["warmup"])
+        torch.cuda.synchronize()
 
-    def step(profile=False):
-        acc = 0
-        for s in range(sweeps):
-            if profile:
-                acc += int(ctx.sample(1)[0])
+        def sampling(profile=False):
+            acc = 0
+            for s in range(sweeps):
+                if profile:
+                    acc += int(ctx.sample(1)[0])
+                else:
+                    ctx.sample_async(1)
+                ctx.measure(s)
+            return acc
+
+        def sr():
+            E, V = ctx.build_sr(sweeps)
+            ctx.sr_update(dtau=wl["dtau"], eps_rel=wl["eps_rel"], eps_abs=wl["eps_abs"],
+                          solver=solver)
+            return float(E[0])
+
+        for _ in range(warmup):
+            sampling()
+            sr()
+        graph = None
+        if use_graph:
+            torch.cuda.synchronize()
+            graph = ctx.capture_sampling(1, range(sweeps))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        energies = []
+        for _ in range(steps):
+            if graph is not None:
+                graph.replay()
             else:
-                ctx.sample_async(1)
-            ctx.measure(s)
-        E, V = ctx.build_sr(sweeps)
-        ctx.sr_update(dtau=wl["dtau"], eps_rel=wl["eps_rel"], eps_abs=wl["eps_abs"], solver=solver)
-        return acc, float(E[0])
-
-    for _ in range(warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    energies = []
-    for _ in range(steps):
-        energies.append(step()[1])
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    # one more step with HIP events around every kernel group, for the roofline
-    ctx.sample(0)          # read and clear the accepted counters
-    ctx.timing(True)
-    accepted, _ = step(profile=True)
-    ms, calls = ctx.timing(False)
-    ctx.close()
+                sampling()
+            energies.append(sr())
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        # one more step, eager, with HIP events around every kernel group
+        ctx.sample(0)          # read and clear the accepted counters
+        ctx.timing(True)
+        accepted = sampling(profile=True)
+        sr()
+        ms, calls = ctx.timing(False)
+        torch.cuda.synchronize()
+        ctx.close()
     W, ne, npar = inst.n_walkers, inst.n_elec, inst.n_params
     proposals = steps * sweeps * W * ne
     return {
@@ -84,7 +105,7 @@ def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", 
         "ms_per_step": 1e3 * dt / steps, "energies": energies,
         "accept_ratio": accepted / (sweeps * W * ne), "kernel_ms": ms.tolist(),
         "kernel_calls": calls.tolist(), "W": W, "ne": ne, "np": npar, "sweeps": sweeps,
-        "N": sweeps * W,
+        "N": sweeps * W, "graph": graph is not None,
     }
 
 
@@ -186,6 +207,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--skip-legs", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="launch the sampling eagerly")
     ap.add_argument("--sweep-threads", type=int, default=0,
                     help="0: register-resident sweep where it fits; 64/128/256: LDS sweep")
     a = ap.parse_args()
@@ -201,7 +223,7 @@ def main():
     log(f"[bench] c2_sq8_fp64 fp64: W=1024 sweeps/step={wl['sweeps']} steps={a.steps} "
         f"warmup={a.warmup}")
     r = run_sr_workload(wl, "fp64", a.steps, a.warmup, wl["refresh_every"],
-                        sweep_threads=a.sweep_threads)
+                        sweep_threads=a.sweep_threads, use_graph=not a.no_graph)
     avg_ms, bytes_, flops = sweep_roofline(r, 8)
     achieved = bytes_ / (avg_ms * 1e-3) / 1e9
     s_ms = r["kernel_ms"][4] / max(r["kernel_calls"][4], 1)
@@ -214,7 +236,8 @@ def main():
         "config": {"workload": "c2_sq8_fp64: 8x8 Hubbard U=4, Ne=64, Np=271, 1024 walkers x "
                                "200 sweeps + SR (Cholesky) per step",
                    "walkers": r["W"], "n_elec": r["ne"], "n_params": r["np"],
-                   "sweeps_per_step": r["sweeps"], "samples_per_step": r["N"]},
+                   "sweeps_per_step": r["sweeps"], "samples_per_step": r["N"],
+                   "sampling_in_hip_graph": r["graph"]},
         "accepted_per_s": r["rate"] * r["accept_ratio"],
         "accept_ratio": r["accept_ratio"],
         "s_build": {"tflops": s_flops / (s_ms * 1e-3) / 1e12, "ms": s_ms, "dtype": "f64",
@@ -231,7 +254,7 @@ def main():
     if not a.skip_legs:
         log("[bench] mixed-precision leg (same workload, fp32 sweeps, refresh every 32)")
         m = run_sr_workload(wl, "mixed", max(1, a.steps - 1), 1, 32,
-                            sweep_threads=a.sweep_threads)
+                            sweep_threads=a.sweep_threads, use_graph=not a.no_graph)
         out["mixed"] = {"value": m["rate"], "ms_per_step": m["ms_per_step"],
                         "speedup_vs_fp64": m["rate"] / r["rate"],
                         "energy_per_site": [e / 64 for e in m["energies"]],

@@ -149,7 +149,9 @@ int mvmc_init_wavefunction(mvmc_ctx **out, const mvmc_config *cfg, void *d_works
  * from a row of X^-1 and the correlator ratios, followed on acceptance by the
  * rank-2 update of X^-1.  h_accepted (may be NULL): [n_instances] accepted
  * proposals since the last call that returned them (the counters are then
- * cleared; with NULL they keep accumulating).
+ * cleared; with NULL they keep accumulating).  With h_accepted == NULL the
+ * call only enqueues kernels on the context's stream, so it can be captured
+ * into a HIP graph (as can mvmc_measure_energy_and_O).
  */
 int mvmc_sample_sweeps(mvmc_ctx *ctx, int32_t n_sweeps, int64_t *h_accepted);
 

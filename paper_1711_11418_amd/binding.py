@@ -170,7 +170,10 @@ class MVMC:
     """One library context plus the torch buffers it works on."""
 
     def __init__(self, instances, params, *, precision="fp64", refresh_every=0, seed=1,
-                 n_slots=1, solver="chol", build_s=True, sweep_threads=0, device="cuda:0"):
+                 n_slots=1, solver="chol", build_s=True, sweep_threads=0, device="cuda:0",
+                 stream=None):
+        """stream: torch.cuda.Stream for all of the context's work (default: the
+        current stream).  A non-default stream is needed for graph capture."""
         import torch
         self.torch = torch
         self.lib = load()
@@ -194,7 +197,7 @@ class MVMC:
                   if build_s else None)
         self.g = torch.zeros(int(self.sizes.n_params), dtype=torch.float64, device=dev)
         self.dparams = torch.zeros_like(self.g)
-        self.stream = torch.cuda.current_stream(dev)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
         self.ctx = C.c_void_p()
         rc = self.lib.mvmc_init_wavefunction(C.byref(self.ctx), C.byref(self.cfg),
                                              C.c_void_p(self._ws_ptr),
@@ -237,6 +240,16 @@ class MVMC:
 
     def sample_async(self, n_sweeps: int) -> None:
         self._check(self.lib.mvmc_sample_sweeps(self.ctx, int(n_sweeps), None))
+
+    def capture_sampling(self, n_sweeps: int, slots):
+        """HIP graph of [n_sweeps sweeps, measurement into slot s] for s in slots,
+        captured on the context's stream (which must not be the default stream)."""
+        g = self.torch.cuda.CUDAGraph()
+        with self.torch.cuda.graph(g, stream=self.stream):
+            for s in slots:
+                self.sample_async(n_sweeps)
+                self.measure(s)
+        return g
 
     def measure(self, slot: int) -> None:
         self._check(self.lib.mvmc_measure_energy_and_O(self.ctx, int(slot), self._p(self.eloc),

@@ -851,26 +851,20 @@ int mvmc_sample_sweeps(mvmc_ctx* c, int32_t n_sweeps, int64_t* h_accepted) {
     const uint64_t tot = (uint64_t)n_sweeps * P.inst[k].ne;
     target[k] = tot;
     if (R > 0 && !P.reg_class[k]) {
+      // enough refresh-aligned rounds for any starting phase (an extra round
+      // is an empty launch); independent of the host's view of the counters,
+      // so a captured graph stays valid on replay
       lds_refresh = true;
-      const uint64_t ph = c->cnt_host[k] % (uint64_t)R;
-      uint64_t rem = tot, r = 0, first = (uint64_t)R - ph;
-      if (rem <= first) r = 1;
-      else r = 1 + (rem - first + R - 1) / R;
-      rounds = std::max<int>(rounds, (int)r);
+      rounds = std::max<int>(rounds, (int)((tot + R - 1) / R) + 1);
     }
   }
   const int64_t cap = R > 0 ? R : (int64_t)1 << 62;
   uint64_t* tgt = reinterpret_cast<uint64_t*>(c->ws + P.target.off);
   int32_t* nr = reinterpret_cast<int32_t*>(c->ws + P.needs_refresh.off);
-  {
-    // target[w] = cnt[w] + n_sweeps * N_e(instance of w), computed on the host mirror
-    std::vector<uint64_t> t(P.W);
-    for (int k = 0; k < c->cfg.n_instances; ++k) {
-      const InstDev& I = P.inst[k];
-      for (int w = 0; w < I.W; ++w) t[I.walker_off + w] = c->cnt_host[k] + target[k];
-    }
-    HIPCHK(c, hipMemcpy(tgt, t.data(), 8 * P.W, hipMemcpyHostToDevice));
-  }
+  // per-walker end counters on the device: the call enqueues only kernels
+  // (graph-capturable) unless h_accepted asks for a read-back
+  launch_set_target(c->P, tgt, P.W, n_sweeps, c->stream);
+  LAUNCHCHK(c);
   const uint64_t* tb = reinterpret_cast<uint64_t*>(c->ws + P.trace_base.off);
   for (int r = 0; r < rounds; ++r) {
     const int id = tic(c, 0);

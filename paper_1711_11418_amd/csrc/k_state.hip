@@ -146,6 +146,19 @@ __global__ void k_build_empty(Pools P, const int32_t* __restrict__ wlist) {
   }
 }
 
+// target[w] = cnt[w] + n_sweeps * N_e(instance of w): the proposal index at
+// which this call's sweeps end for every walker.
+__global__ void k_set_target(Pools P, uint64_t* __restrict__ target, int64_t W, int n_sweeps) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= W) return;
+  target[w] = P.cnt[w] + (uint64_t)n_sweeps * (uint64_t)P.inst[P.walker_inst[w]].ne;
+}
+
+void launch_set_target(const Pools& P, uint64_t* target, int64_t W, int n_sweeps, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_target, dim3((unsigned)((W + 255) / 256)), dim3(256), 0, s, P, target,
+                     W, n_sweeps);
+}
+
 void launch_build_empty(const Pools& P, const int32_t* wlist, int n, int max_ns, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_build_empty, dim3(n), dim3(64), 2 * max_ns * sizeof(int32_t), s, P, wlist);

@@ -14,6 +14,7 @@ void launch_expand(const Pools& P, const InstDev* inst_host, int n_inst, const d
 void launch_draw_configs(const Pools& P, const int32_t* wlist, int n, uint64_t seed,
                          uint32_t attempt, hipStream_t s);
 void launch_build_empty(const Pools& P, const int32_t* wlist, int n, int max_ns, hipStream_t s);
+void launch_set_target(const Pools& P, uint64_t* target, int64_t W, int n_sweeps, hipStream_t s);
 
 // k_refresh.hip: full double-precision X^-1, log|Pf|, sign, Jastrow field and
 // RBM angles for the walkers in wlist.  T is the walker-matrix type.
