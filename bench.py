@@ -29,6 +29,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 BF16_PEAK_TFLOPS = 2500.0
+TRAFFIC_SUMMARY = "sweep_reg_fp64_c2_sq8_traffic.txt"
+TRAFFIC_SOURCES = ("k_sweep_reg.hip", "common.h")
 METRIC = "walker hop-updates/s + SR S-build TFLOP/s, batched/mixed vs plain FP64"
 
 
@@ -53,7 +55,8 @@ def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", 
         ctx = MVMC([inst], inst.params0, precision=precision, refresh_every=refresh_every,
                    seed=wl["sampler_seed"], n_slots=sweeps, solver=solver, build_s=True,
                    sweep_threads=sweep_threads, stream=side)
-        ctx.sample(wl["warmup"])
+        for _ in range(wl["warmup"]):   # one launch per sweep, as in the timed steps
+            ctx.sample_async(1)
         torch.cuda.synchronize()
 
         def sampling(profile=False):
@@ -107,6 +110,60 @@ def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", 
         "kernel_calls": calls.tolist(), "W": W, "ne": ne, "np": npar, "sweeps": sweeps,
         "N": sweeps * W, "graph": graph is not None,
     }
+
+
+def hbm_copy_probe(gib=1.0, reps=10):
+    """Attainable HBM bandwidth: torch's elementwise negation over a buffer of
+    `gib` GiB (read once, written once).  Under rocprofv3 --pmc its
+    FETCH_SIZE and WRITE_SIZE calibrate the counters against known bytes."""
+    import torch
+    n = int(gib * (1 << 30)) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.neg(src, out=dst)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return {"kernel": "torch.neg (elementwise)", "bytes_per_launch": 2 * n * 8, "ms": ms,
+            "gbs": 2 * n * 8 / (ms * 1e-3) / 1e9}
+
+
+def sweep_sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_1711_11418_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per sweep launch from the committed counter summary, scaled by
+    the calibration copy; None when the summary is missing or the sweep
+    kernel's sources changed after the counters were taken."""
+    path = os.path.join(ROOT, "profiles", TRAFFIC_SUMMARY)
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("sources_sha256_16") != sweep_sources_digest():
+        return None, "sweep sources changed since the counters were taken"
+    copy_bytes = float(kv["copy_bytes_per_launch"])
+    f_scale = copy_bytes / 2 / (float(kv["copy_fetch_kib"]) * 1024)
+    w_scale = copy_bytes / 2 / (float(kv["copy_write_kib"]) * 1024)
+    t = (float(kv["sweep_fetch_kib"]) * 1024 * f_scale
+         + float(kv["sweep_write_kib"]) * 1024 * w_scale)
+    return t, f"FETCH_SIZE+WRITE_SIZE per launch (median), scaled by the copy ({f_scale:.3f}, {w_scale:.3f})"
 
 
 def sweep_roofline(r, wsize):
@@ -219,6 +276,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     from mvmc_inputs import workload
 
+    copy = hbm_copy_probe()
+    log(f"[bench] HBM copy probe: {copy['gbs']:.0f} GB/s")
     wl = workload("c2_sq8_fp64")
     log(f"[bench] c2_sq8_fp64 fp64: W=1024 sweeps/step={wl['sweeps']} steps={a.steps} "
         f"warmup={a.warmup}")
@@ -228,6 +287,7 @@ def main():
     achieved = bytes_ / (avg_ms * 1e-3) / 1e9
     s_ms = r["kernel_ms"][4] / max(r["kernel_calls"][4], 1)
     s_flops = r["N"] * r["np"] * (r["np"] + 1)
+    traffic, traffic_note = measured_traffic() if a.sweep_threads == 0 else (None, "LDS sweep")
     out = {
         "metric": METRIC, "value": r["rate"], "unit": "hop-updates/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": r["ms_per_step"],
@@ -242,11 +302,18 @@ def main():
         "accept_ratio": r["accept_ratio"],
         "s_build": {"tflops": s_flops / (s_ms * 1e-3) / 1e12, "ms": s_ms, "dtype": "f64",
                     "shape": [r["N"], r["np"]]},
-        "roofline": {"kernel": "k_sweep<double>", "bound": "hbm", "achieved": achieved,
+        "roofline": {"kernel": ("k_sweep_reg<double, 64, 4>" if a.sweep_threads == 0
+                                else f"k_sweep<double, true, {a.sweep_threads}>"), "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "avg_launch_ms": avg_ms,
+                     "traffic": traffic, "traffic_note": traffic_note,
+                     "traffic_frac_of_alg": None if traffic is None else traffic / bytes_,
+                     "avg_launch_ms": avg_ms,
                      "alg_bytes_per_launch": bytes_, "alg_flops_per_launch": flops,
-                     "fp64_tflops": flops / (avg_ms * 1e-3) / 1e12},
+                     "fp64_tflops": flops / (avg_ms * 1e-3) / 1e12,
+                     "fp64_valu_frac": flops / (avg_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                     "residency": "Y stays in registers for the whole launch; the modelled "
+                                  "bytes are the method's per-proposal/per-accept streams"},
+        "measured_peaks": {"hbm_copy_gbs": copy["gbs"], "hbm_copy": copy},
         "kernel_ms_per_step": dict(zip(["sweep", "refresh", "measure", "sr_stats", "s_build",
                                         "sr_solve"], r["kernel_ms"])),
         "energy_per_site": [e / 64 for e in r["energies"]],
