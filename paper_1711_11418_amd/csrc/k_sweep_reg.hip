@@ -27,14 +27,17 @@ namespace {
 
 __host__ __device__ inline size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
 
-// LDS: [f table ns x (ns+1) | WPB x per-walker block]
+// LDS: [f table ns x (ns+1) in double | WPB x per-walker block]; the
+// single-precision sweep converts the gathered amplitudes, which equals
+// reading the single-precision copy of the table.
 __host__ __device__ inline size_t reg_table_bytes(int ns, size_t ts) {
-  return a16((size_t)ns * (ns + 1) * ts);
+  (void)ts;
+  return a16((size_t)ns * (ns + 1) * sizeof(double));
 }
 __host__ __device__ inline size_t reg_walker_bytes(int ne_max, int ns, int M, size_t ts) {
   return a16(3 * (size_t)ne_max * ts) + a16(2 * (size_t)ne_max * sizeof(double)) +
          a16((size_t)ns * sizeof(double)) + a16((size_t)M * ts) +
-         a16((size_t)(4 * ns + 2 * ne_max) * sizeof(int32_t));
+         a16((size_t)(4 * ns + ne_max) * sizeof(int32_t));
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -115,13 +118,6 @@ __device__ __forceinline__ int wave_min_i(int v) {
   return __builtin_amdgcn_readlane(v, 63);
 }
 
-template <typename T> __device__ __forceinline__ const T* table_ptr(const Pools& P, int64_t off);
-template <> __device__ __forceinline__ const double* table_ptr<double>(const Pools& P, int64_t off) {
-  return P.A64 + off;
-}
-template <> __device__ __forceinline__ const float* table_ptr<float>(const Pools& P, int64_t off) {
-  return P.A32 + off;
-}
 template <typename T> __device__ __forceinline__ const T* rbmT_ptr(const Pools& P);
 template <> __device__ __forceinline__ const double* rbmT_ptr<double>(const Pools& P) { return P.rbmT64; }
 template <> __device__ __forceinline__ const float* rbmT_ptr<float>(const Pools& P) { return P.rbmT32; }
@@ -149,45 +145,78 @@ constexpr int kChunk = 8;   // rows per group of broadcast loads in the update
 #define MVMC_SWEEP_INKERNEL_REFRESH 1
 #endif
 
+// Number of not yet pivoted indices strictly between i and j (i < j, both
+// below 128): moving j next to i in an order that keeps the remaining indices
+// ascending takes that many transpositions.
+__device__ __forceinline__ int unpivoted_between(uint64_t done0, uint64_t done1, int i, int j) {
+  int cnt = 0;
+#pragma unroll
+  for (int w = 0; w < 2; ++w) {
+    const int lo = max(i + 1 - 64 * w, 0), hi = min(j - 64 * w, 64);
+    if (lo < hi) {
+      const uint64_t upto = hi == 64 ? ~0ull : (1ull << hi) - 1;
+      const uint64_t bits = upto & ~((1ull << lo) - 1);
+      cnt += __builtin_popcountll(~(w ? done1 : done0) & bits);
+    }
+  }
+  return cnt;
+}
+
 // Double-precision recomputation of X^-1 for the walker of this wavefront,
-// in registers (lane c keeps column c).  Same in-place skew Gauss-Jordan as
-// the refresh kernel: pivot block K = {i, j}, x = M[i][j], and
+// in registers (lane c keeps column c, m[k][r] = M[r][c] for c = lane + 64k),
+// by the in-place skew Gauss-Jordan elimination of the refresh kernel: pivot
+// block K = {i, j}, x = M[i][j], P^-1 = [[0, -1/x], [1/x, 0]],
 //   M_Kc <- P^-1 M_Kc,  M_rK <- -M_rK P^-1,  M_rc <- M_rc - M_rK P^-1 M_Kc.
-// Every intermediate M is skew-symmetric, so column j of M is minus row j:
-// each lane reads rows i and j from its own registers (uniform index), and
-// the update of lane c's column is
-//   m[r] <- g_c m[r] + a_c M[j][r] + b_c M[i][r]
-// with (g, a, b) = (1, M[i][c]/x, -M[j][c]/x) off the pivot columns,
-// (0, 1/x, 0) for c = i and (0, 0, -1/x) for c = j; rows i and j are then
-// set to P^-1 applied to the old rows.  Pf(X) = sgn(pi) prod_k x_k.
+// With rows i and j broadcast through LDS (M[i][r] and M[j][r]), lane c
+// updates its whole column as
+//   m[r] <- g m[r] + a M[j][r] + b M[i][r],
+//   (g, a, b) = (1, M[i][c]/x, -M[j][c]/x) off the pivot columns,
+//               (0, 1/x, 0) for c = i,  (0, 0, -1/x) for c = j.
+// Broadcasting 1 in place of the diagonal entries M[i][i] and M[j][j] makes
+// that one formula also produce the new pivot rows (P^-1 M_Kc) on every
+// column; the only entries it gets wrong are the two diagonal ones of the
+// pivot columns, which no later step reads, and the diagonal of the skew
+// inverse is set to zero at the end.  i is the first index not yet pivoted
+// and j maximises |M[i][c]| over the rest (lowest c on ties), so
+// Pf(X) = sgn(pi) prod_k x_k with the sign of the pivot order counted as it
+// is built.
 template <int NE_MAX, int KC>
 __device__ __forceinline__ int reg_refresh(double (&m)[KC][NE_MAX], const int (&posr)[KC],
-                                           const double* __restrict__ f, int ldf, bool f_in_lds,  // f(i,j) at f[i*ldf+j] in LDS or f[i*n2+j] in HBM
-                                           int n2, int ns, int ne, int lane, int32_t* posl,
-                                           double* sri, double* srj, int32_t* ord,
-                                           double& logabs, double& sgn) {
+                                           const double* __restrict__ fs, int ldf, int ns, int ne,
+                                           int lane, int32_t* posl, double2* s2, double& logabs,
+                                           double& sgn) {
 #pragma unroll
   for (int k = 0; k < KC; ++k)
     if (lane + 64 * k < NE_MAX) posl[lane + 64 * k] = posr[k];
   wave_sync();
-  // X[r][c]: anti-parallel pairing, f(i, j) = A[i][Ns + j]
+  // X[r][c] = A[I_r][I_c]: f(site_r, site_c) when r is up and c down, minus
+  // f(site_c, site_r) when r is down and c up, zero between equal spins.
+  // The row bound goes through an opaque move so that the per-row compares
+  // stay here instead of being hoisted out of the caller's loop.
+  int nel = ne;
+  asm volatile("" : "+s"(nel));
 #pragma unroll
   for (int k = 0; k < KC; ++k) {
     const int c = lane + 64 * k, pc = posr[k];
+    const bool cup = pc < ns;
+    const int base = cup ? pc * ldf - ns : pc - ns;
+    const double w = cup ? -1.0 : 1.0;
 #pragma unroll
-    for (int r = 0; r < NE_MAX; ++r) {
-      double v = 0.0;
-      if (r < ne && c < ne) {
+    for (int r0 = 0; r0 < NE_MAX; r0 += kChunk) {
+#pragma unroll
+      for (int r = r0; r < r0 + kChunk && r < NE_MAX; ++r) {
         const int pr = posl[r];
-        if (pr < ns && pc >= ns)
-          v = f_in_lds ? f[pr * ldf + (pc - ns)] : f[(int64_t)pr * n2 + (pc - ns)];
-        else if (pr >= ns && pc < ns)
-          v = f_in_lds ? -f[pc * ldf + (pr - ns)] : -f[(int64_t)pc * n2 + (pr - ns)];
+        const bool rup = pr < ns;
+        const bool live = r < nel && c < ne && rup != cup;
+        const int addr = rup ? pr * ldf + base : base + pr;
+        const double t = fs[live ? addr : 0];
+        m[k][r] = live ? w * t : 0.0;
       }
-      m[k][r] = v;
+      asm volatile("" ::: "memory");
     }
   }
-  uint64_t done0 = 0, done1 = 0;   // pivoted indices (NE_MAX <= 128)
+  uint64_t done0 = 0, done1 = 0;
+  int parity = 0;
   logabs = 0.0;
   sgn = 1.0;
   for (int step = 0; step < ne / 2; ++step) {
@@ -219,10 +248,7 @@ __device__ __forceinline__ int reg_refresh(double (&m)[KC][NE_MAX], const int (&
     const double x = __hiloint2double(xhi, xlo);
     logabs += log(fabs(x));
     if (x < 0.0) sgn = -sgn;
-    if (lane == 0) {
-      ord[2 * step] = i;
-      ord[2 * step + 1] = j;
-    }
+    parity += unpivoted_between(done0, done1, i, j);
     if (i < 64) done0 |= 1ull << i; else done1 |= 1ull << (i - 64);
     if (j < 64) done0 |= 1ull << j; else done1 |= 1ull << (j - 64);
     const double ix = 1.0 / x;
@@ -230,10 +256,7 @@ __device__ __forceinline__ int reg_refresh(double (&m)[KC][NE_MAX], const int (&
     for (int k = 0; k < KC; ++k) {
       rj[k] = pick<double, NE_MAX, 0, NE_MAX>(m[k], j);
       const int c = lane + 64 * k;
-      if (c < NE_MAX) {
-        sri[c] = ri[k];
-        srj[c] = rj[k];
-      }
+      if (c < NE_MAX) s2[c] = make_double2(c == i ? 1.0 : ri[k], c == j ? 1.0 : rj[k]);
     }
     wave_sync();
 #pragma unroll
@@ -243,44 +266,32 @@ __device__ __forceinline__ int reg_refresh(double (&m)[KC][NE_MAX], const int (&
       const double g = (isI || isJ) ? 0.0 : 1.0;
       const double a = isI ? ix : (isJ ? 0.0 : ri[k] * ix);
       const double b = isJ ? -ix : (isI ? 0.0 : -rj[k] * ix);
-      // rows i and j become P^-1 applied to the old rows
-      const double vi = isI ? 0.0 : (isJ ? -ix : -rj[k] * ix);
-      const double vj = isI ? ix : (isJ ? 0.0 : ri[k] * ix);
 #pragma unroll
       for (int r0 = 0; r0 < NE_MAX; r0 += kChunk) {
 #pragma unroll
         for (int r = r0; r < r0 + kChunk && r < NE_MAX; ++r) {
-          double nv = g * m[k][r] + a * srj[r] + b * sri[r];
-          nv = (r == i) ? vi : nv;
-          nv = (r == j) ? vj : nv;
-          m[k][r] = nv;
+          const double2 t = s2[r];
+          m[k][r] = fma(a, t.y, fma(b, t.x, g * m[k][r]));
         }
         asm volatile("" ::: "memory");
       }
     }
     wave_sync();
   }
-  // sign of the pivot permutation (scalar cycle walk)
-  uint64_t vis0 = 0, vis1 = 0;
-  int parity = 0;
-  for (int b = 0; b < ne; ++b) {
-    const bool seen = b < 64 ? ((vis0 >> b) & 1) : ((vis1 >> (b - 64)) & 1);
-    if (seen) continue;
-    int c = b, len = 0;
-    while (true) {
-      const bool sc = c < 64 ? ((vis0 >> c) & 1) : ((vis1 >> (c - 64)) & 1);
-      if (sc) break;
-      if (c < 64) vis0 |= 1ull << c; else vis1 |= 1ull << (c - 64);
-      c = __builtin_amdgcn_readfirstlane(ord[c]);
-      ++len;
-    }
-    parity += len - 1;
+  // zero diagonal; the lane index goes through an opaque move so that the
+  // 64 compares are made here and not hoisted out of the caller's loop
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    int cl = lane + 64 * k;
+    asm volatile("" : "+v"(cl));
+#pragma unroll
+    for (int r = 0; r < NE_MAX; ++r) m[k][r] = r == cl ? 0.0 : m[k][r];
   }
   if (parity & 1) sgn = -sgn;
   return 0;
 }
 
-template <typename T, int NE_MAX, int WPB>
+template <typename T, int NE_MAX, int WPB, bool TRACE, bool RBM>
 __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* __restrict__ wlist,
                                                         int cap, uint64_t seed, TraceRec* trace,
                                                         int64_t trace_cap,
@@ -298,9 +309,9 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
   const int ldf = ns + 1;
 
   // shared pair-amplitude table f[i][j] = A[i][Ns + j]
-  T* fs = (T*)smem;
+  double* fs = (double*)smem;
   {
-    const T* A = table_ptr<T>(P, I.A_off);
+    const double* A = P.A64 + I.A_off;
     for (int e = threadIdx.x; e < ns * ns; e += 64 * WPB) {
       const int i = e / ns, j = e - (e / ns) * ns;
       fs[i * ldf + j] = A[(int64_t)i * n2 + ns + j];
@@ -328,8 +339,7 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
   T* pv = xn + NE_MAX;
   T* qv = pv + NE_MAX;
   q += a16(3 * (size_t)NE_MAX * sizeof(T));
-  double* sri = (double*)q;          // refresh scratch: rows i and j of M
-  double* srj = sri + NE_MAX;
+  double2* s2 = (double2*)q;         // refresh scratch: rows i and j of M
   q += a16(2 * (size_t)NE_MAX * sizeof(double));
   double* hs = (double*)q;
   q += a16((size_t)ns * sizeof(double));
@@ -338,7 +348,6 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
   int32_t* eidx = (int32_t*)q;      // 2ns
   int32_t* emp = eidx + n2;         // 2ns
   int32_t* posl = emp + n2;         // NE_MAX: configuration broadcast for the refresh
-  int32_t* ord = posl + NE_MAX;     // NE_MAX: pivot order of the refresh
 
   int32_t* posg = P.pos + I.pos_off + lw * ne;
   int32_t* empg = P.empty + I.empty_off + lw * n2;
@@ -380,25 +389,38 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
   const double* G = P.G + I.site_off;
   const T* raT = rbmT_ptr<T>(P) + I.rbm_a_off;                 // a (2Ns)
   const T* WT = rbmT_ptr<T>(P) + I.rbm_W_off;                  // W^T [2Ns][M]
-  const uint64_t tb = trace ? trace_base[gw] : 0;
+  const uint64_t tb = TRACE ? trace_base[gw] : 0;
   int64_t acc = 0;
   int singular = 0;
   double last_logpf = 0.0, last_sgn = 0.0;
   bool refreshed = false;
-  const double* f64 = sizeof(T) == 8 ? (const double*)fs : P.A64 + I.A_off + ns;
-  const bool f64_lds = sizeof(T) == 8;
   const double* rbT64 = P.rbmT64;
 
   int to_refresh = R > 0 ? R - (int)(n0 % (uint64_t)R) : 0;   // proposals until the next refresh
+  // Philox words of the next 64 proposals, one proposal per lane: the vector
+  // unit evaluates them together and each proposal reads its four words back
+  uint32_t d0 = 0, d1 = 0, d2 = 0, d3 = 0;
   for (int it = 0; it < n_prop; ++it) {
     const uint64_t n = n0 + (uint64_t)it;
+    const int slot = it & 63;
+    if (slot == 0) {
+      const uint4 d = draw(seed, n + (uint64_t)lane, (uint32_t)gw, 0u);
+      d0 = d.x;
+      d1 = d.y;
+      d2 = d.z;
+      d3 = d.w;
+    }
     do {
-    const uint4 r = draw_lean(seed, n, (uint32_t)gw, 0u);
+    uint4 r;
+    r.x = (uint32_t)__builtin_amdgcn_readlane((int)d0, slot);
+    r.y = (uint32_t)__builtin_amdgcn_readlane((int)d1, slot);
+    r.z = (uint32_t)__builtin_amdgcn_readlane((int)d2, slot);
+    r.w = (uint32_t)__builtin_amdgcn_readlane((int)d3, slot);
     const int a = opaque(sgpr(scaled(r.x, ne)));
     const int sigma = a >= nup ? 1 : 0;
     const int nemp = ns - (sigma ? I.ndn : nup);
     if (nemp == 0) {
-      if (trace && lane == 0 && n - tb < (uint64_t)trace_cap) {
+      if (TRACE && lane == 0 && n - tb < (uint64_t)trace_cap) {
         TraceRec rec;
         rec.n = (int64_t)n; rec.walker = gw; rec.a = a; rec.i_new = -1; rec.accepted = 0;
         rec.ratio = 0.0;
@@ -432,9 +454,9 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
       T xb = T(0);
       if (c < ne && c != a) {
         if (sigma == 0) {
-          if (pb >= ns) xb = fs[site_new * ldf + (pb - ns)];
+          if (pb >= ns) xb = (T)fs[site_new * ldf + (pb - ns)];
         } else {
-          if (pb < ns) xb = -fs[pb * ldf + site_new];
+          if (pb < ns) xb = -(T)fs[pb * ldf + site_new];
         }
       }
       xc[k] = xb;
@@ -442,7 +464,7 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
       part += (double)(ya[k] * xb);
     }
     double rbm = 0.0;
-    if (M) {
+    if (RBM && M) {
       for (int hh = lane; hh < M; hh += 64) {
         const T d = T(2) * (WT[(int64_t)Inew * M + hh] - WT[(int64_t)Iold * M + hh]);
         const T th = ths[hh];
@@ -454,11 +476,11 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
     double logc = gnew * (eidx[site_new + opp] >= 0 ? 1.0 : 0.0) -
                   gold * (eidx[site_old + opp] >= 0 ? 1.0 : 0.0) + hs[site_new] - hs[site_old] -
                   vio;
-    if (M) logc += 2.0 * ((double)raT[Inew] - (double)raT[Iold]) + rbm;
+    if (RBM && M) logc += 2.0 * ((double)raT[Inew] - (double)raT[Iold]) + rbm;
     const double Rt = r_pf * exp(logc);
     const double u = uniform53(r.z, r.w);
     const int accept = sgpr(u < Rt * Rt ? 1 : 0);
-    if (trace && lane == 0 && n - tb < (uint64_t)trace_cap) {
+    if (TRACE && lane == 0 && n - tb < (uint64_t)trace_cap) {
       TraceRec rec;
       rec.n = (int64_t)n; rec.walker = gw; rec.a = a; rec.i_new = Inew; rec.accepted = accept;
       rec.ratio = Rt;
@@ -501,8 +523,9 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
     }
     for (int l = lane; l < ns; l += 64)
       hs[l] += V[(int64_t)site_new * ns + l] - V[(int64_t)site_old * ns + l];
-    for (int hh = lane; hh < M; hh += 64)
-      ths[hh] += T(2) * (WT[(int64_t)Inew * M + hh] - WT[(int64_t)Iold * M + hh]);
+    if (RBM)
+      for (int hh = lane; hh < M; hh += 64)
+        ths[hh] += T(2) * (WT[(int64_t)Inew * M + hh] - WT[(int64_t)Iold * M + hh]);
 #pragma unroll
     for (int k = 0; k < KC; ++k)
       if (ka == k && lane == la) posr[k] = Inew;
@@ -520,12 +543,10 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
     if (kref && R > 0 && to_refresh == R) {
       double lp, sg;
       if constexpr (sizeof(T) == 8) {
-        singular = reg_refresh<NE_MAX, KC>(y, posr, f64, ldf, f64_lds, n2, ns, ne, lane, posl,
-                                           sri, srj, ord, lp, sg);
+        singular = reg_refresh<NE_MAX, KC>(y, posr, fs, ldf, ns, ne, lane, posl, s2, lp, sg);
       } else {
         double m[KC][NE_MAX];
-        singular = reg_refresh<NE_MAX, KC>(m, posr, f64, ldf, f64_lds, n2, ns, ne, lane, posl,
-                                           sri, srj, ord, lp, sg);
+        singular = reg_refresh<NE_MAX, KC>(m, posr, fs, ldf, ns, ne, lane, posl, s2, lp, sg);
 #pragma unroll
         for (int k = 0; k < KC; ++k)
 #pragma unroll
@@ -534,14 +555,17 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
       last_logpf = lp;
       last_sgn = sg;
       refreshed = true;
-      // Jastrow field and RBM angles from scratch
+      // Jastrow field and RBM angles from scratch (V is symmetric: row mm of
+      // V read across the lanes is coalesced)
       for (int l = lane; l < ns; l += 64) {
         double sum = 0.0;
+#pragma unroll 8
         for (int mm = 0; mm < ns; ++mm)
-          sum += V[(int64_t)l * ns + mm] *
+          sum += V[(int64_t)mm * ns + l] *
                  (double)((eidx[mm] >= 0 ? 1 : 0) + (eidx[mm + ns] >= 0 ? 1 : 0) - 1);
         hs[l] = sum;
       }
+      if (RBM)
       for (int hh = lane; hh < M; hh += 64) {
         double th = rbT64[I.rbm_b_off + hh];
         for (int v = 0; v < n2; ++v)
@@ -595,18 +619,28 @@ bool launch_sweep_reg(const Pools& P, const int32_t* wlist, int n_groups, int ne
   constexpr int WPB = 4;
   if (n_groups <= 0 || cap <= 0) return true;
   const size_t sh = sweep_reg_lds_bytes(ne_max, max_ns, max_M, sizeof(T), WPB);
-#define MVMC_REG(NEM)                                                                            \
+#define MVMC_REG_V(NEM, TR, RB)                                                                  \
   do {                                                                                           \
     if (sh > 65536)                                                                              \
-      (void)hipFuncSetAttribute((const void*)&k_sweep_reg<T, NEM, WPB>,                          \
+      (void)hipFuncSetAttribute((const void*)&k_sweep_reg<T, NEM, WPB, TR, RB>,                  \
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);            \
-    hipLaunchKernelGGL((k_sweep_reg<T, NEM, WPB>), dim3(n_groups), dim3(64 * WPB), sh, s, P,     \
-                       wlist, cap, seed, trace, trace_cap, trace_base, target, needs_refresh, R, \
-                       kref);                                                                    \
+    hipLaunchKernelGGL((k_sweep_reg<T, NEM, WPB, TR, RB>), dim3(n_groups), dim3(64 * WPB), sh,   \
+                       s, P, wlist, cap, seed, trace, trace_cap, trace_base, target,             \
+                       needs_refresh, R, kref);                                                  \
     return true;                                                                                 \
+  } while (0)
+#define MVMC_REG(NEM)                                                                            \
+  do {                                                                                           \
+    if (trace) {                                                                                 \
+      if (max_M > 0) MVMC_REG_V(NEM, true, true);                                                \
+      MVMC_REG_V(NEM, true, false);                                                              \
+    }                                                                                            \
+    if (max_M > 0) MVMC_REG_V(NEM, false, true);                                                 \
+    MVMC_REG_V(NEM, false, false);                                                               \
   } while (0)
   if (ne_max == 32) MVMC_REG(32);
   if (ne_max == 64) MVMC_REG(64);
+#undef MVMC_REG_V
 #undef MVMC_REG
   return false;
 }
