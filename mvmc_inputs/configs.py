@@ -121,6 +121,20 @@ def workload(name: str, **overrides) -> dict:
                                f_noise=0.05, n_hidden=12, rbm_sigma=0.1,
                                n_walkers=nw or 16, seed=INPUT_SEED)],
                 sweeps=100, warmup=20, sr_iters=0)
+    elif name == "ring6_u8_gain":
+        # 6-site ring at U = 8 with a translation-invariant pair amplitude
+        # f(j - i): the same Pfaffian-Jastrow-Gutzwiller start with and
+        # without an RBM factor of 12 hidden units (2 per site, weights
+        # N(0, 0.01)); the RBM parameters are appended after the shared block
+        lat = chain(6)
+        pj = make_instance("ring6_U8_pj", lat, 3, 3, 8.0, f_map_sublattice(lat, 1, 1),
+                           v_map_nn(lat), n_walkers=nw or 512, seed=INPUT_SEED)
+        rbm = make_instance("ring6_U8_rbm", lat, 3, 3, 8.0, f_map_sublattice(lat, 1, 1),
+                            v_map_nn(lat), n_hidden=12, rbm_sigma=0.01,
+                            n_walkers=nw or 512, seed=INPUT_SEED)
+        assert np.array_equal(rbm.params0[:pj.n_params], pj.params0)
+        d = _wl([pj, rbm], sweeps=20, warmup=20, sr_iters=80, dtau=0.05,
+                sampler_seed=1711 * 1000 + 6)
     else:
         raise KeyError(name)
     d["name"] = name
@@ -129,7 +143,7 @@ def workload(name: str, **overrides) -> dict:
 
 
 WORKLOADS = ("c1_ring8_fp64", "c2_sq8_fp64", "c3_sq10_mixed", "c4_batch32_mixed",
-             "c5_sq16_rbm_mixed", "ring4", "ring6", "sq4_sub2", "ring6_rbm")
+             "c5_sq16_rbm_mixed", "ring4", "ring6", "sq4_sub2", "ring6_rbm", "ring6_u8_gain")
 
 
 def random_configs(inst: Instance, n: int, seed: int) -> np.ndarray:
