@@ -30,6 +30,7 @@ __device__ __forceinline__ void slot_sums(int nslot, const int32_t* __restrict__
   const int grp = threadIdx.x / G, ngrp = blockDim.x / G;
   for (int k = grp; k < nslot; k += ngrp) {
     double s = 0.0;
+#pragma unroll 8
     for (int m = ptr[k] + lane_in; m < ptr[k + 1]; m += G) s += val(mem[m]);
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
@@ -41,9 +42,10 @@ template <typename T, typename F>
 __device__ __forceinline__ void slot_sums_any(int nslot, int nmem, const int32_t* ptr,
                                               const int32_t* mem, F val, T* out) {
   const int avg = nslot > 0 ? (nmem + nslot - 1) / nslot : 0;
-  if (avg <= 2) slot_sums<1>(nslot, ptr, mem, val, out);
-  else if (avg <= 8) slot_sums<4>(nslot, ptr, mem, val, out);
-  else if (avg <= 32) slot_sums<16>(nslot, ptr, mem, val, out);
+  // one lane per slot while a slot has few members (independent loads, no
+  // cross-lane reduction); lane groups for slots with many members
+  if (avg <= 32) slot_sums<1>(nslot, ptr, mem, val, out);
+  else if (avg <= 256) slot_sums<16>(nslot, ptr, mem, val, out);
   else slot_sums<64>(nslot, ptr, mem, val, out);
 }
 
@@ -56,10 +58,16 @@ template <> __device__ __forceinline__ const float* table_of<float>(const Pools&
 }
 }  // namespace
 
-// LDS carve-up: [red 16 | hs ns | ths M] doubles, [Y ne*ne | f ns*(ns+1)] T, ints.
+// LDS carve-up: [red 16 | hs ns | ths M] doubles, [Yh ne*(ne/2+1) | f ns*(ns+1)] T, ints.
+// Yh keeps, for every electron a, only the entries of row a of Y on the
+// electrons of the other spin (b >= n_up for an up electron, b < n_up for a
+// down one): with the anti-parallel pair amplitude the new row a of X vanishes
+// on the electrons of a's own spin, and the f log-derivatives pair an up with
+// a down electron, so no other entry of Y enters the measurement.
 __host__ __device__ inline size_t mal16(size_t x) { return (x + 15) & ~(size_t)15; }
 __host__ __device__ inline size_t measure_lds(int ne, int ns, int M, size_t ts, bool ylds, bool flds) {
-  return mal16((16 + (size_t)ns + M) * sizeof(double)) + (ylds ? mal16((size_t)ne * (ne + 1) * ts) : 0) +
+  return mal16((16 + (size_t)ns + M) * sizeof(double)) +
+         (ylds ? mal16((size_t)ne * (ne / 2 + 1) * ts) : 0) +
          (flds ? mal16((size_t)ns * (ns + 1) * ts) : 0) + (size_t)(ne + 2 * ns) * sizeof(int32_t);
 }
 
@@ -83,8 +91,8 @@ __global__ __launch_bounds__(kMeasureThreads) void k_measure(Pools P,
   q += mal16((16 + (size_t)ns + M) * sizeof(double));
   const T* Yglob = (const T*)P.Y + I.Y_off + lw * ne * ne;
   T* Ys = (T*)q;
-  if (YLDS) q += mal16((size_t)ne * (ne + 1) * sizeof(T));
-  const int ldy = YLDS ? ne + 1 : ne;   // padded rows avoid LDS bank conflicts
+  if (YLDS) q += mal16((size_t)ne * (ne / 2 + 1) * sizeof(T));
+  const int ldy = nup + 1;   // padded rows of Yh avoid LDS bank conflicts
   T* fs = (T*)q;
   if (FLDS) q += mal16((size_t)ns * ldf * sizeof(T));
   int32_t* pos_s = (int32_t*)q;                 // ne
@@ -96,7 +104,10 @@ __global__ __launch_bounds__(kMeasureThreads) void k_measure(Pools P,
   for (int l = tid; l < ns; l += blockDim.x) hs[l] = P.h[I.h_off + lw * ns + l];
   for (int hh = tid; hh < M; hh += blockDim.x) ths[hh] = P.theta[I.theta_off + lw * M + hh];
   if (YLDS)
-    for (int e = tid; e < ne * ne; e += blockDim.x) Ys[(e / ne) * ldy + e % ne] = Yglob[e];
+    for (int e = tid; e < ne * nup; e += blockDim.x) {
+      const int a = e / nup, bp = e - (e / nup) * nup;
+      Ys[a * ldy + bp] = Yglob[(int64_t)a * ne + (a < nup ? nup : 0) + bp];
+    }
   if (FLDS)
     for (int e = tid; e < ns * ns; e += blockDim.x) {
       const int i = e / ns, j = e - (e / ns) * ns;
@@ -109,7 +120,10 @@ __global__ __launch_bounds__(kMeasureThreads) void k_measure(Pools P,
   }
   __syncthreads();
 
-  const T* Y = YLDS ? (const T*)Ys : Yglob;
+  // Y[a][b] for electrons a, b of opposite spin
+  auto yab = [&](int a, int b) -> T {
+    return YLDS ? Ys[a * ldy + (b < nup ? b : b - nup)] : Yglob[(int64_t)a * ne + b];
+  };
   // pair amplitude f(i, j) = A[i][Ns + j]
   auto fval = [&](int i, int j) -> T { return FLDS ? fs[i * ldf + j] : A[(int64_t)i * n2 + ns + j]; };
   const double* V = P.V + I.V_off;
@@ -136,14 +150,15 @@ __global__ __launch_bounds__(kMeasureThreads) void k_measure(Pools P,
     const int Inew = site_new + sigma * ns;
     if (eidx[Inew] >= 0) continue;
     // new row a of X is non-zero only on the opposite-spin electrons (Eq. AP-Pf)
-    const T* Ya = Y + a * ldy;
+    const T* Ya = YLDS ? Ys + a * ldy : Yglob + (int64_t)a * ne + (sigma ? 0 : nup);
     double s = 0.0;
     if (sigma == 0) {
-#pragma unroll 4
-      for (int b = nup; b < ne; ++b) s += (double)Ya[b] * (double)fval(site_new, pos_s[b] - ns);
+#pragma unroll 8
+      for (int bp = 0; bp < nup; ++bp)
+        s += (double)Ya[bp] * (double)fval(site_new, pos_s[nup + bp] - ns);
     } else {
-#pragma unroll 4
-      for (int b = 0; b < nup; ++b) s -= (double)Ya[b] * (double)fval(pos_s[b], site_new);
+#pragma unroll 8
+      for (int bp = 0; bp < nup; ++bp) s -= (double)Ya[bp] * (double)fval(pos_s[bp], site_new);
     }
     const double r_pf = -s;
     const int opp = (1 - sigma) * ns;
@@ -171,7 +186,7 @@ __global__ __launch_bounds__(kMeasureThreads) void k_measure(Pools P,
   slot_sums_any(I.nf, fptr[I.nf], fptr, P.fm + I.fm_off,
                 [&](int pk) -> double {
                   const int ea = eidx[pk / ns], eb = eidx[pk % ns + ns];
-                  return (ea >= 0 && eb >= 0) ? -(double)Y[ea * ldy + eb] : 0.0;
+                  return (ea >= 0 && eb >= 0) ? -(double)yab(ea, eb) : 0.0;
                 },
                 Orow);
   const int32_t* gptr = P.gm_ptr + I.gm_ptr_off;
@@ -205,9 +220,13 @@ template <typename T>
 void launch_measure(const Pools& P, const int32_t* wlist, int n, int slot, double* eloc, T* O,
                     int max_ne, int max_ns, int max_M, hipStream_t s) {
   if (n <= 0) return;
-  const size_t budget = 96 * 1024;
+  // Keep a workgroup's LDS small enough for several walkers per CU: the
+  // opposite-spin half of Y is staged when it fits, the pair-amplitude table
+  // (shared by every walker of an instance and L2-resident) only when small.
+  const size_t budget = 64 * 1024;
   const bool ylds = measure_lds(max_ne, max_ns, max_M, sizeof(T), true, false) <= budget;
-  const bool flds = measure_lds(max_ne, max_ns, max_M, sizeof(T), ylds, true) <= budget;
+  const bool flds = (size_t)max_ns * (max_ns + 1) * sizeof(T) <= 16 * 1024 &&
+                    measure_lds(max_ne, max_ns, max_M, sizeof(T), ylds, true) <= budget;
   const size_t sh = measure_lds(max_ne, max_ns, max_M, sizeof(T), ylds, flds);
 #define MVMC_MEAS(YL, FL)                                                                       \
   do {                                                                                          \

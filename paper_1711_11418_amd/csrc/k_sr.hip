@@ -442,17 +442,44 @@ __global__ __launch_bounds__(256) void k_gemv_rows(SrArgs A, const T* __restrict
   if (lane == 0) A.t[I.eloc_off + m] = s;
 }
 
-// w = mask o (O~^T t) / N + shift o p: threads over columns.
+// w = mask o (O~^T t) / N + shift o p, in two passes: partial sums over
+// chunks of kRowChunk rows (a workgroup covers 64 columns, its four waves
+// interleave the rows of the chunk, coalesced along the columns), then the
+// chunk partials summed in chunk order.  The partial buffer of the column
+// statistics is free once they have been reduced.
 template <typename T>
-__global__ __launch_bounds__(256) void k_gemv_cols(SrArgs A, const T* __restrict__ O) {
+__global__ __launch_bounds__(256) void k_gemv_cols_part(SrArgs A, const T* __restrict__ O) {
+  const SrInst& I = A.inst[blockIdx.z];
+  if (A.scal[blockIdx.z * kScal + kDone] != 0.0) return;
+  const int64_t m0 = (int64_t)blockIdx.y * kRowChunk;
+  if (m0 >= I.rows) return;
+  const int64_t m1 = m0 + kRowChunk < I.rows ? m0 + kRowChunk : I.rows;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t k = (int64_t)blockIdx.x * 64 + lane;
+  const double* t = A.t + I.eloc_off;
+  double s = 0.0;
+  if (k < I.np) {
+    const T* col = O + I.O_off + k;
+#pragma unroll 8
+    for (int64_t m = m0 + wv; m < m1; m += 4) s += (double)col[m * I.ldO] * t[m];
+  }
+  __shared__ double red[4][64];
+  red[wv][lane] = s;
+  __syncthreads();
+  if (wv == 0 && k < I.np)
+    A.colpart[I.colpart_off + (int64_t)blockIdx.y * I.np + k] =
+        (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+}
+
+__global__ __launch_bounds__(256) void k_gemv_cols_finish(SrArgs A) {
   const SrInst& I = A.inst[blockIdx.y];
   if (A.scal[blockIdx.y * kScal + kDone] != 0.0) return;
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= I.np) return;
-  const T* col = O + I.O_off + k;
-  const double* t = A.t + I.eloc_off;
+  const int64_t nch = ceil_div<int64_t>(I.rows, kRowChunk);
+  const double* part = A.colpart + I.colpart_off + k;
   double s = 0.0;
-  for (int64_t m = 0; m < I.rows; ++m) s += (double)col[m * I.ldO] * t[m];
+  for (int64_t c = 0; c < nch; ++c) s += part[c * I.np];
   const int64_t o = I.param_off + k;
   A.w[o] = A.mask[o] * s / (double)I.rows + A.shift[o] * A.p[o];
 }
@@ -580,7 +607,11 @@ void sr_cg_iter(const SrArgs& A, const T* O, int iter, int n_inst, int64_t max_n
   const int cb = (int)ceil_div<int64_t>(max_np, 256);
   hipLaunchKernelGGL(k_gemv_rows<T>, dim3((unsigned)ceil_div<int64_t>(max_rows, 4), n_inst),
                      dim3(256), 0, s, A, O);
-  hipLaunchKernelGGL(k_gemv_cols<T>, dim3(cb, n_inst), dim3(256), 0, s, A, O);
+  hipLaunchKernelGGL(k_gemv_cols_part<T>,
+                     dim3((unsigned)ceil_div<int64_t>(max_np, 64),
+                          (unsigned)ceil_div<int64_t>(max_rows, kRowChunk), n_inst),
+                     dim3(256), 0, s, A, O);
+  hipLaunchKernelGGL(k_gemv_cols_finish, dim3(cb, n_inst), dim3(256), 0, s, A);
   hipLaunchKernelGGL(k_dot, dim3(n_inst), dim3(256), 0, s, A, (const double*)A.p, (const double*)A.w,
                      kPw, 1);
   hipLaunchKernelGGL(k_cg_xr, dim3(cb, n_inst), dim3(256), 0, s, A);

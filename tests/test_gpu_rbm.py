@@ -27,12 +27,14 @@ def _train(inst, wl, solver):
                build_s=solver == "chol")
     ctx.sample(wl["warmup"])
     hist = []
-    for _ in range(wl["sr_iters"]):
+    for it in range(wl["sr_iters"]):
         for s in range(sweeps):
             ctx.sample_async(1)
             ctx.measure(s)
         E, _ = ctx.build_sr(sweeps)
         hist.append(float(E[0]))
+        if it % 20 == 0:
+            log(f"  {inst.name} SR step {it}: E_mc = {hist[-1]:.5f}")
         ctx.sr_update(dtau=wl["dtau"], eps_rel=wl["eps_rel"], eps_abs=wl["eps_abs"],
                       solver=solver, cg_tol=1e-8, cg_maxit=2000)
         ctx.sample(5)          # re-equilibrate after the parameter change
