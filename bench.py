@@ -226,12 +226,16 @@ def s_build_leg():
     N, npar = inst.n_walkers, inst.n_params
     flops = N * npar * (npar + 1)
     avg = ms[4] / max(calls[4], 1)
-    # the kernel runs 64x64 upper-triangle tiles, three bf16 MFMA passes each
-    nt = -(-npar // 64)
-    issued = 3 * 2 * (-(-N // 16) * 16) * 64 * 64 * nt * (nt + 1) // 2
+    # upper-triangle tiles of 128x128 (wide parameter sets) or 64x64, three
+    # bf16 MFMA passes each over the samples rounded up to 16
+    nt2 = -(-npar // 128)
+    tile = 128 if nt2 * (nt2 + 1) // 2 >= 512 else 64
+    nt = -(-npar // tile)
+    issued = 3 * 2 * (-(-N // 16) * 16) * tile * tile * nt * (nt + 1) // 2
     return {"shape": [N, npar], "ms": avg, "tflops": flops / (avg * 1e-3) / 1e12,
             "algorithmic_flops": flops, "issued_mfma_tflops": issued / (avg * 1e-3) / 1e12,
             "issued_frac_of_bf16_peak": issued / (avg * 1e-3) / 1e12 / BF16_PEAK_TFLOPS,
+            "tile": tile,
             "note": "time of the S kernels only (centring and split excluded)"}
 
 

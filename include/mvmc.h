@@ -116,7 +116,9 @@ typedef struct {
   int64_t walker_off, n_walkers;   /* global walker ids [walker_off, walker_off+n_walkers) */
   int64_t param_off, n_params;     /* block of params / g / dparams */
   int64_t eloc_off;                /* eloc[eloc_off + slot*n_walkers + w] */
-  int64_t O_off, O_ld;             /* O row (slot*n_walkers + w) at O_off + row*O_ld */
+  int64_t O_off, O_ld;             /* O row (slot*n_walkers + w) at O_off + row*O_ld;
+                                      O_ld = n_params rounded up to 64 (to 128 when
+                                      n_params > 3968) */
   int64_t S_off;                   /* S block [n_params][n_params] at S_off (full square) */
   int64_t Y_off;                   /* get_inverse: walker w at Y_off + w*n_elec^2, row-major */
   int64_t pos_off;                 /* get/set_state: walker w at pos_off + w*n_elec */

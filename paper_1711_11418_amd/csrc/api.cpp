@@ -81,6 +81,14 @@ int sweep_threads_for(const mvmc_config& c, int ne) {
   return ne <= 48 ? 64 : (ne <= 96 ? 128 : 256);
 }
 
+// Parameter sets wide enough for one wavefront per 128 x 128 tile of S to
+// fill the GPU without splitting the sample sum (at least 512 tiles in the
+// upper triangle).
+static bool wide_params(int64_t np) {
+  const int64_t nt = (np + 127) / 128;
+  return nt * (nt + 1) / 2 >= 512;
+}
+
 Err validate(const mvmc_config* c) {
   if (!c) return fail(MVMC_E_ARG, "config is NULL");
   if (c->precision != MVMC_FP64 && c->precision != MVMC_MIXED)
@@ -175,7 +183,9 @@ Plan make_plan(const mvmc_config& c) {
     I.M = d.n_hidden;
     I.W = d.n_walkers;
     I.np = (int32_t)nparams_of(d);
-    I.ldO = (int32_t)((I.np + 63) / 64 * 64);
+    // O rows padded to 64 parameters, to 128 when the split-bf16 S build
+    // takes 128 x 128 tiles (whose operand loads then stay inside the row)
+    I.ldO = (int32_t)(wide_params(I.np) ? (I.np + 127) / 128 * 128 : (I.np + 63) / 64 * 64);
     std::vector<int> deg(I.ns, 0);
     for (int b = 0; b < d.n_bonds; ++b) {
       ++deg[d.bond_i[b]];
@@ -260,6 +270,9 @@ Plan make_plan(const mvmc_config& c) {
     int64_t ks = std::max<int64_t>(1, 1024 / std::max<int64_t>(tiles, 1));
     ks = std::min<int64_t>(ks, std::max<int64_t>(1, I.rows / 256));
     while (ks > 1 && ks * tiles * 4096 * 8 > ((int64_t)256 << 20)) ks /= 2;
+    // wide parameter sets: 128 x 128 tiles per wave fill the GPU without a K split
+    S.tile128 = wide_params(I.np) ? 1 : 0;
+    if (S.tile128) ks = 1;
     S.ksplit = (int32_t)ks;
     S.syrkpart_off = off_syrkpart;
     if (c.build_s) off_syrkpart += ks * tiles * 4096;

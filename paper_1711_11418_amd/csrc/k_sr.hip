@@ -76,6 +76,14 @@ __global__ void k_colpass(SrArgs A, T* __restrict__ O, int mode, uint16_t* __res
         lo[si] = f32_to_bf16((float)c - bf16_to_f32(h));
       }
     }
+    // zero rows up to the next multiple of 16 samples, which the S kernels
+    // read as whole MFMA operands
+    if (hi && r1 == I.rows)
+      for (int64_t m = I.rows; m < (I.rows + 15) / 16 * 16; ++m) {
+        const int64_t si = split_index(m, k, ld);
+        hi[si] = 0;
+        lo[si] = 0;
+      }
     part[(blockIdx.y * 3 + 1) * ld + k] = s2;
     part[(blockIdx.y * 3 + 2) * ld + k] = sg;
   }

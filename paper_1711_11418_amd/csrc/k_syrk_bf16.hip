@@ -46,6 +46,7 @@ __device__ __forceinline__ bf16x8 load8(const uint16_t* __restrict__ base, int64
 __global__ __launch_bounds__(64) void k_syrk_mfma(SrArgs A, const uint16_t* __restrict__ split,
                                                   float* __restrict__ S) {
   const SrInst& I = A.inst[blockIdx.z];
+  if (I.tile128) return;   // built by the 128-tile kernel
   const int nt = (int)ceil_div<int64_t>(I.np, kT);
   const int ntiles = nt * (nt + 1) / 2;
   if ((int)blockIdx.x >= ntiles || (int)blockIdx.y >= I.ksplit) return;
@@ -116,6 +117,107 @@ __global__ __launch_bounds__(64) void k_syrk_mfma(SrArgs A, const uint16_t* __re
       }
 }
 
+// Wide parameter sets: one wavefront per 128 x 128 tile of the upper
+// triangle, 4 x 4 blocks of 32 x 32 accumulators (held in the accumulation
+// registers), three bf16 products per block and 16 samples, so each
+// 16-sample step loads 16 operand vectors for 48 MFMAs (three times the
+// operand reuse of the 64-tile kernel).  The next step's operands are loaded
+// before the current step's products are issued.  No K split: S is written
+// directly, both triangles.
+namespace {
+constexpr int kT2 = 128;
+struct Ops128 {
+  bf16x8 ah[4], al[4], bh[4], bl[4];
+};
+// Operands of one 16-sample step.  The split arrays hold zeros up to the
+// next multiple of 16 samples and in the padding parameters (rows of O are
+// padded to a multiple of 128 for these instances), so no load is masked.
+__device__ __forceinline__ bf16x8 load8u(const uint16_t* __restrict__ p) {
+  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(p));
+}
+__device__ __forceinline__ void load_ops128(Ops128& o, const uint16_t* hi, const uint16_t* lo,
+                                            int64_t k, int64_t ld, int64_t p0, int64_t q0,
+                                            int m, int kh) {
+  const int64_t kg = (k >> 3) + kh;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t ip = (kg * ld + p0 + 32 * i + m) * 8, iq = (kg * ld + q0 + 32 * i + m) * 8;
+    o.ah[i] = load8u(hi + ip);
+    o.al[i] = load8u(lo + ip);
+    o.bh[i] = load8u(hi + iq);
+    o.bl[i] = load8u(lo + iq);
+  }
+}
+__device__ __forceinline__ void mfma_step128(f32x16 (&acc)[4][4], const Ops128& o) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.ah[i], o.bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.ah[i], o.bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.al[i], o.bh[j], acc[i][j], 0, 0, 0);
+}
+}  // namespace
+
+__global__ __launch_bounds__(64) void k_syrk_mfma128(SrArgs A, const uint16_t* __restrict__ split,
+                                                     float* __restrict__ S) {
+  const SrInst& I = A.inst[blockIdx.y];
+  if (!I.tile128) return;
+  const int nt = (int)ceil_div<int64_t>(I.np, kT2);
+  if ((int)blockIdx.x >= nt * (nt + 1) / 2) return;
+  int ti, tj;
+  tile_index(blockIdx.x, nt, ti, tj);
+  const int64_t ld = I.ldO, np = I.np, rows = I.rows;
+  const uint16_t* hi = split + I.split_off;
+  const uint16_t* lo = hi + I.split_rows * ld;
+  const int lane = threadIdx.x, m = lane & 31, kh = lane >> 5;
+  const int64_t p0 = (int64_t)ti * kT2, q0 = (int64_t)tj * kT2;
+  f32x16 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+  // The products run pass by pass, so each accumulator's dependent MFMAs
+  // are 16 issues apart; the loads of a step are unconditional (the last
+  // step reloads itself), which keeps the number in flight fixed.
+  Ops128 cur, nxt;
+  const int64_t rows16 = (rows + 15) / 16 * 16;
+  load_ops128(cur, hi, lo, 0, ld, p0, q0, m, kh);
+  for (int64_t k = 0; k < rows16; k += 16) {
+    load_ops128(nxt, hi, lo, k + 16 < rows16 ? k + 16 : k, ld, p0, q0, m, kh);
+    mfma_step128(acc, cur);
+    cur = nxt;
+  }
+  // accumulator r of lane l holds D[row][col], col = l % 32,
+  // row = 8 (r / 4) + 4 (l / 32) + r % 4
+  const float invN = (float)(1.0 / (double)rows);
+  float* Sb = S + I.S_off;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t row = p0 + 32 * i + 8 * (r >> 2) + 4 * kh + (r & 3);
+        const int64_t col = q0 + 32 * j + m;
+        if (row < np && col < np && (ti != tj || row <= col)) {
+          const float v = acc[i][j][r] * invN;
+          Sb[row * np + col] = v;
+          Sb[col * np + row] = v;
+        }
+      }
+}
+
 __global__ void k_syrk_split_reduce(SrArgs A, float* __restrict__ S) {
   const SrInst& I = A.inst[blockIdx.y];
   if (I.ksplit == 1) return;   // written directly by the tile kernel
@@ -145,6 +247,10 @@ void sr_syrk_bf16x3(const SrArgs& A, const uint16_t* split, float* S, int n_inst
   const int ntiles = nt * (nt + 1) / 2;
   hipLaunchKernelGGL(k_syrk_mfma, dim3(ntiles, max_ksplit, n_inst), dim3(64), 0, s, A, split, S);
   hipLaunchKernelGGL(k_syrk_split_reduce, dim3(ntiles, n_inst), dim3(256), 0, s, A, S);
+  const int nt2 = (int)ceil_div<int64_t>(max_np, kT2);
+  if (nt2 * (nt2 + 1) / 2 >= 512)
+    hipLaunchKernelGGL(k_syrk_mfma128, dim3(nt2 * (nt2 + 1) / 2, n_inst), dim3(64), 0, s, A,
+                       split, S);
 }
 
 }  // namespace mvmc

@@ -18,7 +18,8 @@ struct SrInst {
   int64_t O_off, S_off, eloc_off, param_off;
   int64_t colpart_off, syrkpart_off, chol_off, split_off;
   int64_t split_rows;             // rows allocated per bf16 array (multiple of 16)
-  int32_t ksplit, pad;
+  int32_t ksplit;                 // K split of the 64-tile split-bf16 S kernel
+  int32_t tile128;                // 1: S built by the 128-tile split-bf16 kernel (ksplit 1)
 };
 
 // bf16 split layout: element (sample m, parameter k) of the hi (or lo) array

@@ -185,11 +185,15 @@ def test_mixed_precision_ratios(name, sweeps):
     ctx.close()
 
 
-def test_mixed_split_bf16_overlap():
-    inst = workload("sq4_sub2")["instances"][0]
-    inst.n_walkers = 256
+@pytest.mark.parametrize("name,walkers", [("sq4_sub2", 256), ("sq10_full", 60)])
+def test_mixed_split_bf16_overlap(name, walkers):
+    """Split-bf16 S against the FP64 product of the same centred O.  The
+    10x10 case (N_p = 10002, 120 samples: a ragged 16-sample tail) runs the
+    128-tile kernel, the 4x4 case the 64-tile kernel with a K split."""
+    inst = workload(name)["instances"][0] if name == "sq4_sub2" else _case(name)
+    inst.n_walkers = walkers
     slots = 2
-    log("[mixed-S] sq4_sub2 W=256 slots=2")
+    log(f"[mixed-S] {name} W={walkers} slots={slots} N_p={inst.n_params}")
     ctx = _ctx([inst], inst.params0, seed=SEED, precision="mixed", refresh_every=32,
                n_slots=slots)
     ctx.sample(5)
