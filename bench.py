@@ -39,31 +39,39 @@ def log(msg):
 
 
 def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", sweep_threads=0,
-                    use_graph=True):
-    """Time whole SR steps.  With use_graph the sampling part of a step (the
-    sweeps and the measurement after each of them) is captured once into a
-    HIP graph and replayed; the SR build and update run eagerly."""
+                    use_graph=True, autotune=False):
+    """Time whole SR steps of every instance of the workload.  With use_graph
+    the sampling part of a step (the sweeps and the measurement after each
+    of them) is captured once into a HIP graph and replayed; the SR build and
+    update run eagerly.  With autotune the sweep variant of every instance is
+    chosen by timing after the warm-up."""
     import numpy as np
     import torch
 
     from paper_1711_11418_amd import MVMC
 
-    inst = wl["instances"][0]
+    insts = wl["instances"]
+    params = np.concatenate([i.params0 for i in insts])
     sweeps = wl["sweeps"]
     side = torch.cuda.Stream()
+    tuned = None
     with torch.cuda.stream(side):
-        ctx = MVMC([inst], inst.params0, precision=precision, refresh_every=refresh_every,
+        ctx = MVMC(insts, params, precision=precision, refresh_every=refresh_every,
                    seed=wl["sampler_seed"], n_slots=sweeps, solver=solver, build_s=True,
                    sweep_threads=sweep_threads, stream=side)
         for _ in range(wl["warmup"]):   # one launch per sweep, as in the timed steps
             ctx.sample_async(1)
         torch.cuda.synchronize()
+        if autotune:
+            ms = ctx.autotune(3)
+            tuned = {"variants": ctx.sweep_variants(),
+                     "ms_by_variant": np.where(np.isnan(ms), None, ms).tolist()}
 
         def sampling(profile=False):
             acc = 0
             for s in range(sweeps):
                 if profile:
-                    acc += int(ctx.sample(1)[0])
+                    acc += int(np.sum(ctx.sample(1)))
                 else:
                     ctx.sample_async(1)
                 ctx.measure(s)
@@ -73,7 +81,7 @@ def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", 
             E, V = ctx.build_sr(sweeps)
             ctx.sr_update(dtau=wl["dtau"], eps_rel=wl["eps_rel"], eps_abs=wl["eps_abs"],
                           solver=solver)
-            return float(E[0])
+            return [float(e) for e in E]
 
         for _ in range(warmup):
             sampling()
@@ -101,15 +109,37 @@ def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", 
         ms, calls = ctx.timing(False)
         torch.cuda.synchronize()
         ctx.close()
-    W, ne, npar = inst.n_walkers, inst.n_elec, inst.n_params
-    proposals = steps * sweeps * W * ne
+    per_sweep = sum(i.n_walkers * i.n_elec for i in insts)
+    proposals = steps * sweeps * per_sweep
+    i0 = insts[0]
     return {
         "seconds": dt, "proposals": proposals, "rate": proposals / dt,
-        "ms_per_step": 1e3 * dt / steps, "energies": energies,
-        "accept_ratio": accepted / (sweeps * W * ne), "kernel_ms": ms.tolist(),
-        "kernel_calls": calls.tolist(), "W": W, "ne": ne, "np": npar, "sweeps": sweeps,
-        "N": sweeps * W, "graph": graph is not None,
+        "ms_per_step": 1e3 * dt / steps,
+        "energies": [e[0] for e in energies] if len(insts) == 1 else energies,
+        "accept_ratio": accepted / (sweeps * per_sweep), "kernel_ms": ms.tolist(),
+        "kernel_calls": calls.tolist(), "W": i0.n_walkers, "ne": i0.n_elec, "np": i0.n_params,
+        "sweeps": sweeps, "N": sweeps * i0.n_walkers, "graph": graph is not None,
+        "autotune": tuned,
     }
+
+
+def batch_leg(steps):
+    """32 ragged clusters (square L = 4..12, U in [2, 10], filling 0.8-1.0,
+    256 walkers each), mixed precision, each instance its own SR step; all
+    instances of a register tier sweep in one launch, variants autotuned."""
+    from mvmc_inputs import workload
+    wl = workload("c4_batch32_mixed")
+    r = run_sr_workload(wl, "mixed", steps, 1, wl["refresh_every"], use_graph=True,
+                        autotune=True)
+    insts = wl["instances"]
+    return {"value": r["rate"], "unit": "hop-updates/s", "ms_per_step": r["ms_per_step"],
+            "instances": len(insts), "walkers": sum(i.n_walkers for i in insts),
+            "n_elec_range": [min(i.n_elec for i in insts), max(i.n_elec for i in insts)],
+            "sweeps_per_step": r["sweeps"], "accept_ratio": r["accept_ratio"],
+            "kernel_ms_per_step": dict(zip(["sweep", "refresh", "measure", "sr_stats",
+                                            "s_build", "sr_solve"], r["kernel_ms"])),
+            "autotune": r["autotune"], "energy_per_site_last_step":
+                [e / i.n_sites for e, i in zip(r["energies"][-1], insts)]}
 
 
 def hbm_copy_probe(gib=1.0, reps=10):
@@ -347,6 +377,8 @@ def main():
                         "kernel_ms_per_step": m["kernel_ms"]}
         log("[bench] split-bf16 S build at 4096 x 10^4")
         out["s_build_bf16x3_c3"] = s_build_leg()
+        log("[bench] ragged batch of 32 clusters (mixed, autotuned)")
+        out["batch32_mixed"] = batch_leg(max(1, a.steps - 1))
     if not a.no_cpu:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline()

@@ -157,6 +157,30 @@ int mvmc_init_wavefunction(mvmc_ctx **out, const mvmc_config *cfg, void *d_works
  */
 int mvmc_sample_sweeps(mvmc_ctx *ctx, int32_t n_sweeps, int64_t *h_accepted);
 
+/* Sweep kernel variants (same arithmetic as mvmc_sample_sweeps, different
+ * residency of X^-1): 0 registers (one wavefront per walker, N_e <= 64),
+ * 1-3 LDS with 64/128/256 threads per walker, 4-6 HBM with 64/128/256. */
+enum { MVMC_N_SWEEP_VARIANTS = 7 };
+
+/*
+ * Autotuner for the ragged batch (section 3.1.2 sweeps, any mix of lattice
+ * sizes): times n_sweeps >= 1 sweeps of every instance with each variant
+ * that fits it (register tier, LDS kernel at three thread counts, HBM
+ * kernel), the refresh launches between LDS rounds included, and keeps the
+ * fastest per instance for all later calls.  The timed sweeps advance the
+ * chains exactly like mvmc_sample_sweeps (they count as warm-up); the
+ * accepted counters are cleared at the end.  cache_path (may be NULL): text
+ * file of earlier choices, one line per (precision, N_e, N_s, M, walkers);
+ * matching instances are not timed, new choices are appended.  h_ms (may be
+ * NULL): [n_instances][MVMC_N_SWEEP_VARIANTS] measured milliseconds, NaN for
+ * variants not timed.  Synchronises the stream; not capturable.
+ * Errors: MVMC_E_ARG, MVMC_E_HIP.
+ */
+int mvmc_autotune(mvmc_ctx *ctx, int32_t n_sweeps, const char *cache_path, double *h_ms);
+
+/* Current sweep variant of every instance ([n_instances], host). */
+int mvmc_sweep_variants(const mvmc_ctx *ctx, int32_t *h_variant);
+
 /*
  * Local energy E_loc(x) (Eq. MC, H of section 2.3) and the row of
  * O_k = d ln<x|psi>/d alpha_k (section 3.3.1) of every walker's current

@@ -22,7 +22,10 @@ ENTRY_POINTS = (
     "mvmc_measure_energy_and_O", "mvmc_build_sr", "mvmc_sr_update", "mvmc_set_params",
     "mvmc_get_state", "mvmc_set_state", "mvmc_get_inverse", "mvmc_get_pfaffian", "mvmc_refresh",
     "mvmc_trace_enable", "mvmc_timing", "mvmc_destroy", "mvmc_last_error", "mvmc_status_string",
+    "mvmc_autotune", "mvmc_sweep_variants",
 )
+N_SWEEP_VARIANTS = 7
+SWEEP_VARIANT_NAMES = ("reg", "lds64", "lds128", "lds256", "hbm64", "hbm128", "hbm256")
 
 
 class InstanceDesc(C.Structure):
@@ -102,6 +105,8 @@ def load() -> C.CDLL:
         "mvmc_trace_enable": [vp, vp, i64],
         "mvmc_timing": [vp, i32, vp, vp],
         "mvmc_destroy": [vp],
+        "mvmc_autotune": [vp, i32, C.c_char_p, vp],
+        "mvmc_sweep_variants": [vp, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -325,6 +330,20 @@ class MVMC:
     def trace_records(self) -> np.ndarray:
         raw = self._trace.cpu().numpy().view(TRACE_DTYPE)
         return raw.reshape(int(self.sizes.n_walkers), self._trace_cap)
+
+    def autotune(self, n_sweeps: int = 3, cache_path: str | None = None) -> np.ndarray:
+        """Time every sweep variant per instance and keep the fastest
+        (mvmc_autotune); returns [n_instances, 7] milliseconds (NaN = not timed)."""
+        ms = np.full((self.n_inst, N_SWEEP_VARIANTS), np.nan)
+        path = None if cache_path is None else str(cache_path).encode()
+        self._check(self.lib.mvmc_autotune(self.ctx, int(n_sweeps), path,
+                                           ms.ctypes.data_as(C.c_void_p)))
+        return ms
+
+    def sweep_variants(self) -> list[str]:
+        v = np.zeros(self.n_inst, dtype=np.int32)
+        self._check(self.lib.mvmc_sweep_variants(self.ctx, v.ctypes.data_as(C.c_void_p)))
+        return [SWEEP_VARIANT_NAMES[i] for i in v]
 
     def timing(self, enable: bool):
         ms = np.zeros(6)

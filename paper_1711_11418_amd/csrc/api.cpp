@@ -10,6 +10,7 @@
 #include <map>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/mvmc.h"
@@ -38,6 +39,7 @@ struct Plan {
   std::vector<InstDev> inst;
   std::vector<SrInst> sr;
   std::vector<int> reg_class;     // register-sweep tier per instance (0 = LDS/HBM kernel)
+  std::vector<int> sweep_nt;      // threads of the LDS/HBM sweep kernel per instance
   // pools (byte offsets into the workspace)
   Pool inst_p, srinst_p, walker_inst, lists, A64, A32, V, fidx, vidx, G, U, gidx, nbr_ptr,
       nbr_site, nbr_t, fm_ptr, fm, gm_ptr, gm, vm_ptr, vm, rbm64, rbm32, rbmT64, rbmT32, Y, Y64,
@@ -165,6 +167,7 @@ Plan make_plan(const mvmc_config& c) {
   P.inst.resize(n);
   P.sr.resize(n);
   P.reg_class.assign(n, 0);
+  P.sweep_nt.assign(n, 256);
   int64_t off_A = 0, off_V = 0, off_site = 0, off_nptr = 0, off_nbr = 0, off_fm_ptr = 0,
           off_fm = 0, off_gm_ptr = 0, off_gm = 0, off_vm_ptr = 0, off_vm = 0, off_rbm = 0,
           off_Y = 0, off_pos = 0, off_empty = 0, off_h = 0, off_theta = 0, off_chol = 0,
@@ -194,6 +197,7 @@ Plan make_plan(const mvmc_config& c) {
     I.deg_max = 0;
     for (int x : deg) I.deg_max = std::max(I.deg_max, x);
     const int nt = sweep_threads_for(c, I.ne);
+    P.sweep_nt[k] = nt;
     I.sweep_lds = sweep_lds_bytes(I.ne, I.ns, I.M, true, P.tsize, nt) <= kLdsLimit;
     if (c.sweep_threads == 0) {
       const int rc = sweep_reg_class(I.ne, P.tsize);
@@ -408,6 +412,7 @@ struct Bucket {
   int n = 0, max_ne = 0, max_ns = 0, max_M = 0, nthreads = 256;
   bool lds = true;
   int reg = 0;       // register-sweep tier (n = number of walker groups) or 0
+  int inst = -1;     // the one instance of the bucket (autotuning), else -1
 };
 
 }  // namespace
@@ -495,33 +500,48 @@ void harvest(mvmc_ctx* c) {
   c->ev_used = 0;
 }
 
-void build_buckets(mvmc_ctx* c) {
+// Buckets of walkers launched together.  Normally instances that share a
+// kernel variant and LDS size class share a bucket; with per_instance (the
+// autotuner) every instance gets its own sweep and refresh bucket so that
+// its launches can be timed on their own.
+void build_buckets(mvmc_ctx* c, bool per_instance = false) {
   const Plan& P = c->plan;
   const int n = c->cfg.n_instances;
-  // key: (lds flag, LDS size class or 0, threads)
-  std::map<std::tuple<int, size_t, int>, std::vector<int>> sweep_groups, refresh_groups;
-  std::map<int, std::vector<int>> reg_groups;
+  c->sweep_b.clear();
+  c->refresh_b.clear();
+  // key: (lds flag, LDS size class or 0, threads, instance or -1)
+  std::map<std::tuple<int, size_t, int, int>, std::vector<int>> sweep_groups, refresh_groups;
+  std::map<std::pair<int, int>, std::vector<int>> reg_groups;
   for (int k = 0; k < n; ++k) {
     const InstDev& I = P.inst[k];
-    size_t rb = refresh_lds_bytes(I.ne, I.ns, I.refresh_lds);
-    size_t rcls = 4096;
-    while (rcls < rb) rcls <<= 1;
-    refresh_groups[{I.refresh_lds, rcls, 256}].push_back(k);
+    const int own = per_instance ? k : -1;
+    // instances within reach of the anti-parallel block refresh share
+    // buckets of their own, so that one large instance does not send the
+    // whole bucket to the workgroup-per-walker kernel
+    if (refresh_ap_fits(I.ne, I.ns)) {
+      refresh_groups[{2, 0, 64, own}].push_back(k);
+    } else {
+      size_t rb = refresh_lds_bytes(I.ne, I.ns, I.refresh_lds);
+      size_t rcls = 4096;
+      while (rcls < rb) rcls <<= 1;
+      refresh_groups[{I.refresh_lds, rcls, 256, own}].push_back(k);
+    }
     if (P.reg_class[k]) {
-      reg_groups[P.reg_class[k]].push_back(k);
+      reg_groups[{P.reg_class[k], own}].push_back(k);
       continue;
     }
-    const int nt = sweep_threads_for(c->cfg, I.ne);
+    const int nt = P.sweep_nt[k];
     size_t sb = sweep_lds_bytes(I.ne, I.ns, I.M, I.sweep_lds, P.tsize, nt);
     size_t cls = 4096;
     while (cls < sb) cls <<= 1;
-    sweep_groups[{I.sweep_lds, cls, nt}].push_back(k);
+    sweep_groups[{I.sweep_lds, cls, nt, own}].push_back(k);
   }
   std::vector<int32_t> lists;
   // register tiers: each instance's walkers in groups of kRegWpb, padded with -1
   for (auto& g : reg_groups) {
     Bucket b;
-    b.reg = g.first;
+    b.reg = g.first.first;
+    b.inst = g.first.second;
     b.list_off = lists.size() * 4;
     std::vector<int> ks = g.second;
     std::stable_sort(ks.begin(), ks.end(), [&](int x, int y) { return P.inst[x].ne > P.inst[y].ne; });
@@ -536,12 +556,13 @@ void build_buckets(mvmc_ctx* c) {
     b.n = (int)((lists.size() - b.list_off / 4) / kRegWpb);
     c->sweep_b.push_back(b);
   }
-  auto emit = [&](const std::map<std::tuple<int, size_t, int>, std::vector<int>>& groups,
+  auto emit = [&](const std::map<std::tuple<int, size_t, int, int>, std::vector<int>>& groups,
                   std::vector<Bucket>& out) {
     for (auto& g : groups) {
       Bucket b;
       b.lds = std::get<0>(g.first);
       b.nthreads = std::get<2>(g.first);
+      b.inst = std::get<3>(g.first);
       b.list_off = lists.size() * 4;
       std::vector<int> ks = g.second;
       // longest walkers first (cost ~ N_e^2)
@@ -850,13 +871,17 @@ int mvmc_refresh(mvmc_ctx* c) {
   return refresh_any(c, 0.0);
 }
 
-int mvmc_sample_sweeps(mvmc_ctx* c, int32_t n_sweeps, int64_t* h_accepted) {
-  if (!c || n_sweeps < 0) return set_err(c, fail(MVMC_E_ARG, "n_sweeps must be >= 0"));
+}  // extern "C"
+
+namespace {
+// The sweeps of one call.  Register-tier walkers refresh inside the sweep
+// kernel; LDS-tier walkers stop at every multiple of refresh_every and are
+// refreshed between launches.  With inst_ms, every bucket launch is
+// bracketed by events and its time added to the bucket's instance (the
+// buckets are then per instance).
+int run_sweeps(mvmc_ctx* c, int32_t n_sweeps, std::vector<double>* inst_ms) {
   const Plan& P = c->plan;
   const int R = c->cfg.refresh_every;
-  // proposals per walker this call and the number of refresh-aligned rounds
-  // register-tier walkers refresh inside the sweep kernel; LDS-tier walkers
-  // stop at every multiple of refresh_every and are refreshed between launches
   int rounds = 1;
   bool lds_refresh = false;
   std::vector<uint64_t> target(c->cfg.n_instances);
@@ -875,10 +900,26 @@ int mvmc_sample_sweeps(mvmc_ctx* c, int32_t n_sweeps, int64_t* h_accepted) {
   uint64_t* tgt = reinterpret_cast<uint64_t*>(c->ws + P.target.off);
   int32_t* nr = reinterpret_cast<int32_t*>(c->ws + P.needs_refresh.off);
   // per-walker end counters on the device: the call enqueues only kernels
-  // (graph-capturable) unless h_accepted asks for a read-back
+  // (graph-capturable) unless the caller asks for a read-back
   launch_set_target(c->P, tgt, P.W, n_sweeps, c->stream);
   LAUNCHCHK(c);
   const uint64_t* tb = reinterpret_cast<uint64_t*>(c->ws + P.trace_base.off);
+  std::vector<std::tuple<hipEvent_t, hipEvent_t, int>> ev;
+  auto t0 = [&](int inst) -> int {
+    if (!inst_ms || inst < 0) return -1;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return -1;
+    if (hipEventCreate(&b) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      return -1;
+    }
+    (void)hipEventRecord(a, c->stream);
+    ev.emplace_back(a, b, inst);
+    return (int)ev.size() - 1;
+  };
+  auto t1 = [&](int id) {
+    if (id >= 0) (void)hipEventRecord(std::get<1>(ev[id]), c->stream);
+  };
   for (int r = 0; r < rounds; ++r) {
     const int id = tic(c, 0);
     for (auto& b : c->sweep_b) {
@@ -886,6 +927,7 @@ int mvmc_sample_sweeps(mvmc_ctx* c, int32_t n_sweeps, int64_t* h_accepted) {
       if (b.reg) {
         if (r > 0) continue;   // refreshes inside the kernel; done in the first round
         const int cp = INT32_MAX;
+        const int e = t0(b.inst);
         const bool ok =
             c->cfg.precision == MVMC_FP64
                 ? launch_sweep_reg<double>(c->P, lst, b.n, b.reg, b.max_ns, b.max_M, cp,
@@ -894,9 +936,11 @@ int mvmc_sample_sweeps(mvmc_ctx* c, int32_t n_sweeps, int64_t* h_accepted) {
                 : launch_sweep_reg<float>(c->P, lst, b.n, b.reg, b.max_ns, b.max_M, cp,
                                           c->cfg.seed, c->trace, c->trace_cap, tb, tgt, nr, R,
                                           1, c->stream);
+        t1(e);
         if (!ok) return set_err(c, fail(MVMC_E_ARG, "no register sweep tier %d", b.reg));
         continue;
       }
+      const int e = t0(b.inst);
       if (c->cfg.precision == MVMC_FP64)
         launch_sweep<double>(c->P, lst, b.n, (int)std::min<int64_t>(cap, INT32_MAX), c->cfg.seed,
                              b.max_ne, b.max_ns, b.max_M, b.lds, b.nthreads, c->trace,
@@ -905,23 +949,50 @@ int mvmc_sample_sweeps(mvmc_ctx* c, int32_t n_sweeps, int64_t* h_accepted) {
         launch_sweep<float>(c->P, lst, b.n, (int)std::min<int64_t>(cap, INT32_MAX), c->cfg.seed,
                             b.max_ne, b.max_ns, b.max_M, b.lds, b.nthreads, c->trace,
                             c->trace_cap, tb, tgt, nr, R, c->stream);
+      t1(e);
     }
     toc(c, id);
     LAUNCHCHK(c);
     if (lds_refresh) {
       const int id2 = tic(c, 1);
       for (auto& b : c->refresh_b) {
+        // register-tier walkers never ask for this refresh
+        if (b.inst >= 0 && P.reg_class[b.inst]) continue;
         const int32_t* lst = reinterpret_cast<int32_t*>(c->ws + P.lists.off + b.list_off);
+        const int e = t0(b.inst);
         if (c->cfg.precision == MVMC_FP64)
           launch_refresh_if<double>(c->P, lst, b.n, b.max_ne, b.max_ns, b.lds, nr, c->stream);
         else
           launch_refresh_if<float>(c->P, lst, b.n, b.max_ne, b.max_ns, b.lds, nr, c->stream);
+        t1(e);
       }
       toc(c, id2);
       LAUNCHCHK(c);
     }
   }
   for (int k = 0; k < c->cfg.n_instances; ++k) c->cnt_host[k] += target[k];
+  if (inst_ms) {
+    const hipError_t se = hipStreamSynchronize(c->stream);
+    for (auto& e : ev) {
+      float ms = 0.f;
+      if (se == hipSuccess && hipEventElapsedTime(&ms, std::get<0>(e), std::get<1>(e)) == hipSuccess)
+        (*inst_ms)[std::get<2>(e)] += ms;
+      (void)hipEventDestroy(std::get<0>(e));
+      (void)hipEventDestroy(std::get<1>(e));
+    }
+    HIPCHK(c, se);
+  }
+  return MVMC_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int mvmc_sample_sweeps(mvmc_ctx* c, int32_t n_sweeps, int64_t* h_accepted) {
+  if (!c || n_sweeps < 0) return set_err(c, fail(MVMC_E_ARG, "n_sweeps must be >= 0"));
+  const Plan& P = c->plan;
+  const int rc = run_sweeps(c, n_sweeps, nullptr);
+  if (rc) return rc;
   if (h_accepted) {
     std::vector<int64_t> acc(P.W);
     HIPCHK(c, hipMemcpyAsync(acc.data(), c->P.accepted, 8 * P.W, hipMemcpyDeviceToHost, c->stream));
@@ -934,6 +1005,121 @@ int mvmc_sample_sweeps(mvmc_ctx* c, int32_t n_sweeps, int64_t* h_accepted) {
     }
     HIPCHK(c, hipMemsetAsync(c->P.accepted, 0, 8 * P.W, c->stream));
   }
+  return MVMC_OK;
+}
+
+// Sweep variant of instance k: 0 register tier, 1-3 LDS kernel with
+// 64/128/256 threads, 4-6 HBM kernel with 64/128/256 threads.
+static bool variant_fits(const Plan& P, int k, int v) {
+  const InstDev& I = P.inst[k];
+  if (v == 0) {
+    const int rc = sweep_reg_class(I.ne, P.tsize);
+    return rc && sweep_reg_lds_bytes(rc, I.ns, I.M, P.tsize, kRegWpb) <= kLdsLimit;
+  }
+  const int nt = 64 << ((v - 1) % 3);
+  return sweep_lds_bytes(I.ne, I.ns, I.M, v <= 3, P.tsize, nt) <= kLdsLimit;
+}
+static int variant_of(const Plan& P, int k) {
+  if (P.reg_class[k]) return 0;
+  const int nt = P.sweep_nt[k];
+  return (P.inst[k].sweep_lds ? 1 : 4) + (nt == 64 ? 0 : (nt == 128 ? 1 : 2));
+}
+static void set_variant(Plan& P, int k, int v) {
+  InstDev& I = P.inst[k];
+  if (v == 0) {
+    P.reg_class[k] = sweep_reg_class(I.ne, P.tsize);
+    return;
+  }
+  P.reg_class[k] = 0;
+  P.sweep_nt[k] = 64 << ((v - 1) % 3);
+  I.sweep_lds = v <= 3;
+}
+
+int mvmc_autotune(mvmc_ctx* c, int32_t n_sweeps, const char* cache_path, double* h_ms) {
+  if (!c || n_sweeps < 1) return set_err(c, fail(MVMC_E_ARG, "n_sweeps must be >= 1"));
+  Plan& P = c->plan;
+  const int n = c->cfg.n_instances, nv = MVMC_N_SWEEP_VARIANTS;
+  std::vector<double> ms((size_t)n * nv, std::nan(""));
+  std::vector<int> chosen(n, -1);
+  // cached choices: "mvmc-sweep precision ne ns M walkers variant" per line
+  auto key = [&](int k) {
+    const InstDev& I = P.inst[k];
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "mvmc-sweep %d %d %d %d %d", c->cfg.precision, I.ne, I.ns,
+                  I.M, I.W);
+    return std::string(buf);
+  };
+  if (cache_path) {
+    if (FILE* f = std::fopen(cache_path, "r")) {
+      char line[256];
+      while (std::fgets(line, sizeof line, f)) {
+        char tag[32];
+        int prec, ne, ns, M, W, v;
+        if (std::sscanf(line, "%31s %d %d %d %d %d %d", tag, &prec, &ne, &ns, &M, &W, &v) != 7)
+          continue;
+        if (std::string(tag) != "mvmc-sweep" || v < 0 || v >= nv) continue;
+        for (int k = 0; k < n; ++k) {
+          const InstDev& I = P.inst[k];
+          if (prec == c->cfg.precision && ne == I.ne && ns == I.ns && M == I.M && W == I.W &&
+              variant_fits(P, k, v))
+            chosen[k] = v;
+        }
+      }
+      std::fclose(f);
+    }
+  }
+  std::vector<int> dflt(n);
+  for (int k = 0; k < n; ++k) dflt[k] = variant_of(P, k);
+  bool any = false;
+  for (int k = 0; k < n; ++k) any = any || chosen[k] < 0;
+  // one timed call per variant; instances it does not fit (or already
+  // chosen) run their default variant untimed
+  for (int v = 0; v < nv && any; ++v) {
+    std::vector<char> timed(n, 0);
+    for (int k = 0; k < n; ++k) {
+      const bool t = chosen[k] < 0 && variant_fits(P, k, v);
+      set_variant(P, k, t ? v : (chosen[k] >= 0 ? chosen[k] : dflt[k]));
+      timed[k] = t;
+    }
+    build_buckets(c, true);
+    std::vector<double> t_inst(n, 0.0);
+    const int rc = run_sweeps(c, n_sweeps, &t_inst);
+    if (rc) {
+      for (int k = 0; k < n; ++k) set_variant(P, k, dflt[k]);
+      build_buckets(c);
+      return rc;
+    }
+    for (int k = 0; k < n; ++k)
+      if (timed[k]) ms[(size_t)k * nv + v] = t_inst[k];
+  }
+  FILE* out = cache_path ? std::fopen(cache_path, "a") : nullptr;
+  for (int k = 0; k < n; ++k) {
+    if (chosen[k] < 0) {
+      int best = dflt[k];
+      double bm = INFINITY;
+      for (int v = 0; v < nv; ++v) {
+        const double t = ms[(size_t)k * nv + v];
+        if (t == t && t < bm) {
+          bm = t;
+          best = v;
+        }
+      }
+      chosen[k] = best;
+      if (out) std::fprintf(out, "%s %d\n", key(k).c_str(), best);
+    }
+    set_variant(P, k, chosen[k]);
+  }
+  if (out) std::fclose(out);
+  build_buckets(c);
+  HIPCHK(c, hipMemsetAsync(c->P.accepted, 0, 8 * P.W, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (h_ms) std::memcpy(h_ms, ms.data(), ms.size() * sizeof(double));
+  return MVMC_OK;
+}
+
+int mvmc_sweep_variants(const mvmc_ctx* c, int32_t* h_variant) {
+  if (!c || !h_variant) return MVMC_E_ARG;
+  for (int k = 0; k < c->cfg.n_instances; ++k) h_variant[k] = variant_of(c->plan, k);
   return MVMC_OK;
 }
 

@@ -243,6 +243,12 @@ template <typename T>
 static void refresh_impl(const Pools& P, const int32_t* wlist, int n, int max_ne, int max_ns,
                          bool lds, double sing_tol, int32_t* flags, hipStream_t s) {
   if (n <= 0) return;
+  // up to 64 electrons per spin: the anti-parallel block route, one
+  // wavefront per walker with the block in registers
+  if (refresh_ap_fits(max_ne, max_ns)) {
+    launch_refresh_ap<T>(P, wlist, n, max_ne, max_ns, sing_tol, flags, s);
+    return;
+  }
   const size_t sh = refresh_lds_bytes(max_ne, max_ns, lds);
   if (lds) {
     if (sh > 65536)

@@ -216,7 +216,8 @@ __global__ __launch_bounds__(NT) void k_sweep(Pools P, const int32_t* __restrict
       T* Yr = Y + rr * ne;
       for (int c = lane; c < ne; c += 64) Yr[c] += pr * qv[c] - qr * pv[c];
     }
-    for (int l = tid; l < ns; l += NT) hs[l] += V[(int64_t)l * ns + site_new] - V[(int64_t)l * ns + site_old];
+    // V is symmetric: row site_new read across the threads is coalesced
+    for (int l = tid; l < ns; l += NT) hs[l] += V[(int64_t)site_new * ns + l] - V[(int64_t)site_old * ns + l];
     for (int hh = tid; hh < M; hh += NT)
       ths[hh] += T(2) * (rW[(int64_t)hh * n2 + Inew] - rW[(int64_t)hh * n2 + Iold]);
     if (tid == 0) {

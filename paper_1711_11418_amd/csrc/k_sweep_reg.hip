@@ -20,10 +20,12 @@
 // scalar registers (Philox runs on the scalar unit), so the proposal loop has
 // no workgroup barrier.
 #include "launch.h"
+#include "wave.h"
 
 namespace mvmc {
 
 namespace {
+using namespace wave;
 
 __host__ __device__ inline size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
 
@@ -38,34 +40,6 @@ __host__ __device__ inline size_t reg_walker_bytes(int ne_max, int ns, int M, si
   return a16(3 * (size_t)ne_max * ts) + a16(2 * (size_t)ne_max * sizeof(double)) +
          a16((size_t)ns * sizeof(double)) + a16((size_t)M * ts) +
          a16((size_t)(4 * ns + ne_max) * sizeof(int32_t));
-}
-
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ double dpp_d(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-
-// Sum over the 64 lanes: butterflies inside each row of 16 (quad_perm,
-// half-row and row mirrors), then the row sums are carried up by the row
-// broadcasts; lane 63 ends with the total, which is read back as a scalar.
-__device__ __forceinline__ double wave_total(double v) {
-  v += dpp_d<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
-  v += dpp_d<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
-  v += dpp_d<0x141, 0xF>(v);   // row_half_mirror
-  v += dpp_d<0x140, 0xF>(v);   // row_mirror
-  v += dpp_d<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
-  v += dpp_d<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
-  return __hiloint2double(hi, lo);
 }
 
 // y[a] for a uniform runtime index a, as a branch tree over compile-time
@@ -84,45 +58,10 @@ __device__ __forceinline__ T pick(const T (&y)[N], int a) {
   }
 }
 
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ double dpp_keep(double v) {
-  // lanes outside the row mask keep their own value
-  const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, ROWMASK,
-                                             0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), CTRL, ROWMASK,
-                                             0xF, false);
-  return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double wave_max(double v) {
-  v = fmax(v, dpp_keep<0xB1, 0xF>(v));
-  v = fmax(v, dpp_keep<0x4E, 0xF>(v));
-  v = fmax(v, dpp_keep<0x141, 0xF>(v));
-  v = fmax(v, dpp_keep<0x140, 0xF>(v));
-  v = fmax(v, dpp_keep<0x142, 0xA>(v));
-  v = fmax(v, dpp_keep<0x143, 0xC>(v));
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
-  return __hiloint2double(hi, lo);
-}
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ int dpp_keep_i(int v) {
-  return __builtin_amdgcn_update_dpp(v, v, CTRL, ROWMASK, 0xF, false);
-}
-__device__ __forceinline__ int wave_min_i(int v) {
-  v = min(v, dpp_keep_i<0xB1, 0xF>(v));
-  v = min(v, dpp_keep_i<0x4E, 0xF>(v));
-  v = min(v, dpp_keep_i<0x141, 0xF>(v));
-  v = min(v, dpp_keep_i<0x140, 0xF>(v));
-  v = min(v, dpp_keep_i<0x142, 0xA>(v));
-  v = min(v, dpp_keep_i<0x143, 0xC>(v));
-  return __builtin_amdgcn_readlane(v, 63);
-}
-
 template <typename T> __device__ __forceinline__ const T* rbmT_ptr(const Pools& P);
 template <> __device__ __forceinline__ const double* rbmT_ptr<double>(const Pools& P) { return P.rbmT64; }
 template <> __device__ __forceinline__ const float* rbmT_ptr<float>(const Pools& P) { return P.rbmT32; }
 
-__device__ __forceinline__ int sgpr(int v) { return __builtin_amdgcn_readfirstlane(v); }
 // Uniform value the optimiser may not look through (keeps branch-tree tests
 // as 32-bit scalar compares).
 __device__ __forceinline__ int opaque(int v) {

@@ -18,6 +18,12 @@ void launch_set_target(const Pools& P, uint64_t* target, int64_t W, int n_sweeps
 
 // k_refresh.hip: full double-precision X^-1, log|Pf|, sign, Jastrow field and
 // RBM angles for the walkers in wlist.  T is the walker-matrix type.
+// Refresh through the anti-parallel block M (N_e <= 128): X^-1 and Pf(X)
+// from M^-1 and det M.
+bool refresh_ap_fits(int max_ne, int max_ns);
+template <typename T>
+void launch_refresh_ap(const Pools& P, const int32_t* wlist, int n, int max_ne, int max_ns,
+                       double sing_tol, int32_t* flags, hipStream_t s);
 template <typename T>
 void launch_refresh(const Pools& P, const int32_t* wlist, int n, int max_ne, int max_ns,
                     bool lds, double sing_tol, hipStream_t s);

@@ -1,0 +1,75 @@
+// Wavefront-level helpers shared by the per-walker kernels (wave64, DPP).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace mvmc {
+namespace wave {
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes: butterflies inside each row of 16 (quad_perm,
+// half-row and row mirrors), then the row sums are carried up by the row
+// broadcasts; lane 63 ends with the total, which is read back as a scalar.
+__device__ __forceinline__ double wave_total(double v) {
+  v += dpp_d<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+  v += dpp_d<0x141, 0xF>(v);   // row_half_mirror
+  v += dpp_d<0x140, 0xF>(v);   // row_mirror
+  v += dpp_d<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_d<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_keep(double v) {
+  // lanes outside the row mask keep their own value
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, ROWMASK,
+                                             0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), CTRL, ROWMASK,
+                                             0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, dpp_keep<0xB1, 0xF>(v));
+  v = fmax(v, dpp_keep<0x4E, 0xF>(v));
+  v = fmax(v, dpp_keep<0x141, 0xF>(v));
+  v = fmax(v, dpp_keep<0x140, 0xF>(v));
+  v = fmax(v, dpp_keep<0x142, 0xA>(v));
+  v = fmax(v, dpp_keep<0x143, 0xC>(v));
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ int dpp_keep_i(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, ROWMASK, 0xF, false);
+}
+__device__ __forceinline__ int wave_min_i(int v) {
+  v = min(v, dpp_keep_i<0xB1, 0xF>(v));
+  v = min(v, dpp_keep_i<0x4E, 0xF>(v));
+  v = min(v, dpp_keep_i<0x141, 0xF>(v));
+  v = min(v, dpp_keep_i<0x140, 0xF>(v));
+  v = min(v, dpp_keep_i<0x142, 0xA>(v));
+  v = min(v, dpp_keep_i<0x143, 0xC>(v));
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
+
+__device__ __forceinline__ int sgpr(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+}  // namespace wave
+}  // namespace mvmc
