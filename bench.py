@@ -53,11 +53,13 @@ def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", 
     insts = wl["instances"]
     params = np.concatenate([i.params0 for i in insts])
     sweeps = wl["sweeps"]
+    every = wl.get("sample_every", 1)   # sweeps between samples
+    slots = sweeps // every
     side = torch.cuda.Stream()
     tuned = None
     with torch.cuda.stream(side):
         ctx = MVMC(insts, params, precision=precision, refresh_every=refresh_every,
-                   seed=wl["sampler_seed"], n_slots=sweeps, solver=solver, build_s=True,
+                   seed=wl["sampler_seed"], n_slots=slots, solver=solver, build_s=True,
                    sweep_threads=sweep_threads, stream=side)
         for _ in range(wl["warmup"]):   # one launch per sweep, as in the timed steps
             ctx.sample_async(1)
@@ -69,16 +71,16 @@ def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", 
 
         def sampling(profile=False):
             acc = 0
-            for s in range(sweeps):
+            for s in range(slots):
                 if profile:
-                    acc += int(np.sum(ctx.sample(1)))
+                    acc += int(np.sum(ctx.sample(every)))
                 else:
-                    ctx.sample_async(1)
+                    ctx.sample_async(every)
                 ctx.measure(s)
             return acc
 
         def sr():
-            E, V = ctx.build_sr(sweeps)
+            E, V = ctx.build_sr(slots)
             ctx.sr_update(dtau=wl["dtau"], eps_rel=wl["eps_rel"], eps_abs=wl["eps_abs"],
                           solver=solver)
             return [float(e) for e in E]
@@ -89,7 +91,7 @@ def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", 
         graph = None
         if use_graph:
             torch.cuda.synchronize()
-            graph = ctx.capture_sampling(1, range(sweeps))
+            graph = ctx.capture_sampling(every, range(slots))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         energies = []
@@ -118,9 +120,35 @@ def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", 
         "energies": [e[0] for e in energies] if len(insts) == 1 else energies,
         "accept_ratio": accepted / (sweeps * per_sweep), "kernel_ms": ms.tolist(),
         "kernel_calls": calls.tolist(), "W": i0.n_walkers, "ne": i0.n_elec, "np": i0.n_params,
-        "sweeps": sweeps, "N": sweeps * i0.n_walkers, "graph": graph is not None,
+        "sweeps": sweeps, "N": slots * i0.n_walkers, "graph": graph is not None,
         "autotune": tuned,
     }
+
+
+def precision_leg(steps):
+    """10x10 Hubbard, U = 8, N_e = 100, unconstrained f (N_p = 10002), 4096
+    walkers, 10 sweeps and one sample per walker per SR step, S and a
+    Cholesky solve: the mixed path (single-precision sweeps, double
+    refresh every 32 proposals, split-bf16 S) against the plain double path
+    (refresh every 4 sweeps, double S), same kernels otherwise."""
+    from mvmc_inputs import workload
+    out = {}
+    for prec, R in (("mixed", 32), ("fp64", 400)):
+        wl = workload("c3_sq10_mixed", warmup=20)
+        log(f"[bench]   10x10 {prec} (refresh every {R})")
+        r = run_sr_workload(wl, prec, steps, 1, R, solver="chol")
+        i0 = wl["instances"][0]
+        km = dict(zip(["sweep", "refresh", "measure", "sr_stats", "s_build", "sr_solve"],
+                      r["kernel_ms"]))
+        N, npar = r["N"], r["np"]
+        out[prec] = {"value": r["rate"], "unit": "hop-updates/s", "ms_per_step": r["ms_per_step"],
+                     "accept_ratio": r["accept_ratio"], "kernel_ms_per_step": km,
+                     "s_build_tflops": N * npar * (npar + 1) / (km["s_build"] * 1e-3) / 1e12,
+                     "energy_per_site": [e / i0.n_sites for e in r["energies"]]}
+    out["speedup_mixed_vs_fp64"] = out["mixed"]["value"] / out["fp64"]["value"]
+    out["s_build_speedup_mixed_vs_fp64"] = (out["fp64"]["kernel_ms_per_step"]["s_build"] /
+                                            out["mixed"]["kernel_ms_per_step"]["s_build"])
+    return out
 
 
 def batch_leg(steps):
@@ -377,6 +405,8 @@ def main():
                         "kernel_ms_per_step": m["kernel_ms"]}
         log("[bench] split-bf16 S build at 4096 x 10^4")
         out["s_build_bf16x3_c3"] = s_build_leg()
+        log("[bench] 10x10 precision leg: mixed vs plain FP64")
+        out["sq10_mixed_vs_fp64"] = precision_leg(2)
         log("[bench] ragged batch of 32 clusters (mixed, autotuned)")
         out["batch32_mixed"] = batch_leg(max(1, a.steps - 1))
     if not a.no_cpu:
