@@ -79,10 +79,14 @@ def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", 
                 ctx.measure(s)
             return acc
 
+        escalations = []
+
         def sr():
             E, V = ctx.build_sr(slots)
-            ctx.sr_update(dtau=wl["dtau"], eps_rel=wl["eps_rel"], eps_abs=wl["eps_abs"],
-                          solver=solver)
+            it = ctx.sr_update(dtau=wl["dtau"], eps_rel=wl["eps_rel"], eps_abs=wl["eps_abs"],
+                               solver=solver)
+            if solver == "chol":
+                escalations.append(int(np.max(it)))
             return [float(e) for e in E]
 
         for _ in range(warmup):
@@ -121,7 +125,7 @@ def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", 
         "accept_ratio": accepted / (sweeps * per_sweep), "kernel_ms": ms.tolist(),
         "kernel_calls": calls.tolist(), "W": i0.n_walkers, "ne": i0.n_elec, "np": i0.n_params,
         "sweeps": sweeps, "N": slots * i0.n_walkers, "graph": graph is not None,
-        "autotune": tuned,
+        "autotune": tuned, "cholesky_shift_raises": escalations,
     }
 
 
@@ -144,6 +148,7 @@ def precision_leg(steps):
         out[prec] = {"value": r["rate"], "unit": "hop-updates/s", "ms_per_step": r["ms_per_step"],
                      "accept_ratio": r["accept_ratio"], "kernel_ms_per_step": km,
                      "s_build_tflops": N * npar * (npar + 1) / (km["s_build"] * 1e-3) / 1e12,
+                     "cholesky_shift_raises": r["cholesky_shift_raises"],
                      "energy_per_site": [e / i0.n_sites for e in r["energies"]]}
     out["speedup_mixed_vs_fp64"] = out["mixed"]["value"] / out["fp64"]["value"]
     out["s_build_speedup_mixed_vs_fp64"] = (out["fp64"]["kernel_ms_per_step"]["s_build"] /

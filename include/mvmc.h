@@ -206,9 +206,15 @@ int mvmc_build_sr(mvmc_ctx *ctx, int32_t n_slots_used, const double *d_eloc, voi
  * |r|^2 < cg_tol^2 |g|^2 or after cg_maxit iterations); then
  * d_params += d_dparams = -dtau x (Eq. SR_equation_system), re-expands the
  * tables and recomputes every walker's X^-1 in double.
- * h_cg_iters (may be NULL): [n_instances].  d_dparams may be NULL.
+ * Cholesky: when S_reg is not numerically positive definite (possible when S
+ * has fewer samples than parameters and is built in reduced precision), the
+ * shift eps_rel is raised tenfold and the factorisation repeated, at most 4
+ * times, for every instance of the context.
+ * h_cg_iters (may be NULL): [n_instances] CG iterations, or for the Cholesky
+ * solver the number of tenfold raises of eps_rel (0: the caller's value).
+ * d_dparams may be NULL.
  * Errors: MVMC_E_STATE (build_sr not called), MVMC_E_SINGULAR (Cholesky failed
- * or a walker's X became singular), MVMC_E_NONFINITE.
+ * after the raises, or a walker's X became singular), MVMC_E_NONFINITE.
  */
 int mvmc_sr_update(mvmc_ctx *ctx, const void *d_S, const void *d_O, const double *d_g, double dtau,
                    double eps_rel, double eps_abs, int32_t solver, double cg_tol, int32_t cg_maxit,

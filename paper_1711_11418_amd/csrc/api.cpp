@@ -27,6 +27,7 @@ constexpr int kMaxSites = 1024;
 constexpr int kMaxElec = 2048;
 constexpr int kTimingCats = 6;
 constexpr int kRegWpb = 4;   // walkers per workgroup of the register sweep
+constexpr int kMaxShiftEscalations = 4;   // Cholesky retries with eps_rel x 10 each
 
 inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
 
@@ -1206,25 +1207,40 @@ int mvmc_sr_update(mvmc_ctx* c, const void* d_S, const void* d_O, const double* 
   if (solver == MVMC_SOLVE_CHOL) {
     if (!d_S || c->cfg.solver != MVMC_SOLVE_CHOL)
       return set_err(c, fail(MVMC_E_STATE, "Cholesky needs d_S and a context built for it"));
-    for (int k = 0; k < n; ++k) {
-      HIPCHK(c, hipMemsetAsync(c->SA.scal + k * kScal + kFlag, 0, 8, c->stream));
+    // A rank-deficient S (fewer samples than parameters) built in reduced
+    // precision can leave S_reg short of numerical positive definiteness;
+    // then the diagonal shift eps_rel is raised tenfold and the
+    // factorisation repeated (from S, which it does not overwrite).
+    double eps = eps_rel;
+    int escalations = 0;
+    for (;;) {
+      for (int k = 0; k < n; ++k) {
+        HIPCHK(c, hipMemsetAsync(c->SA.scal + k * kScal + kFlag, 0, 8, c->stream));
+      }
+      const int id = tic(c, 5);
+      if (mixed)
+        sr_cholesky_solve<float>(c->SA, (const float*)d_S, d_g, eps, eps_abs, freeze, n,
+                                 P.max_np, c->stream);
+      else
+        sr_cholesky_solve<double>(c->SA, (const double*)d_S, d_g, eps, eps_abs, freeze, n,
+                                  P.max_np, c->stream);
+      toc(c, id);
+      LAUNCHCHK(c);
+      HIPCHK(c, hipMemcpyAsync(sc.data(), c->SA.scal, 8 * sc.size(), hipMemcpyDeviceToHost,
+                               c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      int bad = -1;
+      for (int k = 0; k < n && bad < 0; ++k)
+        if (sc[k * kScal + kFlag] != 0.0) bad = k;
+      if (bad < 0) break;
+      if (escalations == kMaxShiftEscalations || !(eps > 0))
+        return set_err(c, fail(MVMC_E_SINGULAR, "instance %d: S_reg not positive definite "
+                                                "(eps_rel raised to %g)", bad, eps));
+      eps *= 10.0;
+      ++escalations;
     }
-    const int id = tic(c, 5);
-    if (mixed)
-      sr_cholesky_solve<float>(c->SA, (const float*)d_S, d_g, eps_rel, eps_abs, freeze, n, P.max_np,
-                               c->stream);
-    else
-      sr_cholesky_solve<double>(c->SA, (const double*)d_S, d_g, eps_rel, eps_abs, freeze, n,
-                                P.max_np, c->stream);
-    toc(c, id);
-    LAUNCHCHK(c);
-    HIPCHK(c, hipMemcpyAsync(sc.data(), c->SA.scal, 8 * sc.size(), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (int k = 0; k < n; ++k)
-      if (sc[k * kScal + kFlag] != 0.0)
-        return set_err(c, fail(MVMC_E_SINGULAR, "instance %d: S_reg not positive definite", k));
     if (h_cg_iters)
-      for (int k = 0; k < n; ++k) h_cg_iters[k] = 0;
+      for (int k = 0; k < n; ++k) h_cg_iters[k] = escalations;
   } else if (solver == MVMC_SOLVE_CG) {
     if (!d_O) return set_err(c, fail(MVMC_E_ARG, "CG needs the centred O"));
     if (cg_maxit < 1 || !(cg_tol > 0)) return set_err(c, fail(MVMC_E_ARG, "cg_maxit >= 1 and cg_tol > 0"));

@@ -218,6 +218,124 @@ __global__ __launch_bounds__(64) void k_syrk_mfma128(SrArgs A, const uint16_t* _
       }
 }
 
+// Wide parameter sets, LDS-staged: one workgroup of four wavefronts per
+// 128 x 128 tile of the upper triangle, each wavefront a 64 x 64 quadrant
+// (2 x 2 blocks of 32 x 32 accumulators).  Panels of 32 samples (four
+// groups of 8) of the two 128-parameter ranges, hi and lo, pass from global
+// memory through registers into one of two LDS buffers: the next panel's
+// global loads are in flight while the current panel's products issue.
+// Sample groups past the last multiple of 16 samples read as zero.
+namespace {
+constexpr int kStageVecs = 4 * 4 * 128;   // [hiA | loA | hiB | loB][group][parameter]
+__device__ __forceinline__ void mfma_quad(f32x16 (&acc)[2][2], const bf16x8 (&ah)[2],
+                                          const bf16x8 (&al)[2], const bf16x8 (&bh)[2],
+                                          const bf16x8 (&bl)[2]) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+}
+}  // namespace
+
+__global__ __launch_bounds__(256) void k_syrk_lds128(SrArgs A, const uint16_t* __restrict__ split,
+                                                     float* __restrict__ S) {
+  const SrInst& I = A.inst[blockIdx.y];
+  if (!I.tile128) return;
+  const int nt = (int)ceil_div<int64_t>(I.np, kT2);
+  if ((int)blockIdx.x >= nt * (nt + 1) / 2) return;
+  int ti, tj;
+  tile_index(blockIdx.x, nt, ti, tj);
+  const int64_t ld = I.ldO, np = I.np, rows = I.rows;
+  const int64_t ng = (rows + 15) / 16 * 2;   // groups of 8 samples in use
+  const uint16_t* hi = split + I.split_off;
+  const uint16_t* lo = hi + I.split_rows * ld;
+  const int64_t p0 = (int64_t)ti * kT2, q0 = (int64_t)tj * kT2;
+  __shared__ u16x8 stage[2][kStageVecs];
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, m = lane & 31, kh = lane >> 5;
+  const int qi = wv >> 1, qj = wv & 1;
+
+  u16x8 reg[8];
+  auto gload = [&](int64_t kg0) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int v = tid + 256 * e;
+      const int arr = v >> 9, g = (v >> 7) & 3, p = v & 127;
+      const int64_t kg = kg0 + g;
+      const int64_t col = (arr < 2 ? p0 : q0) + p;
+      const uint16_t* base = (arr & 1) ? lo : hi;
+      u16x8 z = {0, 0, 0, 0, 0, 0, 0, 0};
+      reg[e] = kg < ng ? *reinterpret_cast<const u16x8*>(base + (kg * ld + col) * 8) : z;
+    }
+  };
+  auto lstore = [&](int b) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) stage[b][tid + 256 * e] = reg[e];
+  };
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  int b = 0;
+  for (int64_t kg0 = 0; kg0 < ng; kg0 += 4) {
+    const bool more = kg0 + 4 < ng;
+    if (more) gload(kg0 + 4);
+#pragma unroll
+    for (int sub = 0; sub < 2; ++sub) {
+      const int g = 2 * sub + kh;
+      bf16x8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int pa = g * 128 + 64 * qi + 32 * i + m, pb = g * 128 + 64 * qj + 32 * i + m;
+        ah[i] = __builtin_bit_cast(bf16x8, stage[b][pa]);
+        al[i] = __builtin_bit_cast(bf16x8, stage[b][512 + pa]);
+        bh[i] = __builtin_bit_cast(bf16x8, stage[b][1024 + pb]);
+        bl[i] = __builtin_bit_cast(bf16x8, stage[b][1536 + pb]);
+      }
+      mfma_quad(acc, ah, al, bh, bl);
+    }
+    if (more) lstore(b ^ 1);
+    __syncthreads();
+    b ^= 1;
+  }
+  // accumulator r of lane l holds D[row][col], col = l % 32,
+  // row = 8 (r / 4) + 4 (l / 32) + r % 4
+  const float invN = (float)(1.0 / (double)rows);
+  float* Sb = S + I.S_off;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t row = p0 + 64 * qi + 32 * i + 8 * (r >> 2) + 4 * kh + (r & 3);
+        const int64_t col = q0 + 64 * qj + 32 * j + m;
+        if (row < np && col < np && (ti != tj || row <= col)) {
+          const float v = acc[i][j][r] * invN;
+          Sb[row * np + col] = v;
+          Sb[col * np + row] = v;
+        }
+      }
+}
+
 __global__ void k_syrk_split_reduce(SrArgs A, float* __restrict__ S) {
   const SrInst& I = A.inst[blockIdx.y];
   if (I.ksplit == 1) return;   // written directly by the tile kernel
@@ -249,7 +367,7 @@ void sr_syrk_bf16x3(const SrArgs& A, const uint16_t* split, float* S, int n_inst
   hipLaunchKernelGGL(k_syrk_split_reduce, dim3(ntiles, n_inst), dim3(256), 0, s, A, S);
   const int nt2 = (int)ceil_div<int64_t>(max_np, kT2);
   if (nt2 * (nt2 + 1) / 2 >= 512)
-    hipLaunchKernelGGL(k_syrk_mfma128, dim3(nt2 * (nt2 + 1) / 2, n_inst), dim3(64), 0, s, A,
+    hipLaunchKernelGGL(k_syrk_lds128, dim3(nt2 * (nt2 + 1) / 2, n_inst), dim3(256), 0, s, A,
                        split, S);
 }
 
