@@ -39,7 +39,7 @@ def log(msg):
 
 
 def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", sweep_threads=0,
-                    use_graph=True, autotune=False):
+                    use_graph=True, autotune=False, build_s=True, cg_tol=1e-10, cg_maxit=1000):
     """Time whole SR steps of every instance of the workload.  With use_graph
     the sampling part of a step (the sweeps and the measurement after each
     of them) is captured once into a HIP graph and replayed; the SR build and
@@ -59,7 +59,7 @@ def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", 
     tuned = None
     with torch.cuda.stream(side):
         ctx = MVMC(insts, params, precision=precision, refresh_every=refresh_every,
-                   seed=wl["sampler_seed"], n_slots=slots, solver=solver, build_s=True,
+                   seed=wl["sampler_seed"], n_slots=slots, solver=solver, build_s=build_s,
                    sweep_threads=sweep_threads, stream=side)
         for _ in range(wl["warmup"]):   # one launch per sweep, as in the timed steps
             ctx.sample_async(1)
@@ -81,12 +81,16 @@ def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", 
 
         escalations = []
 
+        cg_iters = []
+
         def sr():
-            E, V = ctx.build_sr(slots)
+            E, V = ctx.build_sr(slots, with_S=build_s)
             it = ctx.sr_update(dtau=wl["dtau"], eps_rel=wl["eps_rel"], eps_abs=wl["eps_abs"],
-                               solver=solver)
+                               solver=solver, cg_tol=cg_tol, cg_maxit=cg_maxit)
             if solver == "chol":
                 escalations.append(int(np.max(it)))
+            else:
+                cg_iters.append(int(np.max(it)))
             return [float(e) for e in E]
 
         for _ in range(warmup):
@@ -125,7 +129,7 @@ def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", 
         "accept_ratio": accepted / (sweeps * per_sweep), "kernel_ms": ms.tolist(),
         "kernel_calls": calls.tolist(), "W": i0.n_walkers, "ne": i0.n_elec, "np": i0.n_params,
         "sweeps": sweeps, "N": slots * i0.n_walkers, "graph": graph is not None,
-        "autotune": tuned, "cholesky_shift_raises": escalations,
+        "autotune": tuned, "cholesky_shift_raises": escalations, "cg_iterations": cg_iters,
     }
 
 
@@ -154,6 +158,31 @@ def precision_leg(steps):
     out["s_build_speedup_mixed_vs_fp64"] = (out["fp64"]["kernel_ms_per_step"]["s_build"] /
                                             out["mixed"]["kernel_ms_per_step"]["s_build"])
     return out
+
+
+def rbm_leg(steps):
+    """16x16 Hubbard, U = 8, N_e = 224 (1/8 hole doping), 2x2-sublattice f
+    times an RBM factor of 512 hidden units over the 512 spin-resolved
+    occupations (N_p = 264194), 8192 walkers, single-precision sweeps, 10
+    sweeps and one sample per walker per SR step, SR by CG over the centred
+    O (8192 x 264320 single precision, no explicit S); CG is capped at 50
+    iterations per step here."""
+    from mvmc_inputs import workload
+    wl = workload("c5_sq16_rbm_mixed", warmup=10)
+    r = run_sr_workload(wl, "mixed", steps, 1, 0, solver="cg", build_s=False, cg_tol=1e-6,
+                        cg_maxit=50)
+    i0 = wl["instances"][0]
+    km = dict(zip(["sweep", "refresh", "measure", "sr_stats", "s_build", "sr_solve"],
+                  r["kernel_ms"]))
+    o_bytes = r["N"] * (-(-r["np"] // 128) * 128) * 4
+    it = r["cg_iterations"][-1] if r["cg_iterations"] else 0
+    return {"value": r["rate"], "unit": "hop-updates/s", "ms_per_step": r["ms_per_step"],
+            "walkers": r["W"], "n_elec": r["ne"], "n_params": r["np"], "n_hidden": i0.n_hidden,
+            "accept_ratio": r["accept_ratio"], "kernel_ms_per_step": km,
+            "cg_iterations": r["cg_iterations"], "cg_cap": 50,
+            "cg_ms_per_iteration": km["sr_solve"] / max(it, 1),
+            "cg_gbs_per_iteration": 2 * o_bytes / (km["sr_solve"] / max(it, 1) * 1e-3) / 1e9,
+            "energy_per_site": [e / i0.n_sites for e in r["energies"]]}
 
 
 def batch_leg(steps):
@@ -412,6 +441,8 @@ def main():
         out["s_build_bf16x3_c3"] = s_build_leg()
         log("[bench] 10x10 precision leg: mixed vs plain FP64")
         out["sq10_mixed_vs_fp64"] = precision_leg(2)
+        log("[bench] 16x16 RBM leg (8192 walkers, CG)")
+        out["sq16_rbm_mixed"] = rbm_leg(1)
         log("[bench] ragged batch of 32 clusters (mixed, autotuned)")
         out["batch32_mixed"] = batch_leg(max(1, a.steps - 1))
     if not a.no_cpu:

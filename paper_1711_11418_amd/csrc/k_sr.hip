@@ -433,21 +433,59 @@ __global__ void k_dot(SrArgs A, const double* __restrict__ a, const double* __re
   if (threadIdx.x == 0) A.scal[blockIdx.x * kScal + slot] = s;
 }
 
-// t = O~ (mask o p): one wave per sample row.
+// t = O~ (mask o p).  A wavefront takes kRowsPerWave sample rows (one read
+// of mask o p serves them all) over one chunk of kColChunk parameters; wide
+// rows are split into chunks whose partial sums go to the upper third of the
+// column-statistics buffer and are added in chunk order by k_gemv_rows_finish.
+constexpr int kRowsPerWave = 4;
+constexpr int kColChunk = 4096;
+__device__ __forceinline__ int64_t row_chunks(int64_t np) { return ceil_div<int64_t>(np, kColChunk); }
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemv_rows(SrArgs A, const T* __restrict__ O) {
-  const SrInst& I = A.inst[blockIdx.y];
-  if (A.scal[blockIdx.y * kScal + kDone] != 0.0) return;
-  const int64_t m = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (m >= I.rows) return;
+  const SrInst& I = A.inst[blockIdx.z];
+  if (A.scal[blockIdx.z * kScal + kDone] != 0.0) return;
+  const int64_t nch = row_chunks(I.np);
+  if ((int64_t)blockIdx.y >= nch) return;
+  const int64_t m0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kRowsPerWave;
+  if (m0 >= I.rows) return;
   const int lane = threadIdx.x & 63;
-  const T* row = O + I.O_off + m * I.ldO;
+  const int64_t c0 = (int64_t)blockIdx.y * kColChunk;
+  const int64_t c1 = c0 + kColChunk < I.np ? c0 + kColChunk : I.np;
+  const T* row = O + I.O_off + m0 * I.ldO;
   const double* p = A.p + I.param_off;
   const double* mk = A.mask + I.param_off;
+  const int nr = I.rows - m0 < kRowsPerWave ? (int)(I.rows - m0) : kRowsPerWave;
+  double s[kRowsPerWave] = {};
+#pragma unroll 4
+  for (int64_t k = c0 + lane; k < c1; k += 64) {
+    const double pk = p[k] * mk[k];
+#pragma unroll
+    for (int r = 0; r < kRowsPerWave; ++r)
+      if (r < nr) s[r] += (double)row[r * I.ldO + k] * pk;
+  }
+  double* part = A.colpart + I.colpart_off +
+                 2 * ceil_div<int64_t>(I.rows, kRowChunk) * I.ldO;   // upper third
+#pragma unroll
+  for (int r = 0; r < kRowsPerWave; ++r) {
+    const double v = wave_sum(s[r]);
+    if (lane == 0 && r < nr) {
+      if (nch == 1) A.t[I.eloc_off + m0 + r] = v;
+      else part[(int64_t)blockIdx.y * I.rows + m0 + r] = v;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gemv_rows_finish(SrArgs A) {
+  const SrInst& I = A.inst[blockIdx.y];
+  if (A.scal[blockIdx.y * kScal + kDone] != 0.0) return;
+  const int64_t nch = row_chunks(I.np);
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (nch == 1 || m >= I.rows) return;
+  const double* part = A.colpart + I.colpart_off + 2 * ceil_div<int64_t>(I.rows, kRowChunk) * I.ldO;
   double s = 0.0;
-  for (int64_t k = lane; k < I.np; k += 64) s += (double)row[k] * (p[k] * mk[k]);
-  s = wave_sum(s);
-  if (lane == 0) A.t[I.eloc_off + m] = s;
+  for (int64_t c = 0; c < nch; ++c) s += part[c * I.rows + m];
+  A.t[I.eloc_off + m] = s;
 }
 
 // w = mask o (O~^T t) / N + shift o p, in two passes: partial sums over
@@ -613,8 +651,12 @@ template <typename T>
 void sr_cg_iter(const SrArgs& A, const T* O, int iter, int n_inst, int64_t max_np, int64_t max_rows,
                 hipStream_t s) {
   const int cb = (int)ceil_div<int64_t>(max_np, 256);
-  hipLaunchKernelGGL(k_gemv_rows<T>, dim3((unsigned)ceil_div<int64_t>(max_rows, 4), n_inst),
+  hipLaunchKernelGGL(k_gemv_rows<T>,
+                     dim3((unsigned)ceil_div<int64_t>(max_rows, 4 * kRowsPerWave),
+                          (unsigned)ceil_div<int64_t>(max_np, kColChunk), n_inst),
                      dim3(256), 0, s, A, O);
+  hipLaunchKernelGGL(k_gemv_rows_finish, dim3((unsigned)ceil_div<int64_t>(max_rows, 256), n_inst),
+                     dim3(256), 0, s, A);
   hipLaunchKernelGGL(k_gemv_cols_part<T>,
                      dim3((unsigned)ceil_div<int64_t>(max_np, 64),
                           (unsigned)ceil_div<int64_t>(max_rows, kRowChunk), n_inst),
