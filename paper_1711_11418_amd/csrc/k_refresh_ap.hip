@@ -19,6 +19,7 @@
 // h_l = sum_m v_lm (n_m - 1) and the RBM angles theta = b + W sigma.
 #include <float.h>
 
+#include "ap_block.h"
 #include "launch.h"
 #include "wave.h"
 
@@ -33,57 +34,6 @@ constexpr int kApWpb = 4;   // walkers (wavefronts) per workgroup
 __host__ __device__ inline size_t ap_walker_bytes(int ns_max, int nsmax_sites) {
   const size_t ints = (size_t)(2 * ns_max + ns_max + 2 * nsmax_sites);
   return (ns_max * sizeof(double)) + ((ints * sizeof(int32_t) + 15) & ~(size_t)15);
-}
-
-struct ApState {
-  double logabs = 0.0, sgn = 1.0, minpiv = DBL_MAX;
-  uint64_t used = 0;   // rows pivoted so far
-  int parity = 0;
-  bool singular = false;
-};
-
-// Exchange step K (column K), then the next one: compile-time recursion, so
-// every m[K] is a constant register index whatever the unroll heuristics.
-template <int K, int NS>
-__device__ __forceinline__ void ap_steps(ApState& st, double (&m)[NS], double* rowp,
-                                         int32_t* piv, int lane, bool live, int nh,
-                                         double tol) {
-  if constexpr (K < NS) {
-    if (K < nh && !st.singular) {
-      const bool free_row = live && !((st.used >> lane) & 1ull);
-      const double v = free_row ? fabs(m[K]) : -1.0;
-      const double vmax = wave_max(v);
-      const int p = wave_min_i(v == vmax ? lane : (1 << 30));
-      if (!(vmax > tol) || p >= nh) {
-        st.singular = true;
-      } else {
-        const int xlo = __builtin_amdgcn_readlane(__double2loint(m[K]), p);
-        const int xhi = __builtin_amdgcn_readlane(__double2hiint(m[K]), p);
-        const double pv = __hiloint2double(xhi, xlo);
-        st.logabs += log(fabs(pv));
-        if (pv < 0.0) st.sgn = -st.sgn;
-        st.minpiv = fmin(st.minpiv, fabs(pv));
-        st.parity += __builtin_popcountll(~st.used & ((1ull << p) - 1ull));
-        st.used |= 1ull << p;
-        const bool me = lane == p;
-        if (lane == 0) piv[K] = p;
-        if (me)
-#pragma unroll
-          for (int c = 0; c < NS; ++c) rowp[c] = m[c];
-        wave_sync();
-        const double ip = 1.0 / pv;
-        const double t = m[K];
-        const double g = me ? -ip : 1.0;
-        const double f = me ? 0.0 : t * ip;
-#pragma unroll
-        for (int c = 0; c < NS; ++c)
-          if (c != K) m[c] = fma(-f, rowp[c], g * m[c]);
-        m[K] = me ? ip : t * ip;
-        wave_sync();
-      }
-    }
-    ap_steps<K + 1, NS>(st, m, rowp, piv, lane, live, nh, tol);
-  }
 }
 
 template <typename T, int NS>

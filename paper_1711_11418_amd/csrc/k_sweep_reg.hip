@@ -19,6 +19,7 @@
 // Every per-proposal quantity that is the same for the whole walker lives in
 // scalar registers (Philox runs on the scalar unit), so the proposal loop has
 // no workgroup barrier.
+#include "ap_block.h"
 #include "launch.h"
 #include "wave.h"
 
@@ -36,10 +37,14 @@ __host__ __device__ inline size_t reg_table_bytes(int ns, size_t ts) {
   (void)ts;
   return a16((size_t)ns * (ns + 1) * sizeof(double));
 }
+__host__ __device__ inline size_t reg_refresh_bytes(int ne_max) {
+  const size_t nh = (size_t)ne_max / 2;
+  return a16(nh * (nh + 1) * sizeof(double)) + a16(nh * sizeof(double)) +
+         a16(2 * nh * sizeof(int32_t));
+}
 __host__ __device__ inline size_t reg_walker_bytes(int ne_max, int ns, int M, size_t ts) {
-  return a16(3 * (size_t)ne_max * ts) + a16(2 * (size_t)ne_max * sizeof(double)) +
-         a16((size_t)ns * sizeof(double)) + a16((size_t)M * ts) +
-         a16((size_t)(4 * ns + ne_max) * sizeof(int32_t));
+  return a16(3 * (size_t)ne_max * ts) + a16((size_t)ns * sizeof(double)) + a16((size_t)M * ts) +
+         a16((size_t)(4 * ns + ne_max) * sizeof(int32_t)) + reg_refresh_bytes(ne_max);
 }
 
 // y[a] for a uniform runtime index a, as a branch tree over compile-time
@@ -84,149 +89,58 @@ constexpr int kChunk = 8;   // rows per group of broadcast loads in the update
 #define MVMC_SWEEP_INKERNEL_REFRESH 1
 #endif
 
-// Number of not yet pivoted indices strictly between i and j (i < j, both
-// below 128): moving j next to i in an order that keeps the remaining indices
-// ascending takes that many transpositions.
-__device__ __forceinline__ int unpivoted_between(uint64_t done0, uint64_t done1, int i, int j) {
-  int cnt = 0;
-#pragma unroll
-  for (int w = 0; w < 2; ++w) {
-    const int lo = max(i + 1 - 64 * w, 0), hi = min(j - 64 * w, 64);
-    if (lo < hi) {
-      const uint64_t upto = hi == 64 ? ~0ull : (1ull << hi) - 1;
-      const uint64_t bits = upto & ~((1ull << lo) - 1);
-      cnt += __builtin_popcountll(~(w ? done1 : done0) & bits);
-    }
-  }
-  return cnt;
-}
-
-// Double-precision recomputation of X^-1 for the walker of this wavefront,
-// in registers (lane c keeps column c, m[k][r] = M[r][c] for c = lane + 64k),
-// by the in-place skew Gauss-Jordan elimination of the refresh kernel: pivot
-// block K = {i, j}, x = M[i][j], P^-1 = [[0, -1/x], [1/x, 0]],
-//   M_Kc <- P^-1 M_Kc,  M_rK <- -M_rK P^-1,  M_rc <- M_rc - M_rK P^-1 M_Kc.
-// With rows i and j broadcast through LDS (M[i][r] and M[j][r]), lane c
-// updates its whole column as
-//   m[r] <- g m[r] + a M[j][r] + b M[i][r],
-//   (g, a, b) = (1, M[i][c]/x, -M[j][c]/x) off the pivot columns,
-//               (0, 1/x, 0) for c = i,  (0, 0, -1/x) for c = j.
-// Broadcasting 1 in place of the diagonal entries M[i][i] and M[j][j] makes
-// that one formula also produce the new pivot rows (P^-1 M_Kc) on every
-// column; the only entries it gets wrong are the two diagonal ones of the
-// pivot columns, which no later step reads, and the diagonal of the skew
-// inverse is set to zero at the end.  i is the first index not yet pivoted
-// and j maximises |M[i][c]| over the rest (lowest c on ties), so
-// Pf(X) = sgn(pi) prod_k x_k with the sign of the pivot order counted as it
-// is built.
-template <int NE_MAX, int KC>
-__device__ __forceinline__ int reg_refresh(double (&m)[KC][NE_MAX], const int (&posr)[KC],
-                                           const double* __restrict__ fs, int ldf, int ns, int ne,
-                                           int lane, int32_t* posl, double2* s2, double& logabs,
-                                           double& sgn) {
-#pragma unroll
-  for (int k = 0; k < KC; ++k)
-    if (lane + 64 * k < NE_MAX) posl[lane + 64 * k] = posr[k];
+// Double-precision recomputation inside the launch through the
+// anti-parallel block (Eq. AP-Pf): the n = N_e/2 rows of M sit one per lane
+// during the exchange steps (ap_steps); the final tableau then goes through
+// LDS and every lane rebuilds its column c of X^-1 = [[0, -M^-T], [M^-1, 0]]:
+//   c an up electron:          X^-1[n + a][c] = M^-1[a][c]
+//   c = n + a' a down one:     X^-1[q][c]     = -M^-1[a'][q]
+// with M^-1[a][p_b] = T[p_a][b]; same-spin blocks are zero.
+template <int NE_MAX, typename T>
+__device__ __forceinline__ int reg_refresh_ap(T (&y)[1][NE_MAX], int posr0,
+                                              const double* __restrict__ fs, int ldf, int ns,
+                                              int ne, int lane, int32_t* posl, double* tab,
+                                              double* rowp, int32_t* piv, int32_t* pinv,
+                                              double& logabs, double& sgn) {
+  constexpr int NH = NE_MAX / 2;
+  constexpr int LDT = NH + 1;
+  int nh = ne / 2;
+  asm volatile("" : "+s"(nh));   // keep the per-index compares inside this call
+  if (lane < NE_MAX) posl[lane] = posr0;
   wave_sync();
-  // X[r][c] = A[I_r][I_c]: f(site_r, site_c) when r is up and c down, minus
-  // f(site_c, site_r) when r is down and c up, zero between equal spins.
-  // The row bound goes through an opaque move so that the per-row compares
-  // stay here instead of being hoisted out of the caller's loop.
-  int nel = ne;
-  asm volatile("" : "+s"(nel));
+  const bool live = lane < nh;
+  const int su = live ? posr0 : 0;   // site of up electron `lane`
+  double m[NH];
 #pragma unroll
-  for (int k = 0; k < KC; ++k) {
-    const int c = lane + 64 * k, pc = posr[k];
-    const bool cup = pc < ns;
-    const int base = cup ? pc * ldf - ns : pc - ns;
-    const double w = cup ? -1.0 : 1.0;
-#pragma unroll
-    for (int r0 = 0; r0 < NE_MAX; r0 += kChunk) {
-#pragma unroll
-      for (int r = r0; r < r0 + kChunk && r < NE_MAX; ++r) {
-        const int pr = posl[r];
-        const bool rup = pr < ns;
-        const bool live = r < nel && c < ne && rup != cup;
-        const int addr = rup ? pr * ldf + base : base + pr;
-        const double t = fs[live ? addr : 0];
-        m[k][r] = live ? w * t : 0.0;
-      }
-      asm volatile("" ::: "memory");
-    }
+  for (int b = 0; b < NH; ++b) {
+    const bool in = live && b < nh;
+    const int sd = in ? posl[nh + b] - ns : 0;
+    m[b] = in ? fs[su * ldf + sd] : 0.0;
   }
-  uint64_t done0 = 0, done1 = 0;
-  int parity = 0;
-  logabs = 0.0;
-  sgn = 1.0;
-  for (int step = 0; step < ne / 2; ++step) {
-    const int i = done0 != ~0ull ? __builtin_ctzll(~done0) : 64 + __builtin_ctzll(~done1);
-    double ri[KC], rj[KC];
-    double best = -1.0;
-    int bc = 1 << 30;
+  ApState st;
+  ap_steps<0, NH>(st, m, rowp, piv, lane, live, nh, 0.0);
+  if (st.singular) return 1;
+  logabs = st.logabs;
+  sgn = st.sgn;
+  if (st.parity & 1) sgn = -sgn;
+  if (((nh * (nh - 1)) / 2) & 1) sgn = -sgn;   // Pf(X) = (-1)^{n(n-1)/2} det M
+  if (live) {
 #pragma unroll
-    for (int k = 0; k < KC; ++k) {
-      ri[k] = pick<double, NE_MAX, 0, NE_MAX>(m[k], i);
-      const int c = lane + 64 * k;
-      const bool piv = c < 64 ? ((done0 >> c) & 1) : ((done1 >> (c - 64)) & 1);
-      const double v = (c < ne && !piv && c != i) ? fabs(ri[k]) : -1.0;
-      if (v > best) {
-        best = v;
-        bc = c;
-      }
-    }
-    const double vmax = wave_max(best);
-    const int j = wave_min_i(best == vmax ? bc : (1 << 30));
-    if (!(vmax > 0.0) || j >= ne) return 1;   // singular
-    const int kj = j >> 6;
-    double xij = 0.0;
-#pragma unroll
-    for (int k = 0; k < KC; ++k)
-      if (k == kj) xij = ri[k];
-    const int xlo = __builtin_amdgcn_readlane(__double2loint(xij), j & 63);
-    const int xhi = __builtin_amdgcn_readlane(__double2hiint(xij), j & 63);
-    const double x = __hiloint2double(xhi, xlo);
-    logabs += log(fabs(x));
-    if (x < 0.0) sgn = -sgn;
-    parity += unpivoted_between(done0, done1, i, j);
-    if (i < 64) done0 |= 1ull << i; else done1 |= 1ull << (i - 64);
-    if (j < 64) done0 |= 1ull << j; else done1 |= 1ull << (j - 64);
-    const double ix = 1.0 / x;
-#pragma unroll
-    for (int k = 0; k < KC; ++k) {
-      rj[k] = pick<double, NE_MAX, 0, NE_MAX>(m[k], j);
-      const int c = lane + 64 * k;
-      if (c < NE_MAX) s2[c] = make_double2(c == i ? 1.0 : ri[k], c == j ? 1.0 : rj[k]);
-    }
-    wave_sync();
-#pragma unroll
-    for (int k = 0; k < KC; ++k) {
-      const int c = lane + 64 * k;
-      const bool isI = c == i, isJ = c == j;
-      const double g = (isI || isJ) ? 0.0 : 1.0;
-      const double a = isI ? ix : (isJ ? 0.0 : ri[k] * ix);
-      const double b = isJ ? -ix : (isI ? 0.0 : -rj[k] * ix);
-#pragma unroll
-      for (int r0 = 0; r0 < NE_MAX; r0 += kChunk) {
-#pragma unroll
-        for (int r = r0; r < r0 + kChunk && r < NE_MAX; ++r) {
-          const double2 t = s2[r];
-          m[k][r] = fma(a, t.y, fma(b, t.x, g * m[k][r]));
-        }
-        asm volatile("" ::: "memory");
-      }
-    }
-    wave_sync();
+    for (int b = 0; b < NH; ++b) tab[lane * LDT + b] = m[b];
+    pinv[piv[lane]] = lane;
   }
-  // zero diagonal; the lane index goes through an opaque move so that the
-  // 64 compares are made here and not hoisted out of the caller's loop
+  wave_sync();
+  const bool up = lane < nh, dn = lane >= nh && lane < ne;
+  // column of T for an up lane (pinv[c]), row of T for a down lane (p_{a'})
+  const int own = up ? pinv[lane] : (dn ? piv[lane - nh] : 0);
 #pragma unroll
-  for (int k = 0; k < KC; ++k) {
-    int cl = lane + 64 * k;
-    asm volatile("" : "+v"(cl));
-#pragma unroll
-    for (int r = 0; r < NE_MAX; ++r) m[k][r] = r == cl ? 0.0 : m[k][r];
+  for (int r = 0; r < NE_MAX; ++r) {
+    double v = 0.0;
+    if (up && r >= nh && r < ne) v = tab[piv[r >= nh ? r - nh : 0] * LDT + own];
+    else if (dn && r < nh) v = -tab[own * LDT + pinv[r < nh ? r : 0]];
+    y[0][r] = (T)v;
   }
-  if (parity & 1) sgn = -sgn;
+  wave_sync();
   return 0;
 }
 
@@ -278,8 +192,6 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
   T* pv = xn + NE_MAX;
   T* qv = pv + NE_MAX;
   q += a16(3 * (size_t)NE_MAX * sizeof(T));
-  double2* s2 = (double2*)q;         // refresh scratch: rows i and j of M
-  q += a16(2 * (size_t)NE_MAX * sizeof(double));
   double* hs = (double*)q;
   q += a16((size_t)ns * sizeof(double));
   T* ths = (T*)q;
@@ -287,6 +199,14 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
   int32_t* eidx = (int32_t*)q;      // 2ns
   int32_t* emp = eidx + n2;         // 2ns
   int32_t* posl = emp + n2;         // NE_MAX: configuration broadcast for the refresh
+  q += a16((size_t)(4 * ns + NE_MAX) * sizeof(int32_t));
+  // refresh scratch: tableau, pivot row, pivot rows per column and inverse
+  double* tab = (double*)q;
+  q += a16((size_t)(NE_MAX / 2) * (NE_MAX / 2 + 1) * sizeof(double));
+  double* rowp = (double*)q;
+  q += a16((size_t)(NE_MAX / 2) * sizeof(double));
+  int32_t* piv = (int32_t*)q;
+  int32_t* pinv = piv + NE_MAX / 2;
 
   int32_t* posg = P.pos + I.pos_off + lw * ne;
   int32_t* empg = P.empty + I.empty_off + lw * n2;
@@ -481,16 +401,9 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
     if (R > 0 && --to_refresh == 0) to_refresh = R;
     if (kref && R > 0 && to_refresh == R) {
       double lp, sg;
-      if constexpr (sizeof(T) == 8) {
-        singular = reg_refresh<NE_MAX, KC>(y, posr, fs, ldf, ns, ne, lane, posl, s2, lp, sg);
-      } else {
-        double m[KC][NE_MAX];
-        singular = reg_refresh<NE_MAX, KC>(m, posr, fs, ldf, ns, ne, lane, posl, s2, lp, sg);
-#pragma unroll
-        for (int k = 0; k < KC; ++k)
-#pragma unroll
-          for (int r = 0; r < NE_MAX; ++r) y[k][r] = (T)m[k][r];
-      }
+      static_assert(KC == 1, "register tiers hold one column per lane");
+      singular = reg_refresh_ap<NE_MAX, T>(y, posr[0], fs, ldf, ns, ne, lane, posl, tab, rowp,
+                                           piv, pinv, lp, sg);
       last_logpf = lp;
       last_sgn = sg;
       refreshed = true;
