@@ -295,7 +295,8 @@ def sweep_roofline_entry(sweep_threads, avg_ms, bytes_, flops, traffic, traffic_
 
 
 def s_build_leg():
-    """Split-bf16 S build at the 4096-sample x 10^4-parameter shape."""
+    """Split-bf16 S build at the 4096-sample x 10^4-parameter shape, at the
+    tile side the library's tuner picks on this data."""
     import numpy as np
     import torch
 
@@ -306,8 +307,11 @@ def s_build_leg():
     inst = wl["instances"][0]
     ctx = MVMC([inst], inst.params0, precision="mixed", refresh_every=32,
                seed=wl["sampler_seed"], n_slots=1, solver="cg", build_s=True)
+    ctx.autotune(1)          # sweep variants, and arms the S tile tuner
     ctx.sample(2)
     ctx.measure(0)
+    ctx.build_sr(1)          # tunes the tile side on this O (untimed)
+    sides, tune_ms = ctx.s_tiles()
     torch.cuda.synchronize()
     ctx.timing(True)
     reps = 3
@@ -318,16 +322,34 @@ def s_build_leg():
     N, npar = inst.n_walkers, inst.n_params
     flops = N * npar * (npar + 1)
     avg = ms[4] / max(calls[4], 1)
-    # upper-triangle tiles of 128x128 (wide parameter sets) or 64x64, three
-    # bf16 MFMA passes each over the samples rounded up to 16
-    nt2 = -(-npar // 128)
-    tile = 128 if nt2 * (nt2 + 1) // 2 >= 512 else 64
+    # context: the vendor GEMM (torch.mm, hipBLASLt) forming the same
+    # three-pass bf16 product as a full square [N_p x 3N] x [3N x N_p]
+    g = torch.Generator(device="cuda").manual_seed(1)
+    a = torch.randn(npar, 3 * N, device="cuda", dtype=torch.bfloat16, generator=g)
+    b = torch.randn(3 * N, npar, device="cuda", dtype=torch.bfloat16, generator=g)
+    for _ in range(2):
+        c = a @ b
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        c = a @ b
+    e1.record()
+    torch.cuda.synchronize()
+    gemm_ms = e0.elapsed_time(e1) / 3
+    del a, b, c
+    # upper-triangle tiles of the chosen side (64 for narrow parameter
+    # sets), three bf16 MFMA passes each over the samples rounded up to 32
+    tile = sides[0] or 64
     nt = -(-npar // tile)
-    issued = 3 * 2 * (-(-N // 16) * 16) * tile * tile * nt * (nt + 1) // 2
+    rows = -(-N // 32) * 32 if sides[0] else -(-N // 16) * 16
+    issued = 3 * 2 * rows * tile * tile * nt * (nt + 1) // 2
     return {"shape": [N, npar], "ms": avg, "tflops": flops / (avg * 1e-3) / 1e12,
             "algorithmic_flops": flops, "issued_mfma_tflops": issued / (avg * 1e-3) / 1e12,
             "issued_frac_of_bf16_peak": issued / (avg * 1e-3) / 1e12 / BF16_PEAK_TFLOPS,
             "tile": tile,
+            "tuning_ms_by_tile": {"128": float(tune_ms[0][0]), "192": float(tune_ms[0][1]),
+                                  "256": float(tune_ms[0][2])},
+            "vendor_gemm_same_product_ms": gemm_ms,
             "note": "time of the S kernels only (centring and split excluded)"}
 
 

@@ -174,12 +174,36 @@ enum { MVMC_N_SWEEP_VARIANTS = 7 };
  * matching instances are not timed, new choices are appended.  h_ms (may be
  * NULL): [n_instances][MVMC_N_SWEEP_VARIANTS] measured milliseconds, NaN for
  * variants not timed.  Synchronises the stream; not capturable.
+ * With MVMC_MIXED and build_s it also arms the tile tuner of the split-bf16
+ * S build (section 3.3.1 S_km): the next mvmc_build_sr times the instances
+ * with wide parameter sets (at least 512 upper-triangle tiles of 128) at
+ * tile sides 128, 192 and 256 on that call's own data and keeps the fastest;
+ * that call synchronises the stream.
  * Errors: MVMC_E_ARG, MVMC_E_HIP.
  */
 int mvmc_autotune(mvmc_ctx *ctx, int32_t n_sweeps, const char *cache_path, double *h_ms);
 
 /* Current sweep variant of every instance ([n_instances], host). */
 int mvmc_sweep_variants(const mvmc_ctx *ctx, int32_t *h_variant);
+
+/*
+ * Tile side of the split-bf16 S build of every instance (h_tile,
+ * [n_instances], host): 0 for the 64-tile kernel (narrow parameter sets, or
+ * no split-bf16 build), else 128, 192 or 256 (default 256 until tuned or set).
+ * h_ms (may be NULL): [n_instances][3] milliseconds of the last tuning at
+ * sides 128, 192, 256 (NaN where not timed).
+ * Errors: MVMC_E_ARG.
+ */
+int mvmc_s_tiles(const mvmc_ctx *ctx, int32_t *h_tile, double *h_ms);
+
+/*
+ * Sets the tile side (128, 192 or 256) of the split-bf16 S build for every
+ * instance that uses the direct-to-LDS kernel (those with 64 in
+ * mvmc_s_tiles are unchanged) and cancels a pending tile tuning.  S does
+ * not depend on the side except in the order of FP32 partial sums.
+ * Synchronises the stream.  Errors: MVMC_E_ARG, MVMC_E_HIP.
+ */
+int mvmc_set_s_tile(mvmc_ctx *ctx, int32_t side);
 
 /*
  * Local energy E_loc(x) (Eq. MC, H of section 2.3) and the row of

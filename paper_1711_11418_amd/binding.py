@@ -22,7 +22,7 @@ ENTRY_POINTS = (
     "mvmc_measure_energy_and_O", "mvmc_build_sr", "mvmc_sr_update", "mvmc_set_params",
     "mvmc_get_state", "mvmc_set_state", "mvmc_get_inverse", "mvmc_get_pfaffian", "mvmc_refresh",
     "mvmc_trace_enable", "mvmc_timing", "mvmc_destroy", "mvmc_last_error", "mvmc_status_string",
-    "mvmc_autotune", "mvmc_sweep_variants",
+    "mvmc_autotune", "mvmc_sweep_variants", "mvmc_s_tiles", "mvmc_set_s_tile",
 )
 N_SWEEP_VARIANTS = 7
 SWEEP_VARIANT_NAMES = ("reg", "lds64", "lds128", "lds256", "hbm64", "hbm128", "hbm256")
@@ -107,6 +107,8 @@ def load() -> C.CDLL:
         "mvmc_destroy": [vp],
         "mvmc_autotune": [vp, i32, C.c_char_p, vp],
         "mvmc_sweep_variants": [vp, vp],
+        "mvmc_s_tiles": [vp, vp, vp],
+        "mvmc_set_s_tile": [vp, C.c_int32],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -339,6 +341,21 @@ class MVMC:
         self._check(self.lib.mvmc_autotune(self.ctx, int(n_sweeps), path,
                                            ms.ctypes.data_as(C.c_void_p)))
         return ms
+
+    def s_tiles(self) -> tuple[list[int], np.ndarray]:
+        """Tile side of the split-bf16 S build per instance (0: 64-tile
+        kernel) and the milliseconds of the last tuning at sides 128, 192,
+        256 ([n_instances, 3], NaN where not timed)."""
+        n = self.n_inst
+        t = np.zeros(n, np.int32)
+        ms = np.zeros((n, 3), np.float64)
+        self._check(self.lib.mvmc_s_tiles(self.ctx, t.ctypes.data_as(C.c_void_p),
+                                          ms.ctypes.data_as(C.c_void_p)))
+        return [int(x) for x in t], ms
+
+    def set_s_tile(self, side: int) -> None:
+        """Force the split-bf16 S tile side (128, 192 or 256) of the wide instances."""
+        self._check(self.lib.mvmc_set_s_tile(self.ctx, int(side)))
 
     def sweep_variants(self) -> list[str]:
         v = np.zeros(self.n_inst, dtype=np.int32)

@@ -28,6 +28,8 @@ constexpr int kMaxElec = 2048;
 constexpr int kTimingCats = 6;
 constexpr int kRegWpb = 4;   // walkers per workgroup of the register sweep
 constexpr int kMaxShiftEscalations = 4;   // Cholesky retries with eps_rel x 10 each
+constexpr int kTailUnitsMax = 512;        // split-bf16 S: sample parts of tail tiles, all together
+constexpr int kMaxTileSb = 4;             // largest direct-to-LDS S tile: 64 * 4
 
 inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
 
@@ -50,7 +52,7 @@ struct Plan {
   size_t total = 0;
   int64_t W = 0, np = 0, eloc = 0, O_elems = 0, S_elems = 0, Y_elems = 0;
   int max_ne = 0, max_ns = 0, max_M = 0, max_ksplit = 1;
-  int64_t max_np = 0, max_ld = 0, max_rows = 0;
+  int64_t max_np = 0, max_ld = 0, max_rows = 0, max_sld = 0;
   bool need_Y64 = false;
   size_t tsize = 8;
 };
@@ -90,6 +92,36 @@ int sweep_threads_for(const mvmc_config& c, int ne) {
 static bool wide_params(int64_t np) {
   const int64_t nt = (np + 127) / 128;
   return nt * (nt + 1) / 2 >= 512;
+}
+
+// Parameter stride of the bf16 split arrays: every direct-to-LDS tile side
+// (128, 192, 256) reads whole tiles without leaving the row.
+static int64_t split_ld_for(int64_t np, int64_t ldO) {
+  int64_t ld = ldO;
+  for (int b = 2; b <= kMaxTileSb; ++b) ld = std::max(ld, (np + 64 * b - 1) / (64 * b) * (64 * b));
+  return ld;
+}
+
+// Tile side 64 sb of the direct-to-LDS S kernel (0: the 64-tile kernel) and
+// the split of the tiles past the last full round over n_slots workgroup
+// slots into sample parts, so the last round is as full as the others.
+static void set_tiles(SrInst& S, int sb, int n_cu) {
+  S.sb = sb;
+  S.nfull = 0;
+  S.tail_ks = 1;
+  if (!sb) return;
+  const int64_t T = 64 * sb, nt = (S.np + T - 1) / T, ntl = nt * (nt + 1) / 2;
+  const int64_t slots = (int64_t)std::max(n_cu, 1) * (sb == 2 ? 2 : 1);
+  const int64_t rem = ntl % slots;
+  S.nfull = (int32_t)ntl;
+  if (rem) {
+    int64_t ks = std::min<int64_t>(8, slots / rem);
+    while (ks > 1 && rem * ks > kTailUnitsMax) --ks;
+    if (ks >= 2) {
+      S.nfull = (int32_t)(ntl - rem);
+      S.tail_ks = (int32_t)ks;
+    }
+  }
 }
 
 Err validate(const mvmc_config* c) {
@@ -253,8 +285,10 @@ Plan make_plan(const mvmc_config& c) {
     I.chol_off = off_chol;
     if (c.build_s && c.solver == MVMC_SOLVE_CHOL) off_chol += (int64_t)I.np * I.np;
     I.split_off = off_split;
-    const int64_t rows16 = (I.rows + 15) / 16 * 16;
-    if (c.build_s && c.precision == MVMC_MIXED) off_split += 2 * rows16 * I.ldO;
+    const int64_t rows32 = (I.rows + 31) / 32 * 32;
+    const bool tiled_s = c.build_s && c.precision == MVMC_MIXED && wide_params(I.np);
+    const int64_t sld = tiled_s ? split_ld_for(I.np, I.ldO) : I.ldO;
+    if (c.build_s && c.precision == MVMC_MIXED) off_split += 2 * rows32 * sld;
 
     SrInst& S = P.sr[k];
     std::memset(&S, 0, sizeof S);
@@ -267,7 +301,8 @@ Plan make_plan(const mvmc_config& c) {
     S.param_off = I.param_off;
     S.chol_off = I.chol_off;
     S.split_off = I.split_off;
-    S.split_rows = rows16;
+    S.split_rows = rows32;
+    S.split_ld = sld;
     S.colpart_off = off_colpart;
     off_colpart += 3 * ((I.rows + kRowChunk - 1) / kRowChunk) * I.ldO;
     const int64_t ntile = (I.np + 63) / 64;
@@ -275,12 +310,15 @@ Plan make_plan(const mvmc_config& c) {
     int64_t ks = std::max<int64_t>(1, 1024 / std::max<int64_t>(tiles, 1));
     ks = std::min<int64_t>(ks, std::max<int64_t>(1, I.rows / 256));
     while (ks > 1 && ks * tiles * 4096 * 8 > ((int64_t)256 << 20)) ks /= 2;
-    // wide parameter sets: 128 x 128 tiles per wave fill the GPU without a K split
-    S.tile128 = wide_params(I.np) ? 1 : 0;
-    if (S.tile128) ks = 1;
+    // wide parameter sets: direct-to-LDS tiles (256 by default), no sample
+    // split except for the tail tiles, whose FP32 partials share this pool
+    if (tiled_s) ks = 1;
     S.ksplit = (int32_t)ks;
+    S.sb = tiled_s ? kMaxTileSb : 0;
     S.syrkpart_off = off_syrkpart;
-    if (c.build_s) off_syrkpart += ks * tiles * 4096;
+    if (c.build_s)
+      off_syrkpart += tiled_s ? (int64_t)kTailUnitsMax * (64 * kMaxTileSb) * (64 * kMaxTileSb) / 2
+                              : ks * tiles * 4096;
 
     off_O += I.rows * I.ldO;
     if (c.build_s) off_S += (int64_t)I.np * I.np;
@@ -293,6 +331,7 @@ Plan make_plan(const mvmc_config& c) {
     P.max_M = std::max(P.max_M, I.M);
     P.max_np = std::max<int64_t>(P.max_np, I.np);
     P.max_ld = std::max<int64_t>(P.max_ld, I.ldO);
+    P.max_sld = std::max<int64_t>(P.max_sld, S.split_ld);
     P.max_rows = std::max<int64_t>(P.max_rows, I.rows);
     P.max_ksplit = std::max<int>(P.max_ksplit, S.ksplit);
   }
@@ -436,6 +475,9 @@ struct mvmc_ctx {
   bool sr_ready = false;
   std::string err;
   SrInst* h_sr = nullptr;           // pinned staging of the SR table
+  int n_cu = 256;                   // compute units of the device
+  bool s_tune = false;              // time the S tile sides at the next mvmc_build_sr
+  std::vector<double> s_tile_ms;    // [instance][tile side 128, 192, 256] of the last tuning
   // timing
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
@@ -812,6 +854,14 @@ int mvmc_init_wavefunction(mvmc_ctx** out, const mvmc_config* cfg, void* d_ws, s
     mvmc_destroy(c);
     return MVMC_E_HIP;
   }
+  {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        ncu > 0)
+      c->n_cu = ncu;
+    for (SrInst& S : c->plan.sr) set_tiles(S, S.sb, c->n_cu);
+  }
   std::memcpy(c->h_sr, P.sr.data(), sizeof(SrInst) * P.sr.size());
   build_buckets(c);
   c->cnt_host.assign(cfg->n_instances, 0);
@@ -1112,6 +1162,7 @@ int mvmc_autotune(mvmc_ctx* c, int32_t n_sweeps, const char* cache_path, double*
   }
   if (out) std::fclose(out);
   build_buckets(c);
+  c->s_tune = c->cfg.build_s && c->cfg.precision == MVMC_MIXED;
   HIPCHK(c, hipMemsetAsync(c->P.accepted, 0, 8 * P.W, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (h_ms) std::memcpy(h_ms, ms.data(), ms.size() * sizeof(double));
@@ -1121,6 +1172,30 @@ int mvmc_autotune(mvmc_ctx* c, int32_t n_sweeps, const char* cache_path, double*
 int mvmc_sweep_variants(const mvmc_ctx* c, int32_t* h_variant) {
   if (!c || !h_variant) return MVMC_E_ARG;
   for (int k = 0; k < c->cfg.n_instances; ++k) h_variant[k] = variant_of(c->plan, k);
+  return MVMC_OK;
+}
+
+int mvmc_s_tiles(const mvmc_ctx* c, int32_t* h_tile, double* h_ms) {
+  if (!c || !h_tile) return MVMC_E_ARG;
+  const int n = c->cfg.n_instances;
+  for (int k = 0; k < n; ++k) h_tile[k] = 64 * c->plan.sr[k].sb;
+  if (h_ms)
+    for (size_t i = 0; i < (size_t)n * 3; ++i)
+      h_ms[i] = i < c->s_tile_ms.size() ? c->s_tile_ms[i] : std::nan("");
+  return MVMC_OK;
+}
+
+int mvmc_set_s_tile(mvmc_ctx* c, int32_t side) {
+  if (!c) return MVMC_E_ARG;
+  if (side != 128 && side != 192 && side != 256)
+    return set_err(c, fail(MVMC_E_ARG, "S tile side %d is not 128, 192 or 256", side));
+  HIPCHK(c, hipStreamSynchronize(c->stream));   // the SR table staging may be in flight
+  for (int k = 0; k < c->cfg.n_instances; ++k)
+    if (c->plan.sr[k].sb) {
+      set_tiles(c->plan.sr[k], side / 64, c->n_cu);
+      set_tiles(c->h_sr[k], side / 64, c->n_cu);
+    }
+  c->s_tune = false;
   return MVMC_OK;
 }
 
@@ -1140,6 +1215,83 @@ int mvmc_measure_energy_and_O(mvmc_ctx* c, int32_t slot, double* d_eloc, void* d
   LAUNCHCHK(c);
   return MVMC_OK;
 }
+
+namespace {
+// Grid shape of the split-bf16 S build for the current tile choices.
+SyrkLaunch syrk_launch(const SrInst* sr, int n) {
+  SyrkLaunch L{};
+  for (int k = 0; k < n; ++k) {
+    const SrInst& S = sr[k];
+    if (!S.sb) {
+      L.any64 = true;
+      continue;
+    }
+    const int64_t T = 64 * S.sb, nt = (S.np + T - 1) / T, ntl = nt * (nt + 1) / 2;
+    const int64_t units = S.nfull + (ntl - S.nfull) * S.tail_ks;
+    L.units[S.sb] = std::max<int>(L.units[S.sb], (int)units);
+    L.tail[S.sb] = std::max<int>(L.tail[S.sb], (int)(ntl - S.nfull));
+  }
+  return L;
+}
+
+// Times the S build of the wide instances at each direct-to-LDS tile side
+// (on the split arrays just written) and keeps the fastest per instance.
+// Every instance of a launch takes the same side while it is timed.
+int tune_s_tiles(mvmc_ctx* c, const uint16_t* split, float* d_S) {
+  const int n = c->cfg.n_instances;
+  c->s_tune = false;
+  c->s_tile_ms.assign((size_t)n * 3, std::nan(""));
+  bool any = false;
+  for (int k = 0; k < n; ++k) any = any || c->h_sr[k].sb != 0;
+  if (!any) return MVMC_OK;
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  std::vector<int> best(n, 0);
+  std::vector<double> best_ms(n, INFINITY);
+  int rc = MVMC_OK;
+  for (int sb = 2; sb <= kMaxTileSb && rc == MVMC_OK; ++sb) {
+    for (int k = 0; k < n; ++k)
+      if (c->h_sr[k].sb) set_tiles(c->h_sr[k], sb, c->n_cu);
+    const SyrkLaunch L = syrk_launch(c->h_sr, n);
+    if (hipMemcpyAsync((void*)c->SA.inst, c->h_sr, sizeof(SrInst) * n, hipMemcpyHostToDevice,
+                       c->stream) != hipSuccess) {
+      rc = set_err(c, fail(MVMC_E_HIP, "S tile tuning: table upload failed"));
+      break;
+    }
+    float ms = 0.f;
+    for (int rep = 0; rep < 2; ++rep) {   // the first run warms up
+      (void)hipEventRecord(e0, c->stream);
+      sr_syrk_bf16x3(c->SA, split, d_S, n, c->plan.max_np, c->plan.max_ksplit, L, c->stream);
+      (void)hipEventRecord(e1, c->stream);
+      if (hipGetLastError() != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        rc = set_err(c, fail(MVMC_E_HIP, "S tile tuning: kernel failed"));
+        break;
+      }
+      (void)hipEventElapsedTime(&ms, e0, e1);
+    }
+    for (int k = 0; k < n; ++k)
+      if (c->h_sr[k].sb) {
+        c->s_tile_ms[(size_t)k * 3 + sb - 2] = ms;
+        if (ms < best_ms[k]) {
+          best_ms[k] = ms;
+          best[k] = sb;
+        }
+      }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (int k = 0; k < n; ++k)
+    if (c->h_sr[k].sb) {
+      set_tiles(c->h_sr[k], best[k] ? best[k] : kMaxTileSb, c->n_cu);
+      set_tiles(c->plan.sr[k], c->h_sr[k].sb, c->n_cu);
+    }
+  if (rc) return rc;
+  HIPCHK(c, hipMemcpyAsync((void*)c->SA.inst, c->h_sr, sizeof(SrInst) * n, hipMemcpyHostToDevice,
+                           c->stream));
+  return MVMC_OK;
+}
+}  // namespace
 
 int mvmc_build_sr(mvmc_ctx* c, int32_t n_used, const double* d_eloc, void* d_O, void* d_S,
                   double* d_g, double* h_E, double* h_Evar) {
@@ -1163,15 +1315,21 @@ int mvmc_build_sr(mvmc_ctx* c, int32_t n_used, const double* d_eloc, void* d_O, 
   int id = tic(c, 3);
   sr_estats(c->SA, n, c->stream);
   if (mixed)
-    sr_colstats<float>(c->SA, (float*)d_O, split, d_g, n, P.max_ld, max_rows, c->stream);
+    sr_colstats<float>(c->SA, (float*)d_O, split, d_g, n, std::max(P.max_ld, P.max_sld), max_rows,
+                       c->stream);
   else
     sr_colstats<double>(c->SA, (double*)d_O, nullptr, d_g, n, P.max_ld, max_rows, c->stream);
   toc(c, id);
   LAUNCHCHK(c);
   if (d_S) {
+    if (mixed && c->s_tune) {
+      const int rc = tune_s_tiles(c, split, (float*)d_S);
+      if (rc) return rc;
+    }
     id = tic(c, 4);
     if (mixed)
-      sr_syrk_bf16x3(c->SA, split, (float*)d_S, n, P.max_np, P.max_ksplit, c->stream);
+      sr_syrk_bf16x3(c->SA, split, (float*)d_S, n, P.max_np, P.max_ksplit,
+                     syrk_launch(c->h_sr, n), c->stream);
     else
       sr_syrk_vec<double, double>(c->SA, (const double*)d_O, (double*)d_S, n, P.max_np,
                                   P.max_ksplit, c->stream);

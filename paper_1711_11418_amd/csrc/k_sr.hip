@@ -48,7 +48,23 @@ __global__ void k_colpass(SrArgs A, T* __restrict__ O, int mode, uint16_t* __res
   const int64_t r0 = (int64_t)blockIdx.y * kRowChunk;
   if (r0 >= I.rows) return;
   const int64_t r1 = r0 + kRowChunk < I.rows ? r0 + kRowChunk : I.rows;
-  if (k >= I.ldO) return;
+  // rows up to the next multiple of 32 samples are read by the S kernels
+  const int64_t rows32 = (I.rows + 31) / 32 * 32;
+  const int64_t sld = I.split_ld;
+  uint16_t* hi = (mode == 1 && split) ? split + I.split_off : nullptr;
+  uint16_t* lo = hi ? hi + I.split_rows * sld : nullptr;
+  if (k >= I.ldO) {
+    // padding parameters of the split arrays (read by whole-tile loads): zero
+    if (hi && k < sld) {
+      const int64_t re = r1 == I.rows ? rows32 : r1;
+      for (int64_t m = r0; m < re; ++m) {
+        const int64_t si = split_index(m, k, sld);
+        hi[si] = 0;
+        lo[si] = 0;
+      }
+    }
+    return;
+  }
   T* Ob = O + I.O_off;
   double* part = A.colpart + I.colpart_off;
   const int64_t ld = I.ldO;
@@ -60,8 +76,6 @@ __global__ void k_colpass(SrArgs A, T* __restrict__ O, int mode, uint16_t* __res
     const double ob = A.obar[I.param_off + k];
     const double eb = A.scal[blockIdx.z * kScal + kEbar];
     const double* e = A.eloc + I.eloc_off;
-    uint16_t* hi = split ? split + I.split_off : nullptr;
-    uint16_t* lo = split ? split + I.split_off + I.split_rows * ld : nullptr;
     double s2 = 0.0, sg = 0.0;
     for (int64_t m = r0; m < r1; ++m) {
       const T c = (T)((double)Ob[m * ld + k] - ob);
@@ -71,16 +85,14 @@ __global__ void k_colpass(SrArgs A, T* __restrict__ O, int mode, uint16_t* __res
       sg += cd * (e[m] - eb);
       if (hi) {
         const uint16_t h = f32_to_bf16((float)c);
-        const int64_t si = split_index(m, k, ld);
+        const int64_t si = split_index(m, k, sld);
         hi[si] = h;
         lo[si] = f32_to_bf16((float)c - bf16_to_f32(h));
       }
     }
-    // zero rows up to the next multiple of 16 samples, which the S kernels
-    // read as whole MFMA operands
     if (hi && r1 == I.rows)
-      for (int64_t m = I.rows; m < (I.rows + 15) / 16 * 16; ++m) {
-        const int64_t si = split_index(m, k, ld);
+      for (int64_t m = I.rows; m < rows32; ++m) {
+        const int64_t si = split_index(m, k, sld);
         hi[si] = 0;
         lo[si] = 0;
       }

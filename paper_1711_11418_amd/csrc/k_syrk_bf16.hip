@@ -46,13 +46,13 @@ __device__ __forceinline__ bf16x8 load8(const uint16_t* __restrict__ base, int64
 __global__ __launch_bounds__(64) void k_syrk_mfma(SrArgs A, const uint16_t* __restrict__ split,
                                                   float* __restrict__ S) {
   const SrInst& I = A.inst[blockIdx.z];
-  if (I.tile128) return;   // built by the 128-tile kernel
+  if (I.sb) return;   // built by the direct-to-LDS kernel
   const int nt = (int)ceil_div<int64_t>(I.np, kT);
   const int ntiles = nt * (nt + 1) / 2;
   if ((int)blockIdx.x >= ntiles || (int)blockIdx.y >= I.ksplit) return;
   int ti, tj;
   tile_index(blockIdx.x, nt, ti, tj);
-  const int64_t ld = I.ldO, np = I.np, rows = I.rows;
+  const int64_t ld = I.split_ld, np = I.np, rows = I.rows;
   const int64_t chunk = ceil_div<int64_t>(ceil_div<int64_t>(rows, I.ksplit), 16) * 16;
   const int64_t k0 = (int64_t)blockIdx.y * chunk;
   const int64_t k1 = k0 + chunk < rows ? k0 + chunk : rows;
@@ -117,228 +117,234 @@ __global__ __launch_bounds__(64) void k_syrk_mfma(SrArgs A, const uint16_t* __re
       }
 }
 
-// Wide parameter sets: one wavefront per 128 x 128 tile of the upper
-// triangle, 4 x 4 blocks of 32 x 32 accumulators (held in the accumulation
-// registers), three bf16 products per block and 16 samples, so each
-// 16-sample step loads 16 operand vectors for 48 MFMAs (three times the
-// operand reuse of the 64-tile kernel).  The next step's operands are loaded
-// before the current step's products are issued.  No K split: S is written
-// directly, both triangles.
+// Wide parameter sets: direct-to-LDS staged tiles of side T = 64 B.  One
+// workgroup of four wavefronts owns a T x T tile of the upper triangle; each
+// wavefront accumulates a (T/2) x (T/2) quadrant as B x B blocks of 32 x 32
+// MFMA accumulators.  The contraction runs in steps of 16 samples (two
+// groups of 8).  A step's operands, the hi and lo halves of both T-parameter
+// ranges, go straight from global memory into one of four LDS stages
+// (global_load_lds, no staging registers), issued three steps ahead and
+// interleaved one per MFMA; a step's operands are read from LDS into
+// registers one step ahead, interleaved the same way.  One barrier per step
+// publishes the next stage.  The split arrays are padded (parameters to
+// split_ld, samples to a multiple of 32) so no load is guarded.
+//
+// Tiles past the last full round of the GPU are split over the samples
+// (tail_ks parts); their FP32 partial tiles are summed in part order by
+// k_syrk_tail, so S is deterministic.  Whole tiles write S directly.
 namespace {
-constexpr int kT2 = 128;
-struct Ops128 {
-  bf16x8 ah[4], al[4], bh[4], bl[4];
+template <int B>
+struct Ops {
+  bf16x8 ah[B], al[B], bh[B], bl[B];
 };
-// Operands of one 16-sample step.  The split arrays hold zeros up to the
-// next multiple of 16 samples and in the padding parameters (rows of O are
-// padded to a multiple of 128 for these instances), so no load is masked.
-__device__ __forceinline__ bf16x8 load8u(const uint16_t* __restrict__ p) {
-  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(p));
-}
-__device__ __forceinline__ void load_ops128(Ops128& o, const uint16_t* hi, const uint16_t* lo,
-                                            int64_t k, int64_t ld, int64_t p0, int64_t q0,
-                                            int m, int kh) {
-  const int64_t kg = (k >> 3) + kh;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int64_t ip = (kg * ld + p0 + 32 * i + m) * 8, iq = (kg * ld + q0 + 32 * i + m) * 8;
-    o.ah[i] = load8u(hi + ip);
-    o.al[i] = load8u(lo + ip);
-    o.bh[i] = load8u(hi + iq);
-    o.bl[i] = load8u(lo + iq);
-  }
-}
-__device__ __forceinline__ void mfma_step128(f32x16 (&acc)[4][4], const Ops128& o) {
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.ah[i], o.bh[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.ah[i], o.bl[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.al[i], o.bh[j], acc[i][j], 0, 0, 0);
-}
-}  // namespace
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) const void gbl_void_t;
 
-__global__ __launch_bounds__(64) void k_syrk_mfma128(SrArgs A, const uint16_t* __restrict__ split,
-                                                     float* __restrict__ S) {
-  const SrInst& I = A.inst[blockIdx.y];
-  if (!I.tile128) return;
-  const int nt = (int)ceil_div<int64_t>(I.np, kT2);
-  if ((int)blockIdx.x >= nt * (nt + 1) / 2) return;
-  int ti, tj;
-  tile_index(blockIdx.x, nt, ti, tj);
-  const int64_t ld = I.ldO, np = I.np, rows = I.rows;
-  const uint16_t* hi = split + I.split_off;
-  const uint16_t* lo = hi + I.split_rows * ld;
-  const int lane = threadIdx.x, m = lane & 31, kh = lane >> 5;
-  const int64_t p0 = (int64_t)ti * kT2, q0 = (int64_t)tj * kT2;
-  f32x16 acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-  // The products run pass by pass, so each accumulator's dependent MFMAs
-  // are 16 issues apart; the loads of a step are unconditional (the last
-  // step reloads itself), which keeps the number in flight fixed.
-  Ops128 cur, nxt;
-  const int64_t rows16 = (rows + 15) / 16 * 16;
-  load_ops128(cur, hi, lo, 0, ld, p0, q0, m, kh);
-  for (int64_t k = 0; k < rows16; k += 16) {
-    load_ops128(nxt, hi, lo, k + 16 < rows16 ? k + 16 : k, ld, p0, q0, m, kh);
-    mfma_step128(acc, cur);
-    cur = nxt;
-  }
-  // accumulator r of lane l holds D[row][col], col = l % 32,
-  // row = 8 (r / 4) + 4 (l / 32) + r % 4
-  const float invN = (float)(1.0 / (double)rows);
-  float* Sb = S + I.S_off;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int64_t row = p0 + 32 * i + 8 * (r >> 2) + 4 * kh + (r & 3);
-        const int64_t col = q0 + 32 * j + m;
-        if (row < np && col < np && (ti != tj || row <= col)) {
-          const float v = acc[i][j][r] * invN;
-          Sb[row * np + col] = v;
-          Sb[col * np + row] = v;
-        }
-      }
-}
+template <int B>
+struct DmaTile {
+  static constexpr int T = 64 * B;
+  static constexpr int V = 8 * T;          // 16-byte vectors per stage: [hiA|loA|hiB|loB][2 groups][T]
+  static constexpr int PT = V / 256;       // vectors per thread and stage
+  static constexpr int kStages = 4;
+};
 
-// Wide parameter sets, LDS-staged: one workgroup of four wavefronts per
-// 128 x 128 tile of the upper triangle, each wavefront a 64 x 64 quadrant
-// (2 x 2 blocks of 32 x 32 accumulators).  Panels of 32 samples (four
-// groups of 8) of the two 128-parameter ranges, hi and lo, pass from global
-// memory through registers into one of two LDS buffers: the next panel's
-// global loads are in flight while the current panel's products issue.
-// Sample groups past the last multiple of 16 samples read as zero.
-namespace {
-constexpr int kStageVecs = 4 * 4 * 128;   // [hiA | loA | hiB | loB][group][parameter]
-__device__ __forceinline__ void mfma_quad(f32x16 (&acc)[2][2], const bf16x8 (&ah)[2],
-                                          const bf16x8 (&al)[2], const bf16x8 (&bh)[2],
-                                          const bf16x8 (&bl)[2]) {
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-      acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-      acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-      acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-}
-}  // namespace
-
-__global__ __launch_bounds__(256) void k_syrk_lds128(SrArgs A, const uint16_t* __restrict__ split,
-                                                     float* __restrict__ S) {
-  const SrInst& I = A.inst[blockIdx.y];
-  if (!I.tile128) return;
-  const int nt = (int)ceil_div<int64_t>(I.np, kT2);
-  if ((int)blockIdx.x >= nt * (nt + 1) / 2) return;
-  int ti, tj;
-  tile_index(blockIdx.x, nt, ti, tj);
-  const int64_t ld = I.ldO, np = I.np, rows = I.rows;
-  const int64_t ng = (rows + 15) / 16 * 2;   // groups of 8 samples in use
-  const uint16_t* hi = split + I.split_off;
-  const uint16_t* lo = hi + I.split_rows * ld;
-  const int64_t p0 = (int64_t)ti * kT2, q0 = (int64_t)tj * kT2;
-  __shared__ u16x8 stage[2][kStageVecs];
+// Steps [s0, s1) (both even) of the tile at (p0, q0); writes S (part null)
+// or the unscaled FP32 partial tile.
+template <int B>
+__device__ __forceinline__ void syrk_dma_tile(const uint16_t* __restrict__ hi, int64_t lo_elems,
+                                              int64_t sld, int64_t np, float invN,
+                                              float* __restrict__ S, int64_t p0, int64_t q0,
+                                              bool diag, u16x8* stage, int64_t s0, int64_t s1,
+                                              float* __restrict__ part) {
+  using C = DmaTile<B>;
+  constexpr int T = C::T, V = C::V, PT = C::PT, H = T / 2;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, m = lane & 31, kh = lane >> 5;
   const int qi = wv >> 1, qj = wv & 1;
-
-  u16x8 reg[8];
-  auto gload = [&](int64_t kg0) {
+  // byte offset of each of this thread's vectors from the step's hi base
+  uint32_t off[PT];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int v = tid + 256 * e;
-      const int arr = v >> 9, g = (v >> 7) & 3, p = v & 127;
-      const int64_t kg = kg0 + g;
-      const int64_t col = (arr < 2 ? p0 : q0) + p;
-      const uint16_t* base = (arr & 1) ? lo : hi;
-      u16x8 z = {0, 0, 0, 0, 0, 0, 0, 0};
-      reg[e] = kg < ng ? *reinterpret_cast<const u16x8*>(base + (kg * ld + col) * 8) : z;
+  for (int e = 0; e < PT; ++e) {
+    const int v = tid + 256 * e;
+    const int arr = v / (2 * T), g = (v / T) % 2, p = v % T;
+    const int64_t col = (arr < 2 ? p0 : q0) + p;
+    off[e] = (uint32_t)(((arr & 1) ? lo_elems * 2 : 0) + ((int64_t)g * sld + col) * 16);
+  }
+  auto dma = [&](int64_t s, int st) {
+    const char* base = reinterpret_cast<const char*>(hi) + s * 2 * sld * 16;
+#pragma unroll
+    for (int e = 0; e < PT; ++e)
+      __builtin_amdgcn_global_load_lds((gbl_void_t*)(base + off[e]),
+                                       (lds_void_t*)(stage + st * V + 256 * e + 64 * wv), 16, 0, 0);
+  };
+  auto lread = [&](Ops<B>& o, int st) {
+    const u16x8* sp = stage + st * V + kh * T;
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      const int pa = H * qi + 32 * i + m, pb = H * qj + 32 * i + m;
+      o.ah[i] = __builtin_bit_cast(bf16x8, sp[pa]);
+      o.al[i] = __builtin_bit_cast(bf16x8, sp[2 * T + pa]);
+      o.bh[i] = __builtin_bit_cast(bf16x8, sp[4 * T + pb]);
+      o.bl[i] = __builtin_bit_cast(bf16x8, sp[6 * T + pb]);
     }
   };
-  auto lstore = [&](int b) {
+  f32x16 acc[B][B];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) stage[b][tid + 256 * e] = reg[e];
-  };
-
-  f32x16 acc[2][2];
+  for (int i = 0; i < B; ++i)
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < B; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-
-  gload(0);
-  lstore(0);
-  __syncthreads();
-  int b = 0;
-  for (int64_t kg0 = 0; kg0 < ng; kg0 += 4) {
-    const bool more = kg0 + 4 < ng;
-    if (more) gload(kg0 + 4);
+  auto pass = [&](const bf16x8 (&a)[B], const bf16x8 (&b)[B]) {
 #pragma unroll
-    for (int sub = 0; sub < 2; ++sub) {
-      const int g = 2 * sub + kh;
-      bf16x8 ah[2], al[2], bh[2], bl[2];
+    for (int i = 0; i < B; ++i)
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int pa = g * 128 + 64 * qi + 32 * i + m, pb = g * 128 + 64 * qj + 32 * i + m;
-        ah[i] = __builtin_bit_cast(bf16x8, stage[b][pa]);
-        al[i] = __builtin_bit_cast(bf16x8, stage[b][512 + pa]);
-        bh[i] = __builtin_bit_cast(bf16x8, stage[b][1024 + pb]);
-        bl[i] = __builtin_bit_cast(bf16x8, stage[b][1536 + pb]);
-      }
-      mfma_quad(acc, ah, al, bh, bl);
+      for (int j = 0; j < B; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+  };
+  // s_waitcnt with vmcnt <= 2 PT (the two later steps stay in flight)
+  constexpr int W2 = 2 * PT;
+  constexpr int kWait2 = (W2 & 15) | ((W2 >> 4) << 14) | (7 << 4) | (15 << 8);
+  const int64_t last = s1 - 1;
+  // One step: issue the loads of step s + 3 among the first pass of
+  // products, wait for step s + 1 and publish it, then read its operands
+  // among the remaining two passes.
+  auto step = [&](int64_t s, Ops<B>& X, Ops<B>& Y) {
+    dma(s + 3 <= last ? s + 3 : last, (int)((s + 3) & 3));
+    pass(X.ah, X.bh);
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+      __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);   // one global load
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
     }
-    if (more) lstore(b ^ 1);
-    __syncthreads();
-    b ^= 1;
+    __builtin_amdgcn_sched_group_barrier(0x008, B * B > PT ? B * B - PT : 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(kWait2);
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+    lread(Y, (int)((s + 1) & 3));
+    pass(X.ah, X.bl);
+    pass(X.al, X.bh);
+#pragma unroll
+    for (int k = 0; k < 4 * B; ++k) {
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, 2 * B * B - 4 * B, 0);
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  dma(s0, (int)(s0 & 3));
+  dma(s0 + 1 <= last ? s0 + 1 : last, (int)((s0 + 1) & 3));
+  dma(s0 + 2 <= last ? s0 + 2 : last, (int)((s0 + 2) & 3));
+  __builtin_amdgcn_s_waitcnt(kWait2);
+  __builtin_amdgcn_s_barrier();
+  Ops<B> X, Y;
+  lread(X, (int)(s0 & 3));
+  for (int64_t s = s0; s < s1; s += 2) {
+    step(s, X, Y);
+    step(s + 1, Y, X);
   }
+  // no load may still be writing this workgroup's LDS when it exits
+  __builtin_amdgcn_s_waitcnt(0);
   // accumulator r of lane l holds D[row][col], col = l % 32,
   // row = 8 (r / 4) + 4 (l / 32) + r % 4
-  const float invN = (float)(1.0 / (double)rows);
-  float* Sb = S + I.S_off;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < B; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < B; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int64_t row = p0 + 64 * qi + 32 * i + 8 * (r >> 2) + 4 * kh + (r & 3);
-        const int64_t col = q0 + 64 * qj + 32 * j + m;
-        if (row < np && col < np && (ti != tj || row <= col)) {
-          const float v = acc[i][j][r] * invN;
-          Sb[row * np + col] = v;
-          Sb[col * np + row] = v;
+        const int lr = H * qi + 32 * i + 8 * (r >> 2) + 4 * kh + (r & 3);
+        const int lc = H * qj + 32 * j + m;
+        if (part) {
+          part[lr * T + lc] = acc[i][j][r];
+        } else {
+          const int64_t row = p0 + lr, col = q0 + lc;
+          if (row < np && col < np && (!diag || row <= col)) {
+            const float v = acc[i][j][r] * invN;
+            S[row * np + col] = v;
+            S[col * np + row] = v;
+          }
         }
       }
+}
+
+// unit u of an instance: a whole tile (u < nfull) or part k of tail tile t
+__device__ __forceinline__ void unit_of(int u, int nfull, int ks, int& t, int& k) {
+  if (u < nfull) {
+    t = u;
+    k = -1;
+  } else {
+    t = nfull + (u - nfull) / ks;
+    k = (u - nfull) % ks;
+  }
+}
+}  // namespace
+
+template <int B>
+__global__ __launch_bounds__(256) void k_syrk_dma(SrArgs A, const uint16_t* __restrict__ split,
+                                                  float* __restrict__ S) {
+  const SrInst& I = A.inst[blockIdx.y];
+  if (I.sb != B) return;
+  constexpr int T = DmaTile<B>::T;
+  const int nt = (int)ceil_div<int64_t>(I.np, T);
+  const int ntl = nt * (nt + 1) / 2;
+  const int nunits = I.nfull + (ntl - I.nfull) * I.tail_ks;
+  if ((int)blockIdx.x >= nunits) return;
+  __shared__ u16x8 stage[DmaTile<B>::kStages * DmaTile<B>::V];
+  int t, k;
+  unit_of(blockIdx.x, I.nfull, I.tail_ks, t, k);
+  int ti, tj;
+  tile_index(t, nt, ti, tj);
+  const int64_t steps = (I.rows + 31) / 32 * 2;   // 16-sample steps, an even count
+  int64_t s0 = 0, s1 = steps;
+  float* part = nullptr;
+  if (k >= 0) {
+    const int64_t chunk = ceil_div<int64_t>(steps / 2, I.tail_ks) * 2;
+    s0 = k * chunk;
+    s1 = s0 + chunk < steps ? s0 + chunk : steps;
+    part = reinterpret_cast<float*>(A.syrkpart + I.syrkpart_off) +
+           ((int64_t)(t - I.nfull) * I.tail_ks + k) * T * T;
+    if (s0 >= s1) {   // empty part: contributes zero
+      for (int e = threadIdx.x; e < T * T; e += blockDim.x) part[e] = 0.f;
+      return;
+    }
+  }
+  const uint16_t* hi = split + I.split_off;
+  const float invN = (float)(1.0 / (double)I.rows);
+  syrk_dma_tile<B>(hi, I.split_rows * I.split_ld, I.split_ld, I.np, invN, S + I.S_off,
+                   (int64_t)ti * T, (int64_t)tj * T, ti == tj, stage, s0, s1, part);
+}
+
+// Tail tiles: sum the sample parts in order, scale by 1/N, write both triangles.
+template <int B>
+__global__ void k_syrk_tail(SrArgs A, float* __restrict__ S) {
+  const SrInst& I = A.inst[blockIdx.z];
+  if (I.sb != B) return;
+  constexpr int T = DmaTile<B>::T;
+  const int nt = (int)ceil_div<int64_t>(I.np, T);
+  const int ntl = nt * (nt + 1) / 2;
+  const int tt = I.nfull + (int)blockIdx.y;
+  if (tt >= ntl) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= T * T) return;
+  int ti, tj;
+  tile_index(tt, nt, ti, tj);
+  const int lr = e / T, lc = e % T;
+  const int64_t row = (int64_t)ti * T + lr, col = (int64_t)tj * T + lc;
+  if (row >= I.np || col >= I.np || (ti == tj && row > col)) return;
+  const float* part = reinterpret_cast<const float*>(A.syrkpart + I.syrkpart_off) +
+                      (int64_t)blockIdx.y * I.tail_ks * T * T;
+  float a = 0.f;
+  for (int k = 0; k < I.tail_ks; ++k) a += part[(int64_t)k * T * T + e];
+  const float v = a * (float)(1.0 / (double)I.rows);
+  float* Sb = S + I.S_off;
+  Sb[row * I.np + col] = v;
+  Sb[col * I.np + row] = v;
 }
 
 __global__ void k_syrk_split_reduce(SrArgs A, float* __restrict__ S) {
   const SrInst& I = A.inst[blockIdx.y];
-  if (I.ksplit == 1) return;   // written directly by the tile kernel
+  if (I.sb || I.ksplit == 1) return;   // written directly by a tile kernel
   const int nt = (int)ceil_div<int64_t>(I.np, kT);
   const int ntiles = nt * (nt + 1) / 2;
   if ((int)blockIdx.x >= ntiles) return;
@@ -360,15 +366,29 @@ __global__ void k_syrk_split_reduce(SrArgs A, float* __restrict__ S) {
 }
 
 void sr_syrk_bf16x3(const SrArgs& A, const uint16_t* split, float* S, int n_inst, int64_t max_np,
-                    int max_ksplit, hipStream_t s) {
-  const int nt = (int)ceil_div<int64_t>(max_np, kT);
-  const int ntiles = nt * (nt + 1) / 2;
-  hipLaunchKernelGGL(k_syrk_mfma, dim3(ntiles, max_ksplit, n_inst), dim3(64), 0, s, A, split, S);
-  hipLaunchKernelGGL(k_syrk_split_reduce, dim3(ntiles, n_inst), dim3(256), 0, s, A, S);
-  const int nt2 = (int)ceil_div<int64_t>(max_np, kT2);
-  if (nt2 * (nt2 + 1) / 2 >= 512)
-    hipLaunchKernelGGL(k_syrk_lds128, dim3(nt2 * (nt2 + 1) / 2, n_inst), dim3(256), 0, s, A,
-                       split, S);
+                    int max_ksplit, const SyrkLaunch& L, hipStream_t s) {
+  if (L.any64) {
+    const int nt = (int)ceil_div<int64_t>(max_np, kT);
+    const int ntiles = nt * (nt + 1) / 2;
+    hipLaunchKernelGGL(k_syrk_mfma, dim3(ntiles, max_ksplit, n_inst), dim3(64), 0, s, A, split, S);
+    if (max_ksplit > 1)
+      hipLaunchKernelGGL(k_syrk_split_reduce, dim3(ntiles, n_inst), dim3(256), 0, s, A, S);
+  }
+  if (L.units[2]) {
+    hipLaunchKernelGGL(k_syrk_dma<2>, dim3(L.units[2], n_inst), dim3(256), 0, s, A, split, S);
+    if (L.tail[2])
+      hipLaunchKernelGGL(k_syrk_tail<2>, dim3(128 * 128 / 256, L.tail[2], n_inst), dim3(256), 0, s, A, S);
+  }
+  if (L.units[3]) {
+    hipLaunchKernelGGL(k_syrk_dma<3>, dim3(L.units[3], n_inst), dim3(256), 0, s, A, split, S);
+    if (L.tail[3])
+      hipLaunchKernelGGL(k_syrk_tail<3>, dim3(192 * 192 / 256, L.tail[3], n_inst), dim3(256), 0, s, A, S);
+  }
+  if (L.units[4]) {
+    hipLaunchKernelGGL(k_syrk_dma<4>, dim3(L.units[4], n_inst), dim3(256), 0, s, A, split, S);
+    if (L.tail[4])
+      hipLaunchKernelGGL(k_syrk_tail<4>, dim3(256 * 256 / 256, L.tail[4], n_inst), dim3(256), 0, s, A, S);
+  }
 }
 
 }  // namespace mvmc

@@ -17,14 +17,26 @@ struct SrInst {
   int64_t np, ldO, rows;          // parameters, O stride, samples used in this SR step
   int64_t O_off, S_off, eloc_off, param_off;
   int64_t colpart_off, syrkpart_off, chol_off, split_off;
-  int64_t split_rows;             // rows allocated per bf16 array (multiple of 16)
-  int32_t ksplit;                 // K split of the 64-tile split-bf16 S kernel
-  int32_t tile128;                // 1: S built by the 128-tile split-bf16 kernel (ksplit 1)
+  int64_t split_rows;             // rows per bf16 array (multiple of 32; zero past rows)
+  int64_t split_ld;               // parameter stride of the bf16 arrays (>= ldO, covers every tile)
+  int32_t ksplit;                 // sample split of the 64-tile split-bf16 S kernel
+  int32_t sb;                     // 0: 64-tile kernel; 2..4: direct-to-LDS tiles of side 64 sb
+  int32_t nfull;                  // direct-to-LDS tiles computed whole (the first nfull)
+  int32_t tail_ks;                // sample parts of each remaining (tail) tile
+};
+
+// Launch shape of the split-bf16 S build over all instances: whether any
+// instance takes the 64-tile kernel, and per tile side 64 b the largest
+// unit count (grid) and tail-tile count.
+struct SyrkLaunch {
+  bool any64;
+  int units[5];
+  int tail[5];
 };
 
 // bf16 split layout: element (sample m, parameter k) of the hi (or lo) array
-// at ((m / 8) * ldO + k) * 8 + m % 8, so the eight samples of one k-group of a
-// parameter are one 16-byte vector (an MFMA operand).
+// at ((m / 8) * split_ld + k) * 8 + m % 8, so the eight samples of one k-group
+// of a parameter are one 16-byte vector (an MFMA operand).
 __host__ __device__ inline int64_t split_index(int64_t m, int64_t k, int64_t ld) {
   return ((m >> 3) * ld + k) * 8 + (m & 7);
 }
@@ -70,7 +82,7 @@ void sr_syrk_vec(const SrArgs& A, const T* O, TS* S, int n_inst, int64_t max_np,
                  hipStream_t s);
 // split-bf16 (hi*hi + hi*lo + lo*hi) MFMA S build, FP32 accumulation
 void sr_syrk_bf16x3(const SrArgs& A, const uint16_t* split, float* S, int n_inst, int64_t max_np,
-                    int max_ksplit, hipStream_t s);
+                    int max_ksplit, const SyrkLaunch& L, hipStream_t s);
 template <typename TS>
 void sr_cholesky_solve(const SrArgs& A, const TS* S, const double* g, double eps_rel, double eps_abs,
                        double freeze, int n_inst, int64_t max_np, hipStream_t s);

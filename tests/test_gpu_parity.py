@@ -200,28 +200,44 @@ def test_mixed_precision_ratios(name, sweeps):
     ctx.close()
 
 
-@pytest.mark.parametrize("name,walkers", [("sq4_sub2", 256), ("sq10_full", 60)])
-def test_mixed_split_bf16_overlap(name, walkers):
+@pytest.mark.parametrize("name,walkers,tile", [("sq4_sub2", 256, 0), ("sq10_full", 60, 128),
+                                               ("sq10_full", 60, 192), ("sq10_full", 60, 256),
+                                               ("sq10_full", 60, "tuned")])
+def test_mixed_split_bf16_overlap(name, walkers, tile):
     """Split-bf16 S against the FP64 product of the same centred O.  The
-    10x10 case (N_p = 10002, 120 samples: a ragged 16-sample tail) runs the
-    128-tile kernel, the 4x4 case the 64-tile kernel with a K split."""
+    4x4 case runs the 64-tile kernel with a sample split; the 10x10 case
+    (N_p = 10002, 120 samples: a ragged tail of 24 past the last 32) runs
+    the direct-to-LDS kernel at each tile side, whose tail tiles are split
+    into sample parts (some empty at this size), and once with the side
+    chosen by the tuner."""
     inst = workload(name)["instances"][0] if name == "sq4_sub2" else _case(name)
     inst.n_walkers = walkers
     slots = 2
-    log(f"[mixed-S] {name} W={walkers} slots={slots} N_p={inst.n_params}")
+    log(f"[mixed-S] {name} W={walkers} slots={slots} N_p={inst.n_params} tile={tile}")
     ctx = _ctx([inst], inst.params0, seed=SEED, precision="mixed", refresh_every=32,
                n_slots=slots)
+    if tile == "tuned":
+        ctx.autotune(1)
+    elif tile:
+        ctx.set_s_tile(tile)
     ctx.sample(5)
     for s in range(slots):
         ctx.sample(1)
         ctx.measure(s)
     ctx.build_sr(slots)
+    sides, ms = ctx.s_tiles()
+    log(f"  S tile side {sides[0]}, tuning ms {ms[0]}")
+    if tile == "tuned":
+        assert sides[0] in (128, 192, 256) and np.all(np.isfinite(ms[0]))
+    else:
+        assert sides[0] == tile
     Oc = ctx.O_of(0, slots).cpu().numpy().astype(np.float64)
     S_ref = Oc.T @ Oc / Oc.shape[0]
     S = ctx.S_of(0).cpu().numpy().astype(np.float64)
     err = np.max(np.abs(S - S_ref)) / np.max(np.abs(S_ref))
     log(f"  split-bf16 S max rel error {err:.2e}")
     assert err < 2e-5
+    assert np.array_equal(S, S.T)
     ctx.close()
 
 
