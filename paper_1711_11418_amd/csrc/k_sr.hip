@@ -14,6 +14,7 @@
 #include <float.h>
 
 #include "sr.h"
+#include "wave.h"
 
 namespace mvmc {
 
@@ -237,85 +238,127 @@ __global__ void k_chol_prep(SrArgs A, const TS* __restrict__ S, const double* __
 
 constexpr int kNb = 64;
 
-__global__ __launch_bounds__(256) void k_potrf_diag(SrArgs A, int kb) {
+namespace {
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+}  // namespace
+
+// Cholesky of diagonal block kb, left-looking (Cholesky-Crout), one
+// wavefront: lane i keeps row i in registers and finishes it left to right,
+//   L[i][j] = (A[i][j] - sum_{m<j} L[i][m] L[j][m]) / L[j][j],
+//   L[j][j] = sqrt(A[j][j] - sum_{m<j} L[j][m]^2),
+// reading the finished row j from LDS.  Entries above the diagonal (and rows
+// past the matrix) are computed but never read or stored.  A non-positive
+// pivot sets the instance's flag.
+__global__ __launch_bounds__(64) void k_potrf_diag(SrArgs A, int kb) {
   const SrInst& I = A.inst[blockIdx.x];
   const int nblk = (int)ceil_div<int64_t>(I.np, kNb);
   if (kb >= nblk) return;
   const int64_t o = (int64_t)kb * kNb;
   const int nb = (int)(I.np - o < kNb ? I.np - o : kNb);
-  __shared__ double L[kNb][kNb + 1];
+  const int i = threadIdx.x;
+  if (i >= kNb) return;   // one wavefront per block
   double* F = A.chol + I.chol_off;
-  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
-    const int i = e / nb, j = e % nb;
-    L[i][j] = j <= i ? F[(o + i) * I.np + o + j] : 0.0;
+  double r[kNb];
+  const double* Fi = F + (o + (i < nb ? i : nb - 1)) * I.np + o;
+#pragma unroll
+  for (int j = 0; j < kNb; ++j) r[j] = Fi[j < nb ? j : nb - 1];
+  __shared__ double Ls[kNb][kNb + 1];
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < kNb; ++j) {
+    double s = r[j];
+#pragma unroll
+    for (int m = 0; m < j; ++m) s -= r[m] * Ls[j][m];
+    const double dj = lane_value(s, j);
+    if (j < nb && !(dj > 0.0)) bad = true;
+    const double ljj = sqrt(dj > 0.0 ? dj : DBL_MIN);
+    r[j] = i == j ? ljj : s / ljj;
+    Ls[i][j] = r[j];
+    wave::wave_sync();
+    asm volatile("" ::: "memory");   // keep each row's loads within its step
   }
-  __syncthreads();
-  for (int j = 0; j < nb; ++j) {
-    if (threadIdx.x == 0) {
-      const double dj = L[j][j];
-      if (!(dj > 0.0)) A.scal[blockIdx.x * kScal + kFlag] = 1.0;
-      L[j][j] = sqrt(dj > 0.0 ? dj : DBL_MIN);
-    }
-    __syncthreads();
-    const double ljj = L[j][j];
-    for (int i = j + 1 + threadIdx.x; i < nb; i += blockDim.x) L[i][j] /= ljj;
-    __syncthreads();
-    const int rem = nb - j - 1;
-    for (int e = threadIdx.x; e < rem * rem; e += blockDim.x) {
-      const int i = j + 1 + e / rem, k = j + 1 + e % rem;
-      if (k <= i) L[i][k] -= L[i][j] * L[k][j];
-    }
-    __syncthreads();
-  }
-  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
-    const int i = e / nb, j = e % nb;
-    if (j <= i) F[(o + i) * I.np + o + j] = L[i][j];
+  if (bad && i == 0) A.scal[blockIdx.x * kScal + kFlag] = 1.0;
+  double* Fw = F + (o + i) * I.np + o;
+  if (nb == kNb) {
+    // whole rows: the part above the diagonal is never read
+#pragma unroll
+    for (int j = 0; j < kNb; ++j) Fw[j] = r[j];
+  } else if (i < nb) {
+    for (int j = 0; j <= i; ++j) Fw[j] = Ls[i][j];
   }
 }
 
-// Panel below the diagonal block: rows r solve  L[r][blk] L_kk^T = F[r][blk].
-__global__ __launch_bounds__(64) void k_trsm_panel(SrArgs A, int kb) {
+// Panel below the diagonal block: every row r below it solves
+// L[r][blk] L_kk^T = F[r][blk], one thread per row with the row in
+// registers and L_kk shared in LDS (256 rows per workgroup).
+constexpr int kTrsmRows = 256;
+__global__ __launch_bounds__(kTrsmRows) void k_trsm_panel(SrArgs A, int kb) {
   const SrInst& I = A.inst[blockIdx.y];
   const int nblk = (int)ceil_div<int64_t>(I.np, kNb);
-  const int ib = kb + 1 + blockIdx.x;
-  if (kb >= nblk || ib >= nblk) return;
-  const int64_t o = (int64_t)kb * kNb, ro = (int64_t)ib * kNb;
+  if (kb >= nblk) return;
+  const int64_t o = (int64_t)kb * kNb;
+  const int64_t r0 = o + kNb + (int64_t)blockIdx.x * kTrsmRows;
+  if (r0 >= I.np) return;
   const int nb = (int)(I.np - o < kNb ? I.np - o : kNb);
-  const int nr = (int)(I.np - ro < kNb ? I.np - ro : kNb);
-  __shared__ double L[kNb][kNb + 1];
-  __shared__ double Pn[kNb][kNb + 1];
+  __shared__ double L[kNb][kNb];
   double* F = A.chol + I.chol_off;
   for (int e = threadIdx.x; e < kNb * kNb; e += blockDim.x) {
     const int i = e / kNb, j = e % kNb;
-    L[i][j] = (i < nb && j <= i) ? F[(o + i) * I.np + o + j] : 0.0;
-    Pn[i][j] = (i < nr && j < nb) ? F[(ro + i) * I.np + o + j] : 0.0;
+    L[i][j] = (i < nb && j <= i) ? F[(o + i) * I.np + o + j] : (i == j ? 1.0 : 0.0);
   }
   __syncthreads();
-  const int r = threadIdx.x;
-  if (r < nr) {
+  const int64_t row = r0 + threadIdx.x;
+  if (row >= I.np) return;
+  // columns past the matrix (last block only) read the last column and are
+  // replaced by zero, so the loads need no branch
+  double x[kNb];
+  double* Fr = F + row * I.np;
+#pragma unroll
+  for (int j = 0; j < kNb; ++j) {
+    const double v = Fr[o + j < I.np ? o + j : I.np - 1];
+    x[j] = j < nb ? v : 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < kNb; ++j) {
+    double s = x[j];
+#pragma unroll
+    for (int m = 0; m < j; ++m) s -= x[m] * L[j][m];
+    x[j] = s / L[j][j];
+    asm volatile("" ::: "memory");   // keep each row of L_kk's loads within its step
+  }
+  if (nb == kNb) {
+#pragma unroll
+    for (int j = 0; j < kNb; ++j) Fr[o + j] = x[j];
+  } else {
     for (int j = 0; j < nb; ++j) {
-      double s = Pn[r][j];
-      for (int m = 0; m < j; ++m) s -= Pn[r][m] * L[j][m];
-      Pn[r][j] = s / L[j][j];
+      double v = x[0];
+#pragma unroll
+      for (int t = 1; t < kNb; ++t)
+        if (t == j) v = x[t];
+      Fr[o + j] = v;
     }
-    for (int j = 0; j < nb; ++j) F[(ro + r) * I.np + o + j] = Pn[r][j];
   }
 }
 
-// Trailing update of the lower triangle: F[ib][jb] -= L[ib][kb] L[jb][kb]^T.
-__global__ __launch_bounds__(256) void k_chol_update(SrArgs A, int kb) {
+// Update inside an outer panel: F[ib][jb] -= L[ib][kb] L[jb][kb]^T for the
+// later blocks jb of the panel (kb < jb < jb_end) and every block row
+// ib >= jb (lower triangle).  The columns past the panel are left to
+// k_chol_trail, which applies the whole panel at once.
+__global__ __launch_bounds__(256) void k_chol_update(SrArgs A, int kb, int jb_end) {
   const SrInst& I = A.inst[blockIdx.y];
   const int nblk = (int)ceil_div<int64_t>(I.np, kNb);
-  const int R = nblk - kb - 1;
-  if (R <= 0 || (int)blockIdx.x >= R * (R + 1) / 2) return;
-  // linear index -> (ib', jb') with ib' >= jb'
-  int ibp = 0, start = 0;
-  while ((int)blockIdx.x >= start + ibp + 1) {
-    start += ibp + 1;
-    ++ibp;
+  const int jend = jb_end < nblk ? jb_end : nblk;
+  int idx = blockIdx.x, jb = kb + 1;
+  while (jb < jend && idx >= nblk - jb) {
+    idx -= nblk - jb;
+    ++jb;
   }
-  const int jbp = blockIdx.x - start;
-  const int ib = kb + 1 + ibp, jb = kb + 1 + jbp;
+  if (jb >= jend) return;
+  const int ib = jb + idx;
   const int64_t o = (int64_t)kb * kNb, ro = (int64_t)ib * kNb, co = (int64_t)jb * kNb;
   const int nk = (int)(I.np - o < kNb ? I.np - o : kNb);
   const int nr = (int)(I.np - ro < kNb ? I.np - ro : kNb);
@@ -351,40 +394,143 @@ __global__ __launch_bounds__(256) void k_chol_update(SrArgs A, int kb) {
     }
 }
 
-// Forward substitution L y = b on diagonal block kb (in place in x).
+// Trailing update of outer step ob: the lower triangle of the rows and
+// columns past the outer panel [o, o + kOuter) less L[:, panel] L[:, panel]^T,
+// on the FP64 matrix cores (v_mfma_f64_16x16x4f64).  A workgroup of four
+// wavefronts owns a 128 x 128 tile, each wavefront a 64 x 64 quadrant as
+// 4 x 4 blocks of 16 x 16 accumulators.  The panel's columns pass through
+// LDS 16 at a time, k-major (each MFMA operand is 16 consecutive doubles of
+// one column), double-buffered; rows past the matrix read the last row.
+constexpr int kOuter = 4 * kNb;   // outer panel width
+constexpr int kUT = 128;          // trailing-update tile
+constexpr int kUK = 16;           // panel columns per LDS stage
+constexpr int kUP = kUT + 2;      // padded LDS row (spreads the four k rows of an operand over the banks)
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_chol_trail(SrArgs A, int ob) {
+  const SrInst& I = A.inst[blockIdx.y];
+  const int64_t o = (int64_t)ob * kOuter, t0 = o + kOuter;
+  if (t0 >= I.np) return;
+  const int nt = (int)ceil_div<int64_t>(I.np - t0, kUT);
+  if ((int)blockIdx.x >= nt * (nt + 1) / 2) return;
+  int ti = 0, start = 0;   // lower-triangle tile (ti >= tj)
+  while ((int)blockIdx.x >= start + ti + 1) {
+    start += ti + 1;
+    ++ti;
+  }
+  const int tj = (int)blockIdx.x - start;
+  const int64_t r0 = t0 + (int64_t)ti * kUT, c0 = t0 + (int64_t)tj * kUT;
+  double* F = A.chol + I.chol_off;
+  __shared__ double As[2][kUK][kUP];
+  __shared__ double Bs[2][kUK][kUP];
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int qi = wv >> 1, qj = wv & 1;
+  const int lr = tid >> 1, lk = (tid & 1) * 8;   // staging: 8 panel columns of row lr
+  const int64_t ra = r0 + lr, rb = c0 + lr;
+  const double* pa = F + (ra < I.np ? ra : I.np - 1) * I.np + o + lk;
+  const double* pb = F + (rb < I.np ? rb : I.np - 1) * I.np + o + lk;
+  double ga[8], gb[8];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      ga[e] = pa[k0 + e];
+      gb[e] = pb[k0 + e];
+    }
+  };
+  auto lstore = [&](int st) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      As[st][lk + e][lr] = ga[e];
+      Bs[st][lk + e][lr] = gb[e];
+    }
+  };
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  int st = 0;
+  const int ka = lane >> 4, ma = lane & 15;   // operand element: k row, row within the block
+  for (int k0 = 0; k0 < kOuter; k0 += kUK) {
+    const bool more = k0 + kUK < kOuter;
+    if (more) gload(k0 + kUK);
+#pragma unroll
+    for (int kk = 0; kk < kUK; kk += 4) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[i] = As[st][kk + ka][64 * qi + 16 * i + ma];
+        b[i] = Bs[st][kk + ka][64 * qj + 16 * i + ma];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) lstore(st ^ 1);
+    __syncthreads();
+    st ^= 1;
+  }
+  // element r of lane l holds D[l / 16 + 4 r][l % 16] of its 16 x 16 block
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = r0 + 64 * qi + 16 * i + ka + 4 * r;
+        const int64_t col = c0 + 64 * qj + 16 * j + ma;
+        if (row < I.np && col < I.np && (ti != tj || col <= row)) F[row * I.np + col] -= acc[i][j][r];
+      }
+}
+
+// Substitution on diagonal block kb, in place in x, one wavefront: forward
+// (L y = b, lane i keeps row i of the block) or backward (L^T y = b, lane i
+// keeps column i).  Each solved y_j is broadcast and the later right-hand
+// sides are updated in parallel.
 __global__ __launch_bounds__(64) void k_trsv_diag(SrArgs A, int kb, int transpose) {
   const SrInst& I = A.inst[blockIdx.x];
   const int nblk = (int)ceil_div<int64_t>(I.np, kNb);
   if (kb >= nblk) return;
   const int64_t o = (int64_t)kb * kNb;
   const int nb = (int)(I.np - o < kNb ? I.np - o : kNb);
-  __shared__ double L[kNb][kNb + 1];
-  __shared__ double y[kNb];
+  const int i = threadIdx.x;
+  if (i >= kNb) return;   // one wavefront per block
   const double* F = A.chol + I.chol_off;
   double* x = A.x + I.param_off + o;
-  for (int e = threadIdx.x; e < kNb * kNb; e += blockDim.x) {
-    const int i = e / kNb, j = e % kNb;
-    L[i][j] = (i < nb && j <= i) ? F[(o + i) * I.np + o + j] : 0.0;
+  double Lr[kNb];
+#pragma unroll
+  for (int j = 0; j < kNb; ++j) {
+    if (!transpose)
+      Lr[j] = (i < nb && j <= i) ? F[(o + i) * I.np + o + j] : (i == j ? 1.0 : 0.0);
+    else
+      Lr[j] = (j < nb && i <= j) ? F[(o + j) * I.np + o + i] : (i == j ? 1.0 : 0.0);
   }
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) y[i] = x[i];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    if (!transpose) {
-      for (int i = 0; i < nb; ++i) {
-        double s = y[i];
-        for (int m = 0; m < i; ++m) s -= L[i][m] * y[m];
-        y[i] = s / L[i][i];
-      }
-    } else {
-      for (int i = nb - 1; i >= 0; --i) {
-        double s = y[i];
-        for (int m = i + 1; m < nb; ++m) s -= L[m][i] * y[m];
-        y[i] = s / L[i][i];
-      }
+  double b = i < nb ? x[i] : 0.0;
+  if (!transpose) {
+#pragma unroll
+    for (int j = 0; j < kNb; ++j) {
+      const double yj = lane_value(b / Lr[j], j);
+      if (i == j)
+        b = yj;
+      else if (i > j)
+        b -= Lr[j] * yj;
+    }
+  } else {
+#pragma unroll
+    for (int j = kNb - 1; j >= 0; --j) {
+      const double yj = lane_value(b / Lr[j], j);
+      if (i == j)
+        b = yj;
+      else if (i < j)
+        b -= Lr[j] * yj;
     }
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) x[i] = y[i];
+  if (i < nb) x[i] = b;
 }
 
 // Off-diagonal updates of the right-hand side after block kb is solved.
@@ -629,13 +775,29 @@ void sr_cholesky_solve(const SrArgs& A, const TS* S, const double* g, double eps
                        double freeze, int n_inst, int64_t max_np, hipStream_t s) {
   hipLaunchKernelGGL(k_chol_prep<TS>, dim3(max_np, n_inst), dim3(256), 0, s, A, S, g, eps_rel,
                      eps_abs, freeze);
+  // two levels: blocks of kNb factored inside outer panels of kOuter, the
+  // columns past each outer panel updated once per panel on the matrix cores
   const int nblk = (int)ceil_div<int64_t>(max_np, kNb);
-  for (int kb = 0; kb < nblk; ++kb) {
-    hipLaunchKernelGGL(k_potrf_diag, dim3(n_inst), dim3(256), 0, s, A, kb);
-    const int R = nblk - kb - 1;
-    if (R > 0) {
-      hipLaunchKernelGGL(k_trsm_panel, dim3(R, n_inst), dim3(64), 0, s, A, kb);
-      hipLaunchKernelGGL(k_chol_update, dim3(R * (R + 1) / 2, n_inst), dim3(256), 0, s, A, kb);
+  const int nob = (int)ceil_div<int64_t>(max_np, kOuter);
+  constexpr int kPer = kOuter / kNb;
+  for (int ob = 0; ob < nob; ++ob) {
+    const int kb0 = ob * kPer, kb1 = kb0 + kPer < nblk ? kb0 + kPer : nblk;
+    for (int kb = kb0; kb < kb1; ++kb) {
+      hipLaunchKernelGGL(k_potrf_diag, dim3(n_inst), dim3(kNb), 0, s, A, kb);
+      const int R = nblk - kb - 1;
+      if (R > 0) {
+        const int rows = (int)(max_np - (int64_t)(kb + 1) * kNb);
+        hipLaunchKernelGGL(k_trsm_panel, dim3(ceil_div(rows, kTrsmRows), n_inst), dim3(kTrsmRows),
+                           0, s, A, kb);
+        int tiles = 0;
+        for (int jb = kb + 1; jb < kb1; ++jb) tiles += nblk - jb;
+        if (tiles)
+          hipLaunchKernelGGL(k_chol_update, dim3(tiles, n_inst), dim3(256), 0, s, A, kb, kb1);
+      }
+    }
+    if (kb1 < nblk) {
+      const int nt = (int)ceil_div<int64_t>(max_np - (int64_t)(ob + 1) * kOuter, kUT);
+      hipLaunchKernelGGL(k_chol_trail, dim3(nt * (nt + 1) / 2, n_inst), dim3(256), 0, s, A, ob);
     }
   }
   for (int kb = 0; kb < nblk; ++kb) {

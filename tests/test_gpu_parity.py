@@ -115,14 +115,21 @@ def test_trajectory_replay_fp64(name, sweeps, refresh, threads):
 
 # --------------------------------------------------------------------- SR
 @pytest.mark.parametrize("name,solver", [("sq4_sub2", "chol"), ("sq4_sub2", "cg"),
-                                         ("ring6_rbm", "cg"), ("sq10_full", "cg")])
+                                         ("ring6_rbm", "cg"), ("sq10_full", "cg"),
+                                         ("sq12_sub", "chol")])
 def test_sr_matrices_and_update(name, solver):
     """S, g and the SR step against the oracle on the same samples.  The
-    10x10 case (N_p = 10002) runs the chunked matrix-free CG products."""
+    10x10 case (N_p = 10002) runs the chunked matrix-free CG products; the
+    12x12 case (N_p = 578: nine 64-blocks and a ragged block of 2) the
+    blocked Cholesky across block boundaries."""
     if name == "sq10_full":
         inst = _case(name)
         inst.n_walkers = 16
         slots = 2
+    elif name == "sq12_sub":
+        inst = _case(name)
+        inst.n_walkers = 128
+        slots = 6
     else:
         inst = workload(name)["instances"][0]
         inst.n_walkers = 64
