@@ -248,7 +248,7 @@ __device__ __forceinline__ double lane_value(double v, int lane) {
 
 // Cholesky of diagonal block kb, left-looking (Cholesky-Crout), one
 // wavefront: lane i keeps row i in registers and finishes it left to right,
-//   L[i][j] = (A[i][j] - sum_{m<j} L[i][m] L[j][m]) / L[j][j],
+//   L[i][j] = (A[i][j] - sum_{m<j} L[i][m] L[j][m]) * (1 / L[j][j]),
 //   L[j][j] = sqrt(A[j][j] - sum_{m<j} L[j][m]^2),
 // reading the finished row j from LDS.  Entries above the diagonal (and rows
 // past the matrix) are computed but never read or stored.  A non-positive
@@ -270,13 +270,16 @@ __global__ __launch_bounds__(64) void k_potrf_diag(SrArgs A, int kb) {
   bool bad = false;
 #pragma unroll
   for (int j = 0; j < kNb; ++j) {
-    double s = r[j];
+    // the dot product in four independent chains (latency, not bandwidth)
+    double c[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int m = 0; m < j; ++m) s -= r[m] * Ls[j][m];
+    for (int m = 0; m < j; ++m) c[m & 3] += r[m] * Ls[j][m];
+    const double s = r[j] - ((c[0] + c[1]) + (c[2] + c[3]));
     const double dj = lane_value(s, j);
     if (j < nb && !(dj > 0.0)) bad = true;
     const double ljj = sqrt(dj > 0.0 ? dj : DBL_MIN);
-    r[j] = i == j ? ljj : s / ljj;
+    const double rl = 1.0 / ljj;
+    r[j] = i == j ? ljj : s * rl;
     Ls[i][j] = r[j];
     wave::wave_sync();
     asm volatile("" ::: "memory");   // keep each row's loads within its step
@@ -399,15 +402,17 @@ __global__ __launch_bounds__(256) void k_chol_update(SrArgs A, int kb, int jb_en
 // on the FP64 matrix cores (v_mfma_f64_16x16x4f64).  A workgroup of four
 // wavefronts owns a 128 x 128 tile, each wavefront a 64 x 64 quadrant as
 // 4 x 4 blocks of 16 x 16 accumulators.  The panel's columns pass through
-// LDS 16 at a time, k-major (each MFMA operand is 16 consecutive doubles of
-// one column), double-buffered; rows past the matrix read the last row.
+// LDS k-major (each MFMA operand is 16 consecutive doubles of one column),
+// 16 at a time, double-buffered; rows past the matrix read the last row.
+// Two workgroups share a compute unit (two wavefronts per SIMD), which the
+// FP64 matrix unit needs to stay busy.
 constexpr int kOuter = 4 * kNb;   // outer panel width
 constexpr int kUT = 128;          // trailing-update tile
 constexpr int kUK = 16;           // panel columns per LDS stage
 constexpr int kUP = kUT + 2;      // padded LDS row (spreads the four k rows of an operand over the banks)
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void k_chol_trail(SrArgs A, int ob) {
+__global__ __launch_bounds__(256, 2) void k_chol_trail(SrArgs A, int ob) {
   const SrInst& I = A.inst[blockIdx.y];
   const int64_t o = (int64_t)ob * kOuter, t0 = o + kOuter;
   if (t0 >= I.np) return;
@@ -425,21 +430,21 @@ __global__ __launch_bounds__(256) void k_chol_trail(SrArgs A, int ob) {
   __shared__ double Bs[2][kUK][kUP];
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const int qi = wv >> 1, qj = wv & 1;
-  const int lr = tid >> 1, lk = (tid & 1) * 8;   // staging: 8 panel columns of row lr
+  const int lr = tid >> 1, lk = (tid & 1) * (kUK / 2);   // staging: half a stage row of row lr
   const int64_t ra = r0 + lr, rb = c0 + lr;
   const double* pa = F + (ra < I.np ? ra : I.np - 1) * I.np + o + lk;
   const double* pb = F + (rb < I.np ? rb : I.np - 1) * I.np + o + lk;
-  double ga[8], gb[8];
+  double ga[kUK / 2], gb[kUK / 2];
   auto gload = [&](int k0) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < kUK / 2; ++e) {
       ga[e] = pa[k0 + e];
       gb[e] = pb[k0 + e];
     }
   };
   auto lstore = [&](int st) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < kUK / 2; ++e) {
       As[st][lk + e][lr] = ga[e];
       Bs[st][lk + e][lr] = gb[e];
     }
