@@ -36,10 +36,18 @@ __host__ __device__ inline size_t ap_walker_bytes(int ns_max, int nsmax_sites) {
   return (ns_max * sizeof(double)) + ((ints * sizeof(int32_t) + 15) & ~(size_t)15);
 }
 
+// LDS per walker for M^-1 (row stride wld = max up electrons + 1), staged
+// so X^-1 is written row by row with the lanes across the columns.
+template <typename T>
+__host__ __device__ inline size_t ap_minv_bytes(int wld) {
+  return ((size_t)(wld - 1) * wld * sizeof(T) + 15) & ~(size_t)15;
+}
+
 template <typename T, int NS>
 __global__ __launch_bounds__(64 * kApWpb) void k_refresh_ap(Pools P,
                                                              const int32_t* __restrict__ wlist,
-                                                             int n, int max_sites, double sing_tol,
+                                                             int n, int max_sites, int wld,
+                                                             double sing_tol,
                                                              int32_t* __restrict__ flags) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -51,11 +59,12 @@ __global__ __launch_bounds__(64 * kApWpb) void k_refresh_ap(Pools P,
   const int ne = I.ne, ns = I.ns, n2 = 2 * ns, nh = I.nup;
   const int64_t lw = gw - I.walker_off;
 
-  unsigned char* q = smem + (size_t)wv * ap_walker_bytes(NS, max_sites);
+  unsigned char* q = smem + (size_t)wv * (ap_walker_bytes(NS, max_sites) + ap_minv_bytes<T>(wld));
   double* rowp = (double*)q;
   int32_t* pos = (int32_t*)(rowp + NS);
   int32_t* piv = pos + 2 * NS;
   int32_t* occ = piv + NS;
+  T* Wl = (T*)(q + ap_walker_bytes(NS, max_sites));   // M^-1, row stride wld
 
   const int32_t* posg = P.pos + I.pos_off + lw * ne;
   for (int b = lane; b < ne; b += 64) pos[b] = posg[b];
@@ -95,28 +104,28 @@ __global__ __launch_bounds__(64 * kApWpb) void k_refresh_ap(Pools P,
   } else {
     if (parity & 1) sgn = -sgn;
     if (((nh * (nh - 1)) / 2) & 1) sgn = -sgn;   // Pf(X) = (-1)^{n(n-1)/2} det M
-    // lane p_a holds row a of M^-1 at the columns p_b:
-    //   Y[n + a][p_b] = M^-1[a][p_b],  Y[p_b][n + a] = -M^-1[a][p_b]
+    // lane p_a holds row a of M^-1 at the columns p_b; W[a][q] = M^-1[a][q]
+    // goes to LDS, then every row of Y is written with the lanes across it:
+    //   Y[q][n + a] = -W[a][q],  Y[n + a][q] = W[a][q],  same-spin blocks 0
     T* Y = (T*)P.Y + I.Y_off + lw * ne * ne;
-    // column pivoted by this lane's row
-    int a = -1;
+    int a = -1;   // row of M^-1 pivoted by this lane's row
 #pragma unroll
     for (int k = 0; k < NS; ++k)
       if (k < nh && piv[k] == lane) a = k;
     if (live && a >= 0) {
-      T* rdn = Y + (int64_t)(nh + a) * ne;
-      for (int b = 0; b < nh; ++b) rdn[nh + b] = T(0);   // down-down block
 #pragma unroll
       for (int b = 0; b < NS; ++b)
-        if (b < nh) {
-          const int qb = piv[b];
-          rdn[qb] = (T)m[b];
-          Y[(int64_t)qb * ne + nh + a] = (T)(-m[b]);
-        }
+        if (b < nh) Wl[a * wld + piv[b]] = (T)m[b];
     }
-    if (live) {
-      T* rup = Y + (int64_t)lane * ne;
-      for (int b = 0; b < nh; ++b) rup[b] = T(0);        // up-up block
+    wave_sync();
+    for (int r = 0; r < ne; ++r) {
+      T* yr = Y + (int64_t)r * ne;
+      for (int c = lane; c < ne; c += 64) {
+        T v = T(0);
+        if (r < nh && c >= nh) v = -Wl[(c - nh) * wld + r];
+        if (r >= nh && c < nh) v = Wl[(r - nh) * wld + c];
+        yr[c] = v;
+      }
     }
     if (lane == 0) {
       if (flags) flags[gw] = 0;
@@ -336,7 +345,9 @@ __host__ __device__ inline size_t ap_blk_bytes(int NS, int NW, int max_sites) {
 }  // namespace
 
 bool refresh_ap_fits(int max_ne, int max_ns) {
-  if (max_ne <= 128) return ap_walker_bytes(64, max_ns) * kApWpb <= 64 * 1024;
+  if (max_ne <= 128)
+    return (ap_walker_bytes(64, max_ns) + ap_minv_bytes<double>(max_ne / 2 + 1)) * kApWpb <=
+           152 * 1024;
   return max_ne <= 160 && ap_blk_bytes(80, 2, max_ns) <= 64 * 1024;
 }
 
@@ -351,14 +362,21 @@ void launch_refresh_ap(const Pools& P, const int32_t* wlist, int n, int max_ne, 
                        sing_tol, flags);
     return;
   }
+  const int wld = max_ne / 2 + 1;
   if (max_ne <= 64) {
-    const size_t sh = ap_walker_bytes(32, max_ns) * kApWpb;
+    const size_t sh = (ap_walker_bytes(32, max_ns) + ap_minv_bytes<T>(wld)) * kApWpb;
+    if (sh > 64 * 1024)
+      (void)hipFuncSetAttribute((const void*)&k_refresh_ap<T, 32>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     hipLaunchKernelGGL((k_refresh_ap<T, 32>), dim3(blocks), dim3(64 * kApWpb), sh, s, P, wlist, n,
-                       max_ns, sing_tol, flags);
+                       max_ns, wld, sing_tol, flags);
   } else {
-    const size_t sh = ap_walker_bytes(64, max_ns) * kApWpb;
+    const size_t sh = (ap_walker_bytes(64, max_ns) + ap_minv_bytes<T>(wld)) * kApWpb;
+    if (sh > 64 * 1024)
+      (void)hipFuncSetAttribute((const void*)&k_refresh_ap<T, 64>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     hipLaunchKernelGGL((k_refresh_ap<T, 64>), dim3(blocks), dim3(64 * kApWpb), sh, s, P, wlist, n,
-                       max_ns, sing_tol, flags);
+                       max_ns, wld, sing_tol, flags);
   }
 }
 
