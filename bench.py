@@ -410,6 +410,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="launch the sampling eagerly")
     ap.add_argument("--sweep-threads", type=int, default=0,
                     help="0: register-resident sweep where it fits; 64/128/256: LDS sweep")
+    ap.add_argument("--s-build-only", action="store_true",
+                    help="print only the split-bf16 S build leg (for kernel profiling)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the walkers of this workload fit one MI355X; "
@@ -418,6 +420,10 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     from mvmc_inputs import workload
+
+    if a.s_build_only:
+        print(json.dumps({"s_build_bf16x3_c3": s_build_leg()}), flush=True)
+        return
 
     copy = hbm_copy_probe()
     log(f"[bench] HBM copy probe: {copy['gbs']:.0f} GB/s")
