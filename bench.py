@@ -130,7 +130,31 @@ def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", 
         "kernel_calls": calls.tolist(), "W": i0.n_walkers, "ne": i0.n_elec, "np": i0.n_params,
         "sweeps": sweeps, "N": slots * i0.n_walkers, "graph": graph is not None,
         "autotune": tuned, "cholesky_shift_raises": escalations, "cg_iterations": cg_iters,
+        "steps": steps,
     }
+
+
+def measure_hbm_model(r, wsize):
+    """E_loc and O_k: every sample reads Y once (N_e^2 w) and writes its O row
+    (N_p w); modelled rate over the measurement time of one SR step."""
+    ne, npar = r["ne"], r["np"]
+    bytes_ = r["N"] * (ne * ne + npar) * wsize
+    ms = r["kernel_ms"][2]
+    gbs = bytes_ / (ms * 1e-3) / 1e9
+    return {"alg_bytes_per_step": bytes_, "ms_per_step": ms, "achieved_gbs": gbs,
+            "peak_gbs": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS}
+
+
+def sweep_hbm_model(r, wsize, sweep_ms):
+    """Modelled HBM rate of the sweeps of one SR step: every proposal reads
+    one row of Y (N_e w bytes), every accept reads and writes all of Y
+    (2 N_e^2 w bytes); the fraction is against the HBM peak."""
+    ne = r["ne"]
+    props = r["proposals"] / max(r["steps"], 1)
+    bytes_ = props * ne * wsize + props * r["accept_ratio"] * 2 * ne * ne * wsize
+    gbs = bytes_ / (sweep_ms * 1e-3) / 1e9
+    return {"alg_bytes_per_step": bytes_, "sweep_ms_per_step": sweep_ms, "achieved_gbs": gbs,
+            "peak_gbs": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS}
 
 
 def precision_leg(steps):
@@ -149,9 +173,23 @@ def precision_leg(steps):
         km = dict(zip(["sweep", "refresh", "measure", "sr_stats", "s_build", "sr_solve"],
                       r["kernel_ms"]))
         N, npar = r["N"], r["np"]
+        nh = r["ne"] // 2
+        ref_calls = max(r["kernel_calls"][1], 1)
+        # block-route refresh: Gauss-Jordan inversion of the N_e/2 x N_e/2 block, 2 n^3 flops
+        ref_flops = ref_calls * r["W"] * 2.0 * nh ** 3
         out[prec] = {"value": r["rate"], "unit": "hop-updates/s", "ms_per_step": r["ms_per_step"],
                      "accept_ratio": r["accept_ratio"], "kernel_ms_per_step": km,
                      "s_build_tflops": N * npar * (npar + 1) / (km["s_build"] * 1e-3) / 1e12,
+                     "sweep_modelled_hbm": sweep_hbm_model(r, 4 if prec == "mixed" else 8,
+                                                           km["sweep"]),
+                     "refresh": {"launches_per_step": r["kernel_calls"][1],
+                                 "fp64_tflops": ref_flops / (km["refresh"] * 1e-3) / 1e12,
+                                 "peak_tflops": FP64_PEAK_TFLOPS,
+                                 "flops_model": "2 (N_e/2)^3 per walker (block route)"},
+                     "cholesky": {"fp64_tflops": npar ** 3 / 3 / (km["sr_solve"] * 1e-3) / 1e12,
+                                  "peak_tflops": FP64_PEAK_TFLOPS,
+                                  "note": "N_p^3/3 flops over the whole solve (factor, "
+                                          "substitutions, update)"},
                      "cholesky_shift_raises": r["cholesky_shift_raises"],
                      "energy_per_site": [e / i0.n_sites for e in r["energies"]]}
     out["speedup_mixed_vs_fp64"] = out["mixed"]["value"] / out["fp64"]["value"]
@@ -182,6 +220,7 @@ def rbm_leg(steps):
             "cg_iterations": r["cg_iterations"], "cg_cap": 50,
             "cg_ms_per_iteration": km["sr_solve"] / max(it, 1),
             "cg_gbs_per_iteration": 2 * o_bytes / (km["sr_solve"] / max(it, 1) * 1e-3) / 1e9,
+            "sweep_modelled_hbm": sweep_hbm_model(r, 4, km["sweep"]),
             "energy_per_site": [e / i0.n_sites for e in r["energies"]]}
 
 
@@ -359,8 +398,8 @@ def _oracle_worker(args):
     from mvmc_inputs import random_configs, workload
     from oracle import sampler
     from oracle import wavefunction as wf
-    wid, n_prop, budget = args
-    inst = workload("c2_sq8_fp64", n_walkers=4)["instances"][0]
+    wid, name, n_prop, budget = args
+    inst = workload(name, n_walkers=4)["instances"][0]
     m = wf.expand(inst, inst.params0)
     A = wf.skew_table(m)
     done = 0
@@ -379,25 +418,42 @@ def _oracle_worker(args):
 
 def cpu_baseline(budget_s=12.0):
     """The oracle (full-recompute Metropolis, Parlett-Reid per proposal) on
-    the host cores, one process per core, on a time-bounded sample of the
-    8x8 workload; plus numpy O^T O at 4096 x 2000 in double."""
+    the host cores, one process per core, on time-bounded samples of the 8x8
+    workload (the headline), the 8-site ring and the 10x10 workload; plus
+    numpy O^T O at 4096 x 2000 and numpy's Cholesky at 10^4, in double."""
     import multiprocessing as mp
 
     import numpy as np
     cores = min(os.cpu_count() or 1, 16)
-    with mp.get_context("spawn").Pool(cores) as pool:
-        res = pool.map(_oracle_worker, [(w, 10 ** 9, budget_s) for w in range(cores)])
-    props = sum(r[0] for r in res)
-    wall = max(r[1] for r in res)
+
+    def rate(name, budget):
+        with mp.get_context("spawn").Pool(cores) as pool:
+            res = pool.map(_oracle_worker, [(w, name, 10 ** 9, budget) for w in range(cores)])
+        return sum(r[0] for r in res), max(r[1] for r in res)
+
+    props, wall = rate("c2_sq8_fp64", budget_s)
+    p1, w1 = rate("c1_ring8_fp64", 3.0)
+    p3, w3 = rate("c3_sq10_mixed", 5.0)
     rng = np.random.default_rng(0)
     O = rng.standard_normal((4096, 2000))
     t0 = time.perf_counter()
     S = O.T @ O / 4096
     ts = time.perf_counter() - t0
+    B = rng.standard_normal((10000, 10000))
+    B = (B + B.T) * 0.5 + 10000.0 * np.eye(10000)   # symmetric, diagonally dominant: SPD
+    t0 = time.perf_counter()
+    np.linalg.cholesky(B)
+    tc = time.perf_counter() - t0
+    try:
+        blas = np.show_config(mode="dicts")["Build Dependencies"]["blas"]["name"]
+    except Exception:   # the configuration report differs between numpy versions
+        blas = "unknown"
     return {"value": props / wall, "unit": "hop-updates/s", "cores": cores, "kind": "oracle",
             "sample": f"{props} full-recompute proposals on the 8x8 U=4 workload, "
                       f"{cores} processes x {budget_s:.0f} s",
-            "s_build_gflops_numpy_fp64": 4096 * 2000 * 2001 / ts / 1e9}
+            "ring8_hop_updates_per_s": p1 / w1, "sq10_hop_updates_per_s": p3 / w3,
+            "s_build_gflops_numpy_fp64": 4096 * 2000 * 2001 / ts / 1e9,
+            "cholesky_1e4_numpy_fp64_s": tc, "nproc": os.cpu_count(), "blas": blas}
 
 
 def main():
@@ -455,6 +511,7 @@ def main():
         "measured_peaks": {"hbm_copy_gbs": copy["gbs"], "hbm_copy": copy},
         "kernel_ms_per_step": dict(zip(["sweep", "refresh", "measure", "sr_stats", "s_build",
                                         "sr_solve"], r["kernel_ms"])),
+        "measure_modelled_hbm": measure_hbm_model(r, 8),
         "energy_per_site": [e / 64 for e in r["energies"]],
     }
     if not a.skip_legs:
