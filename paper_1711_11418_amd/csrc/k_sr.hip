@@ -13,6 +13,8 @@
 // instances (the last grid dimension) so ragged batches share launches.
 #include <float.h>
 
+#include <type_traits>
+
 #include "sr.h"
 #include "wave.h"
 
@@ -191,9 +193,74 @@ __global__ __launch_bounds__(256) void k_syrk_vec(SrArgs A, const T* __restrict_
 }
 
 // Sum the split-K partials in order, scale by 1/N, write both triangles.
+// Double-precision S on the FP64 matrix cores (v_mfma_f64_16x16x4f64):
+// the same 64 x 64 upper-triangle tiles and sample split as k_syrk_vec, each
+// wavefront a 32 x 32 quadrant as 2 x 2 blocks of 16 x 16 accumulators,
+// operands read from the k-major LDS stage (16 consecutive doubles of one
+// sample per MFMA operand).
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+constexpr int kTp = kTile + 2;   // padded LDS row
+__global__ __launch_bounds__(256) void k_syrk_f64mfma(SrArgs A, const double* __restrict__ O) {
+  const SrInst& I = A.inst[blockIdx.z];
+  const int nt = (int)ceil_div<int64_t>(I.np, kTile);
+  const int ntiles = nt * (nt + 1) / 2;
+  if ((int)blockIdx.x >= ntiles || (int)blockIdx.y >= I.ksplit) return;
+  int ti, tj;
+  tile_of(blockIdx.x, nt, ti, tj);
+  const int64_t chunk = ceil_div<int64_t>(ceil_div<int64_t>(I.rows, I.ksplit), kKc) * kKc;
+  const int64_t r0 = (int64_t)blockIdx.y * chunk;
+  const int64_t r1 = r0 + chunk < I.rows ? r0 + chunk : I.rows;
+  __shared__ double As[kKc][kTp];
+  __shared__ double Bs[kKc][kTp];
+  const double* Ob = O + I.O_off;
+  const int64_t ld = I.ldO;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int qi = wv >> 1, qj = wv & 1, ka = lane >> 4, ma = lane & 15;
+  const int c_a = ti * kTile, c_b = tj * kTile;
+  f64x4_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+  for (int64_t m0 = r0; m0 < r1; m0 += kKc) {
+    for (int e = tid; e < kKc * kTile; e += 256) {
+      const int kk = e / kTile, c = e % kTile;
+      const int64_t m = m0 + kk;
+      const bool okm = m < r1;
+      As[kk][c] = (okm && c_a + c < I.np) ? Ob[m * ld + c_a + c] : 0.0;
+      Bs[kk][c] = (okm && c_b + c < I.np) ? Ob[m * ld + c_b + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kKc; kk += 4) {
+      double a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        a[i] = As[kk + ka][32 * qi + 16 * i + ma];
+        b[i] = Bs[kk + ka][32 * qj + 16 * i + ma];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // element r of lane l holds D[l / 16 + 4 r][l % 16] of its 16 x 16 block
+  double* part = A.syrkpart + I.syrkpart_off + ((int64_t)blockIdx.y * ntiles + blockIdx.x) * kTile * kTile;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        part[(32 * qi + 16 * i + ka + 4 * r) * kTile + 32 * qj + 16 * j + ma] = acc[i][j][r];
+}
+
 template <typename TS>
 __global__ void k_syrk_reduce(SrArgs A, TS* __restrict__ S) {
-  const SrInst& I = A.inst[blockIdx.y];
+  const SrInst& I = A.inst[blockIdx.z];
   const int nt = (int)ceil_div<int64_t>(I.np, kTile);
   const int ntiles = nt * (nt + 1) / 2;
   if ((int)blockIdx.x >= ntiles) return;
@@ -202,16 +269,16 @@ __global__ void k_syrk_reduce(SrArgs A, TS* __restrict__ S) {
   const double* part = A.syrkpart + I.syrkpart_off;
   const double invN = 1.0 / (double)I.rows;
   TS* Sb = S + I.S_off;
-  for (int e = threadIdx.x; e < kTile * kTile; e += blockDim.x) {
-    const int i = e / kTile, j = e % kTile;
-    const int64_t r = (int64_t)ti * kTile + i, c = (int64_t)tj * kTile + j;
-    if (r >= I.np || c >= I.np) continue;
-    double s = 0.0;
-    for (int ks = 0; ks < I.ksplit; ++ks) s += part[((int64_t)ks * ntiles + blockIdx.x) * kTile * kTile + e];
-    s *= invN;
-    Sb[r * I.np + c] = (TS)s;
-    Sb[c * I.np + r] = (TS)s;
-  }
+  const int e = (int)blockIdx.y * blockDim.x + threadIdx.x;   // element of the tile
+  if (e >= kTile * kTile) return;
+  const int i = e / kTile, j = e % kTile;
+  const int64_t r = (int64_t)ti * kTile + i, c = (int64_t)tj * kTile + j;
+  if (r >= I.np || c >= I.np) return;
+  double s = 0.0;
+  for (int ks = 0; ks < I.ksplit; ++ks) s += part[((int64_t)ks * ntiles + blockIdx.x) * kTile * kTile + e];
+  s *= invN;
+  Sb[r * I.np + c] = (TS)s;
+  Sb[c * I.np + r] = (TS)s;
 }
 
 // ------------------------------------------------------------ SR solve
@@ -771,8 +838,12 @@ void sr_syrk_vec(const SrArgs& A, const T* O, TS* S, int n_inst, int64_t max_np,
                  hipStream_t s) {
   const int nt = (int)ceil_div<int64_t>(max_np, kTile);
   const int ntiles = nt * (nt + 1) / 2;
-  hipLaunchKernelGGL(k_syrk_vec<T>, dim3(ntiles, max_ksplit, n_inst), dim3(256), 0, s, A, O);
-  hipLaunchKernelGGL(k_syrk_reduce<TS>, dim3(ntiles, n_inst), dim3(256), 0, s, A, S);
+  if constexpr (std::is_same<T, double>::value)
+    hipLaunchKernelGGL(k_syrk_f64mfma, dim3(ntiles, max_ksplit, n_inst), dim3(256), 0, s, A, O);
+  else
+    hipLaunchKernelGGL(k_syrk_vec<T>, dim3(ntiles, max_ksplit, n_inst), dim3(256), 0, s, A, O);
+  hipLaunchKernelGGL(k_syrk_reduce<TS>, dim3(ntiles, kTile * kTile / 256, n_inst), dim3(256), 0, s,
+                     A, S);
 }
 
 template <typename TS>
