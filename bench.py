@@ -308,7 +308,8 @@ def sweep_roofline(r, wsize):
     return avg_ms, bytes_, flops
 
 
-def sweep_roofline_entry(sweep_threads, avg_ms, bytes_, flops, traffic, traffic_note):
+def sweep_roofline_entry(sweep_threads, avg_ms, bytes_, flops, traffic, traffic_note,
+                         probes=None, copy_gbs=None):
     """Roofline of the sweep kernel.  The byte model charges every proposal
     one row of Y and every accept a read and a write of all of Y.  The
     register-resident kernel keeps Y on chip for the whole launch (the
@@ -325,6 +326,7 @@ def sweep_roofline_entry(sweep_threads, avg_ms, bytes_, flops, traffic, traffic_
         return {"kernel": "k_sweep_reg<double, 64, 4, false, false>", "bound": "alu",
                 "achieved": tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": tflops / FP64_PEAK_TFLOPS,
+                "frac_of_measured_fp64_fma": (tflops / probes["fp64_fma"]) if probes else None,
                 "modelled_hbm": {"achieved_gbs": gbs, "peak_gbs": HBM_PEAK_GBS,
                                  "frac": gbs / HBM_PEAK_GBS},
                 "residency": "Y in registers for the whole launch", **common}
@@ -483,6 +485,9 @@ def main():
 
     copy = hbm_copy_probe()
     log(f"[bench] HBM copy probe: {copy['gbs']:.0f} GB/s")
+    from paper_1711_11418_amd.binding import peak_probe
+    probes = {k: peak_probe(k) for k in ("bf16_mfma", "fp64_mfma", "fp64_fma")}
+    log(f"[bench] instruction peaks (TFLOP/s): {probes}")
     wl = workload("c2_sq8_fp64")
     log(f"[bench] c2_sq8_fp64 fp64: W=1024 sweeps/step={wl['sweeps']} steps={a.steps} "
         f"warmup={a.warmup}")
@@ -505,10 +510,18 @@ def main():
         "accepted_per_s": r["rate"] * r["accept_ratio"],
         "accept_ratio": r["accept_ratio"],
         "s_build": {"tflops": s_flops / (s_ms * 1e-3) / 1e12, "ms": s_ms, "dtype": "f64",
-                    "shape": [r["N"], r["np"]]},
+                    "shape": [r["N"], r["np"]], "kernel": "FP64 MFMA 16x16x4",
+                    "frac_of_fp64_peak": s_flops / (s_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                    "frac_of_measured_fp64_mfma": s_flops / (s_ms * 1e-3) / 1e12 /
+                                                  probes["fp64_mfma"]},
         "roofline": sweep_roofline_entry(a.sweep_threads, avg_ms, bytes_, flops, traffic,
-                                         traffic_note),
-        "measured_peaks": {"hbm_copy_gbs": copy["gbs"], "hbm_copy": copy},
+                                         traffic_note, probes, copy["gbs"]),
+        "measured_peaks": {"hbm_copy_gbs": copy["gbs"], "hbm_copy": copy,
+                           "bf16_mfma_tflops": probes["bf16_mfma"],
+                           "fp64_mfma_tflops": probes["fp64_mfma"],
+                           "fp64_fma_tflops": probes["fp64_fma"],
+                           "note": "register-only loops on non-zero data, two wavefronts per "
+                                   "SIMD (mvmc_peak_probe); datasheet peaks in roofline.peak"},
         "kernel_ms_per_step": dict(zip(["sweep", "refresh", "measure", "sr_stats", "s_build",
                                         "sr_solve"], r["kernel_ms"])),
         "measure_modelled_hbm": measure_hbm_model(r, 8),
@@ -524,6 +537,8 @@ def main():
                         "kernel_ms_per_step": m["kernel_ms"]}
         log("[bench] split-bf16 S build at 4096 x 10^4")
         out["s_build_bf16x3_c3"] = s_build_leg()
+        out["s_build_bf16x3_c3"]["issued_frac_of_measured_bf16_mfma"] = (
+            out["s_build_bf16x3_c3"]["issued_mfma_tflops"] / probes["bf16_mfma"])
         log("[bench] 10x10 precision leg: mixed vs plain FP64")
         out["sq10_mixed_vs_fp64"] = precision_leg(2)
         log("[bench] 16x16 RBM leg (8192 walkers, CG)")

@@ -206,6 +206,19 @@ int mvmc_s_tiles(const mvmc_ctx *ctx, int32_t *h_tile, double *h_ms);
 int mvmc_set_s_tile(mvmc_ctx *ctx, int32_t side);
 
 /*
+ * Measurement aid for the roofline report (not a step of the method):
+ * attainable throughput of the instructions the path relies on, timed on
+ * register-only loops with non-zero data at two wavefronts per SIMD over
+ * every compute unit.  kind: 0 bf16 MFMA 32x32x16 (FP32 accumulate),
+ * 1 FP64 MFMA 16x16x4, 2 FP64 vector FMA.  d_scratch: device buffer of at
+ * least mvmc_peak_probe_bytes() bytes (overwritten, caller-owned).  Runs on
+ * hip_stream (NULL: the null stream) and synchronises it; *h_tflops receives
+ * TFLOP/s.  Errors: MVMC_E_ARG, MVMC_E_HIP.
+ */
+size_t mvmc_peak_probe_bytes(void);
+int mvmc_peak_probe(int32_t kind, void *d_scratch, void *hip_stream, double *h_tflops);
+
+/*
  * Local energy E_loc(x) (Eq. MC, H of section 2.3) and the row of
  * O_k = d ln<x|psi>/d alpha_k (section 3.3.1) of every walker's current
  * configuration into sample slot `slot` (0 <= slot < n_slots):

@@ -23,6 +23,7 @@ ENTRY_POINTS = (
     "mvmc_get_state", "mvmc_set_state", "mvmc_get_inverse", "mvmc_get_pfaffian", "mvmc_refresh",
     "mvmc_trace_enable", "mvmc_timing", "mvmc_destroy", "mvmc_last_error", "mvmc_status_string",
     "mvmc_autotune", "mvmc_sweep_variants", "mvmc_s_tiles", "mvmc_set_s_tile",
+    "mvmc_peak_probe_bytes", "mvmc_peak_probe",
 )
 N_SWEEP_VARIANTS = 7
 SWEEP_VARIANT_NAMES = ("reg", "lds64", "lds128", "lds256", "hbm64", "hbm128", "hbm256")
@@ -109,17 +110,38 @@ def load() -> C.CDLL:
         "mvmc_sweep_variants": [vp, vp],
         "mvmc_s_tiles": [vp, vp, vp],
         "mvmc_set_s_tile": [vp, C.c_int32],
+        "mvmc_peak_probe_bytes": [],
+        "mvmc_peak_probe": [C.c_int32, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = C.c_int
+    lib.mvmc_peak_probe_bytes.restype = C.c_size_t
     lib.mvmc_last_error.argtypes = [vp]
     lib.mvmc_last_error.restype = C.c_char_p
     lib.mvmc_status_string.argtypes = [C.c_int]
     lib.mvmc_status_string.restype = C.c_char_p
     _lib = lib
     return lib
+
+
+PEAK_PROBES = ("bf16_mfma", "fp64_mfma", "fp64_fma")
+
+
+def peak_probe(kind: str) -> float:
+    """Attainable TFLOP/s of one instruction class on this GPU
+    (mvmc_peak_probe): "bf16_mfma", "fp64_mfma" or "fp64_fma"."""
+    import torch
+    lib = load()
+    buf = torch.empty(int(lib.mvmc_peak_probe_bytes()), dtype=torch.uint8, device="cuda")
+    out = C.c_double(0.0)
+    stream = torch.cuda.current_stream().cuda_stream
+    rc = lib.mvmc_peak_probe(PEAK_PROBES.index(kind), C.c_void_p(buf.data_ptr()),
+                             C.c_void_p(stream), C.byref(out))
+    if rc != 0:
+        raise MVMCError(rc, lib.mvmc_status_string(rc).decode())
+    return out.value
 
 
 class _Desc:

@@ -1199,6 +1199,47 @@ int mvmc_set_s_tile(mvmc_ctx* c, int32_t side) {
   return MVMC_OK;
 }
 
+namespace {
+constexpr int kProbeBlocksMax = 2 * 1024;   // two workgroups per compute unit, up to 1024 CUs
+}  // namespace
+
+size_t mvmc_peak_probe_bytes(void) { return sizeof(float) * 256 * (size_t)kProbeBlocksMax; }
+
+int mvmc_peak_probe(int32_t kind, void* d_scratch, void* hip_stream, double* h_tflops) {
+  if (kind < 0 || kind > 2 || !d_scratch || !h_tflops) return MVMC_E_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      ncu < 1)
+    return MVMC_E_HIP;
+  const int blocks = std::min(2 * ncu, kProbeBlocksMax);
+  const int iters = kind == 2 ? 20000 : 2000;
+  float* out = reinterpret_cast<float*>(d_scratch);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return MVMC_E_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return MVMC_E_HIP;
+  }
+  constexpr int kReps = 3;
+  launch_probe(kind, out, blocks, iters, s);   // warm-up
+  (void)hipEventRecord(e0, s);
+  for (int r = 0; r < kReps; ++r) launch_probe(kind, out, blocks, iters, s);
+  (void)hipEventRecord(e1, s);
+  int rc = MVMC_OK;
+  float ms = 0.f;
+  if (hipGetLastError() != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+      hipEventElapsedTime(&ms, e0, e1) != hipSuccess || !(ms > 0.f))
+    rc = MVMC_E_HIP;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  const double flops = (double)kReps * blocks * 4 * iters * probe_flops_per_wave_iter(kind);
+  *h_tflops = flops / (ms * 1e-3) / 1e12;
+  return MVMC_OK;
+}
+
 int mvmc_measure_energy_and_O(mvmc_ctx* c, int32_t slot, double* d_eloc, void* d_O) {
   if (!c || !d_eloc || !d_O) return set_err(c, fail(MVMC_E_ARG, "NULL buffer"));
   if (slot < 0 || slot >= c->cfg.n_slots)

@@ -59,4 +59,8 @@ template <typename T>
 void launch_measure(const Pools& P, const int32_t* wlist, int n, int slot, double* eloc, T* O,
                     int max_ne, int max_ns, int max_M, hipStream_t s);
 
+// peak probes (k_probe.hip): 0 bf16 MFMA, 1 FP64 MFMA, 2 FP64 vector FMA
+double probe_flops_per_wave_iter(int kind);
+void launch_probe(int kind, float* out, int blocks, int iters, hipStream_t s);
+
 }  // namespace mvmc

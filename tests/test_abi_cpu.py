@@ -21,7 +21,7 @@ def _lib():
 def test_every_declared_symbol_is_exported():
     b = _lib()
     hdr = open(os.path.join(ROOT, "include", "mvmc.h")).read()
-    declared = set(re.findall(r"^(?:int|const char \*)\s*(mvmc_\w+)\(", hdr, re.M))
+    declared = set(re.findall(r"^(?:int|size_t|const char \*)\s*(mvmc_\w+)\(", hdr, re.M))
     assert declared == set(b.ENTRY_POINTS)
     lib = b.load()
     for name in declared:
