@@ -145,16 +145,27 @@ def measure_hbm_model(r, wsize):
             "peak_gbs": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS}
 
 
-def sweep_hbm_model(r, wsize, sweep_ms):
-    """Modelled HBM rate of the sweeps of one SR step: every proposal reads
-    one row of Y (N_e w bytes), every accept reads and writes all of Y
-    (2 N_e^2 w bytes); the fraction is against the HBM peak."""
+def sweep_hbm_model(r, wsize, sweep_ms, kernel_model=True):
+    """Modelled HBM rate of the sweeps of one SR step.  The method's byte
+    model: every proposal reads one row of Y (N_e w bytes), every accept
+    reads and writes all of Y (2 N_e^2 w bytes).  The LDS/HBM kernel moves
+    less: with the anti-parallel pair amplitude the same-spin blocks of Y
+    are zero, so a proposal reads half a row and an accept reads one
+    N_e/2 x N_e/2 block for q and reads and writes the two opposite-spin
+    blocks (1.25 N_e^2 w bytes); that count is reported beside it."""
     ne = r["ne"]
     props = r["proposals"] / max(r["steps"], 1)
-    bytes_ = props * ne * wsize + props * r["accept_ratio"] * 2 * ne * ne * wsize
+    acc = props * r["accept_ratio"]
+    bytes_ = props * ne * wsize + acc * 2 * ne * ne * wsize
     gbs = bytes_ / (sweep_ms * 1e-3) / 1e9
-    return {"alg_bytes_per_step": bytes_, "sweep_ms_per_step": sweep_ms, "achieved_gbs": gbs,
-            "peak_gbs": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS}
+    out = {"alg_bytes_per_step": bytes_, "sweep_ms_per_step": sweep_ms, "achieved_gbs": gbs,
+           "peak_gbs": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS}
+    if kernel_model:
+        kb = props * ne // 2 * wsize + acc * 1.25 * ne * ne * wsize
+        kg = kb / (sweep_ms * 1e-3) / 1e9
+        out.update({"kernel_bytes_per_step": kb, "kernel_gbs": kg,
+                    "kernel_frac": kg / HBM_PEAK_GBS})
+    return out
 
 
 def precision_leg(steps):

@@ -154,12 +154,17 @@ __global__ __launch_bounds__(NT) void k_sweep(Pools P, const int32_t* __restrict
     const int Iold = pos_s[a];
     const int site_old = Iold - sigma * ns;
 
-    // Pfaffian ratio: dot of the new row a of X with row a of Y
+    // Pfaffian ratio: dot of the new row a of X with row a of Y.  With the
+    // anti-parallel pair amplitude (Eq. AP-Pf) the new row of X vanishes on
+    // the electrons of a's own spin, and so do the same-spin blocks of Y
+    // ([[0, -M^-T], [M^-1, 0]]): only the opposite-spin electrons enter.
+    const int o0 = sigma ? 0 : nup, o1 = sigma ? nup : ne;   // opposite spin
+    const int s0 = sigma ? nup : 0, s1 = sigma ? ne : nup;   // a's spin
     const T* Arow = A + (int64_t)Inew * n2;
     const T* Ya = Y + a * ne;
     T accp = T(0);
-    for (int b = tid; b < ne; b += NT) {
-      const T xb = (b == a) ? T(0) : Arow[pos_s[b]];
+    for (int b = o0 + tid; b < o1; b += NT) {
+      const T xb = Arow[pos_s[b]];
       xn[b] = xb;
       accp += xb * Ya[b];
     }
@@ -192,29 +197,40 @@ __global__ __launch_bounds__(NT) void k_sweep(Pools P, const int32_t* __restrict
     ++acc;
     __syncthreads();   // x' visible to every thread
 
-    // p = -Y[a,:];  partial column sums of q = -Y^T x' over row blocks
-    for (int i = tid; i < ne; i += NT) pv[i] = -Ya[i];
+    // p = -Y[a,:] lives on the opposite spin, q = -Y^T x' + e_a on a's spin
+    // (x' is zero on a's spin and Y's same-spin blocks are zero), so only
+    // the two opposite-spin blocks of Y are read and updated; the same-spin
+    // blocks would receive exact zeros.
+    for (int i = o0 + tid; i < o1; i += NT) pv[i] = -Ya[i];
     {
-      const int j0 = (wid * ne) / NW, j1 = ((wid + 1) * ne) / NW;
-      for (int i = lane; i < ne; i += 64) {
-        T s = T(0);
-        for (int j = j0; j < j1; ++j) s += Y[j * ne + i] * xn[j];
-        qpart[wid * ne + i] = s;
+      const int no = o1 - o0;
+      const int j0 = o0 + (wid * no) / NW, j1 = o0 + ((wid + 1) * no) / NW;
+      for (int i = s0 + lane; i < s1; i += 64) {
+        T sq = T(0);
+        for (int j = j0; j < j1; ++j) sq += Y[j * ne + i] * xn[j];
+        qpart[wid * ne + i] = sq;
       }
     }
     __syncthreads();
-    for (int i = tid; i < ne; i += NT) {
-      T s = T(0);
+    for (int i = s0 + tid; i < s1; i += NT) {
+      T sq = T(0);
 #pragma unroll
-      for (int w = 0; w < NW; ++w) s += qpart[w * ne + i];
-      qv[i] = (i == a ? T(1) : T(0)) - s;
+      for (int w = 0; w < NW; ++w) sq += qpart[w * ne + i];
+      qv[i] = (i == a ? T(1) : T(0)) - sq;
     }
     __syncthreads();
     const T ir = T(1.0 / r_pf);
+    // rows of a's spin: Y[r][c] -= q_r p_c / r_Pf over the opposite-spin columns;
+    // rows of the opposite spin: Y[r][c] += p_r q_c / r_Pf over a's spin
     for (int rr = wid; rr < ne; rr += NW) {
-      const T pr = pv[rr] * ir, qr = qv[rr] * ir;
       T* Yr = Y + rr * ne;
-      for (int c = lane; c < ne; c += 64) Yr[c] += pr * qv[c] - qr * pv[c];
+      if (rr >= s0 && rr < s1) {
+        const T qr = qv[rr] * ir;
+        for (int c = o0 + lane; c < o1; c += 64) Yr[c] -= qr * pv[c];
+      } else {
+        const T pr = pv[rr] * ir;
+        for (int c = s0 + lane; c < s1; c += 64) Yr[c] += pr * qv[c];
+      }
     }
     // V is symmetric: row site_new read across the threads is coalesced
     for (int l = tid; l < ns; l += NT) hs[l] += V[(int64_t)site_new * ns + l] - V[(int64_t)site_old * ns + l];

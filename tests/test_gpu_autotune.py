@@ -70,3 +70,39 @@ def test_autotune_ragged_batch_replay(tmp_path):
     assert np.all(np.isnan(ms2))
     assert ctx2.sweep_variants() == after
     ctx2.close()
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6])
+def test_forced_variant_replay(tmp_path, variant):
+    """Every LDS and HBM sweep variant, pinned through a cache line, replays
+    the oracle's chain (FP64, 1e-10) and keeps the inverse equal to inv(X):
+    N_e = 72 on the 8x8 lattice, with in-launch refresh stops."""
+    from paper_1711_11418_amd import MVMC
+    from paper_1711_11418_amd.binding import SWEEP_VARIANT_NAMES
+    from oracle import wavefunction as wf
+    inst = square_case(8, 36, 3, full_f=False)
+    cache = tmp_path / "pin.txt"
+    cache.write_text(f"mvmc-sweep 0 {inst.n_elec} {inst.n_sites} 0 {inst.n_walkers} {variant}\n")
+    log(f"[variant] {SWEEP_VARIANT_NAMES[variant]} Ne={inst.n_elec} W={inst.n_walkers}")
+    ctx = MVMC([inst], inst.params0, seed=SEED, refresh_every=40)
+    ms = ctx.autotune(1, cache)
+    assert np.all(np.isnan(ms)) and ctx.sweep_variants() == [SWEEP_VARIANT_NAMES[variant]]
+    pos0 = good_configs(inst, inst.params0, inst.n_walkers, 13)
+    ctx.set_state(pos0.ravel(), np.zeros(inst.n_walkers, dtype=np.int64))
+    sweeps = 2
+    n_prop = sweeps * inst.n_elec
+    ctx.enable_trace(n_prop)
+    ctx.sample(sweeps)
+    rec = ctx.trace_records()
+    walkers, m = oracle_trajectories(inst, inst.params0, pos0, 0, n_prop, SEED)
+    st = compare_trace(rec, walkers, n_prop, SEED, rtol=1e-10)
+    log(f"  compared {st['compared']} ratios, worst rel err {st['worst_rel']:.2e}")
+    assert st["compared"] == n_prop * inst.n_walkers
+    pos, _ = ctx.get_state()
+    pos = ctx.pos_of(pos, 0).cpu().numpy()
+    Y = ctx.Y_of(ctx.get_inverse(), 0).cpu().numpy()
+    A = wf.skew_table(m)
+    for w in range(inst.n_walkers):
+        Yr = np.linalg.inv(A[np.ix_(pos[w], pos[w])])
+        assert np.max(np.abs(Y[w] - Yr)) <= 1e-9 * np.max(np.abs(Yr)), w
+    ctx.close()
