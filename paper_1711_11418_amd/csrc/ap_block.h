@@ -17,8 +17,22 @@
 namespace mvmc {
 namespace {
 
+// |det M| is carried as a mantissa in [1/2, 1) and a binary exponent,
+// renormalised after every pivot (one frexp per step instead of one
+// logarithm); log|det M| is formed once, after the last step.
+__device__ __forceinline__ void absdet_mul(double& mant, int& ex, double x) {
+  int e;
+  mant = frexp(mant * x, &e);
+  ex += e;
+}
+__device__ __forceinline__ double absdet_log(double mant, int ex) {
+  return log(mant) + (double)ex * 0.69314718055994530942;
+}
+
 struct ApState {
   double logabs = 0.0, sgn = 1.0, minpiv = DBL_MAX;
+  double mant = 1.0;   // |det| = mant 2^ex over the steps taken
+  int ex = 0;
   uint64_t used = 0;   // rows pivoted so far
   int parity = 0;
   bool singular = false;
@@ -44,7 +58,7 @@ __device__ __forceinline__ void ap_steps(ApState& st, double (&m)[NS], double* r
         const int xlo = __builtin_amdgcn_readlane(__double2loint(m[K]), p);
         const int xhi = __builtin_amdgcn_readlane(__double2hiint(m[K]), p);
         const double pv = __hiloint2double(xhi, xlo);
-        st.logabs += log(fabs(pv));
+        absdet_mul(st.mant, st.ex, fabs(pv));
         if (pv < 0.0) st.sgn = -st.sgn;
         st.minpiv = fmin(st.minpiv, fabs(pv));
         st.parity += __builtin_popcountll(~st.used & ((1ull << p) - 1ull));
@@ -67,6 +81,8 @@ __device__ __forceinline__ void ap_steps(ApState& st, double (&m)[NS], double* r
       }
     }
     ap_steps<K + 1, NS>(st, m, rowp, piv, lane, live, nh, tol);
+  } else {
+    st.logabs = absdet_log(st.mant, st.ex);
   }
 }
 

@@ -164,6 +164,8 @@ __global__ __launch_bounds__(64 * kApWpb) void k_refresh_ap(Pools P,
 // through LDS between workgroup barriers.
 struct ApStateBlk {
   double logabs = 0.0, sgn = 1.0, minpiv = DBL_MAX;
+  double mant = 1.0;   // |det| = mant 2^ex over the steps taken
+  int ex = 0;
   uint64_t used[2] = {0, 0};   // rows pivoted so far (up to 128)
   int parity = 0;
   bool singular = false;
@@ -206,7 +208,7 @@ __device__ __forceinline__ void ap_steps_blk(ApStateBlk& st, double (&m)[NS], do
         if (threadIdx.x == 0) piv[K] = p;
         __syncthreads();
         const double pv = rowp[K];
-        st.logabs += log(fabs(pv));
+        absdet_mul(st.mant, st.ex, fabs(pv));
         if (pv < 0.0) st.sgn = -st.sgn;
         st.minpiv = fmin(st.minpiv, fabs(pv));
         const int pl = p & 63, pwv = p >> 6;
@@ -226,6 +228,8 @@ __device__ __forceinline__ void ap_steps_blk(ApStateBlk& st, double (&m)[NS], do
       }
     }
     ap_steps_blk<K + 1, NS, NW>(st, m, rowp, piv, redv, redi, row, live, nh, tol);
+  } else {
+    st.logabs = absdet_log(st.mant, st.ex);
   }
 }
 

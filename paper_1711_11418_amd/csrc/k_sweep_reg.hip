@@ -1,24 +1,34 @@
-// Register-resident Metropolis sweep: one wavefront per walker, X^-1 held in
-// VGPRs for the whole launch, WPB walkers of one instance per workgroup
-// sharing the pair-amplitude table f in LDS.
+// Register-resident Metropolis sweep: one wavefront per walker, the non-zero
+// blocks of X^-1 held in VGPRs for the whole launch, WPB walkers of one
+// instance per workgroup sharing the pair-amplitude table f in LDS.
 //
-// Lane l owns the columns c = l + 64k (k < KC) of Y = X^-1 and keeps
-// y[k][i] = Y[i][c] for every row i.  Per proposal (same arithmetic as the
-// LDS kernel; hopping update of section 3.1.2 with the fast-update ratio):
-//   row a of Y      y[k][a], a uniform index (branch tree over a)
+// With anti-parallel pairing (Eq. AP-Pf), up electrons 0..n-1 and down
+// electrons n..2n-1, X = [[0, M], [-M^T, 0]] and Y = X^-1 =
+// [[0, -M^-T], [M^-1, 0]]: entries of Y between two electrons of the same
+// spin are zero and the hopping update keeps them zero.  Lane c < N_e keeps
+// the n entries of column c in the rows of the opposite spin,
+//   z[i] = Y[o_c + i][c],   o_c = n for an up electron c, 0 for a down one,
+// which halves the registers and the update work of a full column.  Per
+// proposal moving electron a of spin sigma (a' = a - sigma n; hopping update
+// of section 3.1.2 with the fast-update ratio):
+//   Y[a][c]         for c of the other spin is z_c[a'] (an indexed register
+//                   move with a uniform index)
 //   x'_c            the anti-parallel pair amplitude between the new
 //                   spin-orbital I' and electron c: f(site', site_c) when an
 //                   up electron moves and c is down, -f(site_c, site') when a
-//                   down electron moves and c is up, else 0 (Eq. AP-Pf with
-//                   X_IJ = F_IJ - F_JI)
+//                   down electron moves and c is up, else 0 (X_IJ = F_IJ - F_JI)
 //   r_Pf            -sum_c Y[a][c] x'_c   (DPP wave reduction)
-//   correlators     scalar loads (Gutzwiller, Jastrow field in LDS, RBM)
-// On acceptance, with p = -Y[a,:], q = -Y^T x' + e_a (column sums over the
-// registers with x' broadcast from LDS):
-//   y[k][i] += p_i (q_c / r_Pf) - q_i (p_c / r_Pf)
+//   correlators     Gutzwiller factors and Jastrow field from LDS, V[old][new]
+//                   by a vector load, RBM angles in LDS
+// On acceptance, with p = -Y[a,:] (non-zero on the other spin) and
+// q = -Y^T x' + e_a (non-zero on a's spin) written to the two halves of an
+// LDS vector w,
+//   c of a's spin:         z[i] += p_{o_c + i} q_c / r_Pf
+//   c of the other spin:   z[i] -= q_{o_c + i} p_c / r_Pf
+// which is Y += (p q^T - q p^T) / r_Pf restricted to its non-zero blocks.
 // Every per-proposal quantity that is the same for the whole walker lives in
-// scalar registers (Philox runs on the scalar unit), so the proposal loop has
-// no workgroup barrier.
+// scalar registers (Philox runs on the vector unit once per 64 proposals),
+// so the proposal loop has no workgroup barrier.
 #include "ap_block.h"
 #include "launch.h"
 #include "wave.h"
@@ -30,36 +40,51 @@ using namespace wave;
 
 __host__ __device__ inline size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
 
-// LDS: [f table ns x (ns+1) in double | WPB x per-walker block]; the
-// single-precision sweep converts the gathered amplitudes, which equals
-// reading the single-precision copy of the table.
-__host__ __device__ inline size_t reg_table_bytes(int ns, size_t ts) {
-  (void)ts;
-  return a16((size_t)ns * (ns + 1) * sizeof(double));
+// LDS: [f table ns x (ns+1) | Gutzwiller g per site | WPB x per-walker
+// block], all tables in double; the single-precision sweep converts the
+// gathered amplitudes, which equals reading a single-precision copy.
+__host__ __device__ inline size_t reg_table_bytes(int ns) {
+  return a16((size_t)ns * (ns + 1) * sizeof(double)) + a16((size_t)ns * sizeof(double));
 }
 __host__ __device__ inline size_t reg_refresh_bytes(int ne_max) {
   const size_t nh = (size_t)ne_max / 2;
   return a16(nh * (nh + 1) * sizeof(double)) + a16(nh * sizeof(double)) +
          a16(2 * nh * sizeof(int32_t));
 }
+// x' and w, each as [up half | 16-byte gap | down half] of ne_max/2 entries
+__host__ __device__ inline size_t reg_half_len(int ne_max, size_t ts) {
+  return (size_t)ne_max + 16 / ts;
+}
 __host__ __device__ inline size_t reg_walker_bytes(int ne_max, int ns, int M, size_t ts) {
-  return a16(3 * (size_t)ne_max * ts) + a16((size_t)ns * sizeof(double)) + a16((size_t)M * ts) +
-         a16((size_t)(4 * ns + ne_max) * sizeof(int32_t)) + reg_refresh_bytes(ne_max);
+  return a16(2 * reg_half_len(ne_max, ts) * ts) + a16((size_t)ns * sizeof(double)) +
+         a16((size_t)M * ts) + a16((size_t)(4 * ns + ne_max) * sizeof(int32_t)) +
+         reg_refresh_bytes(ne_max);
 }
 
-// y[a] for a uniform runtime index a, as a branch tree over compile-time
-// indices.  The empty volatile asm in each leaf keeps the compiler from
-// folding the tree back into one dynamically indexed access, which would
-// move the whole register array to scratch memory.
-template <typename T, int N, int LO, int HI>
-__device__ __forceinline__ T pick(const T (&y)[N], int a) {
-  if constexpr (HI - LO == 1) {
-    asm volatile("" ::: );
-    return y[LO];
+// The n = NH register entries of a lane as groups of at most 32 dwords, the
+// largest register vector the indexed-move path handles.
+template <typename T, int NH>
+struct RegCol {
+  static constexpr int GS = NH < 128 / (int)sizeof(T) ? NH : 128 / (int)sizeof(T);
+  static constexpr int NG = NH / GS;
+  typedef T __attribute__((ext_vector_type(GS))) Vec;
+};
+
+// z[i] for a uniform runtime i < NH: one indexed register move per group
+// (no branch tree, no scratch), then a select between the groups.
+template <typename T, int NH, typename ZArr>
+__device__ __forceinline__ T pick_col(const ZArr& z, int i) {
+  using RC = RegCol<T, NH>;
+  static_assert(RC::NG == 1 || RC::NG == 2, "one or two register groups");
+  if constexpr (RC::NG == 1) {
+    return z[0][i];
   } else {
-    constexpr int MID = (LO + HI) / 2;
-    if (a < MID) return pick<T, N, LO, MID>(y, a);
-    return pick<T, N, MID, HI>(y, a);
+    T v0 = z[0][i & (RC::GS - 1)], v1 = z[1][i & (RC::GS - 1)];
+    // keep the two extracts apart, so the select is of two values and not
+    // of the two whole groups
+    asm volatile("" : "+v"(v0));
+    asm volatile("" : "+v"(v1));
+    return i >= RC::GS ? v1 : v0;
   }
 }
 
@@ -67,8 +92,8 @@ template <typename T> __device__ __forceinline__ const T* rbmT_ptr(const Pools& 
 template <> __device__ __forceinline__ const double* rbmT_ptr<double>(const Pools& P) { return P.rbmT64; }
 template <> __device__ __forceinline__ const float* rbmT_ptr<float>(const Pools& P) { return P.rbmT32; }
 
-// Uniform value the optimiser may not look through (keeps branch-tree tests
-// as 32-bit scalar compares).
+// Uniform value the optimiser may not look through (keeps the compares on
+// it as 32-bit scalar compares).
 __device__ __forceinline__ int opaque(int v) {
   asm volatile("" : "+s"(v));
   return v;
@@ -77,7 +102,7 @@ __device__ __forceinline__ int opaque(int v) {
 }  // namespace
 
 size_t sweep_reg_lds_bytes(int ne_max, int ns, int M, size_t tsize, int wpb) {
-  return reg_table_bytes(ns, tsize) + (size_t)wpb * reg_walker_bytes(ne_max, ns, M, tsize);
+  return reg_table_bytes(ns) + (size_t)wpb * reg_walker_bytes(ne_max, ns, M, tsize);
 }
 
 constexpr int kChunk = 8;   // rows per group of broadcast loads in the update
@@ -92,18 +117,18 @@ constexpr int kChunk = 8;   // rows per group of broadcast loads in the update
 // Double-precision recomputation inside the launch through the
 // anti-parallel block (Eq. AP-Pf): the n = N_e/2 rows of M sit one per lane
 // during the exchange steps (ap_steps); the final tableau then goes through
-// LDS and every lane rebuilds its column c of X^-1 = [[0, -M^-T], [M^-1, 0]]:
-//   c an up electron:          X^-1[n + a][c] = M^-1[a][c]
-//   c = n + a' a down one:     X^-1[q][c]     = -M^-1[a'][q]
-// with M^-1[a][p_b] = T[p_a][b]; same-spin blocks are zero.
-template <int NE_MAX, typename T>
-__device__ __forceinline__ int reg_refresh_ap(T (&y)[1][NE_MAX], int posr0,
-                                              const double* __restrict__ fs, int ldf, int ns,
-                                              int ne, int lane, int32_t* posl, double* tab,
-                                              double* rowp, int32_t* piv, int32_t* pinv,
-                                              double& logabs, double& sgn) {
+// LDS and every lane rebuilds its n entries of X^-1 = [[0, -M^-T], [M^-1, 0]]:
+//   c an up electron:          z[i] = X^-1[n + i][c] = M^-1[i][c]
+//   c = n + a' a down one:     z[i] = X^-1[i][c]     = -M^-1[a'][i]
+// with M^-1[a][p_b] = T[p_a][b].
+template <int NE_MAX, typename T, typename ZArr>
+__device__ __forceinline__ int reg_refresh_ap(
+    ZArr& z, int posr0,
+    const double* __restrict__ fs, int ldf, int ns, int ne, int lane, int32_t* posl,
+    double* tab, double* rowp, int32_t* piv, int32_t* pinv, double& logabs, double& sgn) {
   constexpr int NH = NE_MAX / 2;
   constexpr int LDT = NH + 1;
+  using RC = RegCol<T, NH>;
   int nh = ne / 2;
   asm volatile("" : "+s"(nh));   // keep the per-index compares inside this call
   if (lane < NE_MAX) posl[lane] = posr0;
@@ -134,12 +159,17 @@ __device__ __forceinline__ int reg_refresh_ap(T (&y)[1][NE_MAX], int posr0,
   // column of T for an up lane (pinv[c]), row of T for a down lane (p_{a'})
   const int own = up ? pinv[lane] : (dn ? piv[lane - nh] : 0);
 #pragma unroll
-  for (int r = 0; r < NE_MAX; ++r) {
-    double v = 0.0;
-    if (up && r >= nh && r < ne) v = tab[piv[r >= nh ? r - nh : 0] * LDT + own];
-    else if (dn && r < nh) v = -tab[own * LDT + pinv[r < nh ? r : 0]];
-    y[0][r] = (T)v;
-  }
+  for (int g = 0; g < RC::NG; ++g)
+#pragma unroll
+    for (int j = 0; j < RC::GS; ++j) {
+      const int i = g * RC::GS + j;
+      double v = 0.0;
+      if (i < nh) {
+        if (up) v = tab[piv[i] * LDT + own];
+        else if (dn) v = -tab[own * LDT + pinv[i]];
+      }
+      z[g][j] = (T)v;
+    }
   wave_sync();
   return 0;
 }
@@ -152,23 +182,34 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
                                                         const uint64_t* __restrict__ target,
                                                         int32_t* __restrict__ needs_refresh, int R,
                                                         int kref) {
-  constexpr int KC = (NE_MAX + 63) / 64;
+  constexpr int NH = NE_MAX / 2;
+  using RC = RegCol<T, NH>;
+  using Vec = typename RC::Vec;
+  constexpr int HD = NH + 16 / (int)sizeof(T);   // start of the down half of x' and w
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x & 63;
   const int wv = sgpr(threadIdx.x >> 6);
   const int g0 = wlist[blockIdx.x * WPB];
   const InstDev& I = P.inst[P.walker_inst[g0]];
-  const int ns = I.ns, ne = I.ne, n2 = 2 * ns, M = I.M, nup = I.nup;
-  const int ldf = ns + 1;
+  // instance fields read once (the loop below then holds them in registers)
+  const int ns = sgpr(I.ns), ne = sgpr(I.ne), M = sgpr(I.M);
+  const int nh = ne / 2;   // n_up = n_dn
+  const int n2 = 2 * ns, ldf = ns + 1;
+  const int64_t walker_off = I.walker_off, pos_off = I.pos_off, empty_off = I.empty_off,
+                h_off = I.h_off, theta_off = I.theta_off, Y_off = I.Y_off, A_off = I.A_off,
+                V_off = I.V_off, site_off = I.site_off, rbm_a_off = I.rbm_a_off,
+                rbm_b_off = I.rbm_b_off, rbm_W_off = I.rbm_W_off;
 
-  // shared pair-amplitude table f[i][j] = A[i][Ns + j]
+  // shared pair-amplitude table f[i][j] = A[i][Ns + j] and Gutzwiller g
   double* fs = (double*)smem;
+  double* gs = (double*)(smem + a16((size_t)ns * ldf * sizeof(double)));
   {
-    const double* A = P.A64 + I.A_off;
+    const double* A = P.A64 + A_off;
     for (int e = threadIdx.x; e < ns * ns; e += 64 * WPB) {
       const int i = e / ns, j = e - (e / ns) * ns;
       fs[i * ldf + j] = A[(int64_t)i * n2 + ns + j];
     }
+    for (int e = threadIdx.x; e < ns; e += 64 * WPB) gs[e] = P.G[site_off + e];
   }
   __syncthreads();   // the only workgroup barrier
 
@@ -184,14 +225,13 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
   }
   if (todo == 0) return;
   const int n_prop = (int)todo;
-  const int64_t lw = gw - I.walker_off;
+  const int64_t lw = gw - walker_off;
 
-  unsigned char* q = smem + reg_table_bytes(ns, sizeof(T)) +
+  unsigned char* q = smem + reg_table_bytes(ns) +
                      (size_t)wv * reg_walker_bytes(NE_MAX, ns, M, sizeof(T));
-  T* xn = (T*)q;
-  T* pv = xn + NE_MAX;
-  T* qv = pv + NE_MAX;
-  q += a16(3 * (size_t)NE_MAX * sizeof(T));
+  T* xn = (T*)q;                               // x', halves at 0 and HD
+  T* w = xn + reg_half_len(NE_MAX, sizeof(T));  // p and q, halves at 0 and HD
+  q += a16(2 * reg_half_len(NE_MAX, sizeof(T)) * sizeof(T));
   double* hs = (double*)q;
   q += a16((size_t)ns * sizeof(double));
   T* ths = (T*)q;
@@ -202,17 +242,23 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
   q += a16((size_t)(4 * ns + NE_MAX) * sizeof(int32_t));
   // refresh scratch: tableau, pivot row, pivot rows per column and inverse
   double* tab = (double*)q;
-  q += a16((size_t)(NE_MAX / 2) * (NE_MAX / 2 + 1) * sizeof(double));
+  q += a16((size_t)NH * (NH + 1) * sizeof(double));
   double* rowp = (double*)q;
-  q += a16((size_t)(NE_MAX / 2) * sizeof(double));
+  q += a16((size_t)NH * sizeof(double));
   int32_t* piv = (int32_t*)q;
-  int32_t* pinv = piv + NE_MAX / 2;
+  int32_t* pinv = piv + NH;
 
-  int32_t* posg = P.pos + I.pos_off + lw * ne;
-  int32_t* empg = P.empty + I.empty_off + lw * n2;
-  double* hg = P.h + I.h_off + lw * ns;
-  double* thg = P.theta + I.theta_off + lw * M;
-  T* Yg = (T*)P.Y + I.Y_off + lw * ne * ne;
+  int32_t* posg = P.pos + pos_off + lw * ne;
+  int32_t* empg = P.empty + empty_off + lw * n2;
+  double* hg = P.h + h_off + lw * ns;
+  double* thg = P.theta + theta_off + lw * M;
+  T* Yg = (T*)P.Y + Y_off + lw * ne * ne;
+
+  const bool live = lane < ne;
+  const bool lane_up = lane < nh;
+  const int slot = lane_up ? lane : HD + (lane - nh);   // lane's entry of x' and w
+  const T* wl = w + (lane_up ? HD : 0);                 // the half of w the lane's rows read
+  const int rb = lane_up ? nh : 0;                      // first row of the lane's entries
 
   for (int v = lane; v < n2; v += 64) {
     eidx[v] = -1;
@@ -220,35 +266,32 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
   }
   for (int l = lane; l < ns; l += 64) hs[l] = hg[l];
   for (int hh = lane; hh < M; hh += 64) ths[hh] = (T)thg[hh];
-  for (int c = lane; c < 3 * NE_MAX; c += 64) xn[c] = T(0);
-  int posr[KC];
-#pragma unroll
-  for (int k = 0; k < KC; ++k) {
-    const int c = lane + 64 * k;
-    posr[k] = c < ne ? posg[c] : -1;
-  }
+  for (int c = lane; c < 2 * (int)reg_half_len(NE_MAX, sizeof(T)); c += 64) xn[c] = T(0);
+  int posr = live ? posg[lane] : -1;
   wave_sync();
-#pragma unroll
-  for (int k = 0; k < KC; ++k)
-    if (posr[k] >= 0) eidx[posr[k]] = lane + 64 * k;
+  if (posr >= 0) eidx[posr] = lane;
 
-  T y[KC][NE_MAX];
+  Vec z[RC::NG];
+  {
+    const int lc = live ? lane : 0;
 #pragma unroll
-  for (int i = 0; i < NE_MAX; ++i) {
-    const T* row = Yg + (size_t)(i < ne ? i : 0) * ne;   // uniform row pointer
+    for (int g = 0; g < RC::NG; ++g)
 #pragma unroll
-    for (int k = 0; k < KC; ++k) {
-      const int c = lane + 64 * k;
-      y[k][i] = (c < ne && i < ne) ? row[c] : T(0);
-    }
+      for (int j = 0; j < RC::GS; ++j) {
+        const int i = g * RC::GS + j;
+        const int ic = i < nh ? i : 0;   // clamped row: every load in bounds
+        const T v = Yg[(size_t)(rb + ic) * ne + lc];
+        z[g][j] = (live && i < nh) ? v : T(0);
+      }
   }
   wave_sync();
 
-  const double* V = P.V + I.V_off;
-  const double* G = P.G + I.site_off;
-  const T* raT = rbmT_ptr<T>(P) + I.rbm_a_off;                 // a (2Ns)
-  const T* WT = rbmT_ptr<T>(P) + I.rbm_W_off;                  // W^T [2Ns][M]
+  const double* V = P.V + V_off;
+  const T* raT = rbmT_ptr<T>(P) + rbm_a_off;                 // a (2Ns)
+  const T* WT = rbmT_ptr<T>(P) + rbm_W_off;                  // W^T [2Ns][M]
   const uint64_t tb = TRACE ? trace_base[gw] : 0;
+  const int nemp = ns - nh;   // empty sites of either spin
+  const int lv = lane < ns ? lane : 0;
   int64_t acc = 0;
   int singular = 0;
   double last_logpf = 0.0, last_sgn = 0.0;
@@ -261,8 +304,8 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
   uint32_t d0 = 0, d1 = 0, d2 = 0, d3 = 0;
   for (int it = 0; it < n_prop; ++it) {
     const uint64_t n = n0 + (uint64_t)it;
-    const int slot = it & 63;
-    if (slot == 0) {
+    const int rs = it & 63;
+    if (rs == 0) {
       const uint4 d = draw(seed, n + (uint64_t)lane, (uint32_t)gw, 0u);
       d0 = d.x;
       d1 = d.y;
@@ -271,13 +314,12 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
     }
     do {
     uint4 r;
-    r.x = (uint32_t)__builtin_amdgcn_readlane((int)d0, slot);
-    r.y = (uint32_t)__builtin_amdgcn_readlane((int)d1, slot);
-    r.z = (uint32_t)__builtin_amdgcn_readlane((int)d2, slot);
-    r.w = (uint32_t)__builtin_amdgcn_readlane((int)d3, slot);
+    r.x = (uint32_t)__builtin_amdgcn_readlane((int)d0, rs);
+    r.y = (uint32_t)__builtin_amdgcn_readlane((int)d1, rs);
+    r.z = (uint32_t)__builtin_amdgcn_readlane((int)d2, rs);
+    r.w = (uint32_t)__builtin_amdgcn_readlane((int)d3, rs);
     const int a = opaque(sgpr(scaled(r.x, ne)));
-    const int sigma = a >= nup ? 1 : 0;
-    const int nemp = ns - (sigma ? I.ndn : nup);
+    const int sigma = a >= nh ? 1 : 0;
     if (nemp == 0) {
       if (TRACE && lane == 0 && n - tb < (uint64_t)trace_cap) {
         TraceRec rec;
@@ -290,38 +332,26 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
     const int kk_emp = sgpr(scaled(r.y, nemp));
     const int site_new = sgpr(emp[sigma * ns + kk_emp]);
     const int Inew = site_new + sigma * ns;
-    const int ka = a >> 6, la = a & 63;
-    int pa = posr[0];
-#pragma unroll
-    for (int k = 1; k < KC; ++k)
-      if (ka == k) pa = posr[k];
-    const int Iold = sgpr(__builtin_amdgcn_readlane(pa, la));
+    const int Iold = sgpr(__builtin_amdgcn_readlane(posr, a));
     const int site_old = Iold - sigma * ns;
+    const int ai = opaque(a - sigma * nh);
 
-    // correlator terms: scalar loads issued before the vector work
-    const int opp = (1 - sigma) * ns;
-    const double gnew = G[site_new], gold = G[site_old];
-    const double vio = V[(int64_t)site_old * ns + site_new];
+    // V[old][new] and the two rows of V for the Jastrow field update by
+    // vector loads, issued first: they wait on the vector counter, so the
+    // LDS reads below never wait for them
+    int vidx = site_old * ns + site_new;
+    asm volatile("" : "+v"(vidx));
+    const double vio = V[vidx];
+    double vnew = V[(int64_t)site_new * ns + lv], vold = V[(int64_t)site_old * ns + lv];
 
-    T ya[KC], xc[KC];
-    double part = 0.0;
-#pragma unroll
-    for (int k = 0; k < KC; ++k) {
-      ya[k] = pick<T, NE_MAX, 0, NE_MAX>(y[k], a);
-      const int c = lane + 64 * k;
-      const int pb = posr[k];
-      T xb = T(0);
-      if (c < ne && c != a) {
-        if (sigma == 0) {
-          if (pb >= ns) xb = (T)fs[site_new * ldf + (pb - ns)];
-        } else {
-          if (pb < ns) xb = -(T)fs[pb * ldf + site_new];
-        }
-      }
-      xc[k] = xb;
-      if (c < NE_MAX) xn[c] = xb;
-      part += (double)(ya[k] * xb);
-    }
+    // this lane's electron is of the other spin than a: its x'_c may be non-zero
+    const bool oppl = live && (lane_up == (sigma != 0));
+    const T ya = pick_col<T, NH>(z, ai);
+    const int sp = live ? posr - (lane_up ? 0 : ns) : 0;   // site of the lane's electron
+    const double fv = fs[sigma ? sp * ldf + site_new : site_new * ldf + sp];
+    const T xb = oppl ? (T)(sigma ? -fv : fv) : T(0);
+    if (live) xn[slot] = xb;
+    double part = (double)(ya * xb);
     double rbm = 0.0;
     if (RBM && M) {
       for (int hh = lane; hh < M; hh += 64) {
@@ -332,9 +362,10 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
       rbm = wave_total(rbm);
     }
     const double r_pf = -wave_total(part);
-    double logc = gnew * (eidx[site_new + opp] >= 0 ? 1.0 : 0.0) -
-                  gold * (eidx[site_old + opp] >= 0 ? 1.0 : 0.0) + hs[site_new] - hs[site_old] -
-                  vio;
+    const int opp = (1 - sigma) * ns;
+    double logc = gs[site_new] * (eidx[site_new + opp] >= 0 ? 1.0 : 0.0) -
+                  gs[site_old] * (eidx[site_old + opp] >= 0 ? 1.0 : 0.0) + hs[site_new] -
+                  hs[site_old] - vio;
     if (RBM && M) logc += 2.0 * ((double)raT[Inew] - (double)raT[Iold]) + rbm;
     const double Rt = r_pf * exp(logc);
     const double u = uniform53(r.z, r.w);
@@ -345,49 +376,50 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
       rec.ratio = Rt;
       trace[(int64_t)gw * trace_cap + (int64_t)(n - tb)] = rec;
     }
+    // the V rows are taken here, after the LDS reads above: their loads stay
+    // at the top of the proposal and are waited for only now
+    asm volatile("" : "+v"(vnew), "+v"(vold));
     if (!accept) break;
     ++acc;
     wave_sync();   // x' of every lane visible
 
-    // q_c = -sum_j Y[j][c] x'_j + delta_{c,a};  p_c = -Y[a][c]
-    T pc[KC], qc[KC];
+    // q_c = -sum_j Y[j][c] x'_j + delta_{c,a} on a's spin (j over the other
+    // spin, the half of x' at hq); p_c = -Y[a][c] on the other spin
+    const bool same = live && !oppl;
+    const int hq = sigma ? 0 : HD;
+    T sc[4] = {T(0), T(0), T(0), T(0)};   // four independent FMA chains
 #pragma unroll
-    for (int k = 0; k < KC; ++k) {
-      T s = T(0);
+    for (int g = 0; g < RC::NG; ++g)
 #pragma unroll
-      for (int j0 = 0; j0 < NE_MAX; j0 += kChunk) {
+      for (int j0 = 0; j0 < RC::GS; j0 += kChunk) {
 #pragma unroll
-        for (int j = j0; j < j0 + kChunk && j < NE_MAX; ++j) s += y[k][j] * xn[j];
+        for (int j = j0; j < j0 + kChunk && j < RC::GS; ++j)
+          sc[j & 3] += z[g][j] * xn[hq + g * RC::GS + j];
         asm volatile("" ::: "memory");   // bound the number of broadcast loads in flight
       }
-      const int c = lane + 64 * k;
-      qc[k] = (c == a ? T(1) : T(0)) - s;
-      pc[k] = -ya[k];
-      if (c < NE_MAX) {
-        pv[c] = pc[k];
-        qv[c] = qc[k];
-      }
-    }
+    const T sq = (sc[0] + sc[1]) + (sc[2] + sc[3]);
+    const T qc = same ? (lane == a ? T(1) : T(0)) - sq : T(0);
+    const T pc = oppl ? -ya : T(0);
+    if (live) w[slot] = same ? qc : pc;
     wave_sync();
     const T ir = T(1.0 / r_pf);
+    const T coef = same ? qc * ir : -(pc * ir);
 #pragma unroll
-    for (int i0 = 0; i0 < NE_MAX; i0 += kChunk) {
+    for (int g = 0; g < RC::NG; ++g)
 #pragma unroll
-      for (int k = 0; k < KC; ++k) {
-        const T qs = qc[k] * ir, ps = pc[k] * ir;
+      for (int j0 = 0; j0 < RC::GS; j0 += kChunk) {
 #pragma unroll
-        for (int i = i0; i < i0 + kChunk && i < NE_MAX; ++i) y[k][i] += pv[i] * qs - qv[i] * ps;
+        for (int j = j0; j < j0 + kChunk && j < RC::GS; ++j)
+          z[g][j] += wl[g * RC::GS + j] * coef;
+        asm volatile("" ::: "memory");
       }
-      asm volatile("" ::: "memory");
-    }
-    for (int l = lane; l < ns; l += 64)
+    if (lane < ns) hs[lane] += vnew - vold;
+    for (int l = lane + 64; l < ns; l += 64)
       hs[l] += V[(int64_t)site_new * ns + l] - V[(int64_t)site_old * ns + l];
     if (RBM)
       for (int hh = lane; hh < M; hh += 64)
         ths[hh] += T(2) * (WT[(int64_t)Inew * M + hh] - WT[(int64_t)Iold * M + hh]);
-#pragma unroll
-    for (int k = 0; k < KC; ++k)
-      if (ka == k && lane == la) posr[k] = Inew;
+    if (lane == a) posr = Inew;
     if (lane == 0) {
       eidx[Iold] = -1;
       eidx[Inew] = a;
@@ -401,9 +433,8 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
     if (R > 0 && --to_refresh == 0) to_refresh = R;
     if (kref && R > 0 && to_refresh == R) {
       double lp, sg;
-      static_assert(KC == 1, "register tiers hold one column per lane");
-      singular = reg_refresh_ap<NE_MAX, T>(y, posr[0], fs, ldf, ns, ne, lane, posl, tab, rowp,
-                                           piv, pinv, lp, sg);
+      singular = reg_refresh_ap<NE_MAX, T>(z, posr, fs, ldf, ns, ne, lane, posl, tab, rowp, piv,
+                                           pinv, lp, sg);
       last_logpf = lp;
       last_sgn = sg;
       refreshed = true;
@@ -419,9 +450,9 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
       }
       if (RBM)
       for (int hh = lane; hh < M; hh += 64) {
-        double th = rbT64[I.rbm_b_off + hh];
+        double th = rbT64[rbm_b_off + hh];
         for (int v = 0; v < n2; ++v)
-          th += rbT64[I.rbm_W_off + (int64_t)v * M + hh] * (eidx[v] >= 0 ? 1.0 : -1.0);
+          th += rbT64[rbm_W_off + (int64_t)v * M + hh] * (eidx[v] >= 0 ? 1.0 : -1.0);
         ths[hh] = (T)th;
       }
       wave_sync();
@@ -430,23 +461,15 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
 #endif
   }
 
-  // write the walker back
+  // write the walker back (the same-spin blocks of Y stay zero in memory)
+  if (live) posg[lane] = posr;
 #pragma unroll
-  for (int k = 0; k < KC; ++k) {
-    const int c = lane + 64 * k;
-    if (c < ne) posg[c] = posr[k];
-  }
+  for (int g = 0; g < RC::NG; ++g)
 #pragma unroll
-  for (int i = 0; i < NE_MAX; ++i) {
-    if (i < ne) {
-      T* row = Yg + (size_t)i * ne;
-#pragma unroll
-      for (int k = 0; k < KC; ++k) {
-        const int c = lane + 64 * k;
-        if (c < ne) row[c] = y[k][i];
-      }
+    for (int j = 0; j < RC::GS; ++j) {
+      const int i = g * RC::GS + j;
+      if (live && i < nh) Yg[(size_t)(rb + i) * ne + lane] = z[g][j];
     }
-  }
   for (int v = lane; v < n2; v += 64) empg[v] = emp[v];
   for (int l = lane; l < ns; l += 64) hg[l] = hs[l];
   for (int hh = lane; hh < M; hh += 64) thg[hh] = (double)ths[hh];
