@@ -18,8 +18,8 @@
 //                   up electron moves and c is down, -f(site_c, site') when a
 //                   down electron moves and c is up, else 0 (X_IJ = F_IJ - F_JI)
 //   r_Pf            -sum_c Y[a][c] x'_c   (DPP wave reduction)
-//   correlators     Gutzwiller factors and Jastrow field from LDS, V[old][new]
-//                   by a vector load, RBM angles in LDS
+//   correlators     Gutzwiller factors, Jastrow field and v, RBM angles, all
+//                   in LDS
 // On acceptance, with p = -Y[a,:] (non-zero on the other spin) and
 // q = -Y^T x' + e_a (non-zero on a's spin) written to the two halves of an
 // LDS vector w,
@@ -40,11 +40,13 @@ using namespace wave;
 
 __host__ __device__ inline size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
 
-// LDS: [f table ns x (ns+1) | Gutzwiller g per site | WPB x per-walker
-// block], all tables in double; the single-precision sweep converts the
-// gathered amplitudes, which equals reading a single-precision copy.
+// LDS: [f table ns x (ns+1) | Gutzwiller g per site | Jastrow v ns x ns |
+// WPB x per-walker block], all tables in double (the single-precision sweep
+// converts the gathered amplitudes, which equals reading a single-precision
+// copy), so the proposal loop makes no global load.
 __host__ __device__ inline size_t reg_table_bytes(int ns) {
-  return a16((size_t)ns * (ns + 1) * sizeof(double)) + a16((size_t)ns * sizeof(double));
+  return a16((size_t)ns * (ns + 1) * sizeof(double)) + a16((size_t)ns * sizeof(double)) +
+         a16((size_t)ns * ns * sizeof(double));
 }
 __host__ __device__ inline size_t reg_refresh_bytes(int ne_max) {
   const size_t nh = (size_t)ne_max / 2;
@@ -200,14 +202,34 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
                 V_off = I.V_off, site_off = I.site_off, rbm_a_off = I.rbm_a_off,
                 rbm_b_off = I.rbm_b_off, rbm_W_off = I.rbm_W_off;
 
-  // shared pair-amplitude table f[i][j] = A[i][Ns + j] and Gutzwiller g
+  // shared tables: pair amplitude f[i][j] = A[i][Ns + j], Gutzwiller g,
+  // Jastrow v (copies with eight loads in flight per thread)
   double* fs = (double*)smem;
   double* gs = (double*)(smem + a16((size_t)ns * ldf * sizeof(double)));
+  double* vs = gs + a16((size_t)ns * sizeof(double)) / sizeof(double);
   {
     const double* A = P.A64 + A_off;
-    for (int e = threadIdx.x; e < ns * ns; e += 64 * WPB) {
-      const int i = e / ns, j = e - (e / ns) * ns;
-      fs[i * ldf + j] = A[(int64_t)i * n2 + ns + j];
+    const double* Vg = P.V + V_off;
+    constexpr int U = 8;
+    for (int e0 = threadIdx.x; e0 < ns * ns; e0 += 64 * WPB * U) {
+      double fa[U], va[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * 64 * WPB;
+        const int ec = e < ns * ns ? e : 0;
+        const int i = ec / ns, j = ec - (ec / ns) * ns;
+        fa[u] = A[(int64_t)i * n2 + ns + j];
+        va[u] = Vg[ec];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * 64 * WPB;
+        if (e < ns * ns) {
+          const int i = e / ns, j = e - (e / ns) * ns;
+          fs[i * ldf + j] = fa[u];
+          vs[e] = va[u];
+        }
+      }
     }
     for (int e = threadIdx.x; e < ns; e += 64 * WPB) gs[e] = P.G[site_off + e];
   }
@@ -286,12 +308,10 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
   }
   wave_sync();
 
-  const double* V = P.V + V_off;
   const T* raT = rbmT_ptr<T>(P) + rbm_a_off;                 // a (2Ns)
   const T* WT = rbmT_ptr<T>(P) + rbm_W_off;                  // W^T [2Ns][M]
   const uint64_t tb = TRACE ? trace_base[gw] : 0;
   const int nemp = ns - nh;   // empty sites of either spin
-  const int lv = lane < ns ? lane : 0;
   int64_t acc = 0;
   int singular = 0;
   double last_logpf = 0.0, last_sgn = 0.0;
@@ -336,14 +356,6 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
     const int site_old = Iold - sigma * ns;
     const int ai = opaque(a - sigma * nh);
 
-    // V[old][new] and the two rows of V for the Jastrow field update by
-    // vector loads, issued first: they wait on the vector counter, so the
-    // LDS reads below never wait for them
-    int vidx = site_old * ns + site_new;
-    asm volatile("" : "+v"(vidx));
-    const double vio = V[vidx];
-    double vnew = V[(int64_t)site_new * ns + lv], vold = V[(int64_t)site_old * ns + lv];
-
     // this lane's electron is of the other spin than a: its x'_c may be non-zero
     const bool oppl = live && (lane_up == (sigma != 0));
     const T ya = pick_col<T, NH>(z, ai);
@@ -365,7 +377,7 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
     const int opp = (1 - sigma) * ns;
     double logc = gs[site_new] * (eidx[site_new + opp] >= 0 ? 1.0 : 0.0) -
                   gs[site_old] * (eidx[site_old + opp] >= 0 ? 1.0 : 0.0) + hs[site_new] -
-                  hs[site_old] - vio;
+                  hs[site_old] - vs[site_old * ns + site_new];
     if (RBM && M) logc += 2.0 * ((double)raT[Inew] - (double)raT[Iold]) + rbm;
     const double Rt = r_pf * exp(logc);
     const double u = uniform53(r.z, r.w);
@@ -376,9 +388,6 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
       rec.ratio = Rt;
       trace[(int64_t)gw * trace_cap + (int64_t)(n - tb)] = rec;
     }
-    // the V rows are taken here, after the LDS reads above: their loads stay
-    // at the top of the proposal and are waited for only now
-    asm volatile("" : "+v"(vnew), "+v"(vold));
     if (!accept) break;
     ++acc;
     wave_sync();   // x' of every lane visible
@@ -413,9 +422,7 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
           z[g][j] += wl[g * RC::GS + j] * coef;
         asm volatile("" ::: "memory");
       }
-    if (lane < ns) hs[lane] += vnew - vold;
-    for (int l = lane + 64; l < ns; l += 64)
-      hs[l] += V[(int64_t)site_new * ns + l] - V[(int64_t)site_old * ns + l];
+    for (int l = lane; l < ns; l += 64) hs[l] += vs[site_new * ns + l] - vs[site_old * ns + l];
     if (RBM)
       for (int hh = lane; hh < M; hh += 64)
         ths[hh] += T(2) * (WT[(int64_t)Inew * M + hh] - WT[(int64_t)Iold * M + hh]);
@@ -438,13 +445,13 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
       last_logpf = lp;
       last_sgn = sg;
       refreshed = true;
-      // Jastrow field and RBM angles from scratch (V is symmetric: row mm of
-      // V read across the lanes is coalesced)
+      // Jastrow field and RBM angles from scratch (v is symmetric: row mm
+      // of v read across the lanes)
       for (int l = lane; l < ns; l += 64) {
         double sum = 0.0;
 #pragma unroll 8
         for (int mm = 0; mm < ns; ++mm)
-          sum += V[(int64_t)mm * ns + l] *
+          sum += vs[mm * ns + l] *
                  (double)((eidx[mm] >= 0 ? 1 : 0) + (eidx[mm + ns] >= 0 ? 1 : 0) - 1);
         hs[l] = sum;
       }
