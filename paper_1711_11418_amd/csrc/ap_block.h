@@ -3,7 +3,8 @@
 // with the up electrons first, X = [[0, M], [-M^T, 0]] with
 // M[a][b] = f(site of up electron a, site of down electron b), so
 // Pf(X) = (-1)^{n(n-1)/2} det M and X^-1 = [[0, -M^-T], [M^-1, 0]].
-// Step k takes the unused row p of largest |T[r][k]|, pi = T[p][k]:
+// Step k takes the unused row p of largest |T[r][k]| (to 2^-46 relative, the
+// lowest such row), pi = T[p][k]:
 //     T[p][k] <- 1/pi,          T[p][c] <- -T[p][c]/pi,
 //     T[r][k] <- T[r][k]/pi,    T[r][c] <- T[r][c] - T[r][k] T[p][c]/pi,
 // and after n steps M^-1[a][p_b] = T[p_a][b] (p_k the pivot row of column k),
@@ -49,10 +50,11 @@ __device__ __forceinline__ void ap_steps(ApState& st, double (&m)[NS], double* r
   if constexpr (K < NS) {
     if (K < nh && !st.singular) {
       const bool free_row = live && !((st.used >> lane) & 1ull);
-      const double v = free_row ? fabs(m[K]) : -1.0;
-      const double vmax = wave::wave_max(v);
-      const int p = wave::wave_min_i(v == vmax ? lane : (1 << 30));
-      if (!(vmax > tol) || p >= nh) {
+      // one reduction for the largest |T[r][K]| over the free rows and its row
+      const uint64_t key = wave::wave_max_u64(wave::pivot_key(m[K], lane, free_row));
+      const double vmax = wave::pivot_mag(key);
+      const int p = wave::pivot_lane(key);
+      if (key == 0 || !(vmax > tol) || p >= nh) {
         st.singular = true;
       } else {
         const int xlo = __builtin_amdgcn_readlane(__double2loint(m[K]), p);

@@ -173,32 +173,30 @@ struct ApStateBlk {
 
 template <int K, int NS, int NW>
 __device__ __forceinline__ void ap_steps_blk(ApStateBlk& st, double (&m)[NS], double* rowp,
-                                             int32_t* piv, double* redv, int32_t* redi,
+                                             int32_t* piv, double* redv,
                                              int row, bool live, int nh, double tol) {
   if constexpr (K < NS) {
     if (K < nh && !st.singular) {
       const int lane = row & 63, wv = row >> 6;
       const bool free_row = live && !((st.used[row >> 6] >> (row & 63)) & 1ull);
-      const double v = free_row ? fabs(m[K]) : -1.0;
-      const double vw = wave_max(v);
-      const int pw = wave_min_i(v == vw ? row : (1 << 30));
-      if (lane == 0) {
-        redv[wv] = vw;
-        redi[wv] = pw;
-      }
+      // per wavefront one reduction of the pivot key (largest |T[r][K]|, then
+      // lowest row); the wavefronts' keys go through LDS as raw bits
+      const uint64_t kw = wave_max_u64(pivot_key(m[K], lane, free_row));
+      if (lane == 0) redv[wv] = __longlong_as_double((long long)kw);
       __syncthreads();
-      double vmax = -1.0;
-      int p = 1 << 30;
+      uint64_t kbest = 0;
+      int wbest = 0;
 #pragma unroll
       for (int w = 0; w < NW; ++w) {
-        const double a = redv[w];
-        const int b = redi[w];
-        if (a > vmax || (a == vmax && b < p)) {
-          vmax = a;
-          p = b;
+        const uint64_t k = (uint64_t)__double_as_longlong(redv[w]);
+        if (k > kbest) {
+          kbest = k;
+          wbest = w;
         }
       }
-      if (!(vmax > tol) || p >= nh) {
+      const double vmax = pivot_mag(kbest);
+      const int p = wbest * 64 + pivot_lane(kbest);
+      if (kbest == 0 || !(vmax > tol) || p >= nh) {
         st.singular = true;
       } else {
         const bool me = row == p;
@@ -227,7 +225,7 @@ __device__ __forceinline__ void ap_steps_blk(ApStateBlk& st, double (&m)[NS], do
         __syncthreads();   // rowp and the reduction slots are reused next step
       }
     }
-    ap_steps_blk<K + 1, NS, NW>(st, m, rowp, piv, redv, redi, row, live, nh, tol);
+    ap_steps_blk<K + 1, NS, NW>(st, m, rowp, piv, redv, row, live, nh, tol);
   } else {
     st.logabs = absdet_log(st.mant, st.ex);
   }
@@ -247,8 +245,7 @@ __global__ __launch_bounds__(64 * NW) void k_refresh_ap_blk(Pools P,
   const int row = threadIdx.x, lane = row & 63;
   double* rowp = (double*)smem;                 // NS
   double* redv = rowp + NS;                     // NW
-  int32_t* redi = (int32_t*)(redv + NW);        // NW
-  int32_t* pos = redi + NW;                     // 2 NS
+  int32_t* pos = (int32_t*)(redv + NW);         // 2 NS
   int32_t* piv = pos + 2 * NS;                  // NS
   int32_t* occ = piv + NS;                      // 2 N_s
 
@@ -279,7 +276,7 @@ __global__ __launch_bounds__(64 * NW) void k_refresh_ap_blk(Pools P,
   __syncthreads();
 
   ApStateBlk st;
-  ap_steps_blk<0, NS, NW>(st, m, rowp, piv, redv, redi, row, live, nh, sing_tol * amax);
+  ap_steps_blk<0, NS, NW>(st, m, rowp, piv, redv, row, live, nh, sing_tol * amax);
   __syncthreads();
   if (st.singular) {
     if (row == 0) {
@@ -344,7 +341,7 @@ __global__ __launch_bounds__(64 * NW) void k_refresh_ap_blk(Pools P,
 
 __host__ __device__ inline size_t ap_blk_bytes(int NS, int NW, int max_sites) {
   return (size_t)(NS + NW) * sizeof(double) +
-         (size_t)(NW + 2 * NS + NS + 2 * max_sites) * sizeof(int32_t);
+         (size_t)(2 * NS + NS + 2 * max_sites) * sizeof(int32_t);
 }
 }  // namespace
 

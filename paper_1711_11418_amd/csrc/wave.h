@@ -69,6 +69,40 @@ __device__ __forceinline__ int wave_min_i(int v) {
 }
 
 
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ uint64_t dpp_keep_u64(uint64_t v) {
+  const int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
+  const int nlo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xF, false);
+  const int nhi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xF, false);
+  return ((uint64_t)(uint32_t)nhi << 32) | (uint64_t)(uint32_t)nlo;
+}
+__device__ __forceinline__ uint64_t max_u64(uint64_t a, uint64_t b) { return a > b ? a : b; }
+// Unsigned 64-bit maximum over the 64 lanes (same DPP pattern as wave_max).
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+  v = max_u64(v, dpp_keep_u64<0xB1, 0xF>(v));
+  v = max_u64(v, dpp_keep_u64<0x4E, 0xF>(v));
+  v = max_u64(v, dpp_keep_u64<0x141, 0xF>(v));
+  v = max_u64(v, dpp_keep_u64<0x140, 0xF>(v));
+  v = max_u64(v, dpp_keep_u64<0x142, 0xA>(v));
+  v = max_u64(v, dpp_keep_u64<0x143, 0xC>(v));
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Partial-pivot search key of a candidate: the IEEE bits of |x| (ordered like
+// the values for x >= 0) with the low six mantissa bits replaced by 63 - lane,
+// so one maximum gives the largest magnitude (to 2^-46 relative) and, among
+// those, the lowest lane.  Rows that may not be chosen take key 0.
+__device__ __forceinline__ uint64_t pivot_key(double x, int lane, bool free_row) {
+  const uint64_t b = (uint64_t)__double_as_longlong(fabs(x));
+  return free_row ? ((b & ~(uint64_t)63) | (uint64_t)(63 - lane)) : 0;
+}
+__device__ __forceinline__ int pivot_lane(uint64_t key) { return 63 - (int)(key & 63); }
+__device__ __forceinline__ double pivot_mag(uint64_t key) {
+  return __longlong_as_double((long long)(key & ~(uint64_t)63));
+}
+
 __device__ __forceinline__ int sgpr(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 }  // namespace wave
