@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 BF16_PEAK_TFLOPS = 2500.0
 TRAFFIC_SUMMARY = "sweep_reg_fp64_c2_sq8_traffic.txt"
-TRAFFIC_SOURCES = ("k_sweep_reg.hip", "common.h")
+TRAFFIC_SOURCES = ("k_sweep_reg.hip", "common.h", "ap_block.h", "wave.h")   # the sweep kernel and its headers
 METRIC = "walker hop-updates/s + SR S-build TFLOP/s, batched/mixed vs plain FP64"
 
 

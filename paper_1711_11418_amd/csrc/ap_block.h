@@ -3,12 +3,19 @@
 // with the up electrons first, X = [[0, M], [-M^T, 0]] with
 // M[a][b] = f(site of up electron a, site of down electron b), so
 // Pf(X) = (-1)^{n(n-1)/2} det M and X^-1 = [[0, -M^-T], [M^-1, 0]].
-// Step k takes the unused row p of largest |T[r][k]| (to 2^-46 relative, the
-// lowest such row), pi = T[p][k]:
+// Step k takes the unused row p of largest |T[r][k]| (to 2^-14 relative, the
+// lowest such row: threshold partial pivoting), pi = T[p][k]:
 //     T[p][k] <- 1/pi,          T[p][c] <- -T[p][c]/pi,
 //     T[r][k] <- T[r][k]/pi,    T[r][c] <- T[r][c] - T[r][k] T[p][c]/pi,
 // and after n steps M^-1[a][p_b] = T[p_a][b] (p_k the pivot row of column k),
 // det M = sgn(p) prod_k pi_k.
+// The pivot row's scaling by -1/pi is deferred: each lane keeps its row as
+// T[r][.] = s_r S[r][.] with s_r = 1 until row r is chosen, then s_r = -1/pi
+// and S[r][k] = -1 (its other entries unchanged).  A row that has not been
+// chosen has T = S, so pi and the multipliers are read from S directly, and
+// with f_r = S[r][k]/pi every other row takes
+//     S[r][k] <- f_r,           S[r][c] <- S[r][c] - f_r S[p][c]
+// (one fused multiply-add per entry); T = s S is formed after the last step.
 #pragma once
 
 #include <float.h>
@@ -30,8 +37,13 @@ __device__ __forceinline__ double absdet_log(double mant, int ex) {
   return log(mant) + (double)ex * 0.69314718055994530942;
 }
 
+// LDS-typed double, so that an address held in one VGPR (the asm barriers
+// below) still addresses LDS with immediate offsets
+typedef __attribute__((address_space(3))) double lds_double;
+
 struct ApState {
   double logabs = 0.0, sgn = 1.0, minpiv = DBL_MAX;
+  double rs = 1.0;     // this lane's deferred row scale s_r
   double mant = 1.0;   // |det| = mant 2^ex over the steps taken
   int ex = 0;
   uint64_t used = 0;   // rows pivoted so far
@@ -50,10 +62,11 @@ __device__ __forceinline__ void ap_steps(ApState& st, double (&m)[NS], double* r
   if constexpr (K < NS) {
     if (K < nh && !st.singular) {
       const bool free_row = live && !((st.used >> lane) & 1ull);
-      // one reduction for the largest |T[r][K]| over the free rows and its row
-      const uint64_t key = wave::wave_max_u64(wave::pivot_key(m[K], lane, free_row));
-      const double vmax = wave::pivot_mag(key);
-      const int p = wave::pivot_lane(key);
+      // one reduction for the (threshold-)largest |T[r][K]| over the free rows
+      // and its row
+      const uint32_t key = wave::wave_max_u32(wave::pivot_key32(m[K], lane, free_row));
+      const double vmax = wave::pivot_mag32(key);
+      const int p = wave::pivot_lane32(key);
       if (key == 0 || !(vmax > tol) || p >= nh) {
         st.singular = true;
       } else {
@@ -67,24 +80,44 @@ __device__ __forceinline__ void ap_steps(ApState& st, double (&m)[NS], double* r
         st.used |= 1ull << p;
         const bool me = lane == p;
         if (lane == 0) piv[K] = p;
-        if (me)
+        if (me) {
+          lds_double* wp = (lds_double*)rowp;
+          asm volatile("" : "+v"(wp));
 #pragma unroll
-          for (int c = 0; c < NS; ++c) rowp[c] = m[c];
-        wave::wave_sync();
+          for (int c = 0; c < NS; ++c) wp[c] = m[c];
+        }
+        // one wavefront's LDS operations complete in issue order, so the
+        // reads below see the row without waiting for the writes: only the
+        // compiler is kept from moving them
+        asm volatile("" ::: "memory");
         const double ip = 1.0 / pv;
-        const double t = m[K];
-        const double g = me ? -ip : 1.0;
-        const double f = me ? 0.0 : t * ip;
+        const double f = me ? 0.0 : m[K] * ip;
+        // the pivot row from one VGPR base with immediate offsets, CH values
+        // in flight per chunk (fewer for long rows, whose registers are scarce)
+        constexpr int CH = NS > 32 ? 4 : 8;
+        const lds_double* rp = (const lds_double*)rowp;
+        asm volatile("" : "+v"(rp));
 #pragma unroll
-        for (int c = 0; c < NS; ++c)
-          if (c != K) m[c] = fma(-f, rowp[c], g * m[c]);
-        m[K] = me ? ip : t * ip;
-        wave::wave_sync();
+        for (int c0 = 0; c0 < NS; c0 += CH) {
+          double r[CH];
+#pragma unroll
+          for (int u = 0; u < CH; ++u) r[u] = c0 + u < NS ? rp[c0 + u] : 0.0;
+#pragma unroll
+          for (int u = 0; u < CH; ++u) {
+            const int c = c0 + u;
+            if (c < NS && c != K) m[c] = fma(-f, r[u], m[c]);
+          }
+        }
+        m[K] = me ? -1.0 : f;
+        if (me) st.rs = -ip;
+        asm volatile("" ::: "memory");   // next step's row write after these reads
       }
     }
     ap_steps<K + 1, NS>(st, m, rowp, piv, lane, live, nh, tol);
   } else {
     st.logabs = absdet_log(st.mant, st.ex);
+#pragma unroll
+    for (int c = 0; c < NS; ++c) m[c] *= st.rs;   // T = s S
   }
 }
 

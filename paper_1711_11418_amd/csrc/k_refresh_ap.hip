@@ -44,7 +44,7 @@ __host__ __device__ inline size_t ap_minv_bytes(int wld) {
 }
 
 template <typename T, int NS>
-__global__ __launch_bounds__(64 * kApWpb) void k_refresh_ap(Pools P,
+__global__ __launch_bounds__(64 * kApWpb, 2) void k_refresh_ap(Pools P,
                                                              const int32_t* __restrict__ wlist,
                                                              int n, int max_sites, int wld,
                                                              double sing_tol,

@@ -59,7 +59,7 @@ __host__ __device__ inline size_t reg_half_len(int ne_max, size_t ts) {
 }
 __host__ __device__ inline size_t reg_walker_bytes(int ne_max, int ns, int M, size_t ts) {
   return a16(2 * reg_half_len(ne_max, ts) * ts) + a16((size_t)ns * sizeof(double)) +
-         a16((size_t)M * ts) + a16((size_t)(4 * ns + ne_max) * sizeof(int32_t)) +
+         a16((size_t)M * ts) + a16((size_t)(4 * ns) * sizeof(int32_t)) +
          reg_refresh_bytes(ne_max);
 }
 
@@ -126,23 +126,23 @@ constexpr int kChunk = 8;   // rows per group of broadcast loads in the update
 template <int NE_MAX, typename T, typename ZArr>
 __device__ __forceinline__ int reg_refresh_ap(
     ZArr& z, int posr0,
-    const double* __restrict__ fs, int ldf, int ns, int ne, int lane, int32_t* posl,
-    double* tab, double* rowp, int32_t* piv, int32_t* pinv, double& logabs, double& sgn) {
+    const double* __restrict__ fs, int ldf, int ns, int ne, int lane, double* tab,
+    double* rowp, int32_t* piv, int32_t* pinv, double& logabs, double& sgn) {
   constexpr int NH = NE_MAX / 2;
   constexpr int LDT = NH + 1;
   using RC = RegCol<T, NH>;
   int nh = ne / 2;
   asm volatile("" : "+s"(nh));   // keep the per-index compares inside this call
-  if (lane < NE_MAX) posl[lane] = posr0;
-  wave_sync();
   const bool live = lane < nh;
   const int su = live ? posr0 : 0;   // site of up electron `lane`
   double m[NH];
 #pragma unroll
   for (int b = 0; b < NH; ++b) {
+    // site of down electron b, read from its lane (no LDS round trip)
+    const int sb = __builtin_amdgcn_readlane(posr0, b < nh ? nh + b : 0) - ns;
     const bool in = live && b < nh;
-    const int sd = in ? posl[nh + b] - ns : 0;
-    m[b] = in ? fs[su * ldf + sd] : 0.0;
+    const double x = fs[su * ldf + (in ? sb : 0)];
+    m[b] = in ? x : 0.0;
   }
   ApState st;
   ap_steps<0, NH>(st, m, rowp, piv, lane, live, nh, 0.0);
@@ -158,18 +158,24 @@ __device__ __forceinline__ int reg_refresh_ap(
   }
   wave_sync();
   const bool up = lane < nh, dn = lane >= nh && lane < ne;
-  // column of T for an up lane (pinv[c]), row of T for a down lane (p_{a'})
-  const int own = up ? pinv[lane] : (dn ? piv[lane - nh] : 0);
+  // the pivot rows per column and their inverse, one entry per lane, then
+  // broadcast by readlane
+  const int mpiv = lane < nh ? piv[lane] : 0;
+  const int mpinv = lane < nh ? pinv[lane] : 0;
+  // column of T for an up lane (pinv[c]), row of T for a down lane (p_{a'},
+  // fetched from lane a' by a full-wave permute)
+  const int pdn = __builtin_amdgcn_ds_bpermute((dn ? lane - nh : 0) << 2, mpiv);
+  const int own = up ? mpinv : (dn ? pdn : 0);
 #pragma unroll
   for (int g = 0; g < RC::NG; ++g)
 #pragma unroll
     for (int j = 0; j < RC::GS; ++j) {
       const int i = g * RC::GS + j;
-      double v = 0.0;
-      if (i < nh) {
-        if (up) v = tab[piv[i] * LDT + own];
-        else if (dn) v = -tab[own * LDT + pinv[i]];
-      }
+      const int pi = __builtin_amdgcn_readlane(mpiv, i < NH ? i : 0);
+      const int qi = __builtin_amdgcn_readlane(mpinv, i < NH ? i : 0);
+      const double vu = tab[pi * LDT + own];
+      const double vd = tab[own * LDT + qi];
+      const double v = i < nh ? (up ? vu : (dn ? -vd : 0.0)) : 0.0;
       z[g][j] = (T)v;
     }
   wave_sync();
@@ -260,8 +266,7 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
   q += a16((size_t)M * sizeof(T));
   int32_t* eidx = (int32_t*)q;      // 2ns
   int32_t* emp = eidx + n2;         // 2ns
-  int32_t* posl = emp + n2;         // NE_MAX: configuration broadcast for the refresh
-  q += a16((size_t)(4 * ns + NE_MAX) * sizeof(int32_t));
+  q += a16((size_t)(4 * ns) * sizeof(int32_t));
   // refresh scratch: tableau, pivot row, pivot rows per column and inverse
   double* tab = (double*)q;
   q += a16((size_t)NH * (NH + 1) * sizeof(double));
@@ -440,8 +445,8 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
     if (R > 0 && --to_refresh == 0) to_refresh = R;
     if (kref && R > 0 && to_refresh == R) {
       double lp, sg;
-      singular = reg_refresh_ap<NE_MAX, T>(z, posr, fs, ldf, ns, ne, lane, posl, tab, rowp, piv,
-                                           pinv, lp, sg);
+      singular = reg_refresh_ap<NE_MAX, T>(z, posr, fs, ldf, ns, ne, lane, tab, rowp, piv, pinv,
+                                           lp, sg);
       last_logpf = lp;
       last_sgn = sg;
       refreshed = true;

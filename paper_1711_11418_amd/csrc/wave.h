@@ -103,6 +103,28 @@ __device__ __forceinline__ double pivot_mag(uint64_t key) {
   return __longlong_as_double((long long)(key & ~(uint64_t)63));
 }
 
+// The same key from the high word of |x| alone (sign, exponent and 14
+// mantissa bits, then 63 - lane): the pivot is within 2^-14 relative of the
+// largest magnitude (threshold partial pivoting), and the maximum is six
+// single-instruction DPP steps.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  v = max(v, (uint32_t)dpp_keep_i<0xB1, 0xF>((int)v));
+  v = max(v, (uint32_t)dpp_keep_i<0x4E, 0xF>((int)v));
+  v = max(v, (uint32_t)dpp_keep_i<0x141, 0xF>((int)v));
+  v = max(v, (uint32_t)dpp_keep_i<0x140, 0xF>((int)v));
+  v = max(v, (uint32_t)dpp_keep_i<0x142, 0xA>((int)v));
+  v = max(v, (uint32_t)dpp_keep_i<0x143, 0xC>((int)v));
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+__device__ __forceinline__ uint32_t pivot_key32(double x, int lane, bool free_row) {
+  const uint32_t hi = (uint32_t)__double2hiint(fabs(x));
+  return free_row ? ((hi & ~63u) | (uint32_t)(63 - lane)) : 0u;
+}
+__device__ __forceinline__ int pivot_lane32(uint32_t key) { return 63 - (int)(key & 63u); }
+__device__ __forceinline__ double pivot_mag32(uint32_t key) {
+  return __hiloint2double((int)(key & ~63u), 0);
+}
+
 __device__ __forceinline__ int sgpr(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 }  // namespace wave
