@@ -73,7 +73,7 @@ struct RegCol {
 };
 
 // z[i] for a uniform runtime i < NH: one indexed register move per group
-// (no branch tree, no scratch), then a select between the groups.
+// (the array stays in registers), then a select between the groups.
 template <typename T, int NH, typename ZArr>
 __device__ __forceinline__ T pick_col(const ZArr& z, int i) {
   using RC = RegCol<T, NH>;

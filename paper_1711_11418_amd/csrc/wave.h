@@ -58,15 +58,6 @@ template <int CTRL, int ROWMASK>
 __device__ __forceinline__ int dpp_keep_i(int v) {
   return __builtin_amdgcn_update_dpp(v, v, CTRL, ROWMASK, 0xF, false);
 }
-__device__ __forceinline__ int wave_min_i(int v) {
-  v = min(v, dpp_keep_i<0xB1, 0xF>(v));
-  v = min(v, dpp_keep_i<0x4E, 0xF>(v));
-  v = min(v, dpp_keep_i<0x141, 0xF>(v));
-  v = min(v, dpp_keep_i<0x140, 0xF>(v));
-  v = min(v, dpp_keep_i<0x142, 0xA>(v));
-  v = min(v, dpp_keep_i<0x143, 0xC>(v));
-  return __builtin_amdgcn_readlane(v, 63);
-}
 
 
 template <int CTRL, int ROWMASK>
