@@ -84,7 +84,7 @@ def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", 
         cg_iters = []
 
         def sr():
-            E, V = ctx.build_sr(slots, with_S=build_s)
+            E, Er, V = ctx.build_sr(slots, with_S=build_s)
             it = ctx.sr_update(dtau=wl["dtau"], eps_rel=wl["eps_rel"], eps_abs=wl["eps_abs"],
                                solver=solver, cg_tol=cg_tol, cg_maxit=cg_maxit)
             if solver == "chol":

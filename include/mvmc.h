@@ -106,6 +106,8 @@ typedef struct {
   int64_t O_elems;            /* elements of O (double for FP64, float for MIXED) */
   int64_t S_elems;            /* elements of S (same type as O); 0 when build_s == 0 */
   int64_t Y_elems;            /* doubles returned by mvmc_get_inverse */
+  int64_t pos_elems;          /* int16 configuration entries of mvmc_get_state */
+  int64_t empty_elems;        /* int16 empty-list entries of mvmc_get_state */
   int64_t workspace_bytes;    /* device workspace, 256-byte aligned */
   int32_t O_elem_bytes;       /* 8 (FP64) or 4 (MIXED) */
   int32_t pad;
@@ -122,6 +124,8 @@ typedef struct {
   int64_t S_off;                   /* S block [n_params][n_params] at S_off (full square) */
   int64_t Y_off;                   /* get_inverse: walker w at Y_off + w*n_elec^2, row-major */
   int64_t pos_off;                 /* get/set_state: walker w at pos_off + w*n_elec */
+  int64_t empty_off;               /* get/set_state: walker w at empty_off + w*2*n_sites,
+                                      [spin][n_sites], n_sites - n_sigma sites then -1 */
   int32_t n_elec, n_sites;
 } mvmc_instance_layout;
 
@@ -132,15 +136,21 @@ int mvmc_query_sizes(const mvmc_config *cfg, mvmc_sizes *out);
 int mvmc_query_layout(const mvmc_config *cfg, int32_t k, mvmc_instance_layout *out);
 
 /*
- * Create a context: copies the descriptors, lays out the workspace, expands
- * d_params (device, double, n_params) into the skew table A = F - F^T, v_ij,
- * g_i and the RBM weights, draws a uniform initial configuration per walker
- * (redrawn while X is singular) and computes X^-1 in double.
+ * Create a context for psi = P_G P_J phi_AP-Pf (section 3.2; Eqs. Pf and
+ * AP-Pf of section 3.2.1, the Gutzwiller and Jastrow factors of section
+ * 3.2.3): copies the descriptors, lays out the workspace, expands d_params
+ * (device, double, n_params) into the skew table A = F - F^T (so that
+ * X_ab = A[I_a][I_b], section 3.2.1), v_ij, g_i and the RBM weights, draws a
+ * uniform real-space configuration per walker (the fixed-S^z basis of
+ * section 3.1.1; redrawn while X is singular) and computes X^-1, log|Pf X|
+ * and its sign in double.
  * d_workspace: device memory of at least workspace_bytes, 256-byte aligned,
  * owned by the caller and untouched by anything else until mvmc_destroy.
- * hip_stream: hipStream_t (NULL = default stream).
- * Errors: MVMC_E_ARG, MVMC_E_SHAPE, MVMC_E_WORKSPACE, MVMC_E_HIP,
- * MVMC_E_SINGULAR (no invertible initial configuration in 100 draws).
+ * hip_stream: hipStream_t (NULL = default stream).  Synchronises the stream.
+ * Errors: MVMC_E_ARG, MVMC_E_SHAPE, MVMC_E_WORKSPACE (ws_bytes below
+ * workspace_bytes, or d_workspace not 256-byte aligned), MVMC_E_HIP,
+ * MVMC_E_NONFINITE (a NaN/Inf parameter), MVMC_E_SINGULAR (no invertible
+ * initial configuration in 100 draws).  On error *out is NULL.
  */
 int mvmc_init_wavefunction(mvmc_ctx **out, const mvmc_config *cfg, void *d_workspace,
                            size_t ws_bytes, const double *d_params, void *hip_stream);
@@ -154,6 +164,15 @@ int mvmc_init_wavefunction(mvmc_ctx **out, const mvmc_config *cfg, void *d_works
  * cleared; with NULL they keep accumulating).  With h_accepted == NULL the
  * call only enqueues kernels on the context's stream, so it can be captured
  * into a HIP graph (as can mvmc_measure_energy_and_O).
+ * Guard: a ratio that is not finite (NaN or Inf) triggers an immediate
+ * double-precision recomputation of the walker's X^-1 and correlator state,
+ * and the same proposal is tried again; if it is still not finite the walker
+ * stops there (its counter stays at that proposal) until the next
+ * mvmc_refresh, mvmc_set_state, mvmc_set_params or mvmc_sr_update.  Calls
+ * that synchronise (this one with h_accepted, mvmc_build_sr with host
+ * outputs) then return MVMC_E_NONFINITE with the instance, walker and
+ * proposal in mvmc_last_error.
+ * Errors: MVMC_E_ARG, MVMC_E_HIP, MVMC_E_NONFINITE (with h_accepted only).
  */
 int mvmc_sample_sweeps(mvmc_ctx *ctx, int32_t n_sweeps, int64_t *h_accepted);
 
@@ -228,13 +247,22 @@ int mvmc_peak_probe(int32_t kind, void *d_scratch, void *hip_stream, double *h_t
 int mvmc_measure_energy_and_O(mvmc_ctx *ctx, int32_t slot, double *d_eloc, void *d_O);
 
 /*
- * SR quantities over the first n_slots_used slots (section 3.3.1):
- * E_bar, var(E); o_k; O is centred in place (O <- O - o); d_g = O~^T(E-E_bar)/N
- * (double, n_params); d_S (may be NULL) = O~^T O~ / N, both triangles of each
- * instance block.  h_E, h_Evar (may be NULL): [n_instances].
+ * SR quantities over the first n_slots_used slots (section 3.3.1, with the
+ * sample means of section 3.3.2): E_bar = <E_loc>; o_k = <O_k>; O is centred
+ * in place (O <- O - o); d_g = O~^T(E-E_bar)/N (double, n_params); d_S (may be
+ * NULL) = O~^T O~ / N, both triangles of each instance block.
+ * Host outputs, each [n_instances] and each may be NULL:
+ *   h_E     E_bar;
+ *   h_Eerr  its statistical error, the walkers being independent chains:
+ *           sigma = std(walker means) / sqrt(W) with the unbiased std
+ *           (NaN for a single walker);
+ *   h_Evar  the sample variance <(E_loc - E_bar)^2>.
+ * Any host output synchronises the stream.
+ * Errors: MVMC_E_ARG (NULL buffer, n_slots_used outside [1, n_slots]),
+ * MVMC_E_STATE (d_S given to a context built with build_s = 0), MVMC_E_HIP.
  */
 int mvmc_build_sr(mvmc_ctx *ctx, int32_t n_slots_used, const double *d_eloc, void *d_O, void *d_S,
-                  double *d_g, double *h_E, double *h_Evar);
+                  double *d_g, double *h_E, double *h_Eerr, double *h_Evar);
 
 /*
  * Solve S_reg x = g with S_reg = S + diag(eps_rel S_kk + eps_abs) (parameters
@@ -251,22 +279,40 @@ int mvmc_build_sr(mvmc_ctx *ctx, int32_t n_slots_used, const double *d_eloc, voi
  * solver the number of tenfold raises of eps_rel (0: the caller's value).
  * d_dparams may be NULL.
  * Errors: MVMC_E_STATE (build_sr not called), MVMC_E_SINGULAR (Cholesky failed
- * after the raises, or a walker's X became singular), MVMC_E_NONFINITE.
+ * after the raises, or a walker's X became singular), MVMC_E_NONFINITE (the
+ * updated parameters hold a NaN/Inf: d_params keeps that update, the walkers
+ * keep the previous tables).
  */
 int mvmc_sr_update(mvmc_ctx *ctx, const void *d_S, const void *d_O, const double *d_g, double dtau,
                    double eps_rel, double eps_abs, int32_t solver, double cg_tol, int32_t cg_maxit,
                    double *d_params, double *d_dparams, int32_t *h_cg_iters);
 
-/* Replace the parameters (device, double) and recompute every walker. */
+/* Replace the parameters (device, double, n_params) and recompute every
+ * walker in double (X^-1 and Pf X of section 3.2.1).  Synchronises.
+ * Errors: MVMC_E_ARG, MVMC_E_NONFINITE (nothing changed),
+ * MVMC_E_SINGULAR (a walker's X is singular for the new parameters). */
 int mvmc_set_params(mvmc_ctx *ctx, const double *d_params);
 
-/* Walker configurations (spin-orbital of each electron; walker w of instance k
- * at pos_off + w*n_elec) and the Philox proposal counters [n_walkers]. */
-int mvmc_get_state(mvmc_ctx *ctx, int32_t *d_pos, uint64_t *d_counter);
+/* Checkpoint of the Markov chains (section 3.1.1): walker configurations as
+ * int16 spin-orbital indices I = i + Ns*sigma (section 3.2.1; walker w of
+ * instance k at pos_off + w*n_elec, up electrons first), the Philox proposal
+ * counters [n_walkers], and the per-spin lists of empty sites in the order
+ * the hopping proposals index them (they are reordered as the chain moves;
+ * layout at empty_off, pos_elems / empty_elems entries in all).  Device
+ * buffers, caller-owned; any may be NULL.  Enqueued only. */
+int mvmc_get_state(mvmc_ctx *ctx, int16_t *d_pos, uint64_t *d_counter, int16_t *d_empty);
 
-/* Load configurations and counters (counters equal within an instance),
- * rebuild the empty-site lists in ascending order and recompute X^-1. */
-int mvmc_set_state(mvmc_ctx *ctx, const int32_t *d_pos, const uint64_t *d_counter);
+/* Resume from a checkpoint: load configurations (int16, layout of
+ * mvmc_get_state), counters (equal within an instance) and, when d_empty is
+ * not NULL, the empty-site lists (each must list exactly the empty sites of
+ * its spin); with d_empty NULL the lists are rebuilt in ascending order.
+ * Every walker is then recomputed in double.  With the lists given, the
+ * chains continue bit for bit as a context that called mvmc_refresh at the
+ * checkpoint would.  Synchronises.
+ * Errors: MVMC_E_ARG (bad configuration, counters or lists; state
+ * unchanged), MVMC_E_SINGULAR (a loaded X is singular), MVMC_E_HIP. */
+int mvmc_set_state(mvmc_ctx *ctx, const int16_t *d_pos, const uint64_t *d_counter,
+                   const int16_t *d_empty);
 
 /* Every walker's current X^-1 as double (Y_elems, layout above). */
 int mvmc_get_inverse(mvmc_ctx *ctx, double *d_Y);
@@ -274,7 +320,9 @@ int mvmc_get_inverse(mvmc_ctx *ctx, double *d_Y);
 /* log|Pf(X)| and sign of every walker from the last full recomputation. */
 int mvmc_get_pfaffian(mvmc_ctx *ctx, double *d_logabs, double *d_sign);
 
-/* Full double recomputation of every walker now. */
+/* Full double recomputation of every walker now (X^-1, log|Pf X| and sign,
+ * section 3.2.1; Jastrow field and RBM angles); clears the non-finite
+ * guard.  Synchronises.  Errors: MVMC_E_SINGULAR, MVMC_E_HIP. */
 int mvmc_refresh(mvmc_ctx *ctx);
 
 /*

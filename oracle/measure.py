@@ -27,7 +27,9 @@ from __future__ import annotations
 
 import numpy as np
 
-from .wavefunction import Model, occupations, ratio, skew_table
+import math
+
+from .wavefunction import Model, log_psi, occupations, skew_table
 
 
 def neighbours(m: Model) -> list[list[tuple[int, float]]]:
@@ -46,6 +48,10 @@ def local_energy(m: Model, pos: np.ndarray, A: np.ndarray | None = None) -> floa
     nv = occupations(m, pos)
     e = float(np.dot(m.U, nv[:ns] * nv[ns:]))
     nb = neighbours(m)
+    # psi(x) once; every hop term is psi(x')/psi(x) with psi(x') from scratch
+    s0, l0 = log_psi(m, pos, A)
+    if s0 == 0.0:
+        raise ZeroDivisionError("psi(x) = 0")
     for a in range(m.n_elec):
         I = int(pos[a])
         sigma = I // ns
@@ -56,7 +62,9 @@ def local_energy(m: Model, pos: np.ndarray, A: np.ndarray | None = None) -> floa
                 continue
             new = pos.copy()
             new[a] = J
-            e += -t * ratio(m, new, pos, A)
+            s1, l1 = log_psi(m, new, A)
+            if s1 != 0.0:
+                e += -t * s1 * s0 * math.exp(l1 - l0)
     return e
 
 

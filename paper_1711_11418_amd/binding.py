@@ -54,6 +54,7 @@ class Sizes(C.Structure):
     _fields_ = [
         ("n_walkers", C.c_int64), ("n_params", C.c_int64), ("eloc_elems", C.c_int64),
         ("O_elems", C.c_int64), ("S_elems", C.c_int64), ("Y_elems", C.c_int64),
+        ("pos_elems", C.c_int64), ("empty_elems", C.c_int64),
         ("workspace_bytes", C.c_int64), ("O_elem_bytes", C.c_int32), ("pad", C.c_int32),
     ]
 
@@ -63,7 +64,7 @@ class Layout(C.Structure):
         ("walker_off", C.c_int64), ("n_walkers", C.c_int64), ("param_off", C.c_int64),
         ("n_params", C.c_int64), ("eloc_off", C.c_int64), ("O_off", C.c_int64),
         ("O_ld", C.c_int64), ("S_off", C.c_int64), ("Y_off", C.c_int64), ("pos_off", C.c_int64),
-        ("n_elec", C.c_int32), ("n_sites", C.c_int32),
+        ("empty_off", C.c_int64), ("n_elec", C.c_int32), ("n_sites", C.c_int32),
     ]
 
 
@@ -95,11 +96,11 @@ def load() -> C.CDLL:
         "mvmc_init_wavefunction": [C.POINTER(vp), C.POINTER(Config), vp, C.c_size_t, vp, vp],
         "mvmc_sample_sweeps": [vp, i32, vp],
         "mvmc_measure_energy_and_O": [vp, i32, vp, vp],
-        "mvmc_build_sr": [vp, i32, vp, vp, vp, vp, vp, vp],
+        "mvmc_build_sr": [vp, i32, vp, vp, vp, vp, vp, vp, vp],
         "mvmc_sr_update": [vp, vp, vp, vp, dbl, dbl, dbl, i32, dbl, i32, vp, vp, vp],
         "mvmc_set_params": [vp, vp],
-        "mvmc_get_state": [vp, vp, vp],
-        "mvmc_set_state": [vp, vp, vp],
+        "mvmc_get_state": [vp, vp, vp, vp],
+        "mvmc_set_state": [vp, vp, vp, vp],
         "mvmc_get_inverse": [vp, vp],
         "mvmc_get_pfaffian": [vp, vp, vp],
         "mvmc_refresh": [vp],
@@ -285,14 +286,18 @@ class MVMC:
                                                        self._p(self.O)))
 
     def build_sr(self, n_used: int, with_S: bool = True):
+        """SR statistics over the first n_used slots; returns (E_bar, sigma, var E)
+        per instance, sigma = std(walker means)/sqrt(W)."""
         E = np.zeros(self.n_inst)
+        Er = np.zeros(self.n_inst)
         V = np.zeros(self.n_inst)
         S = self.S if with_S else None
         self._check(self.lib.mvmc_build_sr(self.ctx, int(n_used), self._p(self.eloc),
                                            self._p(self.O), self._p(S), self._p(self.g),
                                            E.ctypes.data_as(C.c_void_p),
+                                           Er.ctypes.data_as(C.c_void_p),
                                            V.ctypes.data_as(C.c_void_p)))
-        return E, V
+        return E, Er, V
 
     def sr_update(self, dtau=0.02, eps_rel=1e-3, eps_abs=1e-6, solver="chol", cg_tol=1e-10,
                   cg_maxit=1000) -> np.ndarray:
@@ -311,19 +316,23 @@ class MVMC:
         self._check(self.lib.mvmc_set_params(self.ctx, self._p(self.params)))
 
     # ------------------------------------------------------ state / debug
-    def get_state(self):
+    def get_state(self, with_empty: bool = False):
+        """(configurations int16, counters int64[, empty-site lists int16]) on the device."""
         t = self.torch
-        pos = t.empty(sum(l.n_walkers * l.n_elec for l in self.layouts), dtype=t.int32,
-                      device=self.device)
+        pos = t.empty(int(self.sizes.pos_elems), dtype=t.int16, device=self.device)
         cnt = t.empty(int(self.sizes.n_walkers), dtype=t.int64, device=self.device)
-        self._check(self.lib.mvmc_get_state(self.ctx, self._p(pos), self._p(cnt)))
-        return pos, cnt
+        emp = (t.empty(int(self.sizes.empty_elems), dtype=t.int16, device=self.device)
+               if with_empty else None)
+        self._check(self.lib.mvmc_get_state(self.ctx, self._p(pos), self._p(cnt), self._p(emp)))
+        return (pos, cnt, emp) if with_empty else (pos, cnt)
 
-    def set_state(self, pos, cnt) -> None:
+    def set_state(self, pos, cnt, empty=None) -> None:
         t = self.torch
-        pos = t.as_tensor(np.asarray(pos, dtype=np.int32)).to(self.device).contiguous()
+        pos = t.as_tensor(np.asarray(pos, dtype=np.int16)).to(self.device).contiguous()
         cnt = t.as_tensor(np.asarray(cnt, dtype=np.int64)).to(self.device).contiguous()
-        self._check(self.lib.mvmc_set_state(self.ctx, self._p(pos), self._p(cnt)))
+        emp = (None if empty is None else
+               t.as_tensor(np.asarray(empty, dtype=np.int16)).to(self.device).contiguous())
+        self._check(self.lib.mvmc_set_state(self.ctx, self._p(pos), self._p(cnt), self._p(emp)))
 
     def get_inverse(self):
         t = self.torch

@@ -47,7 +47,8 @@ struct Plan {
   Pool inst_p, srinst_p, walker_inst, lists, A64, A32, V, fidx, vidx, G, U, gidx, nbr_ptr,
       nbr_site, nbr_t, fm_ptr, fm, gm_ptr, gm, vm_ptr, vm, rbm64, rbm32, rbmT64, rbmT32, Y, Y64,
       pos, empty, h,
-      theta, cnt, target, needs_refresh, accepted, logpf, sgnpf, minpiv, status, trace_base,
+      theta, cnt, target, needs_refresh, accepted, logpf, sgnpf, minpiv, status, guard, chk,
+      trace_base,
       obar, sdiag, x, r, p, w, t, shift, mask, scal, colpart, syrkpart, chol, split;
   size_t total = 0;
   int64_t W = 0, np = 0, eloc = 0, O_elems = 0, S_elems = 0, Y_elems = 0;
@@ -295,6 +296,7 @@ Plan make_plan(const mvmc_config& c) {
     S.np = I.np;
     S.ldO = I.ldO;
     S.rows = I.rows;
+    S.walkers = I.W;
     S.O_off = I.O_off;
     S.S_off = I.S_off;
     S.eloc_off = I.eloc_off;
@@ -384,6 +386,8 @@ Plan make_plan(const mvmc_config& c) {
   take(P.sgnpf, 8 * W);
   take(P.minpiv, 8 * W);
   take(P.status, 4 * W);
+  take(P.guard, 4 * W);
+  take(P.chk, 8);
   take(P.trace_base, 8 * W);
   const size_t NP = (size_t)P.np;
   take(P.obar, 8 * NP);
@@ -561,8 +565,8 @@ void build_buckets(mvmc_ctx* c, bool per_instance = false) {
     // instances within reach of the anti-parallel block refresh share
     // buckets of their own, so that one large instance does not send the
     // whole bucket to the workgroup-per-walker kernel
-    if (refresh_ap_fits(I.ne, I.ns)) {
-      refresh_groups[{2, 0, 64, own}].push_back(k);
+    if (const int route = refresh_ap_route(I.ne, I.ns)) {
+      refresh_groups[{1 + route, 0, 64, own}].push_back(k);
     } else {
       size_t rb = refresh_lds_bytes(I.ne, I.ns, I.refresh_lds);
       size_t rcls = 4096;
@@ -664,6 +668,63 @@ int first_singular(mvmc_ctx* c, std::vector<int32_t>& st) {
   return -1;
 }
 
+// Walkers whose guard word says a ratio stayed non-finite after a double
+// refresh: MVMC_E_NONFINITE naming the first one (synchronises the stream).
+int check_guard(mvmc_ctx* c) {
+  const Plan& P = c->plan;
+  std::vector<int32_t> g(P.W);
+  std::vector<uint64_t> cnt(P.W);
+  HIPCHK(c, hipMemcpyAsync(g.data(), c->P.guard, 4 * P.W, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(cnt.data(), c->P.cnt, 8 * P.W, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < c->cfg.n_instances; ++k) {
+    const InstDev& I = P.inst[k];
+    for (int w = 0; w < I.W; ++w)
+      if (g[I.walker_off + w] == kGuardFailed)
+        return set_err(c, fail(MVMC_E_NONFINITE,
+                               "instance %d walker %d (global %lld): ratio of proposal %llu is "
+                               "not finite after a double-precision refresh",
+                               k, w, (long long)(I.walker_off + w),
+                               (unsigned long long)cnt[I.walker_off + w]));
+  }
+  return MVMC_OK;
+}
+
+// MVMC_E_NONFINITE when a parameter vector (device, n doubles) holds a NaN
+// or Inf, naming the instance and slot (synchronises the stream).
+int check_params(mvmc_ctx* c, const double* d_params, const char* what) {
+  const Plan& P = c->plan;
+  int64_t* d_first = reinterpret_cast<int64_t*>(c->ws + P.chk.off);
+  launch_first_nonfinite(d_params, P.np, d_first, c->stream);
+  LAUNCHCHK(c);
+  int64_t first = 0;
+  HIPCHK(c, hipMemcpyAsync(&first, d_first, 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (first >= P.np) return MVMC_OK;
+  int k = 0;
+  while (k + 1 < c->cfg.n_instances && P.inst[k + 1].param_off <= first) ++k;
+  return set_err(c, fail(MVMC_E_NONFINITE, "%s: parameter %lld of instance %d is not finite", what,
+                         (long long)(first - P.inst[k].param_off), k));
+}
+
+// MVMC_E_SINGULAR naming the first walker whose last refresh found X
+// singular (synchronises the stream).
+int check_singular(mvmc_ctx* c, const char* when) {
+  std::vector<int32_t> st;
+  const int bad = first_singular(c, st);
+  if (bad == -2) return set_err(c, fail(MVMC_E_HIP, "status read failed"));
+  if (bad < 0) return MVMC_OK;
+  int k = 0;
+  while (k + 1 < c->cfg.n_instances && c->plan.inst[k + 1].walker_off <= bad) ++k;
+  return set_err(c, fail(MVMC_E_SINGULAR, "instance %d walker %lld: X is singular %s", k,
+                         (long long)(bad - c->plan.inst[k].walker_off), when));
+}
+
+int clear_guard(mvmc_ctx* c) {
+  HIPCHK(c, hipMemsetAsync(c->P.guard, 0, 4 * c->plan.W, c->stream));
+  return MVMC_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- entry points
@@ -696,6 +757,8 @@ int mvmc_query_sizes(const mvmc_config* cfg, mvmc_sizes* out) {
   out->O_elems = P.O_elems;
   out->S_elems = P.S_elems;
   out->Y_elems = P.Y_elems;
+  out->pos_elems = (int64_t)(P.pos.bytes / 4);
+  out->empty_elems = (int64_t)(P.empty.bytes / 4);
   out->workspace_bytes = (int64_t)P.total;
   out->O_elem_bytes = (int32_t)P.tsize;
   out->pad = 0;
@@ -718,6 +781,7 @@ int mvmc_query_layout(const mvmc_config* cfg, int32_t k, mvmc_instance_layout* o
   out->S_off = I.S_off;
   out->Y_off = I.Y_off;
   out->pos_off = I.pos_off;
+  out->empty_off = I.empty_off;
   out->n_elec = I.ne;
   out->n_sites = I.ns;
   return MVMC_OK;
@@ -781,6 +845,7 @@ int mvmc_init_wavefunction(mvmc_ctx** out, const mvmc_config* cfg, void* d_ws, s
   Q.sgnpf = at<double>(b, P.sgnpf);
   Q.minpiv = at<double>(b, P.minpiv);
   Q.status = at<int32_t>(b, P.status);
+  Q.guard = at<int32_t>(b, P.guard);
   SrArgs& S = c->SA;
   S.inst = at<SrInst>(b, P.srinst_p);
   S.obar = at<double>(b, P.obar);
@@ -845,6 +910,7 @@ int mvmc_init_wavefunction(mvmc_ctx** out, const mvmc_config* cfg, void* d_ws, s
   chk(up(P.vm, vm.data(), 4 * vm.size()));
   chk(hipMemset(Q.cnt, 0, 8 * P.W));
   chk(hipMemset(Q.accepted, 0, 8 * P.W));
+  chk(hipMemset(Q.guard, 0, 4 * P.W));
   chk(hipMemset(b + P.needs_refresh.off, 0, 4 * P.W));
   chk(hipMemset(Q.theta, 0, 8 * std::max<size_t>(P.theta.bytes / 8, 1)));
   chk(hipMemset(S.scal, 0, P.scal.bytes));
@@ -866,6 +932,11 @@ int mvmc_init_wavefunction(mvmc_ctx** out, const mvmc_config* cfg, void* d_ws, s
   build_buckets(c);
   c->cnt_host.assign(cfg->n_instances, 0);
 
+  if (int rc = check_params(c, d_params, "init")) {
+    std::fprintf(stderr, "mvmc_init_wavefunction: %s\n", c->err.c_str());
+    mvmc_destroy(c);
+    return rc;
+  }
   // parameters -> tables
   launch_expand(Q, P.inst.data(), cfg->n_instances, d_params, c->stream);
   // initial configurations: uniform draws, redrawn while X is singular
@@ -912,14 +983,19 @@ int mvmc_destroy(mvmc_ctx* c) {
 
 int mvmc_set_params(mvmc_ctx* c, const double* d_params) {
   if (!c || !d_params) return MVMC_E_ARG;
+  if (int rc = check_params(c, d_params, "mvmc_set_params")) return rc;
   launch_expand(c->P, c->plan.inst.data(), c->cfg.n_instances, d_params, c->stream);
   LAUNCHCHK(c);
-  return refresh_any(c, 0.0);
+  if (int rc = clear_guard(c)) return rc;
+  if (int rc = refresh_any(c, 0.0)) return rc;
+  return check_singular(c, "with the new parameters");
 }
 
 int mvmc_refresh(mvmc_ctx* c) {
   if (!c) return MVMC_E_ARG;
-  return refresh_any(c, 0.0);
+  if (int rc = clear_guard(c)) return rc;
+  if (int rc = refresh_any(c, 0.0)) return rc;
+  return check_singular(c, "at the refresh");
 }
 
 }  // extern "C"
@@ -939,14 +1015,17 @@ int run_sweeps(mvmc_ctx* c, int32_t n_sweeps, std::vector<double>* inst_ms) {
   for (int k = 0; k < c->cfg.n_instances; ++k) {
     const uint64_t tot = (uint64_t)n_sweeps * P.inst[k].ne;
     target[k] = tot;
-    if (R > 0 && !P.reg_class[k]) {
+    if (!P.reg_class[k]) {
+      lds_refresh = true;
       // enough refresh-aligned rounds for any starting phase (an extra round
       // is an empty launch); independent of the host's view of the counters,
       // so a captured graph stays valid on replay
-      lds_refresh = true;
-      rounds = std::max<int>(rounds, (int)((tot + R - 1) / R) + 1);
+      if (R > 0) rounds = std::max<int>(rounds, (int)((tot + R - 1) / R) + 1);
     }
   }
+  // one more round for LDS-tier walkers stopped by a non-finite ratio: the
+  // refresh between rounds recomputes them and the last launch retries
+  if (lds_refresh && n_sweeps > 0) ++rounds;
   const int64_t cap = R > 0 ? R : (int64_t)1 << 62;
   uint64_t* tgt = reinterpret_cast<uint64_t*>(c->ws + P.target.off);
   int32_t* nr = reinterpret_cast<int32_t*>(c->ws + P.needs_refresh.off);
@@ -1055,6 +1134,7 @@ int mvmc_sample_sweeps(mvmc_ctx* c, int32_t n_sweeps, int64_t* h_accepted) {
       h_accepted[k] = s;
     }
     HIPCHK(c, hipMemsetAsync(c->P.accepted, 0, 8 * P.W, c->stream));
+    return check_guard(c);
   }
   return MVMC_OK;
 }
@@ -1335,7 +1415,7 @@ int tune_s_tiles(mvmc_ctx* c, const uint16_t* split, float* d_S) {
 }  // namespace
 
 int mvmc_build_sr(mvmc_ctx* c, int32_t n_used, const double* d_eloc, void* d_O, void* d_S,
-                  double* d_g, double* h_E, double* h_Evar) {
+                  double* d_g, double* h_E, double* h_Eerr, double* h_Evar) {
   if (!c || !d_eloc || !d_O || !d_g) return set_err(c, fail(MVMC_E_ARG, "NULL buffer"));
   if (n_used < 1 || n_used > c->cfg.n_slots)
     return set_err(c, fail(MVMC_E_ARG, "n_slots_used %d outside [1, %d]", n_used, c->cfg.n_slots));
@@ -1378,14 +1458,19 @@ int mvmc_build_sr(mvmc_ctx* c, int32_t n_used, const double* d_eloc, void* d_O, 
     LAUNCHCHK(c);
   }
   c->sr_ready = true;
-  if (h_E || h_Evar) {
+  if (h_E || h_Eerr || h_Evar) {
     std::vector<double> sc((size_t)kScal * n);
     HIPCHK(c, hipMemcpyAsync(sc.data(), c->SA.scal, 8 * sc.size(), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     for (int k = 0; k < n; ++k) {
       if (h_E) h_E[k] = sc[k * kScal + kEbar];
+      if (h_Eerr) h_Eerr[k] = sc[k * kScal + kEerr];
       if (h_Evar) h_Evar[k] = sc[k * kScal + kEvar];
     }
+    if (int rc = check_guard(c)) return rc;
+    for (int k = 0; k < n; ++k)
+      if (!std::isfinite(sc[k * kScal + kEbar]))
+        return set_err(c, fail(MVMC_E_NONFINITE, "instance %d: mean local energy is not finite", k));
   }
   return MVMC_OK;
 }
@@ -1475,34 +1560,39 @@ int mvmc_sr_update(mvmc_ctx* c, const void* d_S, const void* d_O, const double* 
   }
   sr_apply(c->SA, dtau, d_params, d_dparams, n, P.max_np, c->stream);
   LAUNCHCHK(c);
+  // a non-finite update is reported before it reaches the walkers (the
+  // parameter vector then holds it; the walkers keep the previous tables)
+  if (int rc = check_params(c, d_params, "mvmc_sr_update")) return rc;
   launch_expand(c->P, P.inst.data(), n, d_params, c->stream);
   LAUNCHCHK(c);
+  if (int rc = clear_guard(c)) return rc;
   int rc = refresh_any(c, 0.0);
   if (rc) return rc;
-  std::vector<int32_t> st;
-  const int bad = first_singular(c, st);
-  if (bad == -2) return set_err(c, fail(MVMC_E_HIP, "status read failed"));
-  if (bad >= 0) return set_err(c, fail(MVMC_E_SINGULAR, "walker %d: X singular after update", bad));
-  return MVMC_OK;
+  return check_singular(c, "after the parameter update");
 }
 
-int mvmc_get_state(mvmc_ctx* c, int32_t* d_pos, uint64_t* d_counter) {
+int mvmc_get_state(mvmc_ctx* c, int16_t* d_pos, uint64_t* d_counter, int16_t* d_empty) {
   if (!c) return MVMC_E_ARG;
   const Plan& P = c->plan;
-  if (d_pos)
-    HIPCHK(c, hipMemcpyAsync(d_pos, c->P.pos, P.pos.bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (d_pos) launch_pos_narrow(c->P.pos, d_pos, (int64_t)(P.pos.bytes / 4), c->stream);
+  if (d_empty) launch_pos_narrow(c->P.empty, d_empty, (int64_t)(P.empty.bytes / 4), c->stream);
+  LAUNCHCHK(c);
   if (d_counter)
     HIPCHK(c, hipMemcpyAsync(d_counter, c->P.cnt, 8 * P.W, hipMemcpyDeviceToDevice, c->stream));
   return MVMC_OK;
 }
 
-int mvmc_set_state(mvmc_ctx* c, const int32_t* d_pos, const uint64_t* d_counter) {
+int mvmc_set_state(mvmc_ctx* c, const int16_t* d_pos, const uint64_t* d_counter,
+                   const int16_t* d_empty) {
   if (!c || !d_pos || !d_counter) return set_err(c, fail(MVMC_E_ARG, "NULL buffer"));
   const Plan& P = c->plan;
+  const int64_t npos = (int64_t)(P.pos.bytes / 4), nemp = (int64_t)(P.empty.bytes / 4);
   // validate on the host before touching the walker state
-  std::vector<int32_t> pos(P.pos.bytes / 4);
+  std::vector<int16_t> pos(npos), emp(d_empty ? nemp : 0);
   std::vector<uint64_t> cnt(P.W);
-  HIPCHK(c, hipMemcpyAsync(pos.data(), d_pos, P.pos.bytes, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(pos.data(), d_pos, 2 * npos, hipMemcpyDeviceToHost, c->stream));
+  if (d_empty)
+    HIPCHK(c, hipMemcpyAsync(emp.data(), d_empty, 2 * nemp, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(cnt.data(), d_counter, 8 * P.W, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   for (int k = 0; k < c->cfg.n_instances; ++k) {
@@ -1511,26 +1601,45 @@ int mvmc_set_state(mvmc_ctx* c, const int32_t* d_pos, const uint64_t* d_counter)
       if (cnt[I.walker_off + w] != cnt[I.walker_off])
         return set_err(c, fail(MVMC_E_ARG, "instance %d: counters must be equal", k));
       std::vector<char> occ(2 * I.ns, 0);
-      const int32_t* p = pos.data() + I.pos_off + (int64_t)w * I.ne;
+      const int16_t* p = pos.data() + I.pos_off + (int64_t)w * I.ne;
       for (int a = 0; a < I.ne; ++a) {
         const int lo = a < I.nup ? 0 : I.ns, hi = lo + I.ns;
         if (p[a] < lo || p[a] >= hi || occ[p[a]])
           return set_err(c, fail(MVMC_E_ARG, "instance %d walker %d: bad configuration", k, w));
         occ[p[a]] = 1;
       }
+      if (!d_empty) continue;
+      // each spin's list: exactly its empty sites, then -1
+      for (int sg = 0; sg < 2; ++sg) {
+        const int nfree = I.ns - (sg ? I.ndn : I.nup);
+        const int16_t* e = emp.data() + I.empty_off + ((int64_t)w * 2 + sg) * I.ns;
+        std::vector<char> seen(I.ns, 0);
+        for (int j = 0; j < I.ns; ++j) {
+          const int site = e[j];
+          const bool ok = j < nfree ? (site >= 0 && site < I.ns && !occ[site + sg * I.ns] &&
+                                       !seen[site])
+                                    : site == -1;
+          if (!ok)
+            return set_err(c, fail(MVMC_E_ARG, "instance %d walker %d: bad empty-site list", k,
+                                   w));
+          if (j < nfree) seen[site] = 1;
+        }
+      }
     }
   }
-  HIPCHK(c, hipMemcpyAsync(c->P.pos, d_pos, P.pos.bytes, hipMemcpyDeviceToDevice, c->stream));
+  launch_pos_widen(d_pos, c->P.pos, npos, c->stream);
+  LAUNCHCHK(c);
   HIPCHK(c, hipMemcpyAsync(c->P.cnt, d_counter, 8 * P.W, hipMemcpyDeviceToDevice, c->stream));
-  launch_build_empty(c->P, c->d_all, (int)P.W, P.max_ns, c->stream);
+  if (d_empty)
+    launch_pos_widen(d_empty, c->P.empty, nemp, c->stream);
+  else
+    launch_build_empty(c->P, c->d_all, (int)P.W, P.max_ns, c->stream);
   LAUNCHCHK(c);
   for (int k = 0; k < c->cfg.n_instances; ++k) c->cnt_host[k] = cnt[P.inst[k].walker_off];
+  if (int r0 = clear_guard(c)) return r0;
   int rc = refresh_any(c, 0.0);
   if (rc) return rc;
-  std::vector<int32_t> st;
-  const int bad = first_singular(c, st);
-  if (bad >= 0) return set_err(c, fail(MVMC_E_SINGULAR, "walker %d: X singular", bad));
-  return MVMC_OK;
+  return check_singular(c, "for the loaded configuration");
 }
 
 int mvmc_get_inverse(mvmc_ctx* c, double* d_Y) {

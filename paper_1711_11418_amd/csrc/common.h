@@ -78,7 +78,13 @@ struct Pools {
   double* sgnpf;
   double* minpiv;
   int32_t* status;
+  // non-finite ratio guard per walker: 0 clear; 1 a ratio was not finite and
+  // the walker waits for a double refresh before retrying that proposal;
+  // 2 still not finite after the refresh: the walker stops
+  int32_t* guard;
 };
+
+enum : int32_t { kGuardClear = 0, kGuardPending = 1, kGuardFailed = 2 };
 
 // One record per proposal when tracing is on.
 struct TraceRec {

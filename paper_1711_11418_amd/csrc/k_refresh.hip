@@ -243,10 +243,10 @@ template <typename T>
 static void refresh_impl(const Pools& P, const int32_t* wlist, int n, int max_ne, int max_ns,
                          bool lds, double sing_tol, int32_t* flags, hipStream_t s) {
   if (n <= 0) return;
-  // up to 64 electrons per spin: the anti-parallel block route, one
-  // wavefront per walker with the block in registers
-  if (refresh_ap_fits(max_ne, max_ns)) {
-    launch_refresh_ap<T>(P, wlist, n, max_ne, max_ns, sing_tol, flags, s);
+  // up to 128 electrons per spin: the anti-parallel block route, with the
+  // block in registers (one wavefront per walker, or a 16 x 16 thread tile)
+  if (const int route = refresh_ap_route(max_ne, max_ns)) {
+    launch_refresh_ap<T>(P, wlist, n, max_ne, max_ns, route, sing_tol, flags, s);
     return;
   }
   const size_t sh = refresh_lds_bytes(max_ne, max_ns, lds);

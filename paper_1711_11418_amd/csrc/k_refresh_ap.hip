@@ -159,127 +159,152 @@ __global__ __launch_bounds__(64 * kApWpb, 2) void k_refresh_ap(Pools P,
   }
 }
 
-// Two or more wavefronts per walker (up to 64 NW rows of M, one per lane):
-// the same exchange steps with the pivot search and the pivot row passed
-// through LDS between workgroup barriers.
-struct ApStateBlk {
-  double logabs = 0.0, sgn = 1.0, minpiv = DBL_MAX;
-  double mant = 1.0;   // |det| = mant 2^ex over the steps taken
-  int ex = 0;
-  uint64_t used[2] = {0, 0};   // rows pivoted so far (up to 128)
-  int parity = 0;
-  bool singular = false;
-};
+// Wider blocks (64 < n <= 16 NB): one workgroup of 16 x 16 threads per walker.
+// Thread (ty, tx) keeps the tableau entries T[ty + 16 i][tx + 16 j],
+// i, j < NB, in registers (a cyclic distribution, so every thread has work
+// for any n).  Step k (column k): the threads of column k post the
+// (threshold-)largest |T[r][k]| over their free rows as a 64-bit key through
+// LDS; the pivot row p and column k go to LDS; every thread then applies the
+// exchange step to its block:
+//     T[p][k] <- 1/pi,   T[p][c] <- -T[p][c]/pi,
+//     T[r][k] <- T[r][k]/pi,   T[r][c] <- T[r][c] - T[r][k] T[p][c]/pi.
+// The column loop is split into an unrolled loop over the register column j
+// and a runtime loop over the 16 thread columns, so every register index is
+// a compile-time constant.
+constexpr int kTileT = 16;            // thread grid side
+constexpr int kTileThreads = kTileT * kTileT;
 
-template <int K, int NS, int NW>
-__device__ __forceinline__ void ap_steps_blk(ApStateBlk& st, double (&m)[NS], double* rowp,
-                                             int32_t* piv, double* redv,
-                                             int row, bool live, int nh, double tol) {
-  if constexpr (K < NS) {
-    if (K < nh && !st.singular) {
-      const int lane = row & 63, wv = row >> 6;
-      const bool free_row = live && !((st.used[row >> 6] >> (row & 63)) & 1ull);
-      // per wavefront one reduction of the pivot key (largest |T[r][K]|, then
-      // lowest row); the wavefronts' keys go through LDS as raw bits
-      const uint64_t kw = wave_max_u64(pivot_key(m[K], lane, free_row));
-      if (lane == 0) redv[wv] = __longlong_as_double((long long)kw);
-      __syncthreads();
-      uint64_t kbest = 0;
-      int wbest = 0;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) {
-        const uint64_t k = (uint64_t)__double_as_longlong(redv[w]);
-        if (k > kbest) {
-          kbest = k;
-          wbest = w;
-        }
-      }
-      const double vmax = pivot_mag(kbest);
-      const int p = wbest * 64 + pivot_lane(kbest);
-      if (kbest == 0 || !(vmax > tol) || p >= nh) {
-        st.singular = true;
-      } else {
-        const bool me = row == p;
-        if (me)
-#pragma unroll
-          for (int c = 0; c < NS; ++c) rowp[c] = m[c];
-        if (threadIdx.x == 0) piv[K] = p;
-        __syncthreads();
-        const double pv = rowp[K];
-        absdet_mul(st.mant, st.ex, fabs(pv));
-        if (pv < 0.0) st.sgn = -st.sgn;
-        st.minpiv = fmin(st.minpiv, fabs(pv));
-        const int pl = p & 63, pwv = p >> 6;
-        const uint64_t below = (1ull << pl) - 1ull;
-        st.parity += __builtin_popcountll(~st.used[pwv] & below);
-        if (pwv == 1) st.parity += __builtin_popcountll(~st.used[0]);
-        st.used[pwv] |= 1ull << pl;
-        const double ip = 1.0 / pv;
-        const double t = m[K];
-        const double g = me ? -ip : 1.0;
-        const double f = me ? 0.0 : t * ip;
-#pragma unroll
-        for (int c = 0; c < NS; ++c)
-          if (c != K) m[c] = fma(-f, rowp[c], g * m[c]);
-        m[K] = me ? ip : t * ip;
-        __syncthreads();   // rowp and the reduction slots are reused next step
-      }
-    }
-    ap_steps_blk<K + 1, NS, NW>(st, m, rowp, piv, redv, row, live, nh, tol);
-  } else {
-    st.logabs = absdet_log(st.mant, st.ex);
-  }
+// Pivot key: the IEEE bits of |x| with the low seven mantissa bits replaced by
+// 127 - row, so one unsigned maximum gives the largest magnitude (to 2^-45
+// relative) and, among those, the lowest row; rows that may not be chosen
+// have key 0.
+__device__ __forceinline__ uint64_t tile_key(double x, int row, bool free_row) {
+  const uint64_t b = (uint64_t)__double_as_longlong(fabs(x));
+  return free_row ? ((b & ~(uint64_t)127) | (uint64_t)(127 - row)) : 0;
 }
 
-template <typename T, int NS, int NW>
-__global__ __launch_bounds__(64 * NW) void k_refresh_ap_blk(Pools P,
-                                                             const int32_t* __restrict__ wlist,
-                                                             double sing_tol,
-                                                             int32_t* __restrict__ flags) {
+struct TileLds {
+  double rowp[kTileT * 8];
+  double colk[kTileT * 8];
+  uint64_t keys[kTileT];
+  double amax[kTileThreads / 64];
+  int32_t piv[kTileT * 8];
+  int32_t pinv[kTileT * 8];
+};
+
+template <typename T, int NB>
+__global__ __launch_bounds__(kTileThreads, 2) void k_refresh_ap_tiled(
+    Pools P, const int32_t* __restrict__ wlist, double sing_tol, int32_t* __restrict__ flags) {
+  static_assert(NB <= 8, "tableau side at most 128");
   extern __shared__ __align__(16) unsigned char smem[];
+  TileLds& L = *reinterpret_cast<TileLds*>(smem);
+  int32_t* pos = reinterpret_cast<int32_t*>(smem + sizeof(TileLds));   // N_e
   const int gw = wlist[blockIdx.x];
   if (gw < 0 || (flags && !flags[gw])) return;
   const InstDev& I = P.inst[P.walker_inst[gw]];
   const int ne = I.ne, ns = I.ns, n2 = 2 * ns, nh = I.nup;
+  int32_t* occ = pos + ne;                                              // 2 N_s
   const int64_t lw = gw - I.walker_off;
-  const int row = threadIdx.x, lane = row & 63;
-  double* rowp = (double*)smem;                 // NS
-  double* redv = rowp + NS;                     // NW
-  int32_t* pos = (int32_t*)(redv + NW);         // 2 NS
-  int32_t* piv = pos + 2 * NS;                  // NS
-  int32_t* occ = piv + NS;                      // 2 N_s
+  const int tid = threadIdx.x, tx = tid & (kTileT - 1), ty = tid / kTileT;
 
   const int32_t* posg = P.pos + I.pos_off + lw * ne;
-  for (int b = row; b < ne; b += 64 * NW) pos[b] = posg[b];
-  for (int v = row; v < n2; v += 64 * NW) occ[v] = 0;
+  for (int b = tid; b < ne; b += kTileThreads) pos[b] = posg[b];
+  for (int v = tid; v < n2; v += kTileThreads) occ[v] = 0;
   __syncthreads();
-  for (int b = row; b < ne; b += 64 * NW) occ[pos[b]] = 1;
+  for (int b = tid; b < ne; b += kTileThreads) occ[pos[b]] = 1;
 
+  // M[r][c] = f(site of up electron r, site of down electron c) = A[I_r][I_{n+c}]
   const double* A = P.A64 + I.A_off;
-  const bool live = row < nh;
-  const int64_t roff = live ? (int64_t)pos[row] * n2 : 0;
-  double m[NS];
+  double m[NB][NB];
   double amax = 0.0;
 #pragma unroll
-  for (int c = 0; c < NS; ++c) {
-    const bool in = live && c < nh;
-    const double v = in ? A[roff + pos[nh + (in ? c : 0)]] : 0.0;
-    m[c] = v;
-    amax = fmax(amax, fabs(v));
+  for (int i = 0; i < NB; ++i) {
+    const int r = ty + kTileT * i;
+    const int64_t roff = r < nh ? (int64_t)pos[r] * n2 : 0;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int c = tx + kTileT * j;
+      const bool in = r < nh && c < nh;
+      const double v = in ? A[roff + pos[nh + (in ? c : 0)]] : 0.0;
+      m[i][j] = v;
+      amax = fmax(amax, fabs(v));
+    }
   }
   amax = wave_max(amax);
-  if (lane == 0) redv[row >> 6] = amax;
+  if ((tid & 63) == 0) L.amax[tid / 64] = amax;
   __syncthreads();
-  amax = 0.0;
-#pragma unroll
-  for (int w = 0; w < NW; ++w) amax = fmax(amax, redv[w]);
-  __syncthreads();
+  amax = fmax(fmax(L.amax[0], L.amax[1]), fmax(L.amax[2], L.amax[3]));
+  const double tol = sing_tol * amax;
 
-  ApStateBlk st;
-  ap_steps_blk<0, NS, NW>(st, m, rowp, piv, redv, row, live, nh, sing_tol * amax);
-  __syncthreads();
-  if (st.singular) {
-    if (row == 0) {
+  uint32_t used = 0;   // bit i: row ty + 16 i already pivoted
+  double mant = 1.0, minpiv = DBL_MAX, sgn = 1.0;
+  int ex = 0;
+  bool singular = false;
+#pragma unroll
+  for (int jk = 0; jk < NB; ++jk) {
+    for (int txk = 0; txk < kTileT; ++txk) {
+      const int k = kTileT * jk + txk;
+      if (k >= nh || singular) break;   // uniform
+      // pivot search over the free rows of column k
+      if (tx == txk) {
+        uint64_t key = 0;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          const int r = ty + kTileT * i;
+          const uint64_t kk = tile_key(m[i][jk], r, r < nh && !((used >> i) & 1u));
+          key = kk > key ? kk : key;
+        }
+        L.keys[ty] = key;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) L.colk[ty + kTileT * i] = m[i][jk];
+      }
+      __syncthreads();
+      uint64_t kb = 0;
+#pragma unroll
+      for (int t = 0; t < kTileT; ++t) kb = L.keys[t] > kb ? L.keys[t] : kb;
+      const double vmax = __longlong_as_double((long long)(kb & ~(uint64_t)127));
+      if (kb == 0 || !(vmax > tol)) {
+        singular = true;
+        break;
+      }
+      const int p = 127 - (int)(kb & 127);
+      const int pt = p & (kTileT - 1), pi = p / kTileT;
+      if (ty == pt) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+          if (i == pi)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) L.rowp[tx + kTileT * j] = m[i][j];
+        used |= 1u << pi;
+      }
+      if (tid == 0) {
+        L.piv[k] = p;
+        L.pinv[p] = k;
+      }
+      __syncthreads();
+      const double pv = L.colk[p];
+      absdet_mul(mant, ex, fabs(pv));
+      if (pv < 0.0) sgn = -sgn;
+      minpiv = fmin(minpiv, fabs(pv));
+      const double ip = 1.0 / pv;
+      double rp[NB];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) rp[j] = L.rowp[tx + kTileT * j];
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        const int r = ty + kTileT * i;
+        const bool isp = r == p;
+        const double f = isp ? 0.0 : L.colk[r] * ip;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) m[i][j] = isp ? -rp[j] * ip : fma(-f, rp[j], m[i][j]);
+        if (tx == txk) m[i][jk] = isp ? ip : f;
+      }
+      __syncthreads();   // rowp, colk and keys are rewritten by the next step
+    }
+  }
+
+  if (singular) {
+    if (tid == 0) {
       if (flags) flags[gw] = 0;
       P.logpf[gw] = -INFINITY;
       P.sgnpf[gw] = 0.0;
@@ -287,40 +312,55 @@ __global__ __launch_bounds__(64 * NW) void k_refresh_ap_blk(Pools P,
       P.status[gw] = 1;
     }
   } else {
-    double sgn = st.sgn;
-    if (st.parity & 1) sgn = -sgn;
-    if (((nh * (nh - 1)) / 2) & 1) sgn = -sgn;
-    T* Y = (T*)P.Y + I.Y_off + lw * ne * ne;
-    int a = -1;
-#pragma unroll
-    for (int k = 0; k < NS; ++k)
-      if (k < nh && piv[k] == row) a = k;
-    if (live && a >= 0) {
-      T* rdn = Y + (int64_t)(nh + a) * ne;
-      for (int b = 0; b < nh; ++b) rdn[nh + b] = T(0);
-#pragma unroll
-      for (int b = 0; b < NS; ++b)
-        if (b < nh) {
-          const int qb = piv[b];
-          rdn[qb] = (T)m[b];
-          Y[(int64_t)qb * ne + nh + a] = (T)(-m[b]);
+    // sign of the pivot permutation k -> piv[k] (cycle lengths), then
+    // Pf(X) = (-1)^{n(n-1)/2} det M
+    if (tid == 0) {
+      uint64_t seen[2] = {0, 0};
+      int parity = 0;
+      for (int b = 0; b < nh; ++b) {
+        if ((seen[b >> 6] >> (b & 63)) & 1ull) continue;
+        int c = b, len = 0;
+        while (!((seen[c >> 6] >> (c & 63)) & 1ull)) {
+          seen[c >> 6] |= 1ull << (c & 63);
+          c = L.piv[c];
+          ++len;
         }
-    }
-    if (live) {
-      T* rup = Y + (int64_t)row * ne;
-      for (int b = 0; b < nh; ++b) rup[b] = T(0);
-    }
-    if (row == 0) {
+        parity += len - 1;
+      }
+      if (parity & 1) sgn = -sgn;
+      if (((nh * (nh - 1)) / 2) & 1) sgn = -sgn;
       if (flags) flags[gw] = 0;
-      P.logpf[gw] = st.logabs;
+      P.logpf[gw] = absdet_log(mant, ex);
       P.sgnpf[gw] = sgn;
-      P.minpiv[gw] = st.minpiv / (amax > 0.0 ? amax : 1.0);
+      P.minpiv[gw] = minpiv / (amax > 0.0 ? amax : 1.0);
       P.status[gw] = 0;
     }
+    // X^-1 = [[0, -M^-T], [M^-1, 0]] with M^-1[pinv[r]][piv[c]] = T[r][c]
+    T* Y = (T*)P.Y + I.Y_off + lw * ne * ne;
+    for (int e = tid; e < ne * ne; e += kTileThreads) {
+      const int r = e / ne, c = e - (e / ne) * ne;
+      if ((r < nh) == (c < nh)) Y[e] = T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int r = ty + kTileT * i;
+      if (r >= nh) continue;
+      const int a = L.pinv[r];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const int c = tx + kTileT * j;
+        if (c >= nh) continue;
+        const int q = L.piv[c];
+        Y[(int64_t)(nh + a) * ne + q] = (T)m[i][j];
+        Y[(int64_t)q * ne + nh + a] = (T)(-m[i][j]);
+      }
+    }
   }
+
+  // Jastrow field and RBM angles from scratch (v symmetric, W^T across threads)
   const double* V = P.V + I.V_off;
   double* h = P.h + I.h_off + lw * ns;
-  for (int l = row; l < ns; l += 64 * NW) {
+  for (int l = tid; l < ns; l += kTileThreads) {
     double s = 0.0;
 #pragma unroll 8
     for (int mm = 0; mm < ns; ++mm)
@@ -331,7 +371,7 @@ __global__ __launch_bounds__(64 * NW) void k_refresh_ap_blk(Pools P,
     const double* bb = P.rbm64 + I.rbm_b_off;
     const double* WT = P.rbmT64 + I.rbm_W_off;
     double* th = P.theta + I.theta_off + lw * I.M;
-    for (int hh = row; hh < I.M; hh += 64 * NW) {
+    for (int hh = tid; hh < I.M; hh += kTileThreads) {
       double s = bb[hh];
       for (int v = 0; v < n2; ++v) s += WT[(int64_t)v * I.M + hh] * (double)(2 * occ[v] - 1);
       th[hh] = s;
@@ -339,30 +379,29 @@ __global__ __launch_bounds__(64 * NW) void k_refresh_ap_blk(Pools P,
   }
 }
 
-__host__ __device__ inline size_t ap_blk_bytes(int NS, int NW, int max_sites) {
-  return (size_t)(NS + NW) * sizeof(double) +
-         (size_t)(2 * NS + NS + 2 * max_sites) * sizeof(int32_t);
+__host__ __device__ inline size_t tiled_bytes(int max_ne, int max_sites) {
+  return sizeof(TileLds) + (size_t)(max_ne + 2 * max_sites) * sizeof(int32_t);
 }
 }  // namespace
 
-bool refresh_ap_fits(int max_ne, int max_ns) {
-  if (max_ne <= 128)
-    return (ap_walker_bytes(64, max_ns) + ap_minv_bytes<double>(max_ne / 2 + 1)) * kApWpb <=
-           152 * 1024;
-  return max_ne <= 160 && ap_blk_bytes(80, 2, max_ns) <= 64 * 1024;
+int refresh_ap_route(int max_ne, int max_ns) {
+  if (max_ne <= 128 &&
+      (ap_walker_bytes(64, max_ns) + ap_minv_bytes<double>(max_ne / 2 + 1)) * kApWpb <= 152 * 1024)
+    return 1;
+  if (max_ne <= 2 * kTileT * 8 && tiled_bytes(max_ne, max_ns) <= 64 * 1024) return 2;
+  return 0;
 }
 
 template <typename T>
 void launch_refresh_ap(const Pools& P, const int32_t* wlist, int n, int max_ne, int max_ns,
-                       double sing_tol, int32_t* flags, hipStream_t s) {
+                       int route, double sing_tol, int32_t* flags, hipStream_t s) {
   if (n <= 0) return;
-  const int blocks = (n + kApWpb - 1) / kApWpb;
-  if (max_ne > 128) {   // up to 80 electrons per spin: two wavefronts per walker
-    const size_t sh = ap_blk_bytes(80, 2, max_ns);
-    hipLaunchKernelGGL((k_refresh_ap_blk<T, 80, 2>), dim3(n), dim3(128), sh, s, P, wlist,
-                       sing_tol, flags);
+  if (route == 2) {   // 64 < n_sigma <= 128: the tiled kernel, one workgroup per walker
+    hipLaunchKernelGGL((k_refresh_ap_tiled<T, 8>), dim3(n), dim3(kTileThreads),
+                       tiled_bytes(max_ne, max_ns), s, P, wlist, sing_tol, flags);
     return;
   }
+  const int blocks = (n + kApWpb - 1) / kApWpb;
   const int wld = max_ne / 2 + 1;
   if (max_ne <= 64) {
     const size_t sh = (ap_walker_bytes(32, max_ns) + ap_minv_bytes<T>(wld)) * kApWpb;
@@ -381,9 +420,9 @@ void launch_refresh_ap(const Pools& P, const int32_t* wlist, int n, int max_ne, 
   }
 }
 
-template void launch_refresh_ap<double>(const Pools&, const int32_t*, int, int, int, double,
+template void launch_refresh_ap<double>(const Pools&, const int32_t*, int, int, int, int, double,
                                         int32_t*, hipStream_t);
-template void launch_refresh_ap<float>(const Pools&, const int32_t*, int, int, int, double,
+template void launch_refresh_ap<float>(const Pools&, const int32_t*, int, int, int, int, double,
                                        int32_t*, hipStream_t);
 
 }  // namespace mvmc

@@ -36,9 +36,21 @@ __global__ void k_estats(SrArgs A) {
     v += d * d;
   }
   v = block_sum(v, red);
+  // standard error from the spread of the walker means (independent chains):
+  // sigma = sqrt(sum_w (m_w - E_bar)^2 / (W (W - 1)))
+  const int64_t W = I.walkers, ns = N / W;
+  double d2 = 0.0;
+  for (int64_t w = threadIdx.x; w < W; w += blockDim.x) {
+    double mw = 0.0;
+    for (int64_t s = 0; s < ns; ++s) mw += e[s * W + w];
+    const double d = mw / (double)ns - mean;
+    d2 += d * d;
+  }
+  d2 = block_sum(d2, red);
   if (threadIdx.x == 0) {
     A.scal[blockIdx.x * kScal + kEbar] = mean;
     A.scal[blockIdx.x * kScal + kEvar] = v / (double)N;
+    A.scal[blockIdx.x * kScal + kEerr] = W > 1 ? sqrt(d2 / ((double)W * (double)(W - 1))) : NAN;
   }
 }
 
@@ -76,7 +88,8 @@ __global__ void k_colpass(SrArgs A, T* __restrict__ O, int mode, uint16_t* __res
     for (int64_t m = r0; m < r1; ++m) s += (double)Ob[m * ld + k];
     part[(blockIdx.y * 3 + 0) * ld + k] = s;
   } else {
-    const double ob = A.obar[I.param_off + k];
+    // padding columns (k >= np) hold zeros and have no mean of their own
+    const double ob = k < I.np ? A.obar[I.param_off + k] : 0.0;
     const double eb = A.scal[blockIdx.z * kScal + kEbar];
     const double* e = A.eloc + I.eloc_off;
     double s2 = 0.0, sg = 0.0;

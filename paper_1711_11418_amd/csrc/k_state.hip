@@ -6,6 +6,8 @@
 //   v_ij (zero diagonal), g_i, and the RBM a, b, W copies.
 // A is kept in double and in single precision; the sweep reads the one that
 // matches its arithmetic.
+#include <algorithm>
+
 #include "launch.h"
 
 namespace mvmc {
@@ -157,6 +159,54 @@ __global__ void k_set_target(Pools P, uint64_t* __restrict__ target, int64_t W, 
 void launch_set_target(const Pools& P, uint64_t* target, int64_t W, int n_sweeps, hipStream_t s) {
   hipLaunchKernelGGL(k_set_target, dim3((unsigned)((W + 255) / 256)), dim3(256), 0, s, P, target,
                      W, n_sweeps);
+}
+
+// Index of the first non-finite entry of x[0, n) (n when every entry is
+// finite): one workgroup, a fixed-order minimum.
+__global__ void k_first_nonfinite(const double* __restrict__ x, int64_t n, int64_t* out) {
+  __shared__ int64_t red[256];
+  int64_t first = n;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
+    if (!isfinite(x[i])) {
+      first = i;
+      break;
+    }
+  red[threadIdx.x] = first;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w && red[threadIdx.x + w] < red[threadIdx.x])
+      red[threadIdx.x] = red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+void launch_first_nonfinite(const double* x, int64_t n, int64_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_first_nonfinite, dim3(1), dim3(256), 0, s, x, n, out);
+}
+
+// Walker configurations cross the C ABI as int16 spin-orbital indices
+// (2 N_s <= 2048); the walker pools keep int32.
+__global__ void k_pos_narrow(const int32_t* __restrict__ src, int16_t* __restrict__ dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (int16_t)src[i];
+}
+__global__ void k_pos_widen(const int16_t* __restrict__ src, int32_t* __restrict__ dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (int32_t)src[i];
+}
+
+void launch_pos_narrow(const int32_t* src, int16_t* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_pos_narrow, dim3(nb), dim3(256), 0, s, src, dst, n);
+}
+void launch_pos_widen(const int16_t* src, int32_t* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_pos_widen, dim3(nb), dim3(256), 0, s, src, dst, n);
 }
 
 void launch_build_empty(const Pools& P, const int32_t* wlist, int n, int max_ns, hipStream_t s) {

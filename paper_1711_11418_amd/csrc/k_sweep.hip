@@ -68,6 +68,8 @@ __global__ __launch_bounds__(NT) void k_sweep(Pools P, const int32_t* __restrict
   constexpr int NW = NT / 64;
   extern __shared__ __align__(16) unsigned char smem[];
   const int gw = wlist[blockIdx.x];
+  const int32_t guard0 = P.guard[gw];
+  if (guard0 == kGuardFailed) return;
   const uint64_t n0 = P.cnt[gw];
   const uint64_t tg = target[gw];
   uint64_t todo = tg > n0 ? tg - n0 : 0;
@@ -132,6 +134,11 @@ __global__ __launch_bounds__(NT) void k_sweep(Pools P, const int32_t* __restrict
   const T* rW = rbm_pool<T>(P) + I.rbm_W_off;
   const uint64_t tb = trace ? trace_base[gw] : 0;
   int64_t acc = 0;
+  // A ratio that is not finite stops the walker at that proposal and asks
+  // for a double refresh before it is tried again; not finite again right
+  // after that refresh, the walker stops for good (kGuardFailed).
+  int n_done = n_prop;
+  int32_t guard1 = guard0;
 
   for (int it = 0; it < n_prop; ++it) {
     const uint64_t n = n0 + (uint64_t)it;
@@ -185,6 +192,12 @@ __global__ __launch_bounds__(NT) void k_sweep(Pools P, const int32_t* __restrict
                   hs[site_old] - V[(int64_t)site_old * ns + site_new];
     if (M) logc += 2.0 * ((double)ra[Inew] - (double)ra[Iold]) + sr;
     const double R = r_pf * exp(logc);
+    if (!isfinite(R)) {   // uniform: every thread holds the same sums
+      guard1 = guard1 == kGuardPending ? kGuardFailed : kGuardPending;
+      n_done = it;
+      break;
+    }
+    guard1 = kGuardClear;
     const double u = uniform53(r.z, r.w);
     const bool accept = u < R * R;
     if (trace && tid == 0 && n - tb < (uint64_t)trace_cap) {
@@ -253,10 +266,11 @@ __global__ __launch_bounds__(NT) void k_sweep(Pools P, const int32_t* __restrict
   for (int l = tid; l < ns; l += NT) hg[l] = hs[l];
   for (int hh = tid; hh < M; hh += NT) thg[hh] = (double)ths[hh];
   if (tid == 0) {
-    const uint64_t n1 = n0 + (uint64_t)n_prop;
+    const uint64_t n1 = n0 + (uint64_t)n_done;
     P.cnt[gw] = n1;
     P.accepted[gw] += acc;
-    if (R > 0 && n1 % (uint64_t)R == 0) needs_refresh[gw] = 1;
+    if (guard1 != guard0) P.guard[gw] = guard1;
+    if ((R > 0 && n1 % (uint64_t)R == 0) || guard1 == kGuardPending) needs_refresh[gw] = 1;
   }
 }
 

@@ -242,7 +242,7 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
   __syncthreads();   // the only workgroup barrier
 
   const int gw = sgpr(wlist[blockIdx.x * WPB + wv]);
-  if (gw < 0) return;
+  if (gw < 0 || P.guard[gw] == kGuardFailed) return;
   const uint64_t n0 = P.cnt[gw];
   const uint64_t tg = target[gw];
   uint64_t todo = tg > n0 ? tg - n0 : 0;
@@ -327,16 +327,24 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
   // Philox words of the next 64 proposals, one proposal per lane: the vector
   // unit evaluates them together and each proposal reads its four words back
   uint32_t d0 = 0, d1 = 0, d2 = 0, d3 = 0;
-  for (int it = 0; it < n_prop; ++it) {
+  // A ratio that is not finite (NaN or Inf) refreshes X^-1 in double at once
+  // and the same proposal is tried again; not finite a second time, the
+  // walker stops there (guard word kGuardFailed, reported by the host).
+  bool tripped = false, failed = false;
+  int it = 0;   // proposals taken so far
+  int batch = -1;
+  while (it < n_prop) {
     const uint64_t n = n0 + (uint64_t)it;
     const int rs = it & 63;
-    if (rs == 0) {
+    if ((it >> 6) != batch) {
+      batch = it >> 6;
       const uint4 d = draw(seed, n + (uint64_t)lane, (uint32_t)gw, 0u);
       d0 = d.x;
       d1 = d.y;
       d2 = d.z;
       d3 = d.w;
     }
+    bool nonfinite = false;
     do {
     uint4 r;
     r.x = (uint32_t)__builtin_amdgcn_readlane((int)d0, rs);
@@ -385,6 +393,10 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
                   hs[site_old] - vs[site_old * ns + site_new];
     if (RBM && M) logc += 2.0 * ((double)raT[Inew] - (double)raT[Iold]) + rbm;
     const double Rt = r_pf * exp(logc);
+    if (!isfinite(Rt)) {
+      nonfinite = true;
+      break;
+    }
     const double u = uniform53(r.z, r.w);
     const int accept = sgpr(u < Rt * Rt ? 1 : 0);
     if (TRACE && lane == 0 && n - tb < (uint64_t)trace_cap) {
@@ -440,10 +452,24 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
     wave_sync();
     } while (false);
 
-    // periodic double-precision recomputation, inside the launch
+    bool do_refresh = false;
+    if (nonfinite) {
+      if (tripped) {
+        failed = true;
+        break;
+      }
+      tripped = true;
+      do_refresh = true;   // the proposal is tried again after the refresh
+    } else {
+      tripped = false;
+      ++it;
+      if (R > 0 && --to_refresh == 0) to_refresh = R;
 #if MVMC_SWEEP_INKERNEL_REFRESH
-    if (R > 0 && --to_refresh == 0) to_refresh = R;
-    if (kref && R > 0 && to_refresh == R) {
+      // periodic double-precision recomputation, inside the launch
+      do_refresh = kref && R > 0 && to_refresh == R;
+#endif
+    }
+    if (do_refresh) {
       double lp, sg;
       singular = reg_refresh_ap<NE_MAX, T>(z, posr, fs, ldf, ns, ne, lane, tab, rowp, piv, pinv,
                                            lp, sg);
@@ -470,7 +496,6 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
       wave_sync();
       if (singular) break;
     }
-#endif
   }
 
   // write the walker back (the same-spin blocks of Y stay zero in memory)
@@ -486,9 +511,10 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
   for (int l = lane; l < ns; l += 64) hg[l] = hs[l];
   for (int hh = lane; hh < M; hh += 64) thg[hh] = (double)ths[hh];
   if (lane == 0) {
-    const uint64_t n1 = n0 + (uint64_t)n_prop;
+    const uint64_t n1 = n0 + (uint64_t)it;
     P.cnt[gw] = n1;
     P.accepted[gw] += acc;
+    if (failed) P.guard[gw] = kGuardFailed;
     if (R > 0 && !kref && n1 % (uint64_t)R == 0) needs_refresh[gw] = 1;
     if (refreshed) {
       P.logpf[gw] = singular ? -INFINITY : last_logpf;

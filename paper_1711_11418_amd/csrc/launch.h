@@ -15,15 +15,22 @@ void launch_draw_configs(const Pools& P, const int32_t* wlist, int n, uint64_t s
                          uint32_t attempt, hipStream_t s);
 void launch_build_empty(const Pools& P, const int32_t* wlist, int n, int max_ns, hipStream_t s);
 void launch_set_target(const Pools& P, uint64_t* target, int64_t W, int n_sweeps, hipStream_t s);
+// int32 <-> int16 copies of the configurations (C-ABI form)
+void launch_pos_narrow(const int32_t* src, int16_t* dst, int64_t n, hipStream_t s);
+void launch_pos_widen(const int16_t* src, int32_t* dst, int64_t n, hipStream_t s);
+// *out = index of the first non-finite x[i], or n when all are finite
+void launch_first_nonfinite(const double* x, int64_t n, int64_t* out, hipStream_t s);
 
 // k_refresh.hip: full double-precision X^-1, log|Pf|, sign, Jastrow field and
 // RBM angles for the walkers in wlist.  T is the walker-matrix type.
-// Refresh through the anti-parallel block M (N_e <= 128): X^-1 and Pf(X)
-// from M^-1 and det M.
-bool refresh_ap_fits(int max_ne, int max_ns);
+// Refresh through the anti-parallel block M: X^-1 and Pf(X) from M^-1 and
+// det M.  Route for a walker set: 1 one wavefront per walker (N_e <= 128),
+// 2 a 16 x 16 thread tile per walker (N_e <= 256), 0 none (the generic skew
+// elimination of k_refresh.hip).
+int refresh_ap_route(int max_ne, int max_ns);
 template <typename T>
 void launch_refresh_ap(const Pools& P, const int32_t* wlist, int n, int max_ne, int max_ns,
-                       double sing_tol, int32_t* flags, hipStream_t s);
+                       int route, double sing_tol, int32_t* flags, hipStream_t s);
 template <typename T>
 void launch_refresh(const Pools& P, const int32_t* wlist, int n, int max_ne, int max_ns,
                     bool lds, double sing_tol, hipStream_t s);

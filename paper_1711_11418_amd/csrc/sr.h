@@ -10,11 +10,12 @@ constexpr int kRowChunk = 512;   // rows per partial of the column passes
 // per-instance scalar slots (scal[inst * kScal + slot])
 enum : int {
   kEbar = 0, kEvar = 1, kRho = 2, kRhoNew = 3, kPw = 4, kBeta = 5, kThresh = 6, kDone = 7,
-  kIters = 8, kFlag = 9, kScal = 16
+  kIters = 8, kFlag = 9, kEerr = 10, kScal = 16
 };
 
 struct SrInst {
   int64_t np, ldO, rows;          // parameters, O stride, samples used in this SR step
+  int64_t walkers;                // independent chains; sample row = slot * walkers + walker
   int64_t O_off, S_off, eloc_off, param_off;
   int64_t colpart_off, syrkpart_off, chol_off, split_off;
   int64_t split_rows;             // rows per bf16 array (multiple of 32; zero past rows)

@@ -60,16 +60,12 @@ def oracle_trajectories(inst, params, pos0: np.ndarray, gid0: int, n_prop: int, 
 
 
 def compare_trace(rec: np.ndarray, walkers, n_prop: int, seed: int, rtol: float = 1e-10,
-                  mixed: bool = False, floor: float = 1e-6) -> dict:
-    """Compare GPU trace records with oracle traces.
+                  floor: float = 1e-6) -> dict:
+    """Compare GPU trace records with oracle traces (double precision).
 
-    Ratio error is |R_gpu - R| / max(|R|, floor).  FP64: every decision
-    must match and the error stay below rtol.  Mixed (single-precision
-    inverse): the error stays below rtol with floor ~ 1e-2, because the dot
-    product of row a of X^-1 with the new row of X cancels for small R and
-    its single-precision error is absolute; a differing decision is allowed
-    only when u lies within the ratio error of R^2, after which that chain
-    is no longer compared.
+    Ratio error is |R_gpu - R| / max(|R|, floor); every decision must match
+    and the error stay below rtol.  (Single-precision traces are compared by
+    mixed_ratio_stats against their rounding bound.)
     """
     n_cmp = 0
     worst = 0.0
@@ -89,17 +85,121 @@ def compare_trace(rec: np.ndarray, walkers, n_prop: int, seed: int, rtol: float 
             assert err <= rtol, (w, k, float(g["ratio"]), R, err)
             n_cmp += 1
             if bool(g["accepted"]) != acc:
-                if not mixed:
-                    raise AssertionError(f"walker {w} proposal {k}: decision differs")
-                r = proposal_draw(seed, wk.gid, n)
-                u = uniform53(r[2], r[3])
-                dR = abs(float(g["ratio"]) - R)
-                assert abs(u - R * R) <= 2.5 * dR * (abs(R) + dR) + 1e-15, (w, k, u, R)
-                diverged += 1
-                break
+                raise AssertionError(f"walker {w} proposal {k}: decision differs")
     return {"compared": n_cmp, "worst_rel": worst, "diverged": diverged, "errors": errors}
 
 
 def oracle_measure(inst, m, pos):
     A = wf.skew_table(m)
     return measure.local_energy(m, pos, A), measure.log_derivs(inst, m, pos, A)
+
+
+U32 = 2.0 ** -24   # unit roundoff of binary32
+
+
+def mixed_ratio_stats(inst, m, rec, walkers, pos0, n_prop: int, seed: int, refresh_every: int,
+                      safety: float = 2.0) -> dict:
+    """Single-precision ratios against the oracle, proposal by proposal, with
+    a first-order forward error bound carried along the oracle's chain.
+
+    Let Y be the exact X^-1 of the current configuration and E the error of
+    the single-precision copy the kernel holds (Frobenius norm bounded by e).
+    A double refresh leaves e = u |Y|_F (one rounding, u = 2^-24).  For a
+    proposal moving electron a to I' with x' the new row of X (x'_a = 0):
+
+      r_Pf = x'.Y[:, a]:  |dr| <= |x'| e + (2 + ceil(n/64)) u sum_b |x'_b Y_ba|
+      (E, the rounding of x' and of each product; partial sums of at most
+      ceil(n/64) terms in single precision, the rest in double);
+      RBM log-ratio in single precision: |dlog| <= sum_h [2 dth_h +
+      2u(|theta_h + d_h| + 1) + 2u(|theta_h| + 1) + u |d_h|], d_h the angle
+      change and dth_h the drift bound of the single-precision angle;
+      |dR| <= e^(dlog_c) |dr| + |R| |dlog|.
+
+    An accepted update Y' = Y + (p q^T - q p^T)/r with p = Y[:, a] and
+    q = -Y^T x' + e_a propagates the error to first order as
+      e' <= e + 2(e |q| + |p| |dq|)/|r| + 2 |p| |q| |dr| / r^2
+            + 3u (|Y'|_F + 2 |p| |q| / |r|)
+    with |dq| <= |x'| e + n u | |Y|^T |x'| | (single-precision sums of n
+    terms), and each angle drifts by u(|theta_h| + 2|d_h|).  The test bar is
+    |R_gpu - R| <= safety * bound (first order: second-order terms are
+    neglected).  A differing decision is allowed only when u lies within the
+    bound of R^2; that chain is then no longer compared."""
+    from oracle.philox import proposal_draw, uniform53
+    A = wf.skew_table(m)
+    ns = m.n_sites
+    ne = m.n_elec
+    n_dot = ne // 2
+    rel, over, ks = [], [], []
+    diverged = 0
+    ok = True
+    for w, wk in enumerate(walkers):
+        pos = np.array(pos0[w], dtype=np.int64)
+        lc = wf.log_correlators(m, pos)
+        Y = np.linalg.inv(A[np.ix_(pos, pos)])
+        e = 0.0
+        dth = np.zeros(m.n_hidden)
+        k_acc = 0
+        for k in range(n_prop):
+            n, a, inew, R, acc = wk.trace[k]
+            g = rec[w, k]
+            assert int(g["n"]) == n and int(g["a"]) == a and int(g["i_new"]) == inew, (w, k)
+            nv = wf.occupations(m, pos)
+            theta = m.b + m.W @ (2.0 * nv - 1.0) if m.n_hidden else np.zeros(0)
+            if k == 0 or (refresh_every and n % refresh_every == 0):
+                e = U32 * np.linalg.norm(Y)
+                dth = U32 * np.abs(theta)
+                k_acc = 0
+            if inew < 0:
+                continue
+            new = pos.copy()
+            new[a] = inew
+            xr = A[inew, pos].copy()
+            xr[a] = 0.0
+            lc_new = wf.log_correlators(m, new)
+            corr = np.exp(lc_new - lc)
+            col = Y[:, a]
+            r = float(xr @ col)
+            kd = float(np.sum(np.abs(xr * col)))
+            nx = np.linalg.norm(xr)
+            dr = nx * e + (2 + -(-n_dot // 64)) * U32 * kd
+            dlog = 0.0
+            d = np.zeros(0)
+            if m.n_hidden:
+                d = 2.0 * (m.W[:, inew] - m.W[:, int(pos[a])])
+                dlog = float(np.sum(2 * dth + 2 * U32 * (np.abs(theta + d) + 1)
+                                    + 2 * U32 * (np.abs(theta) + 1) + U32 * np.abs(d)))
+            bound = safety * (corr * dr + abs(R) * dlog) + 1e-300
+            err = abs(float(g["ratio"]) - R)
+            rel.append(err / max(abs(R), 1e-300))
+            over.append(err / bound)
+            ks.append(k_acc)
+            if err > bound:
+                ok = False
+            if bool(g["accepted"]) != acc:
+                rr = proposal_draw(seed, wk.gid, n)
+                u = uniform53(rr[2], rr[3])
+                if abs(u - R * R) > 2.5 * bound * (abs(R) + bound) + 1e-15:
+                    ok = False
+                diverged += 1
+                break
+            if acc:
+                q = -(Y.T @ xr)
+                q[a] += 1.0
+                npv, nq = np.linalg.norm(col), np.linalg.norm(q)
+                dq = nx * e + n_dot * U32 * np.linalg.norm(np.abs(Y).T @ np.abs(xr))
+                pos = new
+                lc = lc_new
+                Y = np.linalg.inv(A[np.ix_(pos, pos)])
+                e = (e + 2 * (e * nq + npv * dq) / abs(r) + 2 * npv * nq * dr / r ** 2
+                     + 3 * U32 * (np.linalg.norm(Y) + 2 * npv * nq / abs(r)))
+                if m.n_hidden:
+                    dth = dth + U32 * (np.abs(theta) + 2 * np.abs(d))
+                k_acc += 1
+    rel = np.array(rel)
+    over = np.array(over)
+    ks = np.array(ks)
+    summary = (f"compared {len(rel)}, error/bound max {over.max():.3f} median "
+               f"{np.median(over):.2e}; rel err median {np.median(rel):.2e} p99 "
+               f"{np.percentile(rel, 99):.2e} max {rel.max():.2e}; diverged chains {diverged}")
+    return {"within_bound": ok, "summary": summary, "over": over, "rel": rel, "k": ks,
+            "compared": len(rel), "diverged": diverged}

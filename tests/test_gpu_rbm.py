@@ -31,7 +31,7 @@ def _train(inst, wl, solver):
         for s in range(sweeps):
             ctx.sample_async(1)
             ctx.measure(s)
-        E, _ = ctx.build_sr(sweeps)
+        E, _, _ = ctx.build_sr(sweeps)
         hist.append(float(E[0]))
         if it % 20 == 0:
             log(f"  {inst.name} SR step {it}: E_mc = {hist[-1]:.5f}")
