@@ -95,7 +95,10 @@ typedef struct {
   int32_t n_slots;            /* sample slots per SR step: rows of O per walker */
   int32_t solver;             /* MVMC_SOLVE_CHOL reserves the double factor; CG does not */
   int32_t build_s;            /* 1 = explicit S is built (reserves its scratch); 0 = CG only */
-  int32_t sweep_threads;      /* 0 = automatic, else 64, 128 or 256 threads per walker */
+  int32_t sweep_threads;      /* 0 = automatic, else 64, 128 or 256 threads per walker of
+                                 the kernels that keep the full X^-1 (LDS, else HBM) */
+  int32_t sweep_variant;      /* 0 = automatic; 1 + v forces sweep variant v (below) for
+                                 every instance (MVMC_E_SHAPE where it does not fit) */
 } mvmc_config;
 
 /* Sizes of the caller-owned buffers for a configuration. */
@@ -176,16 +179,21 @@ int mvmc_init_wavefunction(mvmc_ctx **out, const mvmc_config *cfg, void *d_works
  */
 int mvmc_sample_sweeps(mvmc_ctx *ctx, int32_t n_sweeps, int64_t *h_accepted);
 
-/* Sweep kernel variants (same arithmetic as mvmc_sample_sweeps, different
- * residency of X^-1): 0 registers (one wavefront per walker, N_e <= 64),
- * 1-3 LDS with 64/128/256 threads per walker, 4-6 HBM with 64/128/256. */
-enum { MVMC_N_SWEEP_VARIANTS = 7 };
+/* Sweep kernel variants (same proposals and decisions, different residency
+ * of X^-1): 0 registers (one wavefront per walker, N_e <= 64), 1-3 the full
+ * X^-1 in LDS with 64/128/256 threads per walker, 4-6 the full X^-1 in HBM
+ * with 64/128/256, 7-9 the anti-parallel block alone (M^-1, n x n with
+ * n = N_e/2, Eq. AP-Pf) in LDS with 64/128/256 threads: rank-1
+ * Sherman-Morrison updates of M^-1 (a quarter of the state of 1-6).
+ * Automatic choice: 0 where it fits, else 7-9 (threads by n), else 6. */
+enum { MVMC_N_SWEEP_VARIANTS = 10 };
 
 /*
  * Autotuner for the ragged batch (section 3.1.2 sweeps, any mix of lattice
  * sizes): times n_sweeps >= 1 sweeps of every instance with each variant
- * that fits it (register tier, LDS kernel at three thread counts, HBM
- * kernel), the refresh launches between LDS rounds included, and keeps the
+ * that fits it (register tier; full-X^-1 kernel in LDS or HBM and
+ * anti-parallel-block kernel, each at three thread counts), the refresh
+ * launches between launches included, and keeps the
  * fastest per instance for all later calls.  The timed sweeps advance the
  * chains exactly like mvmc_sample_sweeps (they count as warm-up); the
  * accepted counters are cleared at the end.  cache_path (may be NULL): text

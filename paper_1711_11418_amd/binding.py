@@ -25,8 +25,9 @@ ENTRY_POINTS = (
     "mvmc_autotune", "mvmc_sweep_variants", "mvmc_s_tiles", "mvmc_set_s_tile",
     "mvmc_peak_probe_bytes", "mvmc_peak_probe",
 )
-N_SWEEP_VARIANTS = 7
-SWEEP_VARIANT_NAMES = ("reg", "lds64", "lds128", "lds256", "hbm64", "hbm128", "hbm256")
+N_SWEEP_VARIANTS = 10
+SWEEP_VARIANT_NAMES = ("reg", "lds64", "lds128", "lds256", "hbm64", "hbm128", "hbm256",
+                       "ap64", "ap128", "ap256")
 
 
 class InstanceDesc(C.Structure):
@@ -46,7 +47,7 @@ class Config(C.Structure):
         ("precision", C.c_int32), ("refresh_every", C.c_int32), ("seed", C.c_uint64),
         ("n_instances", C.c_int32), ("inst", C.POINTER(InstanceDesc)),
         ("n_slots", C.c_int32), ("solver", C.c_int32), ("build_s", C.c_int32),
-        ("sweep_threads", C.c_int32),
+        ("sweep_threads", C.c_int32), ("sweep_variant", C.c_int32),
     ]
 
 
@@ -167,13 +168,16 @@ class _Desc:
 
 
 def make_config(instances, precision="fp64", refresh_every=0, seed=1, n_slots=1, solver="chol",
-                build_s=True, sweep_threads=0):
+                build_s=True, sweep_threads=0, sweep_variant=None):
+    """sweep_variant: None (automatic) or a name of SWEEP_VARIANT_NAMES forced for
+    every instance."""
     descs = [_Desc(i) for i in instances]
     arr = (InstanceDesc * len(descs))(*[d.desc for d in descs])
     cfg = Config(MVMC_FP64 if precision == "fp64" else MVMC_MIXED, int(refresh_every),
                  int(seed), len(descs), C.cast(arr, C.POINTER(InstanceDesc)), int(n_slots),
                  MVMC_SOLVE_CHOL if solver == "chol" else MVMC_SOLVE_CG, int(bool(build_s)),
-                 int(sweep_threads))
+                 int(sweep_threads),
+                 0 if sweep_variant is None else 1 + SWEEP_VARIANT_NAMES.index(sweep_variant))
     cfg._keep = (descs, arr)   # keep host arrays alive
     return cfg
 
@@ -200,8 +204,8 @@ class MVMC:
     """One library context plus the torch buffers it works on."""
 
     def __init__(self, instances, params, *, precision="fp64", refresh_every=0, seed=1,
-                 n_slots=1, solver="chol", build_s=True, sweep_threads=0, device="cuda:0",
-                 stream=None):
+                 n_slots=1, solver="chol", build_s=True, sweep_threads=0, sweep_variant=None,
+                 device="cuda:0", stream=None):
         """stream: torch.cuda.Stream for all of the context's work (default: the
         current stream).  A non-default stream is needed for graph capture."""
         import torch
@@ -211,7 +215,7 @@ class MVMC:
         self.instances = list(instances)
         self.precision = precision
         self.cfg = make_config(self.instances, precision, refresh_every, seed, n_slots, solver,
-                               build_s, sweep_threads)
+                               build_s, sweep_threads, sweep_variant)
         self.sizes = query_sizes(self.cfg)
         self.layouts = [query_layout(self.cfg, k) for k in range(len(self.instances))]
         self.n_inst = len(self.instances)

@@ -43,6 +43,8 @@ struct Plan {
   std::vector<SrInst> sr;
   std::vector<int> reg_class;     // register-sweep tier per instance (0 = LDS/HBM kernel)
   std::vector<int> sweep_nt;      // threads of the LDS/HBM sweep kernel per instance
+  std::vector<char> sweep_ap;     // 1 = anti-parallel-block sweep (M^-1 alone in LDS)
+  int bad_variant = -1;           // instance a forced sweep variant does not fit
   // pools (byte offsets into the workspace)
   Pool inst_p, srinst_p, walker_inst, lists, A64, A32, V, fidx, vidx, G, U, gidx, nbr_ptr,
       nbr_site, nbr_t, fm_ptr, fm, gm_ptr, gm, vm_ptr, vm, rbm64, rbm32, rbmT64, rbmT32, Y, Y64,
@@ -139,6 +141,8 @@ Err validate(const mvmc_config* c) {
   if (c->sweep_threads && c->sweep_threads != 64 && c->sweep_threads != 128 &&
       c->sweep_threads != 256)
     return fail(MVMC_E_ARG, "sweep_threads must be 0, 64, 128 or 256");
+  if (c->sweep_variant < 0 || c->sweep_variant > MVMC_N_SWEEP_VARIANTS)
+    return fail(MVMC_E_ARG, "sweep_variant must be 0 (automatic) or 1 + a variant");
   for (int k = 0; k < c->n_instances; ++k) {
     const mvmc_instance_desc& d = c->inst[k];
     const int ns = d.n_sites;
@@ -194,6 +198,48 @@ int64_t v_members(const mvmc_instance_desc& d) {
   return m;
 }
 
+// Sweep variant of instance k: 0 register tier, 1-3 LDS kernel with
+// 64/128/256 threads, 4-6 HBM kernel with 64/128/256 threads (both keep the
+// full X^-1), 7-9 anti-parallel-block kernel (M^-1 alone in LDS) with
+// 64/128/256 threads.
+bool variant_fits(const Plan& P, int k, int v) {
+  const InstDev& I = P.inst[k];
+  if (v == 0) {
+    const int rc = sweep_reg_class(I.ne, P.tsize);
+    return rc && sweep_reg_lds_bytes(rc, I.ns, I.M, P.tsize, kRegWpb) <= kLdsLimit;
+  }
+  const int nt = 64 << ((v - 1) % 3);
+  if (v >= 7) return sweep_ap_lds_bytes(I.ne, I.ns, I.M, P.tsize, nt) <= kLdsLimit;
+  return sweep_lds_bytes(I.ne, I.ns, I.M, v <= 3, P.tsize, nt) <= kLdsLimit;
+}
+int variant_of(const Plan& P, int k) {
+  if (P.reg_class[k]) return 0;
+  const int nt = P.sweep_nt[k];
+  const int base = P.sweep_ap[k] ? 7 : (P.inst[k].sweep_lds ? 1 : 4);
+  return base + (nt == 64 ? 0 : (nt == 128 ? 1 : 2));
+}
+void set_variant(Plan& P, int k, int v) {
+  InstDev& I = P.inst[k];
+  if (v == 0) {
+    P.reg_class[k] = sweep_reg_class(I.ne, P.tsize);
+    P.sweep_ap[k] = 0;
+    return;
+  }
+  P.reg_class[k] = 0;
+  P.sweep_nt[k] = 64 << ((v - 1) % 3);
+  P.sweep_ap[k] = v >= 7;
+  I.sweep_lds = v >= 1 && v <= 3;
+}
+// Default: the register tier where it fits, else the anti-parallel-block
+// kernel (threads by the block side n), else the full-X^-1 kernel from HBM.
+int default_variant(const Plan& P, int k) {
+  if (variant_fits(P, k, 0)) return 0;
+  const int n = P.inst[k].ne / 2;
+  const int v = 7 + (n <= 48 ? 0 : (n <= 96 ? 1 : 2));
+  if (variant_fits(P, k, v)) return v;
+  return 6;
+}
+
 Plan make_plan(const mvmc_config& c) {
   Plan P;
   P.tsize = c.precision == MVMC_FP64 ? 8 : 4;
@@ -202,6 +248,7 @@ Plan make_plan(const mvmc_config& c) {
   P.sr.resize(n);
   P.reg_class.assign(n, 0);
   P.sweep_nt.assign(n, 256);
+  P.sweep_ap.assign(n, 0);
   int64_t off_A = 0, off_V = 0, off_site = 0, off_nptr = 0, off_nbr = 0, off_fm_ptr = 0,
           off_fm = 0, off_gm_ptr = 0, off_gm = 0, off_vm_ptr = 0, off_vm = 0, off_rbm = 0,
           off_Y = 0, off_pos = 0, off_empty = 0, off_h = 0, off_theta = 0, off_chol = 0,
@@ -233,10 +280,11 @@ Plan make_plan(const mvmc_config& c) {
     const int nt = sweep_threads_for(c, I.ne);
     P.sweep_nt[k] = nt;
     I.sweep_lds = sweep_lds_bytes(I.ne, I.ns, I.M, true, P.tsize, nt) <= kLdsLimit;
-    if (c.sweep_threads == 0) {
-      const int rc = sweep_reg_class(I.ne, P.tsize);
-      if (rc && sweep_reg_lds_bytes(rc, I.ns, I.M, P.tsize, kRegWpb) <= kLdsLimit)
-        P.reg_class[k] = rc;
+    if (c.sweep_variant > 0) {   // forced variant
+      if (variant_fits(P, k, c.sweep_variant - 1)) set_variant(P, k, c.sweep_variant - 1);
+      else if (P.bad_variant < 0) P.bad_variant = k;
+    } else if (c.sweep_threads == 0) {
+      set_variant(P, k, default_variant(P, k));
     }
     I.refresh_lds = refresh_lds_bytes(I.ne, I.ns, true) <= kLdsLimit;
     if (!I.refresh_lds) P.need_Y64 = true;
@@ -456,6 +504,7 @@ struct Bucket {
   int n = 0, max_ne = 0, max_ns = 0, max_M = 0, nthreads = 256;
   bool lds = true;
   int reg = 0;       // register-sweep tier (n = number of walker groups) or 0
+  bool ap = false;   // anti-parallel-block sweep kernel
   int inst = -1;     // the one instance of the bucket (autotuning), else -1
 };
 
@@ -578,10 +627,11 @@ void build_buckets(mvmc_ctx* c, bool per_instance = false) {
       continue;
     }
     const int nt = P.sweep_nt[k];
-    size_t sb = sweep_lds_bytes(I.ne, I.ns, I.M, I.sweep_lds, P.tsize, nt);
+    size_t sb = P.sweep_ap[k] ? sweep_ap_lds_bytes(I.ne, I.ns, I.M, P.tsize, nt)
+                              : sweep_lds_bytes(I.ne, I.ns, I.M, I.sweep_lds, P.tsize, nt);
     size_t cls = 4096;
     while (cls < sb) cls <<= 1;
-    sweep_groups[{I.sweep_lds, cls, nt, own}].push_back(k);
+    sweep_groups[{P.sweep_ap[k] ? 2 : (int)I.sweep_lds, cls, nt, own}].push_back(k);
   }
   std::vector<int32_t> lists;
   // register tiers: each instance's walkers in groups of kRegWpb, padded with -1
@@ -607,7 +657,8 @@ void build_buckets(mvmc_ctx* c, bool per_instance = false) {
                   std::vector<Bucket>& out) {
     for (auto& g : groups) {
       Bucket b;
-      b.lds = std::get<0>(g.first);
+      b.lds = std::get<0>(g.first) != 0;
+      b.ap = &out == &c->sweep_b && std::get<0>(g.first) == 2;
       b.nthreads = std::get<2>(g.first);
       b.inst = std::get<3>(g.first);
       b.list_off = lists.size() * 4;
@@ -751,6 +802,7 @@ int mvmc_query_sizes(const mvmc_config* cfg, mvmc_sizes* out) {
   if (e.code) return e.code;
   if (!out) return MVMC_E_ARG;
   Plan P = make_plan(*cfg);
+  if (P.bad_variant >= 0) return MVMC_E_SHAPE;
   out->n_walkers = P.W;
   out->n_params = P.np;
   out->eloc_elems = P.eloc;
@@ -801,6 +853,10 @@ int mvmc_init_wavefunction(mvmc_ctx** out, const mvmc_config* cfg, void* d_ws, s
   c->desc.assign(cfg->inst, cfg->inst + cfg->n_instances);
   c->cfg.inst = c->desc.data();
   c->plan = make_plan(c->cfg);
+  if (c->plan.bad_variant >= 0) {
+    delete c;
+    return MVMC_E_SHAPE;
+  }
   if (ws_bytes < c->plan.total) {
     delete c;
     return MVMC_E_WORKSPACE;
@@ -1071,6 +1127,18 @@ int run_sweeps(mvmc_ctx* c, int32_t n_sweeps, std::vector<double>* inst_ms) {
         continue;
       }
       const int e = t0(b.inst);
+      if (b.ap) {
+        if (c->cfg.precision == MVMC_FP64)
+          launch_sweep_ap<double>(c->P, lst, b.n, (int)std::min<int64_t>(cap, INT32_MAX),
+                                  c->cfg.seed, b.max_ne, b.max_ns, b.max_M, b.nthreads, c->trace,
+                                  c->trace_cap, tb, tgt, nr, R, c->stream);
+        else
+          launch_sweep_ap<float>(c->P, lst, b.n, (int)std::min<int64_t>(cap, INT32_MAX),
+                                 c->cfg.seed, b.max_ne, b.max_ns, b.max_M, b.nthreads, c->trace,
+                                 c->trace_cap, tb, tgt, nr, R, c->stream);
+        t1(e);
+        continue;
+      }
       if (c->cfg.precision == MVMC_FP64)
         launch_sweep<double>(c->P, lst, b.n, (int)std::min<int64_t>(cap, INT32_MAX), c->cfg.seed,
                              b.max_ne, b.max_ns, b.max_M, b.lds, b.nthreads, c->trace,
@@ -1137,33 +1205,6 @@ int mvmc_sample_sweeps(mvmc_ctx* c, int32_t n_sweeps, int64_t* h_accepted) {
     return check_guard(c);
   }
   return MVMC_OK;
-}
-
-// Sweep variant of instance k: 0 register tier, 1-3 LDS kernel with
-// 64/128/256 threads, 4-6 HBM kernel with 64/128/256 threads.
-static bool variant_fits(const Plan& P, int k, int v) {
-  const InstDev& I = P.inst[k];
-  if (v == 0) {
-    const int rc = sweep_reg_class(I.ne, P.tsize);
-    return rc && sweep_reg_lds_bytes(rc, I.ns, I.M, P.tsize, kRegWpb) <= kLdsLimit;
-  }
-  const int nt = 64 << ((v - 1) % 3);
-  return sweep_lds_bytes(I.ne, I.ns, I.M, v <= 3, P.tsize, nt) <= kLdsLimit;
-}
-static int variant_of(const Plan& P, int k) {
-  if (P.reg_class[k]) return 0;
-  const int nt = P.sweep_nt[k];
-  return (P.inst[k].sweep_lds ? 1 : 4) + (nt == 64 ? 0 : (nt == 128 ? 1 : 2));
-}
-static void set_variant(Plan& P, int k, int v) {
-  InstDev& I = P.inst[k];
-  if (v == 0) {
-    P.reg_class[k] = sweep_reg_class(I.ne, P.tsize);
-    return;
-  }
-  P.reg_class[k] = 0;
-  P.sweep_nt[k] = 64 << ((v - 1) % 3);
-  I.sweep_lds = v <= 3;
 }
 
 int mvmc_autotune(mvmc_ctx* c, int32_t n_sweeps, const char* cache_path, double* h_ms) {

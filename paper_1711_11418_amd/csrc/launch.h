@@ -50,6 +50,15 @@ void launch_sweep(const Pools& P, const int32_t* wlist, int n, int cap, uint64_t
                   const uint64_t* target, int32_t* needs_refresh, int R, hipStream_t s);
 size_t sweep_lds_bytes(int ne, int ns, int M, bool lds, size_t tsize, int nthreads);
 
+// k_sweep_ap.hip: the same proposals with only M^-1 (the anti-parallel block
+// of X^-1) resident in LDS, rank-1 updates.
+template <typename T>
+void launch_sweep_ap(const Pools& P, const int32_t* wlist, int n, int cap, uint64_t seed,
+                     int max_ne, int max_ns, int max_M, int nthreads, TraceRec* trace,
+                     int64_t trace_cap, const uint64_t* trace_base, const uint64_t* target,
+                     int32_t* needs_refresh, int R, hipStream_t s);
+size_t sweep_ap_lds_bytes(int ne, int ns, int M, size_t tsize, int nthreads);
+
 // k_sweep_reg.hip: register-resident sweep, one wavefront per walker, groups
 // of 4 walkers of one instance per workgroup (wlist padded with -1).
 // Returns false when ne_max has no instantiation.

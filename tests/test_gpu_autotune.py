@@ -72,9 +72,10 @@ def test_autotune_ragged_batch_replay(tmp_path):
     ctx2.close()
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7, 8, 9])
 def test_forced_variant_replay(tmp_path, variant):
-    """Every LDS and HBM sweep variant, pinned through a cache line, replays
+    """Every LDS, HBM and anti-parallel-block sweep variant, pinned through a
+    cache line, replays
     the oracle's chain (FP64, 1e-10) and keeps the inverse equal to inv(X):
     N_e = 72 on the 8x8 lattice, with in-launch refresh stops."""
     from paper_1711_11418_amd import MVMC

@@ -127,6 +127,52 @@ def test_replay_wide_hbm_rbm_mixed():
     ctx.close()
 
 
+@pytest.mark.parametrize("precision,threads", [("fp64", 256), ("fp64", 128), ("mixed", 256)])
+def test_replay_wide_ap_block_rbm(precision, threads):
+    """The anti-parallel-block sweep (M^-1 alone in LDS, rank-1 updates) at
+    N_e = 224 with M = 64 hidden units: one sweep of two walkers, a double
+    refresh every 100 (double) or 32 (single precision) proposals; ratios
+    to 1e-10 in double, against the rounding bound in single precision; the
+    inverse written back equals inv(X) and E_loc, O_k follow from it."""
+    inst = square_case(16, 112, 2, full_f=False, n_hidden=64)
+    pos0 = good_configs(inst, inst.params0, inst.n_walkers, 7)
+    n_prop = inst.n_elec
+    R = 100 if precision == "fp64" else 32
+    variant = f"ap{threads}"
+    log(f"[replay-ap] 16x16 Ne=224 M=64 W=2 proposals={n_prop} {precision} {variant} "
+        f"refresh {R} seed={SEED}")
+    ctx = _ctx([inst], inst.params0, seed=SEED, precision=precision, refresh_every=R,
+               sweep_variant=variant, build_s=False, solver="cg")
+    assert ctx.sweep_variants() == [variant]
+    ctx.set_state(pos0.ravel(), np.zeros(inst.n_walkers, dtype=np.int64))
+    ctx.enable_trace(n_prop)
+    acc = ctx.sample(1)
+    rec = ctx.trace_records()
+    walkers, m = oracle_trajectories(inst, inst.params0, pos0, 0, n_prop, SEED)
+    if precision == "mixed":
+        st = mixed_ratio_stats(inst, m, rec, walkers, pos0, n_prop, SEED, refresh_every=R)
+        log(f"  mixed ap: {st['summary']}")
+        assert st["within_bound"], st["summary"]
+        ctx.close()
+        return
+    st = compare_trace(rec, walkers, n_prop, SEED, rtol=1e-10)
+    log(f"  compared {st['compared']} ratios, worst rel err {st['worst_rel']:.2e}, accepted {acc}")
+    pos = ctx.pos_of(ctx.get_state()[0], 0).cpu().numpy()
+    assert np.array_equal(pos, np.array([wk.pos for wk in walkers]))
+    Y = ctx.Y_of(ctx.get_inverse(), 0).cpu().numpy()
+    A = wf.skew_table(m)
+    for w in range(inst.n_walkers):
+        Yr = np.linalg.inv(A[np.ix_(pos[w], pos[w])])
+        assert np.max(np.abs(Y[w] - Yr)) <= 1e-9 * np.max(np.abs(Yr)), w
+    if threads == 256:
+        ctx.measure(0)
+        el = ctx.eloc_of(0, 1).cpu().numpy()
+        e_ref, o_ref = oracle_measure(inst, m, pos[1])
+        assert el[1] == pytest.approx(e_ref, rel=1e-10, abs=1e-10)
+        assert np.allclose(ctx.O_of(0, 1).cpu().numpy()[1], o_ref, rtol=1e-9, atol=1e-10)
+    ctx.close()
+
+
 @pytest.mark.parametrize("name", ["sq6_rbm", "sq10_full"])
 def test_measure_single_precision(name):
     """E_loc and O_k of the single-precision path at configurations loaded
