@@ -1,19 +1,24 @@
 """Benchmark of the many-variable VMC hot path on one MI355X.
 
-A step is one SR iteration of the 8x8 periodic Hubbard model (U = 4,
-N_e = 64, 2x2-sublattice pair amplitudes + distance Jastrow + Gutzwiller,
-N_p = 271): 1024 walkers x 200 sweeps (64 proposals each) with the local
-energy and O_k measured after every sweep, then the SR statistics, the S
-build, the Cholesky solve, the parameter update and the full refresh of
-every walker.  Inputs are seeded and synthetic and resident in HBM before
-timing starts.
+A step is one SR iteration of the 10x10 periodic Hubbard model (U = 8,
+N_e = 100, unconstrained pair amplitudes f_ij: N_p = 10002): 4096 walkers x
+10 sweeps (100 proposals each), the local energy and O_k of every walker
+after the last sweep, then the SR statistics, the S build, the Cholesky
+solve, the parameter update and the full double refresh of every walker.
+The headline runs every step in double precision (refresh every 4 sweeps,
+S on the FP64 matrix cores); the same steps in mixed precision
+(single-precision sweeps and O, double refresh every 32 proposals,
+split-bf16 S with FP32 accumulation, double solve) are reported beside it
+with the error of every mixed result against the double path.  Inputs are
+seeded and synthetic and resident in HBM before timing starts.
 
 Printed: one JSON line with the walker hop-update rate (proposals/s) over
-whole steps, the S-build rate, the roofline of the sweep kernel, the
-mixed-precision run of the same workload, the split-bf16 S build at the
-4096 x 10^4 shape, and the CPU oracle timed on the host.
+whole steps, the S-build rates, the roofline of the dominant kernel, the
+mixed-precision run, per-result precision errors, the 8x8, 16x16-RBM and
+32-cluster workloads, and the CPU oracle timed on the host.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu] [--skip-legs]
+    python bench.py --rbm-gain [--sr-steps K]   # 16x16 PJ vs PJ x RBM training
 """
 from __future__ import annotations
 
@@ -29,9 +34,15 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 BF16_PEAK_TFLOPS = 2500.0
-TRAFFIC_SUMMARY = "sweep_reg_fp64_c2_sq8_traffic.txt"
-TRAFFIC_SOURCES = ("k_sweep_reg.hip", "common.h", "ap_block.h", "wave.h")   # the sweep kernel and its headers
 METRIC = "walker hop-updates/s + SR S-build TFLOP/s, batched/mixed vs plain FP64"
+HEADLINE = "sq10_u8"
+FP64_REFRESH = 400      # proposals between double refreshes on the double path (4 sweeps)
+MIXED_REFRESH = 32      # proposals between double refreshes on the mixed path
+KINDS = ["sweep", "refresh", "measure", "sr_stats", "s_build", "sr_solve"]
+# the dominant kernel of the headline step and the committed counter summary
+# of its HBM traffic (bench reports traffic = null once its sources change)
+TRAFFIC_SUMMARY = "sweep_ap_fp64_sq10_traffic.txt"
+TRAFFIC_SOURCES = ("k_sweep_ap.hip", "common.h", "launch.h")
 
 
 def log(msg):
@@ -41,10 +52,10 @@ def log(msg):
 def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", sweep_threads=0,
                     use_graph=True, autotune=False, build_s=True, cg_tol=1e-10, cg_maxit=1000):
     """Time whole SR steps of every instance of the workload.  With use_graph
-    the sampling part of a step (the sweeps and the measurement after each
-    of them) is captured once into a HIP graph and replayed; the SR build and
-    update run eagerly.  With autotune the sweep variant of every instance is
-    chosen by timing after the warm-up."""
+    the sampling part of a step (the sweeps and the measurements) is captured
+    once into a HIP graph and replayed; the SR build and update run eagerly.
+    With autotune the sweep variant of every instance is chosen by timing
+    after the warm-up."""
     import numpy as np
     import torch
 
@@ -79,9 +90,7 @@ def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", 
                 ctx.measure(s)
             return acc
 
-        escalations = []
-
-        cg_iters = []
+        escalations, cg_iters, errs = [], [], []
 
         def sr():
             E, Er, V = ctx.build_sr(slots, with_S=build_s)
@@ -91,6 +100,7 @@ def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", 
                 escalations.append(int(np.max(it)))
             else:
                 cg_iters.append(int(np.max(it)))
+            errs.append([float(e) for e in Er])
             return [float(e) for e in E]
 
         for _ in range(warmup):
@@ -117,6 +127,7 @@ def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", 
         accepted = sampling(profile=True)
         sr()
         ms, calls = ctx.timing(False)
+        variants = ctx.sweep_variants()
         torch.cuda.synchronize()
         ctx.close()
     per_sweep = sum(i.n_walkers * i.n_elec for i in insts)
@@ -126,238 +137,225 @@ def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", 
         "seconds": dt, "proposals": proposals, "rate": proposals / dt,
         "ms_per_step": 1e3 * dt / steps,
         "energies": [e[0] for e in energies] if len(insts) == 1 else energies,
+        "energy_errors": [e[0] for e in errs[warmup:]] if len(insts) == 1 else errs[warmup:],
         "accept_ratio": accepted / (sweeps * per_sweep), "kernel_ms": ms.tolist(),
         "kernel_calls": calls.tolist(), "W": i0.n_walkers, "ne": i0.n_elec, "np": i0.n_params,
-        "sweeps": sweeps, "N": slots * i0.n_walkers, "graph": graph is not None,
-        "autotune": tuned, "cholesky_shift_raises": escalations, "cg_iterations": cg_iters,
-        "steps": steps,
+        "ns": i0.n_sites, "sweeps": sweeps, "N": slots * i0.n_walkers, "graph": graph is not None,
+        "autotune": tuned, "variants": variants, "cholesky_shift_raises": escalations,
+        "cg_iterations": cg_iters, "steps": steps,
     }
 
 
-def measure_hbm_model(r, wsize):
-    """E_loc and O_k: every sample reads Y once (N_e^2 w) and writes its O row
-    (N_p w); modelled rate over the measurement time of one SR step."""
-    ne, npar = r["ne"], r["np"]
-    bytes_ = r["N"] * (ne * ne + npar) * wsize
-    ms = r["kernel_ms"][2]
-    gbs = bytes_ / (ms * 1e-3) / 1e9
-    return {"alg_bytes_per_step": bytes_, "ms_per_step": ms, "achieved_gbs": gbs,
-            "peak_gbs": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS}
+def km(r):
+    return dict(zip(KINDS, r["kernel_ms"]))
 
 
-def sweep_hbm_model(r, wsize, sweep_ms, kernel_model=True):
-    """Modelled HBM rate of the sweeps of one SR step.  The method's byte
-    model: every proposal reads one row of Y (N_e w bytes), every accept
-    reads and writes all of Y (2 N_e^2 w bytes).  The LDS/HBM kernel moves
-    less: with the anti-parallel pair amplitude the same-spin blocks of Y
-    are zero, so a proposal reads half a row and an accept reads one
-    N_e/2 x N_e/2 block for q and reads and writes the two opposite-spin
-    blocks (1.25 N_e^2 w bytes); that count is reported beside it."""
+def sweep_bytes(r, wsize, model):
+    """Bytes of the sweeps of one SR step.  "method": every proposal reads one
+    row of X^-1 (N_e w) and every accepted one reads and writes all of it
+    (2 N_e^2 w).  "ap": the anti-parallel-block kernel reads one column or row
+    of M^-1 (n w, n = N_e/2) per proposal and 3 n^2 w per accepted one (v or
+    t, then the rank-1 update).  "full": the full-X^-1 LDS/HBM kernel reads
+    half a row per proposal and one n x n block plus two blocks read and
+    written per accepted one (1.25 N_e^2 w)."""
     ne = r["ne"]
+    n = ne // 2
     props = r["proposals"] / max(r["steps"], 1)
     acc = props * r["accept_ratio"]
-    bytes_ = props * ne * wsize + acc * 2 * ne * ne * wsize
-    gbs = bytes_ / (sweep_ms * 1e-3) / 1e9
-    out = {"alg_bytes_per_step": bytes_, "sweep_ms_per_step": sweep_ms, "achieved_gbs": gbs,
-           "peak_gbs": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS}
-    if kernel_model:
-        kb = props * ne // 2 * wsize + acc * 1.25 * ne * ne * wsize
-        kg = kb / (sweep_ms * 1e-3) / 1e9
-        out.update({"kernel_bytes_per_step": kb, "kernel_gbs": kg,
-                    "kernel_frac": kg / HBM_PEAK_GBS})
+    if model == "method":
+        return props * ne * wsize + acc * 2 * ne * ne * wsize
+    if model == "ap":
+        return props * n * wsize + acc * 3 * n * n * wsize
+    return props * n * wsize + acc * 1.25 * ne * ne * wsize
+
+
+def sweep_model_of(variant):
+    if variant.startswith("ap"):
+        return "ap"
+    if variant.startswith("reg"):
+        return "method"
+    return "full"
+
+
+def sweep_hbm(r, wsize):
+    """Modelled HBM rate of the sweeps of one SR step on the kernel's own
+    byte model, with the method's model beside it."""
+    ms = km(r)["sweep"]
+    own = sweep_model_of(r["variants"][0])
+    b_own = sweep_bytes(r, wsize, own)
+    b_met = sweep_bytes(r, wsize, "method")
+    return {"kernel": r["variants"][0], "byte_model": own, "sweep_ms_per_step": ms,
+            "bytes_per_step": b_own, "gbs": b_own / (ms * 1e-3) / 1e9,
+            "frac_of_hbm_peak": b_own / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "method_model_bytes_per_step": b_met,
+            "method_model_frac_of_hbm_peak": b_met / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
+def measure_hbm(r, wsize):
+    """E_loc and O_k: every sample reads the opposite-spin half of X^-1
+    (N_e^2/2 w, the part the kernel reads) and writes its O row (N_p w)."""
+    ne, npar = r["ne"], r["np"]
+    bytes_ = r["N"] * (ne * ne // 2 + npar) * wsize
+    ms = km(r)["measure"]
+    return {"bytes_per_step": bytes_, "ms_per_step": ms, "gbs": bytes_ / (ms * 1e-3) / 1e9,
+            "frac_of_hbm_peak": bytes_ / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
+def s_build_rates(r, mixed):
+    """S = O~^T O~ / N over the upper triangle: N N_p (N_p + 1) flops; the
+    split-bf16 build issues three bf16 products."""
+    N, npar = r["N"], r["np"]
+    if r["kernel_calls"][4] == 0:
+        return None
+    ms = km(r)["s_build"] / r["kernel_calls"][4]
+    fl = N * npar * (npar + 1)
+    out = {"shape": [N, npar], "ms": ms, "tflops": fl / (ms * 1e-3) / 1e12}
+    if mixed:
+        out.update({"kernel": "split-bf16 MFMA (hi.hi + hi.lo + lo.hi), FP32 accumulate",
+                    "issued_bf16_tflops": 3 * fl / (ms * 1e-3) / 1e12,
+                    "issued_frac_of_bf16_peak": 3 * fl / (ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS})
+    else:
+        out.update({"kernel": "FP64 MFMA 16x16x4",
+                    "frac_of_fp64_peak": fl / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS})
     return out
 
 
-def precision_leg(steps):
-    """10x10 Hubbard, U = 8, N_e = 100, unconstrained f (N_p = 10002), 4096
-    walkers, 10 sweeps and one sample per walker per SR step, S and a
-    Cholesky solve: the mixed path (single-precision sweeps, double
-    refresh every 32 proposals, split-bf16 S) against the plain double path
-    (refresh every 4 sweeps, double S), same kernels otherwise."""
-    from mvmc_inputs import workload
-    out = {}
-    for prec, R in (("mixed", 32), ("fp64", 400)):
-        wl = workload("c3_sq10_mixed", warmup=20)
-        log(f"[bench]   10x10 {prec} (refresh every {R})")
-        r = run_sr_workload(wl, prec, steps, 1, R, solver="chol")
-        i0 = wl["instances"][0]
-        km = dict(zip(["sweep", "refresh", "measure", "sr_stats", "s_build", "sr_solve"],
-                      r["kernel_ms"]))
-        N, npar = r["N"], r["np"]
-        nh = r["ne"] // 2
-        ref_calls = max(r["kernel_calls"][1], 1)
-        # block-route refresh: Gauss-Jordan inversion of the N_e/2 x N_e/2 block, 2 n^3 flops
-        ref_flops = ref_calls * r["W"] * 2.0 * nh ** 3
-        out[prec] = {"value": r["rate"], "unit": "hop-updates/s", "ms_per_step": r["ms_per_step"],
-                     "accept_ratio": r["accept_ratio"], "kernel_ms_per_step": km,
-                     "s_build_tflops": N * npar * (npar + 1) / (km["s_build"] * 1e-3) / 1e12,
-                     "sweep_modelled_hbm": sweep_hbm_model(r, 4 if prec == "mixed" else 8,
-                                                           km["sweep"]),
-                     "refresh": {"launches_per_step": r["kernel_calls"][1],
-                                 "fp64_tflops": ref_flops / (km["refresh"] * 1e-3) / 1e12,
-                                 "peak_tflops": FP64_PEAK_TFLOPS,
-                                 "flops_model": "2 (N_e/2)^3 per walker (block route)"},
-                     "cholesky": {"fp64_tflops": npar ** 3 / 3 / (km["sr_solve"] * 1e-3) / 1e12,
-                                  "peak_tflops": FP64_PEAK_TFLOPS,
-                                  "note": "N_p^3/3 flops over the whole solve (factor, "
-                                          "substitutions, update)"},
-                     "cholesky_shift_raises": r["cholesky_shift_raises"],
-                     "energy_per_site": [e / i0.n_sites for e in r["energies"]]}
-    out["speedup_mixed_vs_fp64"] = out["mixed"]["value"] / out["fp64"]["value"]
-    out["s_build_speedup_mixed_vs_fp64"] = (out["fp64"]["kernel_ms_per_step"]["s_build"] /
-                                            out["mixed"]["kernel_ms_per_step"]["s_build"])
-    return out
+def refresh_rate(r):
+    """Block-route refresh: Gauss-Jordan inversion of the n x n block,
+    2 n^3 flops per walker."""
+    n = r["ne"] // 2
+    calls = max(r["kernel_calls"][1], 1)
+    ms = km(r)["refresh"]
+    fl = r["kernel_calls"][1] * r["W"] * 2.0 * n ** 3
+    return {"launch_groups_per_step": calls, "ms_per_step": ms,
+            "fp64_tflops": fl / (ms * 1e-3) / 1e12 if ms > 0 else None,
+            "flops_model": "2 (N_e/2)^3 per walker per refresh"}
 
 
-def rbm_leg(steps):
-    """16x16 Hubbard, U = 8, N_e = 224 (1/8 hole doping), 2x2-sublattice f
-    times an RBM factor of 512 hidden units over the 512 spin-resolved
-    occupations (N_p = 264194), 8192 walkers, single-precision sweeps, 10
-    sweeps and one sample per walker per SR step, SR by CG over the centred
-    O (8192 x 264320 single precision, no explicit S); CG is capped at 50
-    iterations per step here."""
-    from mvmc_inputs import workload
-    wl = workload("c5_sq16_rbm_mixed", warmup=10)
-    r = run_sr_workload(wl, "mixed", steps, 1, 0, solver="cg", build_s=False, cg_tol=1e-6,
-                        cg_maxit=50)
-    i0 = wl["instances"][0]
-    km = dict(zip(["sweep", "refresh", "measure", "sr_stats", "s_build", "sr_solve"],
-                  r["kernel_ms"]))
-    o_bytes = r["N"] * (-(-r["np"] // 128) * 128) * 4
-    it = r["cg_iterations"][-1] if r["cg_iterations"] else 0
+def step_summary(r, wsize, mixed):
+    k = km(r)
     return {"value": r["rate"], "unit": "hop-updates/s", "ms_per_step": r["ms_per_step"],
-            "walkers": r["W"], "n_elec": r["ne"], "n_params": r["np"], "n_hidden": i0.n_hidden,
-            "accept_ratio": r["accept_ratio"], "kernel_ms_per_step": km,
-            "cg_iterations": r["cg_iterations"], "cg_cap": 50,
-            "cg_ms_per_iteration": km["sr_solve"] / max(it, 1),
-            "cg_gbs_per_iteration": 2 * o_bytes / (km["sr_solve"] / max(it, 1) * 1e-3) / 1e9,
-            "sweep_modelled_hbm": sweep_hbm_model(r, 4, km["sweep"]),
-            "energy_per_site": [e / i0.n_sites for e in r["energies"]]}
+            "accept_ratio": r["accept_ratio"], "sweep_variant": r["variants"],
+            "kernel_ms_per_step": k, "sweep_hbm": sweep_hbm(r, wsize),
+            "measure_hbm": measure_hbm(r, wsize), "s_build": s_build_rates(r, mixed),
+            "refresh": refresh_rate(r),
+            "cholesky_fp64_tflops": (r["np"] ** 3 / 3 / (k["sr_solve"] * 1e-3) / 1e12
+                                     if r["cholesky_shift_raises"] else None),
+            "cholesky_shift_raises": r["cholesky_shift_raises"],
+            "energy_per_site": [e / r["ns"] for e in r["energies"]],
+            "energy_error_per_site": [e / r["ns"] for e in r["energy_errors"]]}
 
 
-def batch_leg(steps):
-    """32 ragged clusters (square L = 4..12, U in [2, 10], filling 0.8-1.0,
-    256 walkers each), mixed precision, each instance its own SR step; all
-    instances of a register tier sweep in one launch, variants autotuned."""
-    from mvmc_inputs import workload
-    wl = workload("c4_batch32_mixed")
-    r = run_sr_workload(wl, "mixed", steps, 1, wl["refresh_every"], use_graph=True,
-                        autotune=True)
-    insts = wl["instances"]
-    return {"value": r["rate"], "unit": "hop-updates/s", "ms_per_step": r["ms_per_step"],
-            "instances": len(insts), "walkers": sum(i.n_walkers for i in insts),
-            "n_elec_range": [min(i.n_elec for i in insts), max(i.n_elec for i in insts)],
-            "sweeps_per_step": r["sweeps"], "accept_ratio": r["accept_ratio"],
-            "kernel_ms_per_step": dict(zip(["sweep", "refresh", "measure", "sr_stats",
-                                            "s_build", "sr_solve"], r["kernel_ms"])),
-            "autotune": r["autotune"], "energy_per_site_last_step":
-                [e / i.n_sites for e, i in zip(r["energies"][-1], insts)]}
+def precision_errors():
+    """Mixed against double on the 10x10 workload, result by result.
 
-
-def hbm_copy_probe(gib=1.0, reps=10):
-    """Attainable HBM bandwidth: torch's elementwise negation over a buffer of
-    `gib` GiB (read once, written once).  Under rocprofv3 --pmc its
-    FETCH_SIZE and WRITE_SIZE calibrate the counters against known bytes."""
-    import torch
-    n = int(gib * (1 << 30)) // 8
-    src = torch.ones(n, dtype=torch.float64, device="cuda")
-    dst = torch.empty_like(src)
-    torch.neg(src, out=dst)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        torch.neg(src, out=dst)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    del src, dst
-    return {"kernel": "torch.neg (elementwise)", "bytes_per_launch": 2 * n * 8, "ms": ms,
-            "gbs": 2 * n * 8 / (ms * 1e-3) / 1e9}
-
-
-def sweep_sources_digest():
-    import hashlib
-    h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, "paper_1711_11418_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
-def measured_traffic():
-    """HBM bytes per sweep launch from the committed counter summary, scaled by
-    the calibration copy; None when the summary is missing or the sweep
-    kernel's sources changed after the counters were taken."""
-    path = os.path.join(ROOT, "profiles", TRAFFIC_SUMMARY)
-    if not os.path.exists(path):
-        return None, "no counter summary"
-    kv = {}
-    with open(path) as fh:
-        for line in fh:
-            if ":" in line and not line.startswith("#"):
-                k, v = line.split(":", 1)
-                kv[k.strip()] = v.strip()
-    if kv.get("sources_sha256_16") != sweep_sources_digest():
-        return None, "sweep sources changed since the counters were taken"
-    copy_bytes = float(kv["copy_bytes_per_launch"])
-    f_scale = copy_bytes / 2 / (float(kv["copy_fetch_kib"]) * 1024)
-    w_scale = copy_bytes / 2 / (float(kv["copy_write_kib"]) * 1024)
-    t = (float(kv["sweep_fetch_kib"]) * 1024 * f_scale
-         + float(kv["sweep_write_kib"]) * 1024 * w_scale)
-    return t, f"FETCH_SIZE+WRITE_SIZE per launch (median), scaled by the copy ({f_scale:.3f}, {w_scale:.3f})"
-
-
-def sweep_roofline(r, wsize):
-    """Algorithmic bytes of the sweep per launch over its measured duration."""
-    W, ne = r["W"], r["ne"]
-    avg_ms = r["kernel_ms"][0] / max(r["kernel_calls"][0], 1)
-    props = W * ne                          # one sweep per launch in this workload
-    acc = r["accept_ratio"] * props
-    bytes_ = props * ne * wsize + acc * 2 * ne * ne * wsize
-    flops = props * 2 * ne + acc * 6 * ne * ne
-    return avg_ms, bytes_, flops
-
-
-def sweep_roofline_entry(sweep_threads, avg_ms, bytes_, flops, traffic, traffic_note,
-                         probes=None, copy_gbs=None):
-    """Roofline of the sweep kernel.  The byte model charges every proposal
-    one row of Y and every accept a read and a write of all of Y.  The
-    register-resident kernel keeps Y on chip for the whole launch (the
-    counters see it read and written once), so its modelled-byte rate is not
-    bounded by HBM and the kernel is reported against the double-precision
-    vector peak with its algorithmic flops; the LDS kernel streams Y through
-    LDS and is reported against HBM."""
-    gbs = bytes_ / (avg_ms * 1e-3) / 1e9
-    tflops = flops / (avg_ms * 1e-3) / 1e12
-    common = {"avg_launch_ms": avg_ms, "alg_bytes_per_launch": bytes_,
-              "alg_flops_per_launch": flops, "traffic": traffic, "traffic_note": traffic_note,
-              "traffic_frac_of_alg": None if traffic is None else traffic / bytes_}
-    if sweep_threads == 0:
-        return {"kernel": "k_sweep_reg<double, 64, 4, false, false>", "bound": "alu",
-                "achieved": tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": tflops / FP64_PEAK_TFLOPS,
-                "frac_of_measured_fp64_fma": (tflops / probes["fp64_fma"]) if probes else None,
-                "modelled_hbm": {"achieved_gbs": gbs, "peak_gbs": HBM_PEAK_GBS,
-                                 "frac": gbs / HBM_PEAK_GBS},
-                "residency": "Y in registers for the whole launch", **common}
-    return {"kernel": f"k_sweep<double, true, {sweep_threads}>", "bound": "hbm",
-            "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-            "fp64_tflops": tflops, **common}
-
-
-def s_build_leg():
-    """Split-bf16 S build at the 4096-sample x 10^4-parameter shape, at the
-    tile side the library's tuner picks on this data."""
+    The mixed context is warmed up; its configurations, counters and empty
+    lists are loaded into a double context and both are recomputed in double,
+    so every comparison below starts from the same walkers:
+      ratios   one sweep traced on both (compared until a decision differs)
+      E_loc, O measured on both at the loaded configurations
+      S, g     built on both from those samples (split-bf16 vs FP64)
+      dalpha   the SR step of both (double Cholesky of each S_reg)
+    and energies at equal sample counts from two independent chains
+    (different Philox keys), with sigma = std(walker means)/sqrt(W)."""
     import numpy as np
     import torch
 
     from mvmc_inputs import workload
     from paper_1711_11418_amd import MVMC
 
-    wl = workload("c3_sq10_mixed")
+    wl = workload(HEADLINE)
     inst = wl["instances"][0]
-    ctx = MVMC([inst], inst.params0, precision="mixed", refresh_every=32,
+    kw = dict(seed=wl["sampler_seed"], n_slots=1, solver="chol", build_s=True)
+    m = MVMC([inst], inst.params0, precision="mixed", refresh_every=MIXED_REFRESH, **kw)
+    d = MVMC([inst], inst.params0, precision="fp64", refresh_every=FP64_REFRESH, **kw)
+    m.sample(40)
+    pos, cnt, emp = m.get_state(with_empty=True)
+    d.set_state(pos.cpu().numpy(), cnt.cpu().numpy(), emp.cpu().numpy())
+    m.refresh()
+    out = {}
+    # E_loc and O at the same configurations
+    m.measure(0)
+    d.measure(0)
+    em, ed = m.eloc_of(0, 1).double(), d.eloc_of(0, 1)
+    Om, Od = m.O_of(0, 1).double(), d.O_of(0, 1)
+    rel_e = (em - ed).abs() / ed.abs().clamp_min(1e-300)
+    dO = (Om - Od).abs()
+    out["eloc"] = {"max_rel": float(rel_e.max()), "median_rel": float(rel_e.median())}
+    out["O"] = {"max_abs_over_max_O": float(dO.max() / Od.abs().max()),
+                "median_abs": float(dO.median())}
+    # S, g, energy and the SR step from these samples
+    Em, Erm, _ = m.build_sr(1)
+    Ed, Erd, _ = d.build_sr(1)
+    S_err = float((m.S_of(0).double() - d.S_of(0)).abs().max() / d.S_of(0).abs().max())
+    g_err = float((m.g - d.g).abs().max() / d.g.abs().max())
+    out["S"] = {"max_abs_over_max_S": S_err}
+    out["g"] = {"max_abs_over_max_g": g_err}
+    out["mean_energy_same_samples"] = {"mixed": float(Em[0]), "fp64": float(Ed[0]),
+                                       "diff_over_sigma": float((Em[0] - Ed[0]) / Erd[0])}
+    a = dict(dtau=wl["dtau"], eps_rel=wl["eps_rel"], eps_abs=wl["eps_abs"], solver="chol")
+    m.sr_update(**a)
+    d.sr_update(**a)
+    da = float(torch.linalg.norm(m.dparams - d.dparams) / torch.linalg.norm(d.dparams))
+    out["dalpha"] = {"rel_l2": da}
+    m.close()
+    d.close()
+    # ratios over one sweep from identical states
+    m = MVMC([inst], inst.params0, precision="mixed", refresh_every=MIXED_REFRESH, **kw)
+    d = MVMC([inst], inst.params0, precision="fp64", refresh_every=FP64_REFRESH, **kw)
+    m.sample(40)
+    pos, cnt, emp = m.get_state(with_empty=True)
+    d.set_state(pos.cpu().numpy(), cnt.cpu().numpy(), emp.cpu().numpy())
+    m.refresh()
+    m.enable_trace(inst.n_elec)
+    d.enable_trace(inst.n_elec)
+    m.sample(1)
+    d.sample(1)
+    tm, td = m.trace_records(), d.trace_records()
+    m.close()
+    d.close()
+    diff = tm["accepted"] != td["accepted"]
+    first = np.where(diff.any(axis=1), diff.argmax(axis=1), tm.shape[1])
+    mask = np.arange(tm.shape[1])[None, :] <= np.minimum(first, tm.shape[1] - 1)[:, None]
+    mask &= td["i_new"] >= 0
+    rr = np.abs(tm["ratio"] - td["ratio"])[mask] / np.maximum(np.abs(td["ratio"][mask]), 1e-300)
+    out["ratio"] = {"compared": int(mask.sum()), "median_rel": float(np.median(rr)),
+                    "p99_rel": float(np.percentile(rr, 99)), "max_rel": float(rr.max()),
+                    "walkers_with_a_differing_decision": int(diff.any(axis=1).sum()),
+                    "walkers": int(tm.shape[0])}
+    # energies at equal sample counts from independent chains
+    res = {}
+    for prec, R, seed in (("mixed", MIXED_REFRESH, 91), ("fp64", FP64_REFRESH, 92)):
+        slots = 8
+        c = MVMC([inst], inst.params0, precision=prec, refresh_every=R, seed=seed,
+                 n_slots=slots, solver="cg", build_s=False)
+        c.sample(40)
+        for s in range(slots):
+            c.sample_async(5)
+            c.measure(s)
+        E, Er, _ = c.build_sr(slots, with_S=False)
+        res[prec] = (float(E[0]), float(Er[0]))
+        c.close()
+    z = (res["mixed"][0] - res["fp64"][0]) / np.hypot(res["mixed"][1], res["fp64"][1])
+    out["energy_equal_samples"] = {
+        "samples": 8 * inst.n_walkers, "mixed": res["mixed"], "fp64": res["fp64"],
+        "z": float(z), "within_2_sigma": bool(abs(z) < 2.0),
+        "note": "(E, sigma) per precision; 8 samples per walker, 5 sweeps apart, after 40 "
+                "sweeps, initial parameters"}
+    return out
+
+
+def s_build_leg():
+    """Split-bf16 S build at the 4096-sample x 10^4-parameter shape, at the
+    tile side the library's tuner picks on this data."""
+    import torch
+
+    from mvmc_inputs import workload
+    from paper_1711_11418_amd import MVMC
+
+    wl = workload(HEADLINE)
+    inst = wl["instances"][0]
+    ctx = MVMC([inst], inst.params0, precision="mixed", refresh_every=MIXED_REFRESH,
                seed=wl["sampler_seed"], n_slots=1, solver="cg", build_s=True)
     ctx.autotune(1)          # sweep variants, and arms the S tile tuner
     ctx.sample(2)
@@ -389,8 +387,6 @@ def s_build_leg():
     torch.cuda.synchronize()
     gemm_ms = e0.elapsed_time(e1) / 3
     del a, b, c
-    # upper-triangle tiles of the chosen side (64 for narrow parameter
-    # sets), three bf16 MFMA passes each over the samples rounded up to 32
     tile = sides[0] or 64
     nt = -(-npar // tile)
     rows = -(-N // 32) * 32 if sides[0] else -(-N // 16) * 16
@@ -405,8 +401,211 @@ def s_build_leg():
             "note": "time of the S kernels only (centring and split excluded)"}
 
 
-def _oracle_worker(args):
+def reg_sweep_roofline(r):
+    """The register-resident sweep keeps the walker's X^-1 in VGPRs for the
+    whole launch, so neither HBM nor the method's byte model bounds it; its
+    algorithmic flops (2 N_e per proposal, 6 N_e^2 per accepted one) against
+    the FP64 vector peak, with the launch's latency chain the real limit."""
+    ne = r["ne"]
+    launches = max(r["kernel_calls"][0], 1)
+    avg_ms = km(r)["sweep"] / launches
+    props = r["proposals"] / max(r["steps"], 1) / launches
+    acc = r["accept_ratio"] * props
+    flops = props * 2 * ne + acc * 6 * ne * ne
+    return {"avg_launch_ms": avg_ms, "alg_flops_per_launch": flops,
+            "fp64_tflops": flops / (avg_ms * 1e-3) / 1e12,
+            "frac_of_fp64_peak": flops / (avg_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+            "bound": "latency (one wavefront per walker, dependent proposal chain)"}
+
+
+def sq8_leg(steps):
+    """8x8 Hubbard, U = 4, N_e = 64, 2x2-sublattice f + distance Jastrow +
+    Gutzwiller (N_p = 271), 1024 walkers x 200 sweeps with a measurement
+    after every sweep, FP64 S and Cholesky; double and mixed."""
+    from mvmc_inputs import workload
+    wl = workload("sq8_u4")
+    r = run_sr_workload(wl, "fp64", steps, 1, wl["refresh_every"])
+    m = run_sr_workload(wl, "mixed", steps, 1, MIXED_REFRESH)
+    out = {"fp64": step_summary(r, 8, False), "mixed": step_summary(m, 4, True)}
+    out["fp64"]["sweep_reg_alu"] = reg_sweep_roofline(r)
+    out["mixed_speedup_vs_fp64"] = m["rate"] / r["rate"]
+    return out
+
+
+def rbm_leg(steps):
+    """16x16 Hubbard, U = 8, N_e = 224 (1/8 hole doping), 2x2-sublattice f
+    times an RBM factor of 512 hidden units over the 512 spin-resolved
+    occupations (N_p = 264194), 8192 walkers, single-precision sweeps with a
+    double refresh once per sweep (224 proposals), 10 sweeps and one sample
+    per walker per SR step, SR by CG over the centred O (8192 x 264320 single
+    precision, no explicit S) run to the Algorithm 1 stopping rule."""
+    from mvmc_inputs import workload
+    wl = workload("sq16_u8_rbm", warmup=10)
+    r = run_sr_workload(wl, "mixed", steps, 1, wl["refresh_every"], solver="cg",
+                        build_s=False, cg_tol=wl["cg_tol"], cg_maxit=wl["cg_maxit"])
+    out = step_summary(r, 4, True)
+    out.pop("s_build")
+    o_bytes = r["N"] * (-(-r["np"] // 128) * 128) * 4
+    it = r["cg_iterations"][-1] if r["cg_iterations"] else 0
+    out.update({"walkers": r["W"], "n_elec": r["ne"], "n_params": r["np"],
+                "refresh_every": wl["refresh_every"], "cg_tol": wl["cg_tol"],
+                "cg_iterations": r["cg_iterations"], "cg_maxit": wl["cg_maxit"],
+                "cg_ms_per_iteration": km(r)["sr_solve"] / max(it, 1),
+                "cg_gbs_per_iteration":
+                    2 * o_bytes / (km(r)["sr_solve"] / max(it, 1) * 1e-3) / 1e9})
+    return out
+
+
+def batch_leg(steps):
+    """32 ragged clusters (square L = 4..12, U in [2, 10], filling 0.8-1.0,
+    256 walkers each), mixed precision, each instance its own SR step;
+    variants autotuned."""
+    from mvmc_inputs import workload
+    wl = workload("batch32_ragged")
+    r = run_sr_workload(wl, "mixed", steps, 1, wl["refresh_every"], use_graph=True,
+                        autotune=True)
+    insts = wl["instances"]
+    return {"value": r["rate"], "unit": "hop-updates/s", "ms_per_step": r["ms_per_step"],
+            "instances": len(insts), "walkers": sum(i.n_walkers for i in insts),
+            "n_elec_range": [min(i.n_elec for i in insts), max(i.n_elec for i in insts)],
+            "sweeps_per_step": r["sweeps"], "accept_ratio": r["accept_ratio"],
+            "kernel_ms_per_step": km(r), "autotune": r["autotune"],
+            "energy_per_site_last_step": [e / i.n_sites for e, i in zip(r["energies"][-1], insts)]}
+
+
+def rbm_gain(sr_steps):
+    """16x16, U = 8, N_e = 224: the plain Pfaffian-Jastrow(-Gutzwiller) state
+    and the same state times the RBM factor, each trained by SR from the same
+    start on the same GPU with the same sampler settings (8192 walkers, 10
+    sweeps and one sample per walker per step); the energy of each trained
+    state is then estimated with the same number of samples."""
     import numpy as np
+
+    from mvmc_inputs import workload
+    from paper_1711_11418_amd import MVMC
+
+    out = {}
+    for tag, name in (("pj", "sq16_u8_pj"), ("pj_rbm", "sq16_u8_rbm")):
+        wl = workload(name)
+        inst = wl["instances"][0]
+        ctx = MVMC([inst], inst.params0, precision="mixed", refresh_every=wl["refresh_every"],
+                   seed=wl["sampler_seed"], n_slots=1, solver="cg", build_s=False)
+        ctx.sample(wl["warmup"])
+        hist, iters = [], []
+        t0 = time.perf_counter()
+        for it in range(sr_steps):
+            ctx.sample_async(wl["sweeps"])
+            ctx.measure(0)
+            E, Er, _ = ctx.build_sr(1, with_S=False)
+            hist.append((float(E[0]) / inst.n_sites, float(Er[0]) / inst.n_sites))
+            iters.append(int(ctx.sr_update(dtau=wl["dtau"], eps_rel=wl["eps_rel"],
+                                           eps_abs=wl["eps_abs"], solver="cg",
+                                           cg_tol=wl["cg_tol"], cg_maxit=wl["cg_maxit"])[0]))
+            if it % 10 == 0:
+                log(f"[rbm-gain] {tag} step {it}: E/N = {hist[-1][0]:.5f} +- {hist[-1][1]:.5f}, "
+                    f"CG {iters[-1]}")
+        train_s = time.perf_counter() - t0
+        # the trained state: 16 samples per walker, 5 sweeps apart
+        slots = 16
+        ev = MVMC([inst], ctx.params.cpu().numpy(), precision="mixed",
+                  refresh_every=wl["refresh_every"], seed=wl["sampler_seed"] + 7, n_slots=slots,
+                  solver="cg", build_s=False)
+        ctx.close()
+        ev.sample(wl["warmup"])
+        for s in range(slots):
+            ev.sample_async(5)
+            ev.measure(s)
+        E, Er, _ = ev.build_sr(slots, with_S=False)
+        ev.close()
+        out[tag] = {"n_params": inst.n_params, "sr_steps": sr_steps, "train_seconds": train_s,
+                    "energy_per_site": float(E[0]) / inst.n_sites,
+                    "sigma_per_site": float(Er[0]) / inst.n_sites,
+                    "samples": slots * inst.n_walkers, "history_per_site": hist,
+                    "cg_iterations": iters}
+    d = out["pj_rbm"]["energy_per_site"] - out["pj"]["energy_per_site"]
+    out["gain_per_site"] = -d
+    out["gain_over_sigma"] = -d / float(np.hypot(out["pj_rbm"]["sigma_per_site"],
+                                                 out["pj"]["sigma_per_site"]))
+    return out
+
+
+def hbm_copy_probe(gib=1.0, reps=10):
+    """Attainable HBM bandwidth: torch's elementwise negation over a buffer of
+    `gib` GiB (read once, written once).  Under rocprofv3 --pmc its
+    FETCH_SIZE and WRITE_SIZE calibrate the counters against known bytes."""
+    import torch
+    n = int(gib * (1 << 30)) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.neg(src, out=dst)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return {"kernel": "torch.neg (elementwise)", "bytes_per_launch": 2 * n * 8, "ms": ms,
+            "gbs": 2 * n * 8 / (ms * 1e-3) / 1e9}
+
+
+def sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_1711_11418_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, scaled by the calibration copy; None when the summary is missing
+    or the kernel's sources changed after the counters were taken."""
+    path = os.path.join(ROOT, "profiles", TRAFFIC_SUMMARY)
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("sources_sha256_16") != sources_digest():
+        return None, "kernel sources changed since the counters were taken"
+    copy_bytes = float(kv["copy_bytes_per_launch"])
+    f_scale = copy_bytes / 2 / (float(kv["copy_fetch_kib"]) * 1024)
+    w_scale = copy_bytes / 2 / (float(kv["copy_write_kib"]) * 1024)
+    t = (float(kv["kernel_fetch_kib"]) * 1024 * f_scale
+         + float(kv["kernel_write_kib"]) * 1024 * w_scale)
+    return t, (f"FETCH_SIZE+WRITE_SIZE per launch (median), scaled by the copy "
+               f"({f_scale:.3f}, {w_scale:.3f})")
+
+
+def headline_roofline(r, wsize):
+    """Roofline of the dominant kernel of the headline step, the
+    anti-parallel-block sweep: its algorithmic bytes per launch (n w per
+    proposal, 3 n^2 w per accepted one) over its average launch time (HIP
+    events on the library's stream), against the HBM peak."""
+    launches = max(r["kernel_calls"][0], 1)
+    avg_ms = km(r)["sweep"] / launches
+    b = sweep_bytes(r, wsize, sweep_model_of(r["variants"][0])) / launches
+    bm = sweep_bytes(r, wsize, "method") / launches
+    gbs = b / (avg_ms * 1e-3) / 1e9
+    traffic, note = measured_traffic()
+    return {"kernel": f"k_sweep_ap<double, {r['variants'][0][2:]}>", "bound": "hbm",
+            "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "traffic": traffic, "traffic_note": note,
+            "avg_launch_ms": avg_ms, "launches_per_step": launches,
+            "alg_bytes_per_launch": b, "byte_model": "n w per proposal + 3 n^2 w per accepted "
+                                                     "proposal (n = N_e/2, w = 8)",
+            "method_model_bytes_per_launch": bm,
+            "method_model_frac": bm / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
+def _oracle_worker(args):
     os.environ["OMP_NUM_THREADS"] = "1"
     from mvmc_inputs import random_configs, workload
     from oracle import sampler
@@ -429,28 +628,26 @@ def _oracle_worker(args):
     return done, time.perf_counter() - t0
 
 
-def cpu_baseline(budget_s=12.0):
-    """The oracle (full-recompute Metropolis, Parlett-Reid per proposal) on
-    the host cores, one process per core, on time-bounded samples of the 8x8
-    workload (the headline), the 8-site ring and the 10x10 workload; plus
-    numpy O^T O at 4096 x 2000 and numpy's Cholesky at 10^4, in double."""
+def cpu_baseline(budget_s=15.0):
+    """The oracle (full-recompute Metropolis, two Parlett-Reid Pfaffians per
+    proposal) on the host cores, one process per core, on a time-bounded
+    sample of the headline 10x10 workload; numpy O^T O at 4096 x 2000 and
+    numpy's Cholesky at 10^4 in double as context."""
     import multiprocessing as mp
 
     import numpy as np
     cores = min(os.cpu_count() or 1, 16)
-
-    def rate(name, budget):
-        with mp.get_context("spawn").Pool(cores) as pool:
-            res = pool.map(_oracle_worker, [(w, name, 10 ** 9, budget) for w in range(cores)])
-        return sum(r[0] for r in res), max(r[1] for r in res)
-
-    props, wall = rate("c2_sq8_fp64", budget_s)
-    p1, w1 = rate("c1_ring8_fp64", 3.0)
-    p3, w3 = rate("c3_sq10_mixed", 5.0)
+    pool = mp.get_context("spawn").Pool(cores)
+    try:
+        res = pool.map(_oracle_worker, [(w, HEADLINE, 10 ** 9, budget_s) for w in range(cores)])
+    finally:
+        pool.close()
+        pool.join()
+    props, wall = sum(x[0] for x in res), max(x[1] for x in res)
     rng = np.random.default_rng(0)
     O = rng.standard_normal((4096, 2000))
     t0 = time.perf_counter()
-    S = O.T @ O / 4096
+    O.T @ O / 4096
     ts = time.perf_counter() - t0
     B = rng.standard_normal((10000, 10000))
     B = (B + B.T) * 0.5 + 10000.0 * np.eye(10000)   # symmetric, diagonally dominant: SPD
@@ -462,9 +659,8 @@ def cpu_baseline(budget_s=12.0):
     except Exception:   # the configuration report differs between numpy versions
         blas = "unknown"
     return {"value": props / wall, "unit": "hop-updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"{props} full-recompute proposals on the 8x8 U=4 workload, "
-                      f"{cores} processes x {budget_s:.0f} s",
-            "ring8_hop_updates_per_s": p1 / w1, "sq10_hop_updates_per_s": p3 / w3,
+            "sample": f"{props} full-recompute proposals on the 10x10 U=8 workload "
+                      f"(N_e = 100), {cores} processes x {budget_s:.0f} s",
             "s_build_gflops_numpy_fp64": 4096 * 2000 * 2001 / ts / 1e9,
             "cholesky_1e4_numpy_fp64_s": tc, "nproc": os.cpu_count(), "blas": blas}
 
@@ -477,10 +673,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--skip-legs", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch the sampling eagerly")
-    ap.add_argument("--sweep-threads", type=int, default=0,
-                    help="0: register-resident sweep where it fits; 64/128/256: LDS sweep")
     ap.add_argument("--s-build-only", action="store_true",
                     help="print only the split-bf16 S build leg (for kernel profiling)")
+    ap.add_argument("--rbm-gain", action="store_true",
+                    help="train 16x16 PJ and PJ x RBM by SR and print their energies")
+    ap.add_argument("--sr-steps", type=int, default=40)
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the walkers of this workload fit one MI355X; "
@@ -491,7 +688,10 @@ def main():
     from mvmc_inputs import workload
 
     if a.s_build_only:
-        print(json.dumps({"s_build_bf16x3_c3": s_build_leg()}), flush=True)
+        print(json.dumps({"s_build_bf16x3_sq10": s_build_leg()}), flush=True)
+        return
+    if a.rbm_gain:
+        print(json.dumps({"rbm_gain_sq16": rbm_gain(a.sr_steps)}), flush=True)
         return
 
     copy = hbm_copy_probe()
@@ -499,63 +699,64 @@ def main():
     from paper_1711_11418_amd.binding import peak_probe
     probes = {k: peak_probe(k) for k in ("bf16_mfma", "fp64_mfma", "fp64_fma")}
     log(f"[bench] instruction peaks (TFLOP/s): {probes}")
-    wl = workload("c2_sq8_fp64")
-    log(f"[bench] c2_sq8_fp64 fp64: W=1024 sweeps/step={wl['sweeps']} steps={a.steps} "
+    wl = workload(HEADLINE)
+    log(f"[bench] {HEADLINE} fp64: W=4096 sweeps/step={wl['sweeps']} steps={a.steps} "
         f"warmup={a.warmup}")
-    r = run_sr_workload(wl, "fp64", a.steps, a.warmup, wl["refresh_every"],
-                        sweep_threads=a.sweep_threads, use_graph=not a.no_graph)
-    avg_ms, bytes_, flops = sweep_roofline(r, 8)
-    s_ms = r["kernel_ms"][4] / max(r["kernel_calls"][4], 1)
-    s_flops = r["N"] * r["np"] * (r["np"] + 1)
-    traffic, traffic_note = measured_traffic() if a.sweep_threads == 0 else (None, "LDS sweep")
+    r = run_sr_workload(wl, "fp64", a.steps, a.warmup, FP64_REFRESH, use_graph=not a.no_graph)
+    head = step_summary(r, 8, False)
+    log(f"[bench]   fp64: {r['rate']:.3e} hop-updates/s, {r['ms_per_step']:.1f} ms/step, "
+        f"kernel ms {', '.join(f'{k} {v:.2f}' for k, v in km(r).items())}")
     out = {
         "metric": METRIC, "value": r["rate"], "unit": "hop-updates/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": r["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "c2_sq8_fp64: 8x8 Hubbard U=4, Ne=64, Np=271, 1024 walkers x "
-                               "200 sweeps + SR (Cholesky) per step",
+        "config": {"workload": "sq10_u8: 10x10 Hubbard U=8, N_e=100, unconstrained f "
+                               "(N_p=10002), 4096 walkers x 10 sweeps + E_loc/O_k + S (FP64 "
+                               "MFMA) + Cholesky + update + double refresh per SR step",
                    "walkers": r["W"], "n_elec": r["ne"], "n_params": r["np"],
                    "sweeps_per_step": r["sweeps"], "samples_per_step": r["N"],
-                   "sampling_in_hip_graph": r["graph"]},
+                   "refresh_every": FP64_REFRESH, "sampling_in_hip_graph": r["graph"]},
         "accepted_per_s": r["rate"] * r["accept_ratio"],
-        "accept_ratio": r["accept_ratio"],
-        "s_build": {"tflops": s_flops / (s_ms * 1e-3) / 1e12, "ms": s_ms, "dtype": "f64",
-                    "shape": [r["N"], r["np"]], "kernel": "FP64 MFMA 16x16x4",
-                    "frac_of_fp64_peak": s_flops / (s_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
-                    "frac_of_measured_fp64_mfma": s_flops / (s_ms * 1e-3) / 1e12 /
-                                                  probes["fp64_mfma"]},
-        "roofline": sweep_roofline_entry(a.sweep_threads, avg_ms, bytes_, flops, traffic,
-                                         traffic_note, probes, copy["gbs"]),
+        "s_build_tflops": head["s_build"]["tflops"],
+        "roofline": headline_roofline(r, 8),
+        "fp64": head,
         "measured_peaks": {"hbm_copy_gbs": copy["gbs"], "hbm_copy": copy,
                            "bf16_mfma_tflops": probes["bf16_mfma"],
                            "fp64_mfma_tflops": probes["fp64_mfma"],
                            "fp64_fma_tflops": probes["fp64_fma"],
                            "note": "register-only loops on non-zero data, two wavefronts per "
                                    "SIMD (mvmc_peak_probe); datasheet peaks in roofline.peak"},
-        "kernel_ms_per_step": dict(zip(["sweep", "refresh", "measure", "sr_stats", "s_build",
-                                        "sr_solve"], r["kernel_ms"])),
-        "measure_modelled_hbm": measure_hbm_model(r, 8),
-        "energy_per_site": [e / 64 for e in r["energies"]],
     }
+    log(f"[bench] {HEADLINE} mixed (refresh every {MIXED_REFRESH})")
+    mx = run_sr_workload(wl, "mixed", a.steps, a.warmup, MIXED_REFRESH,
+                         use_graph=not a.no_graph)
+    out["mixed"] = step_summary(mx, 4, True)
+    out["mixed"]["speedup_vs_fp64"] = mx["rate"] / r["rate"]
+    out["mixed"]["s_build_speedup_vs_fp64"] = (head["s_build"]["ms"] /
+                                               out["mixed"]["s_build"]["ms"])
+    out["s_build_bf16x3_tflops"] = out["mixed"]["s_build"]["tflops"]
+    log(f"[bench]   mixed: {mx['rate']:.3e} hop-updates/s, {mx['ms_per_step']:.1f} ms/step, "
+        f"kernel ms {', '.join(f'{k} {v:.2f}' for k, v in km(mx).items())}")
     if not a.skip_legs:
-        log("[bench] mixed-precision leg (same workload, fp32 sweeps, refresh every 32)")
-        m = run_sr_workload(wl, "mixed", max(1, a.steps - 1), 1, 32,
-                            sweep_threads=a.sweep_threads, use_graph=not a.no_graph)
-        out["mixed"] = {"value": m["rate"], "ms_per_step": m["ms_per_step"],
-                        "speedup_vs_fp64": m["rate"] / r["rate"],
-                        "energy_per_site": [e / 64 for e in m["energies"]],
-                        "kernel_ms_per_step": m["kernel_ms"]}
-        log("[bench] split-bf16 S build at 4096 x 10^4")
-        out["s_build_bf16x3_c3"] = s_build_leg()
-        out["s_build_bf16x3_c3"]["issued_frac_of_measured_bf16_mfma"] = (
-            out["s_build_bf16x3_c3"]["issued_mfma_tflops"] / probes["bf16_mfma"])
-        log("[bench] 10x10 precision leg: mixed vs plain FP64")
-        out["sq10_mixed_vs_fp64"] = precision_leg(2)
+        log("[bench] precision errors: mixed vs double result by result")
+        out["precision_errors"] = precision_errors()
+        log(f"[bench]   {json.dumps(out['precision_errors'])}")
+        log("[bench] split-bf16 S build at 4096 x 10^4, tuned tile")
+        out["s_build_bf16x3_sq10"] = s_build_leg()
+        out["s_build_bf16x3_sq10"]["issued_frac_of_measured_bf16_mfma"] = (
+            out["s_build_bf16x3_sq10"]["issued_mfma_tflops"] / probes["bf16_mfma"])
+        log("[bench] 8x8 leg (double and mixed)")
+        out["sq8_u4"] = sq8_leg(max(1, a.steps))
+        log(f"[bench]   8x8 fp64 {out['sq8_u4']['fp64']['value']:.3e}, mixed "
+            f"{out['sq8_u4']['mixed']['value']:.3e} hop-updates/s")
         log("[bench] 16x16 RBM leg (8192 walkers, CG)")
-        out["sq16_rbm_mixed"] = rbm_leg(1)
+        out["sq16_u8_rbm"] = rbm_leg(1)
+        log(f"[bench]   16x16 {out['sq16_u8_rbm']['value']:.3e} hop-updates/s, "
+            f"{out['sq16_u8_rbm']['ms_per_step']:.0f} ms/step, CG "
+            f"{out['sq16_u8_rbm']['cg_iterations']}")
         log("[bench] ragged batch of 32 clusters (mixed, autotuned)")
-        out["batch32_mixed"] = batch_leg(max(1, a.steps - 1))
+        out["batch32_ragged"] = batch_leg(max(1, a.steps - 1))
     if not a.no_cpu:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline()

@@ -67,7 +67,8 @@ def _c4(n_walkers: int = 256, n_inst: int = 32) -> list[Instance]:
 
 def _c5(n_walkers: int = 8192, n_hidden: int = 512) -> list[Instance]:
     lat = square(16)
-    return [make_instance("sq16_U8_rbm", lat, 112, 112, 8.0, f_map_sublattice(lat, 2, 2),
+    name = "sq16_U8_rbm" if n_hidden else "sq16_U8_pj"
+    return [make_instance(name, lat, 112, 112, 8.0, f_map_sublattice(lat, 2, 2),
                           v_map_nn(lat), g0=-1.0, v_nn=0.1, n_hidden=n_hidden,
                           rbm_sigma=0.01, n_walkers=n_walkers, seed=INPUT_SEED)]
 
@@ -84,22 +85,25 @@ def workload(name: str, **overrides) -> dict:
     """Build a named workload; keyword overrides replace defaults (e.g. n_walkers)."""
     nw = overrides.pop("n_walkers", None)
     kw_inst = {} if nw is None else {"n_walkers": nw}
-    if name == "c1_ring8_fp64":
+    if name == "ring8_u4":
         d = _wl(_c1(**kw_inst), sweeps=1000, warmup=100, sample_every=1, sr_iters=0,
                 sampler_seed=1711 * 1000 + 1)
-    elif name == "c2_sq8_fp64":
+    elif name == "sq8_u4":
         d = _wl(_c2(**kw_inst), sweeps=200, warmup=100, sample_every=1, sr_iters=10,
                 refresh_every=4 * 64, sampler_seed=1711 * 1000 + 2)
-    elif name == "c3_sq10_mixed":
+    elif name == "sq10_u8":
         d = _wl(_c3(**kw_inst), precision="mixed", refresh_every=32, sweeps=10,
                 warmup=100, sample_every=10, sr_iters=10, sampler_seed=1711 * 1000 + 3)
-    elif name == "c4_batch32_mixed":
+    elif name == "batch32_ragged":
         d = _wl(_c4(**kw_inst), precision="mixed", refresh_every=32, sweeps=10,
                 warmup=100, sample_every=1, sr_iters=10, sampler_seed=1711 * 1000 + 4)
-    elif name == "c5_sq16_rbm_mixed":
-        d = _wl(_c5(**kw_inst), precision="mixed", refresh_every=0, sweeps=10,
+    elif name in ("sq16_u8_rbm", "sq16_u8_pj"):
+        # the RBM state and its plain Pfaffian-Jastrow twin (same f, g, v start;
+        # the RBM parameters are appended); double refresh once per sweep
+        hid = {} if name == "sq16_u8_rbm" else {"n_hidden": 0}
+        d = _wl(_c5(**kw_inst, **hid), precision="mixed", refresh_every=224, sweeps=10,
                 warmup=100, sample_every=10, sr_iters=10, dtau=0.01, solver="cg",
-                sampler_seed=1711 * 1000 + 5)
+                cg_tol=1e-3, cg_maxit=5000, sampler_seed=1711 * 1000 + 5)
     elif name == "ring4":
         lat = chain(4)
         d = _wl([make_instance("ring4_U4", lat, 2, 2, 4.0, f_map_full(lat), v_map_nn(lat),
@@ -142,8 +146,9 @@ def workload(name: str, **overrides) -> dict:
     return d
 
 
-WORKLOADS = ("c1_ring8_fp64", "c2_sq8_fp64", "c3_sq10_mixed", "c4_batch32_mixed",
-             "c5_sq16_rbm_mixed", "ring4", "ring6", "sq4_sub2", "ring6_rbm", "ring6_u8_gain")
+WORKLOADS = ("ring8_u4", "sq8_u4", "sq10_u8", "batch32_ragged",
+             "sq16_u8_rbm", "sq16_u8_pj", "ring4", "ring6", "sq4_sub2", "ring6_rbm",
+             "ring6_u8_gain")
 
 
 def random_configs(inst: Instance, n: int, seed: int) -> np.ndarray:

@@ -30,7 +30,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_query_sizes_c2_shapes():
     b = _lib()
-    wl = workload("c2_sq8_fp64", n_walkers=1024)
+    wl = workload("sq8_u4", n_walkers=1024)
     cfg = b.make_config(wl["instances"], "fp64", 256, 7, n_slots=200)
     s = b.query_sizes(cfg)
     assert s.n_walkers == 1024 and s.n_params == 271
@@ -44,7 +44,7 @@ def test_query_sizes_c2_shapes():
 
 def test_batched_layout_is_contiguous():
     b = _lib()
-    insts = workload("c4_batch32_mixed", n_walkers=8)["instances"]
+    insts = workload("batch32_ragged", n_walkers=8)["instances"]
     cfg = b.make_config(insts, "mixed", 32, 7, n_slots=2, build_s=True)
     s = b.query_sizes(cfg)
     offs = [b.query_layout(cfg, k) for k in range(32)]

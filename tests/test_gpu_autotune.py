@@ -16,7 +16,7 @@ SEED = 4242
 
 
 def _batch():
-    insts = [workload(n)["instances"][0] for n in ("ring6", "sq4_sub2", "c1_ring8_fp64")]
+    insts = [workload(n)["instances"][0] for n in ("ring6", "sq4_sub2", "ring8_u4")]
     insts.append(square_case(6, 15, 3, full_f=False))
     insts.append(square_case(8, 36, 2, full_f=False))    # N_e = 72: LDS/HBM kernels only
     for i in insts[:3]:

@@ -27,7 +27,7 @@ def _gpu():
 
 
 def _instances():
-    insts = [workload(n)["instances"][0] for n in ("ring6", "sq4_sub2", "c1_ring8_fp64")]
+    insts = [workload(n)["instances"][0] for n in ("ring6", "sq4_sub2", "ring8_u4")]
     insts.append(square_case(6, 15, 24, full_f=False, n_hidden=12))
     for i, w in zip(insts[:3], (16, 40, 24)):
         i.n_walkers = w

@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-@pytest.mark.parametrize("name,refresh", [("sq4_sub2", 0), ("c1_ring8_fp64", 16)])
+@pytest.mark.parametrize("name,refresh", [("sq4_sub2", 0), ("ring8_u4", 16)])
 def test_captured_sampling_replays_match_eager(name, refresh):
     from paper_1711_11418_amd import MVMC
     inst = workload(name)["instances"][0]

@@ -47,7 +47,7 @@ def _case(name):
 
 
 # ------------------------------------------------------------------ refresh
-@pytest.mark.parametrize("name", ["ring6", "c1_ring8_fp64", "sq4_sub2", "ring6_rbm", "sq10_full",
+@pytest.mark.parametrize("name", ["ring6", "ring8_u4", "sq4_sub2", "ring6_rbm", "sq10_full",
                                   "sq12_sub"])
 def test_refresh_inverse_and_pfaffian(name):
     inst = _case(name)
@@ -72,7 +72,7 @@ def test_refresh_inverse_and_pfaffian(name):
 # threads = 0 selects the register-resident sweep where N_e fits it (N_e <= 64);
 # 64/128/256 force the LDS-resident sweep with that many threads per walker.
 @pytest.mark.parametrize("name,sweeps,refresh,threads", [
-    ("ring6", 20, 0, 0), ("c1_ring8_fp64", 20, 7, 0), ("sq4_sub2", 10, 0, 0),
+    ("ring6", 20, 0, 0), ("ring8_u4", 20, 7, 0), ("sq4_sub2", 10, 0, 0),
     ("ring6_rbm", 20, 5, 0), ("sq8_half", 3, 0, 0), ("sq8_half", 3, 64, 0),
     ("sq4_sub2", 10, 0, 64), ("sq8_half", 3, 0, 128), ("ring6_rbm", 20, 5, 256),
     ("sq10_full", 2, 0, 0), ("sq6_rbm", 4, 16, 0), ("sq12_sub", 1, 50, 0),
@@ -253,7 +253,7 @@ def test_mixed_split_bf16_overlap(name, walkers, tile):
 
 # ----------------------------------------------------------- ragged batch
 def test_batched_instances_replay():
-    insts = [workload(n)["instances"][0] for n in ("ring6", "sq4_sub2", "c1_ring8_fp64")]
+    insts = [workload(n)["instances"][0] for n in ("ring6", "sq4_sub2", "ring8_u4")]
     insts.append(square_case(6, 15, 3, full_f=False))
     for i in insts[:3]:
         i.n_walkers = 5

@@ -16,7 +16,7 @@ torch = pytest.importorskip("torch")
 
 def test_ring8_energy_within_two_sigma():
     from paper_1711_11418_amd import MVMC
-    wl = workload("c1_ring8_fp64")
+    wl = workload("ring8_u4")
     inst = wl["instances"][0]
     E_exact = en.exact_energy(wf.expand(inst, inst.params0))[0]
     sweeps = 1000

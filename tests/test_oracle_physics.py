@@ -68,7 +68,7 @@ def test_ring8_zero_variance_slater_case():
 
 
 def test_ring8_variational_energy_above_ed():
-    inst = workload("c1_ring8_fp64")["instances"][0]
+    inst = workload("ring8_u4")["instances"][0]
     m = wf.expand(inst, inst.params0)
     E, p, eloc, confs = en.exact_energy(m)
     H = ed.hamiltonian(8, 4, 4, m.bonds, m.bond_t, m.U)
@@ -219,8 +219,8 @@ def test_force_is_half_energy_gradient():
 
 # ---------------------------------------------------------------- inputs
 def test_parameter_counts():
-    assert workload("c1_ring8_fp64")["instances"][0].n_params == 66
-    assert workload("c2_sq8_fp64", n_walkers=4)["instances"][0].n_params == 271
-    insts = workload("c4_batch32_mixed", n_walkers=4)["instances"]
+    assert workload("ring8_u4")["instances"][0].n_params == 66
+    assert workload("sq8_u4", n_walkers=4)["instances"][0].n_params == 271
+    insts = workload("batch32_ragged", n_walkers=4)["instances"]
     assert len(insts) == 32
     assert all(i.n_elec % 2 == 0 and i.n_up == i.n_dn for i in insts)
