@@ -73,7 +73,7 @@ def compare_trace(rec: np.ndarray, walkers, n_prop: int, seed: int, rtol: float 
     errors = []
     for w, wk in enumerate(walkers):
         for k in range(n_prop):
-            n, a, inew, R, acc = wk.trace[k]
+            n, a, inew, R, acc, b = wk.trace[k]
             g = rec[w, k]
             assert int(g["n"]) == n, (w, k, int(g["n"]), n)
             assert int(g["a"]) == a and int(g["i_new"]) == inew, (w, k, g, wk.trace[k])
@@ -140,7 +140,7 @@ def mixed_ratio_stats(inst, m, rec, walkers, pos0, n_prop: int, seed: int, refre
         dth = np.zeros(m.n_hidden)
         k_acc = 0
         for k in range(n_prop):
-            n, a, inew, R, acc = wk.trace[k]
+            n, a, inew, R, acc, b = wk.trace[k]
             g = rec[w, k]
             assert int(g["n"]) == n and int(g["a"]) == a and int(g["i_new"]) == inew, (w, k)
             nv = wf.occupations(m, pos)
