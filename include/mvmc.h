@@ -99,6 +99,9 @@ typedef struct {
                                  the kernels that keep the full X^-1 (LDS, else HBM) */
   int32_t sweep_variant;      /* 0 = automatic; 1 + v forces sweep variant v (below) for
                                  every instance (MVMC_E_SHAPE where it does not fit) */
+  int32_t exchange_per64;     /* 0..64: a proposal is an exchange update (section 3.1.2,
+                                 Fig. 5b) with probability exchange_per64/64, else a hop;
+                                 needs the register or anti-parallel-block sweep */
 } mvmc_config;
 
 /* Sizes of the caller-owned buffers for a configuration. */
@@ -334,10 +337,13 @@ int mvmc_get_pfaffian(mvmc_ctx *ctx, double *d_logabs, double *d_sign);
 int mvmc_refresh(mvmc_ctx *ctx);
 
 /*
- * Record every proposal into d_trace (32-byte records
- * {int64 n; int32 walker; int32 a; int32 i_new; int32 accepted; double ratio}),
- * record for proposal n of walker w at w*capacity + (n - n_at_enable).
- * d_trace NULL or capacity 0 disables.
+ * Record every proposal into d_trace (40-byte records
+ * {int64 n; int32 walker; int32 a; int32 i_new; int32 accepted; double ratio;
+ *  int32 b; int32 pad}: a the moved electron (the up one of an exchange),
+ * i_new its proposed spin-orbital (-1 when no move was possible), b the down
+ * electron of an exchange (-1 for a hop)); the record for proposal n of
+ * walker w at w*capacity + (n - n_at_enable).  d_trace NULL or capacity 0
+ * disables.
  */
 int mvmc_trace_enable(mvmc_ctx *ctx, void *d_trace, int64_t per_walker_capacity);
 

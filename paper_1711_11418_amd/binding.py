@@ -48,6 +48,7 @@ class Config(C.Structure):
         ("n_instances", C.c_int32), ("inst", C.POINTER(InstanceDesc)),
         ("n_slots", C.c_int32), ("solver", C.c_int32), ("build_s", C.c_int32),
         ("sweep_threads", C.c_int32), ("sweep_variant", C.c_int32),
+        ("exchange_per64", C.c_int32),
     ]
 
 
@@ -70,7 +71,7 @@ class Layout(C.Structure):
 
 
 TRACE_DTYPE = np.dtype([("n", "<i8"), ("walker", "<i4"), ("a", "<i4"), ("i_new", "<i4"),
-                        ("accepted", "<i4"), ("ratio", "<f8")])
+                        ("accepted", "<i4"), ("ratio", "<f8"), ("b", "<i4"), ("pad", "<i4")])
 
 _lib = None
 
@@ -168,7 +169,7 @@ class _Desc:
 
 
 def make_config(instances, precision="fp64", refresh_every=0, seed=1, n_slots=1, solver="chol",
-                build_s=True, sweep_threads=0, sweep_variant=None):
+                build_s=True, sweep_threads=0, sweep_variant=None, exchange_per64=0):
     """sweep_variant: None (automatic) or a name of SWEEP_VARIANT_NAMES forced for
     every instance."""
     descs = [_Desc(i) for i in instances]
@@ -177,7 +178,8 @@ def make_config(instances, precision="fp64", refresh_every=0, seed=1, n_slots=1,
                  int(seed), len(descs), C.cast(arr, C.POINTER(InstanceDesc)), int(n_slots),
                  MVMC_SOLVE_CHOL if solver == "chol" else MVMC_SOLVE_CG, int(bool(build_s)),
                  int(sweep_threads),
-                 0 if sweep_variant is None else 1 + SWEEP_VARIANT_NAMES.index(sweep_variant))
+                 0 if sweep_variant is None else 1 + SWEEP_VARIANT_NAMES.index(sweep_variant),
+                 int(exchange_per64))
     cfg._keep = (descs, arr)   # keep host arrays alive
     return cfg
 
@@ -205,7 +207,7 @@ class MVMC:
 
     def __init__(self, instances, params, *, precision="fp64", refresh_every=0, seed=1,
                  n_slots=1, solver="chol", build_s=True, sweep_threads=0, sweep_variant=None,
-                 device="cuda:0", stream=None):
+                 exchange_per64=0, device="cuda:0", stream=None):
         """stream: torch.cuda.Stream for all of the context's work (default: the
         current stream).  A non-default stream is needed for graph capture."""
         import torch
@@ -215,7 +217,7 @@ class MVMC:
         self.instances = list(instances)
         self.precision = precision
         self.cfg = make_config(self.instances, precision, refresh_every, seed, n_slots, solver,
-                               build_s, sweep_threads, sweep_variant)
+                               build_s, sweep_threads, sweep_variant, exchange_per64)
         self.sizes = query_sizes(self.cfg)
         self.layouts = [query_layout(self.cfg, k) for k in range(len(self.instances))]
         self.n_inst = len(self.instances)
@@ -356,8 +358,8 @@ class MVMC:
 
     def enable_trace(self, per_walker: int) -> None:
         t = self.torch
-        self._trace = t.zeros(int(self.sizes.n_walkers) * per_walker * 32, dtype=t.uint8,
-                              device=self.device)
+        self._trace = t.zeros(int(self.sizes.n_walkers) * per_walker * TRACE_DTYPE.itemsize,
+                              dtype=t.uint8, device=self.device)
         self._trace_cap = per_walker
         self._check(self.lib.mvmc_trace_enable(self.ctx, self._p(self._trace), per_walker))
 

@@ -45,6 +45,7 @@ struct Plan {
   std::vector<int> sweep_nt;      // threads of the LDS/HBM sweep kernel per instance
   std::vector<char> sweep_ap;     // 1 = anti-parallel-block sweep (M^-1 alone in LDS)
   int bad_variant = -1;           // instance a forced sweep variant does not fit
+  bool exchange = false;          // exchange updates on (variants 0 and 7-9 only)
   // pools (byte offsets into the workspace)
   Pool inst_p, srinst_p, walker_inst, lists, A64, A32, V, fidx, vidx, G, U, gidx, nbr_ptr,
       nbr_site, nbr_t, fm_ptr, fm, gm_ptr, gm, vm_ptr, vm, rbm64, rbm32, rbmT64, rbmT32, Y, Y64,
@@ -141,6 +142,10 @@ Err validate(const mvmc_config* c) {
   if (c->sweep_threads && c->sweep_threads != 64 && c->sweep_threads != 128 &&
       c->sweep_threads != 256)
     return fail(MVMC_E_ARG, "sweep_threads must be 0, 64, 128 or 256");
+  if (c->exchange_per64 < 0 || c->exchange_per64 > 64)
+    return fail(MVMC_E_ARG, "exchange_per64 must be in [0, 64]");
+  if (c->exchange_per64 && c->sweep_threads)
+    return fail(MVMC_E_ARG, "exchange updates need the register or anti-parallel-block sweep");
   if (c->sweep_variant < 0 || c->sweep_variant > MVMC_N_SWEEP_VARIANTS)
     return fail(MVMC_E_ARG, "sweep_variant must be 0 (automatic) or 1 + a variant");
   for (int k = 0; k < c->n_instances; ++k) {
@@ -201,9 +206,10 @@ int64_t v_members(const mvmc_instance_desc& d) {
 // Sweep variant of instance k: 0 register tier, 1-3 LDS kernel with
 // 64/128/256 threads, 4-6 HBM kernel with 64/128/256 threads (both keep the
 // full X^-1), 7-9 anti-parallel-block kernel (M^-1 alone in LDS) with
-// 64/128/256 threads.
+// 64/128/256 threads.  Exchange updates run on 0 and 7-9 only.
 bool variant_fits(const Plan& P, int k, int v) {
   const InstDev& I = P.inst[k];
+  if (P.exchange && v >= 1 && v <= 6) return false;
   if (v == 0) {
     const int rc = sweep_reg_class(I.ne, P.tsize);
     return rc && sweep_reg_lds_bytes(rc, I.ns, I.M, P.tsize, kRegWpb) <= kLdsLimit;
@@ -237,12 +243,13 @@ int default_variant(const Plan& P, int k) {
   const int n = P.inst[k].ne / 2;
   const int v = 7 + (n <= 48 ? 0 : (n <= 96 ? 1 : 2));
   if (variant_fits(P, k, v)) return v;
-  return 6;
+  return P.exchange ? -1 : 6;
 }
 
 Plan make_plan(const mvmc_config& c) {
   Plan P;
   P.tsize = c.precision == MVMC_FP64 ? 8 : 4;
+  P.exchange = c.exchange_per64 > 0;
   const int n = c.n_instances;
   P.inst.resize(n);
   P.sr.resize(n);
@@ -284,7 +291,9 @@ Plan make_plan(const mvmc_config& c) {
       if (variant_fits(P, k, c.sweep_variant - 1)) set_variant(P, k, c.sweep_variant - 1);
       else if (P.bad_variant < 0) P.bad_variant = k;
     } else if (c.sweep_threads == 0) {
-      set_variant(P, k, default_variant(P, k));
+      const int v = default_variant(P, k);
+      if (v >= 0) set_variant(P, k, v);
+      else if (P.bad_variant < 0) P.bad_variant = k;
     }
     I.refresh_lds = refresh_lds_bytes(I.ne, I.ns, true) <= kLdsLimit;
     if (!I.refresh_lds) P.need_Y64 = true;
@@ -1118,10 +1127,10 @@ int run_sweeps(mvmc_ctx* c, int32_t n_sweeps, std::vector<double>* inst_ms) {
             c->cfg.precision == MVMC_FP64
                 ? launch_sweep_reg<double>(c->P, lst, b.n, b.reg, b.max_ns, b.max_M, cp,
                                            c->cfg.seed, c->trace, c->trace_cap, tb, tgt, nr, R,
-                                           1, c->stream)
+                                           1, c->cfg.exchange_per64, c->stream)
                 : launch_sweep_reg<float>(c->P, lst, b.n, b.reg, b.max_ns, b.max_M, cp,
                                           c->cfg.seed, c->trace, c->trace_cap, tb, tgt, nr, R,
-                                          1, c->stream);
+                                          1, c->cfg.exchange_per64, c->stream);
         t1(e);
         if (!ok) return set_err(c, fail(MVMC_E_ARG, "no register sweep tier %d", b.reg));
         continue;
@@ -1131,11 +1140,11 @@ int run_sweeps(mvmc_ctx* c, int32_t n_sweeps, std::vector<double>* inst_ms) {
         if (c->cfg.precision == MVMC_FP64)
           launch_sweep_ap<double>(c->P, lst, b.n, (int)std::min<int64_t>(cap, INT32_MAX),
                                   c->cfg.seed, b.max_ne, b.max_ns, b.max_M, b.nthreads, c->trace,
-                                  c->trace_cap, tb, tgt, nr, R, c->stream);
+                                  c->trace_cap, tb, tgt, nr, R, c->cfg.exchange_per64, c->stream);
         else
           launch_sweep_ap<float>(c->P, lst, b.n, (int)std::min<int64_t>(cap, INT32_MAX),
                                  c->cfg.seed, b.max_ne, b.max_ns, b.max_M, b.nthreads, c->trace,
-                                 c->trace_cap, tb, tgt, nr, R, c->stream);
+                                 c->trace_cap, tb, tgt, nr, R, c->cfg.exchange_per64, c->stream);
         t1(e);
         continue;
       }

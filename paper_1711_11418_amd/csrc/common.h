@@ -90,10 +90,12 @@ enum : int32_t { kGuardClear = 0, kGuardPending = 1, kGuardFailed = 2 };
 struct TraceRec {
   int64_t n;          // proposal index of the walker
   int32_t walker;     // global walker id
-  int32_t a;          // electron
-  int32_t i_new;      // proposed spin-orbital (-1: no empty site)
+  int32_t a;          // electron (the up electron of an exchange)
+  int32_t i_new;      // proposed spin-orbital of a (-1: no move possible)
   int32_t accepted;
   double ratio;       // psi(x')/psi(x) including correlators
+  int32_t b;          // down electron of an exchange, -1 for a hop
+  int32_t pad;
 };
 
 // ---------------------------------------------------------------- Philox

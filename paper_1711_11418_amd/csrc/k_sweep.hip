@@ -149,6 +149,7 @@ __global__ __launch_bounds__(NT) void k_sweep(Pools P, const int32_t* __restrict
     if (nemp == 0) {
       if (trace && tid == 0 && n - tb < (uint64_t)trace_cap) {
         TraceRec rec;
+        rec.b = -1; rec.pad = 0;
         rec.n = (int64_t)n; rec.walker = gw; rec.a = a; rec.i_new = -1; rec.accepted = 0;
         rec.ratio = 0.0;
         trace[(int64_t)gw * trace_cap + (int64_t)(n - tb)] = rec;
@@ -202,6 +203,7 @@ __global__ __launch_bounds__(NT) void k_sweep(Pools P, const int32_t* __restrict
     const bool accept = u < R * R;
     if (trace && tid == 0 && n - tb < (uint64_t)trace_cap) {
       TraceRec rec;
+      rec.b = -1; rec.pad = 0;
       rec.n = (int64_t)n; rec.walker = gw; rec.a = a; rec.i_new = Inew;
       rec.accepted = accept ? 1 : 0; rec.ratio = R;
       trace[(int64_t)gw * trace_cap + (int64_t)(n - tb)] = rec;

@@ -23,6 +23,20 @@
 // of the walker's X^-1 and writes both non-zero blocks back at the end, so
 // every other kernel sees the usual X^-1.  Proposal, correlators, trace,
 // refresh cadence and non-finite guard are those of k_sweep.hip.
+//
+// Exchange update (section 3.1.2, Fig. 5b): up electron a (site i) and down
+// electron b (site j) trade sites, so row a and column b of M change at once:
+// M' = M + e_a u^T + w e_b^T with u the change of row a (its entry b included)
+// and w the change of column b off row a.  With
+//   rho   = sum_b' r'[b'] M^-1[b'][a]    r' the new row a (r'[b] = f(j, i))
+//   sigma = sum_a' M^-1[b][a'] c[a']     c the new column b off row a, c[a] = f(i, j)
+//   t'    = M^-1 c,   beta = u . t' - u[b],   gamma = M^-1[b][a]
+// the determinant lemma gives det M'/det M = rho sigma - beta gamma, and the
+// Woodbury identity the rank-2 update
+//   M^-1 <- M^-1 - M^-1[:, a] l1^T - (t' - e_b) l2^T,
+//   l1 = (sigma s - beta M^-1[b, :]) / D,  l2 = (rho M^-1[b, :] - gamma s) / D,
+// s = u^T M^-1, D the ratio.  Charges per site do not change, so the
+// Gutzwiller and Jastrow factors stay; four RBM visibles flip.
 #include "launch.h"
 
 namespace mvmc {
@@ -40,12 +54,12 @@ __host__ __device__ inline ApSweepLds ap_sweep_layout(int ne, int ns, int M, siz
   const int n = ne / 2;
   L.ld = n + ((n & 1) ? 0 : 1);
   L.Mi = ap16((size_t)n * L.ld * ts);
-  L.vec = ap16(4 * (size_t)n * ts);             // m', column/row of M^-1, v or t, spare
+  L.vec = ap16(8 * (size_t)n * ts);             // hop: m', column/row, v or t; exchange: 8
   L.part = ap16((size_t)nw * n * ts);           // partial sums of v or t per wavefront
   L.h = ap16((size_t)ns * sizeof(double));
   L.th = ap16((size_t)M * ts);
   L.red = ap16(2 * (size_t)(nw > 8 ? nw : 8) * sizeof(double));
-  L.ints = ap16((size_t)(ne + 4 * ns) * sizeof(int32_t));
+  L.ints = ap16((size_t)(ne + 4 * ns + 2) * sizeof(int32_t));
   L.total = L.Mi + L.vec + L.part + L.h + L.th + L.red + L.ints;
   return L;
 }
@@ -66,13 +80,42 @@ size_t sweep_ap_lds_bytes(int ne, int ns, int M, size_t tsize, int nthreads) {
   return ap_sweep_layout(ne, ns, M, tsize, nthreads / 64).total;
 }
 
+namespace {
+// out = M^-1 x (rows) or out = x^T M^-1 (columns) over the n x n block: each
+// wavefront sums a slice of the contraction index for every output index,
+// the slices are then added in order.  Contains two workgroup barriers.
+template <typename T, int NW, int NT>
+__device__ __forceinline__ void ap_matvec(const T* Mi, int ld, int n, const T* x, T* out, T* part,
+                                          bool rows) {
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int j0 = (wid * n) / NW, j1 = ((wid + 1) * n) / NW;
+  for (int o = lane; o < n; o += 64) {
+    T s = T(0);
+    if (rows)
+      for (int j = j0; j < j1; ++j) s += Mi[o * ld + j] * x[j];
+    else
+      for (int j = j0; j < j1; ++j) s += x[j] * Mi[j * ld + o];
+    part[wid * n + o] = s;
+  }
+  __syncthreads();
+  for (int o = tid; o < n; o += NT) {
+    T s = T(0);
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += part[w * n + o];
+    out[o] = s;
+  }
+  __syncthreads();
+}
+}  // namespace
+
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_sweep_ap(Pools P, const int32_t* __restrict__ wlist,
                                                  int cap, uint64_t seed, TraceRec* trace,
                                                  int64_t trace_cap,
                                                  const uint64_t* __restrict__ trace_base,
                                                  const uint64_t* __restrict__ target,
-                                                 int32_t* __restrict__ needs_refresh, int R) {
+                                                 int32_t* __restrict__ needs_refresh, int R,
+                                                 int ex64) {
   constexpr int NW = NT / 64;
   extern __shared__ __align__(16) unsigned char smem[];
   const int gw = wlist[blockIdx.x];
@@ -113,6 +156,7 @@ __global__ __launch_bounds__(NT) void k_sweep_ap(Pools P, const int32_t* __restr
   int32_t* pos_s = (int32_t*)q;
   int32_t* eidx = pos_s + ne;    // 2ns: electron at spin-orbital, -1 empty
   int32_t* emp = eidx + n2;      // 2ns: empty lists [sigma][ns]
+  int32_t* slot = emp + n2;      // 2: list slots of an exchange
 
   T* Yg = (T*)P.Y + I.Y_off + lw * ne * ne;
   int32_t* posg = P.pos + I.pos_off + lw * ne;
@@ -152,12 +196,126 @@ __global__ __launch_bounds__(NT) void k_sweep_ap(Pools P, const int32_t* __restr
   for (int it = 0; it < n_prop; ++it) {
     const uint64_t nn = n0 + (uint64_t)it;
     const uint4 r = draw(seed, nn, (uint32_t)gw, 0u);
+    if (ex64 && (int)(r.w & 63u) < ex64) {
+      // ------------------------------------------------------ exchange
+      const int a = scaled(r.x, n), bd = scaled(r.y, ne - n), b = n + bd;
+      const int si = pos_s[a], sj = pos_s[b] - ns;
+      if (si == sj || eidx[sj] >= 0 || eidx[si + ns] >= 0) {   // no such move
+        if (trace && tid == 0 && nn - tb < (uint64_t)trace_cap) {
+          TraceRec rec;
+          rec.n = (int64_t)nn; rec.walker = gw; rec.a = a; rec.i_new = -1; rec.accepted = 0;
+          rec.ratio = 0.0; rec.b = b; rec.pad = 0;
+          trace[(int64_t)gw * trace_cap + (int64_t)(nn - tb)] = rec;
+        }
+        continue;
+      }
+      T* rn = mv;            // new row a of M
+      T* cn = mv + n;        // new column b off row a (c[a] = old M[a][b])
+      T* uu = mv + 2 * n;    // change of row a
+      T* ca = mv + 3 * n;    // column a of M^-1
+      T* rb = mv + 4 * n;    // row b of M^-1
+      T* tp = mv + 5 * n;    // t' = M^-1 c
+      T* l1 = mv + 6 * n;
+      T* l2 = mv + 7 * n;
+      const T* Ai = A + (int64_t)si * n2 + ns;   // f(i, .)
+      const T* Aj = A + (int64_t)sj * n2 + ns;   // f(j, .)
+      T accr = T(0), accs = T(0);
+      for (int q2 = tid; q2 < n; q2 += NT) {
+        const int sb = pos_s[n + q2] - ns;
+        const T fn = q2 == bd ? Aj[si] : Aj[sb];
+        const T c = Mi[q2 * ld + a];
+        rn[q2] = fn;
+        uu[q2] = fn - Ai[sb];
+        ca[q2] = c;
+        accr += fn * c;
+        const int s_up = pos_s[q2];
+        const T cv = q2 == a ? Ai[sj] : A[(int64_t)s_up * n2 + ns + si];
+        const T rv = Mi[bd * ld + q2];
+        cn[q2] = cv;
+        rb[q2] = rv;
+        accs += rv * cv;
+      }
+      double accm = 0.0;
+      if (M) {
+        for (int hh = tid; hh < M; hh += NT) {
+          const T* Wh = rW + (int64_t)hh * n2;
+          const T d = T(2) * (Wh[sj] - Wh[si] + Wh[si + ns] - Wh[sj + ns]);
+          const T th = ths[hh];
+          accm += (double)(log2cosh(th + d) - log2cosh(th));
+        }
+      }
+      double rho = (double)accr, sig = (double)accs;
+      block_sum2(rho, sig, red);
+      accm = block_sum(accm, red);
+      __syncthreads();   // the vectors above, for every thread
+      const double gam = (double)Mi[bd * ld + a];
+      ap_matvec<T, NW, NT>(Mi, ld, n, cn, tp, part, true);
+      T accb = T(0);
+      for (int q2 = tid; q2 < n; q2 += NT) accb += uu[q2] * tp[q2];
+      double bet = (double)accb;
+      bet = block_sum(bet, red) - (double)uu[bd];
+      const double D = rho * sig - bet * gam;
+      double logc = 0.0;
+      if (M) logc = 2.0 * ((double)ra[sj] - (double)ra[si] + (double)ra[si + ns] -
+                           (double)ra[sj + ns]) + accm;
+      const double Rt = D * exp(logc);
+      if (!isfinite(Rt)) {
+        guard1 = guard1 == kGuardPending ? kGuardFailed : kGuardPending;
+        n_done = it;
+        break;
+      }
+      guard1 = kGuardClear;
+      const bool accept = uniform53(r.z, r.w) < Rt * Rt;
+      if (trace && tid == 0 && nn - tb < (uint64_t)trace_cap) {
+        TraceRec rec;
+        rec.n = (int64_t)nn; rec.walker = gw; rec.a = a; rec.i_new = sj;
+        rec.accepted = accept ? 1 : 0; rec.ratio = Rt; rec.b = b; rec.pad = 0;
+        trace[(int64_t)gw * trace_cap + (int64_t)(nn - tb)] = rec;
+      }
+      if (!accept) continue;
+      ++acc;
+      ap_matvec<T, NW, NT>(Mi, ld, n, uu, l1, part, false);   // s = u^T M^-1 (into l1)
+      const double iD = 1.0 / D;
+      for (int q2 = tid; q2 < n; q2 += NT) {
+        const double sv = (double)l1[q2], rv = (double)rb[q2];
+        l2[q2] = (T)((rho * rv - gam * sv) * iD);
+        l1[q2] = (T)((sig * sv - bet * rv) * iD);
+      }
+      // list slots of j (up list) and i (down list)
+      for (int q2 = tid; q2 < ns; q2 += NT) {
+        if (emp[q2] == sj) slot[0] = q2;
+        if (emp[ns + q2] == si) slot[1] = q2;
+      }
+      __syncthreads();
+      for (int e = tid; e < n * n; e += NT) {
+        const int i2 = e / n, j2 = e - (e / n) * n;
+        const T tv = tp[i2] - (i2 == bd ? T(1) : T(0));
+        Mi[i2 * ld + j2] -= ca[i2] * l1[j2] + tv * l2[j2];
+      }
+      for (int hh = tid; hh < M; hh += NT) {
+        const T* Wh = rW + (int64_t)hh * n2;
+        ths[hh] += T(2) * (Wh[sj] - Wh[si] + Wh[si + ns] - Wh[sj + ns]);
+      }
+      if (tid == 0) {
+        pos_s[a] = sj;
+        pos_s[b] = si + ns;
+        eidx[si] = -1;
+        eidx[sj + ns] = -1;
+        eidx[sj] = a;
+        eidx[si + ns] = b;
+        emp[slot[0]] = si;
+        emp[ns + slot[1]] = sj;
+      }
+      __syncthreads();
+      continue;
+    }
     const int a = scaled(r.x, ne);
     const int sigma = a >= n ? 1 : 0;
     const int nemp = ns - (sigma ? I.ndn : n);
     if (nemp == 0) {
       if (trace && tid == 0 && nn - tb < (uint64_t)trace_cap) {
         TraceRec rec;
+        rec.b = -1; rec.pad = 0;
         rec.n = (int64_t)nn; rec.walker = gw; rec.a = a; rec.i_new = -1; rec.accepted = 0;
         rec.ratio = 0.0;
         trace[(int64_t)gw * trace_cap + (int64_t)(nn - tb)] = rec;
@@ -219,6 +377,7 @@ __global__ __launch_bounds__(NT) void k_sweep_ap(Pools P, const int32_t* __restr
     const bool accept = u < Rt * Rt;
     if (trace && tid == 0 && nn - tb < (uint64_t)trace_cap) {
       TraceRec rec;
+      rec.b = -1; rec.pad = 0;
       rec.n = (int64_t)nn; rec.walker = gw; rec.a = a; rec.i_new = Inew;
       rec.accepted = accept ? 1 : 0; rec.ratio = Rt;
       trace[(int64_t)gw * trace_cap + (int64_t)(nn - tb)] = rec;
@@ -293,7 +452,7 @@ template <typename T>
 void launch_sweep_ap(const Pools& P, const int32_t* wlist, int n, int cap, uint64_t seed,
                      int max_ne, int max_ns, int max_M, int nthreads, TraceRec* trace,
                      int64_t trace_cap, const uint64_t* trace_base, const uint64_t* target,
-                     int32_t* needs_refresh, int R, hipStream_t s) {
+                     int32_t* needs_refresh, int R, int ex64, hipStream_t s) {
   if (n <= 0 || cap <= 0) return;
   const size_t sh = ap_sweep_layout(max_ne, max_ns, max_M, sizeof(T), nthreads / 64).total;
 #define MVMC_AP_LAUNCH(NTV)                                                                      \
@@ -302,7 +461,7 @@ void launch_sweep_ap(const Pools& P, const int32_t* wlist, int n, int cap, uint6
       (void)hipFuncSetAttribute((const void*)&k_sweep_ap<T, NTV>,                                \
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);            \
     hipLaunchKernelGGL((k_sweep_ap<T, NTV>), dim3(n), dim3(NTV), sh, s, P, wlist, cap, seed,     \
-                       trace, trace_cap, trace_base, target, needs_refresh, R);                  \
+                       trace, trace_cap, trace_base, target, needs_refresh, R, ex64);            \
   } while (0)
   if (nthreads == 64) MVMC_AP_LAUNCH(64);
   else if (nthreads == 128) MVMC_AP_LAUNCH(128);
@@ -312,9 +471,9 @@ void launch_sweep_ap(const Pools& P, const int32_t* wlist, int n, int cap, uint6
 
 template void launch_sweep_ap<double>(const Pools&, const int32_t*, int, int, uint64_t, int, int,
                                       int, int, TraceRec*, int64_t, const uint64_t*,
-                                      const uint64_t*, int32_t*, int, hipStream_t);
+                                      const uint64_t*, int32_t*, int, int, hipStream_t);
 template void launch_sweep_ap<float>(const Pools&, const int32_t*, int, int, uint64_t, int, int,
                                      int, int, TraceRec*, int64_t, const uint64_t*,
-                                     const uint64_t*, int32_t*, int, hipStream_t);
+                                     const uint64_t*, int32_t*, int, int, hipStream_t);
 
 }  // namespace mvmc

@@ -29,6 +29,19 @@
 // Every per-proposal quantity that is the same for the whole walker lives in
 // scalar registers (Philox runs on the vector unit once per 64 proposals),
 // so the proposal loop has no workgroup barrier.
+//
+// Exchange update (section 3.1.2, Fig. 5b; EXCH): up electron a (site i) and
+// down electron b = n + b' (site j) trade sites; with M^-1 columns on the up
+// lanes and rows on the down lanes every quantity of the rank-2 determinant
+// lemma is lane-local or one wave reduction:
+//   rho   = sum over down lanes of r'[b''] M^-1[b''][a]    (r' the new row a)
+//   sigma = sum over up lanes of M^-1[b'][a''] c[a'']      (c the new column b)
+//   t'    = M^-1 c on the down lanes (c through LDS), beta = u . t' - u[b']
+//   gamma = M^-1[b'][a],  ratio D = rho sigma - beta gamma
+// and on acceptance s = u^T M^-1 on the up lanes (u through LDS), then the
+// Woodbury update M^-1 -= M^-1[:, a] l1^T + (t' - e_b') l2^T with
+// l1 = (sigma s - beta M^-1[b', :]) / D, l2 = (rho M^-1[b', :] - gamma s) / D,
+// the up lanes reading M^-1[:, a] and t' and the down lanes l1 and l2 from LDS.
 #include "ap_block.h"
 #include "launch.h"
 #include "wave.h"
@@ -182,14 +195,14 @@ __device__ __forceinline__ int reg_refresh_ap(
   return 0;
 }
 
-template <typename T, int NE_MAX, int WPB, bool TRACE, bool RBM>
+template <typename T, int NE_MAX, int WPB, bool TRACE, bool RBM, bool EXCH>
 __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* __restrict__ wlist,
                                                         int cap, uint64_t seed, TraceRec* trace,
                                                         int64_t trace_cap,
                                                         const uint64_t* __restrict__ trace_base,
                                                         const uint64_t* __restrict__ target,
                                                         int32_t* __restrict__ needs_refresh, int R,
-                                                        int kref) {
+                                                        int kref, int ex64) {
   constexpr int NH = NE_MAX / 2;
   using RC = RegCol<T, NH>;
   using Vec = typename RC::Vec;
@@ -285,6 +298,7 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
   const bool lane_up = lane < nh;
   const int slot = lane_up ? lane : HD + (lane - nh);   // lane's entry of x' and w
   const T* wl = w + (lane_up ? HD : 0);                 // the half of w the lane's rows read
+  const T* xl = xn + (lane_up ? HD : 0);                // the same half of x'
   const int rb = lane_up ? nh : 0;                      // first row of the lane's entries
 
   for (int v = lane; v < n2; v += 64) {
@@ -351,11 +365,156 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
     r.y = (uint32_t)__builtin_amdgcn_readlane((int)d1, rs);
     r.z = (uint32_t)__builtin_amdgcn_readlane((int)d2, rs);
     r.w = (uint32_t)__builtin_amdgcn_readlane((int)d3, rs);
+    if (EXCH && (int)(r.w & 63u) < ex64) {
+      // ---------------------------------------------------- exchange
+      const int a = opaque(sgpr(scaled(r.x, nh)));
+      const int bd = opaque(sgpr(scaled(r.y, nh)));
+      const int b = nh + bd;
+      const int si = sgpr(__builtin_amdgcn_readlane(posr, a));
+      const int sj = sgpr(__builtin_amdgcn_readlane(posr, b)) - ns;
+      if (si == sj || eidx[sj] >= 0 || eidx[si + ns] >= 0) {   // no such move
+        if (TRACE && lane == 0 && n - tb < (uint64_t)trace_cap) {
+          TraceRec rec;
+          rec.n = (int64_t)n; rec.walker = gw; rec.a = a; rec.i_new = -1; rec.accepted = 0;
+          rec.ratio = 0.0; rec.b = b; rec.pad = 0;
+          trace[(int64_t)gw * trace_cap + (int64_t)(n - tb)] = rec;
+        }
+        break;
+      }
+      const T ya = pick_col<T, NH>(z, a);    // down lane b'': -M^-1[b''][a]
+      const T yb = pick_col<T, NH>(z, bd);   // up lane a'':   M^-1[b'][a'']
+      const bool dnl = live && !lane_up;
+      const int sl = live ? posr - (lane_up ? 0 : ns) : 0;   // site of the lane's electron
+      // down lanes: new row a of M and its change; up lanes: new column b off row a
+      const double fnew = lane == b ? fs[sj * ldf + si] : fs[sj * ldf + sl];
+      const double fold = fs[si * ldf + sl];
+      const double fcol = lane == a ? fs[si * ldf + sj] : fs[sl * ldf + si];
+      const T rn = dnl ? (T)fnew : T(0);
+      const T uu = dnl ? (T)(fnew - fold) : T(0);
+      const T cv = lane_up ? (T)fcol : T(0);
+      if (live) {
+        xn[slot] = lane_up ? cv : T(0);
+        w[slot] = lane_up ? T(0) : uu;
+      }
+      double pr = (double)(rn * -ya), ps = (double)(yb * cv);
+      double rbm = 0.0;
+      if (RBM && M) {
+        for (int hh = lane; hh < M; hh += 64) {
+          const T d = T(2) * (WT[(int64_t)sj * M + hh] - WT[(int64_t)si * M + hh] +
+                              WT[(int64_t)(si + ns) * M + hh] - WT[(int64_t)(sj + ns) * M + hh]);
+          const T th = ths[hh];
+          rbm += (double)(log2cosh(th + d) - log2cosh(th));
+        }
+        rbm = wave_total(rbm);
+      }
+      const double rho = wave_total(pr), sig = wave_total(ps);
+      const int ylo = __builtin_amdgcn_readlane(__double2loint((double)yb), a);
+      const int yhi = __builtin_amdgcn_readlane(__double2hiint((double)yb), a);
+      const double gam = __hiloint2double(yhi, ylo);
+      wave_sync();   // c on the up half of x' for every lane
+      // t'[b''] = sum_a'' M^-1[b''][a''] c[a''] on the down lanes (x' up half)
+      T tc[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int g = 0; g < RC::NG; ++g)
+#pragma unroll
+        for (int j0 = 0; j0 < RC::GS; j0 += kChunk) {
+#pragma unroll
+          for (int j = j0; j < j0 + kChunk && j < RC::GS; ++j)
+            tc[j & 3] += z[g][j] * xn[g * RC::GS + j];
+          asm volatile("" ::: "memory");
+        }
+      const T tp = dnl ? -((tc[0] + tc[1]) + (tc[2] + tc[3])) : T(0);
+      const double ub = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint((double)uu), b),
+                                         __builtin_amdgcn_readlane(__double2loint((double)uu), b));
+      const double bet = wave_total((double)(uu * tp)) - ub;
+      const double Dd = rho * sig - bet * gam;
+      double logc = 0.0;
+      if (RBM && M)
+        logc = 2.0 * ((double)raT[sj] - (double)raT[si] + (double)raT[si + ns] -
+                      (double)raT[sj + ns]) + rbm;
+      const double Rt = Dd * exp(logc);
+      if (!isfinite(Rt)) {
+        nonfinite = true;
+        break;
+      }
+      const int accept = sgpr(uniform53(r.z, r.w) < Rt * Rt ? 1 : 0);
+      if (TRACE && lane == 0 && n - tb < (uint64_t)trace_cap) {
+        TraceRec rec;
+        rec.n = (int64_t)n; rec.walker = gw; rec.a = a; rec.i_new = sj; rec.accepted = accept;
+        rec.ratio = Rt; rec.b = b; rec.pad = 0;
+        trace[(int64_t)gw * trace_cap + (int64_t)(n - tb)] = rec;
+      }
+      if (!accept) break;
+      ++acc;
+      // s[a''] = sum_b'' u[b''] M^-1[b''][a''] on the up lanes (u on the down half of w)
+      T sc[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int g = 0; g < RC::NG; ++g)
+#pragma unroll
+        for (int j0 = 0; j0 < RC::GS; j0 += kChunk) {
+#pragma unroll
+          for (int j = j0; j < j0 + kChunk && j < RC::GS; ++j)
+            sc[j & 3] += z[g][j] * w[HD + g * RC::GS + j];
+          asm volatile("" ::: "memory");
+        }
+      const double sv = (double)((sc[0] + sc[1]) + (sc[2] + sc[3]));
+      const double iD = 1.0 / Dd;
+      // up lanes: l1, l2; down lanes: M^-1[b''][a] and t' - e_b'
+      const T l1 = (T)((sig * sv - bet * (double)yb) * iD);
+      const T l2 = (T)((rho * (double)yb - gam * sv) * iD);
+      const T cav = -ya;
+      const T tv = tp - (lane == b ? T(1) : T(0));
+      wave_sync();   // every read of c and u done
+      if (live) {
+        xn[slot] = lane_up ? l1 : cav;
+        w[slot] = lane_up ? l2 : tv;
+      }
+      wave_sync();
+      // up lanes (column of M^-1):  z -= M^-1[:, a] l1 + t l2
+      // down lanes (-row of M^-1):  z += M^-1[b'', a] l1 + t[b''] l2
+      const T ka = lane_up ? -l1 : cav;
+      const T kb = lane_up ? -l2 : tv;
+#pragma unroll
+      for (int g = 0; g < RC::NG; ++g)
+#pragma unroll
+        for (int j0 = 0; j0 < RC::GS; j0 += kChunk) {
+#pragma unroll
+          for (int j = j0; j < j0 + kChunk && j < RC::GS; ++j)
+            z[g][j] += xl[g * RC::GS + j] * ka + wl[g * RC::GS + j] * kb;
+          asm volatile("" ::: "memory");
+        }
+      // the list slots of j (up list) and i (down list)
+      int kup = -1, kdn = -1;
+      for (int c0 = 0; c0 < ns; c0 += 64) {
+        const int idx = c0 + lane;
+        const uint64_t mu = __ballot(idx < ns && emp[idx] == sj);
+        const uint64_t md = __ballot(idx < ns && emp[ns + idx] == si);
+        if (mu) kup = c0 + __builtin_ctzll(mu);
+        if (md) kdn = c0 + __builtin_ctzll(md);
+      }
+      if (RBM)
+        for (int hh = lane; hh < M; hh += 64)
+          ths[hh] += T(2) * (WT[(int64_t)sj * M + hh] - WT[(int64_t)si * M + hh] +
+                             WT[(int64_t)(si + ns) * M + hh] - WT[(int64_t)(sj + ns) * M + hh]);
+      if (lane == a) posr = sj;
+      if (lane == b) posr = si + ns;
+      if (lane == 0) {
+        eidx[si] = -1;
+        eidx[sj + ns] = -1;
+        eidx[sj] = a;
+        eidx[si + ns] = b;
+        emp[kup] = si;
+        emp[ns + kdn] = sj;
+      }
+      wave_sync();
+      break;
+    }
     const int a = opaque(sgpr(scaled(r.x, ne)));
     const int sigma = a >= nh ? 1 : 0;
     if (nemp == 0) {
       if (TRACE && lane == 0 && n - tb < (uint64_t)trace_cap) {
         TraceRec rec;
+        rec.b = -1; rec.pad = 0;
         rec.n = (int64_t)n; rec.walker = gw; rec.a = a; rec.i_new = -1; rec.accepted = 0;
         rec.ratio = 0.0;
         trace[(int64_t)gw * trace_cap + (int64_t)(n - tb)] = rec;
@@ -401,6 +560,7 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep_reg(Pools P, const int32_t* 
     const int accept = sgpr(u < Rt * Rt ? 1 : 0);
     if (TRACE && lane == 0 && n - tb < (uint64_t)trace_cap) {
       TraceRec rec;
+      rec.b = -1; rec.pad = 0;
       rec.n = (int64_t)n; rec.walker = gw; rec.a = a; rec.i_new = Inew; rec.accepted = accept;
       rec.ratio = Rt;
       trace[(int64_t)gw * trace_cap + (int64_t)(n - tb)] = rec;
@@ -528,32 +688,38 @@ template <typename T>
 bool launch_sweep_reg(const Pools& P, const int32_t* wlist, int n_groups, int ne_max, int max_ns,
                       int max_M, int cap, uint64_t seed, TraceRec* trace, int64_t trace_cap,
                       const uint64_t* trace_base, const uint64_t* target, int32_t* needs_refresh,
-                      int R, int kref, hipStream_t s) {
+                      int R, int kref, int ex64, hipStream_t s) {
   constexpr int WPB = 4;
   if (n_groups <= 0 || cap <= 0) return true;
   const size_t sh = sweep_reg_lds_bytes(ne_max, max_ns, max_M, sizeof(T), WPB);
-#define MVMC_REG_V(NEM, TR, RB)                                                                  \
+#define MVMC_REG_V(NEM, TR, RB, EX)                                                              \
   do {                                                                                           \
     if (sh > 65536)                                                                              \
-      (void)hipFuncSetAttribute((const void*)&k_sweep_reg<T, NEM, WPB, TR, RB>,                  \
+      (void)hipFuncSetAttribute((const void*)&k_sweep_reg<T, NEM, WPB, TR, RB, EX>,              \
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);            \
-    hipLaunchKernelGGL((k_sweep_reg<T, NEM, WPB, TR, RB>), dim3(n_groups), dim3(64 * WPB), sh,   \
-                       s, P, wlist, cap, seed, trace, trace_cap, trace_base, target,             \
-                       needs_refresh, R, kref);                                                  \
+    hipLaunchKernelGGL((k_sweep_reg<T, NEM, WPB, TR, RB, EX>), dim3(n_groups), dim3(64 * WPB),   \
+                       sh, s, P, wlist, cap, seed, trace, trace_cap, trace_base, target,         \
+                       needs_refresh, R, kref, ex64);                                            \
     return true;                                                                                 \
+  } while (0)
+#define MVMC_REG_E(NEM, EX)                                                                      \
+  do {                                                                                           \
+    if (trace) {                                                                                 \
+      if (max_M > 0) MVMC_REG_V(NEM, true, true, EX);                                            \
+      MVMC_REG_V(NEM, true, false, EX);                                                          \
+    }                                                                                            \
+    if (max_M > 0) MVMC_REG_V(NEM, false, true, EX);                                             \
+    MVMC_REG_V(NEM, false, false, EX);                                                           \
   } while (0)
 #define MVMC_REG(NEM)                                                                            \
   do {                                                                                           \
-    if (trace) {                                                                                 \
-      if (max_M > 0) MVMC_REG_V(NEM, true, true);                                                \
-      MVMC_REG_V(NEM, true, false);                                                              \
-    }                                                                                            \
-    if (max_M > 0) MVMC_REG_V(NEM, false, true);                                                 \
-    MVMC_REG_V(NEM, false, false);                                                               \
+    if (ex64 > 0) MVMC_REG_E(NEM, true);                                                         \
+    MVMC_REG_E(NEM, false);                                                                      \
   } while (0)
   if (ne_max == 32) MVMC_REG(32);
   if (ne_max == 64) MVMC_REG(64);
 #undef MVMC_REG_V
+#undef MVMC_REG_E
 #undef MVMC_REG
   return false;
 }
@@ -567,9 +733,9 @@ int sweep_reg_class(int ne, size_t tsize) {
 
 template bool launch_sweep_reg<double>(const Pools&, const int32_t*, int, int, int, int, int,
                                        uint64_t, TraceRec*, int64_t, const uint64_t*,
-                                       const uint64_t*, int32_t*, int, int, hipStream_t);
+                                       const uint64_t*, int32_t*, int, int, int, hipStream_t);
 template bool launch_sweep_reg<float>(const Pools&, const int32_t*, int, int, int, int, int,
                                       uint64_t, TraceRec*, int64_t, const uint64_t*,
-                                      const uint64_t*, int32_t*, int, int, hipStream_t);
+                                      const uint64_t*, int32_t*, int, int, int, hipStream_t);
 
 }  // namespace mvmc

@@ -56,7 +56,7 @@ template <typename T>
 void launch_sweep_ap(const Pools& P, const int32_t* wlist, int n, int cap, uint64_t seed,
                      int max_ne, int max_ns, int max_M, int nthreads, TraceRec* trace,
                      int64_t trace_cap, const uint64_t* trace_base, const uint64_t* target,
-                     int32_t* needs_refresh, int R, hipStream_t s);
+                     int32_t* needs_refresh, int R, int ex64, hipStream_t s);
 size_t sweep_ap_lds_bytes(int ne, int ns, int M, size_t tsize, int nthreads);
 
 // k_sweep_reg.hip: register-resident sweep, one wavefront per walker, groups
@@ -66,7 +66,7 @@ template <typename T>
 bool launch_sweep_reg(const Pools& P, const int32_t* wlist, int n_groups, int ne_max, int max_ns,
                       int max_M, int cap, uint64_t seed, TraceRec* trace, int64_t trace_cap,
                       const uint64_t* trace_base, const uint64_t* target, int32_t* needs_refresh,
-                      int R, int kref, hipStream_t s);
+                      int R, int kref, int ex64, hipStream_t s);
 size_t sweep_reg_lds_bytes(int ne_max, int ns, int M, size_t tsize, int wpb);
 int sweep_reg_class(int ne, size_t tsize);   // register tier for ne, 0 = none
 

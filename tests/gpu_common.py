@@ -46,7 +46,8 @@ def good_configs(inst, params, n: int, seed: int, cond_max: float = 1e5) -> np.n
     return np.array(out, dtype=np.int32)
 
 
-def oracle_trajectories(inst, params, pos0: np.ndarray, gid0: int, n_prop: int, seed: int):
+def oracle_trajectories(inst, params, pos0: np.ndarray, gid0: int, n_prop: int, seed: int,
+                        ex64: int = 0):
     """Run the oracle chain of every walker; returns (walkers, model)."""
     m = wf.expand(inst, params)
     A = wf.skew_table(m)
@@ -54,13 +55,45 @@ def oracle_trajectories(inst, params, pos0: np.ndarray, gid0: int, n_prop: int, 
     for w in range(len(pos0)):
         wk = sampler.make_walker(m, pos0[w], gid=gid0 + w)
         for _ in range(n_prop):
-            sampler.step(m, wk, seed, A, record=True)
+            sampler.step(m, wk, seed, A, record=True, ex64=ex64)
         ws.append(wk)
     return ws, m
 
 
+def exchange_term_scale(m, A, pos, a: int, b: int, inew: int) -> float:
+    """Magnitude of the two products whose difference is an exchange ratio:
+    with Y the exact inverse of X and M^-1[b'][a'] = Y[n + b'][a'], the
+    determinant lemma gives det M'/det M = rho sigma - beta gamma
+    (rho: new row a against column a of M^-1; sigma: new column b against
+    row b; beta = u . M^-1 c - u_b; gamma = M^-1[b][a]).  Rounding in the
+    fast update is relative to |rho sigma| + |beta gamma| times the correlator
+    factor, which is what a ratio far below that scale cancels."""
+    ns, n = m.n_sites, m.n_up
+    X = A[np.ix_(pos, pos)]
+    Y = np.linalg.inv(X)
+    Mi = Y[n:, :n]
+    f = A[:ns, ns:]
+    bd = b - n
+    si, sj = int(pos[a]), int(pos[b]) - ns
+    sdn = np.asarray(pos[n:]) - ns
+    sup = np.asarray(pos[:n])
+    rn = f[sj, sdn].copy()
+    rn[bd] = f[sj, si]
+    u = rn - f[si, sdn]
+    c = f[sup, si].copy()
+    c[a] = f[si, sj]
+    rho = rn @ Mi[:, a]
+    sig = Mi[bd, :] @ c
+    bet = u @ (Mi @ c) - u[bd]
+    gam = Mi[bd, a]
+    new = np.array(pos).copy()
+    new[a], new[b] = sj, si + ns
+    corr = np.exp(wf.log_correlators(m, new) - wf.log_correlators(m, pos))
+    return float(corr * (abs(rho * sig) + abs(bet * gam)))
+
+
 def compare_trace(rec: np.ndarray, walkers, n_prop: int, seed: int, rtol: float = 1e-10,
-                  floor: float = 1e-6) -> dict:
+                  floor: float = 1e-6, model=None, pos0=None) -> dict:
     """Compare GPU trace records with oracle traces (double precision).
 
     Ratio error is |R_gpu - R| / max(|R|, floor); every decision must match
@@ -71,15 +104,29 @@ def compare_trace(rec: np.ndarray, walkers, n_prop: int, seed: int, rtol: float 
     worst = 0.0
     diverged = 0
     errors = []
+    A = wf.skew_table(model) if model is not None else None
     for w, wk in enumerate(walkers):
+        pos = None if pos0 is None else np.array(pos0[w], dtype=np.int64)
         for k in range(n_prop):
             n, a, inew, R, acc, b = wk.trace[k]
             g = rec[w, k]
             assert int(g["n"]) == n, (w, k, int(g["n"]), n)
             assert int(g["a"]) == a and int(g["i_new"]) == inew, (w, k, g, wk.trace[k])
+            assert int(g["b"]) == b, (w, k, int(g["b"]), b)
             if inew < 0:
                 continue
-            err = abs(float(g["ratio"]) - R) / max(abs(R), floor)
+            scale = max(abs(R), floor)
+            if b >= 0:
+                # an exchange ratio is a difference of two products (2 x 2
+                # determinant lemma); its rounding is relative to their size
+                assert A is not None and pos is not None, "exchange traces need model and pos0"
+                scale = max(scale, exchange_term_scale(model, A, pos, a, b, inew))
+            if pos is not None and acc:
+                if b >= 0:
+                    pos[a], pos[b] = inew, int(pos[a]) + model.n_sites
+                else:
+                    pos[a] = inew
+            err = abs(float(g["ratio"]) - R) / scale
             worst = max(worst, err)
             errors.append(err)
             assert err <= rtol, (w, k, float(g["ratio"]), R, err)
