@@ -162,6 +162,25 @@ int mvmc_init_wavefunction(mvmc_ctx **out, const mvmc_config *cfg, void *d_works
                            size_t ws_bytes, const double *d_params, void *hip_stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * context as mvmc_init_wavefunction, with the workspace taken from a static
+ * array of MVMC_STATIC_WORKSPACE_BYTES in the library's device memory (one
+ * per device, held until the process ends) instead of a caller buffer.  The
+ * call allocates no device memory and no pinned host memory.
+ * Every static context on a device shares that device's array: creating a
+ * second one overwrites the first, and calls on two static contexts of one
+ * device race.  The array keeps the last context's contents; this call
+ * rewrites everything the context reads before use.
+ * Errors: those of mvmc_init_wavefunction; MVMC_E_WORKSPACE when the
+ * configuration needs more than MVMC_STATIC_WORKSPACE_BYTES (workspace_bytes
+ * of mvmc_query_sizes).
+ */
+#define MVMC_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+int mvmc_init_wavefunction_static(mvmc_ctx **out, const mvmc_config *cfg, const double *d_params,
+                                  void *hip_stream);
+
+/*
  * n_sweeps sweeps of every walker; one sweep is N_e hopping proposals
  * (section 3.1.2), each accepted with probability min(1, R^2), R = psi(x')/psi(x)
  * from a row of X^-1 and the correlator ratios, followed on acceptance by the

@@ -23,7 +23,7 @@ ENTRY_POINTS = (
     "mvmc_get_state", "mvmc_set_state", "mvmc_get_inverse", "mvmc_get_pfaffian", "mvmc_refresh",
     "mvmc_trace_enable", "mvmc_timing", "mvmc_destroy", "mvmc_last_error", "mvmc_status_string",
     "mvmc_autotune", "mvmc_sweep_variants", "mvmc_s_tiles", "mvmc_set_s_tile",
-    "mvmc_peak_probe_bytes", "mvmc_peak_probe",
+    "mvmc_peak_probe_bytes", "mvmc_peak_probe", "mvmc_init_wavefunction_static",
 )
 N_SWEEP_VARIANTS = 10
 SWEEP_VARIANT_NAMES = ("reg", "lds64", "lds128", "lds256", "hbm64", "hbm128", "hbm256",
@@ -96,6 +96,7 @@ def load() -> C.CDLL:
         "mvmc_query_sizes": [C.POINTER(Config), C.POINTER(Sizes)],
         "mvmc_query_layout": [C.POINTER(Config), i32, C.POINTER(Layout)],
         "mvmc_init_wavefunction": [C.POINTER(vp), C.POINTER(Config), vp, C.c_size_t, vp, vp],
+        "mvmc_init_wavefunction_static": [C.POINTER(vp), C.POINTER(Config), vp, vp],
         "mvmc_sample_sweeps": [vp, i32, vp],
         "mvmc_measure_energy_and_O": [vp, i32, vp, vp],
         "mvmc_build_sr": [vp, i32, vp, vp, vp, vp, vp, vp, vp],
@@ -207,9 +208,11 @@ class MVMC:
 
     def __init__(self, instances, params, *, precision="fp64", refresh_every=0, seed=1,
                  n_slots=1, solver="chol", build_s=True, sweep_threads=0, sweep_variant=None,
-                 exchange_per64=0, device="cuda:0", stream=None):
+                 exchange_per64=0, device="cuda:0", stream=None, static_workspace=False):
         """stream: torch.cuda.Stream for all of the context's work (default: the
-        current stream).  A non-default stream is needed for graph capture."""
+        current stream).  A non-default stream is needed for graph capture.
+        static_workspace: take the workspace from the library's static device
+        array (mvmc_init_wavefunction_static) instead of allocating it."""
         import torch
         self.torch = torch
         self.lib = load()
@@ -223,8 +226,12 @@ class MVMC:
         self.n_inst = len(self.instances)
         odt = torch.float64 if precision == "fp64" else torch.float32
         dev = self.device
-        self.ws = torch.empty(int(self.sizes.workspace_bytes) + 256, dtype=torch.uint8, device=dev)
-        self._ws_ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        if static_workspace:
+            self.ws = None
+        else:
+            self.ws = torch.empty(int(self.sizes.workspace_bytes) + 256, dtype=torch.uint8,
+                                  device=dev)
+            self._ws_ptr = (self.ws.data_ptr() + 255) // 256 * 256
         self.params = torch.as_tensor(np.asarray(params, dtype=np.float64)).to(dev).contiguous()
         assert self.params.numel() == self.sizes.n_params
         self.eloc = torch.zeros(int(self.sizes.eloc_elems), dtype=torch.float64, device=dev)
@@ -235,11 +242,16 @@ class MVMC:
         self.dparams = torch.zeros_like(self.g)
         self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
         self.ctx = C.c_void_p()
-        rc = self.lib.mvmc_init_wavefunction(C.byref(self.ctx), C.byref(self.cfg),
-                                             C.c_void_p(self._ws_ptr),
-                                             int(self.sizes.workspace_bytes),
-                                             C.c_void_p(self.params.data_ptr()),
-                                             C.c_void_p(self.stream.cuda_stream))
+        if static_workspace:
+            rc = self.lib.mvmc_init_wavefunction_static(C.byref(self.ctx), C.byref(self.cfg),
+                                                        C.c_void_p(self.params.data_ptr()),
+                                                        C.c_void_p(self.stream.cuda_stream))
+        else:
+            rc = self.lib.mvmc_init_wavefunction(C.byref(self.ctx), C.byref(self.cfg),
+                                                 C.c_void_p(self._ws_ptr),
+                                                 int(self.sizes.workspace_bytes),
+                                                 C.c_void_p(self.params.data_ptr()),
+                                                 C.c_void_p(self.stream.cuda_stream))
         if rc:
             raise MVMCError(rc, self.lib.mvmc_status_string(rc).decode())
         self._trace = None

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -536,7 +537,9 @@ struct mvmc_ctx {
   int64_t trace_cap = 0;
   bool sr_ready = false;
   std::string err;
-  SrInst* h_sr = nullptr;           // pinned staging of the SR table
+  SrInst* h_sr = nullptr;           // staging of the SR table (pinned unless no_alloc)
+  std::vector<SrInst> h_sr_plain;   // its pageable storage for a no-allocation context
+  bool no_alloc = false;            // workspace is the static per-device array
   int n_cu = 256;                   // compute units of the device
   bool s_tune = false;              // time the S tile sides at the next mvmc_build_sr
   std::vector<double> s_tile_ms;    // [instance][tile side 128, 192, 256] of the last tuning
@@ -848,8 +851,11 @@ int mvmc_query_layout(const mvmc_config* cfg, int32_t k, mvmc_instance_layout* o
   return MVMC_OK;
 }
 
-int mvmc_init_wavefunction(mvmc_ctx** out, const mvmc_config* cfg, void* d_ws, size_t ws_bytes,
-                           const double* d_params, void* hip_stream) {
+}  // extern "C"
+
+namespace {
+int init_impl(mvmc_ctx** out, const mvmc_config* cfg, void* d_ws, size_t ws_bytes,
+              const double* d_params, void* hip_stream, bool no_alloc) {
   if (!out) return MVMC_E_ARG;
   *out = nullptr;
   Err e = validate(cfg);
@@ -858,6 +864,7 @@ int mvmc_init_wavefunction(mvmc_ctx** out, const mvmc_config* cfg, void* d_ws, s
   if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) return MVMC_E_WORKSPACE;
   mvmc_ctx* c = new (std::nothrow) mvmc_ctx;
   if (!c) return MVMC_E_ARG;
+  c->no_alloc = no_alloc;
   c->cfg = *cfg;
   c->desc.assign(cfg->inst, cfg->inst + cfg->n_instances);
   c->cfg.inst = c->desc.data();
@@ -979,7 +986,12 @@ int mvmc_init_wavefunction(mvmc_ctx** out, const mvmc_config* cfg, void* d_ws, s
   chk(hipMemset(b + P.needs_refresh.off, 0, 4 * P.W));
   chk(hipMemset(Q.theta, 0, 8 * std::max<size_t>(P.theta.bytes / 8, 1)));
   chk(hipMemset(S.scal, 0, P.scal.bytes));
-  chk(hipHostMalloc((void**)&c->h_sr, sizeof(SrInst) * P.sr.size(), hipHostMallocDefault));
+  if (c->no_alloc) {
+    c->h_sr_plain.resize(P.sr.size());
+    c->h_sr = c->h_sr_plain.data();
+  } else {
+    chk(hipHostMalloc((void**)&c->h_sr, sizeof(SrInst) * P.sr.size(), hipHostMallocDefault));
+  }
   if (he != hipSuccess) {
     c->err = std::string("init upload: ") + hipGetErrorString(he);
     mvmc_destroy(c);
@@ -1035,13 +1047,67 @@ int mvmc_init_wavefunction(mvmc_ctx** out, const mvmc_config* cfg, void* d_ws, s
   return MVMC_OK;
 }
 
+// The workspace of contexts made by mvmc_init_wavefunction_static: one array
+// per device in the code object's device memory.  Host code addresses it
+// only through the pointer hipGetSymbolAddress returns for the current device.
+constexpr size_t kStaticWorkspaceBytes = MVMC_STATIC_WORKSPACE_BYTES;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+
+extern "C" {
+
+int mvmc_init_wavefunction(mvmc_ctx** out, const mvmc_config* cfg, void* d_ws, size_t ws_bytes,
+                           const double* d_params, void* hip_stream) {
+  return init_impl(out, cfg, d_ws, ws_bytes, d_params, hip_stream, false);
+}
+
+int mvmc_init_wavefunction_static(mvmc_ctx** out, const mvmc_config* cfg, const double* d_params,
+                                  void* hip_stream) {
+  if (!out) return MVMC_E_ARG;
+  *out = nullptr;
+  Err e = validate(cfg);
+  if (e.code) return e.code;
+  const Plan P = make_plan(*cfg);
+  if (P.bad_variant >= 0) return MVMC_E_SHAPE;
+  if (P.total > kStaticWorkspaceBytes) {
+    std::fprintf(stderr,
+                 "mvmc_init_wavefunction_static: the configuration needs %zu bytes of workspace; "
+                 "the static workspace holds %zu\n",
+                 P.total, kStaticWorkspaceBytes);
+    return MVMC_E_WORKSPACE;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return MVMC_E_HIP;
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void* p = nullptr;
+      const hipError_t he = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (he != hipSuccess || !p) {
+        std::fprintf(stderr, "mvmc_init_wavefunction_static: hipGetSymbolAddress: %s\n",
+                     hipGetErrorString(he));
+        return MVMC_E_HIP;
+      }
+      g_scratch_ptr[dev] = p;
+    }
+    ws = g_scratch_ptr[dev];
+  }
+  return init_impl(out, cfg, ws, kStaticWorkspaceBytes, d_params, hip_stream, true);
+}
+
 int mvmc_destroy(mvmc_ctx* c) {
   if (!c) return MVMC_OK;
   for (auto& e : c->ev_pool) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
   }
-  if (c->h_sr) (void)hipHostFree(c->h_sr);
+  if (c->h_sr && !c->no_alloc) (void)hipHostFree(c->h_sr);
   delete c;
   return MVMC_OK;
 }
