@@ -59,24 +59,35 @@ def solve_cholesky(Sr: np.ndarray, b: np.ndarray) -> np.ndarray:
 
 
 def cg(matvec, b: np.ndarray, x0: np.ndarray, eps: float, kmax: int) -> tuple[np.ndarray, int]:
-    """Algorithm 1: conjugate gradients with stop rule ||r||^2 < eps^2 ||b||^2."""
-    thresh = eps * eps * float(b @ b)
-    x = x0.copy()
-    r = b - matvec(x)
-    p = r.copy()
-    rho = float(r @ r)
-    it = 0
-    for it in range(1, kmax + 1):
-        w = matvec(p)
-        alpha = rho / float(p @ w)
-        x = x + alpha * p
-        r = r - alpha * w
-        rho_new = float(r @ r)
-        if rho_new < thresh:
+    """Conjugate gradients for a symmetric positive-definite A (A x = b).
+
+    Textbook derivation (Hestenes and Stiefel): minimise the quadratic
+    q(x) = x.A.x / 2 - b.x, whose gradient is -r with r = b - A x.  From x the
+    search goes along a direction d: the exact minimum of q on x + s d is at
+    s = r.r / d.A.d (for the d built below), after which the residual is
+    r - s A d.  The next direction is the new residual made A-conjugate to
+    d, r + (r'.r' / r.r) d, so every step minimises q over the whole Krylov
+    space seen so far.  The stopping rule is that of Algorithm 1
+    (section 3.3.2): stop once |r|^2 < eps^2 |b|^2, or after kmax steps.
+    Returns the solution and the number of steps taken."""
+    x = np.array(x0, dtype=np.float64, copy=True)
+    res = b - matvec(x)
+    direction = res.copy()
+    res2 = float(res @ res)
+    stop2 = eps * eps * float(b @ b)
+    steps = 0
+    while steps < kmax:
+        steps += 1
+        a_dir = matvec(direction)
+        s = res2 / float(direction @ a_dir)      # exact line minimum
+        x += s * direction
+        res -= s * a_dir
+        res2_next = float(res @ res)
+        if res2_next < stop2:
             break
-        p = r + (rho_new / rho) * p
-        rho = rho_new
-    return x, it
+        direction = res + (res2_next / res2) * direction   # A-conjugate to the last
+        res2 = res2_next
+    return x, steps
 
 
 def matrix_free_matvec(Oc: np.ndarray, shift: np.ndarray, keep: np.ndarray):
