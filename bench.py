@@ -42,7 +42,7 @@ KINDS = ["sweep", "refresh", "measure", "sr_stats", "s_build", "sr_solve"]
 # the dominant kernel of the headline step and the committed counter summary
 # of its HBM traffic (bench reports traffic = null once its sources change)
 TRAFFIC_SUMMARY = "sweep_ap_fp64_sq10_traffic.txt"
-TRAFFIC_SOURCES = ("k_sweep_ap.hip", "common.h", "launch.h")
+TRAFFIC_SOURCES = ("k_sweep_ap.hip", "ap_walk.h", "common.h", "launch.h")
 
 
 def log(msg):
@@ -50,7 +50,8 @@ def log(msg):
 
 
 def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", sweep_threads=0,
-                    use_graph=True, autotune=False, build_s=True, cg_tol=1e-10, cg_maxit=1000):
+                    use_graph=True, autotune=False, build_s=True, cg_tol=1e-10, cg_maxit=1000,
+                    schedule="buckets"):
     """Time whole SR steps of every instance of the workload.  With use_graph
     the sampling part of a step (the sweeps and the measurements) is captured
     once into a HIP graph and replayed; the SR build and update run eagerly.
@@ -71,7 +72,7 @@ def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", 
     with torch.cuda.stream(side):
         ctx = MVMC(insts, params, precision=precision, refresh_every=refresh_every,
                    seed=wl["sampler_seed"], n_slots=slots, solver=solver, build_s=build_s,
-                   sweep_threads=sweep_threads, stream=side)
+                   sweep_threads=sweep_threads, stream=side, schedule=schedule)
         for _ in range(wl["warmup"]):   # one launch per sweep, as in the timed steps
             ctx.sample_async(1)
         torch.cuda.synchronize()
@@ -458,42 +459,55 @@ def rbm_leg(steps):
 
 def batch_leg(steps):
     """32 ragged clusters (square L = 4..12, U in [2, 10], filling 0.8-1.0,
-    256 walkers each), mixed precision, each instance its own SR step;
-    variants autotuned."""
+    256 walkers each), mixed precision, each instance its own SR step.  Both
+    schedules: the persistent queue launch (one sweep launch per call,
+    walkers longest first, refreshes inside the launch) and the per-bucket
+    launches with autotuned variants; the faster one is the leg's value."""
     from mvmc_inputs import workload
     wl = workload("batch32_ragged")
-    r = run_sr_workload(wl, "mixed", steps, 1, wl["refresh_every"], use_graph=True,
-                        autotune=True)
     insts = wl["instances"]
-    return {"value": r["rate"], "unit": "hop-updates/s", "ms_per_step": r["ms_per_step"],
-            "instances": len(insts), "walkers": sum(i.n_walkers for i in insts),
-            "n_elec_range": [min(i.n_elec for i in insts), max(i.n_elec for i in insts)],
-            "sweeps_per_step": r["sweeps"], "accept_ratio": r["accept_ratio"],
-            "kernel_ms_per_step": km(r), "autotune": r["autotune"],
-            "energy_per_site_last_step": [e / i.n_sites for e, i in zip(r["energies"][-1], insts)]}
+    out = {"instances": len(insts), "walkers": sum(i.n_walkers for i in insts),
+           "n_elec_range": [min(i.n_elec for i in insts), max(i.n_elec for i in insts)]}
+    for sched in ("queue", "buckets"):
+        log(f"[bench] batch32_ragged {sched}")
+        r = run_sr_workload(wl, "mixed", steps, 1, wl["refresh_every"], use_graph=True,
+                            autotune=sched == "buckets", schedule=sched)
+        leg = {"value": r["rate"], "unit": "hop-updates/s", "ms_per_step": r["ms_per_step"],
+               "sweeps_per_step": r["sweeps"], "accept_ratio": r["accept_ratio"],
+               "kernel_ms_per_step": km(r),
+               "energy_per_site_last_step": [e / i.n_sites
+                                             for e, i in zip(r["energies"][-1], insts)]}
+        if sched == "buckets":
+            leg["autotune"] = r["autotune"]
+        out[sched] = leg
+    best = min(("queue", "buckets"), key=lambda k: out[k]["ms_per_step"])
+    out.update({k: v for k, v in out[best].items() if k != "autotune"})
+    out["schedule"] = best
+    return out
 
 
 def rbm_gain(sr_steps):
-    """16x16, U = 8, N_e = 224: the plain Pfaffian-Jastrow(-Gutzwiller) state
-    and the same state times the RBM factor, each trained by SR from the same
-    start on the same GPU with the same sampler settings (8192 walkers, 10
-    sweeps and one sample per walker per step); the energy of each trained
-    state is then estimated with the same number of samples."""
+    """16x16, U = 8, N_e = 224, 8192 walkers, 10 sweeps and one sample per
+    walker per SR step.  The plain Pfaffian-Jastrow(-Gutzwiller) state is
+    first trained by SR for sr_steps steps; from that state two runs of
+    sr_steps more steps follow on the same GPU with the same sampler seed:
+    the plain state alone, and the same state times an RBM factor whose
+    parameters start small (a tenth of the workload's RBM draw, so the
+    product starts at the trained state's energy).  Each final state's
+    energy is then estimated with the same number of samples (16 per walker,
+    5 sweeps apart)."""
     import numpy as np
 
     from mvmc_inputs import workload
     from paper_1711_11418_amd import MVMC
 
-    out = {}
-    for tag, name in (("pj", "sq16_u8_pj"), ("pj_rbm", "sq16_u8_rbm")):
-        wl = workload(name)
-        inst = wl["instances"][0]
-        ctx = MVMC([inst], inst.params0, precision="mixed", refresh_every=wl["refresh_every"],
+    def train(inst, params, wl, tag, steps):
+        ctx = MVMC([inst], params, precision="mixed", refresh_every=wl["refresh_every"],
                    seed=wl["sampler_seed"], n_slots=1, solver="cg", build_s=False)
         ctx.sample(wl["warmup"])
         hist, iters = [], []
         t0 = time.perf_counter()
-        for it in range(sr_steps):
+        for it in range(steps):
             ctx.sample_async(wl["sweeps"])
             ctx.measure(0)
             E, Er, _ = ctx.build_sr(1, with_S=False)
@@ -505,23 +519,33 @@ def rbm_gain(sr_steps):
                 log(f"[rbm-gain] {tag} step {it}: E/N = {hist[-1][0]:.5f} +- {hist[-1][1]:.5f}, "
                     f"CG {iters[-1]}")
         train_s = time.perf_counter() - t0
-        # the trained state: 16 samples per walker, 5 sweeps apart
-        slots = 16
-        ev = MVMC([inst], ctx.params.cpu().numpy(), precision="mixed",
-                  refresh_every=wl["refresh_every"], seed=wl["sampler_seed"] + 7, n_slots=slots,
-                  solver="cg", build_s=False)
+        p = ctx.params.cpu().numpy().copy()
         ctx.close()
+        return p, {"n_params": inst.n_params, "sr_steps": steps, "train_seconds": train_s,
+                   "history_per_site": hist, "cg_iterations": iters}
+
+    def evaluate(inst, params, wl):
+        slots = 16
+        ev = MVMC([inst], params, precision="mixed", refresh_every=wl["refresh_every"],
+                  seed=wl["sampler_seed"] + 7, n_slots=slots, solver="cg", build_s=False)
         ev.sample(wl["warmup"])
         for s in range(slots):
             ev.sample_async(5)
             ev.measure(s)
         E, Er, _ = ev.build_sr(slots, with_S=False)
         ev.close()
-        out[tag] = {"n_params": inst.n_params, "sr_steps": sr_steps, "train_seconds": train_s,
-                    "energy_per_site": float(E[0]) / inst.n_sites,
-                    "sigma_per_site": float(Er[0]) / inst.n_sites,
-                    "samples": slots * inst.n_walkers, "history_per_site": hist,
-                    "cg_iterations": iters}
+        return {"energy_per_site": float(E[0]) / inst.n_sites,
+                "sigma_per_site": float(Er[0]) / inst.n_sites, "samples": slots * inst.n_walkers}
+
+    wl_pj, wl_rbm = workload("sq16_u8_pj"), workload("sq16_u8_rbm")
+    pj, rbm = wl_pj["instances"][0], wl_rbm["instances"][0]
+    p1, pre = train(pj, pj.params0, wl_pj, "pj (first)", sr_steps)
+    out = {"pretrain": pre, "pretrained": evaluate(pj, p1, wl_pj)}
+    p_pj, out["pj"] = train(pj, p1, wl_pj, "pj", sr_steps)
+    out["pj"].update(evaluate(pj, p_pj, wl_pj))
+    p0_rbm = np.concatenate([p1, 0.1 * rbm.params0[pj.n_params:]])
+    p_rbm, out["pj_rbm"] = train(rbm, p0_rbm, wl_rbm, "pj_rbm", sr_steps)
+    out["pj_rbm"].update(evaluate(rbm, p_rbm, wl_rbm))
     d = out["pj_rbm"]["energy_per_site"] - out["pj"]["energy_per_site"]
     out["gain_per_site"] = -d
     out["gain_over_sigma"] = -d / float(np.hypot(out["pj_rbm"]["sigma_per_site"],
@@ -675,6 +699,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="launch the sampling eagerly")
     ap.add_argument("--s-build-only", action="store_true",
                     help="print only the split-bf16 S build leg (for kernel profiling)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="print only the ragged-batch leg (queue and bucket schedules)")
     ap.add_argument("--rbm-gain", action="store_true",
                     help="train 16x16 PJ and PJ x RBM by SR and print their energies")
     ap.add_argument("--sr-steps", type=int, default=40)
@@ -692,6 +718,9 @@ def main():
         return
     if a.rbm_gain:
         print(json.dumps({"rbm_gain_sq16": rbm_gain(a.sr_steps)}), flush=True)
+        return
+    if a.batch_only:
+        print(json.dumps({"batch32_ragged": batch_leg(max(1, a.steps - 1))}), flush=True)
         return
 
     copy = hbm_copy_probe()
@@ -755,7 +784,7 @@ def main():
         log(f"[bench]   16x16 {out['sq16_u8_rbm']['value']:.3e} hop-updates/s, "
             f"{out['sq16_u8_rbm']['ms_per_step']:.0f} ms/step, CG "
             f"{out['sq16_u8_rbm']['cg_iterations']}")
-        log("[bench] ragged batch of 32 clusters (mixed, autotuned)")
+        log("[bench] ragged batch of 32 clusters (mixed; queue, then autotuned buckets)")
         out["batch32_ragged"] = batch_leg(max(1, a.steps - 1))
     if not a.no_cpu:
         log("[bench] CPU oracle baseline")

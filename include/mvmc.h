@@ -102,7 +102,19 @@ typedef struct {
   int32_t exchange_per64;     /* 0..64: a proposal is an exchange update (section 3.1.2,
                                  Fig. 5b) with probability exchange_per64/64, else a hop;
                                  needs the register or anti-parallel-block sweep */
+  int32_t schedule;           /* MVMC_SCHED_BUCKETS: one launch per group of instances that
+                                 share a sweep variant and LDS class, refresh launches at
+                                 every multiple of refresh_every.  MVMC_SCHED_QUEUE: one
+                                 persistent launch per mvmc_sample_sweeps call for every
+                                 instance, walkers taken longest first (cost ~ N_e^2) from
+                                 a device queue; the register tier (variant 0) where it
+                                 fits, else the anti-parallel-block sweep with 256 threads
+                                 (variant 9, N_e <= 256), both refreshing inside the launch;
+                                 sweep_variant may force 1 or 10, sweep_threads must be 0 */
 } mvmc_config;
+
+#define MVMC_SCHED_BUCKETS 0
+#define MVMC_SCHED_QUEUE 1
 
 /* Sizes of the caller-owned buffers for a configuration. */
 typedef struct {
@@ -228,6 +240,7 @@ enum { MVMC_N_SWEEP_VARIANTS = 10 };
  * with wide parameter sets (at least 512 upper-triangle tiles of 128) at
  * tile sides 128, 192 and 256 on that call's own data and keeps the fastest;
  * that call synchronises the stream.
+ * With MVMC_SCHED_QUEUE the variants are fixed: MVMC_E_ARG.
  * Errors: MVMC_E_ARG, MVMC_E_HIP.
  */
 int mvmc_autotune(mvmc_ctx *ctx, int32_t n_sweeps, const char *cache_path, double *h_ms);

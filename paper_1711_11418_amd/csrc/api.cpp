@@ -47,6 +47,7 @@ struct Plan {
   std::vector<char> sweep_ap;     // 1 = anti-parallel-block sweep (M^-1 alone in LDS)
   int bad_variant = -1;           // instance a forced sweep variant does not fit
   bool exchange = false;          // exchange updates on (variants 0 and 7-9 only)
+  bool queue = false;             // one persistent sweep launch (variants 0 and 9 only)
   // pools (byte offsets into the workspace)
   Pool inst_p, srinst_p, walker_inst, lists, A64, A32, V, fidx, vidx, G, U, gidx, nbr_ptr,
       nbr_site, nbr_t, fm_ptr, fm, gm_ptr, gm, vm_ptr, vm, rbm64, rbm32, rbmT64, rbmT32, Y, Y64,
@@ -149,6 +150,14 @@ Err validate(const mvmc_config* c) {
     return fail(MVMC_E_ARG, "exchange updates need the register or anti-parallel-block sweep");
   if (c->sweep_variant < 0 || c->sweep_variant > MVMC_N_SWEEP_VARIANTS)
     return fail(MVMC_E_ARG, "sweep_variant must be 0 (automatic) or 1 + a variant");
+  if (c->schedule != MVMC_SCHED_BUCKETS && c->schedule != MVMC_SCHED_QUEUE)
+    return fail(MVMC_E_ARG, "schedule must be MVMC_SCHED_BUCKETS or MVMC_SCHED_QUEUE");
+  if (c->schedule == MVMC_SCHED_QUEUE && c->sweep_threads)
+    return fail(MVMC_E_ARG, "the queue schedule takes sweep_threads = 0");
+  if (c->schedule == MVMC_SCHED_QUEUE && c->sweep_variant != 0 && c->sweep_variant != 1 &&
+      c->sweep_variant != 10)
+    return fail(MVMC_E_ARG, "the queue schedule runs variants 0 and 9 only (sweep_variant 0, 1 "
+                            "or 10)");
   for (int k = 0; k < c->n_instances; ++k) {
     const mvmc_instance_desc& d = c->inst[k];
     const int ns = d.n_sites;
@@ -211,9 +220,17 @@ int64_t v_members(const mvmc_instance_desc& d) {
 bool variant_fits(const Plan& P, int k, int v) {
   const InstDev& I = P.inst[k];
   if (P.exchange && v >= 1 && v <= 6) return false;
+  if (P.queue) {
+    if (v != 0 && v != 9) return false;
+    // the anti-parallel walkers refresh by the 16 x 16 tile inside the launch
+    if (v == 9 && (sweep_queue_nb(I.ne) <= 0 ||
+                   sweep_queue_lds_bytes(0, I.ne, I.ns, I.M, P.tsize) > kLdsLimit))
+      return false;
+  }
   if (v == 0) {
     const int rc = sweep_reg_class(I.ne, P.tsize);
-    return rc && sweep_reg_lds_bytes(rc, I.ns, I.M, P.tsize, kRegWpb) <= kLdsLimit;
+    // the queue kernel runs every register-tier group with the 64-electron layout
+    return rc && sweep_reg_lds_bytes(P.queue ? 64 : rc, I.ns, I.M, P.tsize, kRegWpb) <= kLdsLimit;
   }
   const int nt = 64 << ((v - 1) % 3);
   if (v >= 7) return sweep_ap_lds_bytes(I.ne, I.ns, I.M, P.tsize, nt) <= kLdsLimit;
@@ -241,6 +258,7 @@ void set_variant(Plan& P, int k, int v) {
 // kernel (threads by the block side n), else the full-X^-1 kernel from HBM.
 int default_variant(const Plan& P, int k) {
   if (variant_fits(P, k, 0)) return 0;
+  if (P.queue) return variant_fits(P, k, 9) ? 9 : -1;
   const int n = P.inst[k].ne / 2;
   const int v = 7 + (n <= 48 ? 0 : (n <= 96 ? 1 : 2));
   if (variant_fits(P, k, v)) return v;
@@ -251,6 +269,7 @@ Plan make_plan(const mvmc_config& c) {
   Plan P;
   P.tsize = c.precision == MVMC_FP64 ? 8 : 4;
   P.exchange = c.exchange_per64 > 0;
+  P.queue = c.schedule == MVMC_SCHED_QUEUE;
   const int n = c.n_instances;
   P.inst.resize(n);
   P.sr.resize(n);
@@ -408,7 +427,9 @@ Plan make_plan(const mvmc_config& c) {
   take(P.inst_p, sizeof(InstDev) * n);
   take(P.srinst_p, sizeof(SrInst) * n);
   take(P.walker_inst, 4 * W);
-  take(P.lists, 4 * (4 * W + (size_t)kRegWpb * n));
+  // [sweep lists or queue groups and items | refresh lists | all walkers |
+  //  scratch | queue head]
+  take(P.lists, 4 * (5 * W + 2 * (size_t)kRegWpb * n) + 64);
   take(P.A64, 8 * (size_t)off_A);
   take(P.A32, 4 * (size_t)off_A);
   take(P.V, 8 * (size_t)off_V);
@@ -532,6 +553,13 @@ struct mvmc_ctx {
   int32_t* d_all = nullptr;       // every walker, instance order
   int32_t* d_scratch = nullptr;   // redraw list
   std::vector<Bucket> sweep_b, refresh_b;
+  // queue schedule: item list (>= 0 anti-parallel walker, < 0 register group
+  // -(g + 1)), register groups, queue head; all inside the list pool
+  int32_t* q_items = nullptr;
+  int32_t* q_groups = nullptr;
+  int32_t* q_head = nullptr;
+  int q_n = 0, q_ne_reg = 0, q_ne_ap = 0;
+  size_t q_lds = 0;                 // largest LDS need of an item
   std::vector<uint64_t> cnt_host;   // per-instance proposal counter mirror
   TraceRec* trace = nullptr;
   int64_t trace_cap = 0;
@@ -646,8 +674,45 @@ void build_buckets(mvmc_ctx* c, bool per_instance = false) {
     sweep_groups[{P.sweep_ap[k] ? 2 : (int)I.sweep_lds, cls, nt, own}].push_back(k);
   }
   std::vector<int32_t> lists;
+  if (P.queue && !per_instance) {
+    // queue schedule: register-tier groups of kRegWpb walkers of one instance
+    // (padded with -1), then the items, longest first (cost ~ N_e^2; a group
+    // costs as one of its walkers), ties in instance order
+    std::vector<std::pair<int64_t, int32_t>> items;
+    c->q_ne_reg = c->q_ne_ap = 0;
+    c->q_lds = 0;
+    for (int k = 0; k < n; ++k) {
+      const InstDev& I = P.inst[k];
+      const int64_t cost = (int64_t)I.ne * I.ne;
+      c->q_lds = std::max(c->q_lds, sweep_queue_lds_bytes(P.reg_class[k] ? I.ne : 0,
+                                                          P.reg_class[k] ? 0 : I.ne, I.ns, I.M,
+                                                          P.tsize));
+      if (P.reg_class[k]) {
+        c->q_ne_reg = std::max(c->q_ne_reg, I.ne);
+        for (int w = 0; w < I.W; w += kRegWpb) {
+          const int32_t g = (int32_t)(lists.size() / kRegWpb);
+          for (int u = 0; u < kRegWpb; ++u)
+            lists.push_back(w + u < I.W ? (int32_t)(I.walker_off + w + u) : -1);
+          items.push_back({cost, -(g + 1)});
+        }
+      } else {
+        c->q_ne_ap = std::max(c->q_ne_ap, I.ne);
+        for (int w = 0; w < I.W; ++w) items.push_back({cost, (int32_t)(I.walker_off + w)});
+      }
+    }
+    std::stable_sort(items.begin(), items.end(),
+                     [](const std::pair<int64_t, int32_t>& a,
+                        const std::pair<int64_t, int32_t>& b) { return a.first > b.first; });
+    const size_t items_off = lists.size();
+    for (auto& it : items) lists.push_back(it.second);
+    c->q_n = (int)items.size();
+    char* base = c->ws + P.lists.off;
+    c->q_groups = reinterpret_cast<int32_t*>(base);
+    c->q_items = reinterpret_cast<int32_t*>(base) + items_off;
+  }
   // register tiers: each instance's walkers in groups of kRegWpb, padded with -1
   for (auto& g : reg_groups) {
+    if (P.queue && !per_instance) break;
     Bucket b;
     b.reg = g.first.first;
     b.inst = g.first.second;
@@ -690,7 +755,7 @@ void build_buckets(mvmc_ctx* c, bool per_instance = false) {
       out.push_back(b);
     }
   };
-  emit(sweep_groups, c->sweep_b);
+  if (!(P.queue && !per_instance)) emit(sweep_groups, c->sweep_b);
   emit(refresh_groups, c->refresh_b);
   // list pool: [sweep lists (padded) | refresh lists | all walkers | scratch]
   const size_t W = (size_t)P.W;
@@ -700,6 +765,7 @@ void build_buckets(mvmc_ctx* c, bool per_instance = false) {
   (void)hipMemcpy(base, lists.data(), lists.size() * 4, hipMemcpyHostToDevice);
   c->d_all = reinterpret_cast<int32_t*>(base + lists.size() * 4);
   c->d_scratch = c->d_all + W;
+  c->q_head = c->d_scratch + W;
   (void)hipMemcpy(c->d_all, all.data(), W * 4, hipMemcpyHostToDevice);
 }
 
@@ -1140,6 +1206,31 @@ namespace {
 int run_sweeps(mvmc_ctx* c, int32_t n_sweeps, std::vector<double>* inst_ms) {
   const Plan& P = c->plan;
   const int R = c->cfg.refresh_every;
+  if (P.queue && !inst_ms) {
+    // one persistent launch: every walker to its target, refreshes inside
+    uint64_t* tgt = reinterpret_cast<uint64_t*>(c->ws + P.target.off);
+    const uint64_t* tb = reinterpret_cast<uint64_t*>(c->ws + P.trace_base.off);
+    launch_set_target(c->P, tgt, P.W, n_sweeps, c->stream);
+    LAUNCHCHK(c);
+    const bool full = c->trace != nullptr || c->cfg.exchange_per64 > 0 || P.max_M > 0;
+    const int id = tic(c, 0);
+    const bool ok =
+        c->cfg.precision == MVMC_FP64
+            ? launch_sweep_queue<double>(c->P, c->q_items, c->q_n, c->q_groups, c->q_head,
+                                         c->q_ne_reg, c->q_ne_ap, c->q_lds, full,
+                                         c->n_cu, INT32_MAX, c->cfg.seed, c->trace, c->trace_cap,
+                                         tb, tgt, R, c->cfg.exchange_per64, c->stream)
+            : launch_sweep_queue<float>(c->P, c->q_items, c->q_n, c->q_groups, c->q_head,
+                                        c->q_ne_reg, c->q_ne_ap, c->q_lds, full,
+                                        c->n_cu, INT32_MAX, c->cfg.seed, c->trace, c->trace_cap,
+                                        tb, tgt, R, c->cfg.exchange_per64, c->stream);
+    toc(c, id);
+    if (!ok) return set_err(c, fail(MVMC_E_SHAPE, "no queue sweep for these shapes"));
+    LAUNCHCHK(c);
+    for (int k = 0; k < c->cfg.n_instances; ++k)
+      c->cnt_host[k] += (uint64_t)n_sweeps * P.inst[k].ne;
+    return MVMC_OK;
+  }
   int rounds = 1;
   bool lds_refresh = false;
   std::vector<uint64_t> target(c->cfg.n_instances);
@@ -1284,6 +1375,8 @@ int mvmc_sample_sweeps(mvmc_ctx* c, int32_t n_sweeps, int64_t* h_accepted) {
 
 int mvmc_autotune(mvmc_ctx* c, int32_t n_sweeps, const char* cache_path, double* h_ms) {
   if (!c || n_sweeps < 1) return set_err(c, fail(MVMC_E_ARG, "n_sweeps must be >= 1"));
+  if (c->plan.queue)
+    return set_err(c, fail(MVMC_E_ARG, "the queue schedule has fixed sweep variants"));
   Plan& P = c->plan;
   const int n = c->cfg.n_instances, nv = MVMC_N_SWEEP_VARIANTS;
   std::vector<double> ms((size_t)n * nv, std::nan(""));

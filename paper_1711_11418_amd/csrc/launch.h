@@ -70,6 +70,26 @@ bool launch_sweep_reg(const Pools& P, const int32_t* wlist, int n_groups, int ne
 size_t sweep_reg_lds_bytes(int ne_max, int ns, int M, size_t tsize, int wpb);
 int sweep_reg_class(int ne, size_t tsize);   // register tier for ne, 0 = none
 
+// k_sweep_queue.hip: one persistent launch over a cost-sorted item list
+// (>= 0: anti-parallel-block walker; < 0: register-tier group -(item + 1) of
+// `groups`, 4 walkers each), both tiers refreshing inside the launch.  head:
+// one int of device memory, reset by the launch; lds_bytes: the largest
+// sweep_queue_lds_bytes over the instances.  Returns false when the shapes
+// have no instantiation (register tier above 64 electrons, anti-parallel
+// block above 256).
+template <typename T>
+bool launch_sweep_queue(const Pools& P, const int32_t* items, int n_items, const int32_t* groups,
+                        int32_t* head, int max_ne_reg, int max_ne_ap, size_t lds_bytes, bool full,
+                        int n_cu, int cap, uint64_t seed, TraceRec* trace, int64_t trace_cap,
+                        const uint64_t* trace_base, const uint64_t* target, int R, int ex64,
+                        hipStream_t s);
+// register blocks of the refresh tile for anti-parallel walkers of up to
+// max_ne_ap electrons (0 none, -1 too large)
+int sweep_queue_nb(int max_ne_ap);
+// LDS of one instance's items: a register-tier instance (ne_reg > 0) or an
+// anti-parallel one (ne_ap > 0)
+size_t sweep_queue_lds_bytes(int ne_reg, int ne_ap, int ns, int M, size_t tsize);
+
 // k_measure.hip: local energy and O_k rows for sample slot `slot`.
 template <typename T>
 void launch_measure(const Pools& P, const int32_t* wlist, int n, int slot, double* eloc, T* O,

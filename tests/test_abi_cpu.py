@@ -81,3 +81,35 @@ def test_cholesky_requires_explicit_s():
     cfg = b.make_config([inst], "fp64", 0, 1, solver="chol", build_s=False)
     with pytest.raises(b.MVMCError):
         b.query_sizes(cfg)
+
+
+@pytest.mark.parametrize("kw", [dict(sweep_threads=64), dict(sweep_variant="lds64"),
+                                dict(sweep_variant="ap128")])
+def test_queue_schedule_rejects_other_variants(kw):
+    """The persistent queue launch runs the register tier and the 256-thread
+    anti-parallel-block sweep only."""
+    b = _lib()
+    insts = [workload(n)["instances"][0] for n in ("ring6", "sq4_sub2")]
+    cfg = b.make_config(insts, "fp64", 16, 1, schedule="queue", **kw)
+    with pytest.raises(b.MVMCError) as e:
+        b.query_sizes(cfg)
+    assert e.value.status == 1
+
+
+def test_queue_schedule_shapes():
+    """Queue schedule: a ragged batch plans (N_e 6..140); an anti-parallel
+    block beyond 128 x 128 (N_e > 256) has no in-launch refresh: E_SHAPE."""
+    from mvmc_inputs.instance import f_map_sublattice, make_instance, v_map_nn
+    from mvmc_inputs.lattice import square
+    b = _lib()
+    insts = workload("batch32_ragged", n_walkers=8)["instances"]
+    cfg = b.make_config(insts, "mixed", 32, 7, n_slots=1, build_s=False, solver="cg",
+                        schedule="queue")
+    b.query_sizes(cfg)
+    lat = square(17)
+    big = make_instance("sq17", lat, 130, 130, 4.0, f_map_sublattice(lat, 1, 1), v_map_nn(lat),
+                        n_walkers=4)
+    cfg = b.make_config([big], "fp64", 16, 1, build_s=False, solver="cg", schedule="queue")
+    with pytest.raises(b.MVMCError) as e:
+        b.query_sizes(cfg)
+    assert e.value.status == 2

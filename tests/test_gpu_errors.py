@@ -106,8 +106,9 @@ def test_calls_out_of_order_and_bad_arguments():
     ctx.close()
 
 
-@pytest.mark.parametrize("threads", [0, 64])
-def test_nonfinite_parameters_and_ratios(threads):
+@pytest.mark.parametrize("threads,schedule,variant", [(0, "buckets", None), (64, "buckets", None),
+                                                      (0, "queue", None), (0, "queue", "ap256")])
+def test_nonfinite_parameters_and_ratios(threads, schedule, variant):
     """A NaN parameter is refused by set_params (nothing changes).  A finite
     but huge Gutzwiller factor (g = 800, e^800 overflows) makes every ratio
     that creates a doublon infinite: the guard refreshes in double, retries,
@@ -117,9 +118,9 @@ def test_nonfinite_parameters_and_ratios(threads):
     from paper_1711_11418_amd.binding import MVMCError
     inst = workload("sq4_sub2")["instances"][0]
     inst.n_walkers = 8
-    log(f"[errors] non-finite guard, sweep_threads={threads}")
+    log(f"[errors] non-finite guard, sweep_threads={threads} {schedule} {variant}")
     ctx = MVMC([inst], inst.params0, seed=SEED, build_s=False, solver="cg",
-               sweep_threads=threads)
+               sweep_threads=threads, schedule=schedule, sweep_variant=variant)
     p = inst.params0.copy()
     p[inst.offsets()["g"]] = np.nan
     with pytest.raises(MVMCError) as e:
@@ -141,9 +142,10 @@ def test_nonfinite_parameters_and_ratios(threads):
     ctx.close()
 
 
-@pytest.mark.parametrize("precision,threads,refresh", [("fp64", 0, 0), ("fp64", 64, 0),
-                                                        ("mixed", 0, 32), ("mixed", 128, 32)])
-def test_resume_is_bit_exact(precision, threads, refresh):
+@pytest.mark.parametrize("precision,threads,refresh,schedule", [
+    ("fp64", 0, 0, "buckets"), ("fp64", 64, 0, "buckets"), ("mixed", 0, 32, "buckets"),
+    ("mixed", 128, 32, "buckets"), ("mixed", 0, 32, "queue")])
+def test_resume_is_bit_exact(precision, threads, refresh, schedule):
     """Checkpoint after some sweeps, refresh the running context, load the
     checkpoint into a fresh context: both continue with bitwise-identical
     proposal traces (ratios included) and configurations."""
@@ -151,8 +153,8 @@ def test_resume_is_bit_exact(precision, threads, refresh):
     inst = workload("sq4_sub2")["instances"][0] if threads == 0 else _ring6()
     inst.n_walkers = 8
     kw = dict(precision=precision, seed=SEED, refresh_every=refresh, sweep_threads=threads,
-              build_s=False, solver="cg")
-    log(f"[resume] {precision} threads={threads} refresh={refresh} Ne={inst.n_elec}")
+              build_s=False, solver="cg", schedule=schedule)
+    log(f"[resume] {precision} threads={threads} refresh={refresh} {schedule} Ne={inst.n_elec}")
     a = MVMC([inst], inst.params0, **kw)
     a.sample(7)
     pos, cnt, emp = a.get_state(with_empty=True)

@@ -12,8 +12,10 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-@pytest.mark.parametrize("name,refresh", [("sq4_sub2", 0), ("ring8_u4", 16)])
-def test_captured_sampling_replays_match_eager(name, refresh):
+@pytest.mark.parametrize("name,refresh,schedule,variant", [
+    ("sq4_sub2", 0, "buckets", None), ("ring8_u4", 16, "buckets", None),
+    ("ring8_u4", 16, "queue", None), ("sq4_sub2", 16, "queue", "ap256")])
+def test_captured_sampling_replays_match_eager(name, refresh, schedule, variant):
     from paper_1711_11418_amd import MVMC
     inst = workload(name)["instances"][0]
     inst.n_walkers = 16
@@ -21,10 +23,11 @@ def test_captured_sampling_replays_match_eager(name, refresh):
     pos0 = good_configs(inst, inst.params0, inst.n_walkers, 21)
     zero = np.zeros(inst.n_walkers, dtype=np.int64)
     side = torch.cuda.Stream()
-    log(f"[graph] {name}: W=16 slots={slots} refresh={refresh}")
+    log(f"[graph] {name}: W=16 slots={slots} refresh={refresh} {schedule} {variant}")
     with torch.cuda.stream(side):
         eager = MVMC([inst], inst.params0, seed=5, refresh_every=refresh, n_slots=slots,
-                     build_s=False, solver="cg", stream=side)
+                     build_s=False, solver="cg", stream=side, schedule=schedule,
+                     sweep_variant=variant)
         eager.set_state(pos0.ravel(), zero)
         for s in range(slots):
             eager.sample_async(2)
@@ -35,7 +38,8 @@ def test_captured_sampling_replays_match_eager(name, refresh):
         eager.close()
 
         ctx = MVMC([inst], inst.params0, seed=5, refresh_every=refresh, n_slots=slots,
-                   build_s=False, solver="cg", stream=side)
+                   build_s=False, solver="cg", stream=side, schedule=schedule,
+                   sweep_variant=variant)
         ctx.set_state(pos0.ravel(), zero)
         torch.cuda.synchronize()
         g = ctx.capture_sampling(2, range(slots))
