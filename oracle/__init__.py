@@ -28,6 +28,9 @@ method"), not the fast algorithms the GPU uses:
 * sr.py           -- SR overlap, force and update (section 3.3.1,
                      Eq. SR_equation_system), Cholesky solve and the CG method
                      of Algorithm 1 (section 3.3.2).
+* lanczos.py      -- first-step power-Lanczos (section 3.4): F(x, H^2) by two
+                     applications of H with every end point from scratch, the
+                     four moments, E_1(alpha) and the optimal alpha_1.
 
 Parity status: every function here is pinned by a test under tests/ that
 checks it against closed forms, invariants or brute force (see the module
