@@ -433,6 +433,57 @@ def sq8_leg(steps):
     return out
 
 
+def lanczos_leg(sr_steps=30, slots=20):
+    """First-step power-Lanczos (section 3.4) on the 8x8, U = 4 workload: the
+    state is trained by sr_steps FP64 SR steps, then F(x, H) and F(x, H^2)
+    are measured on 1024 walkers x `slots` samples one sweep apart, and the
+    moments give alpha_1 and E_1(alpha_1) against E = h1.  Timed: the
+    F(x, H^2) kernel (HIP events around its launches)."""
+    import numpy as np
+
+    from mvmc_inputs import workload
+    from paper_1711_11418_amd import MVMC
+    wl = workload("sq8_u4")
+    inst = wl["instances"][0]
+    ctx = MVMC([inst], inst.params0, seed=wl["sampler_seed"], n_slots=10, solver="chol",
+               build_s=True, refresh_every=wl["refresh_every"])
+    ctx.sample(wl["warmup"])
+    for _ in range(sr_steps):
+        for s in range(10):
+            ctx.sample_async(1)
+            ctx.measure(s)
+        ctx.build_sr(10)
+        ctx.sr_update(dtau=wl["dtau"], eps_rel=wl["eps_rel"], eps_abs=wl["eps_abs"])
+    p = ctx.params.cpu().numpy().copy()
+    ctx.close()
+    ev = MVMC([inst], p, seed=wl["sampler_seed"] + 3, n_slots=slots, build_s=False, solver="cg",
+              refresh_every=wl["refresh_every"])
+    ev.sample(wl["warmup"])
+    ms = 0.0
+    for s in range(slots):
+        ev.sample(1)
+        ev.timing(True)
+        ev.measure_h2(s)
+        ms += ev.timing(False)[0][2]
+    out = ev.lanczos_first_step(slots)[0]
+    f1 = ev.f1.cpu().numpy()[:slots * inst.n_walkers].reshape(slots, inst.n_walkers)
+    wmean = f1.mean(axis=0)
+    sigma = wmean.std(ddof=1) / np.sqrt(inst.n_walkers)
+    ev.close()
+    ns, n = inst.n_sites, inst.n_up
+    gemm_flops = 2.0 * n * ns * (2 * n + ns)
+    per_call = ms / slots
+    return {"workload": "sq8_u4 after %d FP64 SR steps" % sr_steps, "walkers": inst.n_walkers,
+            "samples": slots * inst.n_walkers,
+            "E_per_site": out[0] / ns, "sigma_E_per_site": sigma / ns,
+            "alpha_1": out[4], "E1_per_site": out[5] / ns,
+            "gain_per_site": (out[0] - out[5]) / ns, "moments": out[:4].tolist(),
+            "real_roots": int(out[6]),
+            "h2_kernel_ms_per_1024_walkers": per_call,
+            "h2_walkers_per_s": inst.n_walkers / (per_call * 1e-3),
+            "products_tflops": gemm_flops * inst.n_walkers / (per_call * 1e-3) / 1e12}
+
+
 def rbm_leg(steps):
     """16x16 Hubbard, U = 8, N_e = 224 (1/8 hole doping), 2x2-sublattice f
     times an RBM factor of 512 hidden units over the 512 spin-resolved
@@ -699,6 +750,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="launch the sampling eagerly")
     ap.add_argument("--s-build-only", action="store_true",
                     help="print only the split-bf16 S build leg (for kernel profiling)")
+    ap.add_argument("--lanczos-only", action="store_true",
+                    help="print only the first-step power-Lanczos leg")
     ap.add_argument("--batch-only", action="store_true",
                     help="print only the ragged-batch leg (queue and bucket schedules)")
     ap.add_argument("--rbm-gain", action="store_true",
@@ -718,6 +771,9 @@ def main():
         return
     if a.rbm_gain:
         print(json.dumps({"rbm_gain_sq16": rbm_gain(a.sr_steps)}), flush=True)
+        return
+    if a.lanczos_only:
+        print(json.dumps({"lanczos_sq8": lanczos_leg()}), flush=True)
         return
     if a.batch_only:
         print(json.dumps({"batch32_ragged": batch_leg(max(1, a.steps - 1))}), flush=True)
@@ -779,6 +835,10 @@ def main():
         out["sq8_u4"] = sq8_leg(max(1, a.steps))
         log(f"[bench]   8x8 fp64 {out['sq8_u4']['fp64']['value']:.3e}, mixed "
             f"{out['sq8_u4']['mixed']['value']:.3e} hop-updates/s")
+        log("[bench] first-step power-Lanczos on 8x8 (trained state)")
+        out["lanczos_sq8"] = lanczos_leg()
+        log(f"[bench]   E/N {out['lanczos_sq8']['E_per_site']:.5f}, E_1/N "
+            f"{out['lanczos_sq8']['E1_per_site']:.5f}, alpha_1 {out['lanczos_sq8']['alpha_1']:.4f}")
         log("[bench] 16x16 RBM leg (8192 walkers, CG)")
         out["sq16_u8_rbm"] = rbm_leg(1)
         log(f"[bench]   16x16 {out['sq16_u8_rbm']['value']:.3e} hop-updates/s, "

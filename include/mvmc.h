@@ -290,6 +290,34 @@ int mvmc_peak_probe(int32_t kind, void *d_scratch, void *hip_stream, double *h_t
 int mvmc_measure_energy_and_O(mvmc_ctx *ctx, int32_t slot, double *d_eloc, void *d_O);
 
 /*
+ * First-step power-Lanczos (section 3.4), local values: for every walker's
+ * current configuration x, F(x, H) = E_loc(x) into d_f1 and
+ * F(x, H^2) = <x|H^2|psi>/<x|psi> into d_f2 (each [eloc_elems] doubles,
+ * device, caller-owned, written at eloc_off + slot*W + w like d_eloc above).
+ * F(x, H^2) sums every two-step path of the Hamiltonian; the Pfaffian ratios
+ * of the one- and two-electron moves come from M^-1 (Eq. AP-Pf) and its
+ * products with the pair amplitudes, formed per walker in LDS in double.
+ * Pfaffian-Jastrow-Gutzwiller states only: an instance with an RBM factor
+ * gives MVMC_E_ARG; MVMC_E_SHAPE where N_s, N_e do not fit the LDS budget
+ * (about N_s <= 90 at half filling).  Enqueues only (capturable).
+ * Errors: MVMC_E_ARG, MVMC_E_SHAPE, MVMC_E_HIP.
+ */
+int mvmc_measure_h2(mvmc_ctx *ctx, int32_t slot, double *d_f1, double *d_f2);
+
+/*
+ * First-step power-Lanczos (section 3.4), energy of (1 + alpha_1 H)|psi>: per
+ * instance the sample means over the first n_slots_used slots
+ *   h1 = <F(x,H)>, h11 = <F(x,H)^2>, h20 = <F(x,H^2)>, h12 = <F(x,H) F(x,H^2)>,
+ * E_1(a) = (h1 + a (h20 + h11) + a^2 h12) / (1 + 2 a h1 + a^2 h11), and
+ * alpha_1 the root of dE_1/da = 0 with the lower E_1 (0 when the quadratic
+ * has no real root).  h_out (host): [n_instances][7] = h1, h11, h20, h12,
+ * alpha_1, E_1(alpha_1), number of real roots.  Synchronises the stream.
+ * Errors: MVMC_E_ARG, MVMC_E_HIP.
+ */
+int mvmc_lanczos_first_step(mvmc_ctx *ctx, int32_t n_slots_used, const double *d_f1,
+                            const double *d_f2, double *h_out);
+
+/*
  * SR quantities over the first n_slots_used slots (section 3.3.1, with the
  * sample means of section 3.3.2): E_bar = <E_loc>; o_k = <O_k>; O is centred
  * in place (O <- O - o); d_g = O~^T(E-E_bar)/N (double, n_params); d_S (may be

@@ -24,6 +24,7 @@ ENTRY_POINTS = (
     "mvmc_trace_enable", "mvmc_timing", "mvmc_destroy", "mvmc_last_error", "mvmc_status_string",
     "mvmc_autotune", "mvmc_sweep_variants", "mvmc_s_tiles", "mvmc_set_s_tile",
     "mvmc_peak_probe_bytes", "mvmc_peak_probe", "mvmc_init_wavefunction_static",
+    "mvmc_measure_h2", "mvmc_lanczos_first_step",
 )
 N_SWEEP_VARIANTS = 10
 SWEEP_VARIANT_NAMES = ("reg", "lds64", "lds128", "lds256", "hbm64", "hbm128", "hbm256",
@@ -100,6 +101,8 @@ def load() -> C.CDLL:
         "mvmc_init_wavefunction_static": [C.POINTER(vp), C.POINTER(Config), vp, vp],
         "mvmc_sample_sweeps": [vp, i32, vp],
         "mvmc_measure_energy_and_O": [vp, i32, vp, vp],
+        "mvmc_measure_h2": [vp, i32, vp, vp],
+        "mvmc_lanczos_first_step": [vp, i32, vp, vp, vp],
         "mvmc_build_sr": [vp, i32, vp, vp, vp, vp, vp, vp, vp],
         "mvmc_sr_update": [vp, vp, vp, vp, dbl, dbl, dbl, i32, dbl, i32, vp, vp, vp],
         "mvmc_set_params": [vp, vp],
@@ -306,6 +309,24 @@ class MVMC:
     def measure(self, slot: int) -> None:
         self._check(self.lib.mvmc_measure_energy_and_O(self.ctx, int(slot), self._p(self.eloc),
                                                        self._p(self.O)))
+
+    def measure_h2(self, slot: int) -> None:
+        """F(x, H) and F(x, H^2) of every walker into slot `slot` of self.f1 /
+        self.f2 (first-step power-Lanczos, allocated on first use)."""
+        t = self.torch
+        if getattr(self, "f1", None) is None:
+            self.f1 = t.zeros(int(self.sizes.eloc_elems), dtype=t.float64, device=self.device)
+            self.f2 = t.zeros_like(self.f1)
+        self._check(self.lib.mvmc_measure_h2(self.ctx, int(slot), self._p(self.f1),
+                                             self._p(self.f2)))
+
+    def lanczos_first_step(self, n_used: int) -> np.ndarray:
+        """[n_instances][7]: h1, h11, h20, h12, alpha_1, E_1(alpha_1), real roots."""
+        out = np.zeros((self.n_inst, 7))
+        self._check(self.lib.mvmc_lanczos_first_step(self.ctx, int(n_used), self._p(self.f1),
+                                                     self._p(self.f2),
+                                                     out.ctypes.data_as(C.c_void_p)))
+        return out
 
     def build_sr(self, n_used: int, with_S: bool = True):
         """SR statistics over the first n_used slots; returns (E_bar, sigma, var E)

@@ -52,7 +52,7 @@ struct Plan {
   Pool inst_p, srinst_p, walker_inst, lists, A64, A32, V, fidx, vidx, G, U, gidx, nbr_ptr,
       nbr_site, nbr_t, fm_ptr, fm, gm_ptr, gm, vm_ptr, vm, rbm64, rbm32, rbmT64, rbmT32, Y, Y64,
       pos, empty, h,
-      theta, cnt, target, needs_refresh, accepted, logpf, sgnpf, minpiv, status, guard, chk,
+      theta, cnt, target, needs_refresh, accepted, logpf, sgnpf, minpiv, status, guard, chk, lz,
       trace_base,
       obar, sdiag, x, r, p, w, t, shift, mask, scal, colpart, syrkpart, chol, split;
   size_t total = 0;
@@ -467,6 +467,7 @@ Plan make_plan(const mvmc_config& c) {
   take(P.status, 4 * W);
   take(P.guard, 4 * W);
   take(P.chk, 8);
+  take(P.lz, 7 * 8 * (size_t)n);
   take(P.trace_base, 8 * W);
   const size_t NP = (size_t)P.np;
   take(P.obar, 8 * NP);
@@ -1543,6 +1544,48 @@ int mvmc_measure_energy_and_O(mvmc_ctx* c, int32_t slot, double* d_eloc, void* d
                           P.max_M, c->stream);
   toc(c, id);
   LAUNCHCHK(c);
+  return MVMC_OK;
+}
+
+int mvmc_measure_h2(mvmc_ctx* c, int32_t slot, double* d_f1, double* d_f2) {
+  if (!c || !d_f1 || !d_f2) return set_err(c, fail(MVMC_E_ARG, "NULL buffer"));
+  if (slot < 0 || slot >= c->cfg.n_slots)
+    return set_err(c, fail(MVMC_E_ARG, "slot %d outside [0, %d)", slot, c->cfg.n_slots));
+  const Plan& P = c->plan;
+  for (int k = 0; k < c->cfg.n_instances; ++k) {
+    const InstDev& I = P.inst[k];
+    if (I.M)
+      return set_err(c, fail(MVMC_E_ARG, "instance %d: F(x, H^2) covers states without an RBM "
+                                         "factor", k));
+    if (local_h2_lds_bytes(I.ne, I.ns) > kLdsLimit)
+      return set_err(c, fail(MVMC_E_SHAPE, "instance %d: N_s = %d, N_e = %d exceed the LDS of "
+                                           "the F(x, H^2) kernel", k, I.ns, I.ne));
+  }
+  const int id = tic(c, 2);
+  if (c->cfg.precision == MVMC_FP64)
+    launch_local_h2<double>(c->P, c->d_all, (int)P.W, slot, d_f1, d_f2, P.max_ne, P.max_ns,
+                            c->stream);
+  else
+    launch_local_h2<float>(c->P, c->d_all, (int)P.W, slot, d_f1, d_f2, P.max_ne, P.max_ns,
+                           c->stream);
+  toc(c, id);
+  LAUNCHCHK(c);
+  return MVMC_OK;
+}
+
+int mvmc_lanczos_first_step(mvmc_ctx* c, int32_t n_used, const double* d_f1, const double* d_f2,
+                            double* h_out) {
+  if (!c || !d_f1 || !d_f2 || !h_out) return set_err(c, fail(MVMC_E_ARG, "NULL buffer"));
+  if (n_used < 1 || n_used > c->cfg.n_slots)
+    return set_err(c, fail(MVMC_E_ARG, "n_slots_used %d outside [1, %d]", n_used,
+                           c->cfg.n_slots));
+  const int n = c->cfg.n_instances;
+  double* d_out = reinterpret_cast<double*>(c->ws + c->plan.lz.off);
+  launch_lanczos_moments(c->P, n, n_used, d_f1, d_f2, d_out, c->stream);
+  LAUNCHCHK(c);
+  HIPCHK(c, hipMemcpyAsync(h_out, d_out, sizeof(double) * 7 * n, hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   return MVMC_OK;
 }
 

@@ -95,6 +95,16 @@ template <typename T>
 void launch_measure(const Pools& P, const int32_t* wlist, int n, int slot, double* eloc, T* O,
                     int max_ne, int max_ns, int max_M, hipStream_t s);
 
+// k_lanczos.hip: F(x, H) and F(x, H^2) of every listed walker into slot
+// `slot` of f1 / f2 (eloc layout); moments, alpha_1 and E_1 per instance
+// into out[k * 7 + 0..6].
+template <typename T>
+void launch_local_h2(const Pools& P, const int32_t* wlist, int n, int slot, double* f1,
+                     double* f2, int max_ne, int max_ns, hipStream_t s);
+size_t local_h2_lds_bytes(int ne, int ns);
+void launch_lanczos_moments(const Pools& P, int n_inst, int n_used, const double* f1,
+                            const double* f2, double* out, hipStream_t s);
+
 // peak probes (k_probe.hip): 0 bf16 MFMA, 1 FP64 MFMA, 2 FP64 vector FMA
 double probe_flops_per_wave_iter(int kind);
 void launch_probe(int kind, float* out, int blocks, int iters, hipStream_t s);
