@@ -361,7 +361,9 @@ Plan make_plan(const mvmc_config& c) {
     I.theta_off = off_theta;
     off_theta += (int64_t)I.W * I.M;
     I.chol_off = off_chol;
-    if (c.build_s && c.solver == MVMC_SOLVE_CHOL) off_chol += (int64_t)I.np * I.np;
+    // the factor, then the inverses of its 64 x 64 diagonal blocks
+    if (c.build_s && c.solver == MVMC_SOLVE_CHOL)
+      off_chol += (int64_t)I.np * I.np + (I.np + 63) / 64 * 64 * 64;
     I.split_off = off_split;
     const int64_t rows32 = (I.rows + 31) / 32 * 32;
     const bool tiled_s = c.build_s && c.precision == MVMC_MIXED && wide_params(I.np);

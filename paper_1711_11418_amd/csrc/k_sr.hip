@@ -573,76 +573,178 @@ __global__ __launch_bounds__(256, 2) void k_chol_trail(SrArgs A, int ob) {
       }
 }
 
-// Substitution on diagonal block kb, in place in x, one wavefront: forward
-// (L y = b, lane i keeps row i of the block) or backward (L^T y = b, lane i
-// keeps column i).  Each solved y_j is broadcast and the later right-hand
-// sides are updated in parallel.
-__global__ __launch_bounds__(64) void k_trsv_diag(SrArgs A, int kb, int transpose) {
-  const SrInst& I = A.inst[blockIdx.x];
+// Inverse of every 64 x 64 diagonal block of the factor, all blocks at once
+// (one wavefront each), stored row-major after the factor at
+// chol_off + np^2 + kb * 64^2.  Lane j forms column j by forward
+// substitution, L z = e_j:  z_i = (delta_ij - sum_{m<i} L[i][m] z_m) / L[i][i],
+// with L_kk in LDS and the columns in LDS.  Rows and columns past the matrix
+// (last block) are the identity.
+__global__ __launch_bounds__(64) void k_trtri_diag(SrArgs A) {
+  const SrInst& I = A.inst[blockIdx.y];
+  const int kb = blockIdx.x;
   const int nblk = (int)ceil_div<int64_t>(I.np, kNb);
   if (kb >= nblk) return;
   const int64_t o = (int64_t)kb * kNb;
   const int nb = (int)(I.np - o < kNb ? I.np - o : kNb);
-  const int i = threadIdx.x;
-  if (i >= kNb) return;   // one wavefront per block
   const double* F = A.chol + I.chol_off;
-  double* x = A.x + I.param_off + o;
-  double Lr[kNb];
-#pragma unroll
-  for (int j = 0; j < kNb; ++j) {
-    if (!transpose)
-      Lr[j] = (i < nb && j <= i) ? F[(o + i) * I.np + o + j] : (i == j ? 1.0 : 0.0);
-    else
-      Lr[j] = (j < nb && i <= j) ? F[(o + j) * I.np + o + i] : (i == j ? 1.0 : 0.0);
+  __shared__ double Ls[kNb][kNb + 1];
+  __shared__ double Zs[kNb][kNb + 1];
+  const int j = threadIdx.x;
+  for (int i = 0; i < kNb; ++i) {
+    Ls[i][j] = (i < nb && j <= i) ? F[(o + i) * I.np + o + j] : (i == j ? 1.0 : 0.0);
+    Zs[i][j] = 0.0;
   }
-  double b = i < nb ? x[i] : 0.0;
-  if (!transpose) {
-#pragma unroll
-    for (int j = 0; j < kNb; ++j) {
-      const double yj = lane_value(b / Lr[j], j);
-      if (i == j)
-        b = yj;
-      else if (i > j)
-        b -= Lr[j] * yj;
-    }
-  } else {
-#pragma unroll
-    for (int j = kNb - 1; j >= 0; --j) {
-      const double yj = lane_value(b / Lr[j], j);
-      if (i == j)
-        b = yj;
-      else if (i < j)
-        b -= Lr[j] * yj;
-    }
+  wave::wave_sync();
+  for (int i = 0; i < kNb; ++i) {
+    double s = i == j ? 1.0 : 0.0;
+    for (int m = j; m < i; ++m) s -= Ls[i][m] * Zs[m][j];
+    Zs[i][j] = i < j ? 0.0 : s / Ls[i][i];
   }
-  if (i < nb) x[i] = b;
+  wave::wave_sync();
+  double* Li = A.chol + I.chol_off + I.np * I.np + (int64_t)kb * kNb * kNb;
+  for (int i = 0; i < kNb; ++i) Li[i * kNb + j] = Zs[i][j];
 }
 
-// Off-diagonal updates of the right-hand side after block kb is solved.
-// forward:  x[r] -= sum_{c in kb} L[r][c] x[c]   for r in later blocks
-// backward: x[c] -= sum_{r in kb} L[r][c] x[r]   for c in earlier blocks
-__global__ __launch_bounds__(64) void k_trsv_update(SrArgs A, int kb, int transpose) {
+// Substitution in groups of G diagonal blocks, in place in x: group gi is
+// blocks kb0, kb0 + 1, ... with kb0 = G gi (forward) or kb0, kb0 - 1, ...
+// with kb0 = nblk - 1 - G gi (backward, from each instance's own last block).
+// One workgroup per instance solves the group: for each block b of it, with
+// the blocks of the group before it already solved,
+//   forward   x_b <- Linv_bb (x_b - sum L[b][c] x_c)          (c earlier in the group)
+//   backward  x_b <- Linv_bb^T (x_b - sum L[c][b]^T x_c)      (c later in the group)
+// every 64 x 64 block staged through LDS by all threads at once (sixteen
+// loads in flight per thread), then one thread per row (forward) or column
+// (backward) of the 64.  Contributions of blocks outside the group come from
+// k_trsv_rest.
+constexpr int kTrsvG = 8;
+__global__ __launch_bounds__(256) void k_trsv_group(SrArgs A, int gi, int transpose) {
+  const SrInst& I = A.inst[blockIdx.x];
+  const int nblk = (int)ceil_div<int64_t>(I.np, kNb);
+  const int kb0 = transpose ? nblk - 1 - gi * kTrsvG : gi * kTrsvG;   // first block of group gi
+  if (kb0 >= nblk || kb0 < 0) return;
+  const double* F = A.chol + I.chol_off;
+  const double* Lv = F + I.np * I.np;
+  double* x = A.x + I.param_off;
+  __shared__ double Ls[kNb][kNb + 1];
+  __shared__ double xs[kTrsvG][kNb];   // solved blocks of the group
+  __shared__ double xb[kNb];
+  const int tid = threadIdx.x;
+  // stage a 64 x 64 block (rows r0.., columns c0.., nr x nc valid) into Ls
+  auto stage = [&](const double* src, int64_t ld, int nr, int nc) {
+    double v[kNb * kNb / 256];
+#pragma unroll
+    for (int u = 0; u < kNb * kNb / 256; ++u) {
+      const int e = tid + 256 * u, i = e / kNb, m = e % kNb;
+      v[u] = (i < nr && m < nc) ? src[(int64_t)i * ld + m] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kNb * kNb / 256; ++u) {
+      const int e = tid + 256 * u;
+      Ls[e / kNb][e % kNb] = v[u];
+    }
+  };
+  for (int g = 0; g < kTrsvG; ++g) {
+    const int b = transpose ? kb0 - g : kb0 + g;
+    if (b < 0 || b >= nblk) break;   // uniform
+    const int64_t ob = (int64_t)b * kNb;
+    const int nb = (int)(I.np - ob < kNb ? I.np - ob : kNb);
+    if (tid < kNb) xb[tid] = tid < nb ? x[ob + tid] : 0.0;
+    // contributions of the blocks of the group solved before b
+    for (int g2 = 0; g2 < g; ++g2) {
+      const int c = transpose ? kb0 - g2 : kb0 + g2;
+      const int64_t oc = (int64_t)c * kNb;
+      const int nc = (int)(I.np - oc < kNb ? I.np - oc : kNb);
+      __syncthreads();   // Ls free, xb written
+      if (!transpose) stage(F + ob * I.np + oc, I.np, nb, nc);   // L[b][c]
+      else stage(F + oc * I.np + ob, I.np, nc, nb);              // L[c][b]
+      __syncthreads();
+      if (tid < kNb) {
+        double s = 0.0;
+        if (!transpose)
+          for (int m = 0; m < kNb; ++m) s += Ls[tid][m] * xs[g2][m];
+        else
+          for (int i = 0; i < kNb; ++i) s += Ls[i][tid] * xs[g2][i];
+        xb[tid] -= s;
+      }
+    }
+    __syncthreads();
+    stage(Lv + (int64_t)b * kNb * kNb, kNb, kNb, kNb);
+    __syncthreads();
+    if (tid < kNb) {
+      double y = 0.0;
+      if (!transpose)
+        for (int m = 0; m < kNb; ++m) y += Ls[tid][m] * xb[m];
+      else
+        for (int i = 0; i < kNb; ++i) y += Ls[i][tid] * xb[i];
+      xs[g][tid] = y;
+      if (tid < nb) x[ob + tid] = y;
+    }
+  }
+}
+
+// The solved group's contribution to every block outside it: one workgroup
+// per target block t (forward: t after the group; backward: t before it),
+//   forward   x_t -= sum over the group's blocks c of L[t][c] x_c
+//   backward  x_t -= sum over the group's blocks c of L[c][t]^T x_c
+// Forward: a wavefront per 16 rows of t, lanes across the group's columns,
+// the 16 rows' loads of a column chunk in flight together, one wave sum per
+// row.  Backward: lanes across the 64 columns of t, the four wavefronts
+// splitting the group's rows (eight loads in flight), partial sums added in
+// wavefront order.
+__global__ __launch_bounds__(256) void k_trsv_rest(SrArgs A, int gi, int transpose) {
   const SrInst& I = A.inst[blockIdx.y];
   const int nblk = (int)ceil_div<int64_t>(I.np, kNb);
-  if (kb >= nblk) return;
-  const int ob = transpose ? (int)blockIdx.x : kb + 1 + (int)blockIdx.x;
-  if (transpose ? ob >= kb : ob >= nblk) return;
-  const int64_t o = (int64_t)kb * kNb, bo = (int64_t)ob * kNb;
-  const int nb = (int)(I.np - o < kNb ? I.np - o : kNb);
-  const int nr = (int)(I.np - bo < kNb ? I.np - bo : kNb);
+  const int kb0 = transpose ? nblk - 1 - gi * kTrsvG : gi * kTrsvG;
+  if (kb0 >= nblk || kb0 < 0) return;
+  // group blocks [c0, c1)
+  const int c0 = transpose ? (kb0 - kTrsvG + 1 > 0 ? kb0 - kTrsvG + 1 : 0) : kb0;
+  const int c1 = transpose ? kb0 + 1 : (kb0 + kTrsvG < nblk ? kb0 + kTrsvG : nblk);
+  const int t = transpose ? (int)blockIdx.x : c1 + (int)blockIdx.x;
+  if (transpose ? t >= c0 : t >= nblk) return;
   const double* F = A.chol + I.chol_off;
   double* x = A.x + I.param_off;
-  __shared__ double xs[kNb];
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) xs[i] = x[o + i];
+  const int64_t ot = (int64_t)t * kNb, gc0 = (int64_t)c0 * kNb;
+  const int64_t gc1 = ((int64_t)c1 * kNb < I.np ? (int64_t)c1 * kNb : I.np);
+  const int nt = (int)(I.np - ot < kNb ? I.np - ot : kNb);
+  const int ncols = (int)(gc1 - gc0);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  __shared__ double xg[kTrsvG * kNb];
+  __shared__ double part[4][kNb];
+  for (int e = tid; e < ncols; e += 256) xg[e] = x[gc0 + e];
   __syncthreads();
-  const int r = threadIdx.x;
-  if (r < nr) {
-    double s = 0.0;
-    if (!transpose)
-      for (int c = 0; c < nb; ++c) s += F[(bo + r) * I.np + o + c] * xs[c];
-    else
-      for (int c = 0; c < nb; ++c) s += F[(o + c) * I.np + bo + r] * xs[c];
-    x[bo + r] -= s;
+  if (!transpose) {
+    constexpr int RW = kNb / 4;   // rows per wavefront
+    double acc[RW];
+#pragma unroll
+    for (int u = 0; u < RW; ++u) acc[u] = 0.0;
+    for (int m0 = 0; m0 < ncols; m0 += 64) {
+      const int m = m0 + lane;
+      const double xm = m < ncols ? xg[m] : 0.0;
+#pragma unroll
+      for (int u = 0; u < RW; ++u) {
+        const int i = wv + 4 * u;
+        acc[u] += (i < nt && m < ncols) ? F[(ot + i) * I.np + gc0 + m] * xm : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RW; ++u) {
+      const int i = wv + 4 * u;
+      const double v = wave::wave_total(acc[u]);
+      if (lane == 0 && i < nt) x[ot + i] -= v;
+    }
+  } else {
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (lane < nt)
+      for (int i0 = wv * 8; i0 < ncols; i0 += 32) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = i0 + u;
+          a[u] += i < ncols ? F[(gc0 + i) * I.np + ot + lane] * xg[i] : 0.0;
+        }
+      }
+    part[wv][lane] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    __syncthreads();
+    if (tid < nt) x[ot + tid] -= ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
   }
 }
 
@@ -889,15 +991,19 @@ void sr_cholesky_solve(const SrArgs& A, const TS* S, const double* g, double eps
       hipLaunchKernelGGL(k_chol_trail, dim3(nt * (nt + 1) / 2, n_inst), dim3(256), 0, s, A, ob);
     }
   }
-  for (int kb = 0; kb < nblk; ++kb) {
-    hipLaunchKernelGGL(k_trsv_diag, dim3(n_inst), dim3(64), 0, s, A, kb, 0);
-    if (nblk - kb - 1 > 0)
-      hipLaunchKernelGGL(k_trsv_update, dim3(nblk - kb - 1, n_inst), dim3(64), 0, s, A, kb, 0);
-  }
-  for (int kb = nblk - 1; kb >= 0; --kb) {
-    hipLaunchKernelGGL(k_trsv_diag, dim3(n_inst), dim3(64), 0, s, A, kb, 1);
-    if (kb > 0) hipLaunchKernelGGL(k_trsv_update, dim3(kb, n_inst), dim3(64), 0, s, A, kb, 1);
-  }
+  // substitutions: the diagonal blocks inverted at once, then groups of
+  // kTrsvG blocks, each solved by one workgroup and applied to the blocks
+  // outside it (group gi counts from the first block forward and from each
+  // instance's own last block backward)
+  hipLaunchKernelGGL(k_trtri_diag, dim3(nblk, n_inst), dim3(64), 0, s, A);
+  const int ngrp = ceil_div(nblk, kTrsvG);
+  for (int t = 0; t < 2; ++t)
+    for (int gi = 0; gi < ngrp; ++gi) {
+      hipLaunchKernelGGL(k_trsv_group, dim3(n_inst), dim3(256), 0, s, A, gi, t);
+      const int rest = nblk - (gi + 1) * kTrsvG;   // most target blocks of any instance
+      if (rest > 0)
+        hipLaunchKernelGGL(k_trsv_rest, dim3(rest, n_inst), dim3(256), 0, s, A, gi, t);
+    }
 }
 
 template <typename T>
