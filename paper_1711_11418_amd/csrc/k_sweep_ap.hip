@@ -16,7 +16,7 @@ namespace {
 // Register budget of four waves per SIMD in single precision, three in
 // double (four would spill the double variants).
 template <typename T, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 3)))
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
 void k_sweep_ap(Pools P, const int32_t* __restrict__ wlist, int cap, uint64_t seed,
                 TraceRec* trace, int64_t trace_cap, const uint64_t* __restrict__ trace_base,
                 const uint64_t* __restrict__ target, int32_t* __restrict__ needs_refresh, int R,
