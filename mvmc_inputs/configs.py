@@ -22,7 +22,7 @@ from __future__ import annotations
 import numpy as np
 
 from .instance import (Instance, f_map_full, f_map_sublattice, make_instance,
-                       ring8_orbitals, v_map_distance, v_map_nn)
+                       ring8_orbitals, translation_projection, v_map_distance, v_map_nn)
 from .lattice import chain, square
 
 INPUT_SEED = 11418
@@ -139,6 +139,31 @@ def workload(name: str, **overrides) -> dict:
         assert np.array_equal(rbm.params0[:pj.n_params], pj.params0)
         d = _wl([pj, rbm], sweeps=20, warmup=20, sr_iters=80, dtau=0.05,
                 sampler_seed=1711 * 1000 + 6)
+    elif name in ("ring4_proj", "ring4_projpi", "ring6_proj3"):
+        # momentum projection (section 3.2.2): every translation of the
+        # 4-site ring at K = 0 or pi, or the translations by 0, 2, 4 sites
+        # of the 6-site ring at K = 0
+        L = 6 if name == "ring6_proj3" else 4
+        lat = chain(L)
+        inst = make_instance(f"{name}_U4", lat, L // 2, L // 2, 4.0, f_map_full(lat),
+                             v_map_nn(lat), f_noise=0.05, n_walkers=nw or 16, seed=INPUT_SEED)
+        steps = [(0, 0), (2, 0), (4, 0)] if L == 6 else [(r, 0) for r in range(4)]
+        inst.proj_q, inst.proj_w = translation_projection(
+            lat, steps, kx=np.pi if name == "ring4_projpi" else 0.0)
+        d = _wl([inst], sweeps=100, warmup=20, sr_iters=0)
+    elif name in ("sq4_u4_proj4", "sq4_sub2_proj4"):
+        # 4x4 with a 2x2-sublattice pair amplitude and the four translations
+        # inside the 2x2 cell at K = 0 (with the sublattice structure this is
+        # the full K = 0 momentum projection): half filling for the energy
+        # leg, 7 + 7 electrons for parity
+        lat = square(4)
+        ne = 8 if name == "sq4_u4_proj4" else 7
+        inst = make_instance(name, lat, ne, ne, 4.0, f_map_sublattice(lat, 2, 2),
+                             v_map_distance(lat), f_noise=0.05, n_walkers=nw or 1024,
+                             seed=INPUT_SEED)
+        inst.proj_q, inst.proj_w = translation_projection(lat, [(0, 0), (1, 0), (0, 1), (1, 1)])
+        d = _wl([inst], sweeps=20, warmup=50, sample_every=1, sr_iters=0, dtau=0.05,
+                sampler_seed=1711 * 1000 + 7)
     else:
         raise KeyError(name)
     d["name"] = name
@@ -148,7 +173,8 @@ def workload(name: str, **overrides) -> dict:
 
 WORKLOADS = ("ring8_u4", "sq8_u4", "sq10_u8", "batch32_ragged",
              "sq16_u8_rbm", "sq16_u8_pj", "ring4", "ring6", "sq4_sub2", "ring6_rbm",
-             "ring6_u8_gain")
+             "ring6_u8_gain", "ring4_proj", "ring4_projpi", "ring6_proj3", "sq4_u4_proj4",
+             "sq4_sub2_proj4")
 
 
 def random_configs(inst: Instance, n: int, seed: int) -> np.ndarray:

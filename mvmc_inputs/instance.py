@@ -39,6 +39,10 @@ class Instance:
     n_hidden: int               # RBM hidden units M (0 = no RBM)
     n_walkers: int
     params0: np.ndarray = field(repr=False)   # initial parameter vector
+    # quantum-number projection (section 3.2.2): site maps q_p [N_P, Ns] and
+    # weights w_p [N_P]; None = no projection (one identity term)
+    proj_q: np.ndarray | None = field(default=None, repr=False)
+    proj_w: np.ndarray | None = field(default=None, repr=False)
 
     @property
     def n_sites(self) -> int:
@@ -95,6 +99,23 @@ def f_map_sublattice(lat: Lattice, sx: int, sy: int) -> tuple[np.ndarray, int]:
             dx, dy = lat.displacement(i, j)
             idx[i, j] = sub * n + dx + lat.Lx * dy
     return idx, sx * sy * n
+
+
+def translation_projection(lat: Lattice, steps: list[tuple[int, int]],
+                           kx: float = 0.0, ky: float = 0.0) -> tuple[np.ndarray, np.ndarray]:
+    """Site maps and weights of the translations by the given (dx, dy) steps
+    with momentum (kx, ky) in {0, pi}: q_p(i) = site of r_i + R_p, weight
+    cos(K . R_p) (real characters only)."""
+    n = lat.n_sites
+    q = np.empty((len(steps), n), dtype=np.int32)
+    w = np.empty(len(steps))
+    for p, (dx, dy) in enumerate(steps):
+        for i in range(n):
+            x, y = lat.coords[i]
+            q[p, i] = ((x + dx) % lat.Lx) + lat.Lx * ((y + dy) % lat.Ly)
+        w[p] = np.cos(kx * dx + ky * dy)
+    w[np.abs(w) < 1e-12] = 0.0
+    return q, np.round(w)
 
 
 def g_map_uniform(lat: Lattice) -> tuple[np.ndarray, int]:

@@ -17,7 +17,9 @@ method"), not the fast algorithms the GPU uses:
                      and a brute-force perfect-matching sum.
 * wavefunction.py -- log <x|psi> from scratch: Pfaffian of X_IJ = F_IJ - F_JI
                      (section 3.2.1, Eqs. Pf and AP-Pf), Gutzwiller and
-                     Jastrow factors (section 3.2.3) and an RBM factor.
+                     Jastrow factors (section 3.2.3), an RBM factor, and the
+                     momentum / point-group projection sum_p w_p T_p of the
+                     pair-product part (section 3.2.2).
 * sampler.py      -- Metropolis chain with a full recomputation per proposal
                      (section 3.1, Eq. MC; hopping update of Fig. 5a).
 * measure.py      -- local energy and O_k = d ln<x|psi>/d alpha_k

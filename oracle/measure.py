@@ -29,7 +29,8 @@ import numpy as np
 
 import math
 
-from .wavefunction import Model, log_psi, occupations, skew_table
+from .pfaffian import pfaffian_log
+from .wavefunction import Model, log_psi, mapped, occupations, skew_table
 
 
 def neighbours(m: Model) -> list[list[tuple[int, float]]]:
@@ -76,15 +77,31 @@ def log_derivs(inst, m: Model, pos: np.ndarray, A: np.ndarray | None = None) -> 
     pos = np.asarray(pos)
     o = inst.offsets()
     out = np.zeros(inst.n_params)
-    X = A[np.ix_(pos, pos)]
-    Y = np.linalg.inv(X)
-    for a in range(m.n_up):
-        i = int(pos[a])
-        for b in range(m.n_up, m.n_elec):
-            j = int(pos[b]) - ns
-            k = int(inst.f_idx[i, j])
-            if k >= 0:
-                out[o["f"] + k] += -Y[a, b]
+    # f: with the projection terms c_p = w_p Pf(X(q_p(x))),
+    # d ln psi / d f_k = sum_p c_p (d ln Pf_p / d f_k) / sum_p c_p, and
+    # d ln Pf(X) / dX_ab (a up, b down; X_ba = -X_ab moves with it) = -(X^-1)_ab
+    # on the entries whose mapped sites (i, j) carry slot k
+    terms = []
+    if m.proj_q is None:
+        terms.append((1.0, pos))
+    else:
+        for p in range(len(m.proj_q)):
+            terms.append((float(m.proj_w[p]), mapped(m, pos, p)))
+    logs = [pfaffian_log(A[np.ix_(y, y)]) for _, y in terms]
+    lmax = max(l for s, l in logs if s != 0.0)
+    cs = [w * s * math.exp(l - lmax) if s != 0.0 else 0.0 for (w, _), (s, l) in zip(terms, logs)]
+    ctot = sum(cs)
+    for (w, y), c in zip(terms, cs):
+        if c == 0.0:
+            continue
+        Y = np.linalg.inv(A[np.ix_(y, y)])
+        for a in range(m.n_up):
+            i = int(y[a])
+            for b in range(m.n_up, m.n_elec):
+                j = int(y[b]) - ns
+                k = int(inst.f_idx[i, j])
+                if k >= 0:
+                    out[o["f"] + k] += -Y[a, b] * c / ctot
     nv = occupations(m, pos)
     nup, ndn = nv[:ns], nv[ns:]
     for i in range(ns):

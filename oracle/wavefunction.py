@@ -13,6 +13,14 @@ Definitions followed (paper arXiv:1711.11418):
 * RBM factor (not in the paper): visible sigma_v = 2 n_v - 1 over the 2 Ns
   spin-orbitals, theta = b + W sigma,
   log psi_RBM = sum_v a_v sigma_v + sum_h log(2 cosh theta_h).
+* Quantum-number projection (section 3.2.2, Eqs. momP and pointP): the
+  projector sum_p w_p T_p acts on the pair-product part,
+  <x|psi> = P_G P_J [RBM] sum_p w_p <x|T_p|phi_Pf>.  With T_p a site
+  permutation, <x|T_p|phi_Pf> is the Pfaffian of the configuration whose
+  electrons sit on the mapped sites (electron labels, hence the fermion
+  sign, kept): Pf(X(q_p(x))), X(y)_ab = A[R_a(y)][R_b(y)] with the site part
+  of every spin-orbital sent through the table q_p.  The normalisation
+  1/N_g is dropped.
 
 Pinned by the Pfaffian tests, by the exhaustive <H> against exact
 diagonalisation and by the zero-variance Slater case (tests/).
@@ -42,6 +50,8 @@ class Model:
     a: np.ndarray          # [2Ns]   (empty if no RBM)
     b: np.ndarray          # [M]
     W: np.ndarray          # [M, 2Ns]
+    proj_q: np.ndarray | None = None   # [N_P, Ns] site maps (None: no projection)
+    proj_w: np.ndarray | None = None   # [N_P] weights
 
     @property
     def n_elec(self) -> int:
@@ -73,8 +83,12 @@ def expand(inst, params: np.ndarray) -> Model:
         a = np.zeros(0)
         b = np.zeros(0)
         W = np.zeros((0, 2 * ns))
+    pq = getattr(inst, "proj_q", None)
+    pw = getattr(inst, "proj_w", None)
     return Model(ns, inst.n_up, inst.n_dn, np.asarray(inst.bonds), inst.bond_t,
-                 np.asarray(inst.U, dtype=np.float64), f, g, V, a, b, W)
+                 np.asarray(inst.U, dtype=np.float64), f, g, V, a, b, W,
+                 None if pq is None else np.asarray(pq, dtype=np.int64),
+                 None if pw is None else np.asarray(pw, dtype=np.float64))
 
 
 def skew_table(m: Model) -> np.ndarray:
@@ -112,16 +126,44 @@ def log_correlators(m: Model, pos: np.ndarray) -> float:
     return out
 
 
+def mapped(m: Model, pos: np.ndarray, p: int) -> np.ndarray:
+    """Spin-orbitals of the configuration q_p(x): site part through q_p,
+    spin kept, electron order kept."""
+    ns = m.n_sites
+    pos = np.asarray(pos)
+    sig = pos // ns
+    return m.proj_q[p][pos - sig * ns] + sig * ns
+
+
+def pair_terms(m: Model, pos: np.ndarray, A: np.ndarray) -> list[tuple[float, float, float]]:
+    """(w_p, sign, log|Pf|) of every projection term (one identity term when
+    there is no projection)."""
+    pos = np.asarray(pos)
+    if m.proj_q is None:
+        s, l = pfaffian_log(A[np.ix_(pos, pos)])
+        return [(1.0, s, l)]
+    out = []
+    for p in range(len(m.proj_q)):
+        y = mapped(m, pos, p)
+        s, l = pfaffian_log(A[np.ix_(y, y)])
+        out.append((float(m.proj_w[p]), s, l))
+    return out
+
+
 def log_psi(m: Model, pos: np.ndarray, A: np.ndarray | None = None) -> tuple[float, float]:
     """(sign, log|psi(x)|) with electron a at spin-orbital pos[a]."""
     if A is None:
         A = skew_table(m)
     pos = np.asarray(pos)
-    X = A[np.ix_(pos, pos)]
-    s, l = pfaffian_log(X)
-    if s == 0.0:
+    terms = [(w, s, l) for w, s, l in pair_terms(m, pos, A) if w != 0.0 and s != 0.0]
+    if not terms:
         return 0.0, -math.inf
-    return s, l + log_correlators(m, pos)
+    lmax = max(l for _, _, l in terms)
+    tot = sum(w * s * math.exp(l - lmax) for w, s, l in terms)
+    if tot == 0.0:
+        return 0.0, -math.inf
+    s = 1.0 if tot > 0.0 else -1.0
+    return s, lmax + math.log(abs(tot)) + log_correlators(m, pos)
 
 
 def ratio(m: Model, pos_new: np.ndarray, pos_old: np.ndarray, A: np.ndarray | None = None) -> float:
