@@ -53,6 +53,7 @@ struct Plan {
       nbr_site, nbr_t, fm_ptr, fm, gm_ptr, gm, vm_ptr, vm, rbm64, rbm32, rbmT64, rbmT32, Y, Y64,
       pos, empty, h,
       theta, cnt, target, needs_refresh, accepted, logpf, sgnpf, minpiv, status, guard, chk, lz,
+      dotpart,
       trace_base,
       obar, sdiag, x, r, p, w, t, shift, mask, scal, colpart, syrkpart, chol, split;
   size_t total = 0;
@@ -480,6 +481,7 @@ Plan make_plan(const mvmc_config& c) {
   take(P.w, 8 * NP);
   take(P.shift, 8 * NP);
   take(P.mask, 8 * NP);
+  take(P.dotpart, 8 * (size_t)kDotParts * n);
   take(P.t, 8 * (size_t)P.eloc);
   take(P.scal, 8 * (size_t)kScal * n);
   take(P.colpart, 8 * (size_t)off_colpart);
@@ -1002,6 +1004,7 @@ int init_impl(mvmc_ctx** out, const mvmc_config* cfg, void* d_ws, size_t ws_byte
   S.t = at<double>(b, P.t);
   S.shift = at<double>(b, P.shift);
   S.mask = at<double>(b, P.mask);
+  S.dotpart = at<double>(b, P.dotpart);
 
   // static tables
   std::vector<int32_t> winst(P.W);

@@ -766,16 +766,40 @@ __global__ void k_cg_init(SrArgs A, const double* __restrict__ g, double eps_rel
   A.mask[o] = keep ? 1.0 : 0.0;
 }
 
-// out = a . b per instance (one block per instance, fixed order)
-__global__ void k_dot(SrArgs A, const double* __restrict__ a, const double* __restrict__ b,
-                      int slot, int check_done) {
-  const SrInst& I = A.inst[blockIdx.x];
-  if (check_done && A.scal[blockIdx.x * kScal + kDone] != 0.0) return;
+// out = a . b per instance in two fixed-order passes: chunk partial sums
+// over up to kDotParts workgroups (chunks of at least 4096 entries), then
+// their sum in chunk order.
+__device__ __forceinline__ int dot_parts(int64_t np) {
+  const int64_t p = ceil_div<int64_t>(np, 4096);
+  return (int)(p < kDotParts ? (p > 0 ? p : 1) : kDotParts);
+}
+
+__global__ __launch_bounds__(256) void k_dot_part(SrArgs A, const double* __restrict__ a,
+                                                  const double* __restrict__ b, int check_done) {
+  const SrInst& I = A.inst[blockIdx.y];
+  if (check_done && A.scal[blockIdx.y * kScal + kDone] != 0.0) return;
+  const int parts = dot_parts(I.np);
+  if ((int)blockIdx.x >= parts) return;
+  const int64_t chunk = ceil_div<int64_t>(I.np, parts);
+  const int64_t k0 = (int64_t)blockIdx.x * chunk;
+  const int64_t k1 = k0 + chunk < I.np ? k0 + chunk : I.np;
   __shared__ double red[16];
   double s = 0.0;
-  for (int64_t k = threadIdx.x; k < I.np; k += blockDim.x) s += a[I.param_off + k] * b[I.param_off + k];
+  for (int64_t k = k0 + threadIdx.x; k < k1; k += blockDim.x)
+    s += a[I.param_off + k] * b[I.param_off + k];
   s = block_sum(s, red);
-  if (threadIdx.x == 0) A.scal[blockIdx.x * kScal + slot] = s;
+  if (threadIdx.x == 0) A.dotpart[(int64_t)blockIdx.y * kDotParts + blockIdx.x] = s;
+}
+
+__global__ void k_dot_finish(SrArgs A, int slot, int check_done) {
+  const SrInst& I = A.inst[blockIdx.x];
+  if (check_done && A.scal[blockIdx.x * kScal + kDone] != 0.0) return;
+  if (threadIdx.x != 0) return;
+  const double* pp = A.dotpart + (int64_t)blockIdx.x * kDotParts;
+  const int parts = dot_parts(I.np);
+  double s = 0.0;
+  for (int q = 0; q < parts; ++q) s += pp[q];
+  A.scal[blockIdx.x * kScal + slot] = s;
 }
 
 // t = O~ (mask o p).  A wavefront takes kRowsPerWave sample rows (one read
@@ -1006,13 +1030,22 @@ void sr_cholesky_solve(const SrArgs& A, const TS* S, const double* g, double eps
     }
 }
 
+namespace {
+void sr_dot(const SrArgs& A, const double* a, const double* b, int slot, int check_done,
+            int n_inst, int64_t max_np, hipStream_t s) {
+  const int64_t p = ceil_div<int64_t>(max_np, 4096);
+  const int parts = (int)(p < kDotParts ? (p > 0 ? p : 1) : kDotParts);
+  hipLaunchKernelGGL(k_dot_part, dim3(parts, n_inst), dim3(256), 0, s, A, a, b, check_done);
+  hipLaunchKernelGGL(k_dot_finish, dim3(n_inst), dim3(64), 0, s, A, slot, check_done);
+}
+}  // namespace
+
 template <typename T>
 void sr_cg_begin(const SrArgs& A, const double* g, double eps_rel, double eps_abs, double freeze,
                  double eps, int n_inst, int64_t max_np, hipStream_t s) {
   const int cb = (int)ceil_div<int64_t>(max_np, 256);
   hipLaunchKernelGGL(k_cg_init, dim3(cb, n_inst), dim3(256), 0, s, A, g, eps_rel, eps_abs, freeze);
-  hipLaunchKernelGGL(k_dot, dim3(n_inst), dim3(256), 0, s, A, (const double*)A.r, (const double*)A.r,
-                     kRho, 0);
+  sr_dot(A, A.r, A.r, kRho, 0, n_inst, max_np, s);
   hipLaunchKernelGGL(k_cg_setup, dim3(n_inst), dim3(1), 0, s, A, eps);
 }
 
@@ -1031,11 +1064,9 @@ void sr_cg_iter(const SrArgs& A, const T* O, int iter, int n_inst, int64_t max_n
                           (unsigned)ceil_div<int64_t>(max_rows, kRowChunk), n_inst),
                      dim3(256), 0, s, A, O);
   hipLaunchKernelGGL(k_gemv_cols_finish, dim3(cb, n_inst), dim3(256), 0, s, A);
-  hipLaunchKernelGGL(k_dot, dim3(n_inst), dim3(256), 0, s, A, (const double*)A.p, (const double*)A.w,
-                     kPw, 1);
+  sr_dot(A, A.p, A.w, kPw, 1, n_inst, max_np, s);
   hipLaunchKernelGGL(k_cg_xr, dim3(cb, n_inst), dim3(256), 0, s, A);
-  hipLaunchKernelGGL(k_dot, dim3(n_inst), dim3(256), 0, s, A, (const double*)A.r, (const double*)A.r,
-                     kRhoNew, 1);
+  sr_dot(A, A.r, A.r, kRhoNew, 1, n_inst, max_np, s);
   hipLaunchKernelGGL(k_cg_check, dim3(n_inst), dim3(1), 0, s, A, iter);
   hipLaunchKernelGGL(k_cg_p, dim3(cb, n_inst), dim3(256), 0, s, A);
 }

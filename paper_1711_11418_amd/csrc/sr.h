@@ -58,7 +58,10 @@ struct SrArgs {
   double* t;
   double* shift;
   double* mask;
+  double* dotpart;                // [inst][kDotParts] partial dot products
 };
+
+constexpr int kDotParts = 256;    // most partial sums of one dot product
 
 // bfloat16 with round-to-nearest-even (NaN kept quiet).
 __host__ __device__ inline uint16_t f32_to_bf16(float f) {
