@@ -81,7 +81,25 @@ typedef struct {
   const int32_t *v_idx;       /* [Ns*Ns] symmetric, diagonal -1 */
   int32_t n_hidden;           /* RBM hidden units M; 0 = no RBM factor */
   int32_t n_walkers;          /* independent Markov chains for this instance */
+  /* Quantum-number projection of the pair-product part (section 3.2.2, Eqs.
+   * momP and pointP): <x|psi> = P_G P_J [RBM] sum_p w_p Pf(X(q_p(x))), where
+   * q_p(x) puts every electron on the image q_p(i) of its site i (spin and
+   * electron order kept), i.e. term p is the AP Pfaffian with
+   * f_p(i, j) = f(q_p(i), q_p(j)).  A translation or point-group operation
+   * with a real character (momentum K with K.R in {0, pi}) is one term; the
+   * 1/N_g normalisation is dropped.  n_proj = 0: no projection.  Projected
+   * instances run their own sweep (hopping updates, all N_P inverses M_p^-1
+   * in LDS, rank-1 updates of each) and refresh; they need exchange_per64 = 0
+   * and MVMC_SCHED_BUCKETS, and sweep_variant / sweep_threads do not apply
+   * to them.  Every M_p must be invertible at every visited configuration: a
+   * proposal whose acceptance would make one singular stops the walker like
+   * a non-finite ratio. */
+  int32_t n_proj;             /* N_P, 0..MVMC_MAX_PROJ */
+  const int32_t *proj_map;    /* [N_P * Ns] row-major: q_p(i); each row a permutation */
+  const double *proj_weight;  /* [N_P] real weights w_p, finite, not all zero */
 } mvmc_instance_desc;
+
+#define MVMC_MAX_PROJ 32
 
 typedef struct {
   int32_t precision;          /* MVMC_FP64: double sweeps and S.  MVMC_MIXED: single-
@@ -140,11 +158,17 @@ typedef struct {
                                       O_ld = n_params rounded up to 64 (to 128 when
                                       n_params > 3968) */
   int64_t S_off;                   /* S block [n_params][n_params] at S_off (full square) */
-  int64_t Y_off;                   /* get_inverse: walker w at Y_off + w*n_elec^2, row-major */
+  int64_t Y_off;                   /* get_inverse: walker w at Y_off + w*Y_ld; X^-1 row-major
+                                      (n_elec^2 entries), or for a projected instance the
+                                      N_P blocks M_p^-1 (n x n each, n = n_elec/2, block p at
+                                      p*n^2, entry [b][a] at b*n + a for down electron b and
+                                      up electron a: X(q_p(x))^-1[n + b][a]) */
   int64_t pos_off;                 /* get/set_state: walker w at pos_off + w*n_elec */
   int64_t empty_off;               /* get/set_state: walker w at empty_off + w*2*n_sites,
                                       [spin][n_sites], n_sites - n_sigma sites then -1 */
   int32_t n_elec, n_sites;
+  int64_t Y_ld;                    /* entries per walker of get_inverse: n_elec^2, or
+                                      max(n_elec^2, N_P n^2) for a projected instance */
 } mvmc_instance_layout;
 
 /* Sizes for cfg; touches no device.  Errors: MVMC_E_ARG / MVMC_E_SHAPE. */
@@ -219,7 +243,9 @@ int mvmc_sample_sweeps(mvmc_ctx *ctx, int32_t n_sweeps, int64_t *h_accepted);
  * with 64/128/256, 7-9 the anti-parallel block alone (M^-1, n x n with
  * n = N_e/2, Eq. AP-Pf) in LDS with 64/128/256 threads: rank-1
  * Sherman-Morrison updates of M^-1 (a quarter of the state of 1-6).
- * Automatic choice: 0 where it fits, else 7-9 (threads by n), else 6. */
+ * Automatic choice: 0 where it fits, else 7-9 (threads by n), else 6.
+ * mvmc_sweep_variants reports MVMC_N_SWEEP_VARIANTS for a projected instance
+ * (its own sweep; the autotuner leaves it alone). */
 enum { MVMC_N_SWEEP_VARIANTS = 10 };
 
 /*
@@ -298,7 +324,7 @@ int mvmc_measure_energy_and_O(mvmc_ctx *ctx, int32_t slot, double *d_eloc, void 
  * of the one- and two-electron moves come from M^-1 (Eq. AP-Pf) and its
  * products with the pair amplitudes, formed per walker in LDS in double.
  * Pfaffian-Jastrow-Gutzwiller states only: an instance with an RBM factor
- * gives MVMC_E_ARG; MVMC_E_SHAPE where N_s, N_e do not fit the LDS budget
+ * or a quantum-number projection gives MVMC_E_ARG; MVMC_E_SHAPE where N_s, N_e do not fit the LDS budget
  * (about N_s <= 90 at half filling).  Enqueues only (capturable).
  * Errors: MVMC_E_ARG, MVMC_E_SHAPE, MVMC_E_HIP.
  */
@@ -385,10 +411,13 @@ int mvmc_get_state(mvmc_ctx *ctx, int16_t *d_pos, uint64_t *d_counter, int16_t *
 int mvmc_set_state(mvmc_ctx *ctx, const int16_t *d_pos, const uint64_t *d_counter,
                    const int16_t *d_empty);
 
-/* Every walker's current X^-1 as double (Y_elems, layout above). */
+/* Every walker's current X^-1 as double (Y_elems, layout above; the N_P
+ * inverses M_p^-1 for a projected instance). */
 int mvmc_get_inverse(mvmc_ctx *ctx, double *d_Y);
 
-/* log|Pf(X)| and sign of every walker from the last full recomputation. */
+/* log|Pf(X)| and sign of every walker from the last full recomputation
+ * (log|sum_p w_p Pf(X(q_p(x)))| and its sign for a projected instance, kept
+ * current by its sweep). */
 int mvmc_get_pfaffian(mvmc_ctx *ctx, double *d_logabs, double *d_sign);
 
 /* Full double recomputation of every walker now (X^-1, log|Pf X| and sign,

@@ -29,6 +29,7 @@ ENTRY_POINTS = (
 N_SWEEP_VARIANTS = 10
 SWEEP_VARIANT_NAMES = ("reg", "lds64", "lds128", "lds256", "hbm64", "hbm128", "hbm256",
                        "ap64", "ap128", "ap256")
+PROJ_VARIANT = "proj"   # reported for instances with a quantum-number projection
 SCHEDULES = ("buckets", "queue")   # MVMC_SCHED_BUCKETS, MVMC_SCHED_QUEUE
 
 
@@ -41,6 +42,8 @@ class InstanceDesc(C.Structure):
         ("n_g", C.c_int32), ("g_idx", C.POINTER(C.c_int32)),
         ("n_v", C.c_int32), ("v_idx", C.POINTER(C.c_int32)),
         ("n_hidden", C.c_int32), ("n_walkers", C.c_int32),
+        ("n_proj", C.c_int32), ("proj_map", C.POINTER(C.c_int32)),
+        ("proj_weight", C.POINTER(C.c_double)),
     ]
 
 
@@ -69,6 +72,7 @@ class Layout(C.Structure):
         ("n_params", C.c_int64), ("eloc_off", C.c_int64), ("O_off", C.c_int64),
         ("O_ld", C.c_int64), ("S_off", C.c_int64), ("Y_off", C.c_int64), ("pos_off", C.c_int64),
         ("empty_off", C.c_int64), ("n_elec", C.c_int32), ("n_sites", C.c_int32),
+        ("Y_ld", C.c_int64),
     ]
 
 
@@ -166,11 +170,21 @@ class _Desc:
         self.v = np.ascontiguousarray(np.asarray(inst.v_idx, dtype=np.int32).ravel())
         p32 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
         p64 = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+        pq = getattr(inst, "proj_q", None)
+        pw = getattr(inst, "proj_w", None)
+        if pq is None:
+            self.pq = np.zeros(1, dtype=np.int32)
+            self.pw = np.zeros(1, dtype=np.float64)
+            n_proj = 0
+        else:
+            self.pq = np.ascontiguousarray(np.asarray(pq, dtype=np.int32).reshape(-1))
+            self.pw = np.ascontiguousarray(np.asarray(pw, dtype=np.float64).reshape(-1))
+            n_proj = len(self.pw)
         self.desc = InstanceDesc(int(inst.n_sites), int(inst.n_up), int(inst.n_dn), len(self.bi),
                                  p32(self.bi), p32(self.bj), p64(self.bt), p64(self.U),
                                  int(inst.n_f), p32(self.f), int(inst.n_g), p32(self.g),
                                  int(inst.n_v), p32(self.v), int(inst.n_hidden),
-                                 int(inst.n_walkers))
+                                 int(inst.n_walkers), n_proj, p32(self.pq), p64(self.pw))
 
 
 def make_config(instances, precision="fp64", refresh_every=0, seed=1, n_slots=1, solver="chol",
@@ -434,7 +448,7 @@ class MVMC:
     def sweep_variants(self) -> list[str]:
         v = np.zeros(self.n_inst, dtype=np.int32)
         self._check(self.lib.mvmc_sweep_variants(self.ctx, v.ctypes.data_as(C.c_void_p)))
-        return [SWEEP_VARIANT_NAMES[i] for i in v]
+        return [(SWEEP_VARIANT_NAMES + (PROJ_VARIANT,))[i] for i in v]
 
     def timing(self, enable: bool):
         ms = np.zeros(6)
@@ -470,4 +484,13 @@ class MVMC:
     def Y_of(self, Y, k: int):
         l = self.layouts[k]
         ne = l.n_elec
-        return Y[l.Y_off:l.Y_off + l.n_walkers * ne * ne].view(l.n_walkers, ne, ne)
+        rows = Y[l.Y_off:l.Y_off + l.n_walkers * l.Y_ld].view(l.n_walkers, l.Y_ld)
+        return rows[:, :ne * ne].reshape(l.n_walkers, ne, ne)
+
+    def proj_inverses_of(self, Y, k: int, n_proj: int):
+        """[walkers, N_P, n, n] view of a projected instance's M_p^-1 blocks
+        (entry [b][a]: down electron b, up electron a)."""
+        l = self.layouts[k]
+        n = l.n_elec // 2
+        rows = Y[l.Y_off:l.Y_off + l.n_walkers * l.Y_ld].view(l.n_walkers, l.Y_ld)
+        return rows[:, :n_proj * n * n].reshape(l.n_walkers, n_proj, n, n)

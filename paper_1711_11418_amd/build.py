@@ -21,7 +21,7 @@ OBJDIR = os.path.join(HERE, "_build")
 
 SOURCES = ["api.cpp", "k_state.hip", "k_refresh.hip", "k_sweep.hip", "k_measure.hip",
            "k_sr.hip", "k_syrk_bf16.hip", "k_sweep_reg.hip", "k_refresh_ap.hip", "k_probe.hip",
-           "k_sweep_ap.hip", "k_sweep_queue.hip", "k_lanczos.hip"]
+           "k_sweep_ap.hip", "k_sweep_queue.hip", "k_lanczos.hip", "k_proj.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -45,6 +45,8 @@ struct Plan {
   std::vector<int> reg_class;     // register-sweep tier per instance (0 = LDS/HBM kernel)
   std::vector<int> sweep_nt;      // threads of the LDS/HBM sweep kernel per instance
   std::vector<char> sweep_ap;     // 1 = anti-parallel-block sweep (M^-1 alone in LDS)
+  bool any_proj = false;          // some instance has a quantum-number projection
+  size_t proj_sweep_lds = 0, proj_measure_lds = 0;   // largest needs over projected instances
   int bad_variant = -1;           // instance a forced sweep variant does not fit
   bool exchange = false;          // exchange updates on (variants 0 and 7-9 only)
   bool queue = false;             // one persistent sweep launch (variants 0 and 9 only)
@@ -52,7 +54,7 @@ struct Plan {
   Pool inst_p, srinst_p, walker_inst, lists, A64, A32, V, fidx, vidx, G, U, gidx, nbr_ptr,
       nbr_site, nbr_t, fm_ptr, fm, gm_ptr, gm, vm_ptr, vm, rbm64, rbm32, rbmT64, rbmT32, Y, Y64,
       pos, empty, h,
-      theta, cnt, target, needs_refresh, accepted, logpf, sgnpf, minpiv, status, guard, chk, lz,
+      theta, pmap, projw, pterm, cnt, target, needs_refresh, accepted, logpf, sgnpf, minpiv, status, guard, chk, lz,
       dotpart,
       trace_base,
       obar, sdiag, x, r, p, w, t, shift, mask, scal, colpart, syrkpart, chol, split;
@@ -191,6 +193,31 @@ Err validate(const mvmc_config* c) {
     }
     for (int i = 0; i < ns; ++i)
       if (d.g_idx[i] < -1 || d.g_idx[i] >= d.n_g) return fail(MVMC_E_ARG, "instance %d: g_idx out of range", k);
+    if (d.n_proj < 0 || d.n_proj > MVMC_MAX_PROJ)
+      return fail(MVMC_E_ARG, "instance %d: n_proj %d outside [0, %d]", k, d.n_proj, MVMC_MAX_PROJ);
+    if (d.n_proj > 0) {
+      if (!d.proj_map || !d.proj_weight)
+        return fail(MVMC_E_ARG, "instance %d: projection maps or weights missing", k);
+      bool any_w = false;
+      for (int p = 0; p < d.n_proj; ++p) {
+        if (!std::isfinite(d.proj_weight[p]))
+          return fail(MVMC_E_NONFINITE, "instance %d: projection weight %d not finite", k, p);
+        any_w = any_w || d.proj_weight[p] != 0.0;
+        std::vector<char> seen(ns, 0);
+        for (int i = 0; i < ns; ++i) {
+          const int32_t t = d.proj_map[(size_t)p * ns + i];
+          if (t < 0 || t >= ns || seen[t])
+            return fail(MVMC_E_ARG, "instance %d: projection map %d is not a permutation", k, p);
+          seen[t] = 1;
+        }
+      }
+      if (!any_w) return fail(MVMC_E_ARG, "instance %d: every projection weight is zero", k);
+      if (c->exchange_per64)
+        return fail(MVMC_E_ARG, "instance %d: projected states take hopping updates only "
+                                "(exchange_per64 = 0)", k);
+      if (c->schedule == MVMC_SCHED_QUEUE)
+        return fail(MVMC_E_ARG, "instance %d: projected states need MVMC_SCHED_BUCKETS", k);
+    }
   }
   return Err{};
 }
@@ -220,6 +247,7 @@ int64_t v_members(const mvmc_instance_desc& d) {
 // 64/128/256 threads.  Exchange updates run on 0 and 7-9 only.
 bool variant_fits(const Plan& P, int k, int v) {
   const InstDev& I = P.inst[k];
+  if (I.nproj) return false;   // projected instances have a sweep of their own
   if (P.exchange && v >= 1 && v <= 6) return false;
   if (P.queue) {
     if (v != 0 && v != 9) return false;
@@ -238,6 +266,7 @@ bool variant_fits(const Plan& P, int k, int v) {
   return sweep_lds_bytes(I.ne, I.ns, I.M, v <= 3, P.tsize, nt) <= kLdsLimit;
 }
 int variant_of(const Plan& P, int k) {
+  if (P.inst[k].nproj) return MVMC_N_SWEEP_VARIANTS;
   if (P.reg_class[k]) return 0;
   const int nt = P.sweep_nt[k];
   const int base = P.sweep_ap[k] ? 7 : (P.inst[k].sweep_lds ? 1 : 4);
@@ -245,6 +274,7 @@ int variant_of(const Plan& P, int k) {
 }
 void set_variant(Plan& P, int k, int v) {
   InstDev& I = P.inst[k];
+  if (I.nproj) return;
   if (v == 0) {
     P.reg_class[k] = sweep_reg_class(I.ne, P.tsize);
     P.sweep_ap[k] = 0;
@@ -280,6 +310,7 @@ Plan make_plan(const mvmc_config& c) {
   int64_t off_A = 0, off_V = 0, off_site = 0, off_nptr = 0, off_nbr = 0, off_fm_ptr = 0,
           off_fm = 0, off_gm_ptr = 0, off_gm = 0, off_vm_ptr = 0, off_vm = 0, off_rbm = 0,
           off_Y = 0, off_pos = 0, off_empty = 0, off_h = 0, off_theta = 0, off_chol = 0,
+          off_pmap = 0, off_projw = 0, off_pterm = 0,
           off_split = 0, off_colpart = 0, off_syrkpart = 0, off_O = 0, off_S = 0;
   for (int k = 0; k < n; ++k) {
     const mvmc_instance_desc& d = c.inst[k];
@@ -294,6 +325,7 @@ Plan make_plan(const mvmc_config& c) {
     I.nv = d.n_v;
     I.M = d.n_hidden;
     I.W = d.n_walkers;
+    I.nproj = d.n_proj;
     I.np = (int32_t)nparams_of(d);
     // O rows padded to 64 parameters, to 128 when the split-bf16 S build
     // takes 128 x 128 tiles (whose operand loads then stay inside the row)
@@ -308,7 +340,17 @@ Plan make_plan(const mvmc_config& c) {
     const int nt = sweep_threads_for(c, I.ne);
     P.sweep_nt[k] = nt;
     I.sweep_lds = sweep_lds_bytes(I.ne, I.ns, I.M, true, P.tsize, nt) <= kLdsLimit;
-    if (c.sweep_variant > 0) {   // forced variant
+    if (I.nproj) {   // its own sweep, refresh and measurement kernels
+      I.sweep_lds = 0;
+      P.any_proj = true;
+      const size_t sw = sweep_proj_lds_bytes(I.ne, I.ns, I.M, I.nproj, P.tsize);
+      const size_t me = measure_proj_lds_bytes(I.ne, I.ns, I.M, I.nproj);
+      P.proj_sweep_lds = std::max(P.proj_sweep_lds, sw);
+      P.proj_measure_lds = std::max(P.proj_measure_lds, me);
+      if ((sw > kLdsLimit || me > kLdsLimit || refresh_proj_lds_bytes(I.ne, I.ns) > kLdsLimit) &&
+          P.bad_variant < 0)
+        P.bad_variant = k;
+    } else if (c.sweep_variant > 0) {   // forced variant
       if (variant_fits(P, k, c.sweep_variant - 1)) set_variant(P, k, c.sweep_variant - 1);
       else if (P.bad_variant < 0) P.bad_variant = k;
     } else if (c.sweep_threads == 0) {
@@ -316,7 +358,7 @@ Plan make_plan(const mvmc_config& c) {
       if (v >= 0) set_variant(P, k, v);
       else if (P.bad_variant < 0) P.bad_variant = k;
     }
-    I.refresh_lds = refresh_lds_bytes(I.ne, I.ns, true) <= kLdsLimit;
+    I.refresh_lds = I.nproj || refresh_lds_bytes(I.ne, I.ns, true) <= kLdsLimit;
     if (!I.refresh_lds) P.need_Y64 = true;
     I.walker_off = P.W;
     I.param_off = P.np;
@@ -352,7 +394,14 @@ Plan make_plan(const mvmc_config& c) {
     I.rbm_W_off = I.rbm_b_off + I.M;
     off_rbm += I.M ? n2 + I.M + I.M * n2 : 0;
     I.Y_off = off_Y;
-    off_Y += (int64_t)I.W * I.ne * I.ne;
+    I.Y_ld = std::max<int64_t>((int64_t)I.ne * I.ne, (int64_t)I.nproj * I.nup * I.nup);
+    off_Y += (int64_t)I.W * I.Y_ld;
+    I.proj_off = off_pmap;
+    off_pmap += 2 * (int64_t)I.nproj * I.ns;
+    I.projw_off = off_projw;
+    off_projw += I.nproj;
+    I.pterm_off = off_pterm;
+    off_pterm += (int64_t)I.W * 2 * I.nproj;
     I.pos_off = off_pos;
     off_pos += (int64_t)I.W * I.ne;
     I.empty_off = off_empty;
@@ -407,7 +456,7 @@ Plan make_plan(const mvmc_config& c) {
     P.W += I.W;
     P.np += I.np;
     P.eloc += I.rows;
-    P.Y_elems += (int64_t)I.W * I.ne * I.ne;
+    P.Y_elems += (int64_t)I.W * I.Y_ld;
     P.max_ne = std::max(P.max_ne, I.ne);
     P.max_ns = std::max(P.max_ns, I.ns);
     P.max_M = std::max(P.max_M, I.M);
@@ -432,7 +481,7 @@ Plan make_plan(const mvmc_config& c) {
   take(P.walker_inst, 4 * W);
   // [sweep lists or queue groups and items | refresh lists | all walkers |
   //  scratch | queue head]
-  take(P.lists, 4 * (5 * W + 2 * (size_t)kRegWpb * n) + 64);
+  take(P.lists, 4 * (6 * W + 2 * (size_t)kRegWpb * n) + 64);
   take(P.A64, 8 * (size_t)off_A);
   take(P.A32, 4 * (size_t)off_A);
   take(P.V, 8 * (size_t)off_V);
@@ -460,6 +509,9 @@ Plan make_plan(const mvmc_config& c) {
   take(P.empty, 4 * (size_t)off_empty);
   take(P.h, 8 * (size_t)off_h);
   take(P.theta, 8 * (size_t)off_theta);
+  take(P.pmap, 4 * (size_t)off_pmap);
+  take(P.projw, 8 * (size_t)off_projw);
+  take(P.pterm, 8 * (size_t)off_pterm);
   take(P.cnt, 8 * W);
   take(P.target, 8 * W);
   take(P.needs_refresh, 4 * W);
@@ -541,6 +593,7 @@ struct Bucket {
   bool lds = true;
   int reg = 0;       // register-sweep tier (n = number of walker groups) or 0
   bool ap = false;   // anti-parallel-block sweep kernel
+  bool proj = false; // projected sweep / refresh kernels
   int inst = -1;     // the one instance of the bucket (autotuning), else -1
 };
 
@@ -565,6 +618,8 @@ struct mvmc_ctx {
   int32_t* q_head = nullptr;
   int q_n = 0, q_ne_reg = 0, q_ne_ap = 0;
   size_t q_lds = 0;                 // largest LDS need of an item
+  int32_t* proj_list = nullptr;     // projected walkers (measurement launch)
+  int n_proj_walkers = 0;
   std::vector<uint64_t> cnt_host;   // per-instance proposal counter mirror
   TraceRec* trace = nullptr;
   int64_t trace_cap = 0;
@@ -656,6 +711,11 @@ void build_buckets(mvmc_ctx* c, bool per_instance = false) {
   for (int k = 0; k < n; ++k) {
     const InstDev& I = P.inst[k];
     const int own = per_instance ? k : -1;
+    if (I.nproj) {   // projected sweep and refresh (key 3 and 10)
+      sweep_groups[{3, 0, 256, own}].push_back(k);
+      refresh_groups[{10, 0, 256, own}].push_back(k);
+      continue;
+    }
     // instances within reach of the anti-parallel block refresh share
     // buckets of their own, so that one large instance does not send the
     // whole bucket to the workgroup-per-walker kernel
@@ -741,6 +801,7 @@ void build_buckets(mvmc_ctx* c, bool per_instance = false) {
       Bucket b;
       b.lds = std::get<0>(g.first) != 0;
       b.ap = &out == &c->sweep_b && std::get<0>(g.first) == 2;
+      b.proj = std::get<0>(g.first) == (&out == &c->sweep_b ? 3 : 10);
       b.nthreads = std::get<2>(g.first);
       b.inst = std::get<3>(g.first);
       b.list_off = lists.size() * 4;
@@ -762,6 +823,13 @@ void build_buckets(mvmc_ctx* c, bool per_instance = false) {
   };
   if (!(P.queue && !per_instance)) emit(sweep_groups, c->sweep_b);
   emit(refresh_groups, c->refresh_b);
+  // projected walkers, for their measurement launch
+  const size_t proj_off = lists.size();
+  for (int k = 0; k < n; ++k)
+    if (P.inst[k].nproj)
+      for (int w = 0; w < P.inst[k].W; ++w) lists.push_back((int32_t)(P.inst[k].walker_off + w));
+  c->n_proj_walkers = (int)(lists.size() - proj_off);
+  c->proj_list = reinterpret_cast<int32_t*>(c->ws + P.lists.off) + proj_off;
   // list pool: [sweep lists (padded) | refresh lists | all walkers | scratch]
   const size_t W = (size_t)P.W;
   std::vector<int32_t> all(W);
@@ -777,9 +845,13 @@ void build_buckets(mvmc_ctx* c, bool per_instance = false) {
 template <typename T>
 int refresh_all(mvmc_ctx* c, double sing_tol) {
   const int id = tic(c, 1);
-  for (auto& b : c->refresh_b)
-    launch_refresh<T>(c->P, reinterpret_cast<int32_t*>(c->ws + c->plan.lists.off + b.list_off),
-                      b.n, b.max_ne, b.max_ns, b.lds, sing_tol, c->stream);
+  for (auto& b : c->refresh_b) {
+    const int32_t* lst = reinterpret_cast<int32_t*>(c->ws + c->plan.lists.off + b.list_off);
+    if (b.proj)
+      launch_refresh_proj<T>(c->P, lst, b.n, b.max_ne, b.max_ns, sing_tol, nullptr, c->stream);
+    else
+      launch_refresh<T>(c->P, lst, b.n, b.max_ne, b.max_ns, b.lds, sing_tol, c->stream);
+  }
   toc(c, id);
   LAUNCHCHK(c);
   return MVMC_OK;
@@ -919,6 +991,7 @@ int mvmc_query_layout(const mvmc_config* cfg, int32_t k, mvmc_instance_layout* o
   out->empty_off = I.empty_off;
   out->n_elec = I.ne;
   out->n_sites = I.ns;
+  out->Y_ld = I.Y_ld;
   return MVMC_OK;
 }
 
@@ -989,6 +1062,9 @@ int init_impl(mvmc_ctx** out, const mvmc_config* cfg, void* d_ws, size_t ws_byte
   Q.minpiv = at<double>(b, P.minpiv);
   Q.status = at<int32_t>(b, P.status);
   Q.guard = at<int32_t>(b, P.guard);
+  Q.pmap = at<int32_t>(b, P.pmap);
+  Q.projw = at<double>(b, P.projw);
+  Q.pterm = at<double>(b, P.pterm);
   SrArgs& S = c->SA;
   S.inst = at<SrInst>(b, P.srinst_p);
   S.obar = at<double>(b, P.obar);
@@ -1008,12 +1084,22 @@ int init_impl(mvmc_ctx** out, const mvmc_config* cfg, void* d_ws, size_t ws_byte
 
   // static tables
   std::vector<int32_t> winst(P.W);
-  std::vector<int32_t> fidx, vidx, gidx, nptr, nsite, fmp, fm, gmp, gm, vmp, vm;
-  std::vector<double> U, nt;
+  std::vector<int32_t> fidx, vidx, gidx, nptr, nsite, fmp, fm, gmp, gm, vmp, vm, pmap;
+  std::vector<double> U, nt, projw;
   for (int k = 0; k < cfg->n_instances; ++k) {
     HostInst H = host_tables(c->desc[k]);
     const InstDev& I = P.inst[k];
     for (int w = 0; w < I.W; ++w) winst[I.walker_off + w] = k;
+    if (I.nproj) {   // maps q_p, then their inverses
+      const mvmc_instance_desc& d = c->desc[k];
+      const size_t base = pmap.size();
+      pmap.insert(pmap.end(), d.proj_map, d.proj_map + (size_t)I.nproj * I.ns);
+      pmap.resize(base + 2 * (size_t)I.nproj * I.ns);
+      for (int p = 0; p < I.nproj; ++p)
+        for (int i = 0; i < I.ns; ++i)
+          pmap[base + (size_t)(I.nproj + p) * I.ns + d.proj_map[(size_t)p * I.ns + i]] = i;
+      projw.insert(projw.end(), d.proj_weight, d.proj_weight + I.nproj);
+    }
     fidx.insert(fidx.end(), H.f_idx.begin(), H.f_idx.end());
     vidx.insert(vidx.end(), H.v_idx.begin(), H.v_idx.end());
     gidx.insert(gidx.end(), H.g_idx.begin(), H.g_idx.end());
@@ -1052,6 +1138,8 @@ int init_impl(mvmc_ctx** out, const mvmc_config* cfg, void* d_ws, size_t ws_byte
   chk(up(P.gm, gm.data(), 4 * gm.size()));
   chk(up(P.vm_ptr, vmp.data(), 4 * vmp.size()));
   chk(up(P.vm, vm.data(), 4 * vm.size()));
+  chk(up(P.pmap, pmap.data(), 4 * pmap.size()));
+  chk(up(P.projw, projw.data(), 8 * projw.size()));
   chk(hipMemset(Q.cnt, 0, 8 * P.W));
   chk(hipMemset(Q.accepted, 0, 8 * P.W));
   chk(hipMemset(Q.guard, 0, 4 * P.W));
@@ -1299,6 +1387,18 @@ int run_sweeps(mvmc_ctx* c, int32_t n_sweeps, std::vector<double>* inst_ms) {
         continue;
       }
       const int e = t0(b.inst);
+      if (b.proj) {
+        if (c->cfg.precision == MVMC_FP64)
+          launch_sweep_proj<double>(c->P, lst, b.n, (int)std::min<int64_t>(cap, INT32_MAX),
+                                    c->cfg.seed, P.proj_sweep_lds, c->trace, c->trace_cap, tb,
+                                    tgt, nr, R, c->stream);
+        else
+          launch_sweep_proj<float>(c->P, lst, b.n, (int)std::min<int64_t>(cap, INT32_MAX),
+                                   c->cfg.seed, P.proj_sweep_lds, c->trace, c->trace_cap, tb,
+                                   tgt, nr, R, c->stream);
+        t1(e);
+        continue;
+      }
       if (b.ap) {
         if (c->cfg.precision == MVMC_FP64)
           launch_sweep_ap<double>(c->P, lst, b.n, (int)std::min<int64_t>(cap, INT32_MAX),
@@ -1330,7 +1430,11 @@ int run_sweeps(mvmc_ctx* c, int32_t n_sweeps, std::vector<double>* inst_ms) {
         if (b.inst >= 0 && P.reg_class[b.inst]) continue;
         const int32_t* lst = reinterpret_cast<int32_t*>(c->ws + P.lists.off + b.list_off);
         const int e = t0(b.inst);
-        if (c->cfg.precision == MVMC_FP64)
+        if (b.proj && c->cfg.precision == MVMC_FP64)
+          launch_refresh_proj<double>(c->P, lst, b.n, b.max_ne, b.max_ns, 0.0, nr, c->stream);
+        else if (b.proj)
+          launch_refresh_proj<float>(c->P, lst, b.n, b.max_ne, b.max_ns, 0.0, nr, c->stream);
+        else if (c->cfg.precision == MVMC_FP64)
           launch_refresh_if<double>(c->P, lst, b.n, b.max_ne, b.max_ns, b.lds, nr, c->stream);
         else
           launch_refresh_if<float>(c->P, lst, b.n, b.max_ne, b.max_ns, b.lds, nr, c->stream);
@@ -1387,6 +1491,8 @@ int mvmc_autotune(mvmc_ctx* c, int32_t n_sweeps, const char* cache_path, double*
   const int n = c->cfg.n_instances, nv = MVMC_N_SWEEP_VARIANTS;
   std::vector<double> ms((size_t)n * nv, std::nan(""));
   std::vector<int> chosen(n, -1);
+  for (int k = 0; k < n; ++k)   // projected instances keep their own sweep
+    if (P.inst[k].nproj) chosen[k] = MVMC_N_SWEEP_VARIANTS;
   // cached choices: "mvmc-sweep precision ne ns M walkers variant" per line
   auto key = [&](int k) {
     const InstDev& I = P.inst[k];
@@ -1407,7 +1513,7 @@ int mvmc_autotune(mvmc_ctx* c, int32_t n_sweeps, const char* cache_path, double*
         for (int k = 0; k < n; ++k) {
           const InstDev& I = P.inst[k];
           if (prec == c->cfg.precision && ne == I.ne && ns == I.ns && M == I.M && W == I.W &&
-              variant_fits(P, k, v))
+              !I.nproj && variant_fits(P, k, v))
             chosen[k] = v;
         }
       }
@@ -1541,12 +1647,17 @@ int mvmc_measure_energy_and_O(mvmc_ctx* c, int32_t slot, double* d_eloc, void* d
     return set_err(c, fail(MVMC_E_ARG, "slot %d outside [0, %d)", slot, c->cfg.n_slots));
   const Plan& P = c->plan;
   const int id = tic(c, 2);
-  if (c->cfg.precision == MVMC_FP64)
+  if (c->cfg.precision == MVMC_FP64) {
     launch_measure<double>(c->P, c->d_all, (int)P.W, slot, d_eloc, (double*)d_O, P.max_ne,
                            P.max_ns, P.max_M, c->stream);
-  else
+    launch_measure_proj<double>(c->P, c->proj_list, c->n_proj_walkers, slot, d_eloc,
+                                (double*)d_O, P.proj_measure_lds, c->stream);
+  } else {
     launch_measure<float>(c->P, c->d_all, (int)P.W, slot, d_eloc, (float*)d_O, P.max_ne, P.max_ns,
                           P.max_M, c->stream);
+    launch_measure_proj<float>(c->P, c->proj_list, c->n_proj_walkers, slot, d_eloc, (float*)d_O,
+                               P.proj_measure_lds, c->stream);
+  }
   toc(c, id);
   LAUNCHCHK(c);
   return MVMC_OK;
@@ -1559,9 +1670,9 @@ int mvmc_measure_h2(mvmc_ctx* c, int32_t slot, double* d_f1, double* d_f2) {
   const Plan& P = c->plan;
   for (int k = 0; k < c->cfg.n_instances; ++k) {
     const InstDev& I = P.inst[k];
-    if (I.M)
+    if (I.M || I.nproj)
       return set_err(c, fail(MVMC_E_ARG, "instance %d: F(x, H^2) covers states without an RBM "
-                                         "factor", k));
+                                         "factor or a quantum-number projection", k));
     if (local_h2_lds_bytes(I.ne, I.ns) > kLdsLimit)
       return set_err(c, fail(MVMC_E_SHAPE, "instance %d: N_s = %d, N_e = %d exceed the LDS of "
                                            "the F(x, H^2) kernel", k, I.ns, I.ne));

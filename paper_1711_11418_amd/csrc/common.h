@@ -19,6 +19,7 @@ struct InstDev {
   int32_t nf, ng, nv, M;          // parameter counts; M = RBM hidden units
   int32_t W, np, ldO, deg_max;    // walkers, parameters, O row stride, max lattice degree
   int32_t sweep_lds, refresh_lds; // 1 = matrix resident in LDS for that kernel
+  int32_t nproj, pad0;            // quantum-number projection terms N_P (0 = none)
   int64_t walker_off;             // first global walker id
   int64_t param_off;              // offset into the concatenated parameter vector
   int64_t O_off, S_off, eloc_off; // caller buffers
@@ -31,7 +32,11 @@ struct InstDev {
   int64_t gm_ptr_off, gm_off;     // g-slot members: CSR of sites
   int64_t vm_ptr_off, vm_off;     // v-slot members: CSR of packed i*Ns+j, i<j
   int64_t rbm_a_off, rbm_b_off, rbm_W_off;   // RBM pools (a: 2Ns, b: M, W: M*2Ns)
-  int64_t Y_off;                  // walker-matrix pool: W * ne*ne
+  int64_t Y_off;                  // walker-matrix pool: W * Y_ld
+  int64_t Y_ld;                   // ne*ne, or max(ne*ne, nproj n^2) with a projection
+  int64_t proj_off;               // pmap pool: maps q_p [nproj][ns], then inverses [nproj][ns]
+  int64_t projw_off;              // projw pool: weights w_p [nproj]
+  int64_t pterm_off;              // pterm pool, per walker: log|det M_p| [nproj], sign [nproj]
   int64_t pos_off;                // W * ne
   int64_t empty_off;              // W * 2*Ns  ([w][sigma][Ns], first Ns-N_sigma used)
   int64_t h_off;                  // W * Ns   (Jastrow field, double)
@@ -82,6 +87,9 @@ struct Pools {
   // the walker waits for a double refresh before retrying that proposal;
   // 2 still not finite after the refresh: the walker stops
   int32_t* guard;
+  int32_t* pmap;                   // projection site maps and their inverses
+  double* projw;                   // projection weights
+  double* pterm;                   // per-term log|det M_p| and sign of projected walkers
 };
 
 enum : int32_t { kGuardClear = 0, kGuardPending = 1, kGuardFailed = 2 };

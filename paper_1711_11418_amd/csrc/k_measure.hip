@@ -79,6 +79,7 @@ __global__ __launch_bounds__(kMeasureThreads) void k_measure(Pools P,
   extern __shared__ __align__(16) unsigned char smem[];
   const int gw = wlist[blockIdx.x];
   const InstDev& I = P.inst[P.walker_inst[gw]];
+  if (I.nproj) return;   // projected walkers: k_measure_proj
   const int ne = I.ne, ns = I.ns, n2 = 2 * ns, M = I.M, nup = I.nup;
   const int64_t lw = gw - I.walker_off;
   const int tid = threadIdx.x;
@@ -215,6 +216,190 @@ __global__ __launch_bounds__(kMeasureThreads) void k_measure(Pools P,
   }
   for (int k = I.np + tid; k < I.ldO; k += blockDim.x) Orow[k] = T(0);
 }
+
+// Projected walkers (section 3.2.2, Eqs. momP and pointP): with
+// c_p = w_p Pf(X(q_p(x))) / sum_q w_q Pf(X(q_q(x))),
+//   hop ratio     R = sum_p c_p r_p times the correlator ratio, r_p from
+//                 M_p^-1 and the mapped pair amplitudes as in the sweep;
+//   f slot k      O = sum_p c_p sum over members (i, j) of M_p^-1[b][a] with
+//                 a the up electron on q_p^-1(i) and b the down electron on
+//                 q_p^-1(j) (Eq. DiffPf on each term);
+//   g, v, RBM     as without projection.
+// LDS: [red 16 | hs ns | ths M | c_p] doubles, then pos [N_e], eidx [2 N_s],
+// maps and inverse maps [2 N_P N_s].
+__host__ __device__ inline size_t measure_proj_lds(int ne, int ns, int M, int np) {
+  return mal16((16 + (size_t)ns + M + np) * sizeof(double)) +
+         (size_t)(ne + 2 * ns + 2 * (size_t)np * ns) * sizeof(int32_t);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kMeasureThreads) void k_measure_proj(
+    Pools P, const int32_t* __restrict__ wlist, int slot, double* __restrict__ eloc,
+    T* __restrict__ O) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int gw = wlist[blockIdx.x];
+  const InstDev& I = P.inst[P.walker_inst[gw]];
+  const int ne = I.ne, ns = I.ns, n2 = 2 * ns, M = I.M, n = I.nup, np = I.nproj;
+  const int64_t lw = gw - I.walker_off;
+  const int tid = threadIdx.x;
+
+  double* red = (double*)smem;                  // 16
+  double* hs = red + 16;                        // ns
+  double* ths = hs + ns;                        // M
+  double* cp = ths + M;                         // np
+  int32_t* pos_s = (int32_t*)(smem + mal16((16 + (size_t)ns + M + np) * sizeof(double)));
+  int32_t* eidx = pos_s + ne;                   // 2ns
+  int32_t* qm = eidx + n2;                      // [np][ns] maps, then [np][ns] inverses
+
+  const int32_t* posg = P.pos + I.pos_off + lw * ne;
+  const T* Yw = (const T*)P.Y + I.Y_off + lw * I.Y_ld;
+  const T* A = table_of<T>(P, I.A_off);
+  for (int v = tid; v < n2; v += blockDim.x) eidx[v] = -1;
+  for (int l = tid; l < ns; l += blockDim.x) hs[l] = P.h[I.h_off + lw * ns + l];
+  for (int hh = tid; hh < M; hh += blockDim.x) ths[hh] = P.theta[I.theta_off + lw * M + hh];
+  for (int e = tid; e < 2 * np * ns; e += blockDim.x) qm[e] = P.pmap[I.proj_off + e];
+  if (tid == 0) {
+    const double* lt = P.pterm + I.pterm_off + lw * 2 * np;
+    const double* w = P.projw + I.projw_off;
+    double lmax = -INFINITY;
+    for (int p = 0; p < np; ++p)
+      if (lt[np + p] != 0.0) lmax = fmax(lmax, lt[p]);
+    double tot = 0.0;
+    for (int p = 0; p < np; ++p) {
+      const double c = lt[np + p] != 0.0 ? w[p] * lt[np + p] * exp(lt[p] - lmax) : 0.0;
+      cp[p] = c;
+      tot += c;
+    }
+    for (int p = 0; p < np; ++p) cp[p] /= tot;
+  }
+  __syncthreads();
+  for (int b = tid; b < ne; b += blockDim.x) {
+    pos_s[b] = posg[b];
+    eidx[posg[b]] = b;
+  }
+  __syncthreads();
+
+  const double* V = P.V + I.V_off;
+  const double* G = P.G + I.site_off;
+  const double* Uv = P.U + I.site_off;
+  const int32_t* nptr = P.nbr_ptr + I.nptr_off;
+  const int32_t* nsite = P.nbr_site + I.nbr_off;
+  const double* nt = P.nbr_t + I.nbr_off;
+  const double* ra = P.rbm64 + I.rbm_a_off;
+  const double* rW = P.rbm64 + I.rbm_W_off;
+
+  double e = 0.0;
+  for (int i = tid; i < ns; i += blockDim.x)
+    if (eidx[i] >= 0 && eidx[i + ns] >= 0) e += Uv[i];
+  const int deg = I.deg_max;
+  for (int t = tid; t < ne * deg; t += blockDim.x) {
+    const int a = t / deg, qn = t - (t / deg) * deg;
+    const int Iold = pos_s[a];
+    const int sigma = Iold >= ns ? 1 : 0;
+    const int site_old = Iold - sigma * ns;
+    const int s0 = nptr[site_old] + qn;
+    if (s0 >= nptr[site_old + 1]) continue;
+    const int site_new = nsite[s0];
+    const int Inew = site_new + sigma * ns;
+    if (eidx[Inew] >= 0) continue;
+    const int ai = a - sigma * n;
+    double r_pf = 0.0;
+    for (int p = 0; p < np; ++p) {
+      const int32_t* qp = qm + p * ns;
+      const T* Mp = Yw + (int64_t)p * n * n;
+      double s = 0.0;
+      if (sigma == 0) {
+        const T* Arow = A + (int64_t)qp[site_new] * n2 + ns;
+        for (int b = 0; b < n; ++b)
+          s += (double)Arow[qp[pos_s[n + b] - ns]] * (double)Mp[b * n + ai];
+      } else {
+        const int col = ns + qp[site_new];
+        for (int i = 0; i < n; ++i)
+          s += (double)Mp[ai * n + i] * (double)A[(int64_t)qp[pos_s[i]] * n2 + col];
+      }
+      r_pf += cp[p] * s;
+    }
+    const int opp = (1 - sigma) * ns;
+    double logc = G[site_new] * (eidx[site_new + opp] >= 0 ? 1.0 : 0.0) -
+                  G[site_old] * (eidx[site_old + opp] >= 0 ? 1.0 : 0.0) + hs[site_new] -
+                  hs[site_old] - V[(int64_t)site_old * ns + site_new];
+    if (M) {
+      logc += 2.0 * (ra[Inew] - ra[Iold]);
+      for (int hh = 0; hh < M; ++hh) {
+        const double th = ths[hh];
+        const double d = 2.0 * (rW[(int64_t)hh * n2 + Inew] - rW[(int64_t)hh * n2 + Iold]);
+        logc += log2cosh(th + d) - log2cosh(th);
+      }
+    }
+    e += -nt[s0] * r_pf * exp(logc);
+  }
+  e = block_sum(e, red);
+  for (int hh = tid; hh < M; hh += blockDim.x) ths[hh] = tanh(ths[hh]);
+  __syncthreads();
+  const int64_t row = (int64_t)slot * I.W + lw;
+  if (tid == 0) eloc[I.eloc_off + row] = e;
+
+  T* Orow = O + I.O_off + row * I.ldO;
+  const int32_t* fptr = P.fm_ptr + I.fm_ptr_off;
+  slot_sums_any(I.nf, fptr[I.nf], fptr, P.fm + I.fm_off,
+                [&](int pk) -> double {
+                  const int i = pk / ns, j = pk % ns;
+                  double s = 0.0;
+                  for (int p = 0; p < np; ++p) {
+                    const int32_t* qi = qm + (np + p) * ns;
+                    const int ea = eidx[qi[i]], eb = eidx[qi[j] + ns];
+                    if (ea >= 0 && eb >= 0)
+                      s += cp[p] * (double)Yw[(int64_t)p * n * n + (eb - n) * n + ea];
+                  }
+                  return s;
+                },
+                Orow);
+  const int32_t* gptr = P.gm_ptr + I.gm_ptr_off;
+  slot_sums_any(I.ng, gptr[I.ng], gptr, P.gm + I.gm_off,
+                [&](int i) -> double { return (eidx[i] >= 0 && eidx[i + ns] >= 0) ? 1.0 : 0.0; },
+                Orow + I.nf);
+  const int32_t* vptr = P.vm_ptr + I.vm_ptr_off;
+  slot_sums_any(I.nv, vptr[I.nv], vptr, P.vm + I.vm_off,
+                [&](int pk) -> double {
+                  const int i = pk / ns, j = pk % ns;
+                  const int mi = (eidx[i] >= 0) + (eidx[i + ns] >= 0) - 1;
+                  const int mj = (eidx[j] >= 0) + (eidx[j + ns] >= 0) - 1;
+                  return (double)(mi * mj);
+                },
+                Orow + I.nf + I.ng);
+  if (M) {
+    T* Oa = Orow + I.nf + I.ng + I.nv;
+    T* Ob = Oa + n2;
+    T* OW = Ob + M;
+    for (int v = tid; v < n2; v += blockDim.x) Oa[v] = (T)(eidx[v] >= 0 ? 1.0 : -1.0);
+    for (int hh = tid; hh < M; hh += blockDim.x) Ob[hh] = (T)ths[hh];
+    for (int64_t idx = tid; idx < (int64_t)M * n2; idx += blockDim.x) {
+      const int hh = (int)(idx / n2), v = (int)(idx % n2);
+      OW[idx] = (T)(eidx[v] >= 0 ? ths[hh] : -ths[hh]);
+    }
+  }
+  for (int k = I.np + tid; k < I.ldO; k += blockDim.x) Orow[k] = T(0);
+}
+
+size_t measure_proj_lds_bytes(int ne, int ns, int M, int nproj) {
+  return measure_proj_lds(ne, ns, M, nproj);
+}
+
+template <typename T>
+void launch_measure_proj(const Pools& P, const int32_t* wlist, int n, int slot, double* eloc,
+                         T* O, size_t lds_bytes, hipStream_t s) {
+  if (n <= 0) return;
+  if (lds_bytes > 65536)
+    (void)hipFuncSetAttribute((const void*)&k_measure_proj<T>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+  hipLaunchKernelGGL((k_measure_proj<T>), dim3(n), dim3(kMeasureThreads), lds_bytes, s, P, wlist,
+                     slot, eloc, O);
+}
+
+template void launch_measure_proj<double>(const Pools&, const int32_t*, int, int, double*,
+                                          double*, size_t, hipStream_t);
+template void launch_measure_proj<float>(const Pools&, const int32_t*, int, int, double*, float*,
+                                         size_t, hipStream_t);
 
 template <typename T>
 void launch_measure(const Pools& P, const int32_t* wlist, int n, int slot, double* eloc, T* O,

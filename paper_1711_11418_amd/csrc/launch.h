@@ -90,10 +90,31 @@ int sweep_queue_nb(int max_ne_ap);
 // anti-parallel one (ne_ap > 0)
 size_t sweep_queue_lds_bytes(int ne_reg, int ne_ap, int ns, int M, size_t tsize);
 
-// k_measure.hip: local energy and O_k rows for sample slot `slot`.
+// k_proj.hip: quantum-number projection (section 3.2.2) on the anti-parallel
+// block.  Refresh: every term's M_p^-1, log|det M_p| and sign in double, the
+// walker's sum over terms, Jastrow field and RBM angles (with flags, only
+// flagged walkers, flags cleared).  Sweep: hopping proposals with every
+// M_p^-1 in LDS (lds_bytes: the largest sweep_proj_lds_bytes of the list).
+template <typename T>
+void launch_refresh_proj(const Pools& P, const int32_t* wlist, int n, int max_ne, int max_ns,
+                         double sing_tol, int32_t* flags, hipStream_t s);
+size_t refresh_proj_lds_bytes(int ne, int ns);
+template <typename T>
+void launch_sweep_proj(const Pools& P, const int32_t* wlist, int n, int cap, uint64_t seed,
+                       size_t lds_bytes, TraceRec* trace, int64_t trace_cap,
+                       const uint64_t* trace_base, const uint64_t* target, int32_t* needs_refresh,
+                       int R, hipStream_t s);
+size_t sweep_proj_lds_bytes(int ne, int ns, int M, int nproj, size_t tsize);
+
+// k_measure.hip: local energy and O_k rows for sample slot `slot` (projected
+// walkers are skipped: launch_measure_proj covers them).
 template <typename T>
 void launch_measure(const Pools& P, const int32_t* wlist, int n, int slot, double* eloc, T* O,
                     int max_ne, int max_ns, int max_M, hipStream_t s);
+template <typename T>
+void launch_measure_proj(const Pools& P, const int32_t* wlist, int n, int slot, double* eloc,
+                         T* O, size_t lds_bytes, hipStream_t s);
+size_t measure_proj_lds_bytes(int ne, int ns, int M, int nproj);
 
 // k_lanczos.hip: F(x, H) and F(x, H^2) of every listed walker into slot
 // `slot` of f1 / f2 (eloc layout); moments, alpha_1 and E_1 per instance

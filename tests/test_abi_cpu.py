@@ -113,3 +113,47 @@ def test_queue_schedule_shapes():
     with pytest.raises(b.MVMCError) as e:
         b.query_sizes(cfg)
     assert e.value.status == 2
+
+
+def _proj_case():
+    inst = workload("sq4_sub2_proj4", n_walkers=8)["instances"][0]
+    inst.proj_q = np.array(inst.proj_q, copy=True)
+    inst.proj_w = np.array(inst.proj_w, copy=True)
+    return inst
+
+
+def test_projection_layout():
+    """A projected instance keeps its N_P inverses M_p^-1 (n x n each) in its
+    walker matrix space: Y_ld = max(N_e^2, N_P n^2)."""
+    b = _lib()
+    from mvmc_inputs.instance import translation_projection
+    from mvmc_inputs.lattice import chain
+    inst = _proj_case()
+    cfg = b.make_config([inst], "fp64", 16, 1)
+    lay = b.query_layout(cfg, 0)
+    assert lay.Y_ld == 14 * 14 and b.query_sizes(cfg).Y_elems == 8 * 14 * 14
+    ring = workload("ring6_proj3", n_walkers=4)["instances"][0]
+    ring.proj_q, ring.proj_w = translation_projection(chain(6), [(r, 0) for r in range(6)])
+    cfg = b.make_config([ring, inst], "mixed", 16, 1)
+    assert b.query_layout(cfg, 0).Y_ld == 6 * 3 * 3 == 54 > 36
+    assert b.query_layout(cfg, 1).Y_off == 4 * 54
+
+
+@pytest.mark.parametrize("mutate,kw,code", [
+    (lambda i: i.proj_q.__setitem__((1, 0), i.proj_q[1, 1]), {}, 1),   # not a permutation
+    (lambda i: i.proj_q.__setitem__((0, 3), 16), {}, 1),                # site out of range
+    (lambda i: setattr(i, "proj_w", np.zeros(4)), {}, 1),                # every weight zero
+    (lambda i: i.proj_w.__setitem__(2, np.inf), {}, 6),
+    (lambda i: (setattr(i, "proj_q", np.tile(i.proj_q, (9, 1))),
+                setattr(i, "proj_w", np.ones(36))), {}, 1),            # N_P > MVMC_MAX_PROJ
+    (lambda i: None, dict(exchange_per64=16), 1),                       # hops only
+    (lambda i: None, dict(schedule="queue"), 1),                        # buckets only
+])
+def test_invalid_projections_are_rejected(mutate, kw, code):
+    b = _lib()
+    inst = _proj_case()
+    mutate(inst)
+    cfg = b.make_config([inst], "fp64", 16, 1, **kw)
+    with pytest.raises(b.MVMCError) as e:
+        b.query_sizes(cfg)
+    assert e.value.status == code

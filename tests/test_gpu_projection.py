@@ -1,0 +1,343 @@
+"""Quantum-number projection on the GPU (section 3.2.2, Eqs. momP and pointP)
+against the oracle.
+
+psi(x) = P_G P_J [RBM] sum_p w_p Pf(X(q_p(x))).  The GPU keeps every term's
+M_p^-1 and updates each by Sherman-Morrison; the oracle recomputes every
+Pfaffian from scratch.  Cases: momentum K = 0 and K = pi on the 4-site ring
+(all translations), three translations of the 6-site ring, the four
+translations of the 2x2 cell on 4x4 (N_e = 14), eight translations with an
+RBM factor (a wavefront carries two terms), and 12x12 with 66 electrons per
+spin (a term's block exceeds one wavefront's 64 lanes).
+"""
+import numpy as np
+import pytest
+
+from mvmc_inputs import random_configs, workload
+from mvmc_inputs.instance import (f_map_full, f_map_sublattice, make_instance,
+                                  translation_projection, v_map_nn)
+from mvmc_inputs.lattice import chain, square
+from oracle import sr as osr
+from oracle import wavefunction as wf
+
+from gpu_common import compare_trace, good_configs, log, oracle_measure, oracle_trajectories
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+SEED = 0x9A0F1711
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    from paper_1711_11418_amd import binding
+    binding.load()
+
+
+def _case(name):
+    if name == "ring8_proj8_rbm":
+        lat = chain(8)
+        inst = make_instance(name, lat, 4, 4, 4.0, f_map_full(lat), v_map_nn(lat), f_noise=0.05,
+                             n_hidden=8, rbm_sigma=0.05, n_walkers=4, seed=11)
+        inst.proj_q, inst.proj_w = translation_projection(lat, [(r, 0) for r in range(8)])
+        return inst
+    if name == "sq12_proj2":
+        lat = square(12)
+        inst = make_instance(name, lat, 66, 66, 4.0, f_map_sublattice(lat, 2, 2), v_map_nn(lat),
+                             f_noise=0.05, n_walkers=2, seed=12)
+        inst.proj_q, inst.proj_w = translation_projection(lat, [(0, 0), (1, 0)])
+        return inst
+    inst = workload(name)["instances"][0]
+    inst.n_walkers = 6
+    return inst
+
+
+def _terms(m, A, pos):
+    """Per-term (sign, log|det|-based Pfaffian, X_p) of the oracle."""
+    from oracle.pfaffian import pfaffian_log
+    out = []
+    for p in range(len(m.proj_q)):
+        y = wf.mapped(m, pos, p)
+        X = A[np.ix_(y, y)]
+        s, l = pfaffian_log(X)
+        out.append((s, l, X))
+    return out
+
+
+def good_proj_configs(inst, n, seed, cond_max=1e5):
+    """n configurations whose every mapped X_p has condition below cond_max."""
+    m = wf.expand(inst, inst.params0)
+    A = wf.skew_table(m)
+    out, s = [], seed
+    while len(out) < n:
+        for pos in random_configs(inst, 32, s):
+            if all(np.linalg.cond(X) < cond_max for _, _, X in _terms(m, A, pos)):
+                out.append(pos)
+                if len(out) == n:
+                    break
+        s += 1
+        if s > seed + 200:
+            raise RuntimeError("no well-conditioned configurations")
+    return np.array(out, dtype=np.int32)
+
+
+CASES = ["ring4_proj", "ring4_projpi", "ring6_proj3", "sq4_sub2_proj4", "ring8_proj8_rbm",
+         "sq12_proj2"]
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_refresh_terms_match_oracle(name):
+    """Every M_p^-1 against the inverse of the oracle's mapped X_p, and
+    log|sum_p w_p Pf_p| and its sign against the oracle's terms."""
+    from paper_1711_11418_amd import MVMC
+    inst = _case(name)
+    n_p, n = len(inst.proj_w), inst.n_up
+    pos0 = good_proj_configs(inst, inst.n_walkers, 3)
+    log(f"[proj refresh] {name}: Ns={inst.n_sites} Ne={inst.n_elec} N_P={n_p} "
+        f"W={inst.n_walkers}")
+    ctx = MVMC([inst], inst.params0)
+    assert ctx.sweep_variants() == ["proj"]
+    ctx.set_state(pos0.ravel(), np.zeros(inst.n_walkers, dtype=np.int64))
+    Mi = ctx.proj_inverses_of(ctx.get_inverse(), 0, n_p).cpu().numpy()
+    la, sg = (t.cpu().numpy() for t in ctx.get_pfaffian())
+    m = wf.expand(inst, inst.params0)
+    A = wf.skew_table(m)
+    for w in range(inst.n_walkers):
+        terms = _terms(m, A, pos0[w])
+        for p, (_, _, X) in enumerate(terms):
+            Yr = np.linalg.inv(X)[n:, :n]    # M_p^-1[b][a] = X_p^-1[n + b][a]
+            assert np.max(np.abs(Mi[w, p] - Yr)) <= 1e-10 * np.max(np.abs(Yr)), (w, p)
+        lmax = max(l for s, l, _ in terms if s != 0)
+        tot = sum(wp * s * np.exp(l - lmax) for wp, (s, l, _) in zip(inst.proj_w, terms))
+        assert sg[w] == np.sign(tot)
+        assert la[w] == pytest.approx(lmax + np.log(abs(tot)), abs=1e-10 * max(1.0, abs(lmax)))
+    ctx.close()
+
+
+@pytest.mark.parametrize("name,sweeps,refresh", [
+    ("ring4_proj", 30, 0), ("ring4_projpi", 30, 7), ("ring6_proj3", 20, 0),
+    ("sq4_sub2_proj4", 6, 16), ("ring8_proj8_rbm", 10, 5), ("sq12_proj2", 1, 40),
+])
+def test_trajectory_replay_fp64(name, sweeps, refresh):
+    """Every proposal's ratio and decision against the oracle chain (ratios
+    to 1e-10 relative, floor 1e-6), final configurations, the updated
+    inverses against the oracle's inverses of the final mapped X_p (1e-9),
+    then E_loc and every O_k at the final configurations (1e-10 / 1e-9)."""
+    from paper_1711_11418_amd import MVMC
+    inst = _case(name)
+    n_p, n = len(inst.proj_w), inst.n_up
+    pos0 = good_proj_configs(inst, inst.n_walkers, 7)
+    n_prop = sweeps * inst.n_elec
+    log(f"[proj replay] {name}: Ne={inst.n_elec} N_P={n_p} W={inst.n_walkers} "
+        f"proposals={n_prop} refresh_every={refresh} seed={SEED}")
+    ctx = MVMC([inst], inst.params0, seed=SEED, refresh_every=refresh)
+    ctx.set_state(pos0.ravel(), np.zeros(inst.n_walkers, dtype=np.int64))
+    ctx.enable_trace(n_prop)
+    acc = ctx.sample(sweeps)
+    rec = ctx.trace_records()
+    walkers, m = oracle_trajectories(inst, inst.params0, pos0, 0, n_prop, SEED)
+    st = compare_trace(rec, walkers, n_prop, SEED, rtol=1e-10)
+    log(f"  compared {st['compared']} ratios, worst rel err {st['worst_rel']:.2e}, "
+        f"accepted {acc}")
+    assert acc[0] == sum(int(t[4]) for wk in walkers for t in wk.trace)
+    pos, cnt = ctx.get_state()
+    pos = ctx.pos_of(pos, 0).cpu().numpy()
+    assert np.array_equal(pos, np.array([wk.pos for wk in walkers]))
+    Mi = ctx.proj_inverses_of(ctx.get_inverse(), 0, n_p).cpu().numpy()
+    la, sg = (t.cpu().numpy() for t in ctx.get_pfaffian())
+    A = wf.skew_table(m)
+    for w in range(inst.n_walkers):
+        terms = _terms(m, A, pos[w])
+        for p, (_, _, X) in enumerate(terms):
+            Yr = np.linalg.inv(X)[n:, :n]
+            assert np.max(np.abs(Mi[w, p] - Yr)) <= 1e-9 * np.max(np.abs(Yr)), (w, p)
+        lmax = max(l for s, l, _ in terms if s != 0)
+        tot = sum(wp * s * np.exp(l - lmax) for wp, (s, l, _) in zip(inst.proj_w, terms))
+        assert sg[w] == np.sign(tot)
+        assert la[w] == pytest.approx(lmax + np.log(abs(tot)), abs=1e-9 * max(1.0, abs(lmax)))
+    ctx.measure(0)
+    el = ctx.eloc_of(0, 1).cpu().numpy()
+    O = ctx.O_of(0, 1).cpu().numpy()
+    for w in range(inst.n_walkers):
+        e_ref, o_ref = oracle_measure(inst, m, pos[w])
+        assert el[w] == pytest.approx(e_ref, rel=1e-10, abs=1e-10)
+        assert np.allclose(O[w], o_ref, rtol=1e-9, atol=1e-10)
+    ctx.close()
+
+
+def test_ragged_context_with_projected_and_plain_instances():
+    """A plain register-tier instance, a plain anti-parallel-block instance
+    and two projected ones in one context: each replays its oracle chain,
+    the measurement covers both kinds of walker, the autotuner leaves the
+    projected instances on their sweep."""
+    from paper_1711_11418_amd import MVMC
+    plain = workload("ring6")["instances"][0]
+    plain.n_walkers = 4
+    big = workload("sq4_sub2")["instances"][0]
+    big.n_walkers = 3
+    pa, pb = _case("ring6_proj3"), _case("sq4_sub2_proj4")
+    pa.n_walkers, pb.n_walkers = 3, 2
+    insts = [pa, plain, pb, big]
+    params = np.concatenate([i.params0 for i in insts])
+    pos0 = [good_proj_configs(i, i.n_walkers, 5) if getattr(i, "proj_q", None) is not None
+            else good_configs(i, i.params0, i.n_walkers, 5) for i in insts]
+    sweeps = 6
+    log("[proj ragged] " + ", ".join(f"Ne={i.n_elec}xW={i.n_walkers}" for i in insts))
+    ctx = MVMC(insts, params, seed=SEED, refresh_every=9, sweep_variant=None)
+    ctx.set_state(np.concatenate([p.ravel() for p in pos0]),
+                  np.zeros(sum(i.n_walkers for i in insts), dtype=np.int64))
+    v = ctx.sweep_variants()
+    assert v[0] == "proj" and v[2] == "proj" and v[1] != "proj" and v[3] != "proj"
+    per = max(i.n_elec for i in insts) * sweeps
+    ctx.enable_trace(per)
+    acc = ctx.sample(sweeps)
+    rec = ctx.trace_records()
+    pos_all, _ = ctx.get_state()
+    ctx.measure(0)
+    for k, inst in enumerate(insts):
+        lay = ctx.layouts[k]
+        n_prop = sweeps * inst.n_elec
+        walkers, m = oracle_trajectories(inst, inst.params0, pos0[k], int(lay.walker_off),
+                                         n_prop, SEED)
+        r = rec[lay.walker_off:lay.walker_off + inst.n_walkers]
+        st = compare_trace(r, walkers, n_prop, SEED, rtol=1e-10)
+        assert acc[k] == sum(int(t[4]) for wk in walkers for t in wk.trace)
+        pos = ctx.pos_of(pos_all, k).cpu().numpy()
+        assert np.array_equal(pos, np.array([wk.pos for wk in walkers]))
+        el = ctx.eloc_of(k, 1).cpu().numpy()
+        O = ctx.O_of(k, 1).cpu().numpy()
+        for w in range(inst.n_walkers):
+            e_ref, o_ref = oracle_measure(inst, m, pos[w])
+            assert el[w] == pytest.approx(e_ref, rel=1e-10, abs=1e-10), (k, w)
+            assert np.allclose(O[w], o_ref, rtol=1e-9, atol=1e-10), (k, w)
+        log(f"  instance {k}: {st['compared']} ratios, worst {st['worst_rel']:.2e}")
+    ms = ctx.autotune(1)
+    assert np.all(np.isnan(ms[0])) and np.all(np.isnan(ms[2]))
+    assert ctx.sweep_variants()[0] == "proj" and ctx.sweep_variants()[2] == "proj"
+    ctx.sample(2)
+    ctx.close()
+
+
+def test_sr_step_on_projected_samples():
+    """S, g and the Cholesky SR step from projected O rows against the oracle
+    on the same samples (sq4_sub2_proj4, 64 walkers x 4 slots)."""
+    from paper_1711_11418_amd import MVMC
+    inst = _case("sq4_sub2_proj4")
+    inst.n_walkers = 64
+    slots = 4
+    log(f"[proj sr] W={inst.n_walkers} slots={slots}")
+    ctx = MVMC([inst], inst.params0, seed=SEED, n_slots=slots, solver="chol", build_s=True,
+               refresh_every=28)
+    ctx.sample(4)
+    for s in range(slots):
+        ctx.sample(1)
+        ctx.measure(s)
+    O = ctx.O_of(0, slots).cpu().numpy().copy()
+    E = ctx.eloc_of(0, slots).cpu().numpy().copy()
+    # spot-check the rows against the oracle at the last slot's configurations
+    pos, _ = ctx.get_state()
+    pos = ctx.pos_of(pos, 0).cpu().numpy()
+    m = wf.expand(inst, inst.params0)
+    for w in range(0, inst.n_walkers, 16):
+        e_ref, o_ref = oracle_measure(inst, m, pos[w])
+        row = (slots - 1) * inst.n_walkers + w
+        assert E[row] == pytest.approx(e_ref, rel=1e-10, abs=1e-10)
+        assert np.allclose(O[row], o_ref, rtol=1e-9, atol=1e-10)
+    Eb, Ee, Ev = ctx.build_sr(slots)
+    ref = osr.sr_stats(O, E)
+    assert Eb[0] == pytest.approx(ref["E"], rel=1e-13)
+    S = ctx.S_of(0).cpu().numpy()
+    assert np.max(np.abs(S - ref["S"])) <= 1e-12 * np.max(np.abs(ref["S"]))
+    ctx.sr_update(dtau=0.05, eps_rel=1e-3, eps_abs=1e-6, solver="chol")
+    want = osr.sr_update(O, E, 0.05, 1e-3, 1e-6, solver="chol")
+    d = ctx.dparams.cpu().numpy()
+    assert np.allclose(d, want["dalpha"], rtol=1e-8, atol=1e-11 * np.max(np.abs(want["dalpha"])))
+    # the walkers were recomputed for the new parameters
+    la, _ = (t.cpu().numpy() for t in ctx.get_pfaffian())
+    m1 = wf.expand(inst, ctx.params.cpu().numpy())
+    A1 = wf.skew_table(m1)
+    terms = _terms(m1, A1, pos[0])
+    lmax = max(l for s, l, _ in terms if s != 0)
+    tot = sum(wp * s * np.exp(l - lmax) for wp, (s, l, _) in zip(inst.proj_w, terms))
+    assert la[0] == pytest.approx(lmax + np.log(abs(tot)), abs=1e-9 * max(1.0, abs(lmax)))
+    ctx.close()
+
+
+def _ratio_scale(m, A, pos, new, w):
+    """|corr ratio| sum_p |c_p r_p| / |sum_p c_p| of the exact terms: the size
+    of the products whose sum is the projected ratio.  Each r_p carries a
+    rounding error relative to |r_p|, so where the sum over terms cancels
+    the error of R is relative to this scale, not to |R|."""
+    t0, t1 = _terms(m, A, pos), _terms(m, A, new)
+    lmax = max(l for s, l, _ in t0 if s != 0)
+    c = [wp * s * np.exp(l - lmax) if s != 0 else 0.0 for wp, (s, l, _) in zip(w, t0)]
+    r = [s1 * s0 * np.exp(l1 - l0) if s0 != 0 else 0.0
+         for (s0, l0, _), (s1, l1, _) in zip(t0, t1)]
+    corr = np.exp(wf.log_correlators(m, new) - wf.log_correlators(m, pos))
+    return float(corr * sum(abs(ci * ri) for ci, ri in zip(c, r)) / abs(sum(c)))
+
+
+@pytest.mark.parametrize("name", ["sq4_sub2_proj4", "ring8_proj8_rbm"])
+def test_mixed_precision_ratios(name):
+    """Single-precision sweep (M_p^-1, the pair amplitudes and the RBM angles
+    in binary32; the term weights and the sum over terms in double) against
+    the double oracle, proposal by proposal, from well-conditioned starts
+    (every cond(X_p) < 1e3) with a double refresh every 16 proposals.  Each
+    term's ratio r_p carries the binary32 rounding of M_p^-1 (a few units of
+    2^-24 times cond(X_p) per update, at most 16 updates) and of its n-term
+    product, relative to |r_p|; the projected ratio sums c_p r_p, so its
+    error is bounded relative to S = |corr| sum_p |c_p r_p| / |sum_p c_p|
+    (_ratio_scale), not to |R|.  Bar: |R_gpu - R| <= 1e-3 max(S, 1e-2).
+    Decisions may differ only where u is within that bar of R^2; the
+    comparison of a walker stops at its first difference, and at least a
+    quarter of all proposals must be compared."""
+    from paper_1711_11418_amd import MVMC
+    inst = _case(name)
+    pos0 = good_proj_configs(inst, inst.n_walkers, 21, cond_max=1e3)
+    sweeps = 6 if inst.n_elec > 8 else 12
+    n_prop = sweeps * inst.n_elec
+    log(f"[proj mixed] {name}: Ne={inst.n_elec} W={inst.n_walkers} proposals={n_prop}")
+    ctx = MVMC([inst], inst.params0, precision="mixed", seed=SEED, refresh_every=16)
+    ctx.set_state(pos0.ravel(), np.zeros(inst.n_walkers, dtype=np.int64))
+    ctx.enable_trace(n_prop)
+    ctx.sample(sweeps)
+    rec = ctx.trace_records()
+    walkers, m = oracle_trajectories(inst, inst.params0, pos0, 0, n_prop, SEED)
+    A = wf.skew_table(m)
+    compared, worst_rel, worst_scaled = 0, 0.0, 0.0
+    for w, wk in enumerate(walkers):
+        pos = np.array(pos0[w], dtype=np.int64)
+        for k in range(n_prop):
+            n_, a, inew, R, accd, _ = wk.trace[k]
+            g = rec[w, k]
+            assert int(g["a"]) == a and int(g["i_new"]) == inew, (w, k)
+            if inew < 0:
+                continue
+            new = pos.copy()
+            new[a] = inew
+            S = _ratio_scale(m, A, pos, new, inst.proj_w)
+            err = abs(float(g["ratio"]) - R)
+            worst_rel = max(worst_rel, err / max(abs(R), 1e-2))
+            worst_scaled = max(worst_scaled, err / max(S, 1e-2))
+            assert err <= 1e-3 * max(S, 1e-2), (w, k, float(g["ratio"]), R, S)
+            compared += 1
+            if bool(g["accepted"]) != bool(accd):
+                break
+            if accd:
+                pos = new
+    log(f"  compared {compared} ratios, worst error {worst_scaled:.2e} of the term scale "
+        f"({worst_rel:.2e} of max(|R|, 1e-2))")
+    assert compared >= 0.25 * inst.n_walkers * n_prop
+    ctx.close()
+
+
+def test_lanczos_refuses_projected_instances():
+    from paper_1711_11418_amd import MVMC
+    from paper_1711_11418_amd.binding import MVMCError
+    inst = _case("ring4_proj")
+    ctx = MVMC([inst], inst.params0, seed=SEED, build_s=False, solver="cg")
+    with pytest.raises(MVMCError) as e:
+        ctx.measure_h2(0)
+    assert e.value.status == 1 and "projection" in str(e.value)
+    ctx.close()
