@@ -484,6 +484,152 @@ def lanczos_leg(sr_steps=30, slots=20):
             "products_tflops": gemm_flops * inst.n_walkers / (per_call * 1e-3) / 1e12}
 
 
+def uhf_start(inst, m0=0.3, mix=0.5, iters=2000, noise=0.02, seed=17):
+    """Initial parameters from the unrestricted Hartree-Fock solution, as the
+    paper starts its Hubbard optimisations (section 4.1.1): per spin
+    H_s = T + U <n_{i,-s}> n_{i,s} iterated to self-consistency from a Neel
+    seed on the bipartite lattice, the lowest N_s orbitals Phi_s of each
+    spin, and f_ij = sum_n Phi_{i n up} Phi_{j n dn} (Eq. fijSL), averaged
+    over the members of each f slot and scaled to max |f| = 1, plus
+    Gaussian noise of `noise` (seeded): the exact mean-field amplitude is so
+    symmetric that translated copies of it vanish identically on some
+    configurations, and the projected sweep needs every term invertible.
+    Gutzwiller and Jastrow parameters start at zero."""
+    import numpy as np
+    ns = inst.n_sites
+    T = np.zeros((ns, ns))
+    nb = [[] for _ in range(ns)]
+    for (i, j), t in zip(np.asarray(inst.bonds), inst.bond_t):
+        T[i, j] = T[j, i] = -t
+        nb[i].append(j)
+        nb[j].append(i)
+    color = -np.ones(ns, dtype=int)
+    color[0] = 0
+    todo = [0]
+    while todo:
+        i = todo.pop()
+        for j in nb[i]:
+            if color[j] < 0:
+                color[j] = 1 - color[i]
+                todo.append(j)
+    U = np.asarray(inst.U, dtype=float)
+    stag = 1.0 - 2.0 * color
+    nu = inst.n_up / ns + m0 * stag
+    nd = inst.n_dn / ns - m0 * stag
+    for _ in range(iters):
+        _, vu = np.linalg.eigh(T + np.diag(U * nd))
+        _, vd = np.linalg.eigh(T + np.diag(U * nu))
+        pu, pd = vu[:, :inst.n_up], vd[:, :inst.n_dn]
+        nu1, nd1 = (pu ** 2).sum(1), (pd ** 2).sum(1)
+        done = max(np.abs(nu1 - nu).max(), np.abs(nd1 - nd).max()) < 1e-12
+        nu, nd = mix * nu1 + (1 - mix) * nu, mix * nd1 + (1 - mix) * nd
+        if done:
+            break
+    f = pu @ pd.T
+    fidx = np.asarray(inst.f_idx)
+    fv = np.zeros(inst.n_f)
+    cnt = np.zeros(inst.n_f)
+    for i in range(ns):
+        for j in range(ns):
+            if fidx[i, j] >= 0:
+                fv[fidx[i, j]] += f[i, j]
+                cnt[fidx[i, j]] += 1
+    fv /= np.maximum(cnt, 1)
+    fv /= np.abs(fv).max()
+    fv += noise * np.random.default_rng(seed).standard_normal(inst.n_f)
+    p = np.zeros(inst.n_params)
+    p[:inst.n_f] = fv
+    return p
+
+
+def projection_leg(sr_steps=1500, slots=4):
+    """4x4 Hubbard, U = 4, t = 1, half filling (section 4.1.1, Table 3): a
+    2x2-sublattice pair amplitude (64 slots), one Gutzwiller and 5 Jastrow
+    distance classes (N_p = 70), 1024 walkers, FP64.  From the UHF start
+    (uhf_start) the plain state is trained by sr_steps SR steps (`slots`
+    samples per walker one sweep apart, Cholesky); from those parameters two
+    runs of sr_steps more steps follow with the same sampler seed: with the
+    momentum projection over the four translations of the 2x2 cell at K = 0
+    (with the sublattice structure, the full K = 0 projection of section
+    3.2.2) and without it.  Energies from 32 samples per walker, 2 sweeps
+    apart; also the UHF start with and without the projection.  The paper's
+    row for this state also carries the total-spin projection, which is not
+    built here: its numbers are context, not a target.  Timed: the sweep
+    kernels (HIP events) over the last 20 steps of each run."""
+    import copy
+
+    import numpy as np
+
+    from mvmc_inputs import workload
+    from paper_1711_11418_amd import MVMC
+    wl = workload("sq4_u4_proj4")
+    proj = wl["instances"][0]
+    plain = copy.deepcopy(proj)
+    plain.proj_q, plain.proj_w = None, None
+    ns = proj.n_sites
+
+    def train(inst, p0, tag, seed_off):
+        ctx = MVMC([inst], p0, seed=wl["sampler_seed"] + seed_off, n_slots=slots,
+                   solver="chol", build_s=True, refresh_every=wl["refresh_every"])
+        ctx.sample(wl["warmup"])
+        hist = []
+        timed = min(20, sr_steps)
+        t0 = time.perf_counter()
+        for it in range(sr_steps):
+            if it == sr_steps - timed:
+                ctx.timing(True)
+            for s in range(slots):
+                ctx.sample_async(1)
+                ctx.measure(s)
+            E, Ee, _ = ctx.build_sr(slots)
+            ctx.sr_update(dtau=wl["dtau"], eps_rel=wl["eps_rel"], eps_abs=wl["eps_abs"])
+            hist.append(float(E[0]) / ns)
+            if it % 250 == 0 or it == sr_steps - 1:
+                log(f"[projection] {tag} step {it}: E/N = {hist[-1]:.5f} "
+                    f"+- {float(Ee[0]) / ns:.5f}")
+        train_s = time.perf_counter() - t0
+        ms, _ = ctx.timing(False)
+        p = ctx.params.cpu().numpy().copy()
+        ctx.close()
+        props = timed * slots * inst.n_elec * inst.n_walkers
+        return p, {"sr_steps": sr_steps, "train_seconds": train_s,
+                   "history_per_site_every_50": hist[::50],
+                   "sweep_hop_updates_per_s": props / (ms[0] * 1e-3),
+                   "ms_per_sr_step": train_s * 1e3 / sr_steps}
+
+    def evaluate(inst, params):
+        ev_slots = 32
+        ev = MVMC([inst], params, seed=wl["sampler_seed"] + 99, n_slots=ev_slots, solver="cg",
+                  build_s=False, refresh_every=wl["refresh_every"])
+        ev.sample(wl["warmup"])
+        for s in range(ev_slots):
+            ev.sample_async(2)
+            ev.measure(s)
+        E, Ee, _ = ev.build_sr(ev_slots, with_S=False)
+        ev.close()
+        return {"energy_per_site": float(E[0]) / ns, "sigma_per_site": float(Ee[0]) / ns,
+                "samples": ev_slots * inst.n_walkers}
+
+    out = {"workload": "sq4_u4_proj4: 4x4 Hubbard U=4 half filling, 2x2-sublattice f, "
+                       "N_p=%d, %d walkers, FP64" % (proj.n_params, proj.n_walkers),
+           "n_proj": len(proj.proj_w)}
+    p0 = uhf_start(plain)
+    out["uhf_start"] = {"plain": evaluate(plain, p0), "projected": evaluate(proj, p0)}
+    p1, out["pretrain_plain"] = train(plain, p0, "plain (first)", 0)
+    p_pl, out["plain"] = train(plain, p1, "plain", 1)
+    out["plain"].update(evaluate(plain, p_pl))
+    p_pr, out["projected"] = train(proj, p1, "projected", 1)
+    out["projected"].update(evaluate(proj, p_pr))
+    d = out["plain"]["energy_per_site"] - out["projected"]["energy_per_site"]
+    out["gain_per_site"] = d
+    out["gain_over_sigma"] = d / float(np.hypot(out["plain"]["sigma_per_site"],
+                                                out["projected"]["sigma_per_site"]))
+    out["context_table3"] = {"ED": -0.85136, "mVMC_2x2_momentum_and_spin_projection": -0.84985,
+                             "mVMC_2x2_sigma": 0.00003}
+    out["relative_error_vs_ED"] = abs(out["projected"]["energy_per_site"] + 0.85136) / 0.85136
+    return out
+
+
 def rbm_leg(steps):
     """16x16 Hubbard, U = 8, N_e = 224 (1/8 hole doping), 2x2-sublattice f
     times an RBM factor of 512 hidden units over the 512 spin-resolved
@@ -754,6 +900,8 @@ def main():
                     help="print only the first-step power-Lanczos leg")
     ap.add_argument("--batch-only", action="store_true",
                     help="print only the ragged-batch leg (queue and bucket schedules)")
+    ap.add_argument("--projection-only", action="store_true",
+                    help="train the 4x4 U=4 state with and without the momentum projection")
     ap.add_argument("--rbm-gain", action="store_true",
                     help="train 16x16 PJ and PJ x RBM by SR and print their energies")
     ap.add_argument("--sr-steps", type=int, default=40)
@@ -774,6 +922,9 @@ def main():
         return
     if a.lanczos_only:
         print(json.dumps({"lanczos_sq8": lanczos_leg()}), flush=True)
+        return
+    if a.projection_only:
+        print(json.dumps({"projection_sq4": projection_leg()}), flush=True)
         return
     if a.batch_only:
         print(json.dumps({"batch32_ragged": batch_leg(max(1, a.steps - 1))}), flush=True)
@@ -839,6 +990,11 @@ def main():
         out["lanczos_sq8"] = lanczos_leg()
         log(f"[bench]   E/N {out['lanczos_sq8']['E_per_site']:.5f}, E_1/N "
             f"{out['lanczos_sq8']['E1_per_site']:.5f}, alpha_1 {out['lanczos_sq8']['alpha_1']:.4f}")
+        log("[bench] 4x4 U=4 with and without the momentum projection (trained by SR)")
+        out["projection_sq4"] = projection_leg()
+        log(f"[bench]   projected {out['projection_sq4']['projected']['energy_per_site']:.5f}, "
+            f"plain {out['projection_sq4']['plain']['energy_per_site']:.5f} per site, gain "
+            f"{out['projection_sq4']['gain_over_sigma']:.1f} sigma")
         log("[bench] 16x16 RBM leg (8192 walkers, CG)")
         out["sq16_u8_rbm"] = rbm_leg(1)
         log(f"[bench]   16x16 {out['sq16_u8_rbm']['value']:.3e} hop-updates/s, "

@@ -305,6 +305,7 @@ __global__ __launch_bounds__(kMeasureThreads) void k_measure_proj(
     const int ai = a - sigma * n;
     double r_pf = 0.0;
     for (int p = 0; p < np; ++p) {
+      if (cp[p] == 0.0) continue;
       const int32_t* qp = qm + p * ns;
       const T* Mp = Yw + (int64_t)p * n * n;
       double s = 0.0;
@@ -346,6 +347,7 @@ __global__ __launch_bounds__(kMeasureThreads) void k_measure_proj(
                   const int i = pk / ns, j = pk % ns;
                   double s = 0.0;
                   for (int p = 0; p < np; ++p) {
+                    if (cp[p] == 0.0) continue;
                     const int32_t* qi = qm + (np + p) * ns;
                     const int ea = eidx[qi[i]], eb = eidx[qi[j] + ns];
                     if (ea >= 0 && eb >= 0)

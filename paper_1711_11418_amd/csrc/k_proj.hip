@@ -434,7 +434,8 @@ __global__ __launch_bounds__(kProjThreads) void k_sweep_proj(
       double num = 0.0, den = 0.0;
       bool zero_term = false;
       for (int p = 0; p < np; ++p) {
-        const double c = sg[p] != 0.0 ? wt[p] * sg[p] * exp(lg[p] - lmax) : 0.0;
+        if (sg[p] == 0.0) continue;   // no inverse to update (kept only for robustness)
+        const double c = wt[p] * sg[p] * exp(lg[p] - lmax);
         num += c * rp[p];
         den += c;
         zero_term = zero_term || !(rp[p] != 0.0);
