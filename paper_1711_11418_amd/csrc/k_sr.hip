@@ -326,155 +326,252 @@ __device__ __forceinline__ double lane_value(double v, int lane) {
 }
 }  // namespace
 
-// Cholesky of diagonal block kb, left-looking (Cholesky-Crout), one
-// wavefront: lane i keeps row i in registers and finishes it left to right,
-//   L[i][j] = (A[i][j] - sum_{m<j} L[i][m] L[j][m]) * (1 / L[j][j]),
-//   L[j][j] = sqrt(A[j][j] - sum_{m<j} L[j][m]^2),
-// reading the finished row j from LDS.  Entries above the diagonal (and rows
-// past the matrix) are computed but never read or stored.  A non-positive
-// pivot sets the instance's flag.
-__global__ __launch_bounds__(64) void k_potrf_diag(SrArgs A, int kb) {
-  const SrInst& I = A.inst[blockIdx.x];
-  const int nblk = (int)ceil_div<int64_t>(I.np, kNb);
-  if (kb >= nblk) return;
-  const int64_t o = (int64_t)kb * kNb;
-  const int nb = (int)(I.np - o < kNb ? I.np - o : kNb);
-  const int i = threadIdx.x;
-  if (i >= kNb) return;   // one wavefront per block
-  double* F = A.chol + I.chol_off;
-  double r[kNb];
-  const double* Fi = F + (o + (i < nb ? i : nb - 1)) * I.np + o;
-#pragma unroll
-  for (int j = 0; j < kNb; ++j) r[j] = Fi[j < nb ? j : nb - 1];
-  __shared__ double Ls[kNb][kNb + 1];
-  bool bad = false;
-#pragma unroll
-  for (int j = 0; j < kNb; ++j) {
-    // the dot product in four independent chains (latency, not bandwidth)
-    double c[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int m = 0; m < j; ++m) c[m & 3] += r[m] * Ls[j][m];
-    const double s = r[j] - ((c[0] + c[1]) + (c[2] + c[3]));
-    const double dj = lane_value(s, j);
-    if (j < nb && !(dj > 0.0)) bad = true;
-    const double ljj = sqrt(dj > 0.0 ? dj : DBL_MIN);
-    const double rl = 1.0 / ljj;
-    r[j] = i == j ? ljj : s * rl;
-    Ls[i][j] = r[j];
-    wave::wave_sync();
-    asm volatile("" ::: "memory");   // keep each row's loads within its step
-  }
-  if (bad && i == 0) A.scal[blockIdx.x * kScal + kFlag] = 1.0;
-  double* Fw = F + (o + i) * I.np + o;
-  if (nb == kNb) {
-    // whole rows: the part above the diagonal is never read
-#pragma unroll
-    for (int j = 0; j < kNb; ++j) Fw[j] = r[j];
-  } else if (i < nb) {
-    for (int j = 0; j <= i; ++j) Fw[j] = Ls[i][j];
-  }
+// One block column of the factor and of the forward substitution per
+// launch.  Within an outer panel the factor is left-looking: block column kb
+// still lacks the contributions of the panel's earlier columns c (kb0 <= c <
+// kb); the columns of earlier panels were applied by k_chol_trail.  Workgroup
+// b of an instance owns row block ib = kb + b and computes
+//   D = F[kb][kb] - sum_c L[kb][c] L[kb][c]^T        (every workgroup; 64 x 64)
+//   L_kk = chol(D),  y_kb = L_kk^-1 x_kb              (forward substitution)
+// and then, for ib == kb, stores L_kk and y_kb (into r), or for ib > kb
+//   B = F[ib][kb] - sum_c L[ib][c] L[kb][c]^T,   L[ib][kb] = B L_kk^-T,
+//   x_ib -= L[ib][kb] y_kb.
+// The 64 x 64 factor runs in four steps over column strips of 16: the
+// strip's 16 x 16 diagonal block by Crout in 16 lanes,
+//   L[i][j] = (D[i][j] - sum_{m<j} L[i][m] L[j][m]) / L[j][j],
+//   L[j][j] = sqrt(D[j][j] - sum_{m<j} L[j][m]^2),
+// then every row below it in the strip, every row of B and the row x_kb^T
+// by the same 16-step recurrence against that block (one thread per row),
+// then the update of the columns right of the strip; B's rows end as
+// B L_kk^-T and the last row as y_kb^T.  Blocks past the matrix are padded
+// with the identity.  L_kk is stored in block kb's slot after the factor
+// (chol_off + np^2 + kb 64^2, row-major), never in F: the other workgroups of
+// the launch still read F[kb][kb].  A non-positive pivot sets the instance's
+// flag.
+constexpr int kColPad = kNb + 1;   // row stride of the factor phase (2-way LDS banks)
+constexpr int kGemmPad = kNb + 2;  // column stride of the k-major GEMM stage (16-byte rows)
+constexpr int kStrip = 16;
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+// 1/sqrt(d) for d > 0 to double precision: the hardware estimate and two
+// Newton steps y <- y (3 - d y^2) / 2 (each doubles the correct bits).
+__device__ __forceinline__ double rsqrt_nr(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  y = y * (1.5 - 0.5 * d * y * y);
+  y = y * (1.5 - 0.5 * d * y * y);
+  return y;
 }
 
-// Panel below the diagonal block: every row r below it solves
-// L[r][blk] L_kk^T = F[r][blk], one thread per row with the row in
-// registers and L_kk shared in LDS (256 rows per workgroup).
-constexpr int kTrsmRows = 256;
-__global__ __launch_bounds__(kTrsmRows) void k_trsm_panel(SrArgs A, int kb) {
+__global__ __launch_bounds__(256) void k_chol_column(SrArgs A, int kb, int kb0) {
   const SrInst& I = A.inst[blockIdx.y];
   const int nblk = (int)ceil_div<int64_t>(I.np, kNb);
   if (kb >= nblk) return;
-  const int64_t o = (int64_t)kb * kNb;
-  const int64_t r0 = o + kNb + (int64_t)blockIdx.x * kTrsmRows;
-  if (r0 >= I.np) return;
-  const int nb = (int)(I.np - o < kNb ? I.np - o : kNb);
-  __shared__ double L[kNb][kNb];
+  const int ib = kb + (int)blockIdx.x;
+  if (ib >= nblk) return;
+  const bool diag = ib == kb;
+  const int64_t o = (int64_t)kb * kNb, ro = (int64_t)ib * kNb, np = I.np;
+  const int nb = (int)(np - o < kNb ? np - o : kNb);
+  const int nr = (int)(np - ro < kNb ? np - ro : kNb);
   double* F = A.chol + I.chol_off;
-  for (int e = threadIdx.x; e < kNb * kNb; e += blockDim.x) {
-    const int i = e / kNb, j = e % kNb;
-    L[i][j] = (i < nb && j <= i) ? F[(o + i) * I.np + o + j] : (i == j ? 1.0 : 0.0);
-  }
-  __syncthreads();
-  const int64_t row = r0 + threadIdx.x;
-  if (row >= I.np) return;
-  // columns past the matrix (last block only) read the last column and are
-  // replaced by zero, so the loads need no branch
-  double x[kNb];
-  double* Fr = F + row * I.np;
+  double* x = A.x + I.param_off;
+  // two LDS regions, each viewed k-major for the GEMM stage and row-major
+  // for the factor phase
+  __shared__ __align__(16) double bufP[kNb * kGemmPad];         // L[kb][c]^T, then D and L_kk
+  __shared__ __align__(16) double bufQ[(kNb + 1) * kGemmPad];   // L[ib][c]^T, then B and x_kb^T
+  __shared__ double rd[kNb];                                    // 1 / L_kk[j][j]
+  auto P = reinterpret_cast<double (*)[kColPad]>(bufP);
+  auto Q = reinterpret_cast<double (*)[kColPad]>(bufQ);
+  auto Pt = reinterpret_cast<double (*)[kGemmPad]>(bufP);
+  auto Qt = reinterpret_cast<double (*)[kGemmPad]>(bufQ);
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  double accD[4][4] = {}, accB[4][4] = {};
+  // in-panel update: 64 x 64 x 64 products per earlier column block (full
+  // blocks), operands staged k-major so a thread's four rows are one 32-byte run
+  for (int c = kb0; c < kb; ++c) {
+    const int64_t co = (int64_t)c * kNb;
+    // every load of the chunk in flight before the first LDS store
+    constexpr int kU = kNb * kNb / 256;
+    double vp[kU], vq[kU];
 #pragma unroll
-  for (int j = 0; j < kNb; ++j) {
-    const double v = Fr[o + j < I.np ? o + j : I.np - 1];
-    x[j] = j < nb ? v : 0.0;
-  }
+    for (int u = 0; u < kU; ++u) {
+      const int e = tid + 256 * u, i = e / kNb, k = e % kNb;
+      vp[u] = i < nb ? F[(o + i) * np + co + k] : 0.0;
+      vq[u] = (!diag && i < nr) ? F[(ro + i) * np + co + k] : 0.0;
+    }
+    __syncthreads();   // the previous chunk is consumed
 #pragma unroll
-  for (int j = 0; j < kNb; ++j) {
-    double s = x[j];
+    for (int u = 0; u < kU; ++u) {
+      const int e = tid + 256 * u, i = e / kNb, k = e % kNb;
+      Pt[k][i] = vp[u];
+      Qt[k][i] = vq[u];
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < kNb; ++k) {
+      const f64x2 a0 = *reinterpret_cast<const f64x2*>(&Pt[k][ty * 4]);
+      const f64x2 a1 = *reinterpret_cast<const f64x2*>(&Pt[k][ty * 4 + 2]);
+      const f64x2 b0 = *reinterpret_cast<const f64x2*>(&Pt[k][tx * 4]);
+      const f64x2 b1 = *reinterpret_cast<const f64x2*>(&Pt[k][tx * 4 + 2]);
+      const double a[4] = {a0.x, a0.y, a1.x, a1.y}, bb[4] = {b0.x, b0.y, b1.x, b1.y};
 #pragma unroll
-    for (int m = 0; m < j; ++m) s -= x[m] * L[j][m];
-    x[j] = s / L[j][j];
-    asm volatile("" ::: "memory");   // keep each row of L_kk's loads within its step
-  }
-  if (nb == kNb) {
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < kNb; ++j) Fr[o + j] = x[j];
-  } else {
-    for (int j = 0; j < nb; ++j) {
-      double v = x[0];
+        for (int j = 0; j < 4; ++j) accD[i][j] += a[i] * bb[j];
+      if (!diag) {
+        const f64x2 q0 = *reinterpret_cast<const f64x2*>(&Qt[k][ty * 4]);
+        const f64x2 q1 = *reinterpret_cast<const f64x2*>(&Qt[k][ty * 4 + 2]);
+        const double bq[4] = {q0.x, q0.y, q1.x, q1.y};
 #pragma unroll
-      for (int t = 1; t < kNb; ++t)
-        if (t == j) v = x[t];
-      Fr[o + j] = v;
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) accB[i][j] += bq[i] * bb[j];
+      }
     }
   }
-}
-
-// Update inside an outer panel: F[ib][jb] -= L[ib][kb] L[jb][kb]^T for the
-// later blocks jb of the panel (kb < jb < jb_end) and every block row
-// ib >= jb (lower triangle).  The columns past the panel are left to
-// k_chol_trail, which applies the whole panel at once.
-__global__ __launch_bounds__(256) void k_chol_update(SrArgs A, int kb, int jb_end) {
-  const SrInst& I = A.inst[blockIdx.y];
-  const int nblk = (int)ceil_div<int64_t>(I.np, kNb);
-  const int jend = jb_end < nblk ? jb_end : nblk;
-  int idx = blockIdx.x, jb = kb + 1;
-  while (jb < jend && idx >= nblk - jb) {
-    idx -= nblk - jb;
-    ++jb;
-  }
-  if (jb >= jend) return;
-  const int ib = jb + idx;
-  const int64_t o = (int64_t)kb * kNb, ro = (int64_t)ib * kNb, co = (int64_t)jb * kNb;
-  const int nk = (int)(I.np - o < kNb ? I.np - o : kNb);
-  const int nr = (int)(I.np - ro < kNb ? I.np - ro : kNb);
-  const int nc = (int)(I.np - co < kNb ? I.np - co : kNb);
-  __shared__ double Ls[kNb][kNb + 1];
-  __shared__ double Ms[kNb][kNb + 1];
-  double* F = A.chol + I.chol_off;
-  for (int e = threadIdx.x; e < kNb * kNb; e += blockDim.x) {
-    const int i = e / kNb, k = e % kNb;
-    Ls[i][k] = (i < nr && k < nk) ? F[(ro + i) * I.np + o + k] : 0.0;
-    Ms[i][k] = (i < nc && k < nk) ? F[(co + i) * I.np + o + k] : 0.0;
-  }
-  __syncthreads();
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  double acc[4][4] = {};
-  for (int k = 0; k < nk; ++k) {
-    double a[4], b[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = Ls[ty * 4 + i][k];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) b[j] = Ms[tx * 4 + j][k];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
-  }
+  // D (lower triangle, identity past the matrix), B and x_kb^T; the loads
+  // first, all in flight
+  double fd[4][4], fb[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int r = ty * 4 + i, c = tx * 4 + j;
-      if (r < nr && c < nc && (ib != jb || c <= r)) F[(ro + r) * I.np + co + c] -= acc[i][j];
+      const int r = ty * 4 + i, cc = tx * 4 + j;
+      fd[i][j] = (r < nb && cc <= r) ? F[(o + r) * np + o + cc] : 0.0;
+      fb[i][j] = (!diag && r < nr && cc < nb) ? F[(ro + r) * np + o + cc] : 0.0;
     }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = ty * 4 + i, cc = tx * 4 + j;
+      double d;
+      if (r < nb && cc < nb) d = cc <= r ? fd[i][j] - accD[i][j] : 0.0;
+      else d = r == cc ? 1.0 : 0.0;
+      P[r][cc] = d;
+      if (!diag) Q[r][cc] = (r < nr && cc < nb) ? fb[i][j] - accB[i][j] : 0.0;
+    }
+  if (tid < kNb) Q[kNb][tid] = tid < nb ? x[o + tid] : 0.0;
+  const int q0 = diag ? kNb : 0;   // first row of Q to solve (the diagonal block solves x only)
+  bool bad = false;
+  for (int c0 = 0; c0 < kNb; c0 += kStrip) {
+    __syncthreads();
+    if (tid < kStrip) {   // the strip's diagonal block, lanes 0..15 of wavefront 0
+      const int i = tid;
+      double rr[kStrip];
+#pragma unroll
+      for (int j = 0; j < kStrip; ++j) rr[j] = P[c0 + i][c0 + j];
+#pragma unroll
+      for (int j = 0; j < kStrip; ++j) {
+        double s0 = rr[j], s1 = 0.0;
+#pragma unroll
+        for (int m = 0; m < j; ++m) {
+          if (m & 1) s1 -= rr[m] * P[c0 + j][c0 + m];
+          else s0 -= rr[m] * P[c0 + j][c0 + m];
+        }
+        const double sv = s0 + s1;
+        const double dj = lane_value(sv, j);
+        if (c0 + j < nb && !(dj > 0.0)) bad = true;
+        const double rl = rsqrt_nr(dj > 0.0 ? dj : DBL_MIN);   // 1 / L[j][j]
+        rr[j] = i == j ? (dj > 0.0 ? dj : DBL_MIN) * rl : sv * rl;
+        if (j <= i) P[c0 + i][c0 + j] = rr[j];
+        if (i == j) rd[c0 + j] = rl;
+        wave::wave_sync();
+        asm volatile("" ::: "memory");   // row j is complete before step j + 1 reads it
+      }
+    }
+    __syncthreads();
+    // rows below the block in the strip, then the rows of Q, one thread each
+    const int nbelow = kNb - c0 - kStrip;
+    const int nrows = nbelow + (kNb + 1 - q0);
+    if (tid < nrows) {
+      double* row = tid < nbelow ? &P[c0 + kStrip + tid][0] : &Q[q0 + tid - nbelow][0];
+      double t[kStrip];
+#pragma unroll
+      for (int j = 0; j < kStrip; ++j) t[j] = row[c0 + j];
+#pragma unroll
+      for (int j = 0; j < kStrip; ++j) {
+        double s0 = t[j], s1 = 0.0;
+#pragma unroll
+        for (int m = 0; m < j; ++m) {
+          if (m & 1) s1 -= t[m] * P[c0 + j][c0 + m];
+          else s0 -= t[m] * P[c0 + j][c0 + m];
+        }
+        t[j] = (s0 + s1) * rd[c0 + j];
+      }
+#pragma unroll
+      for (int j = 0; j < kStrip; ++j) row[c0 + j] = t[j];
+    }
+    __syncthreads();
+    // columns right of the strip, 2 x 2 entries per task: P[r][cc] (cc <= r)
+    // and Q[r][cc]
+    const int c1 = c0 + kStrip;
+    const int hb = nbelow / 2;                          // column pairs
+    const int qrows = kNb + 1 - q0;
+    const int nP = hb * hb, nQ = ((qrows + 1) / 2) * hb;
+    for (int e = tid; e < nP + nQ; e += 256) {
+      const double* r0p;
+      const double* r1p;
+      double* w0;
+      double* w1;
+      int cc;
+      bool tri = false;
+      if (e < nP) {
+        const int rp = e / hb, cp = e % hb;
+        if (cp > rp) continue;
+        const int r = c1 + 2 * rp;
+        cc = c1 + 2 * cp;
+        w0 = &P[r][0];
+        w1 = &P[r + 1][0];
+        tri = cp == rp;   // the 2 x 2 block on the diagonal: skip its upper entry
+      } else {
+        const int u = e - nP, rp = u / hb;
+        cc = c1 + 2 * (u % hb);
+        const int r = q0 + 2 * rp;
+        w0 = &Q[r][0];
+        w1 = r + 1 < kNb + 1 ? &Q[r + 1][0] : nullptr;
+      }
+      r0p = w0;
+      r1p = w1 ? w1 : w0;
+      double s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
+#pragma unroll
+      for (int m = 0; m < kStrip; ++m) {
+        const double x0 = r0p[c0 + m], x1 = r1p[c0 + m];
+        const double y0 = P[cc][c0 + m], y1 = P[cc + 1][c0 + m];
+        s00 += x0 * y0;
+        s01 += x0 * y1;
+        s10 += x1 * y0;
+        s11 += x1 * y1;
+      }
+      w0[cc] -= s00;
+      if (!tri) w0[cc + 1] -= s01;
+      if (w1) {
+        w1[cc] -= s10;
+        w1[cc + 1] -= s11;
+      }
+    }
+  }
+  if (bad && diag) A.scal[blockIdx.y * kScal + kFlag] = 1.0;
+  __syncthreads();
+  if (diag) {
+    double* Lk = F + np * np + (int64_t)kb * kNb * kNb;
+    for (int e = tid; e < kNb * kNb; e += 256) {
+      const int i = e / kNb, j = e % kNb;
+      Lk[e] = j <= i ? P[i][j] : 0.0;
+    }
+    if (tid < nb) A.r[I.param_off + o + tid] = Q[kNb][tid];
+  } else {
+    for (int e = tid; e < kNb * kNb; e += 256) {
+      const int i = e / kNb, j = e % kNb;
+      if (i < nr && j < nb) F[(ro + i) * np + o + j] = Q[i][j];
+    }
+    if (tid < nr) {
+      double cacc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int j = 0; j < kNb; ++j) cacc[j & 3] += Q[tid][j] * Q[kNb][j];
+      x[ro + tid] -= (cacc[0] + cacc[1]) + (cacc[2] + cacc[3]);
+    }
+  }
 }
 
 // Trailing update of outer step ob: the lower triangle of the rows and
@@ -574,11 +671,12 @@ __global__ __launch_bounds__(256, 2) void k_chol_trail(SrArgs A, int ob) {
 }
 
 // Inverse of every 64 x 64 diagonal block of the factor, all blocks at once
-// (one wavefront each), stored row-major after the factor at
-// chol_off + np^2 + kb * 64^2.  Lane j forms column j by forward
-// substitution, L z = e_j:  z_i = (delta_ij - sum_{m<i} L[i][m] z_m) / L[i][i],
-// with L_kk in LDS and the columns in LDS.  Rows and columns past the matrix
-// (last block) are the identity.
+// (one wavefront each), in place in the slots after the factor
+// (chol_off + np^2 + kb * 64^2, row-major, where k_chol_column left L_kk).
+// Lane j forms column j by forward substitution, L z = e_j:
+// z_i = (delta_ij - sum_{m<i} L[i][m] z_m) / L[i][i], with L_kk and the
+// columns in LDS.  Rows and columns past the matrix (last block) are the
+// identity.
 __global__ __launch_bounds__(64) void k_trtri_diag(SrArgs A) {
   const SrInst& I = A.inst[blockIdx.y];
   const int kb = blockIdx.x;
@@ -586,12 +684,12 @@ __global__ __launch_bounds__(64) void k_trtri_diag(SrArgs A) {
   if (kb >= nblk) return;
   const int64_t o = (int64_t)kb * kNb;
   const int nb = (int)(I.np - o < kNb ? I.np - o : kNb);
-  const double* F = A.chol + I.chol_off;
+  double* Li = A.chol + I.chol_off + I.np * I.np + (int64_t)kb * kNb * kNb;
   __shared__ double Ls[kNb][kNb + 1];
   __shared__ double Zs[kNb][kNb + 1];
   const int j = threadIdx.x;
   for (int i = 0; i < kNb; ++i) {
-    Ls[i][j] = (i < nb && j <= i) ? F[(o + i) * I.np + o + j] : (i == j ? 1.0 : 0.0);
+    Ls[i][j] = (i < nb && j <= i) ? Li[i * kNb + j] : (i == j ? 1.0 : 0.0);
     Zs[i][j] = 0.0;
   }
   wave::wave_sync();
@@ -601,151 +699,63 @@ __global__ __launch_bounds__(64) void k_trtri_diag(SrArgs A) {
     Zs[i][j] = i < j ? 0.0 : s / Ls[i][i];
   }
   wave::wave_sync();
-  double* Li = A.chol + I.chol_off + I.np * I.np + (int64_t)kb * kNb * kNb;
   for (int i = 0; i < kNb; ++i) Li[i * kNb + j] = Zs[i][j];
 }
 
-// Substitution in groups of G diagonal blocks, in place in x: group gi is
-// blocks kb0, kb0 + 1, ... with kb0 = G gi (forward) or kb0, kb0 - 1, ...
-// with kb0 = nblk - 1 - G gi (backward, from each instance's own last block).
-// One workgroup per instance solves the group: for each block b of it, with
-// the blocks of the group before it already solved,
-//   forward   x_b <- Linv_bb (x_b - sum L[b][c] x_c)          (c earlier in the group)
-//   backward  x_b <- Linv_bb^T (x_b - sum L[c][b]^T x_c)      (c later in the group)
-// every 64 x 64 block staged through LDS by all threads at once (sixteen
-// loads in flight per thread), then one thread per row (forward) or column
-// (backward) of the 64.  Contributions of blocks outside the group come from
-// k_trsv_rest.
-constexpr int kTrsvG = 8;
-__global__ __launch_bounds__(256) void k_trsv_group(SrArgs A, int gi, int transpose) {
-  const SrInst& I = A.inst[blockIdx.x];
-  const int nblk = (int)ceil_div<int64_t>(I.np, kNb);
-  const int kb0 = transpose ? nblk - 1 - gi * kTrsvG : gi * kTrsvG;   // first block of group gi
-  if (kb0 >= nblk || kb0 < 0) return;
-  const double* F = A.chol + I.chol_off;
-  const double* Lv = F + I.np * I.np;
-  double* x = A.x + I.param_off;
-  __shared__ double Ls[kNb][kNb + 1];
-  __shared__ double xs[kTrsvG][kNb];   // solved blocks of the group
-  __shared__ double xb[kNb];
-  const int tid = threadIdx.x;
-  // stage a 64 x 64 block (rows r0.., columns c0.., nr x nc valid) into Ls
-  auto stage = [&](const double* src, int64_t ld, int nr, int nc) {
-    double v[kNb * kNb / 256];
-#pragma unroll
-    for (int u = 0; u < kNb * kNb / 256; ++u) {
-      const int e = tid + 256 * u, i = e / kNb, m = e % kNb;
-      v[u] = (i < nr && m < nc) ? src[(int64_t)i * ld + m] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < kNb * kNb / 256; ++u) {
-      const int e = tid + 256 * u;
-      Ls[e / kNb][e % kNb] = v[u];
-    }
-  };
-  for (int g = 0; g < kTrsvG; ++g) {
-    const int b = transpose ? kb0 - g : kb0 + g;
-    if (b < 0 || b >= nblk) break;   // uniform
-    const int64_t ob = (int64_t)b * kNb;
-    const int nb = (int)(I.np - ob < kNb ? I.np - ob : kNb);
-    if (tid < kNb) xb[tid] = tid < nb ? x[ob + tid] : 0.0;
-    // contributions of the blocks of the group solved before b
-    for (int g2 = 0; g2 < g; ++g2) {
-      const int c = transpose ? kb0 - g2 : kb0 + g2;
-      const int64_t oc = (int64_t)c * kNb;
-      const int nc = (int)(I.np - oc < kNb ? I.np - oc : kNb);
-      __syncthreads();   // Ls free, xb written
-      if (!transpose) stage(F + ob * I.np + oc, I.np, nb, nc);   // L[b][c]
-      else stage(F + oc * I.np + ob, I.np, nc, nb);              // L[c][b]
-      __syncthreads();
-      if (tid < kNb) {
-        double s = 0.0;
-        if (!transpose)
-          for (int m = 0; m < kNb; ++m) s += Ls[tid][m] * xs[g2][m];
-        else
-          for (int i = 0; i < kNb; ++i) s += Ls[i][tid] * xs[g2][i];
-        xb[tid] -= s;
-      }
-    }
-    __syncthreads();
-    stage(Lv + (int64_t)b * kNb * kNb, kNb, kNb, kNb);
-    __syncthreads();
-    if (tid < kNb) {
-      double y = 0.0;
-      if (!transpose)
-        for (int m = 0; m < kNb; ++m) y += Ls[tid][m] * xb[m];
-      else
-        for (int i = 0; i < kNb; ++i) y += Ls[i][tid] * xb[i];
-      xs[g][tid] = y;
-      if (tid < nb) x[ob + tid] = y;
-    }
-  }
-}
-
-// The solved group's contribution to every block outside it: one workgroup
-// per target block t (forward: t after the group; backward: t before it),
-//   forward   x_t -= sum over the group's blocks c of L[t][c] x_c
-//   backward  x_t -= sum over the group's blocks c of L[c][t]^T x_c
-// Forward: a wavefront per 16 rows of t, lanes across the group's columns,
-// the 16 rows' loads of a column chunk in flight together, one wave sum per
-// row.  Backward: lanes across the 64 columns of t, the four wavefronts
-// splitting the group's rows (eight loads in flight), partial sums added in
-// wavefront order.
-__global__ __launch_bounds__(256) void k_trsv_rest(SrArgs A, int gi, int transpose) {
+// Backward substitution L^T x = y (y left in r by k_chol_column), one block
+// row per launch from each instance's own last block: step s solves block
+// b = nblk - 1 - s, whose y_b is final (every later block's contribution
+// was applied by the earlier steps).  Every workgroup forms
+//   x_b = Linv_bb^T y_b            (the inverted diagonal block, k_trtri_diag)
+// workgroup 0 stores it, and workgroup t < b applies
+//   y_t -= L[b][t]^T x_b.
+// The four wavefronts split the 64 rows of each 64 x 64 block, lanes across
+// its columns (coalesced), partial sums added in wavefront order.
+__global__ __launch_bounds__(256) void k_trsv_back(SrArgs A, int step) {
   const SrInst& I = A.inst[blockIdx.y];
   const int nblk = (int)ceil_div<int64_t>(I.np, kNb);
-  const int kb0 = transpose ? nblk - 1 - gi * kTrsvG : gi * kTrsvG;
-  if (kb0 >= nblk || kb0 < 0) return;
-  // group blocks [c0, c1)
-  const int c0 = transpose ? (kb0 - kTrsvG + 1 > 0 ? kb0 - kTrsvG + 1 : 0) : kb0;
-  const int c1 = transpose ? kb0 + 1 : (kb0 + kTrsvG < nblk ? kb0 + kTrsvG : nblk);
-  const int t = transpose ? (int)blockIdx.x : c1 + (int)blockIdx.x;
-  if (transpose ? t >= c0 : t >= nblk) return;
+  const int b = nblk - 1 - step;
+  const int t = (int)blockIdx.x;
+  if (b < 0 || (t > 0 && t >= b)) return;
+  const int64_t np = I.np, ob = (int64_t)b * kNb;
+  const int nb = (int)(np - ob < kNb ? np - ob : kNb);
   const double* F = A.chol + I.chol_off;
-  double* x = A.x + I.param_off;
-  const int64_t ot = (int64_t)t * kNb, gc0 = (int64_t)c0 * kNb;
-  const int64_t gc1 = ((int64_t)c1 * kNb < I.np ? (int64_t)c1 * kNb : I.np);
-  const int nt = (int)(I.np - ot < kNb ? I.np - ot : kNb);
-  const int ncols = (int)(gc1 - gc0);
+  const double* Li = F + np * np + (int64_t)b * kNb * kNb;
+  double* y = A.r + I.param_off;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  __shared__ double xg[kTrsvG * kNb];
+  constexpr int kR = kNb / 4;   // rows per wavefront
   __shared__ double part[4][kNb];
-  for (int e = tid; e < ncols; e += 256) xg[e] = x[gc0 + e];
-  __syncthreads();
-  if (!transpose) {
-    constexpr int RW = kNb / 4;   // rows per wavefront
-    double acc[RW];
+  __shared__ double xb[kNb];
+  double li[kR], yb[kR];
 #pragma unroll
-    for (int u = 0; u < RW; ++u) acc[u] = 0.0;
-    for (int m0 = 0; m0 < ncols; m0 += 64) {
-      const int m = m0 + lane;
-      const double xm = m < ncols ? xg[m] : 0.0;
-#pragma unroll
-      for (int u = 0; u < RW; ++u) {
-        const int i = wv + 4 * u;
-        acc[u] += (i < nt && m < ncols) ? F[(ot + i) * I.np + gc0 + m] * xm : 0.0;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < RW; ++u) {
-      const int i = wv + 4 * u;
-      const double v = wave::wave_total(acc[u]);
-      if (lane == 0 && i < nt) x[ot + i] -= v;
-    }
-  } else {
-    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (lane < nt)
-      for (int i0 = wv * 8; i0 < ncols; i0 += 32) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int i = i0 + u;
-          a[u] += i < ncols ? F[(gc0 + i) * I.np + ot + lane] * xg[i] : 0.0;
-        }
-      }
-    part[wv][lane] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-    __syncthreads();
-    if (tid < nt) x[ot + tid] -= ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
+  for (int u = 0; u < kR; ++u) {
+    const int i = wv * kR + u;
+    li[u] = Li[i * kNb + lane];
+    yb[u] = i < nb ? y[ob + i] : 0.0;
   }
+  double acc = 0.0;
+#pragma unroll
+  for (int u = 0; u < kR; ++u) acc += li[u] * yb[u];
+  part[wv][lane] = acc;
+  __syncthreads();
+  if (tid < kNb) xb[tid] = ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
+  __syncthreads();
+  if (t == 0 && tid < nb) A.x[I.param_off + ob + tid] = xb[tid];
+  if (t >= b) return;   // uniform per workgroup
+  const int64_t ot = (int64_t)t * kNb;   // a full block (t < b)
+  double lv[kR];
+#pragma unroll
+  for (int u = 0; u < kR; ++u) {
+    const int i = wv * kR + u;
+    lv[u] = i < nb ? F[(ob + i) * np + ot + lane] : 0.0;
+  }
+  acc = 0.0;
+#pragma unroll
+  for (int u = 0; u < kR; ++u) acc += lv[u] * xb[wv * kR + u];
+  __syncthreads();   // part is free
+  part[wv][lane] = acc;
+  __syncthreads();
+  if (tid < kNb) y[ot + tid] -= ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
 }
 
 // ------------------------------------------------------------------- CG
@@ -990,44 +1000,29 @@ void sr_cholesky_solve(const SrArgs& A, const TS* S, const double* g, double eps
                        double freeze, int n_inst, int64_t max_np, hipStream_t s) {
   hipLaunchKernelGGL(k_chol_prep<TS>, dim3(max_np, n_inst), dim3(256), 0, s, A, S, g, eps_rel,
                      eps_abs, freeze);
-  // two levels: blocks of kNb factored inside outer panels of kOuter, the
-  // columns past each outer panel updated once per panel on the matrix cores
+  // two levels: block columns of kNb, left-looking inside outer panels of
+  // kOuter (one fused launch per block column, the forward substitution
+  // with it), the columns past each outer panel updated once per panel on
+  // the matrix cores
   const int nblk = (int)ceil_div<int64_t>(max_np, kNb);
   const int nob = (int)ceil_div<int64_t>(max_np, kOuter);
   constexpr int kPer = kOuter / kNb;
   for (int ob = 0; ob < nob; ++ob) {
     const int kb0 = ob * kPer, kb1 = kb0 + kPer < nblk ? kb0 + kPer : nblk;
-    for (int kb = kb0; kb < kb1; ++kb) {
-      hipLaunchKernelGGL(k_potrf_diag, dim3(n_inst), dim3(kNb), 0, s, A, kb);
-      const int R = nblk - kb - 1;
-      if (R > 0) {
-        const int rows = (int)(max_np - (int64_t)(kb + 1) * kNb);
-        hipLaunchKernelGGL(k_trsm_panel, dim3(ceil_div(rows, kTrsmRows), n_inst), dim3(kTrsmRows),
-                           0, s, A, kb);
-        int tiles = 0;
-        for (int jb = kb + 1; jb < kb1; ++jb) tiles += nblk - jb;
-        if (tiles)
-          hipLaunchKernelGGL(k_chol_update, dim3(tiles, n_inst), dim3(256), 0, s, A, kb, kb1);
-      }
-    }
+    for (int kb = kb0; kb < kb1; ++kb)
+      hipLaunchKernelGGL(k_chol_column, dim3(nblk - kb, n_inst), dim3(256), 0, s, A, kb, kb0);
     if (kb1 < nblk) {
       const int nt = (int)ceil_div<int64_t>(max_np - (int64_t)(ob + 1) * kOuter, kUT);
       hipLaunchKernelGGL(k_chol_trail, dim3(nt * (nt + 1) / 2, n_inst), dim3(256), 0, s, A, ob);
     }
   }
-  // substitutions: the diagonal blocks inverted at once, then groups of
-  // kTrsvG blocks, each solved by one workgroup and applied to the blocks
-  // outside it (group gi counts from the first block forward and from each
-  // instance's own last block backward)
+  // backward substitution: the diagonal blocks inverted at once, then one
+  // block row per launch from each instance's own last block
   hipLaunchKernelGGL(k_trtri_diag, dim3(nblk, n_inst), dim3(64), 0, s, A);
-  const int ngrp = ceil_div(nblk, kTrsvG);
-  for (int t = 0; t < 2; ++t)
-    for (int gi = 0; gi < ngrp; ++gi) {
-      hipLaunchKernelGGL(k_trsv_group, dim3(n_inst), dim3(256), 0, s, A, gi, t);
-      const int rest = nblk - (gi + 1) * kTrsvG;   // most target blocks of any instance
-      if (rest > 0)
-        hipLaunchKernelGGL(k_trsv_rest, dim3(rest, n_inst), dim3(256), 0, s, A, gi, t);
-    }
+  for (int step = 0; step < nblk; ++step) {
+    const int b = nblk - 1 - step;   // of the widest instance
+    hipLaunchKernelGGL(k_trsv_back, dim3(b > 1 ? b : 1, n_inst), dim3(256), 0, s, A, step);
+  }
 }
 
 namespace {
