@@ -442,12 +442,14 @@ Plan make_plan(const mvmc_config& c) {
     ks = std::min<int64_t>(ks, std::max<int64_t>(1, I.rows / 256));
     while (ks > 1 && ks * tiles * 4096 * 8 > ((int64_t)256 << 20)) ks /= 2;
     // wide parameter sets: direct-to-LDS tiles (256 by default), no sample
-    // split except for the tail tiles, whose FP32 partials share this pool
-    if (tiled_s) ks = 1;
+    // split except for the tail tiles, whose FP32 partials share this pool;
+    // in double precision 128 x 128 tiles written straight into S
+    S.wide64 = c.build_s && c.precision == MVMC_FP64 && wide_params(I.np);
+    if (tiled_s || S.wide64) ks = 1;
     S.ksplit = (int32_t)ks;
     S.sb = tiled_s ? kMaxTileSb : 0;
     S.syrkpart_off = off_syrkpart;
-    if (c.build_s)
+    if (c.build_s && !S.wide64)
       off_syrkpart += tiled_s ? (int64_t)kTailUnitsMax * (64 * kMaxTileSb) * (64 * kMaxTileSb) / 2
                               : ks * tiles * 4096;
 
@@ -1820,8 +1822,12 @@ int mvmc_build_sr(mvmc_ctx* c, int32_t n_used, const double* d_eloc, void* d_O, 
       sr_syrk_bf16x3(c->SA, split, (float*)d_S, n, P.max_np, P.max_ksplit,
                      syrk_launch(c->h_sr, n), c->stream);
     else
+    {
+      bool any_wide = false, any_narrow = false;
+      for (const SrInst& si : P.sr) (si.wide64 ? any_wide : any_narrow) = true;
       sr_syrk_vec<double, double>(c->SA, (const double*)d_O, (double*)d_S, n, P.max_np,
-                                  P.max_ksplit, c->stream);
+                                  P.max_ksplit, any_wide, any_narrow, c->stream);
+    }
     toc(c, id);
     LAUNCHCHK(c);
   }

@@ -215,6 +215,7 @@ typedef double f64x4_t __attribute__((ext_vector_type(4)));
 constexpr int kTp = kTile + 2;   // padded LDS row
 __global__ __launch_bounds__(256) void k_syrk_f64mfma(SrArgs A, const double* __restrict__ O) {
   const SrInst& I = A.inst[blockIdx.z];
+  if (I.wide64) return;   // k_syrk_f64_wide
   const int nt = (int)ceil_div<int64_t>(I.np, kTile);
   const int ntiles = nt * (nt + 1) / 2;
   if ((int)blockIdx.x >= ntiles || (int)blockIdx.y >= I.ksplit) return;
@@ -271,9 +272,115 @@ __global__ __launch_bounds__(256) void k_syrk_f64mfma(SrArgs A, const double* __
         part[(32 * qi + 16 * i + ka + 4 * r) * kTile + 32 * qj + 16 * j + ma] = acc[i][j][r];
 }
 
+// Wide parameter sets in double precision: 128 x 128 upper-triangle tiles
+// straight into S (both triangles, scaled by 1/N), no sample split.  Four
+// wavefronts, each a 64 x 64 quadrant as 4 x 4 blocks of 16 x 16 MFMA
+// accumulators; the samples pass through LDS sixteen at a time as they lie in
+// O (sample-major rows, so every MFMA operand is 16 consecutive parameters of
+// one sample), double-buffered through registers.  O's padding columns are
+// zero, so only samples past N need masking.  The lower triangle is written
+// from each 16 x 16 block transposed through LDS, so both writes are
+// coalesced.
+constexpr int kWT = 128, kWK = 16, kWP = kWT + 2;
+__global__ __launch_bounds__(256, 2) void k_syrk_f64_wide(SrArgs A, const double* __restrict__ O,
+                                                          double* __restrict__ S) {
+  const SrInst& I = A.inst[blockIdx.y];
+  if (!I.wide64) return;
+  const int nt = (int)ceil_div<int64_t>(I.np, kWT);
+  if ((int)blockIdx.x >= nt * (nt + 1) / 2) return;
+  int ti, tj;
+  tile_of(blockIdx.x, nt, ti, tj);   // ti <= tj
+  const int64_t ca = (int64_t)ti * kWT, cb = (int64_t)tj * kWT, ld = I.ldO, rows = I.rows;
+  const double* Ob = O + I.O_off;
+  __shared__ double As[2][kWK][kWP];
+  __shared__ double Bs[2][kWK][kWP];
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int qi = wv >> 1, qj = wv & 1;
+  const int lk = tid >> 4, lc = (tid & 15) * 8;   // staging: sample lk, parameters lc..lc+7
+  double ga[8], gb[8];
+  auto gload = [&](int64_t m0) {
+    const int64_t m = m0 + lk;
+    const bool ok = m < rows;
+    const double* pa = Ob + (ok ? m : 0) * ld + ca + lc;
+    const double* pb = Ob + (ok ? m : 0) * ld + cb + lc;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      ga[e] = ok ? pa[e] : 0.0;
+      gb[e] = ok ? pb[e] : 0.0;
+    }
+  };
+  auto lstore = [&](int st) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      As[st][lk][lc + e] = ga[e];
+      Bs[st][lk][lc + e] = gb[e];
+    }
+  };
+  f64x4_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  int st = 0;
+  const int ka = lane >> 4, ma = lane & 15;
+  for (int64_t m0 = 0; m0 < rows; m0 += kWK) {
+    const bool more = m0 + kWK < rows;
+    if (more) gload(m0 + kWK);
+#pragma unroll
+    for (int kk = 0; kk < kWK; kk += 4) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[i] = As[st][kk + ka][64 * qi + 16 * i + ma];
+        b[i] = Bs[st][kk + ka][64 * qj + 16 * i + ma];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) lstore(st ^ 1);
+    __syncthreads();
+    st ^= 1;
+  }
+  // element r of lane l holds D[l / 16 + 4 r][l % 16] of its 16 x 16 block
+  const double invN = 1.0 / (double)rows;
+  double* Sb = S + I.S_off;
+  const int64_t np = I.np;
+  double* tr = &As[0][0][0] + wv * 16 * 17;   // per-wavefront 16 x 17 transpose buffer
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t rb = ca + 64 * qi + 16 * i, cbb = cb + 64 * qj + 16 * j;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = rb + ka + 4 * r, col = cbb + ma;
+        const double v = acc[i][j][r] * invN;
+        if (row < np && col < np) Sb[row * np + col] = v;
+        tr[(ka + 4 * r) * 17 + ma] = v;
+      }
+      if (ti != tj) {   // mirror: row col of S gets this block's column
+        wave::wave_sync();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t row = cbb + ka + 4 * r, col = rb + ma;   // S[row][col] = D[col - rb][row - cbb]
+          const double v = tr[ma * 17 + ka + 4 * r];
+          if (row < np && col < np) Sb[row * np + col] = v;
+        }
+        wave::wave_sync();
+      }
+    }
+}
+
 template <typename TS>
 __global__ void k_syrk_reduce(SrArgs A, TS* __restrict__ S) {
   const SrInst& I = A.inst[blockIdx.z];
+  if (I.wide64) return;
   const int nt = (int)ceil_div<int64_t>(I.np, kTile);
   const int ntiles = nt * (nt + 1) / 2;
   if ((int)blockIdx.x >= ntiles) return;
@@ -984,7 +1091,15 @@ void sr_colstats(const SrArgs& A, T* O, uint16_t* split, double* g, int n_inst, 
 
 template <typename T, typename TS>
 void sr_syrk_vec(const SrArgs& A, const T* O, TS* S, int n_inst, int64_t max_np, int max_ksplit,
-                 hipStream_t s) {
+                 bool any_wide, bool any_narrow, hipStream_t s) {
+  if constexpr (std::is_same<T, double>::value && std::is_same<TS, double>::value) {
+    if (any_wide) {
+      const int nw = (int)ceil_div<int64_t>(max_np, kWT);
+      hipLaunchKernelGGL(k_syrk_f64_wide, dim3(nw * (nw + 1) / 2, n_inst), dim3(256), 0, s, A, O,
+                         S);
+    }
+    if (!any_narrow) return;
+  }
   const int nt = (int)ceil_div<int64_t>(max_np, kTile);
   const int ntiles = nt * (nt + 1) / 2;
   if constexpr (std::is_same<T, double>::value)
@@ -1077,9 +1192,9 @@ template void sr_colstats<double>(const SrArgs&, double*, uint16_t*, double*, in
 template void sr_colstats<float>(const SrArgs&, float*, uint16_t*, double*, int, int64_t, int64_t,
                                  hipStream_t);
 template void sr_syrk_vec<double, double>(const SrArgs&, const double*, double*, int, int64_t, int,
-                                          hipStream_t);
+                                          bool, bool, hipStream_t);
 template void sr_syrk_vec<float, float>(const SrArgs&, const float*, float*, int, int64_t, int,
-                                        hipStream_t);
+                                        bool, bool, hipStream_t);
 template void sr_cholesky_solve<double>(const SrArgs&, const double*, const double*, double, double,
                                         double, int, int64_t, hipStream_t);
 template void sr_cholesky_solve<float>(const SrArgs&, const float*, const double*, double, double,
