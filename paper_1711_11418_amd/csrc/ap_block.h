@@ -51,11 +51,15 @@ struct ApState {
   bool singular = false;
 };
 
+typedef __attribute__((address_space(3))) double lds_f64x2
+    __attribute__((ext_vector_type(2)));
+
 // Exchange step K (column K), then the next one: compile-time recursion, so
 // every m[K] is a constant register index whatever the unroll heuristics.
-// rowp: NS doubles of LDS for the pivot row; piv: NS ints, pivot row of each
-// column.
-template <int K, int NS>
+// rowp: NS doubles of LDS for the pivot row (16-byte aligned); piv: NS ints,
+// pivot row of each column.  CH: pivot-row values in flight per chunk
+// (16-byte loads when even), bounded by the caller's register budget.
+template <int K, int NS, int CH = (NS > 32 ? 4 : 8)>
 __device__ __forceinline__ void ap_steps(ApState& st, double (&m)[NS], double* rowp,
                                          int32_t* piv, int lane, bool live, int nh,
                                          double tol) {
@@ -83,8 +87,19 @@ __device__ __forceinline__ void ap_steps(ApState& st, double (&m)[NS], double* r
         if (me) {
           lds_double* wp = (lds_double*)rowp;
           asm volatile("" : "+v"(wp));
+          if constexpr (NS % 2 == 0) {
+            lds_f64x2* wp2 = (lds_f64x2*)wp;
 #pragma unroll
-          for (int c = 0; c < NS; ++c) wp[c] = m[c];
+            for (int c = 0; c < NS; c += 2) {
+              lds_f64x2 v;
+              v.x = m[c];
+              v.y = m[c + 1];
+              wp2[c / 2] = v;
+            }
+          } else {
+#pragma unroll
+            for (int c = 0; c < NS; ++c) wp[c] = m[c];
+          }
         }
         // one wavefront's LDS operations complete in issue order, so the
         // reads below see the row without waiting for the writes: only the
@@ -93,15 +108,24 @@ __device__ __forceinline__ void ap_steps(ApState& st, double (&m)[NS], double* r
         const double ip = 1.0 / pv;
         const double f = me ? 0.0 : m[K] * ip;
         // the pivot row from one VGPR base with immediate offsets, CH values
-        // in flight per chunk (fewer for long rows, whose registers are scarce)
-        constexpr int CH = NS > 32 ? 4 : 8;
+        // in flight per chunk
         const lds_double* rp = (const lds_double*)rowp;
         asm volatile("" : "+v"(rp));
 #pragma unroll
         for (int c0 = 0; c0 < NS; c0 += CH) {
           double r[CH];
+          if constexpr (CH % 2 == 0 && NS % CH == 0) {
+            const lds_f64x2* rp2 = (const lds_f64x2*)rp;
 #pragma unroll
-          for (int u = 0; u < CH; ++u) r[u] = c0 + u < NS ? rp[c0 + u] : 0.0;
+            for (int u = 0; u < CH; u += 2) {
+              const lds_f64x2 v = rp2[(c0 + u) / 2];
+              r[u] = v.x;
+              r[u + 1] = v.y;
+            }
+          } else {
+#pragma unroll
+            for (int u = 0; u < CH; ++u) r[u] = c0 + u < NS ? rp[c0 + u] : 0.0;
+          }
 #pragma unroll
           for (int u = 0; u < CH; ++u) {
             const int c = c0 + u;
@@ -113,7 +137,7 @@ __device__ __forceinline__ void ap_steps(ApState& st, double (&m)[NS], double* r
         asm volatile("" ::: "memory");   // next step's row write after these reads
       }
     }
-    ap_steps<K + 1, NS>(st, m, rowp, piv, lane, live, nh, tol);
+    ap_steps<K + 1, NS, CH>(st, m, rowp, piv, lane, live, nh, tol);
   } else {
     st.logabs = absdet_log(st.mant, st.ex);
 #pragma unroll

@@ -7,16 +7,18 @@
 // site of down electron b), so
 //     X = [[0, M], [-M^T, 0]],   Pf(X) = (-1)^{n(n-1)/2} det M,
 //     X^-1 = [[0, -M^-T], [M^-1, 0]].
-// One wavefront per walker inverts M in place by Gauss-Jordan exchange
-// steps with partial pivoting.  Lane r keeps row r of the tableau T (= M at
-// the start) in registers; the column loop is unrolled, so every register
-// index is a compile-time constant.  Step k takes the unused row p of
+// One wavefront per walker inverts M^T in place by Gauss-Jordan exchange
+// steps with partial pivoting (det M^T = det M, (M^T)^-1 = (M^-1)^T; M^T
+// loads one row of A per instruction).  Lane r keeps row r of the tableau T
+// (= M^T at the start) in registers; the column loop is unrolled, so every
+// register index is a compile-time constant.  Step k takes the unused row p of
 // largest |T[r][k]|, pi = T[p][k], and exchanges row p with column k:
 //     T[p][k] <- 1/pi,          T[p][c] <- -T[p][c]/pi,
 //     T[r][k] <- T[r][k]/pi,    T[r][c] <- T[r][c] - T[r][k] T[p][c]/pi
-// (r != p, c != k).  After all n steps M^-1[a][p_b] = T[p_a][b], with p_k the
-// pivot row of column k, and det M = sgn(p) prod_k pi_k, the sign counted as
-// the permutation is built.  The same pass recomputes the Jastrow field
+// (r != p, c != k).  After all n steps T0^-1[a][p_b] = T[p_a][b] for the
+// starting tableau T0 (here M^T, so M^-1[p_b][a] = T[p_a][b]), with p_k the
+// pivot row of column k, and det M = det T0 = sgn(p) prod_k pi_k, the sign
+// counted as the permutation is built.  The same pass recomputes the Jastrow field
 // h_l = sum_m v_lm (n_m - 1) and the RBM angles theta = b + W sigma.
 //
 // ap_refresh_wave: one wavefront per walker (n <= NS <= 64).
@@ -41,11 +43,13 @@ __host__ __device__ inline size_t ap_walker_bytes(int ns_max, int nsmax_sites) {
   return (ns_max * sizeof(double)) + ((ints * sizeof(int32_t) + 15) & ~(size_t)15);
 }
 
-// LDS per walker for M^-1 (row stride wld = max up electrons + 1), staged
-// so X^-1 is written row by row with the lanes across the columns.
+// LDS per walker for kMinvChunk rows of M^-1 at a time (row stride wld =
+// max up electrons + 1), staged so X^-1 is written with the lanes across
+// its rows.
+constexpr int kMinvChunk = 16;
 template <typename T>
 __host__ __device__ inline size_t ap_minv_bytes(int wld) {
-  return ((size_t)(wld - 1) * wld * sizeof(T) + 15) & ~(size_t)15;
+  return ((size_t)kMinvChunk * wld * sizeof(T) + 15) & ~(size_t)15;
 }
 
 // Walker gw by the calling wavefront (lane = threadIdx.x & 63); q: this
@@ -75,23 +79,26 @@ __device__ __forceinline__ void ap_refresh_wave(const Pools& P, int gw, unsigned
   wave_sync();
   for (int b = lane; b < ne; b += 64) occ[pos[b]] = 1;
 
-  // row `lane` of M: the up electron `lane` against every down electron
+  // The tableau is M^T: lane b keeps column b of M (the down electron b
+  // against every up electron), so each load reads one row of A, the up
+  // electron's, across the lanes.  det M^T = det M, and the elimination
+  // yields (M^T)^-1 = (M^-1)^T.
   const double* A = P.A64 + I.A_off;
   const bool live = lane < nh;
-  const int64_t roff = live ? (int64_t)pos[lane] * n2 : 0;
+  const int32_t col = live ? pos[nh + lane] : 0;
   double m[NS];
   double amax = 0.0;
 #pragma unroll
   for (int c = 0; c < NS; ++c) {
     const bool in = live && c < nh;
-    const double v = in ? A[roff + pos[nh + (in ? c : 0)]] : 0.0;
+    const double v = in ? A[(int64_t)pos[in ? c : 0] * n2 + col] : 0.0;
     m[c] = v;
     amax = fmax(amax, fabs(v));
   }
   amax = wave_max(amax);
 
   ApState st;
-  ap_steps<0, NS>(st, m, rowp, piv, lane, live, nh, sing_tol * amax);
+  ap_steps<0, NS, (NS > 32 ? 32 : NS)>(st, m, rowp, piv, lane, live, nh, sing_tol * amax);
   double logabs = st.logabs, sgn = st.sgn, minpiv = st.minpiv;
   const int parity = st.parity;
   const bool singular = st.singular;
@@ -107,28 +114,36 @@ __device__ __forceinline__ void ap_refresh_wave(const Pools& P, int gw, unsigned
   } else {
     if (parity & 1) sgn = -sgn;
     if (((nh * (nh - 1)) / 2) & 1) sgn = -sgn;   // Pf(X) = (-1)^{n(n-1)/2} det M
-    // lane p_a holds row a of M^-1 at the columns p_b; W[a][q] = M^-1[a][q]
-    // goes to LDS, then every row of Y is written with the lanes across it:
-    //   Y[q][n + a] = -W[a][q],  Y[n + a][q] = W[a][q],  same-spin blocks 0
+    // lane p_a holds row a of (M^T)^-1, i.e. column a of M^-1, at the
+    // columns p_q.  Sixteen of them at a time, W[a - a0][q] = M^-1[q][a]
+    // goes to LDS and the two non-zero blocks of Y are written with the
+    // lanes across them:
+    //   Y[a][n + q] = -W[a][q]  (rows of the upper-right block),
+    //   Y[n + q][a] =  W[a][q]  (sixteen consecutive entries of each row n + q).
+    // The same-spin blocks stay zero: the pool is cleared at init and no
+    // kernel writes them.
     T* Y = (T*)P.Y + I.Y_off + lw * ne * ne;
-    int a = -1;   // row of M^-1 pivoted by this lane's row
+    int a = -1;   // row of the inverse pivoted by this lane's row
 #pragma unroll
     for (int k = 0; k < NS; ++k)
       if (k < nh && piv[k] == lane) a = k;
-    if (live && a >= 0) {
+    for (int a0 = 0; a0 < nh; a0 += kMinvChunk) {
+      if (live && a >= a0 && a < a0 + kMinvChunk) {
 #pragma unroll
-      for (int b = 0; b < NS; ++b)
-        if (b < nh) Wl[a * wld + piv[b]] = (T)m[b];
-    }
-    wave_sync();
-    for (int r = 0; r < ne; ++r) {
-      T* yr = Y + (int64_t)r * ne;
-      for (int c = lane; c < ne; c += 64) {
-        T v = T(0);
-        if (r < nh && c >= nh) v = -Wl[(c - nh) * wld + r];
-        if (r >= nh && c < nh) v = Wl[(r - nh) * wld + c];
-        yr[c] = v;
+        for (int b = 0; b < NS; ++b)
+          if (b < nh) Wl[(a - a0) * wld + piv[b]] = (T)m[b];
       }
+      wave_sync();
+      const int na = nh - a0 < kMinvChunk ? nh - a0 : kMinvChunk;
+      for (int rr = 0; rr < na; ++rr) {
+        T* yr = Y + (int64_t)(a0 + rr) * ne + nh;
+        for (int q = lane; q < nh; q += 64) yr[q] = -Wl[rr * wld + q];
+      }
+      for (int e = lane; e < nh * kMinvChunk; e += 64) {
+        const int q = e / kMinvChunk, aa = e % kMinvChunk;
+        if (aa < na) Y[(int64_t)(nh + q) * ne + a0 + aa] = Wl[aa * wld + q];
+      }
+      wave_sync();
     }
     if (lane == 0) {
       if (flags) flags[gw] = 0;

@@ -1147,6 +1147,8 @@ int init_impl(mvmc_ctx** out, const mvmc_config* cfg, void* d_ws, size_t ws_byte
   chk(hipMemset(Q.guard, 0, 4 * P.W));
   chk(hipMemset(b + P.needs_refresh.off, 0, 4 * P.W));
   chk(hipMemset(Q.theta, 0, 8 * std::max<size_t>(P.theta.bytes / 8, 1)));
+  // the same-spin blocks of every X^-1 are zero and only this clear writes them
+  chk(hipMemset(Q.Y, 0, std::max<size_t>(P.Y.bytes, 1)));
   chk(hipMemset(S.scal, 0, P.scal.bytes));
   if (c->no_alloc) {
     c->h_sr_plain.resize(P.sr.size());
