@@ -194,9 +194,13 @@ __device__ __forceinline__ bool ap_walk(const Pools& P, int gw, unsigned char* s
   int32_t guard1 = guard0;
 
   int it = 0;
+  // each proposal's draw is formed during the previous one (scalar work that
+  // overlaps the previous proposal's loads)
+  uint4 r_cur = draw(seed, n0, (uint32_t)gw, 0u);
   while (it < n_prop) {
     const uint64_t nn = n0 + (uint64_t)it;
-    const uint4 r = draw(seed, nn, (uint32_t)gw, 0u);
+    const uint4 r = r_cur;
+    r_cur = draw(seed, nn + 1, (uint32_t)gw, 0u);
     bool nonfinite = false;
     do {   // one proposal; `continue` ends it
     if (ex64 && (int)(r.w & 63u) < ex64) {
@@ -385,6 +389,15 @@ __device__ __forceinline__ bool ap_walk(const Pools& P, int gw, unsigned char* s
     }
     if (!accept) continue;
     ++acc;
+    // the Jastrow-field change, requested now so its loads overlap the update
+    // of M^-1 (V is symmetric: row site_new across the threads is coalesced)
+    constexpr int kHv = 4;
+    double dv[kHv];
+#pragma unroll
+    for (int u = 0; u < kHv; ++u) {
+      const int l = tid + u * NT;
+      dv[u] = l < ns ? V[(int64_t)site_new * ns + l] - V[(int64_t)site_old * ns + l] : 0.0;
+    }
     __syncthreads();   // m' and the column/row of M^-1 visible to every thread
 
     // v (up) or t (down): each wavefront sums a slice of the contraction
@@ -416,8 +429,13 @@ __device__ __forceinline__ bool ap_walk(const Pools& P, int gw, unsigned char* s
       const T rgt = sigma == 0 ? vt[j] : cr[j];
       Mi[i * ld + j] -= (lft * ir) * rgt;
     }
-    // V is symmetric: row site_new read across the threads is coalesced
-    for (int l = tid; l < ns; l += NT) hs[l] += V[(int64_t)site_new * ns + l] - V[(int64_t)site_old * ns + l];
+#pragma unroll
+    for (int u = 0; u < kHv; ++u) {
+      const int l = tid + u * NT;
+      if (l < ns) hs[l] += dv[u];
+    }
+    for (int l = tid + kHv * NT; l < ns; l += NT)
+      hs[l] += V[(int64_t)site_new * ns + l] - V[(int64_t)site_old * ns + l];
     for (int hh = tid; hh < M; hh += NT)
       ths[hh] += T(2) * (rW[(int64_t)hh * n2 + Inew] - rW[(int64_t)hh * n2 + Iold]);
     if (tid == 0) {

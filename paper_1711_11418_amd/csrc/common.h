@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "wave.h"
+
 namespace mvmc {
 
 constexpr int kWave = 64;
@@ -161,11 +163,18 @@ __device__ __forceinline__ float log2cosh(float x) {
 }
 
 // ------------------------------------------------------------ reductions
+// Sum over the 64 lanes of a fully active wavefront, the total in every lane.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
   return v;
+}
+// doubles through the DPP row operations and a scalar read-back (each
+// __shfl_xor step is an LDS permute round trip)
+template <>
+__device__ __forceinline__ double wave_sum<double>(double v) {
+  return wave::wave_total(v);
 }
 
 // Block-wide sum of two values; every thread gets the totals.  `red` holds
