@@ -236,7 +236,7 @@ __device__ __forceinline__ bool ap_walk(const Pools& P, int gw, unsigned char* s
         ca[q2] = c;
         accr += fn * c;
         const int s_up = pos_s[q2];
-        const T cv = q2 == a ? Ai[sj] : A[(int64_t)s_up * n2 + ns + si];
+        const T cv = q2 == a ? Ai[sj] : -A[(int64_t)(ns + si) * n2 + s_up];   // f(s_up, i), row-wise
         const T rv = Mi[bd * ld + q2];
         cn[q2] = cv;
         rb[q2] = rv;
@@ -349,7 +349,9 @@ __device__ __forceinline__ bool ap_walk(const Pools& P, int gw, unsigned char* s
       }
     } else {
       for (int i = tid; i < n; i += NT) {
-        const T x = A[(int64_t)pos_s[i] * n2 + Inew];   // f(s_i, s') = A[(s_i, up)][(s', dn)]
+        // f(s_i, s') = A[(s_i, up)][(s', dn)] = -A[(s', dn)][(s_i, up)]: one row of
+        // the skew table across the threads instead of a column
+        const T x = -A[(int64_t)Inew * n2 + pos_s[i]];
         const T c = Mi[ai * ld + i];
         mv[i] = x;
         cr[i] = c;

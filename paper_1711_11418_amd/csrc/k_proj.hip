@@ -406,9 +406,10 @@ __global__ __launch_bounds__(kProjThreads) void k_sweep_proj(
             s += x * c;
           }
         } else {
-          const int col = ns + qp[site_new];                     // f(., q(s'))
+          // f(q(s_i), q(s')) = -A[(q(s'), dn)][(q(s_i), up)]: a row of the table
+          const T* Acol = A + (int64_t)(ns + qp[site_new]) * n2;
           for (int i = lane; i < n; i += 64) {
-            const T x = A[(int64_t)qp[pos_s[i]] * n2 + col];
+            const T x = -Acol[qp[pos_s[i]]];
             const T c = Mp[ai * ld + i];
             mvp[i] = x;
             crp[i] = c;
