@@ -37,10 +37,6 @@ __device__ __forceinline__ double absdet_log(double mant, int ex) {
   return log(mant) + (double)ex * 0.69314718055994530942;
 }
 
-// LDS-typed double, so that an address held in one VGPR (the asm barriers
-// below) still addresses LDS with immediate offsets
-typedef __attribute__((address_space(3))) double lds_double;
-
 struct ApState {
   double logabs = 0.0, sgn = 1.0, minpiv = DBL_MAX;
   double rs = 1.0;     // this lane's deferred row scale s_r
@@ -51,18 +47,12 @@ struct ApState {
   bool singular = false;
 };
 
-typedef __attribute__((address_space(3))) double lds_f64x2
-    __attribute__((ext_vector_type(2)));
-
 // Exchange step K (column K), then the next one: compile-time recursion, so
 // every m[K] is a constant register index whatever the unroll heuristics.
-// rowp: NS doubles of LDS for the pivot row (16-byte aligned); piv: NS ints,
-// pivot row of each column.  CH: pivot-row values in flight per chunk
-// (16-byte loads when even), bounded by the caller's register budget.
-template <int K, int NS, int CH = (NS > 32 ? 4 : 8)>
-__device__ __forceinline__ void ap_steps(ApState& st, double (&m)[NS], double* rowp,
-                                         int32_t* piv, int lane, bool live, int nh,
-                                         double tol) {
+// piv: NS ints of LDS, pivot row of each column.
+template <int K, int NS>
+__device__ __forceinline__ void ap_steps(ApState& st, double (&m)[NS], int32_t* piv, int lane,
+                                         bool live, int nh, double tol) {
   if constexpr (K < NS) {
     if (K < nh && !st.singular) {
       const bool free_row = live && !((st.used >> lane) & 1ull);
@@ -84,60 +74,24 @@ __device__ __forceinline__ void ap_steps(ApState& st, double (&m)[NS], double* r
         st.used |= 1ull << p;
         const bool me = lane == p;
         if (lane == 0) piv[K] = p;
-        if (me) {
-          lds_double* wp = (lds_double*)rowp;
-          asm volatile("" : "+v"(wp));
-          if constexpr (NS % 2 == 0) {
-            lds_f64x2* wp2 = (lds_f64x2*)wp;
-#pragma unroll
-            for (int c = 0; c < NS; c += 2) {
-              lds_f64x2 v;
-              v.x = m[c];
-              v.y = m[c + 1];
-              wp2[c / 2] = v;
-            }
-          } else {
-#pragma unroll
-            for (int c = 0; c < NS; ++c) wp[c] = m[c];
-          }
-        }
-        // one wavefront's LDS operations complete in issue order, so the
-        // reads below see the row without waiting for the writes: only the
-        // compiler is kept from moving them
-        asm volatile("" ::: "memory");
+        // the pivot row comes from lane p's registers as scalars (two
+        // readlanes per entry, no LDS traffic: the LDS instruction queue is
+        // what a wavefront waits on otherwise); lane p's own update is void
+        // (f = 0), so reading entry c before its update is all that is needed
         const double ip = 1.0 / pv;
         const double f = me ? 0.0 : m[K] * ip;
-        // the pivot row from one VGPR base with immediate offsets, CH values
-        // in flight per chunk
-        const lds_double* rp = (const lds_double*)rowp;
-        asm volatile("" : "+v"(rp));
 #pragma unroll
-        for (int c0 = 0; c0 < NS; c0 += CH) {
-          double r[CH];
-          if constexpr (CH % 2 == 0 && NS % CH == 0) {
-            const lds_f64x2* rp2 = (const lds_f64x2*)rp;
-#pragma unroll
-            for (int u = 0; u < CH; u += 2) {
-              const lds_f64x2 v = rp2[(c0 + u) / 2];
-              r[u] = v.x;
-              r[u + 1] = v.y;
-            }
-          } else {
-#pragma unroll
-            for (int u = 0; u < CH; ++u) r[u] = c0 + u < NS ? rp[c0 + u] : 0.0;
-          }
-#pragma unroll
-          for (int u = 0; u < CH; ++u) {
-            const int c = c0 + u;
-            if (c < NS && c != K) m[c] = fma(-f, r[u], m[c]);
-          }
+        for (int c = 0; c < NS; ++c) {
+          if (c == K) continue;
+          const int lo = __builtin_amdgcn_readlane(__double2loint(m[c]), p);
+          const int hi = __builtin_amdgcn_readlane(__double2hiint(m[c]), p);
+          m[c] = fma(-f, __hiloint2double(hi, lo), m[c]);
         }
         m[K] = me ? -1.0 : f;
         if (me) st.rs = -ip;
-        asm volatile("" ::: "memory");   // next step's row write after these reads
       }
     }
-    ap_steps<K + 1, NS, CH>(st, m, rowp, piv, lane, live, nh, tol);
+    ap_steps<K + 1, NS>(st, m, piv, lane, live, nh, tol);
   } else {
     st.logabs = absdet_log(st.mant, st.ex);
 #pragma unroll

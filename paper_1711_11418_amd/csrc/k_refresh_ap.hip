@@ -1,6 +1,7 @@
 // Double-precision recomputation of walkers through the anti-parallel block
-// of X (Eq. AP-Pf; ap_refresh.h): one wavefront per walker for N_e <= 128,
-// one 16 x 16 workgroup per walker for N_e <= 256.
+// of X (Eq. AP-Pf; ap_refresh.h): one wavefront per walker for N_e <= 64,
+// two (the tableau split by columns) for N_e <= 128, one 16 x 16 workgroup
+// per walker for N_e <= 256.
 #include "ap_refresh.h"
 #include "launch.h"
 
@@ -21,6 +22,14 @@ __global__ __launch_bounds__(64 * kApWpb, 2) void k_refresh_ap(Pools P,
   if (idx >= n) return;
   unsigned char* q = smem + (size_t)wv * (ap_walker_bytes(NS, max_sites) + ap_minv_bytes<T>(wld));
   ap_refresh_wave<T, NS>(P, wlist[idx], q, max_sites, wld, sing_tol, flags);
+}
+
+// 32 < n <= 64: two wavefronts per walker.
+template <typename T>
+__global__ __launch_bounds__(kPairThreads) void k_refresh_ap_pair(
+    Pools P, const int32_t* __restrict__ wlist, double sing_tol, int32_t* __restrict__ flags) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  ap_refresh_pair<T>(P, wlist[blockIdx.x], smem, sing_tol, flags, flags == nullptr);
 }
 
 // 64 < n <= 128: one workgroup of 16 x 16 threads per walker.
@@ -59,12 +68,12 @@ void launch_refresh_ap(const Pools& P, const int32_t* wlist, int n, int max_ne, 
     hipLaunchKernelGGL((k_refresh_ap<T, 32>), dim3(blocks), dim3(64 * kApWpb), sh, s, P, wlist, n,
                        max_ns, wld, sing_tol, flags);
   } else {
-    const size_t sh = (ap_walker_bytes(64, max_ns) + ap_minv_bytes<T>(wld)) * kApWpb;
+    const size_t sh = pair_bytes<T>(max_ne, max_ns);
     if (sh > 64 * 1024)
-      (void)hipFuncSetAttribute((const void*)&k_refresh_ap<T, 64>,
+      (void)hipFuncSetAttribute((const void*)&k_refresh_ap_pair<T>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-    hipLaunchKernelGGL((k_refresh_ap<T, 64>), dim3(blocks), dim3(64 * kApWpb), sh, s, P, wlist, n,
-                       max_ns, wld, sing_tol, flags);
+    hipLaunchKernelGGL((k_refresh_ap_pair<T>), dim3(n), dim3(kPairThreads), sh, s, P, wlist,
+                       sing_tol, flags);
   }
 }
 

@@ -69,8 +69,7 @@ __host__ __device__ inline size_t reg_table_bytes(int ns) {
 }
 __host__ __device__ inline size_t reg_refresh_bytes(int ne_max) {
   const size_t nh = (size_t)ne_max / 2;
-  return a16(nh * (nh + 1) * sizeof(double)) + a16(nh * sizeof(double)) +
-         a16(2 * nh * sizeof(int32_t));
+  return a16(nh * (nh + 1) * sizeof(double)) + a16(2 * nh * sizeof(int32_t));
 }
 // x' and w, each as [up half | 16-byte gap | down half] of ne_max/2 entries
 __host__ __device__ inline size_t reg_half_len(int ne_max, size_t ts) {
@@ -143,7 +142,7 @@ template <int NE_MAX, typename T, typename ZArr>
 __device__ __forceinline__ int reg_refresh_ap(
     ZArr& z, int posr0,
     const double* __restrict__ fs, int ldf, int ns, int ne, int lane, double* tab,
-    double* rowp, int32_t* piv, int32_t* pinv, double& logabs, double& sgn) {
+    int32_t* piv, int32_t* pinv, double& logabs, double& sgn) {
   constexpr int NH = NE_MAX / 2;
   constexpr int LDT = NH + 1;
   using RC = RegCol<T, NH>;
@@ -161,7 +160,7 @@ __device__ __forceinline__ int reg_refresh_ap(
     m[b] = in ? x : 0.0;
   }
   ApState st;
-  ap_steps<0, NH>(st, m, rowp, piv, lane, live, nh, 0.0);
+  ap_steps<0, NH>(st, m, piv, lane, live, nh, 0.0);
   if (st.singular) return 1;
   logabs = st.logabs;
   sgn = st.sgn;
@@ -292,11 +291,9 @@ __device__ __forceinline__ void reg_walk(const Pools& P, int gw, int wv, unsigne
   int32_t* eidx = (int32_t*)q;      // 2ns
   int32_t* emp = eidx + n2;         // 2ns
   q += a16((size_t)(4 * ns) * sizeof(int32_t));
-  // refresh scratch: tableau, pivot row, pivot rows per column and inverse
+  // refresh scratch: tableau, pivot rows per column and inverse
   double* tab = (double*)q;
   q += a16((size_t)NH * (NH + 1) * sizeof(double));
-  double* rowp = (double*)q;
-  q += a16((size_t)NH * sizeof(double));
   int32_t* piv = (int32_t*)q;
   int32_t* pinv = piv + NH;
 
@@ -643,7 +640,7 @@ __device__ __forceinline__ void reg_walk(const Pools& P, int gw, int wv, unsigne
     }
     if (do_refresh) {
       double lp, sg;
-      singular = reg_refresh_ap<NE_MAX, T>(z, posr, fs, ldf, ns, ne, lane, tab, rowp, piv, pinv,
+      singular = reg_refresh_ap<NE_MAX, T>(z, posr, fs, ldf, ns, ne, lane, tab, piv, pinv,
                                            lp, sg);
       last_logpf = lp;
       last_sgn = sg;
