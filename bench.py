@@ -7,7 +7,8 @@ after the last sweep, then the SR statistics, the S build, the Cholesky
 solve, the parameter update and the full double refresh of every walker.
 The headline runs every step in double precision (refresh every 4 sweeps,
 S on the FP64 matrix cores); the same steps in mixed precision
-(single-precision sweeps and O, double refresh every 32 proposals,
+(single-precision sweeps and O, double refresh after every 32 applied
+updates (accepted hops, the steps that change X^-1),
 split-bf16 S with FP32 accumulation, double solve) are reported beside it
 with the error of every mixed result against the double path.  Inputs are
 seeded and synthetic and resident in HBM before timing starts.
@@ -37,7 +38,8 @@ BF16_PEAK_TFLOPS = 2500.0
 METRIC = "walker hop-updates/s + SR S-build TFLOP/s, batched/mixed vs plain FP64"
 HEADLINE = "sq10_u8"
 FP64_REFRESH = 400      # proposals between double refreshes on the double path (4 sweeps)
-MIXED_REFRESH = 32      # proposals between double refreshes on the mixed path
+MIXED_REFRESH = 32      # applied updates between double refreshes on the mixed path
+MIXED_UNIT = "updates"  # what MIXED_REFRESH counts (accepted hops: the steps that change X^-1)
 KINDS = ["sweep", "refresh", "measure", "sr_stats", "s_build", "sr_solve"]
 # the dominant kernel of the headline step and the committed counter summary
 # of its HBM traffic (bench reports traffic = null once its sources change)
@@ -51,7 +53,7 @@ def log(msg):
 
 def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", sweep_threads=0,
                     use_graph=True, autotune=False, build_s=True, cg_tol=1e-10, cg_maxit=1000,
-                    schedule="buckets"):
+                    schedule="buckets", refresh_unit="proposals"):
     """Time whole SR steps of every instance of the workload.  With use_graph
     the sampling part of a step (the sweeps and the measurements) is captured
     once into a HIP graph and replayed; the SR build and update run eagerly.
@@ -72,7 +74,8 @@ def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", 
     with torch.cuda.stream(side):
         ctx = MVMC(insts, params, precision=precision, refresh_every=refresh_every,
                    seed=wl["sampler_seed"], n_slots=slots, solver=solver, build_s=build_s,
-                   sweep_threads=sweep_threads, stream=side, schedule=schedule)
+                   sweep_threads=sweep_threads, stream=side, schedule=schedule,
+                   refresh_unit=refresh_unit)
         for _ in range(wl["warmup"]):   # one launch per sweep, as in the timed steps
             ctx.sample_async(1)
         torch.cuda.synchronize()
@@ -268,7 +271,8 @@ def precision_errors():
     wl = workload(HEADLINE)
     inst = wl["instances"][0]
     kw = dict(seed=wl["sampler_seed"], n_slots=1, solver="chol", build_s=True)
-    m = MVMC([inst], inst.params0, precision="mixed", refresh_every=MIXED_REFRESH, **kw)
+    m = MVMC([inst], inst.params0, precision="mixed", refresh_every=MIXED_REFRESH,
+             refresh_unit=MIXED_UNIT, **kw)
     d = MVMC([inst], inst.params0, precision="fp64", refresh_every=FP64_REFRESH, **kw)
     m.sample(40)
     pos, cnt, emp = m.get_state(with_empty=True)
@@ -302,7 +306,8 @@ def precision_errors():
     m.close()
     d.close()
     # ratios over one sweep from identical states
-    m = MVMC([inst], inst.params0, precision="mixed", refresh_every=MIXED_REFRESH, **kw)
+    m = MVMC([inst], inst.params0, precision="mixed", refresh_every=MIXED_REFRESH,
+             refresh_unit=MIXED_UNIT, **kw)
     d = MVMC([inst], inst.params0, precision="fp64", refresh_every=FP64_REFRESH, **kw)
     m.sample(40)
     pos, cnt, emp = m.get_state(with_empty=True)
@@ -329,7 +334,8 @@ def precision_errors():
     for prec, R, seed in (("mixed", MIXED_REFRESH, 91), ("fp64", FP64_REFRESH, 92)):
         slots = 8
         c = MVMC([inst], inst.params0, precision=prec, refresh_every=R, seed=seed,
-                 n_slots=slots, solver="cg", build_s=False)
+                 n_slots=slots, solver="cg", build_s=False,
+                 refresh_unit=MIXED_UNIT if prec == "mixed" else "proposals")
         c.sample(40)
         for s in range(slots):
             c.sample_async(5)
@@ -357,7 +363,8 @@ def s_build_leg():
     wl = workload(HEADLINE)
     inst = wl["instances"][0]
     ctx = MVMC([inst], inst.params0, precision="mixed", refresh_every=MIXED_REFRESH,
-               seed=wl["sampler_seed"], n_slots=1, solver="cg", build_s=True)
+               seed=wl["sampler_seed"], n_slots=1, solver="cg", build_s=True,
+               refresh_unit=MIXED_UNIT)
     ctx.autotune(1)          # sweep variants, and arms the S tile tuner
     ctx.sample(2)
     ctx.measure(0)
@@ -426,7 +433,7 @@ def sq8_leg(steps):
     from mvmc_inputs import workload
     wl = workload("sq8_u4")
     r = run_sr_workload(wl, "fp64", steps, 1, wl["refresh_every"])
-    m = run_sr_workload(wl, "mixed", steps, 1, MIXED_REFRESH)
+    m = run_sr_workload(wl, "mixed", steps, 1, MIXED_REFRESH, refresh_unit=MIXED_UNIT)
     out = {"fp64": step_summary(r, 8, False), "mixed": step_summary(m, 4, True)}
     out["fp64"]["sweep_reg_alu"] = reg_sweep_roofline(r)
     out["mixed_speedup_vs_fp64"] = m["rate"] / r["rate"]
@@ -668,7 +675,7 @@ def batch_leg(steps):
     for sched in ("queue", "buckets"):
         log(f"[bench] batch32_ragged {sched}")
         r = run_sr_workload(wl, "mixed", steps, 1, wl["refresh_every"], use_graph=True,
-                            autotune=sched == "buckets", schedule=sched)
+                            autotune=sched == "buckets", schedule=sched, refresh_unit=MIXED_UNIT)
         leg = {"value": r["rate"], "unit": "hop-updates/s", "ms_per_step": r["ms_per_step"],
                "sweeps_per_step": r["sweeps"], "accept_ratio": r["accept_ratio"],
                "kernel_ms_per_step": km(r),
@@ -964,10 +971,11 @@ def main():
                            "note": "register-only loops on non-zero data, two wavefronts per "
                                    "SIMD (mvmc_peak_probe); datasheet peaks in roofline.peak"},
     }
-    log(f"[bench] {HEADLINE} mixed (refresh every {MIXED_REFRESH})")
+    log(f"[bench] {HEADLINE} mixed (refresh every {MIXED_REFRESH} {MIXED_UNIT})")
     mx = run_sr_workload(wl, "mixed", a.steps, a.warmup, MIXED_REFRESH,
-                         use_graph=not a.no_graph)
+                         use_graph=not a.no_graph, refresh_unit=MIXED_UNIT)
     out["mixed"] = step_summary(mx, 4, True)
+    out["mixed"]["refresh_every"] = {"n": MIXED_REFRESH, "unit": MIXED_UNIT}
     out["mixed"]["speedup_vs_fp64"] = mx["rate"] / r["rate"]
     out["mixed"]["s_build_speedup_vs_fp64"] = (head["s_build"]["ms"] /
                                                out["mixed"]["s_build"]["ms"])

@@ -105,8 +105,9 @@ typedef struct {
   int32_t precision;          /* MVMC_FP64: double sweeps and S.  MVMC_MIXED: single-
                                  precision sweeps/O, split-bf16 S with FP32 accumulation;
                                  inverse refresh and SR solve stay double */
-  int32_t refresh_every;      /* proposals between full double recomputations of X^-1
-                                 (0 = only at init, set_state and parameter updates) */
+  int32_t refresh_every;      /* proposals (or applied updates, see refresh_unit) between
+                                 full double recomputations of X^-1 (0 = only at init,
+                                 set_state and parameter updates) */
   uint64_t seed;              /* Philox4x32-10 key (proposal stream and initial draw) */
   int32_t n_instances;
   const mvmc_instance_desc *inst;
@@ -129,7 +130,18 @@ typedef struct {
                                  fits, else the anti-parallel-block sweep with 256 threads
                                  (variant 9, N_e <= 256), both refreshing inside the launch;
                                  sweep_variant may force 1 or 10, sweep_threads must be 0 */
+  int32_t refresh_unit;       /* MVMC_REFRESH_PROPOSALS: refresh_every counts proposals (the
+                                 walker's counter; bit-exact across get/set_state).
+                                 MVMC_REFRESH_UPDATES: it counts applied updates (accepted
+                                 hops and exchanges, the only steps that change X^-1), from
+                                 the context's creation; a state loaded into a new context
+                                 starts that count again.  A walker that reaches a multiple
+                                 stops for the refresh; a launch takes at most refresh_every
+                                 proposals per walker either way. */
 } mvmc_config;
+
+#define MVMC_REFRESH_PROPOSALS 0
+#define MVMC_REFRESH_UPDATES 1
 
 #define MVMC_SCHED_BUCKETS 0
 #define MVMC_SCHED_QUEUE 1

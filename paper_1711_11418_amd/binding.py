@@ -31,6 +31,7 @@ SWEEP_VARIANT_NAMES = ("reg", "lds64", "lds128", "lds256", "hbm64", "hbm128", "h
                        "ap64", "ap128", "ap256")
 PROJ_VARIANT = "proj"   # reported for instances with a quantum-number projection
 SCHEDULES = ("buckets", "queue")   # MVMC_SCHED_BUCKETS, MVMC_SCHED_QUEUE
+REFRESH_UNITS = ("proposals", "updates")   # MVMC_REFRESH_PROPOSALS, MVMC_REFRESH_UPDATES
 
 
 class InstanceDesc(C.Structure):
@@ -53,7 +54,7 @@ class Config(C.Structure):
         ("n_instances", C.c_int32), ("inst", C.POINTER(InstanceDesc)),
         ("n_slots", C.c_int32), ("solver", C.c_int32), ("build_s", C.c_int32),
         ("sweep_threads", C.c_int32), ("sweep_variant", C.c_int32),
-        ("exchange_per64", C.c_int32), ("schedule", C.c_int32),
+        ("exchange_per64", C.c_int32), ("schedule", C.c_int32), ("refresh_unit", C.c_int32),
     ]
 
 
@@ -189,10 +190,11 @@ class _Desc:
 
 def make_config(instances, precision="fp64", refresh_every=0, seed=1, n_slots=1, solver="chol",
                 build_s=True, sweep_threads=0, sweep_variant=None, exchange_per64=0,
-                schedule="buckets"):
+                schedule="buckets", refresh_unit="proposals"):
     """sweep_variant: None (automatic) or a name of SWEEP_VARIANT_NAMES forced for
     every instance.  schedule: "buckets" (one launch per variant bucket) or
-    "queue" (one persistent launch per call)."""
+    "queue" (one persistent launch per call).  refresh_unit: what refresh_every
+    counts, "proposals" or "updates" (accepted moves)."""
     descs = [_Desc(i) for i in instances]
     arr = (InstanceDesc * len(descs))(*[d.desc for d in descs])
     cfg = Config(MVMC_FP64 if precision == "fp64" else MVMC_MIXED, int(refresh_every),
@@ -200,7 +202,8 @@ def make_config(instances, precision="fp64", refresh_every=0, seed=1, n_slots=1,
                  MVMC_SOLVE_CHOL if solver == "chol" else MVMC_SOLVE_CG, int(bool(build_s)),
                  int(sweep_threads),
                  0 if sweep_variant is None else 1 + SWEEP_VARIANT_NAMES.index(sweep_variant),
-                 int(exchange_per64), SCHEDULES.index(schedule))
+                 int(exchange_per64), SCHEDULES.index(schedule),
+                 REFRESH_UNITS.index(refresh_unit))
     cfg._keep = (descs, arr)   # keep host arrays alive
     return cfg
 
@@ -229,11 +232,12 @@ class MVMC:
     def __init__(self, instances, params, *, precision="fp64", refresh_every=0, seed=1,
                  n_slots=1, solver="chol", build_s=True, sweep_threads=0, sweep_variant=None,
                  exchange_per64=0, schedule="buckets", device="cuda:0", stream=None,
-                 static_workspace=False):
+                 static_workspace=False, refresh_unit="proposals"):
         """stream: torch.cuda.Stream for all of the context's work (default: the
         current stream).  A non-default stream is needed for graph capture.
         static_workspace: take the workspace from the library's static device
-        array (mvmc_init_wavefunction_static) instead of allocating it."""
+        array (mvmc_init_wavefunction_static) instead of allocating it.
+        refresh_unit: what refresh_every counts, "proposals" or "updates"."""
         import torch
         self.torch = torch
         self.lib = load()
@@ -241,7 +245,8 @@ class MVMC:
         self.instances = list(instances)
         self.precision = precision
         self.cfg = make_config(self.instances, precision, refresh_every, seed, n_slots, solver,
-                               build_s, sweep_threads, sweep_variant, exchange_per64, schedule)
+                               build_s, sweep_threads, sweep_variant, exchange_per64, schedule,
+                               refresh_unit)
         self.sizes = query_sizes(self.cfg)
         self.layouts = [query_layout(self.cfg, k) for k in range(len(self.instances))]
         self.n_inst = len(self.instances)

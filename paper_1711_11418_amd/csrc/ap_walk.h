@@ -37,9 +37,10 @@
 // s = u^T M^-1, D the ratio.  Charges per site do not change, so the
 // Gutzwiller and Jastrow factors stay; four RBM visibles flip.
 //
-// The walker stops at every multiple of refresh_every and at a non-finite
-// ratio (guard word kGuardPending; a second one in a row, after the
-// double-precision refresh, gives kGuardFailed) and reports whether it
+// The walker stops at every multiple of refresh_every (of its proposal
+// counter, or of its applied-update counter when the pools say so) and at a
+// non-finite ratio (guard word kGuardPending; a second one in a row, after
+// the double-precision refresh, gives kGuardFailed) and reports whether it
 // stopped for a refresh.
 #pragma once
 
@@ -108,7 +109,7 @@ __device__ __forceinline__ void ap_matvec(const T* Mi, int ld, int n, const T* x
 }
 
 // The proposals of global walker gw up to target[gw], at most cap of them
-// and only up to the next multiple of R.  Every thread of the workgroup calls
+// and only up to the next multiple of R (proposals, or applied updates).  Every thread of the workgroup calls
 // it with the same gw; it contains workgroup barriers and returns the same
 // value in every thread: true when the walker stopped for a refresh (at a
 // multiple of R or at a non-finite ratio), when needs_refresh[gw] (if given)
@@ -126,12 +127,15 @@ __device__ __forceinline__ bool ap_walk(const Pools& P, int gw, unsigned char* s
   const uint64_t tg = target[gw];
   uint64_t todo = tg > n0 ? tg - n0 : 0;
   if (todo > (uint64_t)cap) todo = (uint64_t)cap;
-  if (R > 0) {
+  const bool by_upd = P.refresh_upd != 0;
+  if (R > 0 && !by_upd) {
     const uint64_t left = (uint64_t)R - n0 % (uint64_t)R;
     if (todo > left) todo = left;
   }
   if (todo == 0) return false;
   const int n_prop = (int)todo;
+  const uint64_t u0 = P.upd[gw];
+  bool due = false;   // the applied update that completes a multiple of R was made
   const InstDev& I = P.inst[P.walker_inst[gw]];
   const int ne = I.ne, ns = I.ns, n2 = 2 * ns, M = I.M, n = I.nup;
   const int64_t lw = gw - I.walker_off;
@@ -280,6 +284,7 @@ __device__ __forceinline__ bool ap_walk(const Pools& P, int gw, unsigned char* s
       }
       if (!accept) continue;
       ++acc;
+      due = by_upd && R > 0 && (u0 + (uint64_t)acc) % (uint64_t)R == 0;
       ap_matvec<T, NW, NT>(Mi, ld, n, uu, l1, part, false);   // s = u^T M^-1 (into l1)
       const double iD = 1.0 / D;
       for (int q2 = tid; q2 < n; q2 += NT) {
@@ -391,6 +396,7 @@ __device__ __forceinline__ bool ap_walk(const Pools& P, int gw, unsigned char* s
     }
     if (!accept) continue;
     ++acc;
+    due = by_upd && R > 0 && (u0 + (uint64_t)acc) % (uint64_t)R == 0;
     // the Jastrow-field change, requested now so its loads overlap the update
     // of M^-1 (V is symmetric: row site_new across the threads is coalesced)
     constexpr int kHv = 4;
@@ -454,6 +460,7 @@ __device__ __forceinline__ bool ap_walk(const Pools& P, int gw, unsigned char* s
       break;
     }
     ++it;
+    if (due) break;
   }
 
   __syncthreads();
@@ -468,9 +475,11 @@ __device__ __forceinline__ bool ap_walk(const Pools& P, int gw, unsigned char* s
   for (int l = tid; l < ns; l += NT) hg[l] = hs[l];
   for (int hh = tid; hh < M; hh += NT) thg[hh] = (double)ths[hh];
   const uint64_t n1 = n0 + (uint64_t)it;
-  const bool stop = (R > 0 && n1 % (uint64_t)R == 0) || guard1 == kGuardPending;
+  const bool stop = (R > 0 && (by_upd ? due : n1 % (uint64_t)R == 0)) ||
+                    guard1 == kGuardPending;
   if (tid == 0) {
     P.cnt[gw] = n1;
+    P.upd[gw] = u0 + (uint64_t)acc;
     P.accepted[gw] += acc;
     if (guard1 != guard0) P.guard[gw] = guard1;
     if (stop && needs_refresh) needs_refresh[gw] = 1;

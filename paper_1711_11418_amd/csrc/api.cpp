@@ -54,7 +54,7 @@ struct Plan {
   Pool inst_p, srinst_p, walker_inst, lists, A64, A32, V, fidx, vidx, G, U, gidx, nbr_ptr,
       nbr_site, nbr_t, fm_ptr, fm, gm_ptr, gm, vm_ptr, vm, rbm64, rbm32, rbmT64, rbmT32, Y, Y64,
       pos, empty, h,
-      theta, pmap, projw, pterm, cnt, target, needs_refresh, accepted, logpf, sgnpf, minpiv, status, guard, chk, lz,
+      theta, pmap, projw, pterm, cnt, upd, target, needs_refresh, accepted, logpf, sgnpf, minpiv, status, guard, chk, lz,
       dotpart,
       trace_base,
       obar, sdiag, x, r, p, w, t, shift, mask, scal, colpart, syrkpart, chol, split;
@@ -138,6 +138,8 @@ Err validate(const mvmc_config* c) {
   if (c->precision != MVMC_FP64 && c->precision != MVMC_MIXED)
     return fail(MVMC_E_ARG, "precision must be MVMC_FP64 or MVMC_MIXED");
   if (c->refresh_every < 0) return fail(MVMC_E_ARG, "refresh_every < 0");
+  if (c->refresh_unit != MVMC_REFRESH_PROPOSALS && c->refresh_unit != MVMC_REFRESH_UPDATES)
+    return fail(MVMC_E_ARG, "refresh_unit must be MVMC_REFRESH_PROPOSALS or MVMC_REFRESH_UPDATES");
   if (c->n_instances < 1 || !c->inst) return fail(MVMC_E_ARG, "need at least one instance");
   if (c->n_slots < 1) return fail(MVMC_E_ARG, "n_slots must be >= 1");
   if (c->solver != MVMC_SOLVE_CHOL && c->solver != MVMC_SOLVE_CG)
@@ -515,6 +517,7 @@ Plan make_plan(const mvmc_config& c) {
   take(P.projw, 8 * (size_t)off_projw);
   take(P.pterm, 8 * (size_t)off_pterm);
   take(P.cnt, 8 * W);
+  take(P.upd, 8 * W);
   take(P.target, 8 * W);
   take(P.needs_refresh, 4 * W);
   take(P.accepted, 8 * W);
@@ -1058,12 +1061,14 @@ int init_impl(mvmc_ctx** out, const mvmc_config* cfg, void* d_ws, size_t ws_byte
   Q.h = at<double>(b, P.h);
   Q.theta = at<double>(b, P.theta);
   Q.cnt = at<uint64_t>(b, P.cnt);
+  Q.upd = at<uint64_t>(b, P.upd);
   Q.accepted = at<int64_t>(b, P.accepted);
   Q.logpf = at<double>(b, P.logpf);
   Q.sgnpf = at<double>(b, P.sgnpf);
   Q.minpiv = at<double>(b, P.minpiv);
   Q.status = at<int32_t>(b, P.status);
   Q.guard = at<int32_t>(b, P.guard);
+  Q.refresh_upd = c->cfg.refresh_unit == MVMC_REFRESH_UPDATES ? 1 : 0;
   Q.pmap = at<int32_t>(b, P.pmap);
   Q.projw = at<double>(b, P.projw);
   Q.pterm = at<double>(b, P.pterm);
@@ -1143,6 +1148,7 @@ int init_impl(mvmc_ctx** out, const mvmc_config* cfg, void* d_ws, size_t ws_byte
   chk(up(P.pmap, pmap.data(), 4 * pmap.size()));
   chk(up(P.projw, projw.data(), 8 * projw.size()));
   chk(hipMemset(Q.cnt, 0, 8 * P.W));
+  chk(hipMemset(Q.upd, 0, 8 * P.W));
   chk(hipMemset(Q.accepted, 0, 8 * P.W));
   chk(hipMemset(Q.guard, 0, 4 * P.W));
   chk(hipMemset(b + P.needs_refresh.off, 0, 4 * P.W));
@@ -1339,8 +1345,15 @@ int run_sweeps(mvmc_ctx* c, int32_t n_sweeps, std::vector<double>* inst_ms) {
       lds_refresh = true;
       // enough refresh-aligned rounds for any starting phase (an extra round
       // is an empty launch); independent of the host's view of the counters,
-      // so a captured graph stays valid on replay
-      if (R > 0) rounds = std::max<int>(rounds, (int)((tot + R - 1) / R) + 1);
+      // so a captured graph stays valid on replay.  Counting applied updates,
+      // a launch ends a walker's run at R proposals (at most tot / R times) or
+      // at a multiple of R updates (at most tot / R + 1 times).
+      if (R > 0) {
+        const int64_t per = (tot + R - 1) / R;
+        rounds = std::max<int>(rounds, (int)(c->cfg.refresh_unit == MVMC_REFRESH_UPDATES
+                                                 ? 2 * per + 2
+                                                 : per + 1));
+      }
     }
   }
   // one more round for LDS-tier walkers stopped by a non-finite ratio: the

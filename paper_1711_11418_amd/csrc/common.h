@@ -80,6 +80,7 @@ struct Pools {
   double* h;
   double* theta;
   uint64_t* cnt;                   // Philox proposal counter per walker
+  uint64_t* upd;                   // applied updates per walker since the context's creation
   int64_t* accepted;
   double* logpf;
   double* sgnpf;
@@ -92,6 +93,9 @@ struct Pools {
   int32_t* pmap;                   // projection site maps and their inverses
   double* projw;                   // projection weights
   double* pterm;                   // per-term log|det M_p| and sign of projected walkers
+  // refresh_every counts applied updates (1) or proposals (0)
+  int32_t refresh_upd;
+  int32_t pad_pools;
 };
 
 enum : int32_t { kGuardClear = 0, kGuardPending = 1, kGuardFailed = 2 };

@@ -269,7 +269,8 @@ template <> __device__ __forceinline__ const float* pj_rbm<float>(const Pools& P
 
 // One workgroup per walker; wavefront w carries terms w, w + 4, ...  The
 // proposal draw and stopping rule are those of the unprojected sweeps (the
-// same Philox stream, refresh at every multiple of R, non-finite guard).
+// same Philox stream, refresh at every multiple of R proposals or applied
+// updates, non-finite guard).
 template <typename T>
 __global__ __launch_bounds__(kProjThreads) void k_sweep_proj(
     Pools P, const int32_t* __restrict__ wlist, int cap, uint64_t seed, TraceRec* trace,
@@ -283,11 +284,14 @@ __global__ __launch_bounds__(kProjThreads) void k_sweep_proj(
   const uint64_t tg = target[gw];
   uint64_t todo = tg > n0 ? tg - n0 : 0;
   if (todo > (uint64_t)cap) todo = (uint64_t)cap;
-  if (R > 0) {
+  const bool by_upd = P.refresh_upd != 0;
+  if (R > 0 && !by_upd) {
     const uint64_t left = (uint64_t)R - n0 % (uint64_t)R;
     if (todo > left) todo = left;
   }
   if (todo == 0) return;
+  const uint64_t u0 = P.upd[gw];
+  bool due = false;   // the applied update that completes a multiple of R was made
   const int n_prop = (int)todo;
   const InstDev& I = P.inst[P.walker_inst[gw]];
   const int ne = I.ne, ns = I.ns, n2 = 2 * ns, M = I.M, n = I.nup, np = I.nproj;
@@ -470,6 +474,7 @@ __global__ __launch_bounds__(kProjThreads) void k_sweep_proj(
       }
       if (!accept) continue;
       ++acc;
+      due = by_upd && R > 0 && (u0 + (uint64_t)acc) % (uint64_t)R == 0;
       // v_p = m'_p^T M_p^-1 - e_a (up) or t_p = M_p^-1 m'_p - e_a (down)
       for (int p = wid; p < np; p += kProjWaves) {
         const T* Mp = Mi + (size_t)p * n * ld;
@@ -520,6 +525,7 @@ __global__ __launch_bounds__(kProjThreads) void k_sweep_proj(
       break;
     }
     ++it;
+    if (due) break;
   }
 
   __syncthreads();
@@ -536,7 +542,8 @@ __global__ __launch_bounds__(kProjThreads) void k_sweep_proj(
     ltg[np + p] = sg[p];
   }
   const uint64_t n1 = n0 + (uint64_t)it;
-  const bool stop = (R > 0 && n1 % (uint64_t)R == 0) || guard1 == kGuardPending;
+  const bool stop = (R > 0 && (by_upd ? due : n1 % (uint64_t)R == 0)) ||
+                    guard1 == kGuardPending;
   if (tid == 0) {
     double lmax = -INFINITY;
     for (int p = 0; p < np; ++p)
@@ -547,6 +554,7 @@ __global__ __launch_bounds__(kProjThreads) void k_sweep_proj(
     P.logpf[gw] = lmax + log(fabs(tot));
     P.sgnpf[gw] = tot > 0.0 ? 1.0 : (tot < 0.0 ? -1.0 : 0.0);
     P.cnt[gw] = n1;
+    P.upd[gw] = u0 + (uint64_t)acc;
     P.accepted[gw] += acc;
     if (guard1 != guard0) P.guard[gw] = guard1;
     if (stop && needs_refresh) needs_refresh[gw] = 1;

@@ -56,8 +56,9 @@ size_t sweep_lds_bytes(int ne, int ns, int M, bool lds, size_t tsize, int nthrea
 }
 
 // Each walker runs proposals up to its target counter, at most `cap` per
-// launch and never past a multiple of refresh_every (R > 0): a walker whose
-// counter lands on such a multiple raises its refresh flag.
+// launch and never past a multiple of refresh_every (R > 0) of its proposal
+// counter, or of its applied-update counter when the pools say so: a walker
+// that reaches such a multiple raises its refresh flag.
 template <typename T, bool LDS, int NT>
 __global__ __launch_bounds__(NT) void k_sweep(Pools P, const int32_t* __restrict__ wlist,
                                               int cap, uint64_t seed, TraceRec* trace,
@@ -74,12 +75,16 @@ __global__ __launch_bounds__(NT) void k_sweep(Pools P, const int32_t* __restrict
   const uint64_t tg = target[gw];
   uint64_t todo = tg > n0 ? tg - n0 : 0;
   if (todo > (uint64_t)cap) todo = (uint64_t)cap;
-  if (R > 0) {
+  const bool by_upd = P.refresh_upd != 0;
+  if (R > 0 && !by_upd) {
     const uint64_t left = (uint64_t)R - n0 % (uint64_t)R;
     if (todo > left) todo = left;
   }
   if (todo == 0) return;
   const int n_prop = (int)todo;
+  const uint64_t u0 = P.upd[gw];
+  const uint64_t R_upd = by_upd && R > 0 ? (uint64_t)R : 0;   // R is the ratio inside the loop
+  bool due = false;   // the applied update that completes a multiple of R was made
   const InstDev& I = P.inst[P.walker_inst[gw]];
   const int ne = I.ne, ns = I.ns, n2 = 2 * ns, M = I.M, nup = I.nup;
   const int64_t lw = gw - I.walker_off;
@@ -258,6 +263,11 @@ __global__ __launch_bounds__(NT) void k_sweep(Pools P, const int32_t* __restrict
       emp[sigma * ns + k] = site_old;
     }
     __syncthreads();
+    if (R_upd && (u0 + (uint64_t)acc) % R_upd == 0) {   // uniform
+      due = true;
+      n_done = it + 1;
+      break;
+    }
   }
 
   __syncthreads();
@@ -270,9 +280,11 @@ __global__ __launch_bounds__(NT) void k_sweep(Pools P, const int32_t* __restrict
   if (tid == 0) {
     const uint64_t n1 = n0 + (uint64_t)n_done;
     P.cnt[gw] = n1;
+    P.upd[gw] = u0 + (uint64_t)acc;
     P.accepted[gw] += acc;
     if (guard1 != guard0) P.guard[gw] = guard1;
-    if ((R > 0 && n1 % (uint64_t)R == 0) || guard1 == kGuardPending) needs_refresh[gw] = 1;
+    if ((R > 0 && (by_upd ? due : n1 % (uint64_t)R == 0)) || guard1 == kGuardPending)
+      needs_refresh[gw] = 1;
   }
 }
 

@@ -346,7 +346,10 @@ __device__ __forceinline__ void reg_walk(const Pools& P, int gw, int wv, unsigne
   bool refreshed = false;
   const double* rbT64 = P.rbmT64;
 
-  int to_refresh = R > 0 ? R - (int)(n0 % (uint64_t)R) : 0;   // proposals until the next refresh
+  // proposals (or applied updates) until the next refresh
+  const bool by_upd = P.refresh_upd != 0;
+  const uint64_t u0 = P.upd[gw];
+  int to_refresh = R > 0 ? R - (int)((by_upd ? u0 : n0) % (uint64_t)R) : 0;
   // Philox words of the next 64 proposals, one proposal per lane: the vector
   // unit evaluates them together and each proposal reads its four words back
   uint32_t d0 = 0, d1 = 0, d2 = 0, d3 = 0;
@@ -358,6 +361,7 @@ __device__ __forceinline__ void reg_walk(const Pools& P, int gw, int wv, unsigne
   int batch = -1;
   while (it < n_prop) {
     const uint64_t n = n0 + (uint64_t)it;
+    const int64_t acc_before = acc;
     const int rs = it & 63;
     if ((it >> 6) != batch) {
       batch = it >> 6;
@@ -632,10 +636,14 @@ __device__ __forceinline__ void reg_walk(const Pools& P, int gw, int wv, unsigne
     } else {
       tripped = false;
       ++it;
-      if (R > 0 && --to_refresh == 0) to_refresh = R;
+      bool wrapped = false;
+      if (R > 0 && (!by_upd || acc != acc_before) && --to_refresh == 0) {
+        to_refresh = R;
+        wrapped = true;
+      }
 #if MVMC_SWEEP_INKERNEL_REFRESH
       // periodic double-precision recomputation, inside the launch
-      do_refresh = kref && R > 0 && to_refresh == R;
+      do_refresh = kref && wrapped;
 #endif
     }
     if (do_refresh) {
@@ -682,6 +690,7 @@ __device__ __forceinline__ void reg_walk(const Pools& P, int gw, int wv, unsigne
   if (lane == 0) {
     const uint64_t n1 = n0 + (uint64_t)it;
     P.cnt[gw] = n1;
+    P.upd[gw] = u0 + (uint64_t)acc;
     P.accepted[gw] += acc;
     if (failed) P.guard[gw] = kGuardFailed;
     if (R > 0 && !kref && n1 % (uint64_t)R == 0) needs_refresh[gw] = 1;

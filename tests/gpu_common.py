@@ -145,7 +145,7 @@ U32 = 2.0 ** -24   # unit roundoff of binary32
 
 
 def mixed_ratio_stats(inst, m, rec, walkers, pos0, n_prop: int, seed: int, refresh_every: int,
-                      safety: float = 2.0) -> dict:
+                      safety: float = 2.0, refresh_unit: str = "proposals") -> dict:
     """Single-precision ratios against the oracle, proposal by proposal, with
     a first-order forward error bound carried along the oracle's chain.
 
@@ -170,7 +170,13 @@ def mixed_ratio_stats(inst, m, rec, walkers, pos0, n_prop: int, seed: int, refre
     terms), and each angle drifts by u(|theta_h| + 2|d_h|).  The test bar is
     |R_gpu - R| <= safety * bound (first order: second-order terms are
     neglected).  A differing decision is allowed only when u lies within the
-    bound of R^2; that chain is then no longer compared."""
+    bound of R^2; that chain is then no longer compared.
+
+    The bound restarts at every double refresh: before proposal n when n is
+    a multiple of refresh_every (refresh_unit "proposals"), or right after
+    the accepted proposal that makes the walker's count of applied updates
+    a multiple of it ("updates"; counted from the first traced proposal,
+    which must be the context's first)."""
     from oracle.philox import proposal_draw, uniform53
     A = wf.skew_table(m)
     ns = m.n_sites
@@ -186,13 +192,21 @@ def mixed_ratio_stats(inst, m, rec, walkers, pos0, n_prop: int, seed: int, refre
         e = 0.0
         dth = np.zeros(m.n_hidden)
         k_acc = 0
+        n_upd = 0              # applied updates so far (refresh_unit "updates")
+        upd_refresh = False    # the last one completed a multiple of refresh_every
         for k in range(n_prop):
             n, a, inew, R, acc, b = wk.trace[k]
             g = rec[w, k]
             assert int(g["n"]) == n and int(g["a"]) == a and int(g["i_new"]) == inew, (w, k)
             nv = wf.occupations(m, pos)
             theta = m.b + m.W @ (2.0 * nv - 1.0) if m.n_hidden else np.zeros(0)
-            if k == 0 or (refresh_every and n % refresh_every == 0):
+            if refresh_unit == "updates":
+                assert k > 0 or n == 0, "update counting needs the trace from the start"
+                refreshed = k == 0 or upd_refresh
+            else:
+                refreshed = k == 0 or (refresh_every and n % refresh_every == 0)
+            upd_refresh = False
+            if refreshed:
                 e = U32 * np.linalg.norm(Y)
                 dth = U32 * np.abs(theta)
                 k_acc = 0
@@ -242,6 +256,8 @@ def mixed_ratio_stats(inst, m, rec, walkers, pos0, n_prop: int, seed: int, refre
                 if m.n_hidden:
                     dth = dth + U32 * (np.abs(theta) + 2 * np.abs(d))
                 k_acc += 1
+                n_upd += 1
+                upd_refresh = bool(refresh_every) and n_upd % refresh_every == 0
     rel = np.array(rel)
     over = np.array(over)
     ks = np.array(ks)

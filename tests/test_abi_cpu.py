@@ -83,6 +83,24 @@ def test_cholesky_requires_explicit_s():
         b.query_sizes(cfg)
 
 
+def test_refresh_unit_is_checked():
+    """refresh_every counts proposals (0) or applied updates (1); any other
+    unit is an argument error, and the update count adds one counter per
+    walker to the workspace."""
+    b = _lib()
+    inst = workload("ring6")["instances"][0]
+    sizes = {}
+    for unit in ("proposals", "updates"):
+        cfg = b.make_config([inst], "mixed", 32, 1, refresh_unit=unit)
+        sizes[unit] = b.query_sizes(cfg).workspace_bytes
+    assert sizes["proposals"] == sizes["updates"]
+    cfg = b.make_config([inst], "mixed", 32, 1)
+    cfg.refresh_unit = 2
+    with pytest.raises(b.MVMCError) as e:
+        b.query_sizes(cfg)
+    assert e.value.status == 1
+
+
 @pytest.mark.parametrize("kw", [dict(sweep_threads=64), dict(sweep_variant="lds64"),
                                 dict(sweep_variant="ap128")])
 def test_queue_schedule_rejects_other_variants(kw):

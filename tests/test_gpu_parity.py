@@ -76,14 +76,21 @@ def test_refresh_inverse_and_pfaffian(name):
     ("ring6_rbm", 20, 5, 0), ("sq8_half", 3, 0, 0), ("sq8_half", 3, 64, 0),
     ("sq4_sub2", 10, 0, 64), ("sq8_half", 3, 0, 128), ("ring6_rbm", 20, 5, 256),
     ("sq10_full", 2, 0, 0), ("sq6_rbm", 4, 16, 0), ("sq12_sub", 1, 50, 0),
+    # refresh_every counting applied updates: register tier (refresh inside
+    # the launch), anti-parallel block (stops at every 3rd update), full X^-1
+    ("sq4_sub2", 10, "3u", 0), ("sq10_full", 2, "3u", 0), ("sq8_half", 3, "2u", 128),
+    ("sq12_sub", 1, "5u", 0),
 ])
 def test_trajectory_replay_fp64(name, sweeps, refresh, threads):
     inst = _case(name)
     pos0 = good_configs(inst, inst.params0, inst.n_walkers, 7)
     n_prop = sweeps * inst.n_elec
+    unit = "updates" if isinstance(refresh, str) else "proposals"
+    refresh = int(str(refresh).rstrip("u"))
     log(f"[replay] {name}: Ne={inst.n_elec} W={inst.n_walkers} proposals={n_prop} "
-        f"refresh_every={refresh} sweep_threads={threads} seed={SEED}")
-    ctx = _ctx([inst], inst.params0, seed=SEED, refresh_every=refresh, sweep_threads=threads)
+        f"refresh_every={refresh} ({unit}) sweep_threads={threads} seed={SEED}")
+    ctx = _ctx([inst], inst.params0, seed=SEED, refresh_every=refresh, sweep_threads=threads,
+               refresh_unit=unit)
     ctx.set_state(pos0.ravel(), np.zeros(inst.n_walkers, dtype=np.int64))
     ctx.enable_trace(n_prop)
     acc = ctx.sample(sweeps)
@@ -186,23 +193,29 @@ def test_sr_matrices_and_update(name, solver):
 
 
 # ------------------------------------------------------------ mixed precision
-@pytest.mark.parametrize("name,sweeps", [("sq4_sub2", 10), ("sq10_full", 2), ("sq6_rbm", 4)])
-def test_mixed_precision_ratios(name, sweeps):
-    """Single-precision sweeps with the double refresh every 32 proposals:
-    every ratio against the first-order rounding bound carried along the
-    oracle chain (gpu_common.mixed_ratio_stats), and the typical relative
+@pytest.mark.parametrize("name,sweeps,unit", [
+    ("sq4_sub2", 10, "proposals"), ("sq10_full", 2, "proposals"), ("sq6_rbm", 4, "proposals"),
+    ("sq4_sub2", 10, "updates"), ("sq10_full", 4, "updates"), ("sq6_rbm", 4, "updates")])
+def test_mixed_precision_ratios(name, sweeps, unit):
+    """Single-precision sweeps with the double refresh every 32 proposals or
+    every 32 applied updates: every ratio against the first-order rounding
+    bound carried along the oracle chain (gpu_common.mixed_ratio_stats,
+    which resets the bound at the same points), and the typical relative
     error at the single-precision level."""
     inst = _case(name)
     pos0 = good_configs(inst, inst.params0, inst.n_walkers, 9, cond_max=1e4)
     n_prop = sweeps * inst.n_elec
-    log(f"[mixed] {name}: Ne={inst.n_elec} W={inst.n_walkers} proposals={n_prop} refresh 32")
-    ctx = _ctx([inst], inst.params0, seed=SEED, precision="mixed", refresh_every=32)
+    log(f"[mixed] {name}: Ne={inst.n_elec} W={inst.n_walkers} proposals={n_prop} "
+        f"refresh 32 {unit}")
+    ctx = _ctx([inst], inst.params0, seed=SEED, precision="mixed", refresh_every=32,
+               refresh_unit=unit)
     ctx.set_state(pos0.ravel(), np.zeros(inst.n_walkers, dtype=np.int64))
     ctx.enable_trace(n_prop)
     ctx.sample(sweeps)
     rec = ctx.trace_records()
     walkers, m = oracle_trajectories(inst, inst.params0, pos0, 0, n_prop, SEED)
-    st = mixed_ratio_stats(inst, m, rec, walkers, pos0, n_prop, SEED, refresh_every=32)
+    st = mixed_ratio_stats(inst, m, rec, walkers, pos0, n_prop, SEED, refresh_every=32,
+                           refresh_unit=unit)
     log(f"  mixed: {st['summary']}")
     assert st["within_bound"], st["summary"]
     assert st["compared"] > 0.5 * n_prop * inst.n_walkers

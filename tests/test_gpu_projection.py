@@ -118,6 +118,7 @@ def test_refresh_terms_match_oracle(name):
 @pytest.mark.parametrize("name,sweeps,refresh", [
     ("ring4_proj", 30, 0), ("ring4_projpi", 30, 7), ("ring6_proj3", 20, 0),
     ("sq4_sub2_proj4", 6, 16), ("ring8_proj8_rbm", 10, 5), ("sq12_proj2", 1, 40),
+    ("sq4_sub2_proj4", 6, "3u"),   # refresh after every 3rd applied update
 ])
 def test_trajectory_replay_fp64(name, sweeps, refresh):
     """Every proposal's ratio and decision against the oracle chain (ratios
@@ -129,9 +130,11 @@ def test_trajectory_replay_fp64(name, sweeps, refresh):
     n_p, n = len(inst.proj_w), inst.n_up
     pos0 = good_proj_configs(inst, inst.n_walkers, 7)
     n_prop = sweeps * inst.n_elec
+    unit = "updates" if isinstance(refresh, str) else "proposals"
+    refresh = int(str(refresh).rstrip("u"))
     log(f"[proj replay] {name}: Ne={inst.n_elec} N_P={n_p} W={inst.n_walkers} "
-        f"proposals={n_prop} refresh_every={refresh} seed={SEED}")
-    ctx = MVMC([inst], inst.params0, seed=SEED, refresh_every=refresh)
+        f"proposals={n_prop} refresh_every={refresh} ({unit}) seed={SEED}")
+    ctx = MVMC([inst], inst.params0, seed=SEED, refresh_every=refresh, refresh_unit=unit)
     ctx.set_state(pos0.ravel(), np.zeros(inst.n_walkers, dtype=np.int64))
     ctx.enable_trace(n_prop)
     acc = ctx.sample(sweeps)
