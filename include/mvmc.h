@@ -136,8 +136,9 @@ typedef struct {
                                  hops and exchanges, the only steps that change X^-1), from
                                  the context's creation; a state loaded into a new context
                                  starts that count again.  A walker that reaches a multiple
-                                 stops for the refresh; a launch takes at most refresh_every
-                                 proposals per walker either way. */
+                                 stops for the refresh (bucket schedule: a launch takes at
+                                 most refresh_every proposals per walker, 8 refresh_every in
+                                 the update unit). */
 } mvmc_config;
 
 #define MVMC_REFRESH_PROPOSALS 0

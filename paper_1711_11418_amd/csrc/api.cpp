@@ -1302,6 +1302,13 @@ int mvmc_refresh(mvmc_ctx* c) {
 }  // extern "C"
 
 namespace {
+// Twice the launch cap over R in the update unit: a run then ends mostly at
+// a refresh point (a walker makes about R / acceptance proposals between
+// them), so few launches end short of one.  At 10 x 10, R = 32, acceptance
+// 0.2, 8 R took the mixed sampling from 15.9 ms (cap R) to 12.4 ms per 10
+// sweeps; an unbounded cap measured 12.8 ms.
+constexpr int kUpdCapX2 = 16;
+
 // The sweeps of one call.  Register-tier walkers refresh inside the sweep
 // kernel; LDS-tier walkers stop at every multiple of refresh_every and are
 // refreshed between launches.  With inst_ms, every bucket launch is
@@ -1335,6 +1342,12 @@ int run_sweeps(mvmc_ctx* c, int32_t n_sweeps, std::vector<double>* inst_ms) {
       c->cnt_host[k] += (uint64_t)n_sweeps * P.inst[k].ne;
     return MVMC_OK;
   }
+  // proposals per walker and launch: R, or kUpdCapX2 * R / 2 when R counts
+  // applied updates (fewer rounds; a launch's length is then set by its
+  // longest run)
+  const bool by_upd = c->cfg.refresh_unit == MVMC_REFRESH_UPDATES;
+  const int64_t cap = R > 0 ? (by_upd ? std::max<int64_t>(1, (int64_t)R * kUpdCapX2 / 2) : R)
+                            : (int64_t)1 << 62;
   int rounds = 1;
   bool lds_refresh = false;
   std::vector<uint64_t> target(c->cfg.n_instances);
@@ -1346,20 +1359,18 @@ int run_sweeps(mvmc_ctx* c, int32_t n_sweeps, std::vector<double>* inst_ms) {
       // enough refresh-aligned rounds for any starting phase (an extra round
       // is an empty launch); independent of the host's view of the counters,
       // so a captured graph stays valid on replay.  Counting applied updates,
-      // a launch ends a walker's run at R proposals (at most tot / R times) or
-      // at a multiple of R updates (at most tot / R + 1 times).
+      // a launch ends a walker's run at cap proposals (at most tot / cap
+      // times) or at a multiple of R updates (at most ceil(tot / R) times).
       if (R > 0) {
         const int64_t per = (tot + R - 1) / R;
-        rounds = std::max<int>(rounds, (int)(c->cfg.refresh_unit == MVMC_REFRESH_UPDATES
-                                                 ? 2 * per + 2
-                                                 : per + 1));
+        rounds = std::max<int>(
+            rounds, (int)(by_upd ? per + (int64_t)tot / cap + 2 : per + 1));
       }
     }
   }
   // one more round for LDS-tier walkers stopped by a non-finite ratio: the
   // refresh between rounds recomputes them and the last launch retries
   if (lds_refresh && n_sweeps > 0) ++rounds;
-  const int64_t cap = R > 0 ? R : (int64_t)1 << 62;
   uint64_t* tgt = reinterpret_cast<uint64_t*>(c->ws + P.target.off);
   int32_t* nr = reinterpret_cast<int32_t*>(c->ws + P.needs_refresh.off);
   // per-walker end counters on the device: the call enqueues only kernels
