@@ -288,12 +288,15 @@ void set_variant(Plan& P, int k, int v) {
   I.sweep_lds = v >= 1 && v <= 3;
 }
 // Default: the register tier where it fits, else the anti-parallel-block
-// kernel (threads by the block side n), else the full-X^-1 kernel from HBM.
+// kernel (threads by the block side n; one wavefront up to n = 64 in single
+// precision, measured at 10 x 10: 9.5 ms against 10.1 ms with two for 10
+// sweeps, while double precision prefers two: 11.2 against 12.3 ms), else
+// the full-X^-1 kernel from HBM.
 int default_variant(const Plan& P, int k) {
   if (variant_fits(P, k, 0)) return 0;
   if (P.queue) return variant_fits(P, k, 9) ? 9 : -1;
   const int n = P.inst[k].ne / 2;
-  const int v = 7 + (n <= 48 ? 0 : (n <= 96 ? 1 : 2));
+  const int v = 7 + (n <= (P.tsize == 4 ? 64 : 48) ? 0 : (n <= 96 ? 1 : 2));
   if (variant_fits(P, k, v)) return v;
   return P.exchange ? -1 : 6;
 }
