@@ -134,7 +134,7 @@ typedef struct {
                                  walker's counter; bit-exact across get/set_state).
                                  MVMC_REFRESH_UPDATES: it counts applied updates (accepted
                                  hops and exchanges, the only steps that change X^-1), from
-                                 the context's creation; a state loaded into a new context
+                                 the context's creation or the last mvmc_set_state, which
                                  starts that count again.  A walker that reaches a multiple
                                  stops for the refresh (bucket schedule: a launch takes at
                                  most refresh_every proposals per walker, 8 refresh_every in

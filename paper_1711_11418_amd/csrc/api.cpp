@@ -2033,6 +2033,9 @@ int mvmc_set_state(mvmc_ctx* c, const int16_t* d_pos, const uint64_t* d_counter,
   launch_pos_widen(d_pos, c->P.pos, npos, c->stream);
   LAUNCHCHK(c);
   HIPCHK(c, hipMemcpyAsync(c->P.cnt, d_counter, 8 * P.W, hipMemcpyDeviceToDevice, c->stream));
+  // the count of applied updates restarts with the loaded state (refresh
+  // points in the update unit then follow from the state alone)
+  HIPCHK(c, hipMemsetAsync(c->P.upd, 0, 8 * P.W, c->stream));
   if (d_empty)
     launch_pos_widen(d_empty, c->P.empty, nemp, c->stream);
   else

@@ -176,7 +176,7 @@ def mixed_ratio_stats(inst, m, rec, walkers, pos0, n_prop: int, seed: int, refre
     a multiple of refresh_every (refresh_unit "proposals"), or right after
     the accepted proposal that makes the walker's count of applied updates
     a multiple of it ("updates"; counted from the first traced proposal,
-    which must be the context's first)."""
+    which must be the first after set_state or the context's creation)."""
     from oracle.philox import proposal_draw, uniform53
     A = wf.skew_table(m)
     ns = m.n_sites
