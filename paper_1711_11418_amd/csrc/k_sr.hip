@@ -683,7 +683,8 @@ __global__ __launch_bounds__(256) void k_chol_column(SrArgs A, int kb, int kb0) 
 
 // Trailing update of outer step ob: the lower triangle of the rows and
 // columns past the outer panel [o, o + kOuter) less L[:, panel] L[:, panel]^T,
-// on the FP64 matrix cores (v_mfma_f64_16x16x4f64).  A workgroup of four
+// on the FP64 matrix cores (v_mfma_f64_16x16x4f64), accumulated onto the
+// tile's values loaded at the start.  A workgroup of four
 // wavefronts owns a 128 x 128 tile, each wavefront a 64 x 64 quadrant as
 // 4 x 4 blocks of 16 x 16 accumulators.  The panel's columns pass through
 // LDS k-major (each MFMA operand is 16 consecutive doubles of one column),
@@ -733,16 +734,26 @@ __global__ __launch_bounds__(256, 2) void k_chol_trail(SrArgs A, int ob) {
       Bs[st][lk + e][lr] = gb[e];
     }
   };
+  const int ka = lane >> 4, ma = lane & 15;   // operand element: k row, row within the block
+  // the accumulators start from the tile's current values (element r of lane
+  // l is D[l / 16 + 4 r][l % 16] of its 16 x 16 block) and take the panel's
+  // products with one operand negated, so the tile is written once at the
+  // end and never read there
   f64x4 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = r0 + 64 * qi + 16 * i + ka + 4 * r;
+        const int64_t col = c0 + 64 * qj + 16 * j + ma;
+        acc[i][j][r] = (row < I.np && col < I.np) ? F[row * I.np + col] : 0.0;
+      }
   gload(0);
   lstore(0);
   __syncthreads();
   int st = 0;
-  const int ka = lane >> 4, ma = lane & 15;   // operand element: k row, row within the block
   for (int k0 = 0; k0 < kOuter; k0 += kUK) {
     const bool more = k0 + kUK < kOuter;
     if (more) gload(k0 + kUK);
@@ -751,7 +762,7 @@ __global__ __launch_bounds__(256, 2) void k_chol_trail(SrArgs A, int ob) {
       double a[4], b[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        a[i] = As[st][kk + ka][64 * qi + 16 * i + ma];
+        a[i] = -As[st][kk + ka][64 * qi + 16 * i + ma];
         b[i] = Bs[st][kk + ka][64 * qj + 16 * i + ma];
       }
 #pragma unroll
@@ -773,7 +784,7 @@ __global__ __launch_bounds__(256, 2) void k_chol_trail(SrArgs A, int ob) {
       for (int r = 0; r < 4; ++r) {
         const int64_t row = r0 + 64 * qi + 16 * i + ka + 4 * r;
         const int64_t col = c0 + 64 * qj + 16 * j + ma;
-        if (row < I.np && col < I.np && (ti != tj || col <= row)) F[row * I.np + col] -= acc[i][j][r];
+        if (row < I.np && col < I.np && (ti != tj || col <= row)) F[row * I.np + col] = acc[i][j][r];
       }
 }
 
