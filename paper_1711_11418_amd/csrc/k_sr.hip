@@ -685,23 +685,29 @@ __global__ __launch_bounds__(256) void k_chol_column(SrArgs A, int kb, int kb0) 
 // columns past the outer panel [o, o + kOuter) less L[:, panel] L[:, panel]^T,
 // on the FP64 matrix cores (v_mfma_f64_16x16x4f64), accumulated onto the
 // tile's values loaded at the start.  A workgroup of four
-// wavefronts owns a 128 x 128 tile, each wavefront a 64 x 64 quadrant as
-// 4 x 4 blocks of 16 x 16 accumulators.  The panel's columns pass through
+// wavefronts owns a UT x UT tile, each wavefront a UT/2 x UT/2 quadrant of
+// 16 x 16 accumulator blocks.  The panel's columns pass through
 // LDS k-major (each MFMA operand is 16 consecutive doubles of one column),
 // 16 at a time, double-buffered; rows past the matrix read the last row.
 // Two workgroups share a compute unit (two wavefronts per SIMD), which the
 // FP64 matrix unit needs to stay busy.
 constexpr int kOuter = 4 * kNb;   // outer panel width
-constexpr int kUT = 128;          // trailing-update tile
 constexpr int kUK = 16;           // panel columns per LDS stage
-constexpr int kUP = kUT + 2;      // padded LDS row (spreads the four k rows of an operand over the banks)
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
+// UT: tile side, 128 (each wavefront 4 x 4 blocks) or 64 (2 x 2 blocks, for
+// the small trailing matrices of the last panels, where 128-tiles leave most
+// compute units idle).
+template <int UT>
 __global__ __launch_bounds__(256, 2) void k_chol_trail(SrArgs A, int ob) {
+  constexpr int UP = UT + 2;            // padded LDS row (spreads the four k rows of an operand over the banks)
+  constexpr int QB = UT / 32;           // 16 x 16 blocks per side of a wavefront's quadrant
+  constexpr int EL = kUK * UT / 256;    // staged values per thread and stage
+  constexpr int TPR = kUK / EL;         // threads per staged row
   const SrInst& I = A.inst[blockIdx.y];
   const int64_t o = (int64_t)ob * kOuter, t0 = o + kOuter;
   if (t0 >= I.np) return;
-  const int nt = (int)ceil_div<int64_t>(I.np - t0, kUT);
+  const int nt = (int)ceil_div<int64_t>(I.np - t0, UT);
   if ((int)blockIdx.x >= nt * (nt + 1) / 2) return;
   int ti = 0, start = 0;   // lower-triangle tile (ti >= tj)
   while ((int)blockIdx.x >= start + ti + 1) {
@@ -709,27 +715,27 @@ __global__ __launch_bounds__(256, 2) void k_chol_trail(SrArgs A, int ob) {
     ++ti;
   }
   const int tj = (int)blockIdx.x - start;
-  const int64_t r0 = t0 + (int64_t)ti * kUT, c0 = t0 + (int64_t)tj * kUT;
+  const int64_t r0 = t0 + (int64_t)ti * UT, c0 = t0 + (int64_t)tj * UT;
   double* F = A.chol + I.chol_off;
-  __shared__ double As[2][kUK][kUP];
-  __shared__ double Bs[2][kUK][kUP];
+  __shared__ double As[2][kUK][UP];
+  __shared__ double Bs[2][kUK][UP];
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const int qi = wv >> 1, qj = wv & 1;
-  const int lr = tid >> 1, lk = (tid & 1) * (kUK / 2);   // staging: half a stage row of row lr
+  const int lr = tid / TPR, lk = (tid % TPR) * EL;   // staging: EL values of row lr
   const int64_t ra = r0 + lr, rb = c0 + lr;
   const double* pa = F + (ra < I.np ? ra : I.np - 1) * I.np + o + lk;
   const double* pb = F + (rb < I.np ? rb : I.np - 1) * I.np + o + lk;
-  double ga[kUK / 2], gb[kUK / 2];
+  double ga[EL], gb[EL];
   auto gload = [&](int k0) {
 #pragma unroll
-    for (int e = 0; e < kUK / 2; ++e) {
+    for (int e = 0; e < EL; ++e) {
       ga[e] = pa[k0 + e];
       gb[e] = pb[k0 + e];
     }
   };
   auto lstore = [&](int st) {
 #pragma unroll
-    for (int e = 0; e < kUK / 2; ++e) {
+    for (int e = 0; e < EL; ++e) {
       As[st][lk + e][lr] = ga[e];
       Bs[st][lk + e][lr] = gb[e];
     }
@@ -739,15 +745,15 @@ __global__ __launch_bounds__(256, 2) void k_chol_trail(SrArgs A, int ob) {
   // l is D[l / 16 + 4 r][l % 16] of its 16 x 16 block) and take the panel's
   // products with one operand negated, so the tile is written once at the
   // end and never read there
-  f64x4 acc[4][4];
+  f64x4 acc[QB][QB];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < QB; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < QB; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = r0 + 64 * qi + 16 * i + ka + 4 * r;
-        const int64_t col = c0 + 64 * qj + 16 * j + ma;
+        const int64_t row = r0 + (UT / 2) * qi + 16 * i + ka + 4 * r;
+        const int64_t col = c0 + (UT / 2) * qj + 16 * j + ma;
         acc[i][j][r] = (row < I.np && col < I.np) ? F[row * I.np + col] : 0.0;
       }
   gload(0);
@@ -759,31 +765,30 @@ __global__ __launch_bounds__(256, 2) void k_chol_trail(SrArgs A, int ob) {
     if (more) gload(k0 + kUK);
 #pragma unroll
     for (int kk = 0; kk < kUK; kk += 4) {
-      double a[4], b[4];
+      double a[QB], b[QB];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        a[i] = -As[st][kk + ka][64 * qi + 16 * i + ma];
-        b[i] = Bs[st][kk + ka][64 * qj + 16 * i + ma];
+      for (int i = 0; i < QB; ++i) {
+        a[i] = -As[st][kk + ka][(UT / 2) * qi + 16 * i + ma];
+        b[i] = Bs[st][kk + ka][(UT / 2) * qj + 16 * i + ma];
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < QB; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < QB; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     if (more) lstore(st ^ 1);
     __syncthreads();
     st ^= 1;
   }
-  // element r of lane l holds D[l / 16 + 4 r][l % 16] of its 16 x 16 block
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < QB; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < QB; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = r0 + 64 * qi + 16 * i + ka + 4 * r;
-        const int64_t col = c0 + 64 * qj + 16 * j + ma;
+        const int64_t row = r0 + (UT / 2) * qi + 16 * i + ka + 4 * r;
+        const int64_t col = c0 + (UT / 2) * qj + 16 * j + ma;
         if (row < I.np && col < I.np && (ti != tj || col <= row)) F[row * I.np + col] = acc[i][j][r];
       }
 }
@@ -1121,6 +1126,12 @@ void sr_syrk_vec(const SrArgs& A, const T* O, TS* S, int n_inst, int64_t max_np,
                      A, S);
 }
 
+// A trailing update with fewer 128-tiles than this (two workgroups on each of
+// 256 compute units, four times over) runs on 64-tiles.  At N_p = 10^4 the
+// solve took 15.9, 15.6, 15.2 and 15.5 ms with 512, 1024, 2048 and any
+// count (64-tiles throughout).
+constexpr int kTrailTiles128 = 2048;
+
 template <typename TS>
 void sr_cholesky_solve(const SrArgs& A, const TS* S, const double* g, double eps_rel, double eps_abs,
                        double freeze, int n_inst, int64_t max_np, hipStream_t s) {
@@ -1138,8 +1149,17 @@ void sr_cholesky_solve(const SrArgs& A, const TS* S, const double* g, double eps
     for (int kb = kb0; kb < kb1; ++kb)
       hipLaunchKernelGGL(k_chol_column, dim3(nblk - kb, n_inst), dim3(256), 0, s, A, kb, kb0);
     if (kb1 < nblk) {
-      const int nt = (int)ceil_div<int64_t>(max_np - (int64_t)(ob + 1) * kOuter, kUT);
-      hipLaunchKernelGGL(k_chol_trail, dim3(nt * (nt + 1) / 2, n_inst), dim3(256), 0, s, A, ob);
+      // 128-tiles while they fill the device four times over, then 64-tiles
+      const int64_t m = max_np - (int64_t)(ob + 1) * kOuter;
+      const int nt128 = (int)ceil_div<int64_t>(m, 128);
+      if (nt128 * (nt128 + 1) / 2 >= kTrailTiles128) {
+        hipLaunchKernelGGL(k_chol_trail<128>, dim3(nt128 * (nt128 + 1) / 2, n_inst), dim3(256), 0,
+                           s, A, ob);
+      } else {
+        const int nt = (int)ceil_div<int64_t>(m, 64);
+        hipLaunchKernelGGL(k_chol_trail<64>, dim3(nt * (nt + 1) / 2, n_inst), dim3(256), 0, s, A,
+                           ob);
+      }
     }
   }
   // backward substitution: the diagonal blocks inverted at once, then one
