@@ -113,14 +113,20 @@ __device__ __forceinline__ void ap_matvec(const T* Mi, int ld, int n, const T* x
 // it with the same gw; it contains workgroup barriers and returns the same
 // value in every thread: true when the walker stopped for a refresh (at a
 // multiple of R or at a non-finite ratio), when needs_refresh[gw] (if given)
-// is also set.  smem: ap_sweep_layout.
-template <typename T, int NT>
+// is also set.  smem: ap_sweep_layout.  FULL = false: no trace, no exchange
+// updates and no RBM factor (the caller guarantees it), which leaves their
+// code and its scalar state out of the loop.
+template <typename T, int NT, bool FULL = true>
 __device__ __forceinline__ bool ap_walk(const Pools& P, int gw, unsigned char* smem, int cap,
                                         uint64_t seed, TraceRec* trace, int64_t trace_cap,
                                         const uint64_t* __restrict__ trace_base,
                                         const uint64_t* __restrict__ target,
                                         int32_t* __restrict__ needs_refresh, int R, int ex64) {
   constexpr int NW = NT / 64;
+  if constexpr (!FULL) {
+    trace = nullptr;
+    ex64 = 0;
+  }
   const int32_t guard0 = P.guard[gw];
   if (guard0 == kGuardFailed) return false;
   const uint64_t n0 = P.cnt[gw];
@@ -137,7 +143,7 @@ __device__ __forceinline__ bool ap_walk(const Pools& P, int gw, unsigned char* s
   const uint64_t u0 = P.upd[gw];
   bool due = false;   // the applied update that completes a multiple of R was made
   const InstDev& I = P.inst[P.walker_inst[gw]];
-  const int ne = I.ne, ns = I.ns, n2 = 2 * ns, M = I.M, n = I.nup;
+  const int ne = I.ne, ns = I.ns, n2 = 2 * ns, M = FULL ? I.M : 0, n = I.nup;
   const int64_t lw = gw - I.walker_off;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
 

@@ -287,3 +287,35 @@ def test_batched_instances_replay():
         sub = rec[lay.walker_off:lay.walker_off + inst.n_walkers]
         compare_trace(sub, walkers, n_prop, SEED, rtol=1e-10)
     ctx.close()
+
+
+@pytest.mark.parametrize("name,precision,variant", [
+    ("sq10_full", "fp64", None), ("sq10_full", "mixed", None), ("sq8_half", "fp64", "ap64"),
+    ("sq6_rbm", "fp64", "ap128")])
+def test_lean_sweep_matches_traced(name, precision, variant):
+    """Without a trace, exchange updates or an RBM factor the anti-parallel
+    sweep runs a variant with that code left out; from the same state it must
+    reach the same configurations, inverses and local energies bit for bit as
+    the traced run (the RBM case takes the full variant both times)."""
+    inst = _case(name)
+    pos0 = good_configs(inst, inst.params0, inst.n_walkers, 5)
+    zero = np.zeros(inst.n_walkers, dtype=np.int64)
+    unit = "updates" if precision == "mixed" else "proposals"
+    out = []
+    for traced in (True, False):
+        ctx = _ctx([inst], inst.params0, seed=SEED, precision=precision, refresh_every=32,
+                   refresh_unit=unit, sweep_variant=variant)
+        ctx.set_state(pos0.ravel(), zero)
+        if traced:
+            ctx.enable_trace(3 * inst.n_elec)
+        acc = ctx.sample(3)
+        ctx.measure(0)
+        pos, cnt = ctx.get_state()
+        out.append((acc.copy(), pos.cpu().numpy().copy(), ctx.get_inverse().cpu().numpy().copy(),
+                    ctx.eloc_of(0, 1).cpu().numpy().copy(), ctx.sweep_variants()))
+        ctx.close()
+    log(f"[lean] {name} {precision}: variants {out[0][4]} accepted {out[0][0]}")
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    assert np.array_equal(out[0][2], out[1][2])
+    assert np.array_equal(out[0][3], out[1][3])
