@@ -149,6 +149,7 @@ def run_sr_workload(wl, precision, steps, warmup, refresh_every, solver="chol", 
         "kernel_calls": calls.tolist(), "W": i0.n_walkers, "ne": i0.n_elec, "np": i0.n_params,
         "ns": i0.n_sites, "sweeps": sweeps, "N": slots * i0.n_walkers, "graph": graph is not None,
         "autotune": tuned, "variants": variants, "cholesky_shift_raises": escalations,
+        "n_hidden": i0.n_hidden,
         "cg_iterations": cg_iters, "steps": steps,
     }
 
@@ -826,7 +827,10 @@ def headline_roofline(r, wsize):
     bm = sweep_bytes(r, wsize, "method") / launches
     gbs = b / (avg_ms * 1e-3) / 1e9
     traffic, note = measured_traffic()
-    return {"kernel": f"k_sweep_ap<double, {r['variants'][0][2:]}>", "bound": "hbm",
+    # the timed steps run without a trace or exchange updates, so walkers
+    # without an RBM factor take the variant with that code left out
+    full = "false" if r.get("n_hidden", 0) == 0 else "true"
+    return {"kernel": f"k_sweep_ap<double, {r['variants'][0][2:]}, {full}>", "bound": "hbm",
             "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
             "traffic": traffic, "traffic_note": note,
             "avg_launch_ms": avg_ms, "launches_per_step": launches,
