@@ -33,7 +33,7 @@ __global__ void k_queue_reset(int32_t* head) { *head = 0; }
 // group -(item + 1) of `groups` (kQueueWpb global walker ids, -1 padded).
 // NEM: register tier of the groups (0 when there are none); NB: register
 // blocks of the refresh of the anti-parallel walkers (0 when there are none);
-// FULL: the register tier with trace, RBM and exchange code.
+// FULL: both tiers with trace, RBM and exchange code.
 template <typename T, int NEM, int NB>
 constexpr int queue_waves_per_simd() {
   return NEM > 0 ? 2 : (NB >= 6 ? 2 : (sizeof(T) == 8 ? 2 : 3));
@@ -59,8 +59,8 @@ __attribute__((amdgpu_waves_per_eu(queue_waves_per_simd<T, NEM, NB>()))) void k_
       if constexpr (NB > 0) {
         // runs of proposals up to each multiple of R (or a non-finite
         // ratio), the double-precision refresh between them
-        while (ap_walk<T, kQueueThreads>(P, code, smem, cap, seed, trace, trace_cap, trace_base,
-                                         target, nullptr, R, ex64)) {
+        while (ap_walk<T, kQueueThreads, FULL>(P, code, smem, cap, seed, trace, trace_cap,
+                                               trace_base, target, nullptr, R, ex64)) {
           __syncthreads();   // the walker's state in memory, for every thread
           ap_refresh_tile<T, NB>(P, code, smem, 0.0, nullptr);
           __syncthreads();
