@@ -959,12 +959,42 @@ __global__ __launch_bounds__(256) void k_gemv_rows(SrArgs A, const T* __restrict
   const double* mk = A.mask + I.param_off;
   const int nr = I.rows - m0 < kRowsPerWave ? (int)(I.rows - m0) : kRowsPerWave;
   double s[kRowsPerWave] = {};
-#pragma unroll 4
-  for (int64_t k = c0 + lane; k < c1; k += 64) {
-    const double pk = p[k] * mk[k];
+  if constexpr (sizeof(T) == 4) {
+    // single precision: four consecutive elements per lane and 16-byte
+    // load (the row stride and offsets are multiples of 64 elements), the
+    // ragged end of the chunk one element at a time
+    typedef float vec_t __attribute__((ext_vector_type(4)));
+#pragma unroll 2
+    for (int64_t k0 = c0 + 4 * lane; k0 < c1; k0 += 256) {
+      if (k0 + 4 <= c1) {
+        double pk[4];
 #pragma unroll
-    for (int r = 0; r < kRowsPerWave; ++r)
-      if (r < nr) s[r] += (double)row[r * I.ldO + k] * pk;
+        for (int j = 0; j < 4; ++j) pk[j] = p[k0 + j] * mk[k0 + j];
+#pragma unroll
+        for (int r = 0; r < kRowsPerWave; ++r)
+          if (r < nr) {
+            const vec_t v = *reinterpret_cast<const vec_t*>(row + r * I.ldO + k0);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) s[r] += (double)v[j] * pk[j];
+          }
+      } else {
+        for (int64_t k = k0; k < c1; ++k) {
+          const double pk = p[k] * mk[k];
+#pragma unroll
+          for (int r = 0; r < kRowsPerWave; ++r)
+            if (r < nr) s[r] += (double)row[r * I.ldO + k] * pk;
+        }
+      }
+    }
+  } else {
+    // double: one element per lane, 512 bytes per wave and load
+#pragma unroll 4
+    for (int64_t k = c0 + lane; k < c1; k += 64) {
+      const double pk = p[k] * mk[k];
+#pragma unroll
+      for (int r = 0; r < kRowsPerWave; ++r)
+        if (r < nr) s[r] += (double)row[r * I.ldO + k] * pk;
+    }
   }
   double* part = A.colpart + I.colpart_off +
                  2 * ceil_div<int64_t>(I.rows, kRowChunk) * I.ldO;   // upper third
@@ -997,26 +1027,39 @@ __global__ __launch_bounds__(256) void k_gemv_rows_finish(SrArgs A) {
 // statistics is free once they have been reduced.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemv_cols_part(SrArgs A, const T* __restrict__ O) {
+  // each lane takes 16 bytes of columns (the row stride and offsets are
+  // multiples of 64 elements); the four wavefronts split the rows
+  constexpr int VW = 16 / (int)sizeof(T);
+  typedef T vec_t __attribute__((ext_vector_type(VW)));
   const SrInst& I = A.inst[blockIdx.z];
   if (A.scal[blockIdx.z * kScal + kDone] != 0.0) return;
   const int64_t m0 = (int64_t)blockIdx.y * kRowChunk;
   if (m0 >= I.rows) return;
   const int64_t m1 = m0 + kRowChunk < I.rows ? m0 + kRowChunk : I.rows;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t k = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t k0 = ((int64_t)blockIdx.x * 64 + lane) * VW;
   const double* t = A.t + I.eloc_off;
-  double s = 0.0;
-  if (k < I.np) {
-    const T* col = O + I.O_off + k;
-#pragma unroll 8
-    for (int64_t m = m0 + wv; m < m1; m += 4) s += (double)col[m * I.ldO] * t[m];
+  double s[VW] = {};
+  if (k0 < I.np) {
+    const T* col = O + I.O_off + k0;
+#pragma unroll 4
+    for (int64_t m = m0 + wv; m < m1; m += 4) {
+      const vec_t v = *reinterpret_cast<const vec_t*>(col + m * I.ldO);
+      const double tm = t[m];
+#pragma unroll
+      for (int j = 0; j < VW; ++j) s[j] += (double)v[j] * tm;
+    }
   }
-  __shared__ double red[4][64];
-  red[wv][lane] = s;
+  __shared__ double red[4][VW][64];
+#pragma unroll
+  for (int j = 0; j < VW; ++j) red[wv][j][lane] = s[j];
   __syncthreads();
-  if (wv == 0 && k < I.np)
-    A.colpart[I.colpart_off + (int64_t)blockIdx.y * I.np + k] =
-        (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+  if (wv == 0)
+#pragma unroll
+    for (int j = 0; j < VW; ++j)
+      if (k0 + j < I.np)
+        A.colpart[I.colpart_off + (int64_t)blockIdx.y * I.np + k0 + j] =
+            (red[0][j][lane] + red[1][j][lane]) + (red[2][j][lane] + red[3][j][lane]);
 }
 
 __global__ __launch_bounds__(256) void k_gemv_cols_finish(SrArgs A) {
@@ -1201,7 +1244,7 @@ void sr_cg_iter(const SrArgs& A, const T* O, int iter, int n_inst, int64_t max_n
   hipLaunchKernelGGL(k_gemv_rows_finish, dim3((unsigned)ceil_div<int64_t>(max_rows, 256), n_inst),
                      dim3(256), 0, s, A);
   hipLaunchKernelGGL(k_gemv_cols_part<T>,
-                     dim3((unsigned)ceil_div<int64_t>(max_np, 64),
+                     dim3((unsigned)ceil_div<int64_t>(max_np, 64 * (16 / (int64_t)sizeof(T))),
                           (unsigned)ceil_div<int64_t>(max_rows, kRowChunk), n_inst),
                      dim3(256), 0, s, A, O);
   hipLaunchKernelGGL(k_gemv_cols_finish, dim3(cb, n_inst), dim3(256), 0, s, A);
