@@ -490,10 +490,24 @@ __global__ __launch_bounds__(256) void k_chol_column(SrArgs A, int kb, int kb0) 
   auto Q = reinterpret_cast<double (*)[kColPad]>(bufQ);
   auto Pt = reinterpret_cast<double (*)[kGemmPad]>(bufP);
   auto Qt = reinterpret_cast<double (*)[kGemmPad]>(bufQ);
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  double accD[4][4] = {}, accB[4][4] = {};
-  // in-panel update: 64 x 64 x 64 products per earlier column block (full
-  // blocks), operands staged k-major so a thread's four rows are one 32-byte run
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  // in-panel update on the FP64 matrix cores: wavefront wv owns the 32 x 32
+  // quadrant (qi, qj) of D and B, 2 x 2 blocks of 16 x 16 (element r of lane
+  // l is row l / 16 + 4 r, column l % 16 of its block); an operand is 16
+  // consecutive doubles of one k row of the staged chunk
+  const int qi = wv >> 1, qj = wv & 1, ka = lane >> 4, ma = lane & 15;
+  f64x4_t accD[2][2], accB[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      accD[i][j] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+      accB[i][j] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+    }
+  // D is needed on and below its diagonal: the quadrant above it is skipped
+  const bool needD = qi >= qj;
+  // 64 x 64 x 64 products per earlier column block (full blocks), operands
+  // staged k-major
   for (int c = kb0; c < kb; ++c) {
     const int64_t co = (int64_t)c * kNb;
     // every load of the chunk in flight before the first LDS store
@@ -514,50 +528,50 @@ __global__ __launch_bounds__(256) void k_chol_column(SrArgs A, int kb, int kb0) 
     }
     __syncthreads();
 #pragma unroll 4
-    for (int k = 0; k < kNb; ++k) {
-      const f64x2 a0 = *reinterpret_cast<const f64x2*>(&Pt[k][ty * 4]);
-      const f64x2 a1 = *reinterpret_cast<const f64x2*>(&Pt[k][ty * 4 + 2]);
-      const f64x2 b0 = *reinterpret_cast<const f64x2*>(&Pt[k][tx * 4]);
-      const f64x2 b1 = *reinterpret_cast<const f64x2*>(&Pt[k][tx * 4 + 2]);
-      const double a[4] = {a0.x, a0.y, a1.x, a1.y}, bb[4] = {b0.x, b0.y, b1.x, b1.y};
+    for (int kk = 0; kk < kNb; kk += 4) {
+      double pa[2], pb[2], qa[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) accD[i][j] += a[i] * bb[j];
-      if (!diag) {
-        const f64x2 q0 = *reinterpret_cast<const f64x2*>(&Qt[k][ty * 4]);
-        const f64x2 q1 = *reinterpret_cast<const f64x2*>(&Qt[k][ty * 4 + 2]);
-        const double bq[4] = {q0.x, q0.y, q1.x, q1.y};
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) accB[i][j] += bq[i] * bb[j];
+      for (int i = 0; i < 2; ++i) {
+        pa[i] = Pt[kk + ka][32 * qi + 16 * i + ma];
+        pb[i] = Pt[kk + ka][32 * qj + 16 * i + ma];
+        qa[i] = Qt[kk + ka][32 * qi + 16 * i + ma];
       }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          if (needD) accD[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[i], pb[j], accD[i][j], 0, 0, 0);
+          if (!diag) accB[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[i], pb[j], accB[i][j], 0, 0, 0);
+        }
     }
   }
   // D (lower triangle, identity past the matrix), B and x_kb^T; the loads
   // first, all in flight
-  double fd[4][4], fb[4][4];
+  double fd[2][2][4], fb[2][2][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r = ty * 4 + i, cc = tx * 4 + j;
-      fd[i][j] = (r < nb && cc <= r) ? F[(o + r) * np + o + cc] : 0.0;
-      fb[i][j] = (!diag && r < nr && cc < nb) ? F[(ro + r) * np + o + cc] : 0.0;
-    }
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 32 * qi + 16 * i + ka + 4 * q, cc = 32 * qj + 16 * j + ma;
+        fd[i][j][q] = (r < nb && cc <= r) ? F[(o + r) * np + o + cc] : 0.0;
+        fb[i][j][q] = (!diag && r < nr && cc < nb) ? F[(ro + r) * np + o + cc] : 0.0;
+      }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r = ty * 4 + i, cc = tx * 4 + j;
-      double d;
-      if (r < nb && cc < nb) d = cc <= r ? fd[i][j] - accD[i][j] : 0.0;
-      else d = r == cc ? 1.0 : 0.0;
-      P[r][cc] = d;
-      if (!diag) Q[r][cc] = (r < nr && cc < nb) ? fb[i][j] - accB[i][j] : 0.0;
-    }
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 32 * qi + 16 * i + ka + 4 * q, cc = 32 * qj + 16 * j + ma;
+        double d;
+        if (r < nb && cc < nb) d = cc <= r ? fd[i][j][q] - accD[i][j][q] : 0.0;
+        else d = r == cc ? 1.0 : 0.0;
+        P[r][cc] = d;
+        if (!diag) Q[r][cc] = (r < nr && cc < nb) ? fb[i][j][q] - accB[i][j][q] : 0.0;
+      }
   if (tid < kNb) Q[kNb][tid] = tid < nb ? x[o + tid] : 0.0;
   const int q0 = diag ? kNb : 0;   // first row of Q to solve (the diagonal block solves x only)
   bool bad = false;
