@@ -443,7 +443,8 @@ __device__ __forceinline__ double lane_value(double v, int lane) {
 // and then, for ib == kb, stores L_kk and y_kb (into r), or for ib > kb
 //   B = F[ib][kb] - sum_c L[ib][c] L[kb][c]^T,   L[ib][kb] = B L_kk^-T,
 //   x_ib -= L[ib][kb] y_kb.
-// The 64 x 64 factor runs in four steps over column strips of 16: the
+// The sums over c run on the FP64 matrix cores.  The 64 x 64 factor runs
+// in four steps over column strips of 16: the
 // strip's 16 x 16 diagonal block by Crout in 16 lanes,
 //   L[i][j] = (D[i][j] - sum_{m<j} L[i][m] L[j][m]) / L[j][j],
 //   L[j][j] = sqrt(D[j][j] - sum_{m<j} L[j][m]^2),
@@ -456,7 +457,7 @@ __device__ __forceinline__ double lane_value(double v, int lane) {
 // the launch still read F[kb][kb].  A non-positive pivot sets the instance's
 // flag.
 constexpr int kColPad = kNb + 1;   // row stride of the factor phase (2-way LDS banks)
-constexpr int kGemmPad = kNb + 2;  // column stride of the k-major GEMM stage (16-byte rows)
+constexpr int kGemmPad = kNb + 2;  // row stride of the k-major stage (16-byte aligned rows)
 constexpr int kStrip = 16;
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
