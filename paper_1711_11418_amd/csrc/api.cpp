@@ -30,6 +30,8 @@ constexpr int kTimingCats = 6;
 constexpr int kRegWpb = 4;   // walkers per workgroup of the register sweep
 constexpr int kMaxShiftEscalations = 4;   // Cholesky retries with eps_rel x 10 each
 constexpr int kTailUnitsMax = 512;        // split-bf16 S: sample parts of tail tiles, all together
+constexpr int kWideTile = 128;            // FP64 wide S: tile side of k_syrk_f64_wide
+constexpr int kWideTailUnits = 512;       // FP64 wide S: sample parts of tail tiles, all together
 constexpr int kMaxTileSb = 4;             // largest direct-to-LDS S tile: 64 * 4
 
 inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
@@ -118,6 +120,21 @@ static void set_tiles(SrInst& S, int sb, int n_cu) {
   S.sb = sb;
   S.nfull = 0;
   S.tail_ks = 1;
+  if (!sb && S.wide64) {   // FP64 wide tiles: two workgroups per compute unit
+    const int64_t nt = (S.np + kWideTile - 1) / kWideTile, ntl = nt * (nt + 1) / 2;
+    const int64_t slots = 2 * (int64_t)std::max(n_cu, 1);
+    const int64_t rem = ntl % slots;
+    S.nfull = (int32_t)ntl;
+    if (rem) {
+      int64_t ks = std::min<int64_t>(8, slots / rem);
+      while (ks > 1 && rem * ks > kWideTailUnits) --ks;
+      if (ks >= 2) {
+        S.nfull = (int32_t)(ntl - rem);
+        S.tail_ks = (int32_t)ks;
+      }
+    }
+    return;
+  }
   if (!sb) return;
   const int64_t T = 64 * sb, nt = (S.np + T - 1) / T, ntl = nt * (nt + 1) / 2;
   const int64_t slots = (int64_t)std::max(n_cu, 1) * (sb == 2 ? 2 : 1);
@@ -457,6 +474,8 @@ Plan make_plan(const mvmc_config& c) {
     if (c.build_s && !S.wide64)
       off_syrkpart += tiled_s ? (int64_t)kTailUnitsMax * (64 * kMaxTileSb) * (64 * kMaxTileSb) / 2
                               : ks * tiles * 4096;
+    else if (S.wide64)
+      off_syrkpart += (int64_t)kWideTailUnits * kWideTile * kWideTile;
 
     off_O += I.rows * I.ldO;
     if (c.build_s) off_S += (int64_t)I.np * I.np;
@@ -1853,9 +1872,18 @@ int mvmc_build_sr(mvmc_ctx* c, int32_t n_used, const double* d_eloc, void* d_O, 
     else
     {
       bool any_wide = false, any_narrow = false;
-      for (const SrInst& si : P.sr) (si.wide64 ? any_wide : any_narrow) = true;
+      int wide_units = 0, wide_tail = 0;   // launch extents over the wide instances
+      for (int k = 0; k < n; ++k) {
+        const SrInst& si = c->h_sr[k];
+        (si.wide64 ? any_wide : any_narrow) = true;
+        if (!si.wide64) continue;
+        const int64_t nt = (si.np + kWideTile - 1) / kWideTile, ntl = nt * (nt + 1) / 2;
+        wide_units = std::max<int>(wide_units, (int)(si.nfull + (ntl - si.nfull) * si.tail_ks));
+        if (si.tail_ks > 1) wide_tail = std::max<int>(wide_tail, (int)(ntl - si.nfull));
+      }
       sr_syrk_vec<double, double>(c->SA, (const double*)d_O, (double*)d_S, n, P.max_np,
-                                  P.max_ksplit, any_wide, any_narrow, c->stream);
+                                  P.max_ksplit, any_wide, any_narrow, wide_units, wide_tail,
+                                  c->stream);
     }
     toc(c, id);
     LAUNCHCHK(c);

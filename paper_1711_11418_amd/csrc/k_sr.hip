@@ -280,17 +280,38 @@ __global__ __launch_bounds__(256) void k_syrk_f64mfma(SrArgs A, const double* __
 // one sample), double-buffered through registers.  O's padding columns are
 // zero, so only samples past N need masking.  The lower triangle is written
 // from each 16 x 16 block transposed through LDS, so both writes are
-// coalesced.
+// coalesced.  The tiles past the last full round of workgroups (from nfull
+// on) are split into tail_ks sample parts, whose unscaled partial tiles go to
+// the partial pool and are summed in part order by k_syrk_f64_tail, so the
+// last round is as full as the others.
 constexpr int kWT = 128, kWK = 16, kWP = kWT + 2;
 __global__ __launch_bounds__(256, 2) void k_syrk_f64_wide(SrArgs A, const double* __restrict__ O,
                                                           double* __restrict__ S) {
   const SrInst& I = A.inst[blockIdx.y];
   if (!I.wide64) return;
   const int nt = (int)ceil_div<int64_t>(I.np, kWT);
-  if ((int)blockIdx.x >= nt * (nt + 1) / 2) return;
+  const int ntl = nt * (nt + 1) / 2;
+  const int u = (int)blockIdx.x;
+  if (u >= I.nfull + (ntl - I.nfull) * I.tail_ks) return;
+  // unit u: a whole tile (u < nfull) or sample part pk of tail tile t
+  const int t = u < I.nfull ? u : I.nfull + (u - I.nfull) / I.tail_ks;
+  const int pk = u < I.nfull ? -1 : (u - I.nfull) % I.tail_ks;
   int ti, tj;
-  tile_of(blockIdx.x, nt, ti, tj);   // ti <= tj
+  tile_of(t, nt, ti, tj);   // ti <= tj
   const int64_t ca = (int64_t)ti * kWT, cb = (int64_t)tj * kWT, ld = I.ldO, rows = I.rows;
+  int64_t mb = 0, me = rows;   // samples of this unit (part bounds on kWK steps)
+  double* part = nullptr;
+  if (pk >= 0) {
+    const int64_t steps = ceil_div<int64_t>(rows, kWK);
+    const int64_t chunk = ceil_div<int64_t>(steps, I.tail_ks) * kWK;
+    mb = pk * chunk;
+    me = mb + chunk < rows ? mb + chunk : rows;
+    part = A.syrkpart + I.syrkpart_off + ((int64_t)(t - I.nfull) * I.tail_ks + pk) * kWT * kWT;
+    if (mb >= me) {   // empty part: contributes zero
+      for (int e = threadIdx.x; e < kWT * kWT; e += blockDim.x) part[e] = 0.0;
+      return;
+    }
+  }
   const double* Ob = O + I.O_off;
   __shared__ double As[2][kWK][kWP];
   __shared__ double Bs[2][kWK][kWP];
@@ -321,13 +342,13 @@ __global__ __launch_bounds__(256, 2) void k_syrk_f64_wide(SrArgs A, const double
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f64x4_t{0.0, 0.0, 0.0, 0.0};
-  gload(0);
+  gload(mb);
   lstore(0);
   __syncthreads();
   int st = 0;
   const int ka = lane >> 4, ma = lane & 15;
-  for (int64_t m0 = 0; m0 < rows; m0 += kWK) {
-    const bool more = m0 + kWK < rows;
+  for (int64_t m0 = mb; m0 < me; m0 += kWK) {
+    const bool more = m0 + kWK < me;
     if (more) gload(m0 + kWK);
 #pragma unroll
     for (int kk = 0; kk < kWK; kk += 4) {
@@ -348,6 +369,16 @@ __global__ __launch_bounds__(256, 2) void k_syrk_f64_wide(SrArgs A, const double
     st ^= 1;
   }
   // element r of lane l holds D[l / 16 + 4 r][l % 16] of its 16 x 16 block
+  if (part) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          part[(64 * qi + 16 * i + ka + 4 * r) * kWT + 64 * qj + 16 * j + ma] = acc[i][j][r];
+    return;
+  }
   const double invN = 1.0 / (double)rows;
   double* Sb = S + I.S_off;
   const int64_t np = I.np;
@@ -375,6 +406,28 @@ __global__ __launch_bounds__(256, 2) void k_syrk_f64_wide(SrArgs A, const double
         wave::wave_sync();
       }
     }
+}
+
+// Tail tiles of k_syrk_f64_wide: the sample parts summed in order, scaled by
+// 1/N, written to both triangles (a diagonal tile holds both already).
+__global__ __launch_bounds__(256) void k_syrk_f64_tail(SrArgs A, double* __restrict__ S) {
+  const SrInst& I = A.inst[blockIdx.z];
+  if (!I.wide64 || I.tail_ks < 2) return;
+  const int nt = (int)ceil_div<int64_t>(I.np, kWT);
+  const int tt = I.nfull + (int)blockIdx.y;
+  if (tt >= nt * (nt + 1) / 2) return;
+  const int e = (int)blockIdx.x * 256 + (int)threadIdx.x;   // grid covers kWT^2 exactly
+  int ti, tj;
+  tile_of(tt, nt, ti, tj);
+  const int64_t row = (int64_t)ti * kWT + e / kWT, col = (int64_t)tj * kWT + e % kWT;
+  if (row >= I.np || col >= I.np) return;
+  const double* part = A.syrkpart + I.syrkpart_off + (int64_t)blockIdx.y * I.tail_ks * kWT * kWT;
+  double a = 0.0;
+  for (int k = 0; k < I.tail_ks; ++k) a += part[(int64_t)k * kWT * kWT + e];
+  const double v = a * (1.0 / (double)I.rows);
+  double* Sb = S + I.S_off;
+  Sb[row * I.np + col] = v;
+  if (ti != tj) Sb[col * I.np + row] = v;
 }
 
 template <typename TS>
@@ -1165,12 +1218,14 @@ void sr_colstats(const SrArgs& A, T* O, uint16_t* split, double* g, int n_inst, 
 
 template <typename T, typename TS>
 void sr_syrk_vec(const SrArgs& A, const T* O, TS* S, int n_inst, int64_t max_np, int max_ksplit,
-                 bool any_wide, bool any_narrow, hipStream_t s) {
+                 bool any_wide, bool any_narrow, int wide_units, int wide_tail, hipStream_t s) {
   if constexpr (std::is_same<T, double>::value && std::is_same<TS, double>::value) {
     if (any_wide) {
-      const int nw = (int)ceil_div<int64_t>(max_np, kWT);
-      hipLaunchKernelGGL(k_syrk_f64_wide, dim3(nw * (nw + 1) / 2, n_inst), dim3(256), 0, s, A, O,
-                         S);
+      hipLaunchKernelGGL(k_syrk_f64_wide, dim3(wide_units > 0 ? wide_units : 1, n_inst), dim3(256),
+                         0, s, A, O, S);
+      if (wide_tail > 0)
+        hipLaunchKernelGGL(k_syrk_f64_tail, dim3(kWT * kWT / 256, wide_tail, n_inst), dim3(256), 0,
+                           s, A, S);
     }
     if (!any_narrow) return;
   }
@@ -1281,9 +1336,9 @@ template void sr_colstats<double>(const SrArgs&, double*, uint16_t*, double*, in
 template void sr_colstats<float>(const SrArgs&, float*, uint16_t*, double*, int, int64_t, int64_t,
                                  hipStream_t);
 template void sr_syrk_vec<double, double>(const SrArgs&, const double*, double*, int, int64_t, int,
-                                          bool, bool, hipStream_t);
+                                          bool, bool, int, int, hipStream_t);
 template void sr_syrk_vec<float, float>(const SrArgs&, const float*, float*, int, int64_t, int,
-                                        bool, bool, hipStream_t);
+                                        bool, bool, int, int, hipStream_t);
 template void sr_cholesky_solve<double>(const SrArgs&, const double*, const double*, double, double,
                                         double, int, int64_t, hipStream_t);
 template void sr_cholesky_solve<float>(const SrArgs&, const float*, const double*, double, double,

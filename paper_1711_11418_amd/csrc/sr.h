@@ -24,7 +24,7 @@ struct SrInst {
   int32_t sb;                     // 0: 64-tile kernel; 2..4: direct-to-LDS tiles of side 64 sb
   int32_t nfull;                  // direct-to-LDS tiles computed whole (the first nfull)
   int32_t tail_ks;                // sample parts of each remaining (tail) tile
-  int32_t wide64;                 // 1: FP64 S by 128 x 128 tiles straight into S (no partials)
+  int32_t wide64;                 // 1: FP64 S by 128 x 128 tiles (nfull whole, the rest in tail_ks parts)
   int32_t pad0;
 };
 
@@ -85,7 +85,7 @@ void sr_colstats(const SrArgs& A, T* O, uint16_t* split, double* g, int n_inst, 
                  int64_t max_rows, hipStream_t s);
 template <typename T, typename TS>
 void sr_syrk_vec(const SrArgs& A, const T* O, TS* S, int n_inst, int64_t max_np, int max_ksplit,
-                 bool any_wide, bool any_narrow,
+                 bool any_wide, bool any_narrow, int wide_units, int wide_tail,
                  hipStream_t s);
 // split-bf16 (hi*hi + hi*lo + lo*hi) MFMA S build, FP32 accumulation
 void sr_syrk_bf16x3(const SrArgs& A, const uint16_t* split, float* S, int n_inst, int64_t max_np,
